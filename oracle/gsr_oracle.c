@@ -64,6 +64,7 @@ typedef struct {
     int32_t mask_ambiguous;         /* zero the loss weight at ambiguous pixels */
     int32_t want_grads;
     int32_t n_threads;
+    double res_margin;              /* relative margin that flags a residual sign as ambiguous */
 } or_in;
 
 typedef struct {
@@ -406,23 +407,44 @@ int oracle_run(const or_in *in, or_out *out) {
                     if (out->sil) out->sil[gp] = acc[4];
                     if (out->t_final) out->t_final[gp] = T;
                     if (out->n_contrib) out->n_contrib[gp] = (int32_t)nh;
-                    if (out->ambiguous) out->ambiguous[gp] = (uint8_t)amb;
-                    if (!in->t_rgb) continue;
+                    if (!in->t_rgb) {
+                        if (out->ambiguous) out->ambiguous[gp] = (uint8_t)amb;
+                        continue;
+                    }
 
                     /* loss at this pixel (reading of the combined loss: L1 terms, 1/P per view) */
                     double wgt = in->t_weight ? in->t_weight[gp] : 1.0;
-                    if (in->mask_ambiguous && amb) wgt = 0.0;
-                    if (wgt == 0.0) continue;
                     const double trk = (in->sil_mask_thresh >= 0.0) ? (acc[4] > in->sil_mask_thresh ? 1.0 : 0.0) : 1.0;
                     const double dm = in->t_depth[gp] > 0.0 ? 1.0 : 0.0;
                     const double dpr = (in->t_prior && in->t_prior[gp] > 0.0) ? 1.0 : 0.0;
+                    double tv[5];
+                    tv[0] = in->t_rgb[3 * off + pix];
+                    tv[1] = in->t_rgb[3 * off + P + pix];
+                    tv[2] = in->t_rgb[3 * off + 2 * P + pix];
+                    tv[3] = in->t_depth[gp];
+                    tv[4] = in->t_sil ? in->t_sil[gp] : 0.0;
+                    const double tpr = in->t_prior ? in->t_prior[gp] : 0.0;
                     double res[5];
-                    res[0] = acc[0] - in->t_rgb[3 * off + pix];
-                    res[1] = acc[1] - in->t_rgb[3 * off + P + pix];
-                    res[2] = acc[2] - in->t_rgb[3 * off + 2 * P + pix];
-                    res[3] = acc[3] - in->t_depth[gp];
-                    res[4] = acc[4] - (in->t_sil ? in->t_sil[gp] : 0.0);
-                    const double rpr = in->t_prior ? acc[3] - in->t_prior[gp] : 0.0;
+                    for (int ch = 0; ch < 5; ++ch) res[ch] = acc[ch] - tv[ch];
+                    const double rpr = acc[3] - tpr;
+                    /* sign(residual) and the tracking mask are decisions too: flag
+                     * the pixel when a residual that carries weight is within the
+                     * relative margin of zero (but not both sides exactly zero) */
+                    const double wch[5] = {trk * dm * in->w_rgb, trk * dm * in->w_rgb, trk * dm * in->w_rgb,
+                                           trk * dm * in->w_depth, in->w_sil};
+                    for (int ch = 0; ch < 5; ++ch)
+                        if (wch[ch] != 0.0 && (acc[ch] != 0.0 || tv[ch] != 0.0) &&
+                            fabs(res[ch]) <= in->res_margin * (fabs(acc[ch]) + fabs(tv[ch])))
+                            amb = 1;
+                    if (trk * dpr * in->w_prior != 0.0 && (acc[3] != 0.0 || tpr != 0.0) &&
+                        fabs(rpr) <= in->res_margin * (fabs(acc[3]) + fabs(tpr)))
+                        amb = 1;
+                    if (in->sil_mask_thresh >= 0.0 &&
+                        fabs(acc[4] - in->sil_mask_thresh) <= m * fmax(fabs(acc[4]), in->sil_mask_thresh))
+                        amb = 1;
+                    if (out->ambiguous) out->ambiguous[gp] = (uint8_t)amb;
+                    if (in->mask_ambiguous && amb) wgt = 0.0;
+                    if (wgt == 0.0) continue;
                     const double lp = wgt * inv_P *
                         (trk * dm * (in->w_rgb * (fabs(res[0]) + fabs(res[1]) + fabs(res[2])) + in->w_depth * fabs(res[3])) +
                          in->w_sil * fabs(res[4]) + trk * dpr * in->w_prior * fabs(rpr));

@@ -59,6 +59,7 @@ class _In(C.Structure):
         ("pixel_mask", _u8p),
         ("margin", C.c_double),
         ("mask_ambiguous", C.c_int32), ("want_grads", C.c_int32), ("n_threads", C.c_int32),
+        ("res_margin", C.c_double),
     ]
 
 
@@ -163,8 +164,14 @@ def _make_in(g, views, opts: Options, keep: list):
 
 def run(g, views, opts: Options = Options(), targets: Optional[Targets] = None, want_grads: bool = False,
         pixel_mask: Optional[np.ndarray] = None, margin: float = 1e-5, mask_ambiguous: bool = False,
-        threads: int = 0, want_grad2d: bool = False) -> Result:
-    """Render every view; with targets also the loss; with want_grads the gradients."""
+        threads: int = 0, want_grad2d: bool = False, res_margin: Optional[float] = None) -> Result:
+    """Render every view; with targets also the loss; with want_grads the gradients.
+
+    A pixel is flagged ambiguous when a decision on its path lies within a
+    relative margin of its threshold: alpha vs 1/255 and vs 0.99 and the next
+    transmittance vs 1e-4 (`margin`), or the sign of a weighted loss residual
+    and the tracking mask (`res_margin`, default `margin`).  FP32 and FP64
+    may decide such pixels differently; mask_ambiguous gives them weight 0."""
     keep = []
     s, n, iso = _make_in(g, views, opts, keep)
     V = len(views.cams)
@@ -184,6 +191,7 @@ def run(g, views, opts: Options = Options(), targets: Optional[Targets] = None, 
         assert pm.size == P
         s.pixel_mask = _p(pm, _u8p)
     s.margin = margin
+    s.res_margin = margin if res_margin is None else res_margin
     s.mask_ambiguous = int(mask_ambiguous)
     s.want_grads = int(want_grads)
     s.n_threads = threads
