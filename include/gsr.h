@@ -1,0 +1,229 @@
+/*
+ * gsr.h -- C ABI of the differentiable tile-based Gaussian rasteriser for
+ * gfx950 (MI355X).
+ *
+ * What the library computes (the hot path of Gaussian-splatting RGB-D SLAM):
+ *   Gaussians (centre, rotation quaternion, per-axis scale, opacity, colour;
+ *   Preliminaries, 3D Gaussian Splatting, eq. 1 and its anisotropic form
+ *   Sigma = R S S^T R^T given in the Introduction) and, per view, a pinhole
+ *   camera (Preliminaries, Visual Geometry Residual: pi_m with fx, fy, cx, cy)
+ *   and a world-to-camera pose (R_cw, t_cw; same section) go in.  Out come:
+ *     - the RGB image, eq. 2; the depth image, eq. 3; the silhouette, eq. 4
+ *       (Proposed Approach, Pose Estimation), composited front to back after
+ *       projecting each Gaussian with Sigma' = J W Sigma W^T J^T
+ *       (Introduction);
+ *     - the combined photometric + depth + silhouette (+ depth prior) L1 loss
+ *       used for tracking and mapping (Abstract; Pose Estimation; depth priors
+ *       in the Abstract and Conclusions);
+ *     - its gradients to every Gaussian parameter (Scene Optimization) and to
+ *       each camera pose, both as (q, t) and in the rotation-translation
+ *       decoupled form (q with the camera centre C fixed, C) used by the
+ *       decoupled pose update (Pose Estimation).
+ *
+ * Conventions that the paper leaves open (each is a fixed part of the ABI):
+ *   - quaternions are (w, x, y, z) and need not be unit: the rotation is that
+ *     of q/|q|, and gradients flow through the normalisation;
+ *   - scale = exp(log_scale); opacity = sigmoid(opacity_logit); colour is used
+ *     as given (no activation); the background is black;
+ *   - pixel (u, v) is evaluated at the continuous image point (u, v);
+ *   - the 2D covariance gets blur2d (px^2) added to its diagonal;
+ *   - per pixel, alpha = min(0.99, o G); Gaussians with alpha < 1/255 are
+ *     skipped; a Gaussian that would take the transmittance below 1e-4 ends
+ *     the pixel and is not blended; Gaussians with camera depth <= z_near are
+ *     culled; depth order is (float32 camera-frame z, Gaussian index);
+ *   - the depth of a Gaussian (eq. 3) is its camera-frame z;
+ *   - loss per view v with P_v pixels (L = sum over views):
+ *       L_v = 1/P_v sum_p w(p) [ k(p) m(p) (w_rgb sum_c |C_c - C*_c|
+ *                                            + w_depth |D - D*|)
+ *                                + w_sil |S - S*|
+ *                                + k(p) m_pr(p) w_prior |D - D_prior| ]
+ *     with m = [D* > 0], m_pr = [D_prior > 0], w the optional per-pixel
+ *     weight, k = [S > sil_mask_thresh] if sil_mask_thresh >= 0 else 1
+ *     (a constant mask, no gradient), d|x|/dx = sign(x) with sign(0) = 0.
+ *
+ * Memory and ownership:
+ *   - Every tensor pointer is a DEVICE pointer to contiguous float32 data
+ *     unless stated.  Images of several views are concatenated: view v owns
+ *     pixels [off_v, off_v + W_v H_v) of every per-pixel array (row-major,
+ *     x fastest), where off_v is the running sum of W H over earlier views;
+ *     RGB images are planar per view: channel c of view v starts at
+ *     3 off_v + c W_v H_v.
+ *   - The caller owns all memory: inputs, outputs and one workspace buffer
+ *     whose size gsr_workspace_size() returns.  The library never allocates
+ *     device memory.
+ *   - Outputs are overwritten, never accumulated.  Gradient outputs with a
+ *     NULL pointer are skipped.
+ *   - The workspace carries the forward state (sorted tile lists, per-pixel
+ *     final transmittance and last contributor) from gsr_forward() to
+ *     gsr_backward(); it must not be reused in between.
+ *   - All work is enqueued on `stream` (a hipStream_t; NULL = the null
+ *     stream) and is stream-ordered; no call synchronises the host except
+ *     gsr_read_counters().  Inputs must stay valid until the work completes.
+ *   - A gsr_ctx is not thread-safe: use one per host thread.
+ *
+ * Errors: every call returns a gsr_status.  Arguments are validated on the
+ * host before any work is enqueued; on error nothing is enqueued and
+ * gsr_last_error() describes the problem.  GSR_EHIP wraps a failing HIP call.
+ * If the (Gaussian, tile) pairs of a call exceed the workspace's pair
+ * capacity, the call still returns GSR_OK (it cannot know without a host
+ * synchronisation), outputs are undefined, and gsr_read_counters() reports
+ * the overflow together with the number of pairs that was needed.
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gsr_ctx gsr_ctx;
+
+typedef enum {
+    GSR_OK = 0,
+    GSR_EINVAL = -1,       /* invalid argument (nothing was enqueued) */
+    GSR_ENOMEM = -2,       /* workspace too small for this call */
+    GSR_ECAPACITY = -3,    /* reserved: pair capacity exceeded (see gsr_read_counters) */
+    GSR_EHIP = -4,         /* a HIP runtime call failed; gsr_last_error() has its text */
+    GSR_EUNSUPPORTED = -5  /* e.g. more than GSR_MAX_VIEWS views in one call */
+} gsr_status;
+
+#define GSR_MAX_VIEWS 64
+
+/* option flags */
+#define GSR_ISOTROPIC      0x1u  /* log_scales is [N,1]: one scale for all axes (eq. 1) */
+#define GSR_NO_GAUSS_GRADS 0x2u  /* skip gradients to the Gaussians (pose-only tracking) */
+#define GSR_NO_POSE_GRADS  0x4u  /* skip gradients to the poses (mapping) */
+
+/* Pinhole camera pi_m (Preliminaries, Visual Geometry Residual).  Host memory. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+} gsr_camera;
+
+/* The Gaussian map (eq. 1 and its anisotropic form).  Device pointers, raw
+ * (unactivated) parameters: means [N,3] world metres; quats [N,4] (w,x,y,z);
+ * log_scales [N,3] ([N,1] with GSR_ISOTROPIC); opacity_logits [N]; rgb [N,3]. */
+typedef struct {
+    int64_t n;
+    const float *means, *quats, *log_scales, *opacity_logits, *rgb;
+} gsr_gaussians;
+
+/* Views: n_views cameras (host array) and world-to-camera poses (device):
+ * quat [V,4] (w,x,y,z, any norm) and trans [V,3], X_c = R(q) X_w + t. */
+typedef struct {
+    int32_t n_views;
+    const gsr_camera *cams;
+    const float *quat, *trans;
+} gsr_views;
+
+typedef struct {
+    float w_rgb, w_depth, w_sil, w_prior;  /* loss weights */
+    float z_near;                          /* near-plane cull (camera-frame z, metres) */
+    float blur2d;                          /* added to the 2D covariance diagonal (px^2), >= 0 */
+    float sil_mask_thresh;                 /* < 0: off; else photometric/depth terms need S > thresh */
+    int32_t tile_w, tile_h;                /* binning tile in pixels: multiples of 8, 8..64 */
+    uint32_t flags;                        /* GSR_* flags */
+} gsr_options;
+
+/* Loss targets (device, concatenated like the images).  rgb [3*sumP] planar
+ * per view and depth [sumP] are required; sil, prior and weight may be NULL
+ * (a NULL sil target means S* = 0, a NULL prior disables the prior term, a
+ * NULL weight means 1 everywhere). */
+typedef struct {
+    const float *rgb, *depth, *sil, *prior, *weight;
+} gsr_targets;
+
+/* Rendered images (device): rgb [3*sumP] planar per view, depth [sumP], sil [sumP]. */
+typedef struct {
+    float *rgb, *depth, *sil;
+} gsr_images;
+
+/* Gradients to the raw Gaussian parameters, laid out like gsr_gaussians
+ * (device; NULL = skip that group). */
+typedef struct {
+    float *means, *quats, *log_scales, *opacity_logits, *rgb;
+} gsr_gaussian_grads;
+
+/* Pose gradients (device; NULL = skip): dq_t [V,4] = dL/dq with t fixed,
+ * dt [V,3] = dL/dt, dq_c [V,4] = dL/dq with the camera centre C = -R^T t
+ * fixed, dc [V,3] = dL/dC. */
+typedef struct {
+    float *dq_t, *dt, *dq_c, *dc;
+} gsr_pose_grads;
+
+/* Caller-owned device workspace. */
+typedef struct {
+    void *ptr;
+    size_t bytes;
+    int64_t pair_capacity;   /* (Gaussian, tile) pairs it was sized for */
+} gsr_workspace;
+
+/* Create a context on HIP device `device`.  Returns GSR_EHIP if the device
+ * cannot be queried. */
+gsr_status gsr_create(gsr_ctx **out, int device);
+
+/* Destroy a context (NULL is allowed). */
+void gsr_destroy(gsr_ctx *ctx);
+
+/* Text of the last error on ctx; valid until the next call on ctx.  A NULL
+ * ctx gives the text of the last failed gsr_create(). */
+const char *gsr_last_error(const gsr_ctx *ctx);
+
+/* Bytes of workspace needed for n Gaussians, these views (only the cameras
+ * are read) and pair_capacity (Gaussian, tile) pairs. */
+gsr_status gsr_workspace_size(gsr_ctx *ctx, int64_t n, const gsr_views *views, const gsr_options *opts,
+                              int64_t pair_capacity, size_t *bytes);
+
+/* Forward pass (eqs. 2-4): project, bin, sort and composite every view into
+ * `out`.  Keeps the state that gsr_backward() needs in the workspace. */
+gsr_status gsr_forward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views, const gsr_options *opts,
+                       gsr_workspace ws, gsr_images out, void *stream);
+
+/* Backward pass of gsr_forward(): given dL/d(rgb, depth, sil) images
+ * (device, laid out like the images; any may be NULL = zero), writes the
+ * gradients to the Gaussians and to the poses.  `out` must hold the images
+ * gsr_forward() wrote, and ws the state it left. */
+gsr_status gsr_backward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views, const gsr_options *opts,
+                        gsr_workspace ws, gsr_images out, const float *g_rgb, const float *g_depth,
+                        const float *g_sil, gsr_gaussian_grads *gg, gsr_pose_grads *pg, void *stream);
+
+/* Forward, loss and backward in one call (the tracking/mapping step):
+ * renders into `out`, writes the per-view loss to loss[V] (device, float64,
+ * overwritten) and the gradients. */
+gsr_status gsr_render_loss_grad(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views,
+                                const gsr_options *opts, const gsr_targets *targets, gsr_workspace ws,
+                                gsr_images out, double *loss, gsr_gaussian_grads *gg, gsr_pose_grads *pg,
+                                void *stream);
+
+/* Synchronises `stream` and reads the counters of the last call on ws:
+ * visible (view, Gaussian) records, (Gaussian, tile) pairs needed, and
+ * whether the pair capacity overflowed (then outputs are undefined). */
+gsr_status gsr_read_counters(gsr_ctx *ctx, gsr_workspace ws, void *stream, int64_t *n_visible, int64_t *n_pairs,
+                             int32_t *overflow);
+
+/* Test hook for the binning step: copies out the state that the last
+ * gsr_forward() or gsr_render_loss_grad() left in ws (same g, views, opts;
+ * device destinations, enqueued on stream).  rec_gid [M]: view*N+i of each
+ * visible record in depth order; rec_xy [M,2]: its float32 screen mean (the
+ * leading float32 part); rec_radius [M]: its float32 binning radius; rec_z
+ * [M]: its float32 camera depth; ranges [T,2]: [start, end) of every tile's
+ * list in the sorted pairs (tiles of all views, view by view, row-major
+ * within a view); pair_rec [K]: record index of every sorted pair.  Entries
+ * beyond max_rec, max_tiles and max_pairs are not written. */
+gsr_status gsr_debug_binning(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views, const gsr_options *opts,
+                             gsr_workspace ws, int64_t max_rec, int64_t max_tiles, int64_t max_pairs,
+                             uint32_t *rec_gid, float *rec_xy, float *rec_radius, float *rec_z, uint32_t *ranges,
+                             uint32_t *pair_rec, void *stream);
+
+/* Self test of the wave64 primitives the kernels rely on (cross-lane sums,
+ * ballots, lane ranks): writes the number of failed checks to *failures
+ * (device int32), enqueued on stream.  0 is expected. */
+gsr_status gsr_selftest(gsr_ctx *ctx, int32_t *failures, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSR_H */

@@ -1,0 +1,111 @@
+"""ctypes mirror of include/gsr.h.  Argument marshalling only: every step of
+the rasteriser runs in libgsr.so's HIP kernels."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsr.so")
+
+GSR_OK, GSR_EINVAL, GSR_ENOMEM, GSR_ECAPACITY, GSR_EHIP, GSR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+GSR_MAX_VIEWS = 64
+GSR_ISOTROPIC, GSR_NO_GAUSS_GRADS, GSR_NO_POSE_GRADS = 0x1, 0x2, 0x4
+
+_fp = C.POINTER(C.c_float)
+_vp = C.c_void_p
+
+
+class Camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float)]
+
+
+class Gaussians(C.Structure):
+    _fields_ = [("n", C.c_int64), ("means", _vp), ("quats", _vp), ("log_scales", _vp),
+                ("opacity_logits", _vp), ("rgb", _vp)]
+
+
+class Views(C.Structure):
+    _fields_ = [("n_views", C.c_int32), ("cams", C.POINTER(Camera)), ("quat", _vp), ("trans", _vp)]
+
+
+class Options(C.Structure):
+    _fields_ = [("w_rgb", C.c_float), ("w_depth", C.c_float), ("w_sil", C.c_float), ("w_prior", C.c_float),
+                ("z_near", C.c_float), ("blur2d", C.c_float), ("sil_mask_thresh", C.c_float),
+                ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("flags", C.c_uint32)]
+
+
+class Targets(C.Structure):
+    _fields_ = [("rgb", _vp), ("depth", _vp), ("sil", _vp), ("prior", _vp), ("weight", _vp)]
+
+
+class Images(C.Structure):
+    _fields_ = [("rgb", _vp), ("depth", _vp), ("sil", _vp)]
+
+
+class GaussGrads(C.Structure):
+    _fields_ = [("means", _vp), ("quats", _vp), ("log_scales", _vp), ("opacity_logits", _vp), ("rgb", _vp)]
+
+
+class PoseGrads(C.Structure):
+    _fields_ = [("dq_t", _vp), ("dt", _vp), ("dq_c", _vp), ("dc", _vp)]
+
+
+class Workspace(C.Structure):
+    _fields_ = [("ptr", _vp), ("bytes", C.c_size_t), ("pair_capacity", C.c_int64)]
+
+
+EXPORTS = ["gsr_create", "gsr_destroy", "gsr_last_error", "gsr_workspace_size", "gsr_forward", "gsr_backward",
+           "gsr_render_loss_grad", "gsr_read_counters", "gsr_debug_binning", "gsr_selftest"]
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libgsr.so.  Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m paper_2408_05635_amd.build)")
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    st = C.c_int
+    lib.gsr_create.argtypes = [P(_vp), C.c_int]
+    lib.gsr_create.restype = st
+    lib.gsr_destroy.argtypes = [_vp]
+    lib.gsr_destroy.restype = None
+    lib.gsr_last_error.argtypes = [_vp]
+    lib.gsr_last_error.restype = C.c_char_p
+    lib.gsr_workspace_size.argtypes = [_vp, C.c_int64, P(Views), P(Options), C.c_int64, P(C.c_size_t)]
+    lib.gsr_workspace_size.restype = st
+    lib.gsr_forward.argtypes = [_vp, P(Gaussians), P(Views), P(Options), Workspace, Images, _vp]
+    lib.gsr_forward.restype = st
+    lib.gsr_backward.argtypes = [_vp, P(Gaussians), P(Views), P(Options), Workspace, Images, _vp, _vp, _vp,
+                                 P(GaussGrads), P(PoseGrads), _vp]
+    lib.gsr_backward.restype = st
+    lib.gsr_render_loss_grad.argtypes = [_vp, P(Gaussians), P(Views), P(Options), P(Targets), Workspace, Images,
+                                         _vp, P(GaussGrads), P(PoseGrads), _vp]
+    lib.gsr_render_loss_grad.restype = st
+    lib.gsr_read_counters.argtypes = [_vp, Workspace, _vp, P(C.c_int64), P(C.c_int64), P(C.c_int32)]
+    lib.gsr_read_counters.restype = st
+    lib.gsr_debug_binning.argtypes = [_vp, P(Gaussians), P(Views), P(Options), Workspace, C.c_int64, C.c_int64,
+                                      C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.gsr_debug_binning.restype = st
+    lib.gsr_selftest.argtypes = [_vp, _vp, _vp]
+    lib.gsr_selftest.restype = st
+    _lib = lib
+    return lib
+
+
+class GsrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"gsr status {status}: {msg}")
+        self.status = status
+
+
+def check(status: int, ctx) -> None:
+    if status != GSR_OK:
+        msg = load().gsr_last_error(ctx)
+        raise GsrError(status, msg.decode() if msg else "")

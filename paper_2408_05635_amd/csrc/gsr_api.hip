@@ -1,0 +1,829 @@
+// C ABI of the rasteriser (include/gsr.h): workspace layout, launch sequence
+// and the per-Gaussian kernels (projection, binning, chain rule to the
+// parameters and the pose).  The per-pixel kernels are in gsr_blend.hpp, the
+// scan and radix sort in gsr_scan_sort.hpp.
+//
+// Launch sequence of one call (all views at once, no host synchronisation):
+//   setup         view table and FP64 pose matrices into the workspace
+//   project_count per Gaussian, per view: visibility, depth key, tiles touched
+//   compact       scan of visibility -> (depth key, view*N+i) of visible records
+//   depth sort    stable radix sort on the float32 depth bits
+//   gather        per visible record in depth order: full projection -> record
+//   emit          scan of tiles touched -> (global tile id, record) pairs
+//   tile sort     stable radix sort on the tile id: per-tile lists in depth order
+//   ranges        [start, end) of every tile's list
+//   blend_fwd     compositing (eqs. 2-4)
+//   blend_bwd     loss + reverse compositing -> per-record 2D gradients
+//   project_bwd   chain rule to the raw parameters; pose partials per view
+//   pose_final    (q, t) and decoupled (q | C fixed, C) pose gradients
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "gsr_blend.hpp"
+#include "gsr_common.hpp"
+#include "gsr_project.hpp"
+#include "gsr_scan_sort.hpp"
+
+using namespace gsr;
+
+struct gsr_ctx {
+    int device;
+    int num_cus;
+    std::string err;
+};
+
+static std::string g_create_err;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct Layout {
+    int64_t vn;           // V * N
+    int64_t kcap;         // pair capacity
+    int64_t P;            // total pixels
+    int64_t T;            // total tiles
+    int32_t G;            // total blend blocks
+    int tile_bits;        // key bits of the tile sort
+    size_t views, poses, counters, cnt, zkey, dk0, dv0, dk1, dv1, inv, rec, trect, cnt_s, pk0, pv0, pk1, pv1,
+        ranges, tfinal, nlast, grad2d, posepart, part, hist;
+    size_t total;
+};
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int bits_for(int64_t n) {   // bits to hold ids 0..n-1
+    int b = 0;
+    while ((int64_t(1) << b) < n) ++b;
+    return b;
+}
+
+gsr_status fail(gsr_ctx *ctx, gsr_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return st;
+}
+
+gsr_status check_hip(gsr_ctx *ctx, hipError_t e, const char *what) {
+    if (e == hipSuccess) return GSR_OK;
+    return fail(ctx, GSR_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+gsr_status validate_views(gsr_ctx *ctx, const gsr_views *views, const gsr_options *opts) {
+    if (!views || !opts) return fail(ctx, GSR_EINVAL, "views and opts must not be NULL");
+    if (views->n_views < 1) return fail(ctx, GSR_EINVAL, "n_views must be >= 1 (got %d)", views->n_views);
+    if (views->n_views > GSR_MAX_VIEWS)
+        return fail(ctx, GSR_EUNSUPPORTED, "at most %d views per call (got %d)", GSR_MAX_VIEWS, views->n_views);
+    if (!views->cams) return fail(ctx, GSR_EINVAL, "views->cams must not be NULL");
+    for (int v = 0; v < views->n_views; ++v) {
+        const gsr_camera &c = views->cams[v];
+        if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
+            return fail(ctx, GSR_EINVAL, "view %d: image size %dx%d out of range [1, 16384]", v, c.width, c.height);
+        if (!std::isfinite(c.fx) || !std::isfinite(c.fy) || !std::isfinite(c.cx) || !std::isfinite(c.cy) ||
+            c.fx <= 0.f || c.fy <= 0.f)
+            return fail(ctx, GSR_EINVAL, "view %d: focal lengths must be finite and > 0", v);
+    }
+    const int tw = opts->tile_w, th = opts->tile_h;
+    if (tw < 8 || th < 8 || tw > 64 || th > 64 || tw % 8 || th % 8)
+        return fail(ctx, GSR_EINVAL, "tile size %dx%d must be multiples of 8 in [8, 64]", tw, th);
+    if (!(opts->blur2d >= 0.f) || !std::isfinite(opts->blur2d))
+        return fail(ctx, GSR_EINVAL, "blur2d must be finite and >= 0");
+    if (!(opts->z_near >= 0.f) || !std::isfinite(opts->z_near))
+        return fail(ctx, GSR_EINVAL, "z_near must be finite and >= 0");
+    if (opts->blur2d == 0.f && opts->z_near == 0.f) {
+        // allowed: degenerate covariances are culled
+    }
+    return GSR_OK;
+}
+
+void build_table(const gsr_views *views, const gsr_options *opts, ViewTable &vt) {
+    memset(&vt, 0, sizeof(vt));
+    vt.n_views = views->n_views;
+    vt.tile_w = opts->tile_w;
+    vt.tile_h = opts->tile_h;
+    int64_t pix = 0;
+    int32_t tiles = 0, blocks = 0;
+    const int spt = (opts->tile_w / kBlk) * (opts->tile_h / kBlk);
+    for (int v = 0; v < views->n_views; ++v) {
+        const gsr_camera &c = views->cams[v];
+        ViewInfo &vi = vt.v[v];
+        vi.W = c.width;
+        vi.H = c.height;
+        vi.fx = c.fx;
+        vi.fy = c.fy;
+        vi.cx = c.cx;
+        vi.cy = c.cy;
+        vi.pix_off = pix;
+        vi.tiles_x = (c.width + opts->tile_w - 1) / opts->tile_w;
+        vi.tiles_y = (c.height + opts->tile_h - 1) / opts->tile_h;
+        vi.tile_off = tiles;
+        vi.blk_off = blocks;
+        pix += (int64_t)c.width * c.height;
+        tiles += vi.tiles_x * vi.tiles_y;
+        blocks += vi.tiles_x * vi.tiles_y * spt;
+    }
+    vt.total_tiles = tiles;
+    vt.total_blocks = blocks;
+}
+
+Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
+    Layout L;
+    const int V = vt.n_views;
+    L.vn = (int64_t)V * n;
+    L.kcap = kcap;
+    L.P = 0;
+    for (int v = 0; v < V; ++v) L.P += (int64_t)vt.v[v].W * vt.v[v].H;
+    L.T = vt.total_tiles;
+    L.G = vt.total_blocks;
+    L.tile_bits = bits_for(L.T);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes ? bytes : 1);
+        return o;
+    };
+    const size_t vn = (size_t)L.vn, kc = (size_t)kcap;
+    L.counters = take(sizeof(int64_t) * kNumCounters);   // first: gsr_read_counters finds it at offset 0
+    L.views = take(sizeof(ViewTable));
+    L.poses = take(sizeof(PoseF64) * V);
+    L.cnt = take(4 * vn);
+    L.zkey = take(4 * vn);
+    L.dk0 = take(4 * vn);
+    L.dv0 = take(4 * vn);
+    L.dk1 = take(4 * vn);
+    L.dv1 = take(4 * vn);
+    L.inv = take(4 * vn);
+    L.rec = take(48 * vn);
+    L.trect = take(8 * vn);
+    L.cnt_s = take(4 * vn);
+    L.pk0 = take(4 * kc);
+    L.pv0 = take(4 * kc);
+    L.pk1 = take(4 * kc);
+    L.pv1 = take(4 * kc);
+    L.ranges = take(8 * (size_t)L.T);
+    L.tfinal = take(4 * (size_t)L.P);
+    L.nlast = take(4 * (size_t)L.P);
+    L.grad2d = take(40 * vn);
+    L.posepart = take(sizeof(double) * 12 * V);
+    const int64_t nb_sort = (std::max<int64_t>(L.vn, kcap) + kChunk - 1) / kChunk;
+    const int64_t scan_n = std::max<int64_t>(std::max<int64_t>(L.vn, kcap), 256 * nb_sort);
+    L.part = take(4 * (size_t)((scan_n + kChunk - 1) / kChunk + 1));
+    L.hist = take(4 * (size_t)(256 * nb_sort + 1));
+    L.total = off;
+    return L;
+}
+
+template <class T>
+T *at(const gsr_workspace &ws, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(ws.ptr) + off);
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_setup(ViewTable tab, ViewTable *vt, const float *__restrict__ pq, const float *__restrict__ pt,
+                        PoseF64 *poses, int64_t *counters) {
+    const int t = threadIdx.x;
+    const int words = (int)(sizeof(ViewTable) / 4);
+    const int32_t *src = reinterpret_cast<const int32_t *>(&tab);
+    int32_t *dst = reinterpret_cast<int32_t *>(vt);
+    for (int k = t; k < words; k += blockDim.x) dst[k] = src[k];
+    if (t < kNumCounters) counters[t] = 0;
+    if (t < tab.n_views) {
+        PoseF64 p;
+        quat_to_rot_f64(pq[4 * t], pq[4 * t + 1], pq[4 * t + 2], pq[4 * t + 3], p.W);
+        for (int k = 0; k < 3; ++k) p.t[k] = (double)pt[3 * t + k];
+        poses[t] = p;
+    }
+}
+
+struct ProjParams {
+    gsr_gaussians g;
+    int64_t n;
+    double z_near, blur;
+    bool iso;
+};
+
+__device__ __forceinline__ uint32_t tiles_of(const Proj &r, const ViewTable *vt, const ViewInfo &V, uint32_t &tr0,
+                                            uint32_t &tr1) {
+    const int tx0 = r.px0 / vt->tile_w, tx1 = r.px1 / vt->tile_w;
+    const int ty0 = r.py0 / vt->tile_h, ty1 = r.py1 / vt->tile_h;
+    tr0 = (uint32_t)tx0 | ((uint32_t)tx1 << 16);
+    tr1 = (uint32_t)ty0 | ((uint32_t)ty1 << 16);
+    return (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+}
+
+// per Gaussian i, per view v: tiles touched (0 = not visible) and depth key
+__global__ __launch_bounds__(256) void k_project_count(ProjParams pp, const ViewTable *__restrict__ vt,
+                                                       const PoseF64 *__restrict__ poses, uint32_t *__restrict__ cnt,
+                                                       uint32_t *__restrict__ zkey) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= pp.n) return;
+    const GaussIn p = load_gauss(pp.g, i, pp.iso);
+    const int V = vt->n_views;
+    for (int v = 0; v < V; ++v) {
+        Proj r;
+        project<false>(p, poses[v], vt->v[v], pp.z_near, pp.blur, pp.iso, r);
+        uint32_t c = 0;
+        if (r.visible) {
+            uint32_t a, b;
+            c = tiles_of(r, vt, vt->v[v], a, b);
+        }
+        cnt[(int64_t)v * pp.n + i] = c;
+        zkey[(int64_t)v * pp.n + i] = __float_as_uint(r.z32);
+    }
+}
+
+struct VisSrc {
+    const uint32_t *cnt;
+    __device__ uint32_t operator()(int64_t i) const { return cnt[i] != 0u ? 1u : 0u; }
+};
+struct VisSink {
+    const uint32_t *zkey;
+    uint32_t *keys, *vals;
+    __device__ void operator()(int64_t i, uint32_t pos, uint32_t v) const {
+        if (v) {
+            keys[pos] = zkey[i];
+            vals[pos] = (uint32_t)i;
+        }
+    }
+};
+
+// per visible record s (depth order): full projection -> record, tile rect
+__global__ __launch_bounds__(256) void k_gather(ProjParams pp, const ViewTable *__restrict__ vt,
+                                                const PoseF64 *__restrict__ poses, const int64_t *__restrict__ counters,
+                                                const uint32_t *__restrict__ sorted_gid, float4 *__restrict__ rec,
+                                                uint2 *__restrict__ trect, uint32_t *__restrict__ cnt_s,
+                                                uint32_t *__restrict__ inv, const float *__restrict__ rgb) {
+    const int64_t M = counters[kCntVisible];
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < M; s += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t gid = sorted_gid[s];
+        const int v = (int)(gid / (uint64_t)pp.n);
+        if (v >= vt->n_views) continue;   // never expected; keeps reads in bounds
+        const int64_t i = (int64_t)gid - (int64_t)v * pp.n;
+        const GaussIn p = load_gauss(pp.g, i, pp.iso);
+        Proj r;
+        project<true>(p, poses[v], vt->v[v], pp.z_near, pp.blur, pp.iso, r);
+        uint32_t a = 0, b = 0;
+        const uint32_t c = tiles_of(r, vt, vt->v[v], a, b);
+        rec[3 * s] = make_float4(r.mxh, r.myh, r.mxl, r.myl);
+        rec[3 * s + 1] = make_float4((float)r.l11, (float)r.l21, (float)r.l22, (float)r.o);
+        rec[3 * s + 2] = make_float4(rgb[3 * i], rgb[3 * i + 1], rgb[3 * i + 2], r.z32);
+        trect[s] = make_uint2(a, b);
+        cnt_s[s] = c;
+        inv[gid] = (uint32_t)s;
+    }
+}
+
+struct CntSrc {
+    const uint32_t *cnt;
+    __device__ uint32_t operator()(int64_t i) const { return cnt[i]; }
+};
+struct EmitSink {
+    const uint2 *trect;
+    const uint32_t *gid;
+    const ViewTable *vt;
+    int64_t n;
+    int64_t cap;
+    uint32_t *keys, *vals;
+    __device__ void operator()(int64_t s, uint32_t pos, uint32_t c) const {
+        if ((int64_t)pos + c > cap) return;
+        const int v = (int)(gid[s] / (uint64_t)n);
+        if (v >= vt->n_views) return;   // never expected; keeps writes in bounds
+        const ViewInfo &V = vt->v[v];
+        const uint2 tr = trect[s];
+        const int tx0 = tr.x & 0xffff, tx1 = tr.x >> 16, ty0 = tr.y & 0xffff, ty1 = tr.y >> 16;
+        uint32_t k = pos;
+        for (int ty = ty0; ty <= ty1; ++ty)
+            for (int tx = tx0; tx <= tx1; ++tx) {
+                keys[k] = (uint32_t)(V.tile_off + ty * V.tiles_x + tx);
+                vals[k] = (uint32_t)s;
+                ++k;
+            }
+    }
+};
+
+__global__ void k_check_capacity(int64_t *counters, int64_t cap) {
+    const int64_t K = counters[kCntPairs];
+    counters[kCntPairsUsed] = K <= cap ? K : 0;
+    counters[kCntOverflow] = K <= cap ? 0 : 1;
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t val) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = val;
+}
+
+__global__ void k_fill_f32_dev(float *p, const int64_t *n_dev, int64_t mult, float val) {
+    const int64_t n = *n_dev * mult;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = val;
+}
+
+__global__ void k_fill_f64(double *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+__global__ void k_ranges(const uint32_t *__restrict__ keys, const int64_t *__restrict__ counters,
+                         uint2 *__restrict__ ranges, int64_t n_tiles) {
+    const int64_t K = counters[kCntPairsUsed];
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < K; j += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t t = keys[j];
+        if (t >= (uint32_t)n_tiles) continue;   // never expected; keeps writes in bounds
+        if (j == 0 || keys[j - 1] != t) ranges[t].x = (uint32_t)j;
+        if (j == K - 1 || keys[j + 1] != t) ranges[t].y = (uint32_t)(j + 1);
+    }
+}
+
+struct GradOut {
+    gsr_gaussian_grads gg;
+    bool want_gauss, want_pose;
+};
+
+// per Gaussian: chain rule over the views that see it; pose partials per view
+__global__ __launch_bounds__(256) void k_project_bwd(ProjParams pp, const ViewTable *__restrict__ vt,
+                                                     const PoseF64 *__restrict__ poses, const uint32_t *__restrict__ cnt,
+                                                     const uint32_t *__restrict__ inv,
+                                                     const float *__restrict__ grad2d, GradOut go,
+                                                     double *__restrict__ posepart, const int64_t *__restrict__ counters) {
+    __shared__ double s_pose[GSR_MAX_VIEWS * 12];
+    const uint32_t n_rec = (uint32_t)counters[kCntVisible];
+    const int V = vt->n_views;
+    for (int k = threadIdx.x; k < V * 12; k += blockDim.x) s_pose[k] = 0.0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = i < pp.n;
+    GaussIn p;
+    if (live) p = load_gauss(pp.g, i, pp.iso);
+    ParamGrad pg;
+    for (int k = 0; k < 3; ++k) pg.mu[k] = pg.ls[k] = pg.rgb[k] = 0.0;
+    for (int k = 0; k < 4; ++k) pg.q[k] = 0.0;
+    pg.logit = 0.0;
+    for (int v = 0; v < V; ++v) {
+        const bool vis = live && cnt[(int64_t)v * pp.n + i] != 0u;
+        double gX[3] = {0.0, 0.0, 0.0}, GW[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (vis) {
+            const uint32_t s = inv[(int64_t)v * pp.n + i];
+            float g2[10];
+            for (int c = 0; c < 10; ++c) g2[c] = s < n_rec ? grad2d[10 * (size_t)s + c] : 0.0f;
+            Proj r;
+            project<true>(p, poses[v], vt->v[v], pp.z_near, pp.blur, pp.iso, r);
+            project_backward(p, poses[v], vt->v[v], r, g2, pp.iso, pg, gX, GW);
+        }
+        if (go.want_pose && ballot(vis) != 0) {
+            double vals[12];
+            for (int k = 0; k < 9; ++k) vals[k] = GW[k];
+            for (int k = 0; k < 3; ++k) vals[9 + k] = gX[k];
+            for (int k = 0; k < 12; ++k) {
+                const double t = wave_sum_f64(vals[k]);
+                if ((threadIdx.x & 63) == 0) atomicAdd(&s_pose[v * 12 + k], t);
+            }
+        }
+    }
+    if (live && go.want_gauss) {
+        if (go.gg.means)
+            for (int k = 0; k < 3; ++k) go.gg.means[3 * i + k] = (float)pg.mu[k];
+        if (go.gg.quats)
+            for (int k = 0; k < 4; ++k) go.gg.quats[4 * i + k] = (float)pg.q[k];
+        if (go.gg.log_scales) {
+            if (pp.iso)
+                go.gg.log_scales[i] = (float)pg.ls[0];
+            else
+                for (int k = 0; k < 3; ++k) go.gg.log_scales[3 * i + k] = (float)pg.ls[k];
+        }
+        if (go.gg.opacity_logits) go.gg.opacity_logits[i] = (float)pg.logit;
+        if (go.gg.rgb)
+            for (int k = 0; k < 3; ++k) go.gg.rgb[3 * i + k] = (float)pg.rgb[k];
+    }
+    if (go.want_pose) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < V * 12; k += blockDim.x)
+            if (s_pose[k] != 0.0) atomicAdd(&posepart[k], s_pose[k]);
+    }
+}
+
+// per view: (G_W, g_t) -> dL/dq | t, dL/dt, dL/dq | C, dL/dC with C = -W^T t
+__global__ void k_pose_final(const float *__restrict__ pq, const float *__restrict__ pt, const PoseF64 *poses,
+                             const double *__restrict__ posepart, int V, gsr_pose_grads pg) {
+    const int v = threadIdx.x;
+    if (v >= V) return;
+    const double *GW = posepart + 12 * v;
+    const double *gt = GW + 9;
+    const double q[4] = {pq[4 * v], pq[4 * v + 1], pq[4 * v + 2], pq[4 * v + 3]};
+    const double *W = poses[v].W;
+    double gq[4];
+    rot_grad_to_quat_f64(q, GW, gq);
+    if (pg.dq_t)
+        for (int k = 0; k < 4; ++k) pg.dq_t[4 * v + k] = (float)gq[k];
+    if (pg.dt)
+        for (int k = 0; k < 3; ++k) pg.dt[3 * v + k] = (float)gt[k];
+    double C[3], gc[3];
+    for (int k = 0; k < 3; ++k) {
+        C[k] = -(W[k] * pt[3 * v] + W[3 + k] * pt[3 * v + 1] + W[6 + k] * pt[3 * v + 2]);
+        gc[k] = -(W[k] * gt[0] + W[3 + k] * gt[1] + W[6 + k] * gt[2]);
+    }
+    if (pg.dc)
+        for (int k = 0; k < 3; ++k) pg.dc[3 * v + k] = (float)gc[k];
+    double G2[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) G2[3 * r + c] = GW[3 * r + c] - gt[r] * C[c];
+    rot_grad_to_quat_f64(q, G2, gq);
+    if (pg.dq_c)
+        for (int k = 0; k < 4; ++k) pg.dq_c[4 * v + k] = (float)gq[k];
+}
+
+// Binning test hook: record fields in depth order.
+__global__ void k_debug_records(const int64_t *__restrict__ counters, const uint32_t *__restrict__ gid,
+                                const float4 *__restrict__ rec, const uint2 *__restrict__ trect, int64_t max_rec,
+                                uint32_t *o_gid, float *o_xy, float *o_rad, float *o_z, const ProjParams pp,
+                                const ViewTable *__restrict__ vt, const PoseF64 *__restrict__ poses) {
+    const int64_t M = counters[kCntVisible];
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < M && s < max_rec;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t g = gid[s];
+        o_gid[s] = g;
+        o_xy[2 * s] = rec[3 * s].x;
+        o_xy[2 * s + 1] = rec[3 * s].y;
+        o_z[s] = rec[3 * s + 2].w;
+        // the radius is recomputed exactly as the projection kernels do
+        const int v = (int)(g / (uint64_t)pp.n);
+        const int64_t i = (int64_t)g - (int64_t)v * pp.n;
+        const GaussIn p = load_gauss(pp.g, i, pp.iso);
+        Proj r;
+        project<true>(p, poses[v], vt->v[v], pp.z_near, pp.blur, pp.iso, r);
+        o_rad[s] = r.radius;
+    }
+}
+
+__global__ void k_debug_copy_u32(const uint32_t *src, const int64_t *counters, int which, int64_t max_n, uint32_t *dst,
+                                 int64_t fixed_n) {
+    const int64_t n0 = which >= 0 ? counters[which] : fixed_n;
+    const int64_t n = n0 < max_n ? n0 : max_n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// Wave-primitive self test: 0 failures expected.
+__global__ void k_selftest(int *fail) {
+    const uint32_t lane = threadIdx.x;
+    const float x = (float)(lane + 1);
+    const float s = wave_sum(x);
+    if (s != 2080.0f) atomicAdd(fail, 1);
+    const float s63 = wave_sum_to63(lane == 17 ? 3.5f : 0.0f);
+    if (lane == 63 && s63 != 3.5f) atomicAdd(fail, 1);
+    const uint64_t m = ballot((lane % 3) == 0);
+    const uint32_t r = rank_below(m);
+    if ((lane % 3) == 0 && r != lane / 3) atomicAdd(fail, 1);
+    if (lane_id() != lane) atomicAdd(fail, 1);
+    const uint32_t mx = wave_max_u32(lane * 7 % 64);
+    if (mx != 63u) atomicAdd(fail, 1);
+    const double d = wave_sum_f64((double)lane);
+    if (d != 2016.0) atomicAdd(fail, 1);
+}
+
+unsigned grid_for(int64_t n, int threads, int64_t max_blocks = 65536) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > max_blocks) b = max_blocks;
+    return (unsigned)b;
+}
+
+struct Call {
+    gsr_ctx *ctx;
+    ViewTable tab;
+    Layout L;
+    gsr_workspace ws;
+    hipStream_t st;
+    ProjParams pp;
+};
+
+gsr_status prepare(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views, const gsr_options *opts,
+                   gsr_workspace ws, void *stream, Call &c) {
+    if (!ctx) return GSR_EINVAL;
+    if (!g) return fail(ctx, GSR_EINVAL, "gaussians must not be NULL");
+    gsr_status s = validate_views(ctx, views, opts);
+    if (s != GSR_OK) return s;
+    if (g->n < 0) return fail(ctx, GSR_EINVAL, "n must be >= 0 (got %lld)", (long long)g->n);
+    if ((int64_t)views->n_views * g->n >= (int64_t)0xffffffffLL)
+        return fail(ctx, GSR_EUNSUPPORTED, "views x Gaussians must be < 2^32");
+    if (g->n > 0 && (!g->means || !g->quats || !g->log_scales || !g->opacity_logits || !g->rgb))
+        return fail(ctx, GSR_EINVAL, "Gaussian parameter pointers must not be NULL");
+    if (!views->quat || !views->trans) return fail(ctx, GSR_EINVAL, "pose pointers must not be NULL");
+    if (!ws.ptr) return fail(ctx, GSR_EINVAL, "workspace pointer is NULL");
+    if (ws.pair_capacity < 0 || ws.pair_capacity >= (int64_t)0xffffffffLL)
+        return fail(ctx, GSR_EINVAL, "pair_capacity must be in [0, 2^32)");
+    build_table(views, opts, c.tab);
+    c.L = make_layout(g->n, c.tab, ws.pair_capacity);
+    if (ws.bytes < c.L.total)
+        return fail(ctx, GSR_ENOMEM, "workspace has %zu bytes, this call needs %zu", ws.bytes, c.L.total);
+    c.ctx = ctx;
+    c.ws = ws;
+    c.st = (hipStream_t)stream;
+    c.pp.g = *g;
+    c.pp.n = g->n;
+    c.pp.z_near = opts->z_near;
+    c.pp.blur = opts->blur2d;
+    c.pp.iso = (opts->flags & GSR_ISOTROPIC) != 0;
+    return GSR_OK;
+}
+
+// Projection, binning, sorting and ranges (forward up to the blend).
+void enqueue_binning(Call &c, const gsr_views *views) {
+    const Layout &L = c.L;
+    const gsr_workspace &ws = c.ws;
+    hipStream_t st = c.st;
+    ViewTable *vt = at<ViewTable>(ws, L.views);
+    PoseF64 *poses = at<PoseF64>(ws, L.poses);
+    int64_t *counters = at<int64_t>(ws, L.counters);
+    uint32_t *cnt = at<uint32_t>(ws, L.cnt), *zkey = at<uint32_t>(ws, L.zkey);
+    uint32_t *dk0 = at<uint32_t>(ws, L.dk0), *dv0 = at<uint32_t>(ws, L.dv0);
+    uint32_t *dk1 = at<uint32_t>(ws, L.dk1), *dv1 = at<uint32_t>(ws, L.dv1);
+    uint32_t *part = at<uint32_t>(ws, L.part), *hist = at<uint32_t>(ws, L.hist);
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, st, c.tab, vt, views->quat, views->trans, poses, counters);
+    if (L.vn > 0) {
+        hipLaunchKernelGGL(k_project_count, dim3(grid_for(c.pp.n, 256, 1ll << 30)), dim3(256), 0, st, c.pp, vt,
+                           poses, cnt, zkey);
+    }
+    // compaction of the visible (view, Gaussian) records, index order kept
+    scan_exclusive(VisSrc{cnt}, VisSink{zkey, dk0, dv0}, nullptr, L.vn, part, counters + kCntVisible, st);
+    // depth order: stable sort on the float32 depth bits (positive floats sort as integers)
+    const bool d_in1 = radix_sort(dk0, dv0, dk1, dv1, counters + kCntVisible, L.vn, 32, hist, part,
+                                  counters + kCntScratch, st);
+    const uint32_t *gid_sorted = d_in1 ? dv1 : dv0;
+    float4 *rec = at<float4>(ws, L.rec);
+    uint2 *trect = at<uint2>(ws, L.trect);
+    uint32_t *cnt_s = at<uint32_t>(ws, L.cnt_s), *inv = at<uint32_t>(ws, L.inv);
+    if (L.vn > 0)
+        hipLaunchKernelGGL(k_gather, dim3(grid_for(L.vn, 256, 8192)), dim3(256), 0, st, c.pp, vt, poses, counters,
+                           gid_sorted, rec, trect, cnt_s, inv, c.pp.g.rgb);
+    uint32_t *pk0 = at<uint32_t>(ws, L.pk0), *pv0 = at<uint32_t>(ws, L.pv0);
+    uint32_t *pk1 = at<uint32_t>(ws, L.pk1), *pv1 = at<uint32_t>(ws, L.pv1);
+    scan_exclusive(CntSrc{cnt_s}, EmitSink{trect, gid_sorted, vt, c.pp.n, L.kcap, pk0, pv0}, counters + kCntVisible,
+                   L.vn, part, counters + kCntPairs, st);
+    hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(1), 0, st, counters, L.kcap);
+    const bool p_in1 = radix_sort(pk0, pv0, pk1, pv1, counters + kCntPairsUsed, L.kcap, L.tile_bits, hist, part,
+                                  counters + kCntScratch, st);
+    uint2 *ranges = at<uint2>(ws, L.ranges);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(2 * L.T, 256)), dim3(256), 0, st, (uint32_t *)ranges, 2 * L.T, 0u);
+    if (L.kcap > 0)
+        hipLaunchKernelGGL(k_ranges, dim3(grid_for(L.kcap, 256, 16384)), dim3(256), 0, st, p_in1 ? pk1 : pk0,
+                           counters, ranges, L.T);
+}
+
+// which buffer holds the sorted pair values (the sort's parity is fixed by the key bits)
+const uint32_t *pair_values(const Call &c) {
+    const int passes = (c.L.tile_bits + 7) / 8;
+    const bool in1 = (c.L.kcap > 0 && c.L.tile_bits > 0) ? (passes % 2 == 1) : false;
+    return at<uint32_t>(c.ws, in1 ? c.L.pv1 : c.L.pv0);
+}
+
+const uint32_t *depth_sorted_gid(const Call &c) {
+    const bool in1 = false;   // 4 passes over 32 bits: the result is back in the first buffer
+    return at<uint32_t>(c.ws, in1 ? c.L.dv1 : c.L.dv0);
+}
+
+void enqueue_blend_fwd(Call &c, gsr_images out) {
+    const Layout &L = c.L;
+    BlendOut bo{out.rgb, out.depth, out.sil, at<float>(c.ws, L.tfinal), at<uint32_t>(c.ws, L.nlast)};
+    const unsigned grid = (unsigned)(((L.G + 7) / 8) * 8);
+    if (grid > 0)
+        hipLaunchKernelGGL(k_blend_fwd, dim3(grid), dim3(64), 0, c.st, at<ViewTable>(c.ws, L.views),
+                           at<float4>(c.ws, L.rec), pair_values(c), at<uint2>(c.ws, L.ranges),
+                           at<int64_t>(c.ws, L.counters), bo);
+}
+
+void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, gsr_images out, LossIn li,
+                      bool fused, gsr_gaussian_grads *gg, gsr_pose_grads *pg) {
+    const Layout &L = c.L;
+    hipStream_t st = c.st;
+    ViewTable *vt = at<ViewTable>(c.ws, L.views);
+    int64_t *counters = at<int64_t>(c.ws, L.counters);
+    float *grad2d = at<float>(c.ws, L.grad2d);
+    double *posepart = at<double>(c.ws, L.posepart);
+    hipLaunchKernelGGL(k_fill_f32_dev, dim3(grid_for(10 * L.vn, 256, 8192)), dim3(256), 0, st, grad2d,
+                       counters + kCntVisible, (int64_t)10, 0.0f);
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, posepart, (int64_t)12 * views->n_views);
+    if (fused) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, li.loss, (int64_t)views->n_views);
+    BlendOut bo{out.rgb, out.depth, out.sil, at<float>(c.ws, L.tfinal), at<uint32_t>(c.ws, L.nlast)};
+    const unsigned grid = (unsigned)(((L.G + 7) / 8) * 8);
+    if (grid > 0) {
+        if (fused)
+            hipLaunchKernelGGL(k_blend_bwd<true>, dim3(grid), dim3(64), 0, st, vt, at<float4>(c.ws, L.rec),
+                               pair_values(c), at<uint2>(c.ws, L.ranges), at<int64_t>(c.ws, L.counters), bo, li, grad2d);
+        else
+            hipLaunchKernelGGL(k_blend_bwd<false>, dim3(grid), dim3(64), 0, st, vt, at<float4>(c.ws, L.rec),
+                               pair_values(c), at<uint2>(c.ws, L.ranges), at<int64_t>(c.ws, L.counters), bo, li, grad2d);
+    }
+    GradOut go;
+    memset(&go, 0, sizeof(go));
+    if (gg) go.gg = *gg;
+    go.want_gauss = gg && !(opts->flags & GSR_NO_GAUSS_GRADS) &&
+                    (gg->means || gg->quats || gg->log_scales || gg->opacity_logits || gg->rgb);
+    go.want_pose = pg && !(opts->flags & GSR_NO_POSE_GRADS) && (pg->dq_t || pg->dt || pg->dq_c || pg->dc);
+    if (c.pp.n > 0 && (go.want_gauss || go.want_pose))
+        hipLaunchKernelGGL(k_project_bwd, dim3(grid_for(c.pp.n, 256, 1ll << 30)), dim3(256), 0, st, c.pp, vt,
+                           at<PoseF64>(c.ws, L.poses), at<uint32_t>(c.ws, L.cnt), at<uint32_t>(c.ws, L.inv), grad2d,
+                           go, posepart, (const int64_t *)counters);
+    if (go.want_pose)
+        hipLaunchKernelGGL(k_pose_final, dim3(1), dim3(64), 0, st, views->quat, views->trans,
+                           at<PoseF64>(c.ws, L.poses), posepart, views->n_views, *pg);
+    // with the Gaussian gradients off, or for N = 0, the outputs are still defined (zero)
+    if (gg && !go.want_gauss && c.pp.n > 0) {
+        float *ptrs[5] = {gg->means, gg->quats, gg->log_scales, gg->opacity_logits, gg->rgb};
+        const int64_t sz[5] = {3 * c.pp.n, 4 * c.pp.n, (c.pp.iso ? 1 : 3) * c.pp.n, c.pp.n, 3 * c.pp.n};
+        for (int k = 0; k < 5; ++k)
+            if (ptrs[k])
+                hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(sz[k], 256)), dim3(256), 0, st, (uint32_t *)ptrs[k],
+                                   sz[k], 0u);
+    }
+}
+
+gsr_status finish(Call &c, const char *what) {
+    return check_hip(c.ctx, hipGetLastError(), what);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+gsr_status gsr_create(gsr_ctx **out, int device) {
+    if (!out) {
+        g_create_err = "out must not be NULL";
+        return GSR_EINVAL;
+    }
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) {
+        g_create_err = std::string("hipGetDeviceCount: ") + hipGetErrorString(e);
+        return GSR_EHIP;
+    }
+    if (device < 0 || device >= ndev) {
+        g_create_err = "device ordinal out of range";
+        return GSR_EINVAL;
+    }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) {
+        g_create_err = std::string("hipGetDeviceProperties: ") + hipGetErrorString(e);
+        return GSR_EHIP;
+    }
+    gsr_ctx *c = new gsr_ctx;
+    c->device = device;
+    c->num_cus = prop.multiProcessorCount;
+    *out = c;
+    return GSR_OK;
+}
+
+void gsr_destroy(gsr_ctx *ctx) { delete ctx; }
+
+const char *gsr_last_error(const gsr_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+gsr_status gsr_workspace_size(gsr_ctx *ctx, int64_t n, const gsr_views *views, const gsr_options *opts,
+                              int64_t pair_capacity, size_t *bytes) {
+    if (!ctx) return GSR_EINVAL;
+    if (!bytes) return fail(ctx, GSR_EINVAL, "bytes must not be NULL");
+    gsr_status s = validate_views(ctx, views, opts);
+    if (s != GSR_OK) return s;
+    if (n < 0) return fail(ctx, GSR_EINVAL, "n must be >= 0");
+    if (pair_capacity < 0 || pair_capacity >= (int64_t)0xffffffffLL)
+        return fail(ctx, GSR_EINVAL, "pair_capacity must be in [0, 2^32)");
+    if ((int64_t)views->n_views * n >= (int64_t)0xffffffffLL)
+        return fail(ctx, GSR_EUNSUPPORTED, "views x Gaussians must be < 2^32");
+    ViewTable tab;
+    build_table(views, opts, tab);
+    *bytes = make_layout(n, tab, pair_capacity).total;
+    return GSR_OK;
+}
+
+gsr_status gsr_forward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views, const gsr_options *opts,
+                       gsr_workspace ws, gsr_images out, void *stream) {
+    Call c;
+    gsr_status s = prepare(ctx, g, views, opts, ws, stream, c);
+    if (s != GSR_OK) return s;
+    if (!out.rgb || !out.depth || !out.sil) return fail(ctx, GSR_EINVAL, "output images must not be NULL");
+    if (ctx->device >= 0) {
+        s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+        if (s != GSR_OK) return s;
+    }
+    enqueue_binning(c, views);
+    enqueue_blend_fwd(c, out);
+    return finish(c, "gsr_forward launch");
+}
+
+gsr_status gsr_backward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views, const gsr_options *opts,
+                        gsr_workspace ws, gsr_images out, const float *g_rgb, const float *g_depth,
+                        const float *g_sil, gsr_gaussian_grads *gg, gsr_pose_grads *pg, void *stream) {
+    Call c;
+    gsr_status s = prepare(ctx, g, views, opts, ws, stream, c);
+    if (s != GSR_OK) return s;
+    s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (s != GSR_OK) return s;
+    LossIn li;
+    memset(&li, 0, sizeof(li));
+    li.g_rgb = g_rgb;
+    li.g_depth = g_depth;
+    li.g_sil = g_sil;
+    enqueue_backward(c, views, opts, out, li, false, gg, pg);
+    return finish(c, "gsr_backward launch");
+}
+
+gsr_status gsr_render_loss_grad(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views,
+                                const gsr_options *opts, const gsr_targets *targets, gsr_workspace ws,
+                                gsr_images out, double *loss, gsr_gaussian_grads *gg, gsr_pose_grads *pg,
+                                void *stream) {
+    Call c;
+    gsr_status s = prepare(ctx, g, views, opts, ws, stream, c);
+    if (s != GSR_OK) return s;
+    if (!out.rgb || !out.depth || !out.sil) return fail(ctx, GSR_EINVAL, "output images must not be NULL");
+    if (!targets || !targets->rgb || !targets->depth) return fail(ctx, GSR_EINVAL, "targets rgb and depth are required");
+    if (!loss) return fail(ctx, GSR_EINVAL, "loss must not be NULL");
+    s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (s != GSR_OK) return s;
+    enqueue_binning(c, views);
+    enqueue_blend_fwd(c, out);
+    LossIn li;
+    memset(&li, 0, sizeof(li));
+    li.t_rgb = targets->rgb;
+    li.t_depth = targets->depth;
+    li.t_sil = targets->sil;
+    li.t_prior = targets->prior;
+    li.t_weight = targets->weight;
+    li.w_rgb = opts->w_rgb;
+    li.w_depth = opts->w_depth;
+    li.w_sil = opts->w_sil;
+    li.w_prior = opts->w_prior;
+    li.sil_thresh = opts->sil_mask_thresh;
+    li.loss = loss;
+    enqueue_backward(c, views, opts, out, li, true, gg, pg);
+    return finish(c, "gsr_render_loss_grad launch");
+}
+
+gsr_status gsr_read_counters(gsr_ctx *ctx, gsr_workspace ws, void *stream, int64_t *n_visible, int64_t *n_pairs,
+                             int32_t *overflow) {
+    if (!ctx) return GSR_EINVAL;
+    if (!ws.ptr) return fail(ctx, GSR_EINVAL, "workspace pointer is NULL");
+    if (ws.bytes < sizeof(int64_t) * kNumCounters) return fail(ctx, GSR_EINVAL, "workspace too small");
+    int64_t h[kNumCounters];
+    gsr_status s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (s != GSR_OK) return s;
+    s = check_hip(ctx, hipMemcpyAsync(h, ws.ptr, sizeof(h), hipMemcpyDeviceToHost, (hipStream_t)stream),
+                  "hipMemcpyAsync(counters)");
+    if (s != GSR_OK) return s;
+    s = check_hip(ctx, hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+    if (s != GSR_OK) return s;
+    if (n_visible) *n_visible = h[kCntVisible];
+    if (n_pairs) *n_pairs = h[kCntPairs];
+    if (overflow) *overflow = (int32_t)h[kCntOverflow];
+    return GSR_OK;
+}
+
+gsr_status gsr_debug_binning(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views, const gsr_options *opts,
+                             gsr_workspace ws, int64_t max_rec, int64_t max_tiles, int64_t max_pairs,
+                             uint32_t *rec_gid, float *rec_xy, float *rec_radius, float *rec_z, uint32_t *ranges,
+                             uint32_t *pair_rec, void *stream) {
+    Call c;
+    gsr_status s = prepare(ctx, g, views, opts, ws, stream, c);
+    if (s != GSR_OK) return s;
+    if (!rec_gid || !rec_xy || !rec_radius || !rec_z || !ranges || !pair_rec)
+        return fail(ctx, GSR_EINVAL, "debug output pointers must not be NULL");
+    s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (s != GSR_OK) return s;
+    const Layout &L = c.L;
+    const int64_t *counters = at<int64_t>(ws, L.counters);
+    hipLaunchKernelGGL(k_debug_records, dim3(grid_for(L.vn, 256, 4096)), dim3(256), 0, c.st, counters,
+                       depth_sorted_gid(c), at<float4>(ws, L.rec), at<uint2>(ws, L.trect), max_rec, rec_gid, rec_xy,
+                       rec_radius, rec_z, c.pp, at<ViewTable>(ws, L.views), at<PoseF64>(ws, L.poses));
+    hipLaunchKernelGGL(k_debug_copy_u32, dim3(grid_for(2 * L.T, 256, 4096)), dim3(256), 0, c.st,
+                       at<uint32_t>(ws, L.ranges), counters, -1, 2 * max_tiles, ranges, 2 * L.T);
+    hipLaunchKernelGGL(k_debug_copy_u32, dim3(grid_for(L.kcap, 256, 4096)), dim3(256), 0, c.st, pair_values(c),
+                       counters, (int)kCntPairsUsed, max_pairs, pair_rec, (int64_t)0);
+    return finish(c, "gsr_debug_binning launch");
+}
+
+gsr_status gsr_selftest(gsr_ctx *ctx, int32_t *failures, void *stream) {
+    if (!ctx) return GSR_EINVAL;
+    if (!failures) return fail(ctx, GSR_EINVAL, "failures must not be NULL");
+    gsr_status s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (s != GSR_OK) return s;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, (hipStream_t)stream, (uint32_t *)failures, (int64_t)1, 0u);
+    hipLaunchKernelGGL(k_selftest, dim3(1), dim3(64), 0, (hipStream_t)stream, (int *)failures);
+    return check_hip(ctx, hipGetLastError(), "gsr_selftest launch");
+}
+
+}  // extern "C"

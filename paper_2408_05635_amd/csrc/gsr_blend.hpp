@@ -1,0 +1,351 @@
+// Front-to-back alpha compositing of RGB (eq. 2), depth (eq. 3) and
+// silhouette (eq. 4), and its reverse-order backward.
+//
+// Work decomposition: one wave64 workgroup per 8x8 pixel block, one pixel per
+// lane.  A block reads the depth-sorted list of the binning tile it lies in,
+// 64 entries at a time: each lane fetches one record and tests exactly whether
+// the record's alpha >= 1/255 ellipse can reach the 8x8 block (with a safety
+// margin, so no contributing entry is ever dropped); survivors are compacted in
+// order into LDS and the wave composites them.  Culling never changes a
+// result, because an entry with alpha < 1/255 at a pixel leaves that pixel's
+// state untouched; it only removes work.
+//
+// Record layout (3 x float4 per visible (view, Gaussian), depth-sorted):
+//   A = (mx_hi, my_hi, mx_lo, my_lo)   mean, split so that px - mx is exact
+//   B = (l11, l21, l22, o)             scaled conic factor and opacity
+//   C = (r, g, b, z)                   colour and camera depth
+#pragma once
+
+#include "gsr_common.hpp"
+
+namespace gsr {
+
+struct BlockPos {
+    int v;            // view
+    int tile;         // tile index within the view
+    int bx0, by0;     // top-left pixel of the 8x8 block
+    bool valid;
+};
+
+// Logical block id from the hardware id: consecutive logical blocks (the
+// sub-blocks of one binning tile, then neighbouring tiles) are placed on the
+// same XCD, whose L2 then holds the tile's records for all of them.
+__device__ __forceinline__ BlockPos locate_block(const ViewTable *vt) {
+    BlockPos bp;
+    const int32_t G = vt->total_blocks;
+    const int32_t per = (G + 7) >> 3;
+    const int32_t bid = (int32_t)(blockIdx.x & 7u) * per + (int32_t)(blockIdx.x >> 3);
+    bp.valid = bid < G;
+    if (!bp.valid) return bp;
+    bp.v = view_of_block(vt, bid);
+    const ViewInfo &V = vt->v[bp.v];
+    const int sx = vt->tile_w / kBlk, sy = vt->tile_h / kBlk;
+    const int local = bid - V.blk_off;
+    const int tile = local / (sx * sy);
+    const int sub = local - tile * (sx * sy);
+    const int ty = tile / V.tiles_x, tx = tile - ty * V.tiles_x;
+    bp.tile = tile;
+    bp.bx0 = tx * vt->tile_w + (sub % sx) * kBlk;
+    bp.by0 = ty * vt->tile_h + (sub / sx) * kBlk;
+    bp.valid = bp.bx0 < V.W && bp.by0 < V.H;
+    return bp;
+}
+
+// Can the record reach alpha >= 1/255 anywhere in the 8x8 block?  The
+// quadratic form Q = (l11 dx + l21 dy)^2 + (l22 dy)^2 is minimised over the
+// block's box: zero if the mean is inside, else the least value along the four
+// edges (each edge's minimiser is the clamped 1-D minimiser).  Kept when
+// Q_min <= log2(255 o) with a relative margin of 2^-8, far above FP32 rounding.
+__device__ __forceinline__ bool block_may_contribute(const float4 A, const float4 B, float bx0, float by0) {
+    const float o = B.w;
+    if (!(255.0f * o > 1.0f)) return false;
+    const float qcut = __builtin_amdgcn_logf(255.0f * o);   // log2
+    const float mx = A.x + A.z, my = A.y + A.w;
+    const float dx0 = bx0 - mx, dx1 = bx0 + (float)(kBlk - 1) - mx;
+    const float dy0 = by0 - my, dy1 = by0 + (float)(kBlk - 1) - my;
+    if (dx0 <= 0.0f && dx1 >= 0.0f && dy0 <= 0.0f && dy1 >= 0.0f) return true;
+    const float l11 = B.x, l21 = B.y, l22 = B.z;
+    const float qa = l11 * l11, qb = l11 * l21, qc = l21 * l21 + l22 * l22;
+    auto Q = [&](float dx, float dy) {
+        const float u = l11 * dx + l21 * dy, w = l22 * dy;
+        return u * u + w * w;
+    };
+    auto clampf = [](float x, float lo, float hi) { return fminf(fmaxf(x, lo), hi); };
+    float q = Q(dx0, clampf(-qb * dx0 / qc, dy0, dy1));
+    q = fminf(q, Q(dx1, clampf(-qb * dx1 / qc, dy0, dy1)));
+    q = fminf(q, Q(clampf(-qb * dy0 / qa, dx0, dx1), dy0));
+    q = fminf(q, Q(clampf(-qb * dy1 / qa, dx0, dx1), dy1));
+    return q <= qcut * (1.0f + 0x1p-8f) + 0x1p-10f;
+}
+
+// alpha of one record at one pixel; identical instruction sequence in the
+// forward and the backward kernels (explicit fma, no contraction), so both
+// take the same decisions.
+struct AlphaEval {
+    float dx, dy, u, w, G, alpha;
+    bool clamped;
+};
+
+__device__ __forceinline__ AlphaEval eval_alpha(const float4 A, const float4 B, float px, float py) {
+#pragma clang fp contract(off)
+    AlphaEval e;
+    e.dx = __fsub_rn(__fsub_rn(px, A.x), A.z);
+    e.dy = __fsub_rn(__fsub_rn(py, A.y), A.w);
+    e.u = __builtin_fmaf(B.y, e.dy, __fmul_rn(B.x, e.dx));
+    e.w = __fmul_rn(B.z, e.dy);
+    const float p2 = -__builtin_fmaf(e.u, e.u, __fmul_rn(e.w, e.w));
+    e.G = __builtin_amdgcn_exp2f(p2);
+    const float og = __fmul_rn(B.w, e.G);
+    e.clamped = og > kAlphaMax;
+    e.alpha = e.clamped ? kAlphaMax : og;
+    return e;
+}
+
+struct BlendOut {
+    float *rgb, *depth, *sil;   // images
+    float *t_final;             // per pixel
+    uint32_t *n_last;           // per pixel: list position + 1 of the last contributor (0: none)
+};
+
+__global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ vt, const float4 *__restrict__ rec,
+                                                  const uint32_t *__restrict__ pair_rec,
+                                                  const uint2 *__restrict__ ranges, const int64_t *__restrict__ counters,
+                                                  BlendOut out) {
+    __shared__ float4 s_a[64], s_b[64], s_c[64];
+    __shared__ uint32_t s_pos[64];
+    const BlockPos bp = locate_block(vt);
+    if (!bp.valid) return;
+    const ViewInfo &V = vt->v[bp.v];
+    const uint32_t lane = threadIdx.x;
+    const int px = bp.bx0 + (int)(lane & 7u), py = bp.by0 + (int)(lane >> 3);
+    const bool inside = px < V.W && py < V.H;
+    const float fpx = (float)px, fpy = (float)py;
+    uint2 rg = ranges[V.tile_off + bp.tile];
+    const uint32_t n_rec = (uint32_t)counters[kCntVisible];
+    const uint32_t n_pair = (uint32_t)counters[kCntPairsUsed];
+    if (rg.y > n_pair || rg.x > rg.y) rg = make_uint2(0u, 0u);   // never expected; keeps reads in bounds
+
+    float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, cd = 0.0f, cs = 0.0f;
+    uint32_t last = 0;
+    bool done = !inside;
+    for (uint32_t c = rg.x; c < rg.y; c += 64) {
+        if (ballot(!done) == 0) break;
+        const uint32_t e = c + lane;
+        bool keep = false;
+        float4 A, B, C;
+        if (e < rg.y && pair_rec[e] < n_rec) {
+            const uint32_t s = pair_rec[e];
+            A = rec[3 * (size_t)s];
+            B = rec[3 * (size_t)s + 1];
+            C = rec[3 * (size_t)s + 2];
+            keep = block_may_contribute(A, B, (float)bp.bx0, (float)bp.by0);
+        }
+        const uint64_t m = ballot(keep);
+        if (keep) {
+            const uint32_t slot = rank_below(m);
+            s_a[slot] = A;
+            s_b[slot] = B;
+            s_c[slot] = C;
+            s_pos[slot] = e;
+        }
+        __syncthreads();
+        const int n = __popcll(m);
+        for (int k = 0; k < n; ++k) {
+            if (!done) {
+                const AlphaEval ev = eval_alpha(s_a[k], s_b[k], fpx, fpy);
+                if (ev.alpha >= kAlphaMin) {
+                    const float Tn = T * (1.0f - ev.alpha);
+                    if (Tn < kTMin) {
+                        done = true;
+                    } else {
+                        const float4 cc = s_c[k];
+                        const float wgt = ev.alpha * T;
+                        c0 = __builtin_fmaf(wgt, cc.x, c0);
+                        c1 = __builtin_fmaf(wgt, cc.y, c1);
+                        c2 = __builtin_fmaf(wgt, cc.z, c2);
+                        cd = __builtin_fmaf(wgt, cc.w, cd);
+                        cs += wgt;
+                        T = Tn;
+                        last = s_pos[k] + 1u;
+                    }
+                }
+            }
+            if ((k & 7) == 7 && ballot(!done) == 0) break;
+        }
+        __syncthreads();
+    }
+    if (inside) {
+        const int64_t P = (int64_t)V.W * V.H;
+        const int64_t pix = (int64_t)py * V.W + px;
+        out.rgb[3 * V.pix_off + pix] = c0;
+        out.rgb[3 * V.pix_off + P + pix] = c1;
+        out.rgb[3 * V.pix_off + 2 * P + pix] = c2;
+        out.depth[V.pix_off + pix] = cd;
+        out.sil[V.pix_off + pix] = cs;
+        out.t_final[V.pix_off + pix] = T;
+        out.n_last[V.pix_off + pix] = last;
+    }
+}
+
+// Loss weights and targets for the fused loss, or upstream image gradients.
+struct LossIn {
+    const float *t_rgb, *t_depth, *t_sil, *t_prior, *t_weight;
+    float w_rgb, w_depth, w_sil, w_prior, sil_thresh;
+    const float *g_rgb, *g_depth, *g_sil;   // upstream dL/dimage (split backward)
+    double *loss;                           // [V] (fused)
+};
+
+__device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.0f) - (x < 0.0f)); }
+
+template <bool FUSED>
+__global__ __launch_bounds__(64) void k_blend_bwd(const ViewTable *__restrict__ vt, const float4 *__restrict__ rec,
+                                                  const uint32_t *__restrict__ pair_rec,
+                                                  const uint2 *__restrict__ ranges, const int64_t *__restrict__ counters,
+                                                  BlendOut st, LossIn L, float *__restrict__ grad2d) {
+    __shared__ float4 s_a[64], s_b[64], s_c[64];
+    __shared__ uint32_t s_pos[64], s_id[64];
+    const BlockPos bp = locate_block(vt);
+    if (!bp.valid) return;
+    const ViewInfo &V = vt->v[bp.v];
+    const uint32_t lane = threadIdx.x;
+    const int px = bp.bx0 + (int)(lane & 7u), py = bp.by0 + (int)(lane >> 3);
+    const bool inside = px < V.W && py < V.H;
+    const float fpx = (float)px, fpy = (float)py;
+    const int64_t P = (int64_t)V.W * V.H;
+    const int64_t pix = (int64_t)py * V.W + px;
+    const int64_t gp = V.pix_off + pix;
+
+    // dL/d(r, g, b, depth, silhouette) at this pixel
+    float g[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    float T = 1.0f;
+    uint32_t last = 0;
+    double lp = 0.0;   // this pixel's loss term (fused)
+    if (inside) {
+        T = st.t_final[gp];
+        last = st.n_last[gp];
+        if (FUSED) {
+            const float wgt = L.t_weight ? L.t_weight[gp] : 1.0f;
+            if (wgt != 0.0f) {
+                const float C0 = st.rgb[3 * V.pix_off + pix], C1 = st.rgb[3 * V.pix_off + P + pix],
+                            C2 = st.rgb[3 * V.pix_off + 2 * P + pix];
+                const float D = st.depth[gp], S = st.sil[gp];
+                const float r0 = C0 - L.t_rgb[3 * V.pix_off + pix];
+                const float r1 = C1 - L.t_rgb[3 * V.pix_off + P + pix];
+                const float r2 = C2 - L.t_rgb[3 * V.pix_off + 2 * P + pix];
+                const float td = L.t_depth[gp];
+                const float rd = D - td;
+                const float rs = S - (L.t_sil ? L.t_sil[gp] : 0.0f);
+                const float tp = L.t_prior ? L.t_prior[gp] : 0.0f;
+                const float rp = D - tp;
+                const float trk = (L.sil_thresh >= 0.0f) ? (S > L.sil_thresh ? 1.0f : 0.0f) : 1.0f;
+                const float dm = td > 0.0f ? 1.0f : 0.0f;
+                const float dpr = tp > 0.0f ? 1.0f : 0.0f;
+                const float sc = wgt / (float)P;
+                const double scd = (double)wgt / (double)P;
+                lp = scd * ((double)(trk * dm) * ((double)L.w_rgb * (fabs((double)r0) + fabs((double)r1) + fabs((double)r2)) +
+                                                   (double)L.w_depth * fabs((double)rd)) +
+                            (double)L.w_sil * fabs((double)rs) + (double)(trk * dpr) * (double)L.w_prior * fabs((double)rp));
+                g[0] = sc * trk * dm * L.w_rgb * sgnf(r0);
+                g[1] = sc * trk * dm * L.w_rgb * sgnf(r1);
+                g[2] = sc * trk * dm * L.w_rgb * sgnf(r2);
+                g[3] = sc * (trk * dm * L.w_depth * sgnf(rd) + trk * dpr * L.w_prior * sgnf(rp));
+                g[4] = sc * L.w_sil * sgnf(rs);
+            }
+        } else {
+            if (L.g_rgb) {
+                g[0] = L.g_rgb[3 * V.pix_off + pix];
+                g[1] = L.g_rgb[3 * V.pix_off + P + pix];
+                g[2] = L.g_rgb[3 * V.pix_off + 2 * P + pix];
+            }
+            if (L.g_depth) g[3] = L.g_depth[gp];
+            if (L.g_sil) g[4] = L.g_sil[gp];
+        }
+    }
+    if (FUSED) {   // all 64 lanes take part in the reduction
+        const double tot = wave_sum_f64(lp);
+        if (lane == 0 && tot != 0.0) atomicAdd(&L.loss[bp.v], tot);
+    }
+    if (!(g[0] != 0.f || g[1] != 0.f || g[2] != 0.f || g[3] != 0.f || g[4] != 0.f)) last = 0;
+    uint32_t max_last = wave_max_u32(last);
+    if (max_last == 0) return;
+
+    uint2 rg = ranges[V.tile_off + bp.tile];
+    const uint32_t n_rec = (uint32_t)counters[kCntVisible];
+    const uint32_t n_pair = (uint32_t)counters[kCntPairsUsed];
+    if (rg.y > n_pair || rg.x > rg.y) rg = make_uint2(0u, 0u);   // never expected; keeps reads in bounds
+    // accumulated colour of everything behind the current entry, per unit of
+    // the transmittance just after it
+    float b0 = 0.f, b1 = 0.f, b2 = 0.f, bd = 0.f, bs = 0.f;
+    for (uint32_t hi = max_last; hi > rg.x;) {
+        const uint32_t lo = hi - rg.x > 64u ? hi - 64u : rg.x;
+        const uint32_t e = lo + lane;
+        bool keep = false;
+        float4 A, B, C;
+        uint32_t s = 0;
+        if (e < hi && pair_rec[e] < n_rec) {
+            s = pair_rec[e];
+            A = rec[3 * (size_t)s];
+            B = rec[3 * (size_t)s + 1];
+            C = rec[3 * (size_t)s + 2];
+            keep = block_may_contribute(A, B, (float)bp.bx0, (float)bp.by0);
+        }
+        const uint64_t m = ballot(keep);
+        if (keep) {
+            const uint32_t slot = rank_below(m);
+            s_a[slot] = A;
+            s_b[slot] = B;
+            s_c[slot] = C;
+            s_pos[slot] = e;
+            s_id[slot] = s;
+        }
+        __syncthreads();
+        for (int k = __popcll(m) - 1; k >= 0; --k) {
+            const float4 a = s_a[k], b = s_b[k];
+            float d[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            bool contrib = false;
+            if (s_pos[k] < last) {
+                const AlphaEval ev = eval_alpha(a, b, fpx, fpy);
+                if (ev.alpha >= kAlphaMin) {
+                    contrib = true;
+                    const float4 cc = s_c[k];
+                    const float oma = 1.0f - ev.alpha;
+                    T = T * __builtin_amdgcn_rcpf(oma);   // transmittance in front of this entry
+                    const float wgt = ev.alpha * T;
+                    d[6] = g[0] * wgt;
+                    d[7] = g[1] * wgt;
+                    d[8] = g[2] * wgt;
+                    d[9] = g[3] * wgt;
+                    const float dal = T * (g[0] * (cc.x - b0) + g[1] * (cc.y - b1) + g[2] * (cc.z - b2) +
+                                           g[3] * (cc.w - bd) + g[4] * (1.0f - bs));
+                    b0 = ev.alpha * cc.x + oma * b0;
+                    b1 = ev.alpha * cc.y + oma * b1;
+                    b2 = ev.alpha * cc.z + oma * b2;
+                    bd = ev.alpha * cc.w + oma * bd;
+                    bs = ev.alpha + oma * bs;
+                    if (!ev.clamped) {
+                        d[5] = dal * ev.G;
+                        const float dp2 = dal * ev.alpha * (float)kLn2f;
+                        const float tu = 2.0f * ev.u * dp2, tw = 2.0f * ev.w * dp2;
+                        d[0] = tu * b.x;
+                        d[1] = tu * b.y + tw * b.z;
+                        d[2] = -tu * ev.dx;
+                        d[3] = -tu * ev.dy;
+                        d[4] = -tw * ev.dy;
+                    }
+                }
+            }
+            if (ballot(contrib) != 0) {
+                float *dst = grad2d + 10 * (size_t)s_id[k];
+#pragma unroll
+                for (int c = 0; c < 10; ++c) {
+                    const float t = wave_sum_to63(d[c]);
+                    if (lane == 63 && t != 0.0f) atomicAdd(dst + c, t);
+                }
+            }
+        }
+        __syncthreads();
+        hi = lo;
+    }
+}
+
+}  // namespace gsr

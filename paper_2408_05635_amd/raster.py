@@ -1,0 +1,369 @@
+"""Torch-facing interface of the HIP rasteriser.
+
+torch provides device memory and the stream; every step of the path
+(projection, binning, sorting, compositing, loss, backward) runs in
+libgsr.so.  There is no CPU or PyTorch fallback: if the library is missing
+the import-time load fails loudly.
+
+Conventions (the C ABI's, include/gsr.h): Gaussian parameters are raw
+(means [N,3], quats [N,4] wxyz, log_scales [N,3] or [N,1], opacity_logits
+[N], rgb [N,3]); poses are world-to-camera quats [V,4] (wxyz) and trans
+[V,3]; images of several views are concatenated, RGB planar per view.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+from . import _abi
+
+_ABI = _abi.load()
+
+
+@dataclass
+class RenderOptions:
+    """Loss weights and rasteriser settings (the ABI's gsr_options)."""
+    w_rgb: float = 0.5
+    w_depth: float = 1.0
+    w_sil: float = 1.0
+    w_prior: float = 0.0
+    z_near: float = 0.2
+    blur2d: float = 0.3
+    sil_mask_thresh: float = -1.0
+    tile: Tuple[int, int] = (16, 16)
+    gauss_grads: bool = True
+    pose_grads: bool = True
+
+
+@dataclass
+class GaussianParams:
+    means: torch.Tensor
+    quats: torch.Tensor
+    log_scales: torch.Tensor
+    opacity_logits: torch.Tensor
+    rgb: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @property
+    def isotropic(self) -> bool:
+        return self.log_scales.dim() == 2 and self.log_scales.shape[1] == 1
+
+    def tensors(self):
+        return (self.means, self.quats, self.log_scales, self.opacity_logits, self.rgb)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check_f32(name: str, t: torch.Tensor, shape, device):
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32 (got {t.dtype})")
+    if not t.is_cuda or t.device != device:
+        raise ValueError(f"{name} must be on {device} (got {t.device})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _stream_ptr():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def total_pixels(cams: Sequence) -> int:
+    return int(sum(c.width * c.height for c in cams))
+
+
+class Rasterizer:
+    """Owns a library context and a reusable workspace on one GPU.
+
+    The pair capacity (number of (Gaussian, tile) pairs the workspace holds)
+    grows automatically when a checked call overflows it.
+    """
+
+    def __init__(self, device=None, pair_capacity: int = 1 << 20):
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else torch.device(device).index or 0)
+        self.device = dev
+        h = C.c_void_p()
+        st = _ABI.gsr_create(C.byref(h), dev.index)
+        _abi.check(st, None)
+        self._ctx = h
+        self.pair_capacity = int(pair_capacity)
+        self._ws: Optional[torch.Tensor] = None
+        self.last_counters = (0, 0, 0)
+
+    def __del__(self):
+        try:
+            if getattr(self, "_ctx", None):
+                _ABI.gsr_destroy(self._ctx)
+                self._ctx = None
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ marshalling
+    def _views(self, cams, quat, trans):
+        V = len(cams)
+        arr = (_abi.Camera * V)()
+        for k, c in enumerate(cams):
+            arr[k] = _abi.Camera(int(c.width), int(c.height), float(c.fx), float(c.fy), float(c.cx), float(c.cy))
+        _check_f32("pose quat", quat, (V, 4), self.device)
+        _check_f32("pose trans", trans, (V, 3), self.device)
+        return _abi.Views(V, arr, _ptr(quat), _ptr(trans)), arr
+
+    def _gauss(self, g: GaussianParams):
+        n = g.n
+        _check_f32("means", g.means, (n, 3), self.device)
+        _check_f32("quats", g.quats, (n, 4), self.device)
+        _check_f32("log_scales", g.log_scales, (n, 1) if g.isotropic else (n, 3), self.device)
+        _check_f32("opacity_logits", g.opacity_logits, (n,), self.device)
+        _check_f32("rgb", g.rgb, (n, 3), self.device)
+        return _abi.Gaussians(n, *[_ptr(t) for t in g.tensors()])
+
+    @staticmethod
+    def _opts(o: RenderOptions, iso: bool, gauss_grads=None, pose_grads=None):
+        flags = 0
+        if iso:
+            flags |= _abi.GSR_ISOTROPIC
+        if not (o.gauss_grads if gauss_grads is None else gauss_grads):
+            flags |= _abi.GSR_NO_GAUSS_GRADS
+        if not (o.pose_grads if pose_grads is None else pose_grads):
+            flags |= _abi.GSR_NO_POSE_GRADS
+        return _abi.Options(o.w_rgb, o.w_depth, o.w_sil, o.w_prior, o.z_near, o.blur2d, o.sil_mask_thresh,
+                            int(o.tile[0]), int(o.tile[1]), flags)
+
+    def workspace_bytes(self, n: int, views, opts, capacity: int) -> int:
+        out = C.c_size_t()
+        _abi.check(_ABI.gsr_workspace_size(self._ctx, n, C.byref(views), C.byref(opts), capacity, C.byref(out)),
+                   self._ctx)
+        return int(out.value)
+
+    def new_workspace(self, n: int, views, opts, capacity: int) -> Tuple[torch.Tensor, _abi.Workspace]:
+        nbytes = self.workspace_bytes(n, views, opts, capacity)
+        buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return buf, _abi.Workspace(buf.data_ptr(), nbytes, capacity)
+
+    def _shared_ws(self, n: int, views, opts) -> _abi.Workspace:
+        nbytes = self.workspace_bytes(n, views, opts, self.pair_capacity)
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return _abi.Workspace(self._ws.data_ptr(), self._ws.numel(), self.pair_capacity)
+
+    def read_counters(self, ws: _abi.Workspace) -> Tuple[int, int, int]:
+        m, k, o = C.c_int64(), C.c_int64(), C.c_int32()
+        _abi.check(_ABI.gsr_read_counters(self._ctx, ws, _stream_ptr(), C.byref(m), C.byref(k), C.byref(o)),
+                   self._ctx)
+        self.last_counters = (int(m.value), int(k.value), int(o.value))
+        return self.last_counters
+
+    def _grow(self, needed: int) -> None:
+        self.pair_capacity = max(int(needed * 1.25) + 1024, self.pair_capacity)
+
+    # ------------------------------------------------------------------ calls
+    def render_loss_grad(self, g: GaussianParams, quat: torch.Tensor, trans: torch.Tensor, cams: Sequence,
+                         targets: dict, opts: RenderOptions = RenderOptions(), check: bool = True,
+                         out: Optional[dict] = None):
+        """Forward + fused loss + backward.  Returns a dict with rgb, depth, sil,
+        loss [V] (float64) and the gradients (None where switched off).
+        With check=True the call synchronises once to verify the pair
+        capacity (and re-runs after growing it if needed); pass check=False
+        for capture in a graph or for timing loops, and verify afterwards."""
+        views, keep = self._views(cams, quat, trans)
+        gs = self._gauss(g)
+        o = self._opts(opts, g.isotropic)
+        P = total_pixels(cams)
+        V = len(cams)
+        if out is None:
+            out = self.alloc_outputs(g, V, P, opts)
+        tg = _abi.Targets(_ptr(targets["rgb"]), _ptr(targets["depth"]), _ptr(targets.get("sil")),
+                          _ptr(targets.get("prior")), _ptr(targets.get("weight")))
+        for k in ("rgb", "depth", "sil", "prior", "weight"):
+            t = targets.get(k)
+            if t is not None:
+                _check_f32(f"target {k}", t, (3 * P,) if k == "rgb" else (P,), self.device)
+        while True:
+            ws = self._shared_ws(g.n, views, o)
+            imgs = _abi.Images(_ptr(out["rgb"]), _ptr(out["depth"]), _ptr(out["sil"]))
+            gg = _abi.GaussGrads(*[_ptr(out.get(k)) for k in ("g_means", "g_quats", "g_log_scales",
+                                                                "g_opacity_logits", "g_rgb")])
+            pg = _abi.PoseGrads(*[_ptr(out.get(k)) for k in ("dq_t", "dt", "dq_c", "dc")])
+            st = _ABI.gsr_render_loss_grad(self._ctx, C.byref(gs), C.byref(views), C.byref(o), C.byref(tg), ws,
+                                           imgs, _ptr(out["loss"]), C.byref(gg), C.byref(pg), _stream_ptr())
+            _abi.check(st, self._ctx)
+            if not check:
+                break
+            _, k, ovf = self.read_counters(ws)
+            if not ovf:
+                break
+            self._grow(k)
+        return out
+
+    def alloc_outputs(self, g: GaussianParams, V: int, P: int, opts: RenderOptions) -> dict:
+        dev = self.device
+        e = lambda *s: torch.empty(*s, dtype=torch.float32, device=dev)  # noqa: E731
+        out = dict(rgb=e(3 * P), depth=e(P), sil=e(P), loss=torch.empty(V, dtype=torch.float64, device=dev))
+        n = g.n
+        if opts.gauss_grads:
+            out.update(g_means=e(n, 3), g_quats=e(n, 4), g_log_scales=e(*g.log_scales.shape),
+                       g_opacity_logits=e(n), g_rgb=e(n, 3))
+        if opts.pose_grads:
+            out.update(dq_t=e(V, 4), dt=e(V, 3), dq_c=e(V, 4), dc=e(V, 3))
+        return out
+
+    def forward(self, g: GaussianParams, quat, trans, cams, opts: RenderOptions = RenderOptions(),
+                ws_pair: Optional[Tuple[torch.Tensor, _abi.Workspace]] = None, check: bool = True):
+        """Render only.  Returns (rgb, depth, sil, (ws_tensor, ws)): the
+        workspace holds the state that backward() needs."""
+        views, keep = self._views(cams, quat, trans)
+        gs = self._gauss(g)
+        o = self._opts(opts, g.isotropic)
+        P = total_pixels(cams)
+        rgb = torch.empty(3 * P, dtype=torch.float32, device=self.device)
+        depth = torch.empty(P, dtype=torch.float32, device=self.device)
+        sil = torch.empty(P, dtype=torch.float32, device=self.device)
+        while True:
+            if ws_pair is None:
+                ws_pair = self.new_workspace(g.n, views, o, self.pair_capacity)
+            imgs = _abi.Images(_ptr(rgb), _ptr(depth), _ptr(sil))
+            _abi.check(_ABI.gsr_forward(self._ctx, C.byref(gs), C.byref(views), C.byref(o), ws_pair[1], imgs,
+                                        _stream_ptr()), self._ctx)
+            if not check:
+                break
+            _, k, ovf = self.read_counters(ws_pair[1])
+            if not ovf:
+                break
+            self._grow(k)
+            ws_pair = None
+        return rgb, depth, sil, ws_pair
+
+    def backward(self, g: GaussianParams, quat, trans, cams, opts: RenderOptions, ws_pair, images,
+                 g_rgb=None, g_depth=None, g_sil=None, gauss_grads: bool = True, pose_grads: bool = True):
+        """Backward of forward(): upstream image gradients -> parameter and pose gradients."""
+        views, keep = self._views(cams, quat, trans)
+        gs = self._gauss(g)
+        o = self._opts(opts, g.isotropic, gauss_grads, pose_grads)
+        P = total_pixels(cams)
+        V = len(cams)
+        for name, t, shp in (("g_rgb", g_rgb, (3 * P,)), ("g_depth", g_depth, (P,)), ("g_sil", g_sil, (P,))):
+            if t is not None:
+                _check_f32(name, t, shp, self.device)
+        dev = self.device
+        e = lambda *s: torch.empty(*s, dtype=torch.float32, device=dev)  # noqa: E731
+        gr = {}
+        if gauss_grads:
+            gr = dict(means=e(g.n, 3), quats=e(g.n, 4), log_scales=e(*g.log_scales.shape),
+                      opacity_logits=e(g.n), rgb=e(g.n, 3))
+        pr = {}
+        if pose_grads:
+            pr = dict(dq_t=e(V, 4), dt=e(V, 3), dq_c=e(V, 4), dc=e(V, 3))
+        gg = _abi.GaussGrads(*[_ptr(gr.get(k)) for k in ("means", "quats", "log_scales", "opacity_logits", "rgb")])
+        pg = _abi.PoseGrads(*[_ptr(pr.get(k)) for k in ("dq_t", "dt", "dq_c", "dc")])
+        imgs = _abi.Images(*[_ptr(t) for t in images])
+        _abi.check(_ABI.gsr_backward(self._ctx, C.byref(gs), C.byref(views), C.byref(o), ws_pair[1], imgs,
+                                     _ptr(g_rgb), _ptr(g_depth), _ptr(g_sil), C.byref(gg), C.byref(pg),
+                                     _stream_ptr()), self._ctx)
+        return gr, pr
+
+    def debug_binning(self, g: GaussianParams, quat, trans, cams, opts: RenderOptions, ws: _abi.Workspace):
+        """Copies the binning state of the last call on ws (for bit-exact tests)."""
+        views, keep = self._views(cams, quat, trans)
+        gs = self._gauss(g)
+        o = self._opts(opts, g.isotropic)
+        M, K, ovf = self.read_counters(ws)
+        tw, th = opts.tile
+        T = sum(((c.width + tw - 1) // tw) * ((c.height + th - 1) // th) for c in cams)
+        dev = self.device
+        gid = torch.empty(max(M, 1), dtype=torch.int32, device=dev)
+        xy = torch.empty(max(M, 1), 2, dtype=torch.float32, device=dev)
+        rad = torch.empty(max(M, 1), dtype=torch.float32, device=dev)
+        z = torch.empty(max(M, 1), dtype=torch.float32, device=dev)
+        ranges = torch.empty(max(T, 1), 2, dtype=torch.int32, device=dev)
+        pairs = torch.empty(max(K, 1), dtype=torch.int32, device=dev)
+        _abi.check(_ABI.gsr_debug_binning(self._ctx, C.byref(gs), C.byref(views), C.byref(o), ws, M, T, K,
+                                          _ptr(gid), _ptr(xy), _ptr(rad), _ptr(z), _ptr(ranges), _ptr(pairs),
+                                          _stream_ptr()), self._ctx)
+        torch.cuda.current_stream().synchronize()
+        return dict(M=M, K=K, overflow=ovf, gid=gid[:M].cpu(), xy=xy[:M].cpu(), radius=rad[:M].cpu(),
+                    z=z[:M].cpu(), ranges=ranges[:T].cpu(), pairs=pairs[:K].cpu())
+
+    def selftest(self) -> int:
+        d = torch.empty(1, dtype=torch.int32, device=self.device)
+        _abi.check(_ABI.gsr_selftest(self._ctx, _ptr(d), _stream_ptr()), self._ctx)
+        return int(d.item())
+
+
+# ---------------------------------------------------------------------------
+# autograd
+# ---------------------------------------------------------------------------
+class _RenderFn(torch.autograd.Function):
+    """Images as a differentiable function of the Gaussians and the poses.
+    The workspace holding the forward state travels in ctx."""
+
+    @staticmethod
+    def forward(ctx, means, quats, log_scales, opacity_logits, rgb, pose_q, pose_t, rast, cams, opts):
+        g = GaussianParams(means.detach(), quats.detach(), log_scales.detach(), opacity_logits.detach(),
+                           rgb.detach())
+        img, depth, sil, ws_pair = rast.forward(g, pose_q.detach(), pose_t.detach(), cams, opts)
+        ctx.rast, ctx.cams, ctx.opts, ctx.ws_pair = rast, cams, opts, ws_pair
+        ctx.save_for_backward(means, quats, log_scales, opacity_logits, rgb, pose_q, pose_t, img, depth, sil)
+        return img, depth, sil
+
+    @staticmethod
+    def backward(ctx, g_img, g_depth, g_sil):
+        means, quats, log_scales, opacity_logits, rgb, pose_q, pose_t, img, depth, sil = ctx.saved_tensors
+        g = GaussianParams(means, quats, log_scales, opacity_logits, rgb)
+        need_g = any(ctx.needs_input_grad[:5])
+        need_p = any(ctx.needs_input_grad[5:7])
+        cont = lambda t: None if t is None else t.contiguous()  # noqa: E731
+        gr, pr = ctx.rast.backward(g, pose_q, pose_t, ctx.cams, ctx.opts, ctx.ws_pair, (img, depth, sil),
+                                   cont(g_img), cont(g_depth), cont(g_sil), gauss_grads=need_g, pose_grads=need_p)
+        ctx.ws_pair = None
+        gq = pr.get("dq_t")
+        gt = pr.get("dt")
+        return (gr.get("means"), gr.get("quats"), gr.get("log_scales"), gr.get("opacity_logits"), gr.get("rgb"),
+                gq, gt, None, None, None)
+
+
+def render(rast: Rasterizer, g: GaussianParams, pose_q: torch.Tensor, pose_t: torch.Tensor, cams: Sequence,
+           opts: RenderOptions = RenderOptions()):
+    """(rgb [3*sumP], depth [sumP], sil [sumP]) with autograd to every input tensor."""
+    return _RenderFn.apply(g.means, g.quats, g.log_scales, g.opacity_logits, g.rgb, pose_q, pose_t, rast,
+                           list(cams), opts)
+
+
+class _RenderLossFn(torch.autograd.Function):
+    """The fused paper loss: forward computes the loss and, in the same
+    kernels, all its gradients; backward scales them by the upstream scalar."""
+
+    @staticmethod
+    def forward(ctx, means, quats, log_scales, opacity_logits, rgb, pose_q, pose_t, rast, cams, targets, opts):
+        g = GaussianParams(means.detach(), quats.detach(), log_scales.detach(), opacity_logits.detach(),
+                           rgb.detach())
+        o = RenderOptions(**{**opts.__dict__})
+        o.gauss_grads = any(ctx.needs_input_grad[:5])
+        o.pose_grads = any(ctx.needs_input_grad[5:7])
+        out = rast.render_loss_grad(g, pose_q.detach(), pose_t.detach(), cams, targets, o)
+        ctx.out = out
+        ctx.mark_non_differentiable
+        return out["loss"].sum().to(torch.float32)
+
+    @staticmethod
+    def backward(ctx, gl):
+        out = ctx.out
+        s = lambda k: None if out.get(k) is None else out[k] * gl  # noqa: E731
+        return (s("g_means"), s("g_quats"), s("g_log_scales"), s("g_opacity_logits"), s("g_rgb"), s("dq_t"),
+                s("dt"), None, None, None, None)
+
+
+def render_loss(rast: Rasterizer, g: GaussianParams, pose_q, pose_t, cams, targets: dict,
+                opts: RenderOptions = RenderOptions()):
+    """Scalar loss (sum over views) of the paper's combined objective, differentiable."""
+    return _RenderLossFn.apply(g.means, g.quats, g.log_scales, g.opacity_logits, g.rgb, pose_q, pose_t, rast,
+                               list(cams), targets, opts)
