@@ -1,0 +1,331 @@
+#!/usr/bin/env python3
+"""Throughput of the differentiable Gaussian rasteriser on one MI355X.
+
+Workload (the tracking configuration): a synthetic 4x4x3 m room with 200k
+Gaussians, 8 camera poses along a smooth trajectory, 640x480, f = 525.
+One step = forward + combined L1 loss + backward to every Gaussian
+parameter and to the poses, for all 8 views.  Targets are renders at the
+true poses; the renderer is evaluated at poses 2 deg / 2 cm away.
+
+Reported (one JSON line):
+  value         views/s of the batched path (all views in one launch
+                sequence), full gradients, inputs resident in HBM
+  plain         the same views one at a time (one launch sequence and one
+                pair-count check per view)
+  pose_only     batched, gradients to the poses only (tracking mode)
+  graph         batched, replayed from a captured HIP graph
+  stages_ms     per-stage averages from HIP events on the library's stream
+  roofline      the dominant kernel (the backward blend) against the FP32
+                VALU peak, from counted work
+  cpu_baseline  the FP64 oracle on the host cores, on a bounded sample
+  pose_fd       FP32 central-difference check of the pose gradients
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd views/sec at 640×480, 200k Gaussians (batched vs plain); pose-grad FD err"
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = FP32 VALU lane-operation slots per second
+# (one non-packed FP32 instruction per lane per slot; 157.3 TFLOP/s counts packed FMA as 4 FLOP)
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+HBM_PEAK_GBS = 8000.0
+# algorithmic FP32 lane-op slots per (pixel, Gaussian) pair of the blend,
+# transcendental ops at quarter rate (4 slots): see the roofline section of the design notes
+C_ALPHA = 17     # dx, dy (split mean), factor products, exp2, opacity, clamp, 1/255 test
+C_BLEND = 10     # transmittance update, stop test, 4 channel FMAs + silhouette, position
+C_GRAD = 45      # transmittance recovery (rcp), dL/dalpha, behind-accumulators, 10 partials
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=200_000)
+    ap.add_argument("--views", type=int, default=8)
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--cpu-views", type=int, default=8, help="views in the oracle's timed sample")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="only run this many batched steps (for a profiler) and print nothing else")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2408_05635_amd import raster, scenes
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    tw, th = (int(x) for x in args.tile.split("x"))
+    w = scenes.config2(n_views=args.views, n=args.n)
+    t32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)  # noqa: E731
+    G = w.gaussians
+    g = raster.GaussianParams(t32(G.means), t32(G.quats), t32(G.log_scales), t32(G.opacity_logits), t32(G.rgb))
+    q, t = t32(w.views.quat), t32(w.views.trans)
+    qt, tt = t32(w.target_views.quat), t32(w.target_views.trans)
+    cams = w.views.cams
+    V = len(cams)
+    P = sum(c.width * c.height for c in cams)
+    opts = raster.RenderOptions(tile=(tw, th), **w.weights)
+    rast = raster.Rasterizer(0)
+
+    # targets: renders at the true poses (inputs of the workload)
+    trgb, tdep, tsil, _ = rast.forward(g, qt, tt, cams, opts)
+    targets = dict(rgb=trgb, depth=tdep, sil=tsil)
+    out = rast.render_loss_grad(g, q, t, cams, targets, opts, check=True)   # sizes the pair capacity
+    torch.cuda.synchronize()
+    M, K, ovf = rast.last_counters
+    assert not ovf
+
+    def batched_step(o=opts, dst=out):
+        rast.render_loss_grad(g, q, t, cams, targets, o, check=False, out=dst)
+
+    if args.profile_steps:
+        for _ in range(args.profile_steps):
+            batched_step()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_steps": args.profile_steps, "pairs": K, "visible": M}), flush=True)
+        return
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    # batched, full gradients; per-stage HIP events recorded over the same region
+    for _ in range(args.warmup):
+        batched_step()
+    torch.cuda.synchronize()
+    rast.read_timing()
+    rast.set_timing(True)
+    ms_batched = timed(batched_step, args.steps, 0)
+    rast.set_timing(False)
+    stages = rast.read_timing()
+    _, _, ovf2 = rast.read_counters(rast.shared_workspace())
+    assert not ovf2, "pair capacity overflowed during the timed region"
+    print(f"[bench] batched {ms_batched:.3f} ms/step ({V * 1000.0 / ms_batched:.1f} views/s)", file=sys.stderr,
+          flush=True)
+    stage_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
+
+    # pose-only (tracking) mode
+    o_pose = raster.RenderOptions(**{**opts.__dict__, "gauss_grads": False})
+    out_pose = rast.alloc_outputs(g, V, P, o_pose)
+    rast.render_loss_grad(g, q, t, cams, targets, o_pose, check=True, out=out_pose)
+    ms_pose = timed(lambda: batched_step(o_pose, out_pose), args.steps, args.warmup)
+    print(f"[bench] pose-only {ms_pose:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # plain: one view per launch sequence, each with its pair-count check
+    plain = None
+    if not args.no_plain:
+        rast1 = raster.Rasterizer(0)   # its own workspace, sized for one view
+        singles = []
+        for v in range(V):
+            tg_v = dict(rgb=trgb[3 * P // V * v:3 * P // V * (v + 1)], depth=tdep[P // V * v:P // V * (v + 1)],
+                        sil=tsil[P // V * v:P // V * (v + 1)])
+            singles.append((q[v:v + 1].contiguous(), t[v:v + 1].contiguous(), [cams[v]], tg_v,
+                            rast1.alloc_outputs(g, 1, P // V, opts)))
+
+        def plain_step():
+            for (qv, tv, cv, tgv, ov) in singles:
+                rast1.render_loss_grad(g, qv, tv, cv, tgv, opts, check=True, out=ov)
+
+        ms_plain = timed(plain_step, args.steps, args.warmup)
+        plain = dict(value=V * 1000.0 / ms_plain, ms_per_step=ms_plain)
+        print(f"[bench] plain {ms_plain:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # batched, replayed from a captured HIP graph
+    graph = None
+    if not args.no_graph:
+        try:
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                batched_step()
+            torch.cuda.current_stream().wait_stream(s)
+            torch.cuda.synchronize()
+            gr = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gr):
+                batched_step()
+            torch.cuda.synchronize()
+            ms_graph = timed(gr.replay, args.steps, args.warmup)
+            ref = out["g_means"].clone()
+            batched_step()
+            torch.cuda.synchronize()
+            dev_max = ((ref.double() - out["g_means"].double()).abs().max() / ref.double().abs().max()).item()
+            graph = dict(value=V * 1000.0 / ms_graph, ms_per_step=ms_graph, rel_diff_vs_eager=dev_max)
+            print(f"[bench] graph {ms_graph:.3f} ms/step", file=sys.stderr, flush=True)
+        except Exception as e:   # reported, not hidden
+            graph = dict(error=str(e)[:200])
+
+    # counted work of one batched step (a separate, untimed call)
+    o_cnt = raster.RenderOptions(**{**opts.__dict__, "count_work": True})
+    rast.render_loss_grad(g, q, t, cams, targets, o_cnt, check=False, out=out)
+    work = rast.read_work()
+    ops_fwd = work["contrib_fwd"] * (C_ALPHA + C_BLEND)
+    ops_bwd = work["contrib_bwd"] * (C_ALPHA + C_GRAD)
+    ops_bwd_list = ops_bwd + (work["eval_bwd"] - work["contrib_bwd"]) * C_ALPHA
+    dom = "blend_bwd" if stage_ms["blend_bwd"] >= stage_ms["blend_fwd"] else "blend_fwd"
+    dom_ops = ops_bwd if dom == "blend_bwd" else ops_fwd
+    dom_ms = stage_ms[dom]
+    achieved = dom_ops / (dom_ms * 1e-3) / 1e12
+    peak = VALU_PEAK_LANE_OPS / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "T lane-op/s",
+                "frac": achieved / peak, "traffic": None,
+                "frac_list": ((ops_bwd_list if dom == "blend_bwd" else ops_fwd) / (dom_ms * 1e-3) / 1e12) / peak,
+                "ops_per_launch": dom_ops, "avg_launch_ms": dom_ms}
+
+    # pose-gradient check: FP32 central differences on 64 Gaussians seen by view 0
+    pose_fd = pose_fd_check(rast, raster, w, dev, opts)
+
+    # CPU baseline: the oracle on a bounded sample of the same workload
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(w, args.cpu_views)
+
+    value = V * 1000.0 / ms_batched
+    res = {
+        "metric": METRIC, "value": value, "unit": "views/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_batched, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"tracking room: {args.n} Gaussians, {V} poses at 640x480, fwd+loss+bwd to all "
+                               f"Gaussian parameters and poses, batched in one launch sequence",
+                   "n_gaussians": args.n, "views": V, "width": 640, "height": 480, "tile": [tw, th],
+                   "visible_records": M, "pairs": K},
+        "plain": plain,
+        "pose_only": dict(value=V * 1000.0 / ms_pose, ms_per_step=ms_pose),
+        "graph": graph,
+        "batched_over_plain": (value / plain["value"]) if plain else None,
+        "stages_ms": stage_ms,
+        "work": work,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "pose_fd": pose_fd,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def decision_stable_pose_fd(rast, raster, g, q0, t0, cams, tg, opts, h):
+    """FP32 central differences of the loss with respect to the pose, over the
+    pixels whose decisions (contributing records, clamps, cut-off) are the same
+    at every probed pose: elsewhere the image jumps (a Gaussian crossing the
+    1/255 threshold), and no difference quotient converges there.  The
+    analytic gradient is taken with the same pixel weights.  Returns the
+    analytic and FD gradients (q then t) and the number of stable pixels."""
+    import torch
+    o = raster.RenderOptions(**{**opts.__dict__, "gauss_grads": False})
+    dev = q0.device
+
+    def run(qq, tt, weight=None):
+        t = dict(tg)
+        if weight is not None:
+            t["weight"] = weight
+        out = rast.render_loss_grad(g, qq, tt, cams, t, o)
+        return out, rast.pixel_state(g, qq, tt, cams, o)["hash"]
+
+    base, h0 = run(q0, t0)
+    stable = torch.ones_like(h0, dtype=torch.bool)
+    probes = []
+    for j in range(7):
+        for sgn in (1.0, -1.0):
+            qq, tt = q0.clone(), t0.clone()
+            if j < 4:
+                qq[0, j] += sgn * h
+            else:
+                tt[0, j - 4] += sgn * h
+            probes.append((qq, tt))
+            _, hh = run(qq, tt)
+            stable &= hh == h0
+    wgt = stable.to(torch.float32)
+    an, _ = run(q0, t0, wgt)
+    analytic = np.concatenate([an["dq_t"].double().cpu().numpy().ravel(), an["dt"].double().cpu().numpy().ravel()])
+    fd = np.zeros(7)
+    for j in range(7):
+        lp = run(*probes[2 * j], wgt)[0]["loss"].sum().item()
+        lm = run(*probes[2 * j + 1], wgt)[0]["loss"].sum().item()
+        fd[j] = (lp - lm) / (2 * h)
+    return analytic, fd, int(stable.sum().item())
+
+
+def pose_fd_check(rast, raster, w, dev, opts):
+    import torch
+    G = w.gaussians
+    # Gaussians whose means project inside view 0 at a useful depth, 64 of them (seeded)
+    qv = w.views.quat[0].astype(np.float64)
+    R = _rot(qv)
+    Xc = G.means.astype(np.float64) @ R.T + w.views.trans[0].astype(np.float64)
+    cam = w.views.cams[0]
+    u = cam.fx * Xc[:, 0] / Xc[:, 2] + cam.cx
+    v = cam.fy * Xc[:, 1] / Xc[:, 2] + cam.cy
+    ok = np.nonzero((Xc[:, 2] > 0.5) & (u > 40) & (u < cam.width - 40) & (v > 40) & (v < cam.height - 40))[0]
+    sel = np.sort(np.random.default_rng(51).choice(ok, size=min(64, ok.size), replace=False))
+    sub = G.subset(sel)
+    t32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)  # noqa: E731
+    g = raster.GaussianParams(t32(sub.means), t32(sub.quats), t32(sub.log_scales), t32(sub.opacity_logits),
+                              t32(sub.rgb))
+    cams = [cam]
+    qt, tt = t32(w.target_views.quat[:1]), t32(w.target_views.trans[:1])
+    trgb, tdep, tsil, _ = rast.forward(g, qt, tt, cams, opts)
+    tg = dict(rgb=trgb, depth=tdep, sil=tsil)
+    q0, t0 = t32(w.views.quat[:1]), t32(w.views.trans[:1])
+    res = {"gaussians": int(sel.size), "method": "decision-stable central differences, FP32 renders, FP64 loss sum"}
+    for h in (1e-3, 1e-4):
+        an, fd, n_stable = decision_stable_pose_fd(rast, raster, g, q0, t0, cams, tg, opts, h)
+        res[f"h={h:g}"] = {"rel_err_dq": float(np.abs(fd[:4] - an[:4]).max() / max(np.abs(an[:4]).max(), 1e-30)),
+                           "rel_err_dt": float(np.abs(fd[4:] - an[4:]).max() / max(np.abs(an[4:]).max(), 1e-30)),
+                           "stable_pixels": n_stable}
+    return res
+
+
+def _rot(q):
+    w, x, y, z = q / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def cpu_baseline(w, n_views):
+    """The FP64 oracle (as it stands) on the host cores: fwd + loss + bwd of
+    n_views of the same scene and poses."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    cores = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
+    sub = w.views.select(range(n_views))
+    tsub = w.target_views.select(range(n_views))
+    tr = oracle.run(w.gaussians, tsub, threads=cores)
+    tg = oracle.Targets(tr.rgb, tr.depth, tr.sil)
+    t0 = time.perf_counter()
+    oracle.run(w.gaussians, sub, oracle.Options(**w.weights), tg, want_grads=True, threads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": n_views / dt, "unit": "views/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_views} of the {w.views.n} tracking views, full 640x480, fwd+loss+bwd, FP64",
+            "seconds": dt}
+
+
+if __name__ == "__main__":
+    main()

@@ -96,6 +96,14 @@ typedef enum {
 #define GSR_ISOTROPIC      0x1u  /* log_scales is [N,1]: one scale for all axes (eq. 1) */
 #define GSR_NO_GAUSS_GRADS 0x2u  /* skip gradients to the Gaussians (pose-only tracking) */
 #define GSR_NO_POSE_GRADS  0x4u  /* skip gradients to the poses (mapping) */
+#define GSR_COUNT_WORK     0x8u  /* count blend work (gsr_read_work); costs a little time */
+
+/* stages reported by gsr_read_timing() */
+#define GSR_STAGE_BINNING     0  /* projection, compaction, depth sort, records, pairs, tile sort, ranges */
+#define GSR_STAGE_BLEND_FWD   1  /* front-to-back compositing (eqs. 2-4) */
+#define GSR_STAGE_BLEND_BWD   2  /* loss + reverse compositing -> per-record 2D gradients */
+#define GSR_STAGE_PROJECT_BWD 3  /* chain rule to the parameters, pose gradients */
+#define GSR_NUM_STAGES        4
 
 /* Pinhole camera pi_m (Preliminaries, Visual Geometry Residual).  Host memory. */
 typedef struct {
@@ -124,7 +132,7 @@ typedef struct {
     float z_near;                          /* near-plane cull (camera-frame z, metres) */
     float blur2d;                          /* added to the 2D covariance diagonal (px^2), >= 0 */
     float sil_mask_thresh;                 /* < 0: off; else photometric/depth terms need S > thresh */
-    int32_t tile_w, tile_h;                /* binning tile in pixels: multiples of 8, 8..64 */
+    int32_t tile_w, tile_h;                /* binning tile in pixels: each 8 or 16 */
     uint32_t flags;                        /* GSR_* flags */
 } gsr_options;
 
@@ -204,6 +212,22 @@ gsr_status gsr_render_loss_grad(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_
 gsr_status gsr_read_counters(gsr_ctx *ctx, gsr_workspace ws, void *stream, int64_t *n_visible, int64_t *n_pairs,
                              int32_t *overflow);
 
+/* Work counters of the last call on ws made with GSR_COUNT_WORK (synchronises
+ * `stream`): work[0] (pixel, entry) alpha evaluations in the forward blend,
+ * work[1] contributions (alpha >= 1/255, before termination) in the forward,
+ * work[2], work[3] the same in the backward blend, work[4] (wave, entry)
+ * gradient reductions in the backward.  Host array of 5. */
+gsr_status gsr_read_work(gsr_ctx *ctx, gsr_workspace ws, void *stream, int64_t *work);
+
+/* Per-stage timing with HIP events: while enabled, every call brackets each
+ * stage's launches with events on its stream.  gsr_read_timing() waits for
+ * the recorded events and returns, per stage (GSR_STAGE_*), the summed
+ * milliseconds and the number of timed launches since the last read (host
+ * arrays of GSR_NUM_STAGES), then clears them.  Timing must stay off while a
+ * stream is being captured into a graph. */
+gsr_status gsr_set_timing(gsr_ctx *ctx, int32_t enable);
+gsr_status gsr_read_timing(gsr_ctx *ctx, double *ms, int64_t *launches);
+
 /* Test hook for the binning step: copies out the state that the last
  * gsr_forward() or gsr_render_loss_grad() left in ws (same g, views, opts;
  * device destinations, enqueued on stream).  rec_gid [M]: view*N+i of each
@@ -217,6 +241,18 @@ gsr_status gsr_debug_binning(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_vie
                              gsr_workspace ws, int64_t max_rec, int64_t max_tiles, int64_t max_pairs,
                              uint32_t *rec_gid, float *rec_xy, float *rec_radius, float *rec_z, uint32_t *ranges,
                              uint32_t *pair_rec, void *stream);
+
+/* Test hook: copies the per-pixel state that the last forward on ws left
+ * (device destinations of sumP entries each, any may be NULL; enqueued on
+ * stream): the final transmittance, the list position + 1 of the last
+ * contributing entry, and a hash of the pixel's decisions (which records
+ * contributed, in order, which had their alpha clamped at 0.99, and whether
+ * the transmittance cut-off ended the pixel).  Equal hashes under a small
+ * parameter change mean the images moved smoothly there, which is what a
+ * finite-difference check of the gradients needs. */
+gsr_status gsr_debug_pixel_state(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views,
+                                 const gsr_options *opts, gsr_workspace ws, float *t_final, uint32_t *n_last,
+                                 uint32_t *hash, void *stream);
 
 /* Self test of the wave64 primitives the kernels rely on (cross-lane sums,
  * ballots, lane ranks): writes the number of failed checks to *failures

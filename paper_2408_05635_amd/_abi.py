@@ -10,7 +10,8 @@ LIB_PATH = os.path.join(_HERE, "libgsr.so")
 
 GSR_OK, GSR_EINVAL, GSR_ENOMEM, GSR_ECAPACITY, GSR_EHIP, GSR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 GSR_MAX_VIEWS = 64
-GSR_ISOTROPIC, GSR_NO_GAUSS_GRADS, GSR_NO_POSE_GRADS = 0x1, 0x2, 0x4
+GSR_ISOTROPIC, GSR_NO_GAUSS_GRADS, GSR_NO_POSE_GRADS, GSR_COUNT_WORK = 0x1, 0x2, 0x4, 0x8
+STAGES = ("binning", "blend_fwd", "blend_bwd", "project_bwd")
 
 _fp = C.POINTER(C.c_float)
 _vp = C.c_void_p
@@ -57,7 +58,8 @@ class Workspace(C.Structure):
 
 
 EXPORTS = ["gsr_create", "gsr_destroy", "gsr_last_error", "gsr_workspace_size", "gsr_forward", "gsr_backward",
-           "gsr_render_loss_grad", "gsr_read_counters", "gsr_debug_binning", "gsr_selftest"]
+           "gsr_render_loss_grad", "gsr_read_counters", "gsr_read_work", "gsr_set_timing", "gsr_read_timing",
+           "gsr_debug_binning", "gsr_debug_pixel_state", "gsr_selftest"]
 
 _lib = None
 
@@ -90,9 +92,17 @@ def load() -> C.CDLL:
     lib.gsr_render_loss_grad.restype = st
     lib.gsr_read_counters.argtypes = [_vp, Workspace, _vp, P(C.c_int64), P(C.c_int64), P(C.c_int32)]
     lib.gsr_read_counters.restype = st
+    lib.gsr_read_work.argtypes = [_vp, Workspace, _vp, P(C.c_int64)]
+    lib.gsr_read_work.restype = st
+    lib.gsr_set_timing.argtypes = [_vp, C.c_int32]
+    lib.gsr_set_timing.restype = st
+    lib.gsr_read_timing.argtypes = [_vp, P(C.c_double), P(C.c_int64)]
+    lib.gsr_read_timing.restype = st
     lib.gsr_debug_binning.argtypes = [_vp, P(Gaussians), P(Views), P(Options), Workspace, C.c_int64, C.c_int64,
                                       C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.gsr_debug_binning.restype = st
+    lib.gsr_debug_pixel_state.argtypes = [_vp, P(Gaussians), P(Views), P(Options), Workspace, _vp, _vp, _vp, _vp]
+    lib.gsr_debug_pixel_state.restype = st
     lib.gsr_selftest.argtypes = [_vp, _vp, _vp]
     lib.gsr_selftest.restype = st
     _lib = lib

@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "gsr_blend.hpp"
 #include "gsr_common.hpp"
@@ -32,10 +33,51 @@
 
 using namespace gsr;
 
+// Per-stage HIP event timing (gsr_set_timing / gsr_read_timing).
+enum Stage { kStageBinning = 0, kStageBlendFwd = 1, kStageBlendBwd = 2, kStageProjectBwd = 3, kNumStages = 4 };
+
 struct gsr_ctx {
     int device;
     int num_cus;
     std::string err;
+    bool timing = false;
+    struct Rec {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t take_event() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+
+// Brackets the launches of one stage with events when timing is on.
+struct StageTimer {
+    gsr_ctx *ctx;
+    int stage;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageTimer(gsr_ctx *c, int s, hipStream_t stream) : ctx(c), stage(s), st(stream) {
+        if (ctx->timing && ctx->recs.size() < 65536) {
+            a = ctx->take_event();
+            b = ctx->take_event();
+            if (a && b) (void)hipEventRecord(a, st);
+        }
+    }
+    ~StageTimer() {
+        if (a && b) {
+            (void)hipEventRecord(b, st);
+            ctx->recs.push_back({stage, a, b});
+        }
+    }
 };
 
 static std::string g_create_err;
@@ -43,6 +85,7 @@ static std::string g_create_err;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kRecGrad = 14;   // per-record parameter gradient: mu 3, q 4, log_s 3, logit 1, rgb 3
 
 struct Layout {
     int64_t vn;           // V * N
@@ -51,8 +94,8 @@ struct Layout {
     int64_t T;            // total tiles
     int32_t G;            // total blend blocks
     int tile_bits;        // key bits of the tile sort
-    size_t views, poses, counters, cnt, zkey, dk0, dv0, dk1, dv1, inv, rec, trect, cnt_s, pk0, pv0, pk1, pv1,
-        ranges, tfinal, nlast, grad2d, posepart, part, hist;
+    size_t views, poses, counters, cnt, zkey, dk0, dv0, dk1, dv1, inv, rec, trect, cnt_s, poff, pk0, pv0, pk1, pv1,
+        owner, prec, ranges, tfinal, nlast, phash, gpairs, rgrad, rpose, losst, posepart, part, hist;
     size_t total;
 };
 
@@ -94,8 +137,8 @@ gsr_status validate_views(gsr_ctx *ctx, const gsr_views *views, const gsr_option
             return fail(ctx, GSR_EINVAL, "view %d: focal lengths must be finite and > 0", v);
     }
     const int tw = opts->tile_w, th = opts->tile_h;
-    if (tw < 8 || th < 8 || tw > 64 || th > 64 || tw % 8 || th % 8)
-        return fail(ctx, GSR_EINVAL, "tile size %dx%d must be multiples of 8 in [8, 64]", tw, th);
+    if ((tw != 8 && tw != 16) || (th != 8 && th != 16))
+        return fail(ctx, GSR_EINVAL, "tile size %dx%d: each side must be 8 or 16", tw, th);
     if (!(opts->blur2d >= 0.f) || !std::isfinite(opts->blur2d))
         return fail(ctx, GSR_EINVAL, "blur2d must be finite and >= 0");
     if (!(opts->z_near >= 0.f) || !std::isfinite(opts->z_near))
@@ -166,14 +209,21 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     L.rec = take(48 * vn);
     L.trect = take(8 * vn);
     L.cnt_s = take(4 * vn);
+    L.poff = take(4 * vn);
     L.pk0 = take(4 * kc);
     L.pv0 = take(4 * kc);
     L.pk1 = take(4 * kc);
     L.pv1 = take(4 * kc);
+    L.owner = take(4 * kc);
+    L.prec = take(4 * kc);
     L.ranges = take(8 * (size_t)L.T);
     L.tfinal = take(4 * (size_t)L.P);
     L.nlast = take(4 * (size_t)L.P);
-    L.grad2d = take(40 * vn);
+    L.phash = take(4 * (size_t)L.P);
+    L.gpairs = take(40 * kc);
+    L.rgrad = take(4 * kRecGrad * vn);
+    L.rpose = take(8 * 12 * vn);
+    L.losst = take(sizeof(double) * (size_t)L.T);
     L.posepart = take(sizeof(double) * 12 * V);
     const int64_t nb_sort = (std::max<int64_t>(L.vn, kcap) + kChunk - 1) / kChunk;
     const int64_t scan_n = std::max<int64_t>(std::max<int64_t>(L.vn, kcap), 256 * nb_sort);
@@ -290,29 +340,69 @@ struct CntSrc {
     const uint32_t *cnt;
     __device__ uint32_t operator()(int64_t i) const { return cnt[i]; }
 };
-struct EmitSink {
-    const uint2 *trect;
-    const uint32_t *gid;
-    const ViewTable *vt;
-    int64_t n;
-    int64_t cap;
-    uint32_t *keys, *vals;
-    __device__ void operator()(int64_t s, uint32_t pos, uint32_t c) const {
-        if ((int64_t)pos + c > cap) return;
-        const int v = (int)(gid[s] / (uint64_t)n);
-        if (v >= vt->n_views) return;   // never expected; keeps writes in bounds
-        const ViewInfo &V = vt->v[v];
-        const uint2 tr = trect[s];
-        const int tx0 = tr.x & 0xffff, tx1 = tr.x >> 16, ty0 = tr.y & 0xffff, ty1 = tr.y >> 16;
-        uint32_t k = pos;
-        for (int ty = ty0; ty <= ty1; ++ty)
-            for (int tx = tx0; tx <= tx1; ++tx) {
-                keys[k] = (uint32_t)(V.tile_off + ty * V.tiles_x + tx);
-                vals[k] = (uint32_t)s;
-                ++k;
-            }
-    }
+struct OffSink {
+    uint32_t *off;
+    __device__ void operator()(int64_t s, uint32_t pos, uint32_t) const { off[s] = pos; }
 };
+
+// Pair j's owning record is the number of record starts in [1, j]: records
+// own contiguous, non-empty ranges [poff[s], poff[s] + cnt_s[s]) (every
+// visible record touches at least one tile).  k_mark_heads sets owner[poff[s]]
+// = 1 for s >= 1 into a zeroed array, and an inclusive prefix sum turns it
+// into the owner of every pair.  Emission is then one thread per pair, which
+// stays balanced however many tiles a record covers.
+__global__ void k_mark_heads(const int64_t *__restrict__ counters, const uint32_t *__restrict__ poff,
+                             uint32_t *__restrict__ owner) {
+    const int64_t M = counters[kCntVisible];
+    if (counters[kCntPairsUsed] == 0) return;
+    for (int64_t s = 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < M; s += (int64_t)gridDim.x * blockDim.x)
+        owner[poff[s]] = 1u;
+}
+
+struct OwnSrc {
+    const uint32_t *h;
+    __device__ uint32_t operator()(int64_t i) const { return h[i]; }
+};
+struct OwnSink {   // inclusive prefix, written in place (each thread rewrites only what it read)
+    uint32_t *h;
+    __device__ void operator()(int64_t i, uint32_t pre, uint32_t v) const { h[i] = pre + v; }
+};
+
+// Pair j: key = global tile id, value = j.
+__global__ void k_emit(const int64_t *__restrict__ counters, const uint32_t *__restrict__ poff,
+                       const uint2 *__restrict__ trect, const uint32_t *__restrict__ gid,
+                       const ViewTable *__restrict__ vt, int64_t n, const uint32_t *__restrict__ owner,
+                       uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    const int64_t K = counters[kCntPairsUsed];
+    const int64_t M = counters[kCntVisible];
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < K; j += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t s = owner[j];
+        if ((int64_t)s >= M) s = 0;   // never expected; keeps reads in bounds
+        const uint32_t k = (uint32_t)j - poff[s];
+        const uint2 tr = trect[s];
+        const uint32_t tx0 = tr.x & 0xffffu, nx = (tr.x >> 16) - tx0 + 1u, ty0 = tr.y & 0xffffu;
+        int v = (int)(gid[s] / (uint64_t)n);
+        if (v >= vt->n_views) v = 0;
+        const ViewInfo &V = vt->v[v];
+        const uint32_t ty = ty0 + k / nx, tx = tx0 + k % nx;
+        keys[j] = (uint32_t)V.tile_off + ty * (uint32_t)V.tiles_x + tx;
+        vals[j] = (uint32_t)j;
+    }
+}
+
+__global__ void k_fill_u32_dev(uint32_t *p, const int64_t *n_dev, uint32_t val) {
+    const int64_t n = *n_dev;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = val;
+}
+
+// record index of every sorted pair
+__global__ void k_pair_records(const int64_t *__restrict__ counters, const uint32_t *__restrict__ sorted_j,
+                               const uint32_t *__restrict__ owner, uint32_t *__restrict__ prec) {
+    const int64_t K = counters[kCntPairsUsed];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < K; e += (int64_t)gridDim.x * blockDim.x)
+        prec[e] = owner[sorted_j[e]];
+}
 
 __global__ void k_check_capacity(int64_t *counters, int64_t cap) {
     const int64_t K = counters[kCntPairs];
@@ -352,60 +442,135 @@ struct GradOut {
     bool want_gauss, want_pose;
 };
 
-// per Gaussian: chain rule over the views that see it; pose partials per view
-__global__ __launch_bounds__(256) void k_project_bwd(ProjParams pp, const ViewTable *__restrict__ vt,
-                                                     const PoseF64 *__restrict__ poses, const uint32_t *__restrict__ cnt,
-                                                     const uint32_t *__restrict__ inv,
-                                                     const float *__restrict__ grad2d, GradOut go,
-                                                     double *__restrict__ posepart, const int64_t *__restrict__ counters) {
-    __shared__ double s_pose[GSR_MAX_VIEWS * 12];
-    const uint32_t n_rec = (uint32_t)counters[kCntVisible];
-    const int V = vt->n_views;
-    for (int k = threadIdx.x; k < V * 12; k += blockDim.x) s_pose[k] = 0.0;
-    __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = i < pp.n;
-    GaussIn p;
-    if (live) p = load_gauss(pp.g, i, pp.iso);
+// Per visible record s (one view, one Gaussian): the record's 2D gradient is
+// the sum of its pairs' rows (contiguous); the chain rule takes it to the raw
+// parameters (written per record, 14 floats) and to the view's pose partials
+// (G_W and g_t, 12 doubles, also per record).
+//
+// Load balance: records are depth-sorted, so the nearest ones, which can
+// cover every tile of the image, are neighbours.  Lane l of wave w takes
+// record l * W + w (W = number of waves needed), which spreads neighbours over
+// different waves.  A record with more than kLongRows rows is summed by the
+// whole wave (rows lane, lane + 64, ...; then a fixed-order DPP reduction), so
+// no lane walks a long range alone.  Both sums are deterministic.
+constexpr uint32_t kLongRows = 32;
+
+__global__ __launch_bounds__(256) void k_record_bwd(ProjParams pp, const ViewTable *__restrict__ vt,
+                                                    const PoseF64 *__restrict__ poses,
+                                                    const uint32_t *__restrict__ gid_sorted,
+                                                    const uint32_t *__restrict__ poff,
+                                                    const uint32_t *__restrict__ cnt_s,
+                                                    const float *__restrict__ gpairs, const int64_t *__restrict__ counters,
+                                                    float *__restrict__ rgrad, double *__restrict__ rpose) {
+    const int64_t M = counters[kCntVisible];
+    const bool have_pairs = counters[kCntPairsUsed] > 0;
+    const int64_t W = (M + 63) / 64;
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (w >= W) return;   // wave-uniform
+    const uint32_t lane = threadIdx.x & 63u;
+    const int64_t s = (int64_t)lane * W + w;
+    const bool valid = s < M;
+    uint32_t j0 = 0, nrow = 0;
+    if (valid && have_pairs) {
+        j0 = poff[s];
+        nrow = cnt_s[s];
+    }
+    float g2[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (nrow <= kLongRows) {
+        for (uint32_t jj = j0; jj < j0 + nrow; ++jj) {
+            const float *row = gpairs + 10 * (size_t)jj;
+#pragma unroll
+            for (int c = 0; c < 10; ++c) g2[c] += row[c];
+        }
+    }
+    uint64_t longm = ballot(nrow > kLongRows);
+    while (longm) {   // wave-uniform loop over this wave's long records
+        const int src = __builtin_ctzll(longm);
+        longm &= longm - 1;
+        const uint32_t a = __shfl(j0, src, 64), cnt = __shfl(nrow, src, 64);
+        float part[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (uint32_t jj = a + lane; jj < a + cnt; jj += 64) {
+            const float *row = gpairs + 10 * (size_t)jj;
+#pragma unroll
+            for (int c = 0; c < 10; ++c) part[c] += row[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 10; ++c) {
+            const float t = wave_sum(part[c]);
+            if ((int)lane == src) g2[c] = t;
+        }
+    }
+    if (!valid) return;
+    const uint32_t gid = gid_sorted[s];
+    const int v = (int)(gid / (uint64_t)pp.n);
+    if (v >= vt->n_views) return;   // never expected; keeps reads in bounds
+    const int64_t i = (int64_t)gid - (int64_t)v * pp.n;
+    const GaussIn p = load_gauss(pp.g, i, pp.iso);
+    Proj r;
+    project<true>(p, poses[v], vt->v[v], pp.z_near, pp.blur, pp.iso, r);
     ParamGrad pg;
     for (int k = 0; k < 3; ++k) pg.mu[k] = pg.ls[k] = pg.rgb[k] = 0.0;
     for (int k = 0; k < 4; ++k) pg.q[k] = 0.0;
     pg.logit = 0.0;
+    double gX[3], GW[9];
+    project_backward(p, poses[v], vt->v[v], r, g2, pp.iso, pg, gX, GW);
+    float *o = rgrad + kRecGrad * (size_t)s;
+    for (int k = 0; k < 3; ++k) o[k] = (float)pg.mu[k];
+    for (int k = 0; k < 4; ++k) o[3 + k] = (float)pg.q[k];
+    for (int k = 0; k < 3; ++k) o[7 + k] = (float)pg.ls[k];
+    o[10] = (float)pg.logit;
+    for (int k = 0; k < 3; ++k) o[11 + k] = (float)pg.rgb[k];
+    double *q = rpose + 12 * (size_t)s;
+    for (int k = 0; k < 9; ++k) q[k] = GW[k];
+    for (int k = 0; k < 3; ++k) q[9 + k] = gX[k];
+}
+
+// Per Gaussian: its gradient is the sum of its records' contributions over
+// the views, in view order (deterministic).  Pose partials: per view, summed
+// over the wave (FP64), then over the block in LDS, then one FP64 atomic per
+// block and value.
+__global__ __launch_bounds__(256) void k_gauss_sum(ProjParams pp, const ViewTable *__restrict__ vt,
+                                                   const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ inv,
+                                                   const float *__restrict__ rgrad, const double *__restrict__ rpose,
+                                                   GradOut go, double *__restrict__ posepart,
+                                                   const int64_t *__restrict__ counters) {
+    __shared__ double s_pose[GSR_MAX_VIEWS * 12];
+    const int V = vt->n_views;
+    for (int k = threadIdx.x; k < V * 12; k += blockDim.x) s_pose[k] = 0.0;
+    __syncthreads();
+    const uint32_t n_rec = (uint32_t)counters[kCntVisible];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = i < pp.n;
+    float acc[kRecGrad];
+    for (int k = 0; k < kRecGrad; ++k) acc[k] = 0.0f;
     for (int v = 0; v < V; ++v) {
-        const bool vis = live && cnt[(int64_t)v * pp.n + i] != 0u;
-        double gX[3] = {0.0, 0.0, 0.0}, GW[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        if (vis) {
-            const uint32_t s = inv[(int64_t)v * pp.n + i];
-            float g2[10];
-            for (int c = 0; c < 10; ++c) g2[c] = s < n_rec ? grad2d[10 * (size_t)s + c] : 0.0f;
-            Proj r;
-            project<true>(p, poses[v], vt->v[v], pp.z_near, pp.blur, pp.iso, r);
-            project_backward(p, poses[v], vt->v[v], r, g2, pp.iso, pg, gX, GW);
+        const uint32_t s = live && cnt[(int64_t)v * pp.n + i] != 0u ? inv[(int64_t)v * pp.n + i] : 0xffffffffu;
+        const bool vis = s < n_rec;
+        if (vis && go.want_gauss) {
+            const float *o = rgrad + kRecGrad * (size_t)s;
+            for (int k = 0; k < kRecGrad; ++k) acc[k] += o[k];
         }
         if (go.want_pose && ballot(vis) != 0) {
-            double vals[12];
-            for (int k = 0; k < 9; ++k) vals[k] = GW[k];
-            for (int k = 0; k < 3; ++k) vals[9 + k] = gX[k];
             for (int k = 0; k < 12; ++k) {
-                const double t = wave_sum_f64(vals[k]);
+                const double t = wave_sum_f64(vis ? rpose[12 * (size_t)s + k] : 0.0);
                 if ((threadIdx.x & 63) == 0) atomicAdd(&s_pose[v * 12 + k], t);
             }
         }
     }
     if (live && go.want_gauss) {
         if (go.gg.means)
-            for (int k = 0; k < 3; ++k) go.gg.means[3 * i + k] = (float)pg.mu[k];
+            for (int k = 0; k < 3; ++k) go.gg.means[3 * i + k] = acc[k];
         if (go.gg.quats)
-            for (int k = 0; k < 4; ++k) go.gg.quats[4 * i + k] = (float)pg.q[k];
+            for (int k = 0; k < 4; ++k) go.gg.quats[4 * i + k] = pp.iso ? 0.0f : acc[3 + k];
         if (go.gg.log_scales) {
             if (pp.iso)
-                go.gg.log_scales[i] = (float)pg.ls[0];
+                go.gg.log_scales[i] = acc[7];
             else
-                for (int k = 0; k < 3; ++k) go.gg.log_scales[3 * i + k] = (float)pg.ls[k];
+                for (int k = 0; k < 3; ++k) go.gg.log_scales[3 * i + k] = acc[7 + k];
         }
-        if (go.gg.opacity_logits) go.gg.opacity_logits[i] = (float)pg.logit;
+        if (go.gg.opacity_logits) go.gg.opacity_logits[i] = acc[10];
         if (go.gg.rgb)
-            for (int k = 0; k < 3; ++k) go.gg.rgb[3 * i + k] = (float)pg.rgb[k];
+            for (int k = 0; k < 3; ++k) go.gg.rgb[3 * i + k] = acc[11 + k];
     }
     if (go.want_pose) {
         __syncthreads();
@@ -501,6 +666,7 @@ unsigned grid_for(int64_t n, int threads, int64_t max_blocks = 65536) {
 }
 
 struct Call {
+    bool count;
     gsr_ctx *ctx;
     ViewTable tab;
     Layout L;
@@ -536,11 +702,13 @@ gsr_status prepare(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views,
     c.pp.z_near = opts->z_near;
     c.pp.blur = opts->blur2d;
     c.pp.iso = (opts->flags & GSR_ISOTROPIC) != 0;
+    c.count = (opts->flags & GSR_COUNT_WORK) != 0;
     return GSR_OK;
 }
 
 // Projection, binning, sorting and ranges (forward up to the blend).
 void enqueue_binning(Call &c, const gsr_views *views) {
+    StageTimer timer(c.ctx, kStageBinning, c.st);
     const Layout &L = c.L;
     const gsr_workspace &ws = c.ws;
     hipStream_t st = c.st;
@@ -570,24 +738,39 @@ void enqueue_binning(Call &c, const gsr_views *views) {
                            gid_sorted, rec, trect, cnt_s, inv, c.pp.g.rgb);
     uint32_t *pk0 = at<uint32_t>(ws, L.pk0), *pv0 = at<uint32_t>(ws, L.pv0);
     uint32_t *pk1 = at<uint32_t>(ws, L.pk1), *pv1 = at<uint32_t>(ws, L.pv1);
-    scan_exclusive(CntSrc{cnt_s}, EmitSink{trect, gid_sorted, vt, c.pp.n, L.kcap, pk0, pv0}, counters + kCntVisible,
-                   L.vn, part, counters + kCntPairs, st);
+    uint32_t *poff = at<uint32_t>(ws, L.poff), *owner = at<uint32_t>(ws, L.owner);
+    scan_exclusive(CntSrc{cnt_s}, OffSink{poff}, counters + kCntVisible, L.vn, part, counters + kCntPairs, st);
     hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(1), 0, st, counters, L.kcap);
+    if (L.vn > 0 && L.kcap > 0) {
+        hipLaunchKernelGGL(k_fill_u32_dev, dim3(grid_for(L.kcap, 256, 8192)), dim3(256), 0, st, owner,
+                           (const int64_t *)(counters + kCntPairsUsed), 0u);
+        hipLaunchKernelGGL(k_mark_heads, dim3(grid_for(L.vn, 256, 8192)), dim3(256), 0, st, counters, poff, owner);
+        scan_exclusive(OwnSrc{owner}, OwnSink{owner}, counters + kCntPairsUsed, L.kcap, part,
+                       counters + kCntScratch, st);
+        hipLaunchKernelGGL(k_emit, dim3(grid_for(L.kcap, 256, 16384)), dim3(256), 0, st, counters, poff, trect,
+                           gid_sorted, vt, c.pp.n, owner, pk0, pv0);
+    }
     const bool p_in1 = radix_sort(pk0, pv0, pk1, pv1, counters + kCntPairsUsed, L.kcap, L.tile_bits, hist, part,
                                   counters + kCntScratch, st);
     uint2 *ranges = at<uint2>(ws, L.ranges);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(2 * L.T, 256)), dim3(256), 0, st, (uint32_t *)ranges, 2 * L.T, 0u);
-    if (L.kcap > 0)
+    if (L.kcap > 0) {
         hipLaunchKernelGGL(k_ranges, dim3(grid_for(L.kcap, 256, 16384)), dim3(256), 0, st, p_in1 ? pk1 : pk0,
                            counters, ranges, L.T);
+        hipLaunchKernelGGL(k_pair_records, dim3(grid_for(L.kcap, 256, 16384)), dim3(256), 0, st, counters,
+                           p_in1 ? pv1 : pv0, owner, at<uint32_t>(ws, L.prec));
+    }
 }
 
-// which buffer holds the sorted pair values (the sort's parity is fixed by the key bits)
-const uint32_t *pair_values(const Call &c) {
+// emission index of every sorted pair (the sort's result buffer is fixed by the key bits)
+const uint32_t *pair_j(const Call &c) {
     const int passes = (c.L.tile_bits + 7) / 8;
     const bool in1 = (c.L.kcap > 0 && c.L.tile_bits > 0) ? (passes % 2 == 1) : false;
     return at<uint32_t>(c.ws, in1 ? c.L.pv1 : c.L.pv0);
 }
+
+// record index of every sorted pair
+const uint32_t *pair_values(const Call &c) { return at<uint32_t>(c.ws, c.L.prec); }
 
 const uint32_t *depth_sorted_gid(const Call &c) {
     const bool in1 = false;   // 4 passes over 32 bits: the result is back in the first buffer
@@ -595,13 +778,17 @@ const uint32_t *depth_sorted_gid(const Call &c) {
 }
 
 void enqueue_blend_fwd(Call &c, gsr_images out) {
+    StageTimer timer(c.ctx, kStageBlendFwd, c.st);
     const Layout &L = c.L;
-    BlendOut bo{out.rgb, out.depth, out.sil, at<float>(c.ws, L.tfinal), at<uint32_t>(c.ws, L.nlast)};
+    BlendOut bo{out.rgb, out.depth, out.sil, at<float>(c.ws, L.tfinal), at<uint32_t>(c.ws, L.nlast),
+                at<uint32_t>(c.ws, L.phash)};
     const unsigned grid = (unsigned)(((L.G + 7) / 8) * 8);
-    if (grid > 0)
-        hipLaunchKernelGGL(k_blend_fwd, dim3(grid), dim3(64), 0, c.st, at<ViewTable>(c.ws, L.views),
+    if (grid > 0) {
+        auto kern = c.count ? k_blend_fwd<true> : k_blend_fwd<false>;
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, c.st, at<ViewTable>(c.ws, L.views),
                            at<float4>(c.ws, L.rec), pair_values(c), at<uint2>(c.ws, L.ranges),
                            at<int64_t>(c.ws, L.counters), bo);
+    }
 }
 
 void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, gsr_images out, LossIn li,
@@ -610,21 +797,27 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
     hipStream_t st = c.st;
     ViewTable *vt = at<ViewTable>(c.ws, L.views);
     int64_t *counters = at<int64_t>(c.ws, L.counters);
-    float *grad2d = at<float>(c.ws, L.grad2d);
+    float *gpairs = at<float>(c.ws, L.gpairs);
     double *posepart = at<double>(c.ws, L.posepart);
-    hipLaunchKernelGGL(k_fill_f32_dev, dim3(grid_for(10 * L.vn, 256, 8192)), dim3(256), 0, st, grad2d,
-                       counters + kCntVisible, (int64_t)10, 0.0f);
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, posepart, (int64_t)12 * views->n_views);
-    if (fused) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, li.loss, (int64_t)views->n_views);
-    BlendOut bo{out.rgb, out.depth, out.sil, at<float>(c.ws, L.tfinal), at<uint32_t>(c.ws, L.nlast)};
-    const unsigned grid = (unsigned)(((L.G + 7) / 8) * 8);
-    if (grid > 0) {
-        if (fused)
-            hipLaunchKernelGGL(k_blend_bwd<true>, dim3(grid), dim3(64), 0, st, vt, at<float4>(c.ws, L.rec),
-                               pair_values(c), at<uint2>(c.ws, L.ranges), at<int64_t>(c.ws, L.counters), bo, li, grad2d);
-        else
-            hipLaunchKernelGGL(k_blend_bwd<false>, dim3(grid), dim3(64), 0, st, vt, at<float4>(c.ws, L.rec),
-                               pair_values(c), at<uint2>(c.ws, L.ranges), at<int64_t>(c.ws, L.counters), bo, li, grad2d);
+    li.loss_tile = at<double>(c.ws, L.losst);
+    BlendOut bo{out.rgb, out.depth, out.sil, at<float>(c.ws, L.tfinal), at<uint32_t>(c.ws, L.nlast),
+                at<uint32_t>(c.ws, L.phash)};
+    {
+        StageTimer timer(c.ctx, kStageBlendBwd, st);
+        const unsigned grid = (unsigned)(((L.T + 7) / 8) * 8);
+        const unsigned threads = (unsigned)(64 * (opts->tile_w / kBlk) * (opts->tile_h / kBlk));
+        if (grid > 0 && L.kcap > 0) {
+            auto kern = fused ? (c.count ? k_blend_bwd<true, true> : k_blend_bwd<true, false>)
+                              : (c.count ? k_blend_bwd<false, true> : k_blend_bwd<false, false>);
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, vt, at<float4>(c.ws, L.rec), pair_values(c),
+                               pair_j(c), at<uint2>(c.ws, L.ranges), counters, bo, li, gpairs);
+        }
+        if (fused) {
+            if (L.kcap == 0)   // no blend ran: every tile's partial is zero
+                hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(L.T, 256)), dim3(256), 0, st, li.loss_tile, L.T);
+            hipLaunchKernelGGL(k_loss_final, dim3(views->n_views), dim3(256), 0, st, vt, li.loss_tile, li.loss);
+        }
     }
     GradOut go;
     memset(&go, 0, sizeof(go));
@@ -632,10 +825,16 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
     go.want_gauss = gg && !(opts->flags & GSR_NO_GAUSS_GRADS) &&
                     (gg->means || gg->quats || gg->log_scales || gg->opacity_logits || gg->rgb);
     go.want_pose = pg && !(opts->flags & GSR_NO_POSE_GRADS) && (pg->dq_t || pg->dt || pg->dq_c || pg->dc);
-    if (c.pp.n > 0 && (go.want_gauss || go.want_pose))
-        hipLaunchKernelGGL(k_project_bwd, dim3(grid_for(c.pp.n, 256, 1ll << 30)), dim3(256), 0, st, c.pp, vt,
-                           at<PoseF64>(c.ws, L.poses), at<uint32_t>(c.ws, L.cnt), at<uint32_t>(c.ws, L.inv), grad2d,
-                           go, posepart, (const int64_t *)counters);
+    StageTimer timer(c.ctx, kStageProjectBwd, st);
+    if (c.pp.n > 0 && (go.want_gauss || go.want_pose)) {
+        hipLaunchKernelGGL(k_record_bwd, dim3(grid_for(L.vn, 256, 1ll << 30)), dim3(256), 0, st, c.pp, vt,
+                           at<PoseF64>(c.ws, L.poses), depth_sorted_gid(c), at<uint32_t>(c.ws, L.poff),
+                           at<uint32_t>(c.ws, L.cnt_s), gpairs, (const int64_t *)counters, at<float>(c.ws, L.rgrad),
+                           at<double>(c.ws, L.rpose));
+        hipLaunchKernelGGL(k_gauss_sum, dim3(grid_for(c.pp.n, 256, 1ll << 30)), dim3(256), 0, st, c.pp, vt,
+                           at<uint32_t>(c.ws, L.cnt), at<uint32_t>(c.ws, L.inv), at<float>(c.ws, L.rgrad),
+                           at<double>(c.ws, L.rpose), go, posepart, (const int64_t *)counters);
+    }
     if (go.want_pose)
         hipLaunchKernelGGL(k_pose_final, dim3(1), dim3(64), 0, st, views->quat, views->trans,
                            at<PoseF64>(c.ws, L.poses), posepart, views->n_views, *pg);
@@ -690,7 +889,15 @@ gsr_status gsr_create(gsr_ctx **out, int device) {
     return GSR_OK;
 }
 
-void gsr_destroy(gsr_ctx *ctx) { delete ctx; }
+void gsr_destroy(gsr_ctx *ctx) {
+    if (!ctx) return;
+    for (auto &r : ctx->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : ctx->pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
 
 const char *gsr_last_error(const gsr_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
 
@@ -793,6 +1000,50 @@ gsr_status gsr_read_counters(gsr_ctx *ctx, gsr_workspace ws, void *stream, int64
     return GSR_OK;
 }
 
+gsr_status gsr_read_work(gsr_ctx *ctx, gsr_workspace ws, void *stream, int64_t *work) {
+    if (!ctx) return GSR_EINVAL;
+    if (!ws.ptr || !work) return fail(ctx, GSR_EINVAL, "workspace and work must not be NULL");
+    if (ws.bytes < sizeof(int64_t) * kNumCounters) return fail(ctx, GSR_EINVAL, "workspace too small");
+    int64_t h[kNumCounters];
+    gsr_status s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (s != GSR_OK) return s;
+    s = check_hip(ctx, hipMemcpyAsync(h, ws.ptr, sizeof(h), hipMemcpyDeviceToHost, (hipStream_t)stream),
+                  "hipMemcpyAsync(counters)");
+    if (s != GSR_OK) return s;
+    s = check_hip(ctx, hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+    if (s != GSR_OK) return s;
+    for (int k = 0; k < 5; ++k) work[k] = h[kCntEvalFwd + k];
+    return GSR_OK;
+}
+
+gsr_status gsr_set_timing(gsr_ctx *ctx, int32_t enable) {
+    if (!ctx) return GSR_EINVAL;
+    ctx->timing = enable != 0;
+    return GSR_OK;
+}
+
+gsr_status gsr_read_timing(gsr_ctx *ctx, double *ms, int64_t *launches) {
+    if (!ctx) return GSR_EINVAL;
+    if (!ms || !launches) return fail(ctx, GSR_EINVAL, "ms and launches must not be NULL");
+    for (int k = 0; k < kNumStages; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    gsr_status status = GSR_OK;
+    for (auto &r : ctx->recs) {
+        float t = 0.0f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+        if (e != hipSuccess && status == GSR_OK) status = check_hip(ctx, e, "hipEventElapsedTime");
+        ms[r.stage] += t;
+        launches[r.stage] += 1;
+        ctx->pool.push_back(r.a);
+        ctx->pool.push_back(r.b);
+    }
+    ctx->recs.clear();
+    return status;
+}
+
 gsr_status gsr_debug_binning(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views, const gsr_options *opts,
                              gsr_workspace ws, int64_t max_rec, int64_t max_tiles, int64_t max_pairs,
                              uint32_t *rec_gid, float *rec_xy, float *rec_radius, float *rec_z, uint32_t *ranges,
@@ -814,6 +1065,26 @@ gsr_status gsr_debug_binning(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_vie
     hipLaunchKernelGGL(k_debug_copy_u32, dim3(grid_for(L.kcap, 256, 4096)), dim3(256), 0, c.st, pair_values(c),
                        counters, (int)kCntPairsUsed, max_pairs, pair_rec, (int64_t)0);
     return finish(c, "gsr_debug_binning launch");
+}
+
+gsr_status gsr_debug_pixel_state(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views,
+                                 const gsr_options *opts, gsr_workspace ws, float *t_final, uint32_t *n_last,
+                                 uint32_t *hash, void *stream) {
+    Call c;
+    gsr_status s = prepare(ctx, g, views, opts, ws, stream, c);
+    if (s != GSR_OK) return s;
+    s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (s != GSR_OK) return s;
+    const size_t bytes = 4 * (size_t)c.L.P;
+    if (t_final) s = check_hip(ctx, hipMemcpyAsync(t_final, at<float>(ws, c.L.tfinal), bytes, hipMemcpyDeviceToDevice,
+                                                   c.st), "copy t_final");
+    if (s == GSR_OK && n_last)
+        s = check_hip(ctx, hipMemcpyAsync(n_last, at<uint32_t>(ws, c.L.nlast), bytes, hipMemcpyDeviceToDevice, c.st),
+                      "copy n_last");
+    if (s == GSR_OK && hash)
+        s = check_hip(ctx, hipMemcpyAsync(hash, at<uint32_t>(ws, c.L.phash), bytes, hipMemcpyDeviceToDevice, c.st),
+                      "copy hash");
+    return s;
 }
 
 gsr_status gsr_selftest(gsr_ctx *ctx, int32_t *failures, void *stream) {

@@ -105,14 +105,16 @@ struct BlendOut {
     float *rgb, *depth, *sil;   // images
     float *t_final;             // per pixel
     uint32_t *n_last;           // per pixel: list position + 1 of the last contributor (0: none)
+    uint32_t *hash;             // per pixel: hash of the contributing records, clamp flags and the stop
 };
 
+template <bool COUNT>
 __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ vt, const float4 *__restrict__ rec,
                                                   const uint32_t *__restrict__ pair_rec,
-                                                  const uint2 *__restrict__ ranges, const int64_t *__restrict__ counters,
+                                                  const uint2 *__restrict__ ranges, int64_t *__restrict__ counters,
                                                   BlendOut out) {
     __shared__ float4 s_a[64], s_b[64], s_c[64];
-    __shared__ uint32_t s_pos[64];
+    __shared__ uint32_t s_pos[64], s_rec_id[64];
     const BlockPos bp = locate_block(vt);
     if (!bp.valid) return;
     const ViewInfo &V = vt->v[bp.v];
@@ -126,15 +128,16 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
     if (rg.y > n_pair || rg.x > rg.y) rg = make_uint2(0u, 0u);   // never expected; keeps reads in bounds
 
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, cd = 0.0f, cs = 0.0f;
-    uint32_t last = 0;
+    uint32_t last = 0, n_eval = 0, n_contrib = 0, hsh = 0x811c9dc5u;
     bool done = !inside;
     for (uint32_t c = rg.x; c < rg.y; c += 64) {
         if (ballot(!done) == 0) break;
         const uint32_t e = c + lane;
         bool keep = false;
         float4 A, B, C;
+        uint32_t s = 0;
         if (e < rg.y && pair_rec[e] < n_rec) {
-            const uint32_t s = pair_rec[e];
+            s = pair_rec[e];
             A = rec[3 * (size_t)s];
             B = rec[3 * (size_t)s + 1];
             C = rec[3 * (size_t)s + 2];
@@ -147,17 +150,22 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
             s_b[slot] = B;
             s_c[slot] = C;
             s_pos[slot] = e;
+            s_rec_id[slot] = s;
         }
         __syncthreads();
         const int n = __popcll(m);
         for (int k = 0; k < n; ++k) {
             if (!done) {
                 const AlphaEval ev = eval_alpha(s_a[k], s_b[k], fpx, fpy);
+                if (COUNT) ++n_eval;
                 if (ev.alpha >= kAlphaMin) {
                     const float Tn = T * (1.0f - ev.alpha);
                     if (Tn < kTMin) {
                         done = true;
+                        hsh = (hsh ^ 0xffffffffu) * 0x01000193u;
                     } else {
+                        if (COUNT) ++n_contrib;
+                        hsh = (hsh ^ (2u * s_rec_id[k] + (ev.clamped ? 1u : 0u))) * 0x01000193u;
                         const float4 cc = s_c[k];
                         const float wgt = ev.alpha * T;
                         c0 = __builtin_fmaf(wgt, cc.x, c0);
@@ -174,6 +182,13 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
         }
         __syncthreads();
     }
+    if (COUNT) {
+        const uint32_t e = wave_sum_u32(n_eval), c = wave_sum_u32(n_contrib);
+        if (lane == 0) {
+            atomicAdd((unsigned long long *)&counters[kCntEvalFwd], (unsigned long long)e);
+            atomicAdd((unsigned long long *)&counters[kCntContribFwd], (unsigned long long)c);
+        }
+    }
     if (inside) {
         const int64_t P = (int64_t)V.W * V.H;
         const int64_t pix = (int64_t)py * V.W + px;
@@ -184,6 +199,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
         out.sil[V.pix_off + pix] = cs;
         out.t_final[V.pix_off + pix] = T;
         out.n_last[V.pix_off + pix] = last;
+        out.hash[V.pix_off + pix] = hsh;
     }
 }
 
@@ -192,23 +208,61 @@ struct LossIn {
     const float *t_rgb, *t_depth, *t_sil, *t_prior, *t_weight;
     float w_rgb, w_depth, w_sil, w_prior, sil_thresh;
     const float *g_rgb, *g_depth, *g_sil;   // upstream dL/dimage (split backward)
-    double *loss;                           // [V] (fused)
+    double *loss;                           // [V] per-view loss (fused; written by k_loss_final)
+    double *loss_tile;                      // [tiles] per-tile loss partials (fused, workspace)
 };
 
 __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.0f) - (x < 0.0f)); }
 
-template <bool FUSED>
-__global__ __launch_bounds__(64) void k_blend_bwd(const ViewTable *__restrict__ vt, const float4 *__restrict__ rec,
-                                                  const uint32_t *__restrict__ pair_rec,
-                                                  const uint2 *__restrict__ ranges, const int64_t *__restrict__ counters,
-                                                  BlendOut st, LossIn L, float *__restrict__ grad2d) {
-    __shared__ float4 s_a[64], s_b[64], s_c[64];
-    __shared__ uint32_t s_pos[64], s_id[64];
-    const BlockPos bp = locate_block(vt);
-    if (!bp.valid) return;
-    const ViewInfo &V = vt->v[bp.v];
-    const uint32_t lane = threadIdx.x;
-    const int px = bp.bx0 + (int)(lane & 7u), py = bp.by0 + (int)(lane >> 3);
+// Backward blend.  One workgroup per binning tile, one wave per 8x8 block of
+// it (tiles are at most 16x16, so at most four waves).  The tile's list is
+// walked in reverse in segments of 64 entries; within a segment every wave
+// culls and processes the entries against its own block, reduces each
+// entry's 10 partial derivatives over its 64 lanes (DPP) and writes the sums
+// to its own LDS slots.  At the end of the segment the waves' slots are added
+// in a fixed order and written, without atomics, to the pair's own row of
+// `grad_pairs` (indexed by the pair's emission index, so that a record's rows
+// are contiguous).  Every pair of the list gets exactly one row per call.
+//
+// Partial derivatives per (pixel, entry), for alpha = o exp2(p2),
+// p2 = -(u^2 + w^2), u = l11 dx + l21 dy, w = l22 dy, dx = px - mx:
+//   dL/dalpha = T_k sum_ch g_ch (f_ch - B_ch)    (B: colour behind, per unit of
+//                                                 the transmittance after k)
+//   dL/df_ch  = g_ch alpha T_k                   (rgb and depth)
+//   dL/do = dL/dalpha G,  dL/dp2 = dL/dalpha alpha ln2   (unless clamped)
+//   dL/dmx = dL/dp2 2u l11,  dL/dmy = dL/dp2 2(u l21 + w l22)
+//   dL/dl11 = -dL/dp2 2u dx, dL/dl21 = -dL/dp2 2u dy, dL/dl22 = -dL/dp2 2w dy
+constexpr int kBwdMaxWaves = 4;
+constexpr int kSeg = 64;
+
+template <bool FUSED, bool COUNT>
+__global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__ vt, const float4 *__restrict__ rec,
+                                                   const uint32_t *__restrict__ pair_rec,
+                                                   const uint32_t *__restrict__ pair_j,
+                                                   const uint2 *__restrict__ ranges, int64_t *__restrict__ counters,
+                                                   BlendOut st, LossIn L, float *__restrict__ grad_pairs) {
+    __shared__ float4 s_a[kBwdMaxWaves][64], s_b[kBwdMaxWaves][64], s_c[kBwdMaxWaves][64];
+    __shared__ uint32_t s_pos[kBwdMaxWaves][64];
+    __shared__ float s_acc[kBwdMaxWaves][kSeg * 10];
+    __shared__ uint32_t s_wmax[kBwdMaxWaves];
+    __shared__ double s_loss[kBwdMaxWaves];
+
+    // tile of this workgroup (tiles of all views, view by view)
+    const int32_t T_all = vt->total_tiles;
+    const int32_t per = (T_all + 7) >> 3;
+    const int32_t tid_g = (int32_t)(blockIdx.x & 7u) * per + (int32_t)(blockIdx.x >> 3);   // XCD-aware
+    if (tid_g >= T_all) return;
+    int v = 0;
+    while (v + 1 < vt->n_views && vt->v[v + 1].tile_off <= tid_g) ++v;
+    const ViewInfo &V = vt->v[v];
+    const int tile = tid_g - V.tile_off;
+    const int ty = tile / V.tiles_x, tx = tile - ty * V.tiles_x;
+    const int sx = vt->tile_w / kBlk;
+    const int nw = (vt->tile_w / kBlk) * (vt->tile_h / kBlk);
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const int bx0 = tx * vt->tile_w + (int)(wave % sx) * kBlk;
+    const int by0 = ty * vt->tile_h + (int)(wave / sx) * kBlk;
+    const int px = bx0 + (int)(lane & 7u), py = by0 + (int)(lane >> 3);
     const bool inside = px < V.W && py < V.H;
     const float fpx = (float)px, fpy = (float)py;
     const int64_t P = (int64_t)V.W * V.H;
@@ -263,89 +317,145 @@ __global__ __launch_bounds__(64) void k_blend_bwd(const ViewTable *__restrict__ 
     }
     if (FUSED) {   // all 64 lanes take part in the reduction
         const double tot = wave_sum_f64(lp);
-        if (lane == 0 && tot != 0.0) atomicAdd(&L.loss[bp.v], tot);
+        if (lane == 0) s_loss[wave] = tot;
     }
     if (!(g[0] != 0.f || g[1] != 0.f || g[2] != 0.f || g[3] != 0.f || g[4] != 0.f)) last = 0;
-    uint32_t max_last = wave_max_u32(last);
-    if (max_last == 0) return;
 
-    uint2 rg = ranges[V.tile_off + bp.tile];
+    uint2 rg = ranges[tid_g];
     const uint32_t n_rec = (uint32_t)counters[kCntVisible];
     const uint32_t n_pair = (uint32_t)counters[kCntPairsUsed];
     if (rg.y > n_pair || rg.x > rg.y) rg = make_uint2(0u, 0u);   // never expected; keeps reads in bounds
-    // accumulated colour of everything behind the current entry, per unit of
-    // the transmittance just after it
+    const uint32_t wmax = wave_max_u32(last);
+    if (lane == 0) s_wmax[wave] = wmax;
+    __syncthreads();
+    if (FUSED && threadIdx.x == 0) {   // the tile's loss: its waves in a fixed order
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += s_loss[w];
+        L.loss_tile[tid_g] = t;
+    }
+    uint32_t bmax = rg.x;
+    for (int w = 0; w < nw; ++w) bmax = s_wmax[w] > bmax ? s_wmax[w] : bmax;
+    // entries behind every pixel's last contributor get zero rows
+    for (uint32_t e = bmax + threadIdx.x; e < rg.y; e += blockDim.x) {
+        float *dst = grad_pairs + 10 * (size_t)pair_j[e];
+#pragma unroll
+        for (int c = 0; c < 10; ++c) dst[c] = 0.0f;
+    }
+
     float b0 = 0.f, b1 = 0.f, b2 = 0.f, bd = 0.f, bs = 0.f;
-    for (uint32_t hi = max_last; hi > rg.x;) {
-        const uint32_t lo = hi - rg.x > 64u ? hi - 64u : rg.x;
-        const uint32_t e = lo + lane;
-        bool keep = false;
-        float4 A, B, C;
-        uint32_t s = 0;
-        if (e < hi && pair_rec[e] < n_rec) {
-            s = pair_rec[e];
-            A = rec[3 * (size_t)s];
-            B = rec[3 * (size_t)s + 1];
-            C = rec[3 * (size_t)s + 2];
-            keep = block_may_contribute(A, B, (float)bp.bx0, (float)bp.by0);
-        }
-        const uint64_t m = ballot(keep);
-        if (keep) {
-            const uint32_t slot = rank_below(m);
-            s_a[slot] = A;
-            s_b[slot] = B;
-            s_c[slot] = C;
-            s_pos[slot] = e;
-            s_id[slot] = s;
-        }
-        __syncthreads();
-        for (int k = __popcll(m) - 1; k >= 0; --k) {
-            const float4 a = s_a[k], b = s_b[k];
-            float d[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            bool contrib = false;
-            if (s_pos[k] < last) {
-                const AlphaEval ev = eval_alpha(a, b, fpx, fpy);
-                if (ev.alpha >= kAlphaMin) {
-                    contrib = true;
-                    const float4 cc = s_c[k];
-                    const float oma = 1.0f - ev.alpha;
-                    T = T * __builtin_amdgcn_rcpf(oma);   // transmittance in front of this entry
-                    const float wgt = ev.alpha * T;
-                    d[6] = g[0] * wgt;
-                    d[7] = g[1] * wgt;
-                    d[8] = g[2] * wgt;
-                    d[9] = g[3] * wgt;
-                    const float dal = T * (g[0] * (cc.x - b0) + g[1] * (cc.y - b1) + g[2] * (cc.z - b2) +
-                                           g[3] * (cc.w - bd) + g[4] * (1.0f - bs));
-                    b0 = ev.alpha * cc.x + oma * b0;
-                    b1 = ev.alpha * cc.y + oma * b1;
-                    b2 = ev.alpha * cc.z + oma * b2;
-                    bd = ev.alpha * cc.w + oma * bd;
-                    bs = ev.alpha + oma * bs;
-                    if (!ev.clamped) {
-                        d[5] = dal * ev.G;
-                        const float dp2 = dal * ev.alpha * (float)kLn2f;
-                        const float tu = 2.0f * ev.u * dp2, tw = 2.0f * ev.w * dp2;
-                        d[0] = tu * b.x;
-                        d[1] = tu * b.y + tw * b.z;
-                        d[2] = -tu * ev.dx;
-                        d[3] = -tu * ev.dy;
-                        d[4] = -tw * ev.dy;
+    uint32_t n_eval = 0, n_contrib = 0, n_red = 0;
+    float *acc = s_acc[wave];
+    for (uint32_t seg_hi = bmax; seg_hi > rg.x;) {
+        const uint32_t seg_lo = seg_hi - rg.x > (uint32_t)kSeg ? seg_hi - kSeg : rg.x;
+        for (int c = lane; c < kSeg * 10; c += 64) acc[c] = 0.0f;
+        if (wmax > seg_lo) {   // wave-uniform: this wave has pixels with entries in the segment
+            const uint32_t hi = wmax < seg_hi ? wmax : seg_hi;
+            const uint32_t e = seg_lo + lane;
+            bool keep = false;
+            float4 A, B, C;
+            if (e < hi && pair_rec[e] < n_rec) {
+                const uint32_t s = pair_rec[e];
+                A = rec[3 * (size_t)s];
+                B = rec[3 * (size_t)s + 1];
+                C = rec[3 * (size_t)s + 2];
+                keep = block_may_contribute(A, B, (float)bx0, (float)by0);
+            }
+            const uint64_t m = ballot(keep);
+            if (keep) {
+                const uint32_t slot = rank_below(m);
+                s_a[wave][slot] = A;
+                s_b[wave][slot] = B;
+                s_c[wave][slot] = C;
+                s_pos[wave][slot] = e;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            for (int k = __popcll(m) - 1; k >= 0; --k) {
+                const float4 a = s_a[wave][k], b = s_b[wave][k];
+                const uint32_t pos = s_pos[wave][k];
+                float d[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                bool contrib = false;
+                if (pos < last) {
+                    const AlphaEval ev = eval_alpha(a, b, fpx, fpy);
+                    if (COUNT) ++n_eval;
+                    if (ev.alpha >= kAlphaMin) {
+                        contrib = true;
+                        if (COUNT) ++n_contrib;
+                        const float4 cc = s_c[wave][k];
+                        const float oma = 1.0f - ev.alpha;
+                        T = T * __builtin_amdgcn_rcpf(oma);   // transmittance in front of this entry
+                        const float wgt = ev.alpha * T;
+                        d[6] = g[0] * wgt;
+                        d[7] = g[1] * wgt;
+                        d[8] = g[2] * wgt;
+                        d[9] = g[3] * wgt;
+                        const float dal = T * (g[0] * (cc.x - b0) + g[1] * (cc.y - b1) + g[2] * (cc.z - b2) +
+                                               g[3] * (cc.w - bd) + g[4] * (1.0f - bs));
+                        b0 = ev.alpha * cc.x + oma * b0;
+                        b1 = ev.alpha * cc.y + oma * b1;
+                        b2 = ev.alpha * cc.z + oma * b2;
+                        bd = ev.alpha * cc.w + oma * bd;
+                        bs = ev.alpha + oma * bs;
+                        if (!ev.clamped) {
+                            d[5] = dal * ev.G;
+                            const float dp2 = dal * ev.alpha * kLn2f;
+                            const float tu = 2.0f * ev.u * dp2, tw = 2.0f * ev.w * dp2;
+                            d[0] = tu * b.x;
+                            d[1] = tu * b.y + tw * b.z;
+                            d[2] = -tu * ev.dx;
+                            d[3] = -tu * ev.dy;
+                            d[4] = -tw * ev.dy;
+                        }
+                    }
+                }
+                if (ballot(contrib) != 0) {
+                    if (COUNT) ++n_red;
+                    float *slot = acc + 10 * (pos - seg_lo);
+#pragma unroll
+                    for (int c = 0; c < 10; ++c) {
+                        const float t = wave_sum_to63(d[c]);
+                        if (lane == 63) slot[c] = t;
                     }
                 }
             }
-            if (ballot(contrib) != 0) {
-                float *dst = grad2d + 10 * (size_t)s_id[k];
-#pragma unroll
-                for (int c = 0; c < 10; ++c) {
-                    const float t = wave_sum_to63(d[c]);
-                    if (lane == 63 && t != 0.0f) atomicAdd(dst + c, t);
-                }
-            }
         }
         __syncthreads();
-        hi = lo;
+        // add the waves' sums in a fixed order and write each entry's row
+        const uint32_t n_e = seg_hi - seg_lo;
+        for (uint32_t idx = threadIdx.x; idx < n_e * 10; idx += blockDim.x) {
+            const uint32_t e = idx / 10, c = idx - e * 10;
+            float sum = 0.0f;
+            for (int w = 0; w < nw; ++w) sum += s_acc[w][idx];
+            grad_pairs[10 * (size_t)pair_j[seg_lo + e] + c] = sum;
+        }
+        __syncthreads();
+        seg_hi = seg_lo;
     }
+    if (COUNT) {
+        const uint32_t e = wave_sum_u32(n_eval), c = wave_sum_u32(n_contrib);
+        if (lane == 0) {
+            atomicAdd((unsigned long long *)&counters[kCntEvalBwd], (unsigned long long)e);
+            atomicAdd((unsigned long long *)&counters[kCntContribBwd], (unsigned long long)c);
+            atomicAdd((unsigned long long *)&counters[kCntReduceBwd], (unsigned long long)n_red);
+        }
+    }
+}
+
+// Per-view loss: the view's tile partials added in a fixed tree order.
+__global__ __launch_bounds__(256) void k_loss_final(const ViewTable *__restrict__ vt,
+                                                    const double *__restrict__ loss_tile, double *__restrict__ loss) {
+    __shared__ double s[256];
+    const ViewInfo &V = vt->v[blockIdx.x];
+    const int n = V.tiles_x * V.tiles_y;
+    double t = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) t += loss_tile[V.tile_off + k];
+    s[threadIdx.x] = t;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[blockIdx.x] = s[0];
 }
 
 }  // namespace gsr

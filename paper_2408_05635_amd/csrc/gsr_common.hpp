@@ -43,8 +43,21 @@ enum Counter {
     kCntPairsUsed = 2,   // K if it fits the capacity, else 0
     kCntOverflow = 3,    // 1 if K exceeded the capacity
     kCntScratch = 5,     // totals of internal scans
-    kNumCounters = 8
+    // work counters (GSR_COUNT_WORK): (pixel, entry) evaluations and
+    // contributions in the forward and backward blends, and (wave, entry)
+    // gradient reductions in the backward
+    kCntEvalFwd = 8,
+    kCntContribFwd = 9,
+    kCntEvalBwd = 10,
+    kCntContribBwd = 11,
+    kCntReduceBwd = 12,
+    kNumCounters = 16
 };
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
 
 // ---------------------------------------------------------------------------
 // wave64 helpers

@@ -36,6 +36,7 @@ class RenderOptions:
     tile: Tuple[int, int] = (16, 16)
     gauss_grads: bool = True
     pose_grads: bool = True
+    count_work: bool = False
 
 
 @dataclass
@@ -135,6 +136,8 @@ class Rasterizer:
             flags |= _abi.GSR_NO_GAUSS_GRADS
         if not (o.pose_grads if pose_grads is None else pose_grads):
             flags |= _abi.GSR_NO_POSE_GRADS
+        if o.count_work:
+            flags |= _abi.GSR_COUNT_WORK
         return _abi.Options(o.w_rgb, o.w_depth, o.w_sil, o.w_prior, o.z_near, o.blur2d, o.sil_mask_thresh,
                             int(o.tile[0]), int(o.tile[1]), flags)
 
@@ -162,6 +165,29 @@ class Rasterizer:
                    self._ctx)
         self.last_counters = (int(m.value), int(k.value), int(o.value))
         return self.last_counters
+
+    def read_work(self, ws: Optional[_abi.Workspace] = None) -> dict:
+        """Work counters of the last GSR_COUNT_WORK call (synchronises)."""
+        if ws is None:
+            ws = _abi.Workspace(self._ws.data_ptr(), self._ws.numel(), self.pair_capacity)
+        arr = (C.c_int64 * 5)()
+        _abi.check(_ABI.gsr_read_work(self._ctx, ws, _stream_ptr(), arr), self._ctx)
+        return dict(eval_fwd=arr[0], contrib_fwd=arr[1], eval_bwd=arr[2], contrib_bwd=arr[3], reduce_bwd=arr[4])
+
+    def set_timing(self, on: bool) -> None:
+        _abi.check(_ABI.gsr_set_timing(self._ctx, int(bool(on))), self._ctx)
+
+    def read_timing(self) -> dict:
+        """{stage: (total ms, launches)} since the last read (waits for the events)."""
+        ms = (C.c_double * 4)()
+        cnt = (C.c_int64 * 4)()
+        _abi.check(_ABI.gsr_read_timing(self._ctx, ms, cnt), self._ctx)
+        return {name: (ms[k], cnt[k]) for k, name in enumerate(_abi.STAGES)}
+
+    def shared_workspace(self) -> Optional[_abi.Workspace]:
+        if self._ws is None:
+            return None
+        return _abi.Workspace(self._ws.data_ptr(), self._ws.numel(), self.pair_capacity)
 
     def _grow(self, needed: int) -> None:
         self.pair_capacity = max(int(needed * 1.25) + 1024, self.pair_capacity)
@@ -292,6 +318,23 @@ class Rasterizer:
         torch.cuda.current_stream().synchronize()
         return dict(M=M, K=K, overflow=ovf, gid=gid[:M].cpu(), xy=xy[:M].cpu(), radius=rad[:M].cpu(),
                     z=z[:M].cpu(), ranges=ranges[:T].cpu(), pairs=pairs[:K].cpu())
+
+    def pixel_state(self, g: GaussianParams, quat, trans, cams, opts: RenderOptions,
+                    ws: Optional[_abi.Workspace] = None) -> dict:
+        """Per-pixel final transmittance, last contributor and decision hash
+        left by the last call on ws (default: the shared workspace)."""
+        views, keep = self._views(cams, quat, trans)
+        gs = self._gauss(g)
+        o = self._opts(opts, g.isotropic)
+        ws = self.shared_workspace() if ws is None else ws
+        P = total_pixels(cams)
+        dev = self.device
+        t_final = torch.empty(P, dtype=torch.float32, device=dev)
+        n_last = torch.empty(P, dtype=torch.int32, device=dev)
+        hsh = torch.empty(P, dtype=torch.int32, device=dev)
+        _abi.check(_ABI.gsr_debug_pixel_state(self._ctx, C.byref(gs), C.byref(views), C.byref(o), ws, _ptr(t_final),
+                                              _ptr(n_last), _ptr(hsh), _stream_ptr()), self._ctx)
+        return dict(t_final=t_final, n_last=n_last, hash=hsh)
 
     def selftest(self) -> int:
         d = torch.empty(1, dtype=torch.int32, device=self.device)

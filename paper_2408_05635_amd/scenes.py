@@ -101,6 +101,11 @@ class Workload:
     target_views: Views          # poses the targets are rendered at
     prior_noise: Optional[np.ndarray] = None  # per-pixel multiplicative N(0, sigma) draws, concatenated
     weights: dict = field(default_factory=dict)
+    target_gaussians: Optional[Gaussians] = None  # scene the targets are rendered from (None: `gaussians`)
+
+    @property
+    def truth(self) -> Gaussians:
+        return self.gaussians if self.target_gaussians is None else self.target_gaussians
 
 
 # ----------------------------------------------------------------------------
@@ -352,16 +357,33 @@ def config2(n_views: int = 8, n: int = 200_000) -> Workload:
                     weights=dict(w_rgb=0.5, w_depth=1.0, w_sil=1.0, w_prior=0.0))
 
 
+def perturbed_map(g: Gaussians, rng: np.random.Generator) -> Gaussians:
+    """The map being optimised: every parameter of the true scene off by a
+    small seeded amount (5 mm, 0.1 in log-scale, 0.3 in opacity logit, 0.05
+    in colour and in each quaternion component)."""
+    n = g.n
+    return Gaussians(
+        means=(g.means + rng.normal(0.0, 0.005, size=(n, 3))).astype(np.float32),
+        quats=(g.quats + rng.normal(0.0, 0.05, size=(n, 4))).astype(np.float32),
+        log_scales=(g.log_scales + rng.normal(0.0, 0.1, size=g.log_scales.shape)).astype(np.float32),
+        opacity_logits=(g.opacity_logits + rng.normal(0.0, 0.3, size=n)).astype(np.float32),
+        rgb=(g.rgb + rng.normal(0.0, 0.05, size=(n, 3))).astype(np.float32),
+    )
+
+
 def config3(n: int = 500_000, n_views: int = 8) -> Workload:
-    """Mapping: 500k-Gaussian room, 8 keyframes on a smooth trajectory, depth prior."""
+    """Mapping: 500k-Gaussian room, 8 keyframes on a smooth trajectory, depth
+    prior.  Poses are the true ones; the map is a perturbed copy of the scene
+    (sub-seed 33) and the targets are renders of the true scene."""
     rng = np.random.default_rng(3)
     g, _ = room_gaussians(rng, n)
     q, t = smooth_trajectory(np.random.default_rng(31), n_views, (0.5, 0.5), (3.5, 3.5))
     views = Views([_room_cam()] * n_views, q, t)
     P = sum(c.width * c.height for c in views.cams)
     noise = np.random.default_rng(32).normal(0.0, 0.02, size=P).astype(np.float32)
-    return Workload("config3_500k_8x640x480_prior", g, views, views, prior_noise=noise,
-                    weights=dict(w_rgb=0.5, w_depth=1.0, w_sil=1.0, w_prior=1.0))
+    return Workload("config3_500k_8x640x480_prior", perturbed_map(g, np.random.default_rng(33)), views, views,
+                    prior_noise=noise, weights=dict(w_rgb=0.5, w_depth=1.0, w_sil=1.0, w_prior=1.0),
+                    target_gaussians=g)
 
 
 def config4(n: int = 1_000_000, n_views: int = 32) -> Workload:

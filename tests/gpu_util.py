@@ -31,7 +31,7 @@ def dev_poses(views, device="cuda"):
 def oracle_targets(w, prior_noise=None):
     """Targets = oracle render at the target poses, rounded to float32 (the
     inputs both sides see)."""
-    r = oracle.run(w.gaussians, w.target_views)
+    r = oracle.run(w.truth, w.target_views)
     f = lambda a: np.asarray(a, np.float32)  # noqa: E731
     tg = dict(rgb=f(r.rgb), depth=f(r.depth), sil=f(r.sil))
     if prior_noise is not None:
@@ -77,6 +77,10 @@ def grad_errors(gpu: dict, orc_grads: dict, keys=None) -> dict:
              "opacity_logits": "g_opacity_logits", "rgb": "g_rgb", "dq_t": "dq_t", "dt": "dt", "dq_c": "dq_c",
              "dc": "dc"}
     out = {}
+    # a group whose oracle gradient is rounding noise (e.g. quaternions of
+    # isotropic Gaussians, exactly zero in theory) is measured against the
+    # largest gradient of all groups instead of against itself
+    scale = max(float(np.abs(v).max()) for k, v in orc_grads.items() if k in names)
     for k, gk in names.items():
         if keys is not None and k not in keys:
             continue
@@ -84,6 +88,6 @@ def grad_errors(gpu: dict, orc_grads: dict, keys=None) -> dict:
             continue
         g = gpu[gk].double().cpu().numpy().reshape(orc_grads[k].shape)
         o = orc_grads[k]
-        den = np.abs(o).max()
-        out[k] = float(np.abs(g - o).max() / den) if den > 0 else float(np.abs(g).max())
+        den = max(float(np.abs(o).max()), 1e-9 * scale, 1e-300)
+        out[k] = float(np.abs(g - o).max() / den)
     return out

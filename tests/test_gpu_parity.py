@@ -122,7 +122,7 @@ def _check_binning(rast, w, tile):
     return mism
 
 
-@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 16)])
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (8, 16)])
 def test_binning_bit_exact_config1(rast, tile):
     assert _check_binning(rast, scenes.config1(), tile) == 0
 
@@ -208,12 +208,31 @@ def test_split_backward_matches_oracle(rast):
 
 
 def test_tile_size_invariance(rast):
+    """Each pixel sees the same entries in the same order at every tile size:
+    images are bit-identical and gradients agree to rounding."""
     w = scenes.config1()
-    base, _ = _forward(rast, w, (16, 16))
-    for tile in [(8, 8), (16, 8), (32, 16), (32, 32), (64, 64)]:
-        out, _ = _forward(rast, w, tile)
+    tg = oracle_targets(w)
+    base = _fused(rast, w, (16, 16), tg)
+    for tile in [(8, 8), (16, 8), (8, 16)]:
+        out = _fused(rast, w, tile, tg)
         for k in ("rgb", "depth", "sil"):
             assert torch.equal(out[k], base[k]), (tile, k)
+        # the per-view loss is an FP64 sum whose grouping follows the tiling
+        assert ((out["loss"] - base["loss"]).abs() / base["loss"].abs()).max().item() < 1e-12
+        for k in ("g_means", "g_quats", "g_log_scales", "g_opacity_logits", "g_rgb", "dq_t", "dt"):
+            d = (out[k].double() - base[k].double()).abs().max() / base[k].double().abs().max()
+            assert d.item() < 1e-5, (tile, k, d.item())
+
+
+def test_gradients_are_deterministic(rast):
+    """No float atomics on the Gaussian gradients: two runs agree bit for bit."""
+    w = scenes.config1()
+    tg = oracle_targets(w)
+    a = _fused(rast, w, (16, 16), tg)
+    a = {k: v.clone() for k, v in a.items()}
+    b = _fused(rast, w, (16, 16), tg)
+    for k in ("g_means", "g_quats", "g_log_scales", "g_opacity_logits", "g_rgb", "loss"):
+        assert torch.equal(a[k], b[k]), k
 
 
 def test_order_invariance(rast):
@@ -240,7 +259,8 @@ def test_batched_equals_single_views(rast):
         one = _fused(rast, wv, targets=tv)
         assert torch.equal(one["rgb"], allv["rgb"][3 * P * v:3 * P * (v + 1)])
         assert torch.equal(one["depth"], allv["depth"][P * v:P * (v + 1)])
-        assert torch.equal(one["dt"][0], allv["dt"][v]) or torch.allclose(one["dt"][0], allv["dt"][v], rtol=1e-5)
+        dt1, dtb = one["dt"][0].double(), allv["dt"][v].double()
+        assert ((dt1 - dtb).abs().max() / dtb.abs().max()).item() < 1e-5
         gsum = one["g_means"].clone() if gsum is None else gsum + one["g_means"]
     scale = allv["g_means"].abs().max()
     assert ((gsum - allv["g_means"]).abs().max() / scale).item() < 1e-5
