@@ -39,6 +39,7 @@ METRIC = "fwd+bwd views/sec at 640×480, 200k Gaussians (batched vs plain); pose
 # (one non-packed FP32 instruction per lane per slot; 157.3 TFLOP/s counts packed FMA as 4 FLOP)
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 256 << 20   # the calibration copy reads and writes this many bytes
 # algorithmic FP32 lane-op slots per (pixel, Gaussian) pair of the blend,
 # transcendental ops at quarter rate (4 slots): see the roofline section of the design notes
 C_ALPHA = 17     # dx, dy (split mean), factor products, exp2, opacity, clamp, 1/255 test
@@ -60,6 +61,9 @@ def parse():
     ap.add_argument("--cpu-views", type=int, default=8, help="views in the oracle's timed sample")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many batched steps (for a profiler) and print nothing else")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="with --profile-steps: also copy 256 MiB device to device, the reference for the "
+                         "HBM byte counters")
     return ap.parse_args()
 
 
@@ -102,6 +106,12 @@ def main():
         for _ in range(args.profile_steps):
             batched_step()
         torch.cuda.synchronize()
+        if args.copy_calibration:
+            src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
         print(json.dumps({"profile_steps": args.profile_steps, "pairs": K, "visible": M}), flush=True)
         return
 
@@ -196,7 +206,7 @@ def main():
     achieved = dom_ops / (dom_ms * 1e-3) / 1e12
     peak = VALU_PEAK_LANE_OPS / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "T lane-op/s",
-                "frac": achieved / peak, "traffic": None,
+                "frac": achieved / peak, "traffic": measured_traffic(dom),
                 "frac_list": ((ops_bwd_list if dom == "blend_bwd" else ops_fwd) / (dom_ms * 1e-3) / 1e12) / peak,
                 "ops_per_launch": dom_ops, "avg_launch_ms": dom_ms}
 
@@ -230,16 +240,43 @@ def main():
     print(json.dumps(res), flush=True)
 
 
+def kernel_source_hash() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2408_05635_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (copy-calibrated), or None if the kernel sources changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "blend_bwd_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel") != "k_" + kernel or t.get("source_sha256") != kernel_source_hash():
+        return None
+    return t["read_bytes"] + t["write_bytes"]
+
+
 def decision_stable_pose_fd(rast, raster, g, q0, t0, cams, tg, opts, h):
     """FP32 central differences of the loss with respect to the pose, over the
-    pixels whose decisions (contributing records, clamps, cut-off) are the same
-    at every probed pose: elsewhere the image jumps (a Gaussian crossing the
-    1/255 threshold), and no difference quotient converges there.  The
+    pixels whose decisions (contributing records, clamps, cut-off) and L1
+    residual signs are the same at every probed pose: elsewhere the image
+    jumps (a Gaussian crossing the 1/255 threshold) or the loss has a kink,
+    and the difference quotient does not converge to the gradient there.  The
     analytic gradient is taken with the same pixel weights.  Returns the
     analytic and FD gradients (q then t) and the number of stable pixels."""
     import torch
     o = raster.RenderOptions(**{**opts.__dict__, "gauss_grads": False})
     dev = q0.device
+
+    P = tg["depth"].numel()
 
     def run(qq, tt, weight=None):
         t = dict(tg)
@@ -248,7 +285,14 @@ def decision_stable_pose_fd(rast, raster, g, q0, t0, cams, tg, opts, h):
         out = rast.render_loss_grad(g, qq, tt, cams, t, o)
         return out, rast.pixel_state(g, qq, tt, cams, o)["hash"]
 
+    def signature(out, hsh):   # decisions and the signs of the L1 residuals
+        parts = [hsh.to(torch.int64), torch.sign(out["depth"] - tg["depth"]).to(torch.int64),
+                 torch.sign(out["sil"] - tg["sil"]).to(torch.int64)]
+        rgb = torch.sign(out["rgb"] - tg["rgb"]).to(torch.int64)
+        return parts + [rgb[c * P:(c + 1) * P] for c in range(3)]
+
     base, h0 = run(q0, t0)
+    sig0 = signature(base, h0)
     stable = torch.ones_like(h0, dtype=torch.bool)
     probes = []
     for j in range(7):
@@ -259,8 +303,9 @@ def decision_stable_pose_fd(rast, raster, g, q0, t0, cams, tg, opts, h):
             else:
                 tt[0, j - 4] += sgn * h
             probes.append((qq, tt))
-            _, hh = run(qq, tt)
-            stable &= hh == h0
+            out, hh = run(qq, tt)
+            for a, b in zip(signature(out, hh), sig0):
+                stable &= a == b
     wgt = stable.to(torch.float32)
     an, _ = run(q0, t0, wgt)
     analytic = np.concatenate([an["dq_t"].double().cpu().numpy().ravel(), an["dt"].double().cpu().numpy().ravel()])

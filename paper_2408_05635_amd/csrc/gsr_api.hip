@@ -813,11 +813,11 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
             hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, vt, at<float4>(c.ws, L.rec), pair_values(c),
                                pair_j(c), at<uint2>(c.ws, L.ranges), counters, bo, li, gpairs);
         }
-        if (fused) {
-            if (L.kcap == 0)   // no blend ran: every tile's partial is zero
-                hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(L.T, 256)), dim3(256), 0, st, li.loss_tile, L.T);
-            hipLaunchKernelGGL(k_loss_final, dim3(views->n_views), dim3(256), 0, st, vt, li.loss_tile, li.loss);
-        }
+    }
+    if (fused) {
+        if (L.kcap == 0)   // no blend ran: every tile's partial is zero
+            hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(L.T, 256)), dim3(256), 0, st, li.loss_tile, L.T);
+        hipLaunchKernelGGL(k_loss_final, dim3(views->n_views), dim3(256), 0, st, vt, li.loss_tile, li.loss);
     }
     GradOut go;
     memset(&go, 0, sizeof(go));

@@ -233,7 +233,7 @@ __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.0f) - (x 
 //   dL/dmx = dL/dp2 2u l11,  dL/dmy = dL/dp2 2(u l21 + w l22)
 //   dL/dl11 = -dL/dp2 2u dx, dL/dl21 = -dL/dp2 2u dy, dL/dl22 = -dL/dp2 2w dy
 constexpr int kBwdMaxWaves = 4;
-constexpr int kSeg = 64;
+constexpr int kSeg = 32;   // list entries per segment (LDS: 4 waves x 4 rows x kSeg x 10 floats)
 
 template <bool FUSED, bool COUNT>
 __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__ vt, const float4 *__restrict__ rec,
@@ -241,9 +241,10 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                                                    const uint32_t *__restrict__ pair_j,
                                                    const uint2 *__restrict__ ranges, int64_t *__restrict__ counters,
                                                    BlendOut st, LossIn L, float *__restrict__ grad_pairs) {
-    __shared__ float4 s_a[kBwdMaxWaves][64], s_b[kBwdMaxWaves][64], s_c[kBwdMaxWaves][64];
-    __shared__ uint32_t s_pos[kBwdMaxWaves][64];
-    __shared__ float s_acc[kBwdMaxWaves][kSeg * 10];
+    __shared__ float4 s_a[kBwdMaxWaves][kSeg], s_b[kBwdMaxWaves][kSeg], s_c[kBwdMaxWaves][kSeg];
+    __shared__ uint32_t s_pos[kBwdMaxWaves][kSeg];
+    // per wave, per 16-lane row, per entry of the segment: the row's sums of the 10 partials
+    __shared__ float s_acc[kBwdMaxWaves][4][kSeg * 10];
     __shared__ uint32_t s_wmax[kBwdMaxWaves];
     __shared__ double s_loss[kBwdMaxWaves];
 
@@ -344,16 +345,17 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
 
     float b0 = 0.f, b1 = 0.f, b2 = 0.f, bd = 0.f, bs = 0.f;
     uint32_t n_eval = 0, n_contrib = 0, n_red = 0;
-    float *acc = s_acc[wave];
+    float *acc = &s_acc[wave][0][0];
+    const uint32_t row = lane >> 4;
     for (uint32_t seg_hi = bmax; seg_hi > rg.x;) {
         const uint32_t seg_lo = seg_hi - rg.x > (uint32_t)kSeg ? seg_hi - kSeg : rg.x;
-        for (int c = lane; c < kSeg * 10; c += 64) acc[c] = 0.0f;
+        for (int c = lane; c < 4 * kSeg * 10; c += 64) acc[c] = 0.0f;
         if (wmax > seg_lo) {   // wave-uniform: this wave has pixels with entries in the segment
             const uint32_t hi = wmax < seg_hi ? wmax : seg_hi;
             const uint32_t e = seg_lo + lane;
             bool keep = false;
             float4 A, B, C;
-            if (e < hi && pair_rec[e] < n_rec) {
+            if (lane < (uint32_t)kSeg && e < hi && pair_rec[e] < n_rec) {
                 const uint32_t s = pair_rec[e];
                 A = rec[3 * (size_t)s];
                 B = rec[3 * (size_t)s + 1];
@@ -371,61 +373,77 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             for (int k = __popcll(m) - 1; k >= 0; --k) {
-                const float4 a = s_a[wave][k], b = s_b[wave][k];
                 const uint32_t pos = s_pos[wave][k];
-                float d[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                bool contrib = false;
-                if (pos < last) {
-                    const AlphaEval ev = eval_alpha(a, b, fpx, fpy);
-                    if (COUNT) ++n_eval;
-                    if (ev.alpha >= kAlphaMin) {
-                        contrib = true;
-                        if (COUNT) ++n_contrib;
-                        const float4 cc = s_c[wave][k];
-                        const float oma = 1.0f - ev.alpha;
-                        T = T * __builtin_amdgcn_rcpf(oma);   // transmittance in front of this entry
-                        const float wgt = ev.alpha * T;
-                        d[6] = g[0] * wgt;
-                        d[7] = g[1] * wgt;
-                        d[8] = g[2] * wgt;
-                        d[9] = g[3] * wgt;
-                        const float dal = T * (g[0] * (cc.x - b0) + g[1] * (cc.y - b1) + g[2] * (cc.z - b2) +
-                                               g[3] * (cc.w - bd) + g[4] * (1.0f - bs));
-                        b0 = ev.alpha * cc.x + oma * b0;
-                        b1 = ev.alpha * cc.y + oma * b1;
-                        b2 = ev.alpha * cc.z + oma * b2;
-                        bd = ev.alpha * cc.w + oma * bd;
-                        bs = ev.alpha + oma * bs;
-                        if (!ev.clamped) {
-                            d[5] = dal * ev.G;
-                            const float dp2 = dal * ev.alpha * kLn2f;
-                            const float tu = 2.0f * ev.u * dp2, tw = 2.0f * ev.w * dp2;
-                            d[0] = tu * b.x;
-                            d[1] = tu * b.y + tw * b.z;
-                            d[2] = -tu * ev.dx;
-                            d[3] = -tu * ev.dy;
-                            d[4] = -tw * ev.dy;
-                        }
-                    }
+                const bool act = pos < last;
+                if (ballot(act) == 0) continue;   // wave-uniform
+                const float4 a = s_a[wave][k], b = s_b[wave][k];
+                // every lane evaluates (the wave pays for it either way); the
+                // decisions and the state updates are selects, not branches
+                const AlphaEval ev = eval_alpha(a, b, fpx, fpy);
+                const bool contrib = act && ev.alpha >= kAlphaMin;
+                if (COUNT) n_eval += act ? 1u : 0u;
+                if (ballot(contrib) == 0) continue;   // wave-uniform: nothing to add for this entry
+                if (COUNT) {
+                    n_contrib += contrib ? 1u : 0u;
+                    ++n_red;
                 }
-                if (ballot(contrib) != 0) {
-                    if (COUNT) ++n_red;
-                    float *slot = acc + 10 * (pos - seg_lo);
+                const float4 cc = s_c[wave][k];
+                const float oma = 1.0f - ev.alpha;
+                const float Tk = T * __builtin_amdgcn_rcpf(oma);   // transmittance in front of this entry
+                const float wgt = ev.alpha * Tk;
+                const float dal = Tk * (g[0] * (cc.x - b0) + g[1] * (cc.y - b1) + g[2] * (cc.z - b2) +
+                                        g[3] * (cc.w - bd) + g[4] * (1.0f - bs));
+                const float live = (contrib && !ev.clamped) ? 1.0f : 0.0f;
+                const float dp2 = live * dal * ev.alpha * kLn2f;
+                const float tu = 2.0f * ev.u * dp2, tw = 2.0f * ev.w * dp2;
+                const float wc = contrib ? wgt : 0.0f;
+                float d[10];
+                d[0] = tu * b.x;
+                d[1] = tu * b.y + tw * b.z;
+                d[2] = -tu * ev.dx;
+                d[3] = -tu * ev.dy;
+                d[4] = -tw * ev.dy;
+                d[5] = live * dal * ev.G;
+                d[6] = g[0] * wc;
+                d[7] = g[1] * wc;
+                d[8] = g[2] * wc;
+                d[9] = g[3] * wc;
+                if (contrib) {
+                    b0 = ev.alpha * cc.x + oma * b0;
+                    b1 = ev.alpha * cc.y + oma * b1;
+                    b2 = ev.alpha * cc.z + oma * b2;
+                    bd = ev.alpha * cc.w + oma * bd;
+                    bs = ev.alpha + oma * bs;
+                    T = Tk;
+                }
+                // sums within each row of 16 lanes, the ten chains interleaved
 #pragma unroll
-                    for (int c = 0; c < 10; ++c) {
-                        const float t = wave_sum_to63(d[c]);
-                        if (lane == 63) slot[c] = t;
-                    }
+                for (int c = 0; c < 10; ++c) d[c] += dpp_f<0xb1>(d[c]);    // quad_perm [1,0,3,2]
+#pragma unroll
+                for (int c = 0; c < 10; ++c) d[c] += dpp_f<0x4e>(d[c]);    // quad_perm [2,3,0,1]
+#pragma unroll
+                for (int c = 0; c < 10; ++c) d[c] += dpp_f<0x114>(d[c]);   // row_shr:4
+#pragma unroll
+                for (int c = 0; c < 10; ++c) d[c] += dpp_f<0x118>(d[c]);   // row_shr:8
+                if ((lane & 15u) == 15u) {   // the row's sum is in its last lane
+                    float2 *dst = reinterpret_cast<float2 *>(acc + (row * kSeg + (pos - seg_lo)) * 10);
+                    dst[0] = make_float2(d[0], d[1]);
+                    dst[1] = make_float2(d[2], d[3]);
+                    dst[2] = make_float2(d[4], d[5]);
+                    dst[3] = make_float2(d[6], d[7]);
+                    dst[4] = make_float2(d[8], d[9]);
                 }
             }
         }
         __syncthreads();
-        // add the waves' sums in a fixed order and write each entry's row
+        // add the rows of all waves in a fixed order and write each entry's row
         const uint32_t n_e = seg_hi - seg_lo;
         for (uint32_t idx = threadIdx.x; idx < n_e * 10; idx += blockDim.x) {
             const uint32_t e = idx / 10, c = idx - e * 10;
             float sum = 0.0f;
-            for (int w = 0; w < nw; ++w) sum += s_acc[w][idx];
+            for (int w = 0; w < nw; ++w)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sum += s_acc[w][r][idx];
             grad_pairs[10 * (size_t)pair_j[seg_lo + e] + c] = sum;
         }
         __syncthreads();
