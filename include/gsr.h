@@ -181,7 +181,8 @@ void gsr_destroy(gsr_ctx *ctx);
 const char *gsr_last_error(const gsr_ctx *ctx);
 
 /* Bytes of workspace needed for n Gaussians, these views (only the cameras
- * are read) and pair_capacity (Gaussian, tile) pairs. */
+ * are read) and pair_capacity (Gaussian, tile) pairs.  Needs no device: ctx
+ * may be NULL, and then an error's text is what gsr_last_error(NULL) returns. */
 gsr_status gsr_workspace_size(gsr_ctx *ctx, int64_t n, const gsr_views *views, const gsr_options *opts,
                               int64_t pair_capacity, size_t *bytes);
 

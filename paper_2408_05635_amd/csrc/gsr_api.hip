@@ -113,7 +113,10 @@ gsr_status fail(gsr_ctx *ctx, gsr_status st, const char *fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(buf, sizeof(buf), fmt, ap);
     va_end(ap);
-    if (ctx) ctx->err = buf;
+    if (ctx)
+        ctx->err = buf;
+    else
+        g_create_err = buf;
     return st;
 }
 
@@ -903,7 +906,7 @@ const char *gsr_last_error(const gsr_ctx *ctx) { return ctx ? ctx->err.c_str() :
 
 gsr_status gsr_workspace_size(gsr_ctx *ctx, int64_t n, const gsr_views *views, const gsr_options *opts,
                               int64_t pair_capacity, size_t *bytes) {
-    if (!ctx) return GSR_EINVAL;
+    // needs no device: with ctx == NULL errors go to the text gsr_last_error(NULL) returns
     if (!bytes) return fail(ctx, GSR_EINVAL, "bytes must not be NULL");
     gsr_status s = validate_views(ctx, views, opts);
     if (s != GSR_OK) return s;

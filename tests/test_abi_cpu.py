@@ -1,0 +1,108 @@
+"""The C ABI on the host: the library loads, exports every function that
+include/gsr.h declares, and validates arguments before touching a device
+(these tests run without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2408_05635_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "gsr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gsr_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    lib = _abi.load()
+    names = header_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in include/gsr.h but not exported"
+    assert sorted(names) == sorted(_abi.EXPORTS), "the ctypes binding and the header disagree"
+
+
+def test_struct_sizes_match_the_header():
+    # gsr_options: 7 floats, 2 int32, 1 uint32; gsr_camera: 2 int32 + 4 floats
+    assert C.sizeof(_abi.Options) == 40
+    assert C.sizeof(_abi.Camera) == 24
+    assert C.sizeof(_abi.Workspace) == 24
+
+
+def _views(n_views=1, w=640, h=480):
+    cams = (_abi.Camera * n_views)(*[_abi.Camera(w, h, 525.0, 525.0, 319.5, 239.5) for _ in range(n_views)])
+    return _abi.Views(n_views, cams, None, None), cams
+
+
+def _opts(tw=16, th=16, blur=0.3, znear=0.2):
+    return _abi.Options(0.5, 1.0, 1.0, 0.0, znear, blur, -1.0, tw, th, 0)
+
+
+def _size(n, views, opts, cap):
+    lib = _abi.load()
+    out = C.c_size_t()
+    st = lib.gsr_workspace_size(None, n, C.byref(views), C.byref(opts), cap, C.byref(out))
+    return st, out.value, (lib.gsr_last_error(None) or b"").decode()
+
+
+def test_workspace_size_grows_with_inputs():
+    v1, keep1 = _views(1)
+    v8, keep8 = _views(8)
+    st, a, _ = _size(200_000, v1, _opts(), 1 << 20)
+    assert st == _abi.GSR_OK and a > 0
+    st, b, _ = _size(200_000, v8, _opts(), 1 << 20)
+    assert st == _abi.GSR_OK and b > a
+    st, c, _ = _size(200_000, v8, _opts(), 1 << 22)
+    assert st == _abi.GSR_OK and c > b
+    st, d, _ = _size(0, v1, _opts(), 0)
+    assert st == _abi.GSR_OK and d > 0
+
+
+@pytest.mark.parametrize("tile", [(4, 16), (16, 12), (32, 16), (0, 0)])
+def test_rejects_bad_tiles(tile):
+    v, keep = _views(1)
+    st, _, msg = _size(1000, v, _opts(*tile), 1000)
+    assert st == _abi.GSR_EINVAL and "tile" in msg
+
+
+def test_rejects_bad_views_and_options():
+    v, keep = _views(1, w=0)
+    st, _, msg = _size(1000, v, _opts(), 1000)
+    assert st == _abi.GSR_EINVAL and "image size" in msg
+    v, keep = _views(_abi.GSR_MAX_VIEWS + 1)
+    st, _, msg = _size(1000, v, _opts(), 1000)
+    assert st == _abi.GSR_EUNSUPPORTED
+    v, keep = _views(1)
+    st, _, msg = _size(-1, v, _opts(), 1000)
+    assert st == _abi.GSR_EINVAL
+    st, _, msg = _size(1000, v, _opts(blur=-1.0), 1000)
+    assert st == _abi.GSR_EINVAL and "blur" in msg
+    st, _, msg = _size(1000, v, _opts(znear=float("nan")), 1000)
+    assert st == _abi.GSR_EINVAL and "z_near" in msg
+    st, _, msg = _size(1000, v, _opts(), -5)
+    assert st == _abi.GSR_EINVAL and "pair_capacity" in msg
+    st, _, msg = _size(1 << 31, _views(4)[0], _opts(), 1000)
+    assert st == _abi.GSR_EUNSUPPORTED
+
+
+def test_null_context_calls_fail_cleanly():
+    lib = _abi.load()
+    assert lib.gsr_forward(None, None, None, None, _abi.Workspace(), _abi.Images(), None) == _abi.GSR_EINVAL
+    assert lib.gsr_set_timing(None, 1) == _abi.GSR_EINVAL
+    lib.gsr_destroy(None)   # allowed
+
+
+def test_create_without_a_device_reports_an_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = _abi.load()
+    h = C.c_void_p()
+    st = lib.gsr_create(C.byref(h), 0)
+    assert st != _abi.GSR_OK and not h.value
+    assert lib.gsr_last_error(None)
