@@ -289,6 +289,28 @@ int oracle_run(const or_in *in, or_out *out) {
     for (int v = 0; v < V; ++v) {
         const int Wd = in->width[v], Hd = in->height[v];
         const int64_t P = (int64_t)Wd * Hd;
+        if (in->pixel_mask) {   /* a view with no selected pixel contributes nothing: skip its work */
+            int any = 0;
+            for (int64_t p = 0; p < P && !any; ++p) any = in->pixel_mask[off + p] != 0;
+            if (!any) {
+                for (int64_t p = 0; p < P; ++p) {
+                    if (out->rgb) { out->rgb[3 * off + p] = 0; out->rgb[3 * off + P + p] = 0; out->rgb[3 * off + 2 * P + p] = 0; }
+                    if (out->depth) out->depth[off + p] = 0;
+                    if (out->sil) out->sil[off + p] = 0;
+                    if (out->t_final) out->t_final[off + p] = 1.0;
+                    if (out->n_contrib) out->n_contrib[off + p] = 0;
+                    if (out->ambiguous) out->ambiguous[off + p] = 0;
+                }
+                if (out->loss) out->loss[v] = 0.0;
+                if (out->decision_hash) out->decision_hash[v] = 0;
+                if (in->want_grads && in->t_rgb && out->g_q_t)
+                    for (int k = 0; k < 4; ++k) { out->g_q_t[4 * v + k] = 0; out->g_q_c[4 * v + k] = 0; }
+                if (in->want_grads && in->t_rgb && out->g_t)
+                    for (int k = 0; k < 3; ++k) { out->g_t[3 * v + k] = 0; out->g_c[3 * v + k] = 0; }
+                off += P;
+                continue;
+            }
+        }
         double W[9];
         quat_to_rot(in->pose_q + 4 * v, W, NULL);
         const double *t = in->pose_t + 3 * v;

@@ -488,3 +488,27 @@ def test_binning_rectangle_is_superset(oracle_lib):
     # and the per-tile lists do not depend on the image being visited tile by tile
     s16, ids16 = oracle.bin_view(pr, cam.width, cam.height, 16, 16)
     assert s16[-1] == ids16.size and ids16.size > 0
+
+
+def test_pixel_mask_skips_unselected_views_exactly(oracle_lib):
+    """With a pixel mask that selects nothing in a view, that view contributes
+    exactly nothing: the result equals the one-view run on the selected view."""
+    w = scenes.tiny_scene(17, n=30)
+    cam = w.views.cams[0]
+    two = scenes.Views([cam, cam], np.concatenate([w.views.quat, w.target_views.quat]),
+                       np.concatenate([w.views.trans, w.target_views.trans]))
+    P = cam.width * cam.height
+    tg1 = oracle.run(w.gaussians, w.target_views, OPTS)
+    rgb = np.concatenate([tg1.rgb, tg1.rgb])   # planar per view: view 0 (r, g, b), then view 1
+    mask = np.zeros(2 * P, np.uint8)
+    mask[:P:3] = 1
+    t2 = oracle.Targets(rgb, np.concatenate([tg1.depth, tg1.depth]), np.concatenate([tg1.sil, tg1.sil]),
+                        weight=mask.astype(float))
+    r2 = oracle.run(w.gaussians, two, OPTS, t2, want_grads=True, pixel_mask=mask)
+    t1 = oracle.Targets(tg1.rgb, tg1.depth, tg1.sil, weight=mask[:P].astype(float))
+    r1 = oracle.run(w.gaussians, w.views, OPTS, t1, want_grads=True, pixel_mask=mask[:P])
+    assert r2.loss[1] == 0.0 and r2.loss[0] == r1.loss[0]
+    for k in ("means", "quats", "log_scales", "opacity_logits", "rgb"):
+        np.testing.assert_array_equal(r2.grads[k], r1.grads[k])
+    assert np.all(r2.grads["dq_t"][1] == 0) and np.all(r2.grads["dt"][1] == 0)
+    np.testing.assert_array_equal(r2.grads["dq_t"][0], r1.grads["dq_t"][0])
