@@ -492,7 +492,8 @@ def test_binning_rectangle_is_superset(oracle_lib):
 
 def test_pixel_mask_skips_unselected_views_exactly(oracle_lib):
     """With a pixel mask that selects nothing in a view, that view contributes
-    exactly nothing: the result equals the one-view run on the selected view."""
+    exactly nothing: the result equals the one-view run on the selected view
+    (up to the grouping of sums, which follows the threads' dynamic schedule)."""
     w = scenes.tiny_scene(17, n=30)
     cam = w.views.cams[0]
     two = scenes.Views([cam, cam], np.concatenate([w.views.quat, w.target_views.quat]),
@@ -507,8 +508,9 @@ def test_pixel_mask_skips_unselected_views_exactly(oracle_lib):
     r2 = oracle.run(w.gaussians, two, OPTS, t2, want_grads=True, pixel_mask=mask)
     t1 = oracle.Targets(tg1.rgb, tg1.depth, tg1.sil, weight=mask[:P].astype(float))
     r1 = oracle.run(w.gaussians, w.views, OPTS, t1, want_grads=True, pixel_mask=mask[:P])
-    assert r2.loss[1] == 0.0 and r2.loss[0] == r1.loss[0]
+    assert r2.loss[1] == 0.0
+    np.testing.assert_allclose(r2.loss[0], r1.loss[0], rtol=1e-13)
     for k in ("means", "quats", "log_scales", "opacity_logits", "rgb"):
-        np.testing.assert_array_equal(r2.grads[k], r1.grads[k])
+        np.testing.assert_allclose(r2.grads[k], r1.grads[k], rtol=1e-12, atol=1e-15 * np.abs(r1.grads[k]).max())
     assert np.all(r2.grads["dq_t"][1] == 0) and np.all(r2.grads["dt"][1] == 0)
-    np.testing.assert_array_equal(r2.grads["dq_t"][0], r1.grads["dq_t"][0])
+    np.testing.assert_allclose(r2.grads["dq_t"][0], r1.grads["dq_t"][0], rtol=1e-12)
