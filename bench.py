@@ -169,29 +169,22 @@ def main():
         plain = dict(value=V * 1000.0 / ms_plain, ms_per_step=ms_plain)
         print(f"[bench] plain {ms_plain:.3f} ms/step", file=sys.stderr, flush=True)
 
-    # batched, replayed from a captured HIP graph
+    # batched, replayed from a HIP graph captured by the library (gsr_graph_capture)
     graph = None
     if not args.no_graph:
-        try:
-            s = torch.cuda.Stream()
-            s.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(s):
-                batched_step()
-            torch.cuda.current_stream().wait_stream(s)
-            torch.cuda.synchronize()
-            gr = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(gr):
-                batched_step()
-            torch.cuda.synchronize()
-            ms_graph = timed(gr.replay, args.steps, args.warmup)
-            ref = out["g_means"].clone()
-            batched_step()
-            torch.cuda.synchronize()
-            dev_max = ((ref.double() - out["g_means"].double()).abs().max() / ref.double().abs().max()).item()
-            graph = dict(value=V * 1000.0 / ms_graph, ms_per_step=ms_graph, rel_diff_vs_eager=dev_max)
-            print(f"[bench] graph {ms_graph:.3f} ms/step", file=sys.stderr, flush=True)
-        except Exception as e:   # reported, not hidden
-            graph = dict(error=str(e)[:200])
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            gid, gout = rast.capture_graph(g, q, t, cams, targets, opts)
+            ms_graph = timed(lambda: rast.launch_graph(gid), args.steps, args.warmup)
+            s.synchronize()
+            _, _, ovf3 = rast.read_counters(rast.shared_workspace())
+            assert not ovf3
+            same = all(torch.equal(gout[k], out[k]) for k in ("rgb", "loss", "g_means", "dq_t"))
+            rast.destroy_graph(gid)
+        torch.cuda.synchronize()
+        graph = dict(value=V * 1000.0 / ms_graph, ms_per_step=ms_graph, bitwise_equal_to_eager=bool(same))
+        print(f"[bench] graph {ms_graph:.3f} ms/step", file=sys.stderr, flush=True)
 
     # counted work of one batched step (a separate, untimed call)
     o_cnt = raster.RenderOptions(**{**opts.__dict__, "count_work": True})

@@ -132,7 +132,8 @@ typedef struct {
     float z_near;                          /* near-plane cull (camera-frame z, metres) */
     float blur2d;                          /* added to the 2D covariance diagonal (px^2), >= 0 */
     float sil_mask_thresh;                 /* < 0: off; else photometric/depth terms need S > thresh */
-    int32_t tile_w, tile_h;                /* binning tile in pixels: each 8 or 16 */
+    int32_t tile_w, tile_h;                /* binning tile in pixels: each 8 or 16; 0 and 0 = the tile
+                                              gsr_autotune() chose for this input shape, else 16x16 */
     uint32_t flags;                        /* GSR_* flags */
 } gsr_options;
 
@@ -206,6 +207,39 @@ gsr_status gsr_render_loss_grad(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_
                                 const gsr_options *opts, const gsr_targets *targets, gsr_workspace ws,
                                 gsr_images out, double *loss, gsr_gaussian_grads *gg, gsr_pose_grads *pg,
                                 void *stream);
+
+/* Tile autotuner.  Runs the fused call of gsr_render_loss_grad() (same
+ * arguments; opts' tile is ignored) with every supported tile size (16x16,
+ * 16x8, 8x16, 8x8) that fits ws, checks each once against the pair capacity
+ * (a synchronisation), times `reps` calls of each with HIP events, and keeps
+ * the fastest for this input shape (the views' resolutions, N rounded up to a
+ * power of two, the flags); later calls with tile 0x0 use it.  Writes the
+ * choice to best_tile[2] (host) and its time per call to *ms_per_call (host).
+ * Outputs hold the last candidate's results (every tile gives the same
+ * images).  GSR_ECAPACITY if no candidate fits the workspace. */
+gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views, const gsr_options *opts,
+                        const gsr_targets *targets, gsr_workspace ws, gsr_images out, double *loss,
+                        gsr_gaussian_grads *gg, gsr_pose_grads *pg, int32_t reps, int32_t *best_tile,
+                        double *ms_per_call, void *stream);
+
+/* Sets the tile used for an input shape (as gsr_autotune() would), e.g. from
+ * a cache of earlier tuning runs.  n, views (cameras only) and flags form the
+ * shape key. */
+gsr_status gsr_set_tile(gsr_ctx *ctx, int64_t n, const gsr_views *views, uint32_t flags, int32_t tile_w,
+                        int32_t tile_h);
+
+/* HIP graph capture of one gsr_render_loss_grad() call (same arguments) on
+ * `stream` (not the null stream).  Every pointer is baked into the graph:
+ * inputs, outputs and the workspace must stay allocated and in place for as
+ * long as the graph is launched; their contents may change between launches.
+ * The pair capacity is checked only on the device: after launches, use
+ * gsr_read_counters() to detect an overflow (then re-plan and re-capture).
+ * Returns an id for gsr_graph_launch() / gsr_graph_destroy(). */
+gsr_status gsr_graph_capture(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views, const gsr_options *opts,
+                             const gsr_targets *targets, gsr_workspace ws, gsr_images out, double *loss,
+                             gsr_gaussian_grads *gg, gsr_pose_grads *pg, void *stream, int32_t *graph_id);
+gsr_status gsr_graph_launch(gsr_ctx *ctx, int32_t graph_id, void *stream);
+gsr_status gsr_graph_destroy(gsr_ctx *ctx, int32_t graph_id);
 
 /* Synchronises `stream` and reads the counters of the last call on ws:
  * visible (view, Gaussian) records, (Gaussian, tile) pairs needed, and

@@ -59,7 +59,8 @@ class Workspace(C.Structure):
 
 EXPORTS = ["gsr_create", "gsr_destroy", "gsr_last_error", "gsr_workspace_size", "gsr_forward", "gsr_backward",
            "gsr_render_loss_grad", "gsr_read_counters", "gsr_read_work", "gsr_set_timing", "gsr_read_timing",
-           "gsr_debug_binning", "gsr_debug_pixel_state", "gsr_selftest"]
+           "gsr_debug_binning", "gsr_debug_pixel_state", "gsr_selftest", "gsr_autotune", "gsr_set_tile",
+           "gsr_graph_capture", "gsr_graph_launch", "gsr_graph_destroy"]
 
 _lib = None
 
@@ -103,6 +104,18 @@ def load() -> C.CDLL:
     lib.gsr_debug_binning.restype = st
     lib.gsr_debug_pixel_state.argtypes = [_vp, P(Gaussians), P(Views), P(Options), Workspace, _vp, _vp, _vp, _vp]
     lib.gsr_debug_pixel_state.restype = st
+    lib.gsr_autotune.argtypes = [_vp, P(Gaussians), P(Views), P(Options), P(Targets), Workspace, Images, _vp,
+                                 P(GaussGrads), P(PoseGrads), C.c_int32, P(C.c_int32), P(C.c_double), _vp]
+    lib.gsr_autotune.restype = st
+    lib.gsr_set_tile.argtypes = [_vp, C.c_int64, P(Views), C.c_uint32, C.c_int32, C.c_int32]
+    lib.gsr_set_tile.restype = st
+    lib.gsr_graph_capture.argtypes = [_vp, P(Gaussians), P(Views), P(Options), P(Targets), Workspace, Images, _vp,
+                                      P(GaussGrads), P(PoseGrads), _vp, P(C.c_int32)]
+    lib.gsr_graph_capture.restype = st
+    lib.gsr_graph_launch.argtypes = [_vp, C.c_int32, _vp]
+    lib.gsr_graph_launch.restype = st
+    lib.gsr_graph_destroy.argtypes = [_vp, C.c_int32]
+    lib.gsr_graph_destroy.restype = st
     lib.gsr_selftest.argtypes = [_vp, _vp, _vp]
     lib.gsr_selftest.restype = st
     _lib = lib

@@ -23,6 +23,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -41,6 +42,10 @@ struct gsr_ctx {
     int num_cus;
     std::string err;
     bool timing = false;
+    bool capturing = false;                            // no event timing inside a graph capture
+    std::map<std::string, std::pair<int, int>> tuned;  // autotuned tile per input shape
+    std::map<int32_t, hipGraphExec_t> graphs;          // captured call sequences
+    int32_t next_graph = 1;
     struct Rec {
         int stage;
         hipEvent_t a, b;
@@ -66,7 +71,7 @@ struct StageTimer {
     hipStream_t st;
     hipEvent_t a = nullptr, b = nullptr;
     StageTimer(gsr_ctx *c, int s, hipStream_t stream) : ctx(c), stage(s), st(stream) {
-        if (ctx->timing && ctx->recs.size() < 65536) {
+        if (ctx->timing && !ctx->capturing && ctx->recs.size() < 65536) {
             a = ctx->take_event();
             b = ctx->take_event();
             if (a && b) (void)hipEventRecord(a, st);
@@ -123,6 +128,35 @@ gsr_status fail(gsr_ctx *ctx, gsr_status st, const char *fmt, ...) {
 gsr_status check_hip(gsr_ctx *ctx, hipError_t e, const char *what) {
     if (e == hipSuccess) return GSR_OK;
     return fail(ctx, GSR_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Key of an input shape for the autotuner: views' resolutions, the size class
+// of N (power of two) and the flags that change the work.
+std::string shape_key(int64_t n, const gsr_views *views, uint32_t flags) {
+    std::string k = std::to_string(views->n_views) + ":";
+    for (int v = 0; v < views->n_views; ++v)
+        k += std::to_string(views->cams[v].width) + "x" + std::to_string(views->cams[v].height) + ",";
+    int b = 0;
+    while ((int64_t(1) << b) < n) ++b;
+    k += "n2^" + std::to_string(b) + ":f" + std::to_string(flags & (GSR_ISOTROPIC | GSR_NO_GAUSS_GRADS | GSR_NO_POSE_GRADS));
+    return k;
+}
+
+// opts with a zero tile replaced by the autotuned one (or 16x16).
+gsr_options resolve_tile(const gsr_ctx *ctx, int64_t n, const gsr_views *views, const gsr_options *opts) {
+    gsr_options o = *opts;
+    if (o.tile_w == 0 && o.tile_h == 0 && views && views->cams && views->n_views >= 1 &&
+        views->n_views <= GSR_MAX_VIEWS) {
+        o.tile_w = o.tile_h = 16;
+        if (ctx) {
+            auto it = ctx->tuned.find(shape_key(n, views, opts->flags));
+            if (it != ctx->tuned.end()) {
+                o.tile_w = it->second.first;
+                o.tile_h = it->second.second;
+            }
+        }
+    }
+    return o;
 }
 
 gsr_status validate_views(gsr_ctx *ctx, const gsr_views *views, const gsr_options *opts) {
@@ -856,6 +890,37 @@ gsr_status finish(Call &c, const char *what) {
     return check_hip(c.ctx, hipGetLastError(), what);
 }
 
+gsr_status render_loss_grad_impl(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views,
+                                 const gsr_options *opts, const gsr_targets *targets, gsr_workspace ws,
+                                 gsr_images out, double *loss, gsr_gaussian_grads *gg, gsr_pose_grads *pg,
+                                 void *stream) {
+    Call c;
+    gsr_status s = prepare(ctx, g, views, opts, ws, stream, c);
+    if (s != GSR_OK) return s;
+    if (!out.rgb || !out.depth || !out.sil) return fail(ctx, GSR_EINVAL, "output images must not be NULL");
+    if (!targets || !targets->rgb || !targets->depth) return fail(ctx, GSR_EINVAL, "targets rgb and depth are required");
+    if (!loss) return fail(ctx, GSR_EINVAL, "loss must not be NULL");
+    s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (s != GSR_OK) return s;
+    enqueue_binning(c, views);
+    enqueue_blend_fwd(c, out);
+    LossIn li;
+    memset(&li, 0, sizeof(li));
+    li.t_rgb = targets->rgb;
+    li.t_depth = targets->depth;
+    li.t_sil = targets->sil;
+    li.t_prior = targets->prior;
+    li.t_weight = targets->weight;
+    li.w_rgb = opts->w_rgb;
+    li.w_depth = opts->w_depth;
+    li.w_sil = opts->w_sil;
+    li.w_prior = opts->w_prior;
+    li.sil_thresh = opts->sil_mask_thresh;
+    li.loss = loss;
+    enqueue_backward(c, views, opts, out, li, true, gg, pg);
+    return finish(c, "gsr_render_loss_grad launch");
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -899,6 +964,7 @@ void gsr_destroy(gsr_ctx *ctx) {
         (void)hipEventDestroy(r.b);
     }
     for (auto e : ctx->pool) (void)hipEventDestroy(e);
+    for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
     delete ctx;
 }
 
@@ -908,6 +974,11 @@ gsr_status gsr_workspace_size(gsr_ctx *ctx, int64_t n, const gsr_views *views, c
                               int64_t pair_capacity, size_t *bytes) {
     // needs no device: with ctx == NULL errors go to the text gsr_last_error(NULL) returns
     if (!bytes) return fail(ctx, GSR_EINVAL, "bytes must not be NULL");
+    gsr_options o_res;
+    if (opts && views) {
+        o_res = resolve_tile(ctx, n, views, opts);
+        opts = &o_res;
+    }
     gsr_status s = validate_views(ctx, views, opts);
     if (s != GSR_OK) return s;
     if (n < 0) return fail(ctx, GSR_EINVAL, "n must be >= 0");
@@ -923,6 +994,11 @@ gsr_status gsr_workspace_size(gsr_ctx *ctx, int64_t n, const gsr_views *views, c
 
 gsr_status gsr_forward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views, const gsr_options *opts,
                        gsr_workspace ws, gsr_images out, void *stream) {
+    gsr_options o_res;
+    if (opts && views && g) {
+        o_res = resolve_tile(ctx, g->n, views, opts);
+        opts = &o_res;
+    }
     Call c;
     gsr_status s = prepare(ctx, g, views, opts, ws, stream, c);
     if (s != GSR_OK) return s;
@@ -939,6 +1015,11 @@ gsr_status gsr_forward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *vi
 gsr_status gsr_backward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views, const gsr_options *opts,
                         gsr_workspace ws, gsr_images out, const float *g_rgb, const float *g_depth,
                         const float *g_sil, gsr_gaussian_grads *gg, gsr_pose_grads *pg, void *stream) {
+    gsr_options o_res;
+    if (opts && views && g) {
+        o_res = resolve_tile(ctx, g->n, views, opts);
+        opts = &o_res;
+    }
     Call c;
     gsr_status s = prepare(ctx, g, views, opts, ws, stream, c);
     if (s != GSR_OK) return s;
@@ -957,31 +1038,138 @@ gsr_status gsr_render_loss_grad(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_
                                 const gsr_options *opts, const gsr_targets *targets, gsr_workspace ws,
                                 gsr_images out, double *loss, gsr_gaussian_grads *gg, gsr_pose_grads *pg,
                                 void *stream) {
+    gsr_options o_res;
+    if (opts && views && g) {
+        o_res = resolve_tile(ctx, g->n, views, opts);
+        opts = &o_res;
+    }
+    return render_loss_grad_impl(ctx, g, views, opts, targets, ws, out, loss, gg, pg, stream);
+}
+
+// Tile autotuner: every candidate is run once (checked against the pair
+// capacity, one synchronisation), then timed over `reps` calls with HIP
+// events; the fastest is kept for this input shape.
+gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views, const gsr_options *opts,
+                        const gsr_targets *targets, gsr_workspace ws, gsr_images out, double *loss,
+                        gsr_gaussian_grads *gg, gsr_pose_grads *pg, int32_t reps, int32_t *best_tile,
+                        double *ms_per_call, void *stream) {
+    if (!ctx) return GSR_EINVAL;
+    if (!g || !views || !opts || !best_tile || !ms_per_call) return fail(ctx, GSR_EINVAL, "autotune: NULL argument");
+    if (reps < 1) return fail(ctx, GSR_EINVAL, "autotune: reps must be >= 1");
+    static const int cand[4][2] = {{16, 16}, {16, 8}, {8, 16}, {8, 8}};
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t a = nullptr, b = nullptr;
+    gsr_status s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (s == GSR_OK) s = check_hip(ctx, hipEventCreate(&a), "hipEventCreate");
+    if (s == GSR_OK) s = check_hip(ctx, hipEventCreate(&b), "hipEventCreate");
+    double best = -1.0;
+    int bw = 0, bh = 0;
+    for (int k = 0; k < 4 && s == GSR_OK; ++k) {
+        gsr_options o = *opts;
+        o.tile_w = cand[k][0];
+        o.tile_h = cand[k][1];
+        size_t need = 0;
+        if (gsr_workspace_size(ctx, g->n, views, &o, ws.pair_capacity, &need) != GSR_OK || need > ws.bytes) continue;
+        s = render_loss_grad_impl(ctx, g, views, &o, targets, ws, out, loss, gg, pg, stream);
+        if (s != GSR_OK) break;
+        int64_t m = 0, kk = 0;
+        int32_t ovf = 0;
+        s = gsr_read_counters(ctx, ws, stream, &m, &kk, &ovf);
+        if (s != GSR_OK) break;
+        if (ovf) continue;   // this tile needs more pairs than the workspace holds
+        (void)hipEventRecord(a, st);
+        for (int r = 0; r < reps && s == GSR_OK; ++r)
+            s = render_loss_grad_impl(ctx, g, views, &o, targets, ws, out, loss, gg, pg, stream);
+        (void)hipEventRecord(b, st);
+        if (s != GSR_OK) break;
+        s = check_hip(ctx, hipEventSynchronize(b), "hipEventSynchronize");
+        float ms = 0.0f;
+        if (s == GSR_OK) s = check_hip(ctx, hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+        const double per = (double)ms / reps;
+        if (s == GSR_OK && (best < 0.0 || per < best)) {
+            best = per;
+            bw = o.tile_w;
+            bh = o.tile_h;
+        }
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (s != GSR_OK) return s;
+    if (best < 0.0) return fail(ctx, GSR_ECAPACITY, "autotune: no tile size fits the workspace's pair capacity");
+    ctx->tuned[shape_key(g->n, views, opts->flags)] = {bw, bh};
+    best_tile[0] = bw;
+    best_tile[1] = bh;
+    *ms_per_call = best;
+    return GSR_OK;
+}
+
+gsr_status gsr_set_tile(gsr_ctx *ctx, int64_t n, const gsr_views *views, uint32_t flags, int32_t tile_w,
+                        int32_t tile_h) {
+    if (!ctx) return GSR_EINVAL;
+    if (!views || !views->cams || views->n_views < 1 || views->n_views > GSR_MAX_VIEWS)
+        return fail(ctx, GSR_EINVAL, "set_tile: invalid views");
+    if ((tile_w != 8 && tile_w != 16) || (tile_h != 8 && tile_h != 16))
+        return fail(ctx, GSR_EINVAL, "set_tile: each side must be 8 or 16");
+    ctx->tuned[shape_key(n, views, flags)] = {tile_w, tile_h};
+    return GSR_OK;
+}
+
+// Graph capture of one fused call (forward, loss, backward): the sequence
+// has no host synchronisation and no memset nodes, so it replays as is.
+gsr_status gsr_graph_capture(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views, const gsr_options *opts,
+                             const gsr_targets *targets, gsr_workspace ws, gsr_images out, double *loss,
+                             gsr_gaussian_grads *gg, gsr_pose_grads *pg, void *stream, int32_t *graph_id) {
+    if (!ctx) return GSR_EINVAL;
+    if (!graph_id) return fail(ctx, GSR_EINVAL, "graph_id must not be NULL");
+    if (!stream) return fail(ctx, GSR_EINVAL, "graph capture needs a stream other than the null stream");
+    gsr_options o_res;
+    if (opts && views && g) {
+        o_res = resolve_tile(ctx, g->n, views, opts);
+        opts = &o_res;
+    }
+    // validate everything before the capture starts
     Call c;
     gsr_status s = prepare(ctx, g, views, opts, ws, stream, c);
     if (s != GSR_OK) return s;
-    if (!out.rgb || !out.depth || !out.sil) return fail(ctx, GSR_EINVAL, "output images must not be NULL");
-    if (!targets || !targets->rgb || !targets->depth) return fail(ctx, GSR_EINVAL, "targets rgb and depth are required");
-    if (!loss) return fail(ctx, GSR_EINVAL, "loss must not be NULL");
+    hipStream_t st = (hipStream_t)stream;
     s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     if (s != GSR_OK) return s;
-    enqueue_binning(c, views);
-    enqueue_blend_fwd(c, out);
-    LossIn li;
-    memset(&li, 0, sizeof(li));
-    li.t_rgb = targets->rgb;
-    li.t_depth = targets->depth;
-    li.t_sil = targets->sil;
-    li.t_prior = targets->prior;
-    li.t_weight = targets->weight;
-    li.w_rgb = opts->w_rgb;
-    li.w_depth = opts->w_depth;
-    li.w_sil = opts->w_sil;
-    li.w_prior = opts->w_prior;
-    li.sil_thresh = opts->sil_mask_thresh;
-    li.loss = loss;
-    enqueue_backward(c, views, opts, out, li, true, gg, pg);
-    return finish(c, "gsr_render_loss_grad launch");
+    s = check_hip(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    if (s != GSR_OK) return s;
+    ctx->capturing = true;
+    const gsr_status s_call = render_loss_grad_impl(ctx, g, views, opts, targets, ws, out, loss, gg, pg, stream);
+    ctx->capturing = false;
+    hipGraph_t graph = nullptr;
+    s = check_hip(ctx, hipStreamEndCapture(st, &graph), "hipStreamEndCapture");
+    if (s_call != GSR_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s_call;
+    }
+    if (s != GSR_OK) return s;
+    hipGraphExec_t exec = nullptr;
+    s = check_hip(ctx, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    (void)hipGraphDestroy(graph);
+    if (s != GSR_OK) return s;
+    const int32_t id = ctx->next_graph++;
+    ctx->graphs[id] = exec;
+    *graph_id = id;
+    return GSR_OK;
+}
+
+gsr_status gsr_graph_launch(gsr_ctx *ctx, int32_t graph_id, void *stream) {
+    if (!ctx) return GSR_EINVAL;
+    auto it = ctx->graphs.find(graph_id);
+    if (it == ctx->graphs.end()) return fail(ctx, GSR_EINVAL, "unknown graph id %d", graph_id);
+    return check_hip(ctx, hipGraphLaunch(it->second, (hipStream_t)stream), "hipGraphLaunch");
+}
+
+gsr_status gsr_graph_destroy(gsr_ctx *ctx, int32_t graph_id) {
+    if (!ctx) return GSR_EINVAL;
+    auto it = ctx->graphs.find(graph_id);
+    if (it == ctx->graphs.end()) return fail(ctx, GSR_EINVAL, "unknown graph id %d", graph_id);
+    const gsr_status s = check_hip(ctx, hipGraphExecDestroy(it->second), "hipGraphExecDestroy");
+    ctx->graphs.erase(it);
+    return s;
 }
 
 gsr_status gsr_read_counters(gsr_ctx *ctx, gsr_workspace ws, void *stream, int64_t *n_visible, int64_t *n_pairs,
@@ -1051,6 +1239,11 @@ gsr_status gsr_debug_binning(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_vie
                              gsr_workspace ws, int64_t max_rec, int64_t max_tiles, int64_t max_pairs,
                              uint32_t *rec_gid, float *rec_xy, float *rec_radius, float *rec_z, uint32_t *ranges,
                              uint32_t *pair_rec, void *stream) {
+    gsr_options o_res;
+    if (opts && views && g) {
+        o_res = resolve_tile(ctx, g->n, views, opts);
+        opts = &o_res;
+    }
     Call c;
     gsr_status s = prepare(ctx, g, views, opts, ws, stream, c);
     if (s != GSR_OK) return s;
@@ -1073,6 +1266,11 @@ gsr_status gsr_debug_binning(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_vie
 gsr_status gsr_debug_pixel_state(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views,
                                  const gsr_options *opts, gsr_workspace ws, float *t_final, uint32_t *n_last,
                                  uint32_t *hash, void *stream) {
+    gsr_options o_res;
+    if (opts && views && g) {
+        o_res = resolve_tile(ctx, g->n, views, opts);
+        opts = &o_res;
+    }
     Call c;
     gsr_status s = prepare(ctx, g, views, opts, ws, stream, c);
     if (s != GSR_OK) return s;

@@ -193,6 +193,82 @@ class Rasterizer:
         self.pair_capacity = max(int(needed * 1.25) + 1024, self.pair_capacity)
 
     # ------------------------------------------------------------------ calls
+    def _fused_args(self, g: GaussianParams, quat, trans, cams, targets: dict, opts: RenderOptions, out: dict):
+        views, keep = self._views(cams, quat, trans)
+        gs = self._gauss(g)
+        o = self._opts(opts, g.isotropic)
+        P = total_pixels(cams)
+        for k in ("rgb", "depth", "sil", "prior", "weight"):
+            t = targets.get(k)
+            if t is not None:
+                _check_f32(f"target {k}", t, (3 * P,) if k == "rgb" else (P,), self.device)
+        tg = _abi.Targets(_ptr(targets["rgb"]), _ptr(targets["depth"]), _ptr(targets.get("sil")),
+                          _ptr(targets.get("prior")), _ptr(targets.get("weight")))
+        imgs = _abi.Images(_ptr(out["rgb"]), _ptr(out["depth"]), _ptr(out["sil"]))
+        gg = _abi.GaussGrads(*[_ptr(out.get(k)) for k in ("g_means", "g_quats", "g_log_scales", "g_opacity_logits",
+                                                            "g_rgb")])
+        pg = _abi.PoseGrads(*[_ptr(out.get(k)) for k in ("dq_t", "dt", "dq_c", "dc")])
+        return dict(views=views, keep=keep, gs=gs, o=o, tg=tg, imgs=imgs, gg=gg, pg=pg)
+
+    def autotune(self, g: GaussianParams, quat, trans, cams, targets: dict, opts: RenderOptions = RenderOptions(),
+                 reps: int = 5, out: Optional[dict] = None) -> Tuple[Tuple[int, int], float]:
+        """Time every tile size on these inputs and keep the fastest for this
+        shape (later calls with opts.tile == (0, 0) use it).  The workspace is
+        first sized for the tile that needs the most pairs."""
+        V = len(cams)
+        P = total_pixels(cams)
+        if out is None:
+            out = self.alloc_outputs(g, V, P, opts)
+        for tile in ((8, 8), (8, 16), (16, 8), (16, 16)):
+            self.render_loss_grad(g, quat, trans, cams, targets, RenderOptions(**{**opts.__dict__, "tile": tile}),
+                                  check=True, out=out)
+        a = self._fused_args(g, quat, trans, cams, targets, opts, out)
+        ws = self._shared_ws(g.n, a["views"], self._opts(RenderOptions(**{**opts.__dict__, "tile": (8, 8)}),
+                                                          g.isotropic))
+        best = (C.c_int32 * 2)()
+        ms = C.c_double()
+        _abi.check(_ABI.gsr_autotune(self._ctx, C.byref(a["gs"]), C.byref(a["views"]), C.byref(a["o"]),
+                                     C.byref(a["tg"]), ws, a["imgs"], _ptr(out["loss"]), C.byref(a["gg"]),
+                                     C.byref(a["pg"]), int(reps), best, C.byref(ms), _stream_ptr()), self._ctx)
+        return (int(best[0]), int(best[1])), float(ms.value)
+
+    def set_tile(self, n: int, cams, tile: Tuple[int, int], isotropic=False, gauss_grads=True, pose_grads=True):
+        """Record a tile choice for a shape (e.g. loaded from a tuning cache)."""
+        V = len(cams)
+        arr = (_abi.Camera * V)(*[_abi.Camera(int(c.width), int(c.height), float(c.fx), float(c.fy), float(c.cx),
+                                              float(c.cy)) for c in cams])
+        views = _abi.Views(V, arr, None, None)
+        flags = (_abi.GSR_ISOTROPIC if isotropic else 0) | (0 if gauss_grads else _abi.GSR_NO_GAUSS_GRADS) | \
+            (0 if pose_grads else _abi.GSR_NO_POSE_GRADS)
+        _abi.check(_ABI.gsr_set_tile(self._ctx, n, C.byref(views), flags, int(tile[0]), int(tile[1])), self._ctx)
+
+    def capture_graph(self, g: GaussianParams, quat, trans, cams, targets: dict,
+                      opts: RenderOptions = RenderOptions(), out: Optional[dict] = None):
+        """Capture one fused call into a HIP graph; returns (graph id, out).
+        Every tensor passed (and the workspace) must stay alive and in place
+        while the graph is used."""
+        V = len(cams)
+        P = total_pixels(cams)
+        if out is None:
+            out = self.alloc_outputs(g, V, P, opts)
+        self.render_loss_grad(g, quat, trans, cams, targets, opts, check=True, out=out)   # size the capacity
+        a = self._fused_args(g, quat, trans, cams, targets, opts, out)
+        ws = self._shared_ws(g.n, a["views"], a["o"])
+        gid = C.c_int32()
+        _abi.check(_ABI.gsr_graph_capture(self._ctx, C.byref(a["gs"]), C.byref(a["views"]), C.byref(a["o"]),
+                                          C.byref(a["tg"]), ws, a["imgs"], _ptr(out["loss"]), C.byref(a["gg"]),
+                                          C.byref(a["pg"]), _stream_ptr(), C.byref(gid)), self._ctx)
+        self._graph_refs = getattr(self, "_graph_refs", {})
+        self._graph_refs[gid.value] = (a, out, self._ws)
+        return gid.value, out
+
+    def launch_graph(self, graph_id: int) -> None:
+        _abi.check(_ABI.gsr_graph_launch(self._ctx, int(graph_id), _stream_ptr()), self._ctx)
+
+    def destroy_graph(self, graph_id: int) -> None:
+        _abi.check(_ABI.gsr_graph_destroy(self._ctx, int(graph_id)), self._ctx)
+        getattr(self, "_graph_refs", {}).pop(graph_id, None)
+
     def render_loss_grad(self, g: GaussianParams, quat: torch.Tensor, trans: torch.Tensor, cams: Sequence,
                          targets: dict, opts: RenderOptions = RenderOptions(), check: bool = True,
                          out: Optional[dict] = None):

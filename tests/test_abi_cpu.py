@@ -63,11 +63,19 @@ def test_workspace_size_grows_with_inputs():
     assert st == _abi.GSR_OK and d > 0
 
 
-@pytest.mark.parametrize("tile", [(4, 16), (16, 12), (32, 16), (0, 0)])
+@pytest.mark.parametrize("tile", [(4, 16), (16, 12), (32, 16), (0, 8)])
 def test_rejects_bad_tiles(tile):
     v, keep = _views(1)
     st, _, msg = _size(1000, v, _opts(*tile), 1000)
     assert st == _abi.GSR_EINVAL and "tile" in msg
+
+
+def test_zero_tile_means_the_tuned_or_default_tile():
+    v, keep = _views(2)
+    st0, a, _ = _size(100_000, v, _opts(0, 0), 1 << 20)
+    st1, b, _ = _size(100_000, v, _opts(16, 16), 1 << 20)
+    st2, c, _ = _size(100_000, v, _opts(8, 8), 1 << 20)
+    assert st0 == st1 == st2 == _abi.GSR_OK and a == b and c > b
 
 
 def test_rejects_bad_views_and_options():

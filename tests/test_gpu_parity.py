@@ -289,3 +289,51 @@ def test_config3_two_keyframes_with_depth_prior(rast):
     P = w.views.cams[0].width * w.views.cams[0].height
     tg = oracle_targets(w, prior_noise=w.prior_noise[:2 * P])
     _fused_parity(rast, w, tg, "config3[2 views]")
+
+
+def test_autotune_and_tuned_calls(rast):
+    """The autotuner returns a supported tile and its time; a call with tile
+    (0, 0) then uses it and gives the same images and loss as that tile."""
+    from paper_2408_05635_amd import raster
+    w = scenes.config2(n_views=2, n=50000)
+    tg = to_dev(oracle_targets(w))
+    g = dev_params(w.gaussians)
+    q, t = dev_poses(w.views)
+    r2 = raster.Rasterizer(0)
+    opts = _opts(w)
+    tile, ms = r2.autotune(g, q, t, w.views.cams, tg, opts, reps=3)
+    print("autotuned tile", tile, f"{ms:.3f} ms per call")
+    assert tile in [(16, 16), (16, 8), (8, 16), (8, 8)] and ms > 0
+    auto = r2.render_loss_grad(g, q, t, w.views.cams, tg, _opts(w, (0, 0)))
+    auto = {k: v.clone() for k, v in auto.items()}
+    expl = r2.render_loss_grad(g, q, t, w.views.cams, tg, _opts(w, tile))
+    for k in ("rgb", "depth", "sil", "loss", "g_means", "dq_t"):
+        assert torch.equal(auto[k], expl[k]), k
+
+
+def test_native_graph_replay_matches_eager(rast):
+    """A captured fused call replays with the same results as the eager call,
+    several times, with eager work and synchronisations in between."""
+    from paper_2408_05635_amd import raster
+    w = scenes.config2(n_views=3, n=30000)
+    tg = to_dev(oracle_targets(w))
+    g = dev_params(w.gaussians)
+    q, t = dev_poses(w.views)
+    r3 = raster.Rasterizer(0)
+    opts = _opts(w)
+    eager = r3.render_loss_grad(g, q, t, w.views.cams, tg, opts)
+    eager = {k: v.clone() for k, v in eager.items()}
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        gid, gout = r3.capture_graph(g, q, t, w.views.cams, tg, opts)
+        for rep in range(3):
+            for v in gout.values():
+                v.fill_(-1.0)   # the replay must overwrite every output
+            r3.launch_graph(gid)
+            s.synchronize()
+            for k in eager:
+                assert torch.equal(gout[k], eager[k]), (rep, k)
+            torch.ones(1000, device="cuda").sum().item()   # unrelated eager work between replays
+        r3.destroy_graph(gid)
+    torch.cuda.synchronize()
