@@ -91,6 +91,12 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kRecGrad = 14;   // per-record parameter gradient: mu 3, q 4, log_s 3, logit 1, rgb 3
+// synchronisation region, cleared by every call: scan tickets (256 B), the
+// scans' look-back words, the sort passes' arrival counters and tagged words
+constexpr size_t kSyncTickets = 256;
+constexpr int kSortPasses = 8;   // 4 passes of the depth sort, at most 4 of the tile sort
+// ids of the binning's scans
+enum SyncId : uint32_t { kIdVisible = 0, kIdOffsets = 1, kIdOwner = 2 };
 
 struct Layout {
     int64_t vn;           // V * N
@@ -100,7 +106,11 @@ struct Layout {
     int32_t G;            // total blend blocks
     int tile_bits;        // key bits of the tile sort
     size_t views, poses, counters, cnt, zkey, dk0, dv0, dk1, dv1, inv, rec, trect, cnt_s, poff, pk0, pv0, pk1, pv1,
-        owner, prec, ranges, tfinal, nlast, phash, gpairs, rgrad, rpose, losst, posepart, part, hist;
+        owner, prec, ranges, tfinal, nlast, phash, gpairs, rgrad, rpose, losst, posepart, sgbase, sync;
+    int64_t sort_groups;  // groups of sort blocks at the capacity
+    // offsets in the sync region (cleared by every call): scan look-back
+    // words, sort arrival counters, sort block words, sort group words
+    size_t sync_status, sync_done, sync_words, sync_gwords, sync_bytes;
     size_t total;
 };
 
@@ -262,10 +272,15 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     L.rpose = take(8 * 12 * vn);
     L.losst = take(sizeof(double) * (size_t)L.T);
     L.posepart = take(sizeof(double) * 12 * V);
-    const int64_t nb_sort = (std::max<int64_t>(L.vn, kcap) + kChunk - 1) / kChunk;
-    const int64_t scan_n = std::max<int64_t>(std::max<int64_t>(L.vn, kcap), 256 * nb_sort);
-    L.part = take(4 * (size_t)((scan_n + kChunk - 1) / kChunk + 1));
-    L.hist = take(4 * (size_t)(256 * nb_sort + 1));
+    const int64_t nb = std::max<int64_t>((std::max<int64_t>(L.vn, kcap) + kChunk - 1) / kChunk, 1);
+    L.sort_groups = (nb + kSortGroup - 1) / kSortGroup;
+    L.sgbase = take(4 * 256 * (size_t)L.sort_groups);
+    L.sync_status = kSyncTickets;
+    L.sync_done = align_up(L.sync_status + 8 * (size_t)nb);
+    L.sync_words = align_up(L.sync_done + 4 * (size_t)kSortPasses * (size_t)(L.sort_groups + 1));
+    L.sync_gwords = align_up(L.sync_words + 8 * 256 * (size_t)nb);
+    L.sync_bytes = align_up(L.sync_gwords + 8 * 256 * (size_t)L.sort_groups);
+    L.sync = take(L.sync_bytes);
     L.total = off;
     return L;
 }
@@ -279,8 +294,13 @@ T *at(const gsr_workspace &ws, size_t off) {
 // kernels
 // ---------------------------------------------------------------------------
 
+// Call setup: view table, FP64 poses, zero counters (block 0), and a cleared
+// synchronisation region (all blocks).
 __global__ void k_setup(ViewTable tab, ViewTable *vt, const float *__restrict__ pq, const float *__restrict__ pt,
-                        PoseF64 *poses, int64_t *counters) {
+                        PoseF64 *poses, int64_t *counters, uint4 *sync, int64_t sync16) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < sync16; k += (int64_t)gridDim.x * blockDim.x)
+        sync[k] = make_uint4(0u, 0u, 0u, 0u);
+    if (blockIdx.x != 0) return;
     const int t = threadIdx.x;
     const int words = (int)(sizeof(ViewTable) / 4);
     const int32_t *src = reinterpret_cast<const int32_t *>(&tab);
@@ -755,17 +775,25 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     uint32_t *cnt = at<uint32_t>(ws, L.cnt), *zkey = at<uint32_t>(ws, L.zkey);
     uint32_t *dk0 = at<uint32_t>(ws, L.dk0), *dv0 = at<uint32_t>(ws, L.dv0);
     uint32_t *dk1 = at<uint32_t>(ws, L.dk1), *dv1 = at<uint32_t>(ws, L.dv1);
-    uint32_t *part = at<uint32_t>(ws, L.part), *hist = at<uint32_t>(ws, L.hist);
-    hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, st, c.tab, vt, views->quat, views->trans, poses, counters);
+    char *sync = at<char>(ws, L.sync);
+    SyncState ss{reinterpret_cast<uint32_t *>(sync), reinterpret_cast<uint64_t *>(sync + L.sync_status),
+                 counters + kCntSyncError};
+    SortState so{reinterpret_cast<uint64_t *>(sync + L.sync_words), reinterpret_cast<uint64_t *>(sync + L.sync_gwords),
+                 at<uint32_t>(ws, L.sgbase), reinterpret_cast<uint32_t *>(sync + L.sync_done), L.sort_groups,
+                 counters + kCntSyncError};
+    const int64_t sync16 = (int64_t)(L.sync_bytes / 16);
+    hipLaunchKernelGGL(k_setup, dim3((unsigned)std::min<int64_t>(std::max<int64_t>((sync16 + 255) / 256, 1), 1024)),
+                       dim3(256), 0, st, c.tab, vt, views->quat, views->trans, poses, counters,
+                       reinterpret_cast<uint4 *>(sync), sync16);
     if (L.vn > 0) {
         hipLaunchKernelGGL(k_project_count, dim3(grid_for(c.pp.n, 256, 1ll << 30)), dim3(256), 0, st, c.pp, vt,
                            poses, cnt, zkey);
     }
     // compaction of the visible (view, Gaussian) records, index order kept
-    scan_exclusive(VisSrc{cnt}, VisSink{zkey, dk0, dv0}, nullptr, L.vn, part, counters + kCntVisible, st);
+    scan_exclusive(VisSrc{cnt}, VisSink{zkey, dk0, dv0}, nullptr, L.vn, ss, kIdVisible, counters + kCntVisible, st);
     // depth order: stable sort on the float32 depth bits (positive floats sort as integers)
-    const bool d_in1 = radix_sort(dk0, dv0, dk1, dv1, counters + kCntVisible, L.vn, 32, hist, part,
-                                  counters + kCntScratch, st);
+    const bool d_in1 =
+        radix_sort(dk0, dv0, dk1, dv1, counters + kCntVisible, L.vn, 32, so, 0, st);
     const uint32_t *gid_sorted = d_in1 ? dv1 : dv0;
     float4 *rec = at<float4>(ws, L.rec);
     uint2 *trect = at<uint2>(ws, L.trect);
@@ -776,19 +804,19 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     uint32_t *pk0 = at<uint32_t>(ws, L.pk0), *pv0 = at<uint32_t>(ws, L.pv0);
     uint32_t *pk1 = at<uint32_t>(ws, L.pk1), *pv1 = at<uint32_t>(ws, L.pv1);
     uint32_t *poff = at<uint32_t>(ws, L.poff), *owner = at<uint32_t>(ws, L.owner);
-    scan_exclusive(CntSrc{cnt_s}, OffSink{poff}, counters + kCntVisible, L.vn, part, counters + kCntPairs, st);
+    scan_exclusive(CntSrc{cnt_s}, OffSink{poff}, counters + kCntVisible, L.vn, ss, kIdOffsets, counters + kCntPairs,
+                   st);
     hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(1), 0, st, counters, L.kcap);
     if (L.vn > 0 && L.kcap > 0) {
         hipLaunchKernelGGL(k_fill_u32_dev, dim3(grid_for(L.kcap, 256, 8192)), dim3(256), 0, st, owner,
                            (const int64_t *)(counters + kCntPairsUsed), 0u);
         hipLaunchKernelGGL(k_mark_heads, dim3(grid_for(L.vn, 256, 8192)), dim3(256), 0, st, counters, poff, owner);
-        scan_exclusive(OwnSrc{owner}, OwnSink{owner}, counters + kCntPairsUsed, L.kcap, part,
+        scan_exclusive(OwnSrc{owner}, OwnSink{owner}, counters + kCntPairsUsed, L.kcap, ss, kIdOwner,
                        counters + kCntScratch, st);
         hipLaunchKernelGGL(k_emit, dim3(grid_for(L.kcap, 256, 16384)), dim3(256), 0, st, counters, poff, trect,
                            gid_sorted, vt, c.pp.n, owner, pk0, pv0);
     }
-    const bool p_in1 = radix_sort(pk0, pv0, pk1, pv1, counters + kCntPairsUsed, L.kcap, L.tile_bits, hist, part,
-                                  counters + kCntScratch, st);
+    const bool p_in1 = radix_sort(pk0, pv0, pk1, pv1, counters + kCntPairsUsed, L.kcap, L.tile_bits, so, 4, st);
     uint2 *ranges = at<uint2>(ws, L.ranges);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(2 * L.T, 256)), dim3(256), 0, st, (uint32_t *)ranges, 2 * L.T, 0u);
     if (L.kcap > 0) {
@@ -1188,6 +1216,9 @@ gsr_status gsr_read_counters(gsr_ctx *ctx, gsr_workspace ws, void *stream, int64
     if (n_visible) *n_visible = h[kCntVisible];
     if (n_pairs) *n_pairs = h[kCntPairs];
     if (overflow) *overflow = (int32_t)h[kCntOverflow];
+    if (h[kCntSyncError] != 0)
+        return fail(ctx, GSR_EHIP, "%lld waits between blocks of the binning gave up; outputs are undefined",
+                    (long long)h[kCntSyncError]);
     return GSR_OK;
 }
 

@@ -1,7 +1,22 @@
 // Exclusive scan and stable LSD radix sort for the binning step, written for
-// wave64.  Element counts may live in device memory, so a whole call can be
-// enqueued (or captured in a graph) without a host synchronisation: grids are
-// sized for a host-side capacity and blocks past the device count exit.
+// wave64 and for few launches.
+//
+// The scan is single-pass with decoupled look-back: each block takes a ticket
+// (tickets follow the order in which blocks start, so a block only ever
+// waits for blocks that are already running), publishes its aggregate, then
+// walks back over its predecessors' published values until it meets an
+// inclusive prefix, and publishes its own.  A status word is 64 bits: the
+// high half holds (id << 2 | flag), the low half the value.  The status
+// words and tickets are cleared at the start of every call and every scan
+// of a call has its own id, so a word left by an earlier scan never passes
+// for a current one.  A waiting loop gives up after kSpinLimit polls and
+// raises an error counter: every wave terminates, whatever happens.  The
+// radix sort needs no waiting (see below).
+//
+// Element counts may live in device memory: grids are sized for a host-side
+// capacity and blocks whose ticket lies past the device count exit at once,
+// so a whole call can be enqueued (or captured in a graph) without a host
+// synchronisation.
 #pragma once
 
 #include "gsr_common.hpp"
@@ -11,9 +26,102 @@ namespace gsr {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kChunk = kScanThreads * kScanItems;   // 4096 items per block
+constexpr uint32_t kFlagAgg = 1u, kFlagPrefix = 2u;
+constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr int kMaxSyncIds = 32;
+
+// Synchronisation state of one call (cleared by the call's first kernel).
+struct SyncState {
+    uint32_t *tickets;   // [kMaxSyncIds] block tickets, one per scan
+    uint64_t *status;    // [blocks of the largest scan] look-back words
+    int64_t *error;      // raised when a wait gives up
+};
 
 __device__ __forceinline__ int64_t dev_count(const int64_t *n_dev, int64_t n_host) {
     return n_dev ? *n_dev : n_host;
+}
+
+// Status words carry their value with them, so relaxed device-wide atomics
+// suffice: no other data is published through them.
+__device__ __forceinline__ void store_word(uint64_t *p, uint32_t tag, uint32_t value) {
+    __hip_atomic_store(p, ((uint64_t)tag << 32) | (uint64_t)value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void publish(uint64_t *p, uint32_t id, uint32_t flag, uint32_t value) {
+    store_word(p, (id << 2) | flag, value);
+}
+
+__device__ __forceinline__ uint64_t peek(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Value of a word once it carries `tag` (bounded wait; raises *error and
+// returns 0 if it never does).
+__device__ __forceinline__ uint32_t await_word(const uint64_t *p, uint64_t first, uint32_t tag, int64_t *error) {
+    uint64_t v = first;
+    for (uint32_t spins = 0; (uint32_t)(v >> 32) != tag; v = peek(p)) {
+        if (++spins > kSpinLimit) {   // never expected: report it and stop waiting
+            atomicAdd((unsigned long long *)error, 1ull);
+            return 0u;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return (uint32_t)v;
+}
+
+__device__ __forceinline__ uint32_t take_ticket(uint32_t *tickets, uint32_t id) {
+    return __hip_atomic_fetch_add(&tickets[id], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of block b in a chain of consecutive status words, walked
+// by a whole wave: lane l of window k inspects block p - 64 k - l, and the
+// kLookWindows windows are loaded at once, so one round trip covers 256
+// predecessors.  All 64 lanes must call it.
+constexpr int kLookWindows = 4;
+
+__device__ __forceinline__ uint32_t look_back_wave(const uint64_t *chain, int64_t b, uint32_t id, int64_t *error) {
+    const uint32_t lane = lane_id();
+    const uint32_t t_agg = (id << 2) | kFlagAgg, t_pre = (id << 2) | kFlagPrefix;
+    uint32_t excl = 0, spins = 0;
+    int64_t p = b - 1;
+    while (p >= 0) {
+        uint64_t v[kLookWindows];
+#pragma unroll
+        for (int k = 0; k < kLookWindows; ++k) {
+            const int64_t q = p - 64 * k - (int64_t)lane;
+            v[k] = q >= 0 ? peek(chain + q) : 0ull;
+        }
+        bool finished = false, moved = false;
+#pragma unroll
+        for (int k = 0; k < kLookWindows; ++k) {
+            const int64_t q = p - (int64_t)lane;   // p has moved past the windows already summed
+            const uint32_t tag = q >= 0 ? (uint32_t)(v[k] >> 32) : t_pre;   // a zero prefix before block 0
+            const uint32_t val = q >= 0 ? (uint32_t)v[k] : 0u;
+            const uint64_t pre = ballot(tag == t_pre);
+            const uint64_t ready = ballot(tag == t_pre || tag == t_agg);
+            const int fp = pre ? (int)__builtin_ctzll(pre) : 64;   // nearest predecessor with a prefix
+            const uint64_t need = fp >= 63 ? ~0ull : ((2ull << fp) - 1ull);
+            if ((ready & need) != need) break;   // poll this window again
+            uint32_t mine = ((int)lane <= fp) ? val : 0u;
+            for (int off = 32; off >= 1; off >>= 1) mine += __shfl_xor(mine, off, 64);
+            excl += mine;
+            if (fp < 64) {
+                finished = true;
+                break;
+            }
+            p -= 64;
+            moved = true;
+        }
+        if (finished) break;
+        if (!moved) {
+            if (++spins > kSpinLimit) {   // never expected: report it and stop waiting
+                if (lane == 0) atomicAdd((unsigned long long *)error, 1ull);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    return excl;
 }
 
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
@@ -44,51 +152,22 @@ __device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t x, uint32_t &to
     return before + incl - x;
 }
 
-// Pass 1: per-block sums of src(i) over a chunk of kChunk items.
-template <class Src>
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(Src src, const int64_t *n_dev, int64_t n_host,
-                                                              uint32_t *part) {
+// Single-pass exclusive scan: sink(i, exclusive_prefix, value) for every
+// i < n, the total to *total.  The sink may overwrite the source in place.
+template <class Src, class Sink>
+__global__ __launch_bounds__(kScanThreads) void k_scan(Src src, Sink sink, const int64_t *n_dev, int64_t n_host,
+                                                       SyncState ss, uint32_t id, int64_t *total) {
+    __shared__ uint32_t s_b, s_excl;
+    if (threadIdx.x == 0) s_b = take_ticket(ss.tickets, id);
+    __syncthreads();
+    const int64_t b = s_b;
     const int64_t n = dev_count(n_dev, n_host);
-    const int64_t base = (int64_t)blockIdx.x * kChunk;
-    if (base >= n) {
-        if (threadIdx.x == 0) part[blockIdx.x] = 0;
+    const int64_t nb = (n + kChunk - 1) / kChunk;
+    if (b >= nb) {   // block-uniform
+        if (nb == 0 && b == 0 && threadIdx.x == 0 && total) *total = 0;
         return;
     }
-    uint32_t s = 0;
-    for (int j = 0; j < kScanItems; ++j) {
-        const int64_t i = base + (int64_t)j * kScanThreads + threadIdx.x;
-        if (i < n) s += src(i);
-    }
-    uint32_t tot;
-    block_excl_scan_u32<kScanThreads>(s, tot);
-    if (threadIdx.x == 0) part[blockIdx.x] = tot;
-}
-
-// Pass 2: exclusive scan of the nb block sums in place (one block), total to *total.
-__global__ __launch_bounds__(1024) void k_scan_partials(uint32_t *part, int64_t nb, int64_t *total) {
-    const int64_t per = (nb + 1023) / 1024;
-    const int64_t lo = (int64_t)threadIdx.x * per;
-    const int64_t hi = lo + per < nb ? lo + per : nb;
-    uint32_t s = 0;
-    for (int64_t k = lo; k < hi; ++k) s += part[k];
-    uint32_t tot;
-    uint32_t run = block_excl_scan_u32<1024>(s, tot);
-    for (int64_t k = lo; k < hi; ++k) {
-        const uint32_t c = part[k];
-        part[k] = run;
-        run += c;
-    }
-    if (threadIdx.x == 0 && total) *total = (int64_t)tot;
-}
-
-// Pass 3: per-block scan with the block's offset; sink(i, exclusive_prefix, value).
-template <class Src, class Sink>
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(Src src, Sink sink, const int64_t *n_dev, int64_t n_host,
-                                                            const uint32_t *part) {
-    const int64_t n = dev_count(n_dev, n_host);
-    const int64_t base = (int64_t)blockIdx.x * kChunk;
-    if (base >= n) return;
-    const int64_t first = base + (int64_t)threadIdx.x * kScanItems;
+    const int64_t first = b * kChunk + (int64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
     uint32_t s = 0;
 #pragma unroll
@@ -96,8 +175,20 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(Src src, Sink sink, 
         v[j] = (first + j < n) ? src(first + j) : 0u;
         s += v[j];
     }
-    uint32_t tot;
-    uint32_t run = part[blockIdx.x] + block_excl_scan_u32<kScanThreads>(s, tot);
+    uint32_t agg;
+    uint32_t run = block_excl_scan_u32<kScanThreads>(s, agg);
+    uint64_t *mine = ss.status + b;
+    if (threadIdx.x == 0) publish(mine, id, b == 0 ? kFlagPrefix : kFlagAgg, agg);
+    if (threadIdx.x < 64) {   // wave 0 looks back
+        const uint32_t excl = b == 0 ? 0u : look_back_wave(ss.status, b, id, ss.error);
+        if (threadIdx.x == 0) {
+            if (b > 0) publish(mine, id, kFlagPrefix, excl + agg);
+            s_excl = excl;
+            if (b == nb - 1 && total) *total = (int64_t)excl + (int64_t)agg;
+        }
+    }
+    __syncthreads();
+    run += s_excl;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
         if (first + j < n) sink(first + j, run, v[j]);
@@ -106,23 +197,37 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(Src src, Sink sink, 
 }
 
 template <class Src, class Sink>
-inline void scan_exclusive(Src src, Sink sink, const int64_t *n_dev, int64_t n_cap, uint32_t *part, int64_t *total,
-                           hipStream_t st) {
-    const int64_t nb = (n_cap + kChunk - 1) / kChunk;
-    if (nb == 0) {
-        // still publish a zero total
-        hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, part, (int64_t)0, total);
-        return;
-    }
-    hipLaunchKernelGGL(k_scan_reduce<Src>, dim3((unsigned)nb), dim3(kScanThreads), 0, st, src, n_dev, n_cap, part);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, part, nb, total);
-    hipLaunchKernelGGL((k_scan_down<Src, Sink>), dim3((unsigned)nb), dim3(kScanThreads), 0, st, src, sink, n_dev,
-                       n_cap, part);
+inline void scan_exclusive(Src src, Sink sink, const int64_t *n_dev, int64_t n_cap, const SyncState &ss, uint32_t id,
+                           int64_t *total, hipStream_t st) {
+    int64_t nb = (n_cap + kChunk - 1) / kChunk;
+    if (nb < 1) nb = 1;   // one block still publishes a zero total
+    hipLaunchKernelGGL((k_scan<Src, Sink>), dim3((unsigned)nb), dim3(kScanThreads), 0, st, src, sink, n_dev, n_cap,
+                       ss, id, total);
 }
 
 // ---------------------------------------------------------------------------
 // stable LSD radix sort of (uint32 key, uint32 value) pairs, <= 8 bits a pass
+//
+// Two launches a pass.  k_radix_count publishes every block's digit counts
+// as tagged words; the last block of each group of kSortGroup blocks to
+// arrive (found with an atomic counter) collects its group's counts, stores
+// exclusive offsets within the group and publishes the group totals; the
+// last group to arrive turns the group totals into global bases.  Blocks
+// that arrive last only wait for words whose writers have already issued
+// them.  k_radix_scatter then places every block's items stably.
 // ---------------------------------------------------------------------------
+
+constexpr int kSortGroup = 64;
+
+// Per-call state of the sort passes.
+struct SortState {
+    uint64_t *words;     // [256 * blocks] tagged digit counts, then offsets within the group (cleared per call)
+    uint64_t *gwords;    // [256 * groups] tagged group totals (cleared per call)
+    uint32_t *gbase;     // [256 * groups] global base of each (group, digit)
+    uint32_t *done;      // [passes][groups + 1] arrival counters (cleared per call)
+    int64_t groups_cap;  // groups of the capacity
+    int64_t *error;      // raised when a wait gives up
+};
 
 // Lanes of the wave holding the same digit as this lane (among `valid` lanes).
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, int dbits, uint64_t valid) {
@@ -135,27 +240,90 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, int dbits, uint64_t 
     return peers;
 }
 
-// Per-block digit counts, stored digit-major: hist[d * nb + block].
-__global__ __launch_bounds__(kScanThreads) void k_radix_hist(const uint32_t *__restrict__ keys, const int64_t *n_dev,
-                                                             int64_t n_host, int shift, int dbits,
-                                                             uint32_t *__restrict__ hist, int64_t nb) {
-    __shared__ uint32_t h[256];
+// Whether this block is the last of `of` blocks to arrive at the counter
+// (every thread's earlier stores are issued before the block arrives).
+__device__ __forceinline__ bool arrive_last(uint32_t *counter, uint32_t of) {
+    __shared__ uint32_t s_last;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        s_last = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == of - 1u;
+    __syncthreads();
+    return s_last != 0u;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_radix_count(const uint32_t *__restrict__ kin, const int64_t *n_dev,
+                                                              int64_t n_host, int shift, int dbits, SortState so,
+                                                              int pass) {
+    __shared__ uint32_t s_cnt[256];
+    const uint32_t t = threadIdx.x;
     const int64_t n = dev_count(n_dev, n_host);
+    const int64_t nb = (n + kChunk - 1) / kChunk;
+    const int64_t b = blockIdx.x;
+    if (b >= nb) return;   // block-uniform
     const int nd = 1 << dbits;
     const uint32_t mask = (uint32_t)nd - 1u;
-    h[threadIdx.x] = 0;
+    const uint32_t tag = (uint32_t)pass + 1u;
+    s_cnt[t] = 0u;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    const int64_t base = b * kChunk;
+    uint32_t key[kScanItems];   // all loads in flight at once
+#pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
-        const int64_t i = base + (int64_t)j * kScanThreads + threadIdx.x;
-        if (base + (int64_t)j * kScanThreads >= n) break;   // block-uniform
-        const bool valid = i < n;
-        const uint32_t d = valid ? (keys[i] >> shift) & mask : 0u;
+        const int64_t i = base + (int64_t)j * kScanThreads + t;
+        key[j] = i < n ? kin[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const bool valid = base + (int64_t)j * kScanThreads + t < n;
+        const uint32_t d = (key[j] >> shift) & mask;
         const uint64_t peers = match_digit(d, dbits, ballot(valid));
-        if (valid && rank_below(peers) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+        if (valid && rank_below(peers) == 0) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
     }
     __syncthreads();
-    if ((int)threadIdx.x < nd) hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+    store_word(so.words + (size_t)b * 256 + t, tag, s_cnt[t]);
+    const int64_t ng = (nb + kSortGroup - 1) / kSortGroup;
+    const int64_t g = b / kSortGroup;
+    const int64_t g0 = g * kSortGroup;
+    const int g_n = (int)((g0 + kSortGroup < nb ? g0 + kSortGroup : nb) - g0);
+    uint32_t *done = so.done + (size_t)pass * (so.groups_cap + 1);
+    if (!arrive_last(done + g, (uint32_t)g_n)) return;
+    // last block of group g: exclusive offsets of digit t within the group
+    uint32_t run = 0;
+    for (int q0 = 0; q0 < g_n; q0 += 16) {
+        uint64_t w[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k)   // 16 loads in flight
+            w[k] = q0 + k < g_n ? peek(so.words + (size_t)(g0 + q0 + k) * 256 + t) : 0ull;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (q0 + k < g_n) {
+                uint64_t *p = so.words + (size_t)(g0 + q0 + k) * 256 + t;
+                const uint32_t c = await_word(p, w[k], tag, so.error);
+                store_word(p, 0u, run);
+                run += c;
+            }
+        }
+    }
+    store_word(so.gwords + (size_t)g * 256 + t, tag, run);
+    if (!arrive_last(done + so.groups_cap, (uint32_t)ng)) return;
+    // last group: global base of every (group, digit)
+    uint32_t tot = 0;
+    for (int64_t q0 = 0; q0 < ng; q0 += 16) {
+        uint64_t w[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) w[k] = q0 + k < ng ? peek(so.gwords + (size_t)(q0 + k) * 256 + t) : 0ull;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (q0 + k < ng) {
+                const uint32_t c = await_word(so.gwords + (size_t)(q0 + k) * 256 + t, w[k], tag, so.error);
+                so.gbase[(size_t)(q0 + k) * 256 + t] = tot;
+                tot += c;
+            }
+        }
+    }
+    uint32_t all;
+    const uint32_t dbase = block_excl_scan_u32<kScanThreads>((int)t < nd ? tot : 0u, all);
+    for (int64_t q = 0; q < ng; ++q) so.gbase[(size_t)q * 256 + t] += dbase;
 }
 
 // Stable scatter: items keep their input order within a digit.
@@ -163,22 +331,31 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
                                                                 const uint32_t *__restrict__ vin,
                                                                 uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                                 const int64_t *n_dev, int64_t n_host, int shift,
-                                                                int dbits, const uint32_t *__restrict__ hist, int64_t nb) {
+                                                                int dbits, SortState so) {
     __shared__ uint32_t s_off[256];
     __shared__ uint32_t s_w[kScanThreads / 64][256];
     const int64_t n = dev_count(n_dev, n_host);
-    const int64_t base = (int64_t)blockIdx.x * kChunk;
-    if (base >= n) return;
+    const int64_t b = blockIdx.x;
+    const int64_t base = b * kChunk;
+    if (base >= n) return;   // block-uniform
     const int nd = 1 << dbits;
     const uint32_t mask = (uint32_t)nd - 1u;
     const uint32_t t = threadIdx.x, wave = t >> 6;
-    if ((int)t < nd) s_off[t] = hist[(int64_t)t * nb + blockIdx.x];
+    s_off[t] = (uint32_t)so.words[(size_t)b * 256 + t] + so.gbase[(size_t)(b / kSortGroup) * 256 + t];
+    uint32_t keys[kScanItems], vals[kScanItems];   // all loads in flight at once
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = base + (int64_t)j * kScanThreads + t;
+        keys[j] = i < n ? kin[i] : 0u;
+        vals[j] = i < n ? vin[i] : 0u;
+    }
+#pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
         if (base + (int64_t)j * kScanThreads >= n) break;   // block-uniform
         const int64_t i = base + (int64_t)j * kScanThreads + t;
         const bool valid = i < n;
-        const uint32_t key = valid ? kin[i] : 0u;
-        const uint32_t val = valid ? vin[i] : 0u;
+        const uint32_t key = keys[j];
+        const uint32_t val = vals[j];
         const uint32_t d = (key >> shift) & mask;
         for (int k = t; k < (kScanThreads / 64) * 256; k += kScanThreads) (&s_w[0][0])[k] = 0u;
         __syncthreads();
@@ -198,7 +375,7 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
         __syncthreads();
         if (valid) {
             const uint32_t pos = s_w[wave][d] + rank;
-            if ((int64_t)pos < n) {   // always true for a correct histogram; keeps writes in bounds
+            if ((int64_t)pos < n) {   // always true for consistent counts; keeps writes in bounds
                 kout[pos] = key;
                 vout[pos] = val;
             }
@@ -207,42 +384,22 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
     }
 }
 
-struct HistSrc {
-    const uint32_t *h;
-    __device__ uint32_t operator()(int64_t i) const { return h[i]; }
-};
-struct HistSink {
-    uint32_t *h;
-    __device__ void operator()(int64_t i, uint32_t pre, uint32_t) const { h[i] = pre; }
-};
-
-// nb_dev[0] = number of blocks for the device count, nb_dev[1] = 256 * that
-__global__ void k_sort_blocks(const int64_t *n_dev, int64_t *nb_dev) {
-    const int64_t nb = (*n_dev + kChunk - 1) / kChunk;
-    nb_dev[0] = nb;
-    nb_dev[1] = 256 * nb;
-}
-
-// Sorts n (device count, <= cap) pairs by key bits [0, bits).  Returns true if
-// the result is in (k1, v1), false if in (k0, v0).  The histogram stride is the
-// host capacity's block count; only the device count's blocks are touched.
+// Sorts n (device count, <= cap) pairs by key bits [0, bits), using the
+// arrival counters and tags of passes pass0, pass0 + 1, ...  Returns true if the result is in
+// (k1, v1), false if in (k0, v0).
 inline bool radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const int64_t *n_dev, int64_t cap,
-                       int bits, uint32_t *hist, uint32_t *part, int64_t *scratch_counts, hipStream_t st) {
+                       int bits, const SortState &so, int pass0, hipStream_t st) {
     const int64_t nb = (cap + kChunk - 1) / kChunk;
     if (nb == 0 || bits <= 0) return false;
     bool in1 = false;
-    for (int shift = 0; shift < bits; shift += 8) {
+    for (int shift = 0, p = pass0; shift < bits; shift += 8, ++p) {
         const int dbits = bits - shift < 8 ? bits - shift : 8;
         uint32_t *ki = in1 ? k1 : k0, *vi = in1 ? v1 : v0;
         uint32_t *ko = in1 ? k0 : k1, *vo = in1 ? v0 : v1;
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kScanThreads), 0, st, ki, n_dev, cap, shift, dbits,
-                           hist, nb);
-        // digit-major counts of all nb blocks (blocks past n wrote zeros or nothing:
-        // they are cleared by k_radix_hist only when launched, so the scan covers
-        // the full capacity grid, which k_radix_hist always writes)
-        scan_exclusive(HistSrc{hist}, HistSink{hist}, nullptr, (int64_t)(1 << dbits) * nb, part, scratch_counts, st);
+        hipLaunchKernelGGL(k_radix_count, dim3((unsigned)nb), dim3(kScanThreads), 0, st, ki, n_dev, cap, shift, dbits,
+                           so, p);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kScanThreads), 0, st, ki, vi, ko, vo, n_dev, cap,
-                           shift, dbits, hist, nb);
+                           shift, dbits, so);
         in1 = !in1;
     }
     return in1;

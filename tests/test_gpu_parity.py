@@ -132,6 +132,13 @@ def test_binning_bit_exact_multiview(rast):
     assert _check_binning(rast, w, (16, 16)) == 0
 
 
+def test_binning_bit_exact_many_blocks(rast):
+    """Hundreds of scan and sort blocks per pass, so that the blocks' look-back
+    chains are long and blocks overtake each other."""
+    w = scenes.config2(n_views=4, n=120000)
+    assert _check_binning(rast, w, (16, 16)) == 0
+
+
 def _fused(rast, w, tile=(16, 16), targets=None, weight=None, **kw):
     g = dev_params(w.gaussians)
     q, t = dev_poses(w.views)
