@@ -113,7 +113,8 @@ typedef struct {
 
 /* The Gaussian map (eq. 1 and its anisotropic form).  Device pointers, raw
  * (unactivated) parameters: means [N,3] world metres; quats [N,4] (w,x,y,z);
- * log_scales [N,3] ([N,1] with GSR_ISOTROPIC); opacity_logits [N]; rgb [N,3]. */
+ * log_scales [N,3] ([N,1] with GSR_ISOTROPIC); opacity_logits [N]; rgb [N,3].
+ * With GSR_ISOTROPIC, quats is not read and may be NULL. */
 typedef struct {
     int64_t n;
     const float *means, *quats, *log_scales, *opacity_logits, *rgb;

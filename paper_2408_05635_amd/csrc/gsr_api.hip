@@ -91,6 +91,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kRecGrad = 14;   // per-record parameter gradient: mu 3, q 4, log_s 3, logit 1, rgb 3
+constexpr int kRecBwdMaxBlocks = 2048;   // grid cap of the record backward (one pose row per block)
 // synchronisation region, cleared by every call: scan tickets (256 B), the
 // scans' look-back words, the sort passes' arrival counters and tagged words
 constexpr size_t kSyncTickets = 256;
@@ -106,7 +107,7 @@ struct Layout {
     int32_t G;            // total blend blocks
     int tile_bits;        // key bits of the tile sort
     size_t views, poses, counters, cnt, zkey, dk0, dv0, dk1, dv1, inv, rec, trect, cnt_s, poff, pk0, pv0, pk1, pv1,
-        owner, prec, ranges, tfinal, nlast, phash, gpairs, rgrad, rpose, losst, posepart, sgbase, sync;
+        owner, prec, ranges, tfinal, nlast, phash, gpairs, rgrad, losst, poseblk, sgbase, sync;
     int64_t sort_groups;  // groups of sort blocks at the capacity
     // offsets in the sync region (cleared by every call): scan look-back
     // words, sort arrival counters, sort block words, sort group words
@@ -269,9 +270,9 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     L.phash = take(4 * (size_t)L.P);
     L.gpairs = take(40 * kc);
     L.rgrad = take(4 * kRecGrad * vn);
-    L.rpose = take(8 * 12 * vn);
     L.losst = take(sizeof(double) * (size_t)L.T);
-    L.posepart = take(sizeof(double) * 12 * V);
+    L.poseblk = take(sizeof(double) * 12 * V * (size_t)std::max<int64_t>(
+                                           std::min<int64_t>((L.vn + 255) / 256, kRecBwdMaxBlocks), 1));
     const int64_t nb = std::max<int64_t>((std::max<int64_t>(L.vn, kcap) + kChunk - 1) / kChunk, 1);
     L.sort_groups = (nb + kSortGroup - 1) / kSortGroup;
     L.sgbase = take(4 * 256 * (size_t)L.sort_groups);
@@ -332,16 +333,17 @@ __device__ __forceinline__ uint32_t tiles_of(const Proj &r, const ViewTable *vt,
 }
 
 // per Gaussian i, per view v: tiles touched (0 = not visible) and depth key
+template <bool ISO>
 __global__ __launch_bounds__(256) void k_project_count(ProjParams pp, const ViewTable *__restrict__ vt,
                                                        const PoseF64 *__restrict__ poses, uint32_t *__restrict__ cnt,
                                                        uint32_t *__restrict__ zkey) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= pp.n) return;
-    const GaussIn p = load_gauss(pp.g, i, pp.iso);
+    const GaussIn p = load_gauss<ISO>(pp.g, i);
     const int V = vt->n_views;
     for (int v = 0; v < V; ++v) {
         Proj r;
-        project<false>(p, poses[v], vt->v[v], pp.z_near, pp.blur, pp.iso, r);
+        project<false, ISO>(p, poses[v], vt->v[v], pp.z_near, pp.blur, r);
         uint32_t c = 0;
         if (r.visible) {
             uint32_t a, b;
@@ -368,6 +370,7 @@ struct VisSink {
 };
 
 // per visible record s (depth order): full projection -> record, tile rect
+template <bool ISO>
 __global__ __launch_bounds__(256) void k_gather(ProjParams pp, const ViewTable *__restrict__ vt,
                                                 const PoseF64 *__restrict__ poses, const int64_t *__restrict__ counters,
                                                 const uint32_t *__restrict__ sorted_gid, float4 *__restrict__ rec,
@@ -379,9 +382,9 @@ __global__ __launch_bounds__(256) void k_gather(ProjParams pp, const ViewTable *
         const int v = (int)(gid / (uint64_t)pp.n);
         if (v >= vt->n_views) continue;   // never expected; keeps reads in bounds
         const int64_t i = (int64_t)gid - (int64_t)v * pp.n;
-        const GaussIn p = load_gauss(pp.g, i, pp.iso);
+        const GaussIn p = load_gauss<ISO>(pp.g, i);
         Proj r;
-        project<true>(p, poses[v], vt->v[v], pp.z_near, pp.blur, pp.iso, r);
+        project<true, ISO>(p, poses[v], vt->v[v], pp.z_near, pp.blur, r);
         uint32_t a = 0, b = 0;
         const uint32_t c = tiles_of(r, vt, vt->v[v], a, b);
         rec[3 * s] = make_float4(r.mxh, r.myh, r.mxl, r.myl);
@@ -502,146 +505,191 @@ struct GradOut {
 // Per visible record s (one view, one Gaussian): the record's 2D gradient is
 // the sum of its pairs' rows (contiguous); the chain rule takes it to the raw
 // parameters (written per record, 14 floats) and to the view's pose partials
-// (G_W and g_t, 12 doubles, also per record).
+// (G_W and g_t, 12 values), which are summed per view in FP64: in LDS over
+// the block, then written as one row per block (no global atomics) for
+// k_pose_final to add in a fixed order.
 //
 // Load balance: records are depth-sorted, so the nearest ones, which can
-// cover every tile of the image, are neighbours.  Lane l of wave w takes
-// record l * W + w (W = number of waves needed), which spreads neighbours over
-// different waves.  A record with more than kLongRows rows is summed by the
-// whole wave (rows lane, lane + 64, ...; then a fixed-order DPP reduction), so
-// no lane walks a long range alone.  Both sums are deterministic.
+// cover every tile of the image, are neighbours.  Lane l of wave slot w takes
+// record l * W + w (W = number of wave slots needed), which spreads
+// neighbours over different waves; the grid's waves walk the slots with a
+// stride.  A record with more than kLongRows rows is summed by the whole wave
+// (rows lane, lane + 64, ...; then a fixed-order reduction), so no lane walks
+// a long range alone.  Both row sums are deterministic.
 constexpr uint32_t kLongRows = 32;
 
+template <bool ISO>
 __global__ __launch_bounds__(256) void k_record_bwd(ProjParams pp, const ViewTable *__restrict__ vt,
                                                     const PoseF64 *__restrict__ poses,
                                                     const uint32_t *__restrict__ gid_sorted,
                                                     const uint32_t *__restrict__ poff,
                                                     const uint32_t *__restrict__ cnt_s,
                                                     const float *__restrict__ gpairs, const int64_t *__restrict__ counters,
-                                                    float *__restrict__ rgrad, double *__restrict__ rpose) {
+                                                    float *__restrict__ rgrad, double *__restrict__ pose_blocks,
+                                                    bool want_gauss, bool want_pose) {
+    __shared__ double s_pose[GSR_MAX_VIEWS * 12];
+    const int V = vt->n_views;
+    if (want_pose) {
+        for (int k = threadIdx.x; k < V * 12; k += blockDim.x) s_pose[k] = 0.0;
+        __syncthreads();
+    }
     const int64_t M = counters[kCntVisible];
     const bool have_pairs = counters[kCntPairsUsed] > 0;
     const int64_t W = (M + 63) / 64;
-    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (w >= W) return;   // wave-uniform
     const uint32_t lane = threadIdx.x & 63u;
-    const int64_t s = (int64_t)lane * W + w;
-    const bool valid = s < M;
-    uint32_t j0 = 0, nrow = 0;
-    if (valid && have_pairs) {
-        j0 = poff[s];
-        nrow = cnt_s[s];
-    }
-    float g2[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (nrow <= kLongRows) {
-        for (uint32_t jj = j0; jj < j0 + nrow; ++jj) {
-            const float *row = gpairs + 10 * (size_t)jj;
+    const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < W; w += wstride) {   // wave-uniform
+        const int64_t s = (int64_t)lane * W + w;
+        const bool valid = s < M;
+        uint32_t j0 = 0, nrow = 0;
+        if (valid && have_pairs) {
+            j0 = poff[s];
+            nrow = cnt_s[s];
+        }
+        float g2[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (nrow <= kLongRows) {   // rows in order; four rows' loads in flight at once
+            uint32_t jj = j0;
+            const uint32_t end = j0 + nrow;
+            for (; jj + 4 <= end; jj += 4) {
+                float rows[40];
+                const float *row = gpairs + 10 * (size_t)jj;
 #pragma unroll
-            for (int c = 0; c < 10; ++c) g2[c] += row[c];
+                for (int c = 0; c < 40; ++c) rows[c] = row[c];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int c = 0; c < 10; ++c) g2[c] += rows[10 * q + c];
+            }
+            for (; jj < end; ++jj) {
+                const float *row = gpairs + 10 * (size_t)jj;
+#pragma unroll
+                for (int c = 0; c < 10; ++c) g2[c] += row[c];
+            }
+        }
+        uint64_t longm = ballot(nrow > kLongRows);
+        while (longm) {   // wave-uniform loop over this wave's long records
+            const int src = __builtin_ctzll(longm);
+            longm &= longm - 1;
+            const uint32_t a = __shfl(j0, src, 64), cnt = __shfl(nrow, src, 64);
+            float part[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            for (uint32_t jj = a + lane; jj < a + cnt; jj += 64) {
+                const float *row = gpairs + 10 * (size_t)jj;
+#pragma unroll
+                for (int c = 0; c < 10; ++c) part[c] += row[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 10; ++c) {
+                const float t = wave_sum(part[c]);
+                if ((int)lane == src) g2[c] = t;
+            }
+        }
+        if (!valid) continue;
+        const uint32_t gid = gid_sorted[s];
+        const int v = (int)(gid / (uint64_t)pp.n);
+        if (v >= V) continue;   // never expected; keeps reads in bounds
+        const int64_t i = (int64_t)gid - (int64_t)v * pp.n;
+        const GaussIn p = load_gauss<ISO>(pp.g, i);
+        Proj r;
+        project<true, ISO>(p, poses[v], vt->v[v], pp.z_near, pp.blur, r);
+        ParamGrad pg;
+        for (int k = 0; k < 3; ++k) pg.mu[k] = pg.ls[k] = pg.rgb[k] = 0.0;
+        for (int k = 0; k < 4; ++k) pg.q[k] = 0.0;
+        pg.logit = 0.0;
+        double gX[3], GW[9];
+        project_backward<ISO>(p, poses[v], vt->v[v], r, g2, pg, gX, GW);
+        if (want_gauss) {
+            float *o = rgrad + kRecGrad * (size_t)s;
+            for (int k = 0; k < 3; ++k) o[k] = (float)pg.mu[k];
+            for (int k = 0; k < 4; ++k) o[3 + k] = (float)pg.q[k];
+            for (int k = 0; k < 3; ++k) o[7 + k] = (float)pg.ls[k];
+            o[10] = (float)pg.logit;
+            for (int k = 0; k < 3; ++k) o[11 + k] = (float)pg.rgb[k];
+        }
+        if (want_pose) {
+            for (int k = 0; k < 9; ++k) atomicAdd(&s_pose[v * 12 + k], GW[k]);
+            for (int k = 0; k < 3; ++k) atomicAdd(&s_pose[v * 12 + 9 + k], gX[k]);
         }
     }
-    uint64_t longm = ballot(nrow > kLongRows);
-    while (longm) {   // wave-uniform loop over this wave's long records
-        const int src = __builtin_ctzll(longm);
-        longm &= longm - 1;
-        const uint32_t a = __shfl(j0, src, 64), cnt = __shfl(nrow, src, 64);
-        float part[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        for (uint32_t jj = a + lane; jj < a + cnt; jj += 64) {
-            const float *row = gpairs + 10 * (size_t)jj;
-#pragma unroll
-            for (int c = 0; c < 10; ++c) part[c] += row[c];
-        }
-#pragma unroll
-        for (int c = 0; c < 10; ++c) {
-            const float t = wave_sum(part[c]);
-            if ((int)lane == src) g2[c] = t;
-        }
+    if (want_pose) {
+        __syncthreads();
+        double *o = pose_blocks + (size_t)blockIdx.x * V * 12;
+        for (int k = threadIdx.x; k < V * 12; k += blockDim.x) o[k] = s_pose[k];
     }
-    if (!valid) return;
-    const uint32_t gid = gid_sorted[s];
-    const int v = (int)(gid / (uint64_t)pp.n);
-    if (v >= vt->n_views) return;   // never expected; keeps reads in bounds
-    const int64_t i = (int64_t)gid - (int64_t)v * pp.n;
-    const GaussIn p = load_gauss(pp.g, i, pp.iso);
-    Proj r;
-    project<true>(p, poses[v], vt->v[v], pp.z_near, pp.blur, pp.iso, r);
-    ParamGrad pg;
-    for (int k = 0; k < 3; ++k) pg.mu[k] = pg.ls[k] = pg.rgb[k] = 0.0;
-    for (int k = 0; k < 4; ++k) pg.q[k] = 0.0;
-    pg.logit = 0.0;
-    double gX[3], GW[9];
-    project_backward(p, poses[v], vt->v[v], r, g2, pp.iso, pg, gX, GW);
-    float *o = rgrad + kRecGrad * (size_t)s;
-    for (int k = 0; k < 3; ++k) o[k] = (float)pg.mu[k];
-    for (int k = 0; k < 4; ++k) o[3 + k] = (float)pg.q[k];
-    for (int k = 0; k < 3; ++k) o[7 + k] = (float)pg.ls[k];
-    o[10] = (float)pg.logit;
-    for (int k = 0; k < 3; ++k) o[11 + k] = (float)pg.rgb[k];
-    double *q = rpose + 12 * (size_t)s;
-    for (int k = 0; k < 9; ++k) q[k] = GW[k];
-    for (int k = 0; k < 3; ++k) q[9 + k] = gX[k];
 }
 
 // Per Gaussian: its gradient is the sum of its records' contributions over
-// the views, in view order (deterministic).  Pose partials: per view, summed
-// over the wave (FP64), then over the block in LDS, then one FP64 atomic per
-// block and value.
+// the views, in view order (deterministic).  The loads of four views are in
+// flight together.
 __global__ __launch_bounds__(256) void k_gauss_sum(ProjParams pp, const ViewTable *__restrict__ vt,
                                                    const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ inv,
-                                                   const float *__restrict__ rgrad, const double *__restrict__ rpose,
-                                                   GradOut go, double *__restrict__ posepart,
+                                                   const float *__restrict__ rgrad, GradOut go,
                                                    const int64_t *__restrict__ counters) {
-    __shared__ double s_pose[GSR_MAX_VIEWS * 12];
     const int V = vt->n_views;
-    for (int k = threadIdx.x; k < V * 12; k += blockDim.x) s_pose[k] = 0.0;
-    __syncthreads();
     const uint32_t n_rec = (uint32_t)counters[kCntVisible];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = i < pp.n;
+    if (i >= pp.n) return;
     float acc[kRecGrad];
     for (int k = 0; k < kRecGrad; ++k) acc[k] = 0.0f;
-    for (int v = 0; v < V; ++v) {
-        const uint32_t s = live && cnt[(int64_t)v * pp.n + i] != 0u ? inv[(int64_t)v * pp.n + i] : 0xffffffffu;
-        const bool vis = s < n_rec;
-        if (vis && go.want_gauss) {
-            const float *o = rgrad + kRecGrad * (size_t)s;
-            for (int k = 0; k < kRecGrad; ++k) acc[k] += o[k];
+    for (int v0 = 0; v0 < V; v0 += 4) {
+        uint32_t sv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t gi = (int64_t)(v0 + k) * pp.n + i;
+            const bool in = v0 + k < V;
+            const uint32_t c = in ? cnt[gi] : 0u;
+            const uint32_t t = in ? inv[gi] : 0u;
+            sv[k] = (c != 0u && t < n_rec) ? t : 0xffffffffu;
         }
-        if (go.want_pose && ballot(vis) != 0) {
-            for (int k = 0; k < 12; ++k) {
-                const double t = wave_sum_f64(vis ? rpose[12 * (size_t)s + k] : 0.0);
-                if ((threadIdx.x & 63) == 0) atomicAdd(&s_pose[v * 12 + k], t);
-            }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool vis = sv[k] != 0xffffffffu;
+            const float *o = rgrad + kRecGrad * (size_t)(vis ? sv[k] : 0u);   // row 0 stands in, unused
+            float row[kRecGrad];
+#pragma unroll
+            for (int c = 0; c < kRecGrad; ++c) row[c] = o[c];
+#pragma unroll
+            for (int c = 0; c < kRecGrad; ++c) acc[c] += vis ? row[c] : 0.0f;
         }
     }
-    if (live && go.want_gauss) {
-        if (go.gg.means)
-            for (int k = 0; k < 3; ++k) go.gg.means[3 * i + k] = acc[k];
-        if (go.gg.quats)
-            for (int k = 0; k < 4; ++k) go.gg.quats[4 * i + k] = pp.iso ? 0.0f : acc[3 + k];
-        if (go.gg.log_scales) {
-            if (pp.iso)
-                go.gg.log_scales[i] = acc[7];
-            else
-                for (int k = 0; k < 3; ++k) go.gg.log_scales[3 * i + k] = acc[7 + k];
-        }
-        if (go.gg.opacity_logits) go.gg.opacity_logits[i] = acc[10];
-        if (go.gg.rgb)
-            for (int k = 0; k < 3; ++k) go.gg.rgb[3 * i + k] = acc[11 + k];
+    if (go.gg.means)
+        for (int k = 0; k < 3; ++k) go.gg.means[3 * i + k] = acc[k];
+    if (go.gg.quats)
+        for (int k = 0; k < 4; ++k) go.gg.quats[4 * i + k] = pp.iso ? 0.0f : acc[3 + k];
+    if (go.gg.log_scales) {
+        if (pp.iso)
+            go.gg.log_scales[i] = acc[7];
+        else
+            for (int k = 0; k < 3; ++k) go.gg.log_scales[3 * i + k] = acc[7 + k];
     }
-    if (go.want_pose) {
-        __syncthreads();
-        for (int k = threadIdx.x; k < V * 12; k += blockDim.x)
-            if (s_pose[k] != 0.0) atomicAdd(&posepart[k], s_pose[k]);
-    }
+    if (go.gg.opacity_logits) go.gg.opacity_logits[i] = acc[10];
+    if (go.gg.rgb)
+        for (int k = 0; k < 3; ++k) go.gg.rgb[3 * i + k] = acc[11 + k];
 }
 
-// per view: (G_W, g_t) -> dL/dq | t, dL/dt, dL/dq | C, dL/dC with C = -W^T t
-__global__ void k_pose_final(const float *__restrict__ pq, const float *__restrict__ pt, const PoseF64 *poses,
-                             const double *__restrict__ posepart, int V, gsr_pose_grads pg) {
-    const int v = threadIdx.x;
-    if (v >= V) return;
-    const double *GW = posepart + 12 * v;
+// Per view (one block each): the pose partials (G_W, g_t) summed over the
+// record blocks' rows in a fixed order (deterministic), then
+// (G_W, g_t) -> dL/dq | t, dL/dt, dL/dq | C, dL/dC with C = -W^T t.
+__global__ __launch_bounds__(256) void k_pose_final(const float *__restrict__ pq, const float *__restrict__ pt,
+                                                    const PoseF64 *poses, const double *__restrict__ pose_blocks,
+                                                    int nblocks, int V, gsr_pose_grads pg) {
+    __shared__ double s_red[12][256];
+    const int v = blockIdx.x, t = threadIdx.x;
+    double acc[12];
+    for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+    for (int b = t; b < nblocks; b += 256) {
+        const double *row = pose_blocks + ((size_t)b * V + v) * 12;
+        for (int k = 0; k < 12; ++k) acc[k] += row[k];
+    }
+    for (int k = 0; k < 12; ++k) s_red[k][t] = acc[k];
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if (t < h)
+            for (int k = 0; k < 12; ++k) s_red[k][t] += s_red[k][t + h];
+        __syncthreads();
+    }
+    if (t != 0) return;
+    double GW[12];
+    for (int k = 0; k < 12; ++k) GW[k] = s_red[k][0];
     const double *gt = GW + 9;
     const double q[4] = {pq[4 * v], pq[4 * v + 1], pq[4 * v + 2], pq[4 * v + 3]};
     const double *W = poses[v].W;
@@ -667,6 +715,7 @@ __global__ void k_pose_final(const float *__restrict__ pq, const float *__restri
 }
 
 // Binning test hook: record fields in depth order.
+template <bool ISO>
 __global__ void k_debug_records(const int64_t *__restrict__ counters, const uint32_t *__restrict__ gid,
                                 const float4 *__restrict__ rec, const uint2 *__restrict__ trect, int64_t max_rec,
                                 uint32_t *o_gid, float *o_xy, float *o_rad, float *o_z, const ProjParams pp,
@@ -682,9 +731,9 @@ __global__ void k_debug_records(const int64_t *__restrict__ counters, const uint
         // the radius is recomputed exactly as the projection kernels do
         const int v = (int)(g / (uint64_t)pp.n);
         const int64_t i = (int64_t)g - (int64_t)v * pp.n;
-        const GaussIn p = load_gauss(pp.g, i, pp.iso);
+        const GaussIn p = load_gauss<ISO>(pp.g, i);
         Proj r;
-        project<true>(p, poses[v], vt->v[v], pp.z_near, pp.blur, pp.iso, r);
+        project<true, ISO>(p, poses[v], vt->v[v], pp.z_near, pp.blur, r);
         o_rad[s] = r.radius;
     }
 }
@@ -741,7 +790,8 @@ gsr_status prepare(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views,
     if (g->n < 0) return fail(ctx, GSR_EINVAL, "n must be >= 0 (got %lld)", (long long)g->n);
     if ((int64_t)views->n_views * g->n >= (int64_t)0xffffffffLL)
         return fail(ctx, GSR_EUNSUPPORTED, "views x Gaussians must be < 2^32");
-    if (g->n > 0 && (!g->means || !g->quats || !g->log_scales || !g->opacity_logits || !g->rgb))
+    const bool iso = (opts->flags & GSR_ISOTROPIC) != 0;   // isotropic Gaussians have no quaternions
+    if (g->n > 0 && (!g->means || (!g->quats && !iso) || !g->log_scales || !g->opacity_logits || !g->rgb))
         return fail(ctx, GSR_EINVAL, "Gaussian parameter pointers must not be NULL");
     if (!views->quat || !views->trans) return fail(ctx, GSR_EINVAL, "pose pointers must not be NULL");
     if (!ws.ptr) return fail(ctx, GSR_EINVAL, "workspace pointer is NULL");
@@ -786,7 +836,8 @@ void enqueue_binning(Call &c, const gsr_views *views) {
                        dim3(256), 0, st, c.tab, vt, views->quat, views->trans, poses, counters,
                        reinterpret_cast<uint4 *>(sync), sync16);
     if (L.vn > 0) {
-        hipLaunchKernelGGL(k_project_count, dim3(grid_for(c.pp.n, 256, 1ll << 30)), dim3(256), 0, st, c.pp, vt,
+        hipLaunchKernelGGL(c.pp.iso ? k_project_count<true> : k_project_count<false>,
+                           dim3(grid_for(c.pp.n, 256, 1ll << 30)), dim3(256), 0, st, c.pp, vt,
                            poses, cnt, zkey);
     }
     // compaction of the visible (view, Gaussian) records, index order kept
@@ -799,7 +850,8 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     uint2 *trect = at<uint2>(ws, L.trect);
     uint32_t *cnt_s = at<uint32_t>(ws, L.cnt_s), *inv = at<uint32_t>(ws, L.inv);
     if (L.vn > 0)
-        hipLaunchKernelGGL(k_gather, dim3(grid_for(L.vn, 256, 8192)), dim3(256), 0, st, c.pp, vt, poses, counters,
+        hipLaunchKernelGGL(c.pp.iso ? k_gather<true> : k_gather<false>, dim3(grid_for(L.vn, 256, 8192)), dim3(256),
+                           0, st, c.pp, vt, poses, counters,
                            gid_sorted, rec, trect, cnt_s, inv, c.pp.g.rgb);
     uint32_t *pk0 = at<uint32_t>(ws, L.pk0), *pv0 = at<uint32_t>(ws, L.pv0);
     uint32_t *pk1 = at<uint32_t>(ws, L.pk1), *pv1 = at<uint32_t>(ws, L.pv1);
@@ -863,8 +915,6 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
     ViewTable *vt = at<ViewTable>(c.ws, L.views);
     int64_t *counters = at<int64_t>(c.ws, L.counters);
     float *gpairs = at<float>(c.ws, L.gpairs);
-    double *posepart = at<double>(c.ws, L.posepart);
-    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, posepart, (int64_t)12 * views->n_views);
     li.loss_tile = at<double>(c.ws, L.losst);
     BlendOut bo{out.rgb, out.depth, out.sil, at<float>(c.ws, L.tfinal), at<uint32_t>(c.ws, L.nlast),
                 at<uint32_t>(c.ws, L.phash)};
@@ -891,18 +941,25 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
                     (gg->means || gg->quats || gg->log_scales || gg->opacity_logits || gg->rgb);
     go.want_pose = pg && !(opts->flags & GSR_NO_POSE_GRADS) && (pg->dq_t || pg->dt || pg->dq_c || pg->dc);
     StageTimer timer(c.ctx, kStageProjectBwd, st);
-    if (c.pp.n > 0 && (go.want_gauss || go.want_pose)) {
-        hipLaunchKernelGGL(k_record_bwd, dim3(grid_for(L.vn, 256, 1ll << 30)), dim3(256), 0, st, c.pp, vt,
-                           at<PoseF64>(c.ws, L.poses), depth_sorted_gid(c), at<uint32_t>(c.ws, L.poff),
-                           at<uint32_t>(c.ws, L.cnt_s), gpairs, (const int64_t *)counters, at<float>(c.ws, L.rgrad),
-                           at<double>(c.ws, L.rpose));
+    const unsigned rec_blocks = std::min<unsigned>(grid_for(L.vn, 256, 1ll << 30), kRecBwdMaxBlocks);
+    double *pose_blocks = at<double>(c.ws, L.poseblk);
+    if (c.pp.n > 0 && (go.want_gauss || go.want_pose))
+        hipLaunchKernelGGL(c.pp.iso ? k_record_bwd<true> : k_record_bwd<false>, dim3(rec_blocks), dim3(256), 0, st,
+                           c.pp, vt, at<PoseF64>(c.ws, L.poses),
+                           depth_sorted_gid(c), at<uint32_t>(c.ws, L.poff), at<uint32_t>(c.ws, L.cnt_s), gpairs,
+                           (const int64_t *)counters, at<float>(c.ws, L.rgrad), pose_blocks, go.want_gauss,
+                           go.want_pose);
+    if (c.pp.n > 0 && go.want_gauss)
         hipLaunchKernelGGL(k_gauss_sum, dim3(grid_for(c.pp.n, 256, 1ll << 30)), dim3(256), 0, st, c.pp, vt,
-                           at<uint32_t>(c.ws, L.cnt), at<uint32_t>(c.ws, L.inv), at<float>(c.ws, L.rgrad),
-                           at<double>(c.ws, L.rpose), go, posepart, (const int64_t *)counters);
+                           at<uint32_t>(c.ws, L.cnt), at<uint32_t>(c.ws, L.inv), at<float>(c.ws, L.rgrad), go,
+                           (const int64_t *)counters);
+    if (go.want_pose) {
+        if (c.pp.n == 0)   // no record blocks ran: their rows are zero
+            hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((int64_t)rec_blocks * 12 * views->n_views, 256)), dim3(256),
+                               0, st, pose_blocks, (int64_t)rec_blocks * 12 * views->n_views);
+        hipLaunchKernelGGL(k_pose_final, dim3(views->n_views), dim3(256), 0, st, views->quat, views->trans,
+                           at<PoseF64>(c.ws, L.poses), pose_blocks, (int)rec_blocks, views->n_views, *pg);
     }
-    if (go.want_pose)
-        hipLaunchKernelGGL(k_pose_final, dim3(1), dim3(64), 0, st, views->quat, views->trans,
-                           at<PoseF64>(c.ws, L.poses), posepart, views->n_views, *pg);
     // with the Gaussian gradients off, or for N = 0, the outputs are still defined (zero)
     if (gg && !go.want_gauss && c.pp.n > 0) {
         float *ptrs[5] = {gg->means, gg->quats, gg->log_scales, gg->opacity_logits, gg->rgb};
@@ -1284,7 +1341,8 @@ gsr_status gsr_debug_binning(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_vie
     if (s != GSR_OK) return s;
     const Layout &L = c.L;
     const int64_t *counters = at<int64_t>(ws, L.counters);
-    hipLaunchKernelGGL(k_debug_records, dim3(grid_for(L.vn, 256, 4096)), dim3(256), 0, c.st, counters,
+    hipLaunchKernelGGL(c.pp.iso ? k_debug_records<true> : k_debug_records<false>, dim3(grid_for(L.vn, 256, 4096)),
+                       dim3(256), 0, c.st, counters,
                        depth_sorted_gid(c), at<float4>(ws, L.rec), at<uint2>(ws, L.trect), max_rec, rec_gid, rec_xy,
                        rec_radius, rec_z, c.pp, at<ViewTable>(ws, L.views), at<PoseF64>(ws, L.poses));
     hipLaunchKernelGGL(k_debug_copy_u32, dim3(grid_for(2 * L.T, 256, 4096)), dim3(256), 0, c.st,

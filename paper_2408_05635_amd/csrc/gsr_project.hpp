@@ -69,14 +69,19 @@ struct GaussIn {
     double logit;
 };
 
-__device__ __forceinline__ GaussIn load_gauss(const gsr_gaussians &g, int64_t i, bool iso) {
+// ISO: the isotropic parameterization (one log-scale per Gaussian, no
+// rotation): quaternions are not read.
+template <bool ISO>
+__device__ __forceinline__ GaussIn load_gauss(const gsr_gaussians &g, int64_t i) {
     GaussIn p;
     for (int k = 0; k < 3; ++k) p.mu[k] = (double)g.means[3 * i + k];
-    for (int k = 0; k < 4; ++k) p.q[k] = (double)g.quats[4 * i + k];
-    if (iso) {
+    if constexpr (ISO) {
         const double l = (double)g.log_scales[i];
         p.ls[0] = p.ls[1] = p.ls[2] = l;
+        p.q[0] = 1.0;
+        p.q[1] = p.q[2] = p.q[3] = 0.0;
     } else {
+        for (int k = 0; k < 4; ++k) p.q[k] = (double)g.quats[4 * i + k];
         for (int k = 0; k < 3; ++k) p.ls[k] = (double)g.log_scales[3 * i + k];
     }
     p.logit = (double)g.opacity_logits[i];
@@ -102,10 +107,12 @@ struct Proj {
 };
 
 // Project Gaussian p into view (pose, camera).  Culls: z <= z_near, 255 o <= 1,
-// det(Sigma') <= 0, non-finite values, rectangle outside the image.
-template <bool FULL>
+// det(Sigma') <= 0, non-finite values, rectangle outside the image.  With
+// ISO, Sigma = s^2 I, so M = W Sigma W^T = s^2 I (W is a rotation) and no
+// rotation or covariance product is formed.
+template <bool FULL, bool ISO>
 __device__ __forceinline__ void project(const GaussIn &p, const PoseF64 &pose, const ViewInfo &cam, double z_near,
-                                        double blur, bool iso, Proj &r) {
+                                        double blur, Proj &r) {
     r.visible = false;
     const double *W = pose.W;
     for (int k = 0; k < 3; ++k)
@@ -115,12 +122,11 @@ __device__ __forceinline__ void project(const GaussIn &p, const PoseF64 &pose, c
     if (!(z > z_near)) return;
     r.o = 1.0 / (1.0 + exp(-p.logit));
     if (!(255.0 * r.o > 1.0)) return;
-    for (int k = 0; k < 3; ++k) r.s2[k] = exp(2.0 * p.ls[k]);
-    if (iso) {
-        for (int k = 0; k < 9; ++k) r.Sig[k] = 0.0;
-        r.Sig[0] = r.Sig[4] = r.Sig[8] = r.s2[0];
-        for (int k = 0; k < 9; ++k) r.Rg[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    if constexpr (ISO) {
+        r.s2[0] = r.s2[1] = r.s2[2] = exp(2.0 * p.ls[0]);
+        for (int k = 0; k < 9; ++k) r.M[k] = (k % 4 == 0) ? r.s2[0] : 0.0;
     } else {
+        for (int k = 0; k < 3; ++k) r.s2[k] = exp(2.0 * p.ls[k]);
         quat_to_rot_f64(p.q[0], p.q[1], p.q[2], p.q[3], r.Rg);
         for (int i = 0; i < 3; ++i)
             for (int j = i; j < 3; ++j) {
@@ -129,18 +135,18 @@ __device__ __forceinline__ void project(const GaussIn &p, const PoseF64 &pose, c
                 r.Sig[3 * i + j] = v;
                 r.Sig[3 * j + i] = v;
             }
+        // M = W Sigma W^T
+        double WS[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                WS[3 * i + j] = W[3 * i] * r.Sig[j] + W[3 * i + 1] * r.Sig[3 + j] + W[3 * i + 2] * r.Sig[6 + j];
+        for (int i = 0; i < 3; ++i)
+            for (int j = i; j < 3; ++j) {
+                const double v = WS[3 * i] * W[3 * j] + WS[3 * i + 1] * W[3 * j + 1] + WS[3 * i + 2] * W[3 * j + 2];
+                r.M[3 * i + j] = v;
+                r.M[3 * j + i] = v;
+            }
     }
-    // M = W Sigma W^T
-    double WS[9];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            WS[3 * i + j] = W[3 * i] * r.Sig[j] + W[3 * i + 1] * r.Sig[3 + j] + W[3 * i + 2] * r.Sig[6 + j];
-    for (int i = 0; i < 3; ++i)
-        for (int j = i; j < 3; ++j) {
-            const double v = WS[3 * i] * W[3 * j] + WS[3 * i + 1] * W[3 * j + 1] + WS[3 * i + 2] * W[3 * j + 2];
-            r.M[3 * i + j] = v;
-            r.M[3 * j + i] = v;
-        }
     const double fx = cam.fx, fy = cam.fy;
     const double iz = 1.0 / z;
     r.J[0] = fx * iz; r.J[1] = 0.0; r.J[2] = -fx * x * iz * iz;
@@ -193,9 +199,10 @@ struct ParamGrad {
     double mu[3], q[4], ls[3], logit, rgb[3];
 };
 
+template <bool ISO>
 __device__ __forceinline__ void project_backward(const GaussIn &p, const PoseF64 &pose, const ViewInfo &cam,
-                                                 const Proj &r, const float *g2, bool iso, ParamGrad &pg,
-                                                 double gX[3], double GW[9]) {
+                                                 const Proj &r, const float *g2, ParamGrad &pg, double gX[3],
+                                                 double GW[9]) {
     const double *W = pose.W;
     for (int k = 0; k < 3; ++k) pg.rgb[k] += (double)g2[6 + k];
     pg.logit += (double)g2[5] * r.o * (1.0 - r.o);
@@ -232,6 +239,15 @@ __device__ __forceinline__ void project_backward(const GaussIn &p, const PoseF64
             dmx * fx * x * iz2 - dmy * fy * y * iz2 + dz;
     for (int k = 0; k < 3; ++k) pg.mu[k] += W[k] * gX[0] + W[3 + k] * gX[1] + W[6 + k] * gX[2];
     // M = W Sigma W^T: dSigma = W^T dM W; dW = 2 dM W Sigma (+ gX mu^T from X = W mu + t)
+    if constexpr (ISO) {
+        // Sigma = s^2 I: dW = gX mu^T + 2 s^2 dM W, and dL/dlog s = 2 s^2 tr(W^T dM W) = 2 s^2 tr(dM)
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                GW[3 * i + j] = gX[i] * p.mu[j] + 2.0 * r.s2[0] *
+                                                      (dM[3 * i] * W[j] + dM[3 * i + 1] * W[3 + j] + dM[3 * i + 2] * W[6 + j]);
+        pg.ls[0] += 2.0 * r.s2[0] * (dM[0] + dM[4] + dM[8]);
+        return;
+    } else {
     double WSg[9];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
@@ -246,10 +262,6 @@ __device__ __forceinline__ void project_backward(const GaussIn &p, const PoseF64
     for (int i = 0; i < 3; ++i)   // dS = T1 W
         for (int j = 0; j < 3; ++j)
             dS[3 * i + j] = T1[3 * i] * W[j] + T1[3 * i + 1] * W[3 + j] + T1[3 * i + 2] * W[6 + j];
-    if (iso) {
-        pg.ls[0] += 2.0 * r.s2[0] * (dS[0] + dS[4] + dS[8]);
-        return;
-    }
     // Sigma = Rg diag(s^2) Rg^T
     const double *Rg = r.Rg;
     double dSR[9];   // dS Rg
@@ -265,6 +277,7 @@ __device__ __forceinline__ void project_backward(const GaussIn &p, const PoseF64
     double gq[4];
     rot_grad_to_quat_f64(p.q, dRg, gq);
     for (int k = 0; k < 4; ++k) pg.q[k] += gq[k];
+    }
 }
 
 }  // namespace gsr
