@@ -295,6 +295,111 @@ gsr_status gsr_debug_pixel_state(gsr_ctx *ctx, const gsr_gaussians *g, const gsr
  * (device int32), enqueued on stream.  0 is expected. */
 gsr_status gsr_selftest(gsr_ctx *ctx, int32_t *failures, void *stream);
 
+/* ======================================================================
+ * Optimisation steps around the rasteriser (tracking, mapping, map growth).
+ * Everything below runs on the device from device state: a whole tracking
+ * or mapping loop is enqueued without host round trips and can be captured.
+ * ====================================================================== */
+
+/* Pose update of tracking.  The paper estimates the pose by gradient-based
+ * optimisation of the render loss, updating rotation and translation
+ * separately (tracking section: a rotation-translation decoupled strategy)
+ * but gives no update rule.  This library makes, per iteration and view,
+ * one Adam step (Kingma & Ba 2015, with bias correction) on the raw
+ * quaternion q with dL/dq at a fixed camera centre, and one on the camera
+ * centre C = -R^T t with dL/dC, then sets t = -R(q/|q|) C.  The state is
+ * FP64 on the device; the pose the renderer reads is its FP32 rounding. */
+typedef struct gsr_pose_adam {
+    float lr_rot;  /* step size of the quaternion components */
+    float lr_pos;  /* step size of the camera centre (metres) */
+    float beta1, beta2, eps;
+} gsr_pose_adam;
+
+/* Doubles of optimiser state per view: q 4, C 3, m_q 4, v_q 4, m_C 3, v_C 3, step 1, pad 2. */
+#define GSR_POSE_STATE_DOUBLES 24
+
+/* Starts the state of n_views poses (device quat [V,4], trans [V,3]) in
+ * `state` (device, GSR_POSE_STATE_DOUBLES * n_views doubles): C = -R^T t,
+ * zero moments, step 0.  EINVAL on NULL pointers or n_views outside
+ * [1, GSR_MAX_VIEWS]. */
+gsr_status gsr_pose_opt_init(gsr_ctx *ctx, int32_t n_views, const float *quat, const float *trans, double *state,
+                             void *stream);
+
+/* One step from the decoupled gradients dq_c [V,4] and dc [V,3] (device, as
+ * written by the backward); rewrites quat and trans (device) from the new
+ * state. */
+gsr_status gsr_pose_opt_step(gsr_ctx *ctx, int32_t n_views, const float *dq_c, const float *dc,
+                             const gsr_pose_adam *hp, double *state, float *quat, float *trans, void *stream);
+
+/* The tracking loop: `iters` times render + loss + pose gradients
+ * (gsr_render_loss_grad with GSR_NO_GAUSS_GRADS, at the tile shape resolved
+ * as there), then gsr_pose_opt_step, all enqueued on `stream`.  quat/trans
+ * (device) hold the start pose and receive the optimised one; `state` must
+ * have been started by gsr_pose_opt_init.  pg must provide dq_c and dc
+ * (scratch for every iteration; dq_t and dt are optional).  loss [V] holds
+ * the last iteration's loss; loss_hist (device, optional) receives every
+ * iteration's, [iters, V].  After the loop, gsr_read_counters reports an
+ * overflow if the pair capacity was exceeded in any iteration. */
+gsr_status gsr_track(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views, float *quat,
+                     float *trans, const gsr_options *opts, const gsr_targets *targets, gsr_workspace ws,
+                     gsr_images out, double *loss, gsr_pose_grads *pg, const gsr_pose_adam *hp, double *state,
+                     int32_t iters, double *loss_hist, void *stream);
+
+/* gsr_track captured into one graph (replayed with gsr_graph_launch; every
+ * replay continues from the state and pose it finds). */
+gsr_status gsr_track_capture(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
+                             float *quat, float *trans, const gsr_options *opts, const gsr_targets *targets,
+                             gsr_workspace ws, gsr_images out, double *loss, gsr_pose_grads *pg,
+                             const gsr_pose_adam *hp, double *state, int32_t iters, double *loss_hist, void *stream,
+                             int32_t *graph_id);
+
+/* Mapping step (scene optimisation section: the map's Gaussian parameters
+ * are refined by gradient-based optimisation with the poses fixed): Adam
+ * over every raw parameter array, each with its own step size. */
+typedef struct gsr_map_adam {
+    float lr_means, lr_quats, lr_log_scales, lr_opacity, lr_rgb;
+    float beta1, beta2, eps;
+} gsr_map_adam;
+
+/* Mutable parameter arrays (device), layout as gsr_gaussians. */
+typedef struct gsr_gaussians_rw {
+    int64_t n;
+    float *means, *quats, *log_scales, *opacity_logits, *rgb;
+} gsr_gaussians_rw;
+
+/* Bytes of mapping optimiser state for n Gaussians: a 256-byte header
+ * (step count) and the two moment arrays, each segment 256-byte aligned. */
+size_t gsr_map_state_size(int64_t n, int32_t isotropic);
+
+/* Zeroes the state (device, gsr_map_state_size bytes). */
+gsr_status gsr_map_opt_init(gsr_ctx *ctx, int64_t n, int32_t isotropic, void *state, void *stream);
+
+/* One Adam step: params -= f(grads) in place, moments and step updated in
+ * `state`.  grads is laid out as params (for example the output of
+ * gsr_backward); a NULL array in params is skipped (its gradient must then
+ * be NULL too).  FP32 arithmetic.  With isotropic, quats may be NULL. */
+gsr_status gsr_map_opt_step(gsr_ctx *ctx, gsr_gaussians_rw params, const gsr_gaussian_grads *grads,
+                            int32_t isotropic, const gsr_map_adam *hp, void *state, void *stream);
+
+/* New Gaussians from one RGB-D frame (initialisation section: one Gaussian
+ * per pixel at the point unprojected with the pixel's depth, with the
+ * pixel's colour, opacity 0.5 and a radius of one pixel, depth / focal
+ * length, with f = (fx + fy) / 2; identity rotation).  A pixel qualifies if
+ * its depth is > 0 and, when sil is given (the rendered silhouette of the
+ * map at this pose), sil < sil_thresh: the regions the map does not cover
+ * yet.  Pixels are taken in raster order; the k-th qualifying one is
+ * written to row offset + k of `out` if that row is < capacity (out.n is
+ * not read).  *n_new (device int64) receives the number of qualifying
+ * pixels, written or not (-1 if an internal wait gave up: never expected).
+ * quat [4], trans [3] (device) give the frame's world-to-camera pose;
+ * rgb [3,H*W] planar, depth [H*W], sil [H*W] or NULL (device).  `work`
+ * (device, gsr_densify_work_size bytes) is scratch. */
+size_t gsr_densify_work_size(int32_t width, int32_t height);
+gsr_status gsr_densify(gsr_ctx *ctx, gsr_camera cam, const float *quat, const float *trans, const float *rgb,
+                       const float *depth, const float *sil, float sil_thresh, gsr_gaussians_rw out,
+                       int32_t isotropic, int64_t offset, int64_t capacity, int64_t *n_new, void *work,
+                       size_t work_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

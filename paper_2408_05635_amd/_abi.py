@@ -57,10 +57,31 @@ class Workspace(C.Structure):
     _fields_ = [("ptr", _vp), ("bytes", C.c_size_t), ("pair_capacity", C.c_int64)]
 
 
+GSR_POSE_STATE_DOUBLES = 24
+
+
+class PoseAdam(C.Structure):
+    _fields_ = [("lr_rot", C.c_float), ("lr_pos", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float)]
+
+
+class MapAdam(C.Structure):
+    _fields_ = [("lr_means", C.c_float), ("lr_quats", C.c_float), ("lr_log_scales", C.c_float),
+                ("lr_opacity", C.c_float), ("lr_rgb", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float)]
+
+
+class GaussiansRW(C.Structure):
+    _fields_ = [("n", C.c_int64), ("means", _vp), ("quats", _vp), ("log_scales", _vp),
+                ("opacity_logits", _vp), ("rgb", _vp)]
+
+
 EXPORTS = ["gsr_create", "gsr_destroy", "gsr_last_error", "gsr_workspace_size", "gsr_forward", "gsr_backward",
            "gsr_render_loss_grad", "gsr_read_counters", "gsr_read_work", "gsr_set_timing", "gsr_read_timing",
            "gsr_debug_binning", "gsr_debug_pixel_state", "gsr_selftest", "gsr_autotune", "gsr_set_tile",
-           "gsr_graph_capture", "gsr_graph_launch", "gsr_graph_destroy"]
+           "gsr_graph_capture", "gsr_graph_launch", "gsr_graph_destroy", "gsr_pose_opt_init", "gsr_pose_opt_step",
+           "gsr_track", "gsr_track_capture", "gsr_map_state_size", "gsr_map_opt_init", "gsr_map_opt_step",
+           "gsr_densify_work_size", "gsr_densify"]
 
 _lib = None
 
@@ -118,6 +139,27 @@ def load() -> C.CDLL:
     lib.gsr_graph_destroy.restype = st
     lib.gsr_selftest.argtypes = [_vp, _vp, _vp]
     lib.gsr_selftest.restype = st
+    lib.gsr_pose_opt_init.argtypes = [_vp, C.c_int32, _vp, _vp, _vp, _vp]
+    lib.gsr_pose_opt_init.restype = st
+    lib.gsr_pose_opt_step.argtypes = [_vp, C.c_int32, _vp, _vp, P(PoseAdam), _vp, _vp, _vp, _vp]
+    lib.gsr_pose_opt_step.restype = st
+    track_args = [_vp, P(Gaussians), P(Camera), C.c_int32, _vp, _vp, P(Options), P(Targets), Workspace, Images, _vp,
+                  P(PoseGrads), P(PoseAdam), _vp, C.c_int32, _vp, _vp]
+    lib.gsr_track.argtypes = track_args
+    lib.gsr_track.restype = st
+    lib.gsr_track_capture.argtypes = track_args + [P(C.c_int32)]
+    lib.gsr_track_capture.restype = st
+    lib.gsr_map_state_size.argtypes = [C.c_int64, C.c_int32]
+    lib.gsr_map_state_size.restype = C.c_size_t
+    lib.gsr_map_opt_init.argtypes = [_vp, C.c_int64, C.c_int32, _vp, _vp]
+    lib.gsr_map_opt_init.restype = st
+    lib.gsr_map_opt_step.argtypes = [_vp, GaussiansRW, P(GaussGrads), C.c_int32, P(MapAdam), _vp, _vp]
+    lib.gsr_map_opt_step.restype = st
+    lib.gsr_densify_work_size.argtypes = [C.c_int32, C.c_int32]
+    lib.gsr_densify_work_size.restype = C.c_size_t
+    lib.gsr_densify.argtypes = [_vp, Camera, _vp, _vp, _vp, _vp, _vp, C.c_float, GaussiansRW, C.c_int32, C.c_int64,
+                                C.c_int64, _vp, _vp, C.c_size_t, _vp]
+    lib.gsr_densify.restype = st
     _lib = lib
     return lib
 

@@ -31,6 +31,7 @@
 #include "gsr_common.hpp"
 #include "gsr_project.hpp"
 #include "gsr_scan_sort.hpp"
+#include "gsr_optim.hpp"
 
 using namespace gsr;
 
@@ -298,7 +299,7 @@ T *at(const gsr_workspace &ws, size_t off) {
 // Call setup: view table, FP64 poses, zero counters (block 0), and a cleared
 // synchronisation region (all blocks).
 __global__ void k_setup(ViewTable tab, ViewTable *vt, const float *__restrict__ pq, const float *__restrict__ pt,
-                        PoseF64 *poses, int64_t *counters, uint4 *sync, int64_t sync16) {
+                        PoseF64 *poses, int64_t *counters, uint4 *sync, int64_t sync16, bool keep_sticky) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < sync16; k += (int64_t)gridDim.x * blockDim.x)
         sync[k] = make_uint4(0u, 0u, 0u, 0u);
     if (blockIdx.x != 0) return;
@@ -307,7 +308,7 @@ __global__ void k_setup(ViewTable tab, ViewTable *vt, const float *__restrict__ 
     const int32_t *src = reinterpret_cast<const int32_t *>(&tab);
     int32_t *dst = reinterpret_cast<int32_t *>(vt);
     for (int k = t; k < words; k += blockDim.x) dst[k] = src[k];
-    if (t < kNumCounters) counters[t] = 0;
+    if (t < kNumCounters && !(keep_sticky && t == kCntOverflowAny)) counters[t] = 0;
     if (t < tab.n_views) {
         PoseF64 p;
         quat_to_rot_f64(pq[4 * t], pq[4 * t + 1], pq[4 * t + 2], pq[4 * t + 3], p.W);
@@ -468,6 +469,7 @@ __global__ void k_check_capacity(int64_t *counters, int64_t cap) {
     const int64_t K = counters[kCntPairs];
     counters[kCntPairsUsed] = K <= cap ? K : 0;
     counters[kCntOverflow] = K <= cap ? 0 : 1;
+    if (K > cap) counters[kCntOverflowAny] = 1;
 }
 
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t val) {
@@ -773,6 +775,7 @@ unsigned grid_for(int64_t n, int threads, int64_t max_blocks = 65536) {
 
 struct Call {
     bool count;
+    bool keep_sticky = false;   // inside a tracking loop after its first iteration
     gsr_ctx *ctx;
     ViewTable tab;
     Layout L;
@@ -834,7 +837,7 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     const int64_t sync16 = (int64_t)(L.sync_bytes / 16);
     hipLaunchKernelGGL(k_setup, dim3((unsigned)std::min<int64_t>(std::max<int64_t>((sync16 + 255) / 256, 1), 1024)),
                        dim3(256), 0, st, c.tab, vt, views->quat, views->trans, poses, counters,
-                       reinterpret_cast<uint4 *>(sync), sync16);
+                       reinterpret_cast<uint4 *>(sync), sync16, c.keep_sticky);
     if (L.vn > 0) {
         hipLaunchKernelGGL(c.pp.iso ? k_project_count<true> : k_project_count<false>,
                            dim3(grid_for(c.pp.n, 256, 1ll << 30)), dim3(256), 0, st, c.pp, vt,
@@ -978,10 +981,11 @@ gsr_status finish(Call &c, const char *what) {
 gsr_status render_loss_grad_impl(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views,
                                  const gsr_options *opts, const gsr_targets *targets, gsr_workspace ws,
                                  gsr_images out, double *loss, gsr_gaussian_grads *gg, gsr_pose_grads *pg,
-                                 void *stream) {
+                                 void *stream, bool keep_sticky = false) {
     Call c;
     gsr_status s = prepare(ctx, g, views, opts, ws, stream, c);
     if (s != GSR_OK) return s;
+    c.keep_sticky = keep_sticky;
     if (!out.rgb || !out.depth || !out.sil) return fail(ctx, GSR_EINVAL, "output images must not be NULL");
     if (!targets || !targets->rgb || !targets->depth) return fail(ctx, GSR_EINVAL, "targets rgb and depth are required");
     if (!loss) return fail(ctx, GSR_EINVAL, "loss must not be NULL");
@@ -1006,6 +1010,34 @@ gsr_status render_loss_grad_impl(gsr_ctx *ctx, const gsr_gaussians *g, const gsr
     return finish(c, "gsr_render_loss_grad launch");
 }
 
+
+// The tracking loop (enqueue only): iters x (render + loss + pose gradients,
+// decoupled Adam step).
+gsr_status track_impl(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int32_t V, float *quat,
+                      float *trans, const gsr_options *opts, const gsr_targets *targets, gsr_workspace ws,
+                      gsr_images out, double *loss, gsr_pose_grads *pg, const gsr_pose_adam *hp, double *state,
+                      int32_t iters, double *loss_hist, void *stream) {
+    if (!ctx) return GSR_EINVAL;
+    if (!g || !cams || !opts || !hp || !state || !quat || !trans || !pg || !pg->dq_c || !pg->dc)
+        return fail(ctx, GSR_EINVAL, "track: NULL argument (g, cams, opts, hp, state, quat, trans, pg->dq_c, pg->dc)");
+    if (iters < 0) return fail(ctx, GSR_EINVAL, "track: iters must be >= 0 (got %d)", iters);
+    if (V < 1 || V > GSR_MAX_VIEWS) return fail(ctx, GSR_EINVAL, "track: n_views must be in [1, %d]", GSR_MAX_VIEWS);
+    const gsr_views views{V, cams, quat, trans};
+    gsr_options o = *opts;
+    o.flags |= GSR_NO_GAUSS_GRADS;
+    o = resolve_tile(ctx, g->n, &views, &o);
+    gsr_status s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    for (int32_t it = 0; it < iters && s == GSR_OK; ++it) {
+        s = render_loss_grad_impl(ctx, g, &views, &o, targets, ws, out, loss, nullptr, pg, stream, it > 0);
+        if (s != GSR_OK) break;
+        hipLaunchKernelGGL(k_pose_opt_step, dim3(1), dim3(64), 0, st, V, (const float *)pg->dq_c,
+                           (const float *)pg->dc, *hp, reinterpret_cast<PoseOptState *>(state), quat, trans,
+                           (const double *)loss, loss_hist ? loss_hist + (size_t)it * V : nullptr);
+        s = check_hip(ctx, hipGetLastError(), "gsr_track launch");
+    }
+    return s;
+}
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1272,7 +1304,7 @@ gsr_status gsr_read_counters(gsr_ctx *ctx, gsr_workspace ws, void *stream, int64
     if (s != GSR_OK) return s;
     if (n_visible) *n_visible = h[kCntVisible];
     if (n_pairs) *n_pairs = h[kCntPairs];
-    if (overflow) *overflow = (int32_t)h[kCntOverflow];
+    if (overflow) *overflow = (int32_t)(h[kCntOverflow] | h[kCntOverflowAny]);
     if (h[kCntSyncError] != 0)
         return fail(ctx, GSR_EHIP, "%lld waits between blocks of the binning gave up; outputs are undefined",
                     (long long)h[kCntSyncError]);
@@ -1387,4 +1419,200 @@ gsr_status gsr_selftest(gsr_ctx *ctx, int32_t *failures, void *stream) {
     return check_hip(ctx, hipGetLastError(), "gsr_selftest launch");
 }
 
+
+// ---------------------------------------------------------------------------
+// optimisation steps
+// ---------------------------------------------------------------------------
+
+gsr_status gsr_pose_opt_init(gsr_ctx *ctx, int32_t n_views, const float *quat, const float *trans, double *state,
+                             void *stream) {
+    if (!ctx) return GSR_EINVAL;
+    if (!quat || !trans || !state) return fail(ctx, GSR_EINVAL, "pose_opt_init: NULL argument");
+    if (n_views < 1 || n_views > GSR_MAX_VIEWS)
+        return fail(ctx, GSR_EINVAL, "pose_opt_init: n_views must be in [1, %d]", GSR_MAX_VIEWS);
+    gsr_status s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (s != GSR_OK) return s;
+    hipLaunchKernelGGL(k_pose_opt_init, dim3(1), dim3(64), 0, (hipStream_t)stream, n_views, quat, trans,
+                       reinterpret_cast<PoseOptState *>(state));
+    return check_hip(ctx, hipGetLastError(), "gsr_pose_opt_init launch");
+}
+
+gsr_status gsr_pose_opt_step(gsr_ctx *ctx, int32_t n_views, const float *dq_c, const float *dc,
+                             const gsr_pose_adam *hp, double *state, float *quat, float *trans, void *stream) {
+    if (!ctx) return GSR_EINVAL;
+    if (!dq_c || !dc || !hp || !state || !quat || !trans) return fail(ctx, GSR_EINVAL, "pose_opt_step: NULL argument");
+    if (n_views < 1 || n_views > GSR_MAX_VIEWS)
+        return fail(ctx, GSR_EINVAL, "pose_opt_step: n_views must be in [1, %d]", GSR_MAX_VIEWS);
+    gsr_status s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (s != GSR_OK) return s;
+    hipLaunchKernelGGL(k_pose_opt_step, dim3(1), dim3(64), 0, (hipStream_t)stream, n_views, dq_c, dc, *hp,
+                       reinterpret_cast<PoseOptState *>(state), quat, trans, (const double *)nullptr,
+                       (double *)nullptr);
+    return check_hip(ctx, hipGetLastError(), "gsr_pose_opt_step launch");
+}
+
+gsr_status gsr_track(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views, float *quat,
+                     float *trans, const gsr_options *opts, const gsr_targets *targets, gsr_workspace ws,
+                     gsr_images out, double *loss, gsr_pose_grads *pg, const gsr_pose_adam *hp, double *state,
+                     int32_t iters, double *loss_hist, void *stream) {
+    return track_impl(ctx, g, cams, n_views, quat, trans, opts, targets, ws, out, loss, pg, hp, state, iters,
+                      loss_hist, stream);
+}
+
+gsr_status gsr_track_capture(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int32_t n_views,
+                             float *quat, float *trans, const gsr_options *opts, const gsr_targets *targets,
+                             gsr_workspace ws, gsr_images out, double *loss, gsr_pose_grads *pg,
+                             const gsr_pose_adam *hp, double *state, int32_t iters, double *loss_hist, void *stream,
+                             int32_t *graph_id) {
+    if (!ctx) return GSR_EINVAL;
+    if (!graph_id) return fail(ctx, GSR_EINVAL, "graph_id must not be NULL");
+    if (!stream) return fail(ctx, GSR_EINVAL, "graph capture needs a stream other than the null stream");
+    // validate before the capture starts (one render's worth of checks)
+    if (!g || !cams || !opts || n_views < 1 || n_views > GSR_MAX_VIEWS)
+        return fail(ctx, GSR_EINVAL, "track_capture: bad arguments");
+    {
+        const gsr_views views{n_views, cams, quat, trans};
+        gsr_options o = *opts;
+        o.flags |= GSR_NO_GAUSS_GRADS;
+        o = resolve_tile(ctx, g->n, &views, &o);
+        Call c;
+        const gsr_status sv = prepare(ctx, g, &views, &o, ws, stream, c);
+        if (sv != GSR_OK) return sv;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    gsr_status s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (s != GSR_OK) return s;
+    s = check_hip(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    if (s != GSR_OK) return s;
+    ctx->capturing = true;
+    const gsr_status s_call = track_impl(ctx, g, cams, n_views, quat, trans, opts, targets, ws, out, loss, pg, hp,
+                                         state, iters, loss_hist, stream);
+    ctx->capturing = false;
+    hipGraph_t graph = nullptr;
+    s = check_hip(ctx, hipStreamEndCapture(st, &graph), "hipStreamEndCapture");
+    if (s_call != GSR_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s_call;
+    }
+    if (s != GSR_OK) return s;
+    hipGraphExec_t exec = nullptr;
+    s = check_hip(ctx, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    (void)hipGraphDestroy(graph);
+    if (s != GSR_OK) return s;
+    const int32_t id = ctx->next_graph++;
+    ctx->graphs[id] = exec;
+    *graph_id = id;
+    return GSR_OK;
+}
+
+namespace {
+// Moment-array layout of the mapping state: segment k of both arrays starts
+// at moff[k] floats (256-byte aligned); returns the floats of one array.
+int64_t map_layout(int64_t n, bool iso, int64_t moff[kMapSegs], int64_t cnt[kMapSegs]) {
+    const int64_t per[kMapSegs] = {3, 4, iso ? 1 : 3, 1, 3};
+    int64_t off = 0;
+    for (int k = 0; k < kMapSegs; ++k) {
+        cnt[k] = (k == 1 && iso) ? 0 : per[k] * n;
+        moff[k] = off;
+        off += (cnt[k] + (int64_t)kMapAlign - 1) / (int64_t)kMapAlign * (int64_t)kMapAlign;
+    }
+    return off;
+}
+}  // namespace
+
+size_t gsr_map_state_size(int64_t n, int32_t isotropic) {
+    if (n < 0) return 0;
+    int64_t moff[kMapSegs], cnt[kMapSegs];
+    return kMapHeader + 2 * sizeof(float) * (size_t)map_layout(n, isotropic != 0, moff, cnt);
+}
+
+gsr_status gsr_map_opt_init(gsr_ctx *ctx, int64_t n, int32_t isotropic, void *state, void *stream) {
+    if (!ctx) return GSR_EINVAL;
+    if (!state || n < 0) return fail(ctx, GSR_EINVAL, "map_opt_init: NULL state or n < 0");
+    gsr_status s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (s != GSR_OK) return s;
+    const int64_t words = (int64_t)(gsr_map_state_size(n, isotropic) / 4);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(words, 256, 65536)), dim3(256), 0, (hipStream_t)stream,
+                       (uint32_t *)state, words, 0u);
+    return check_hip(ctx, hipGetLastError(), "gsr_map_opt_init launch");
+}
+
+gsr_status gsr_map_opt_step(gsr_ctx *ctx, gsr_gaussians_rw params, const gsr_gaussian_grads *grads,
+                            int32_t isotropic, const gsr_map_adam *hp, void *state, void *stream) {
+    if (!ctx) return GSR_EINVAL;
+    if (!grads || !hp || !state) return fail(ctx, GSR_EINVAL, "map_opt_step: NULL argument");
+    if (params.n < 0) return fail(ctx, GSR_EINVAL, "map_opt_step: n must be >= 0");
+    const bool iso = isotropic != 0;
+    float *xs[kMapSegs] = {params.means, iso ? nullptr : params.quats, params.log_scales, params.opacity_logits,
+                           params.rgb};
+    const float *gs[kMapSegs] = {grads->means, iso ? nullptr : grads->quats, grads->log_scales,
+                                 grads->opacity_logits, grads->rgb};
+    const float lrs[kMapSegs] = {hp->lr_means, hp->lr_quats, hp->lr_log_scales, hp->lr_opacity, hp->lr_rgb};
+    int64_t moff[kMapSegs], cnt[kMapSegs];
+    const int64_t per_array = map_layout(params.n, iso, moff, cnt);
+    MapSegs segs;
+    int64_t most = 0;
+    for (int k = 0; k < kMapSegs; ++k) {
+        if ((xs[k] == nullptr) != (gs[k] == nullptr))
+            return fail(ctx, GSR_EINVAL, "map_opt_step: parameter array %d and its gradient must both be given", k);
+        segs.s[k] = MapSeg{xs[k], gs[k], xs[k] ? cnt[k] : 0, moff[k], lrs[k]};
+        most = std::max(most, segs.s[k].count);
+    }
+    gsr_status s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (s != GSR_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    MapHeader *h = reinterpret_cast<MapHeader *>(state);
+    float *m = reinterpret_cast<float *>(static_cast<char *>(state) + kMapHeader);
+    float *v = m + per_array;
+    hipLaunchKernelGGL(k_map_opt_begin, dim3(1), dim3(64), 0, st, h, hp->beta1, hp->beta2);
+    if (most > 0) {
+        const unsigned gx = grid_for((most + 3) / 4, 256, 4096);
+        hipLaunchKernelGGL(k_map_opt_step, dim3(gx, kMapSegs), dim3(256), 0, st, segs, m, v, (const MapHeader *)h,
+                           hp->beta1, hp->beta2, hp->eps);
+    }
+    return check_hip(ctx, hipGetLastError(), "gsr_map_opt_step launch");
+}
+
+size_t gsr_densify_work_size(int32_t width, int32_t height) {
+    if (width < 1 || height < 1) return 0;
+    const int64_t P = (int64_t)width * height;
+    const int64_t nb = (P + kChunk - 1) / kChunk;
+    return kSyncTickets + align_up(8 * (size_t)nb) + 256;   // tickets, look-back words, pose (12 doubles), error
+}
+
+gsr_status gsr_densify(gsr_ctx *ctx, gsr_camera cam, const float *quat, const float *trans, const float *rgb,
+                       const float *depth, const float *sil, float sil_thresh, gsr_gaussians_rw out,
+                       int32_t isotropic, int64_t offset, int64_t capacity, int64_t *n_new, void *work,
+                       size_t work_bytes, void *stream) {
+    if (!ctx) return GSR_EINVAL;
+    if (!quat || !trans || !rgb || !depth || !n_new || !work)
+        return fail(ctx, GSR_EINVAL, "densify: NULL argument (quat, trans, rgb, depth, n_new, work)");
+    if (cam.width < 1 || cam.height < 1 || cam.width > 16384 || cam.height > 16384)
+        return fail(ctx, GSR_EINVAL, "densify: image size %dx%d out of range", cam.width, cam.height);
+    if (!(cam.fx > 0.0f) || !(cam.fy > 0.0f)) return fail(ctx, GSR_EINVAL, "densify: focal lengths must be > 0");
+    if (offset < 0 || capacity < offset) return fail(ctx, GSR_EINVAL, "densify: need 0 <= offset <= capacity");
+    const bool iso = isotropic != 0;
+    if (capacity > offset && (!out.means || !out.log_scales || !out.opacity_logits || !out.rgb || (!iso && !out.quats)))
+        return fail(ctx, GSR_EINVAL, "densify: output arrays must not be NULL");
+    const size_t need = gsr_densify_work_size(cam.width, cam.height);
+    if (work_bytes < need) return fail(ctx, GSR_EINVAL, "densify: work needs %zu bytes (got %zu)", need, work_bytes);
+    gsr_status s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (s != GSR_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t P = (int64_t)cam.width * cam.height;
+    char *w = static_cast<char *>(work);
+    const size_t sync_bytes = kSyncTickets + align_up(8 * (size_t)((P + kChunk - 1) / kChunk));
+    double *Rt = reinterpret_cast<double *>(w + sync_bytes);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for((int64_t)(sync_bytes / 4), 256, 4096)), dim3(256), 0, st,
+                       (uint32_t *)w, (int64_t)(sync_bytes / 4), 0u);
+    hipLaunchKernelGGL(k_densify_setup, dim3(1), dim3(64), 0, st, quat, trans, Rt);
+    int64_t *err = reinterpret_cast<int64_t *>(Rt + 12);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)err, (int64_t)2, 0u);
+    SyncState ss{reinterpret_cast<uint32_t *>(w), reinterpret_cast<uint64_t *>(w + kSyncTickets), err};
+    NewSink sink{cam, Rt, rgb, depth, P, offset, capacity, out.means, iso ? nullptr : out.quats, out.log_scales,
+                 out.opacity_logits, out.rgb, iso};
+    scan_exclusive(NewSrc{depth, sil, sil_thresh}, sink, nullptr, P, ss, 0u, n_new, st);
+    hipLaunchKernelGGL(k_densify_finish, dim3(1), dim3(64), 0, st, (const int64_t *)err, n_new);
+    return check_hip(ctx, hipGetLastError(), "gsr_densify launch");
+}
 }  // extern "C"

@@ -59,6 +59,36 @@ class GaussianParams:
         return (self.means, self.quats, self.log_scales, self.opacity_logits, self.rgb)
 
 
+@dataclass
+class PoseAdam:
+    """Step sizes of the decoupled pose update (quaternion, camera centre in metres)."""
+    lr_rot: float = 2e-3
+    lr_pos: float = 2e-3
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+
+    def c(self) -> _abi.PoseAdam:
+        return _abi.PoseAdam(self.lr_rot, self.lr_pos, self.beta1, self.beta2, self.eps)
+
+
+@dataclass
+class MapAdam:
+    """Step sizes of the map update, one per raw parameter array."""
+    lr_means: float = 1e-4
+    lr_quats: float = 1e-3
+    lr_log_scales: float = 1e-3
+    lr_opacity: float = 5e-2
+    lr_rgb: float = 2.5e-3
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-15
+
+    def c(self) -> _abi.MapAdam:
+        return _abi.MapAdam(self.lr_means, self.lr_quats, self.lr_log_scales, self.lr_opacity, self.lr_rgb,
+                            self.beta1, self.beta2, self.eps)
+
+
 def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else C.c_void_p(t.data_ptr())
 
@@ -411,6 +441,123 @@ class Rasterizer:
         _abi.check(_ABI.gsr_debug_pixel_state(self._ctx, C.byref(gs), C.byref(views), C.byref(o), ws, _ptr(t_final),
                                               _ptr(n_last), _ptr(hsh), _stream_ptr()), self._ctx)
         return dict(t_final=t_final, n_last=n_last, hash=hsh)
+
+    # ------------------------------------------------------------------ optimisation steps
+    def pose_opt_init(self, quat: torch.Tensor, trans: torch.Tensor) -> torch.Tensor:
+        """Optimiser state [V, GSR_POSE_STATE_DOUBLES] (float64) for the poses."""
+        V = int(quat.shape[0])
+        _check_f32("pose quat", quat, (V, 4), self.device)
+        _check_f32("pose trans", trans, (V, 3), self.device)
+        state = torch.empty(V, _abi.GSR_POSE_STATE_DOUBLES, dtype=torch.float64, device=self.device)
+        _abi.check(_ABI.gsr_pose_opt_init(self._ctx, V, _ptr(quat), _ptr(trans), _ptr(state), _stream_ptr()),
+                   self._ctx)
+        return state
+
+    def pose_opt_step(self, state: torch.Tensor, dq_c: torch.Tensor, dc: torch.Tensor, quat: torch.Tensor,
+                      trans: torch.Tensor, hp: PoseAdam = PoseAdam()) -> None:
+        """One decoupled step; rewrites quat and trans in place."""
+        V = int(quat.shape[0])
+        for name, t, shp in (("dq_c", dq_c, (V, 4)), ("dc", dc, (V, 3)), ("pose quat", quat, (V, 4)),
+                             ("pose trans", trans, (V, 3))):
+            _check_f32(name, t, shp, self.device)
+        hpc = hp.c()
+        _abi.check(_ABI.gsr_pose_opt_step(self._ctx, V, _ptr(dq_c), _ptr(dc), C.byref(hpc), _ptr(state), _ptr(quat),
+                                          _ptr(trans), _stream_ptr()), self._ctx)
+
+    def _track_args(self, g, quat, trans, cams, targets, opts, hp, state, iters, out, hist):
+        a = self._fused_args(g, quat, trans, cams, targets, opts, out)
+        ws = self._shared_ws(g.n, a["views"], self._opts(opts, g.isotropic, gauss_grads=False))
+        hpc = hp.c()
+        args = [self._ctx, C.byref(a["gs"]), a["views"].cams, len(cams), _ptr(quat), _ptr(trans), C.byref(a["o"]),
+                C.byref(a["tg"]), ws, a["imgs"], _ptr(out["loss"]), C.byref(a["pg"]), C.byref(hpc), _ptr(state),
+                int(iters), _ptr(hist), _stream_ptr()]
+        return args, (a, hpc, ws)
+
+    def track(self, g: GaussianParams, quat: torch.Tensor, trans: torch.Tensor, cams: Sequence, targets: dict,
+              opts: RenderOptions = RenderOptions(), hp: PoseAdam = PoseAdam(), iters: int = 40,
+              state: Optional[torch.Tensor] = None, capture: bool = False, out: Optional[dict] = None):
+        """The tracking loop on the device: `iters` x (render + loss + pose
+        gradients, decoupled Adam step).  quat/trans are updated in place.
+        Returns dict(loss_hist [iters, V] float64, state, out, graph (id or None)).
+        Eagerly, the pair capacity is checked after the loop and the loop is
+        re-run from its start if any iteration overflowed it; with capture=True
+        the loop is captured (not run) and the caller checks read_counters after
+        replays."""
+        V = len(cams)
+        P = total_pixels(cams)
+        opts = RenderOptions(**{**opts.__dict__, "gauss_grads": False, "pose_grads": True})
+        if out is None:
+            out = self.alloc_outputs(g, V, P, opts)
+        if state is None:
+            state = self.pose_opt_init(quat, trans)
+        hist = torch.zeros(max(iters, 1), V, dtype=torch.float64, device=self.device)
+        self.render_loss_grad(g, quat, trans, cams, targets, opts, check=True, out=out)   # size the capacity
+        if capture:
+            args, keep = self._track_args(g, quat, trans, cams, targets, opts, hp, state, iters, out, hist)
+            gid = C.c_int32()
+            _abi.check(_ABI.gsr_track_capture(*args, C.byref(gid)), self._ctx)
+            self._graph_refs = getattr(self, "_graph_refs", {})
+            self._graph_refs[gid.value] = (keep, out, hist, state, self._ws)
+            return dict(loss_hist=hist[:iters], state=state, out=out, graph=gid.value)
+        q0, t0, s0 = quat.clone(), trans.clone(), state.clone()
+        while True:
+            args, keep = self._track_args(g, quat, trans, cams, targets, opts, hp, state, iters, out, hist)
+            _abi.check(_ABI.gsr_track(*args), self._ctx)
+            _, k, ovf = self.read_counters(keep[2])
+            if not ovf:
+                break
+            self._grow(k)
+            quat.copy_(q0)
+            trans.copy_(t0)
+            state.copy_(s0)
+        return dict(loss_hist=hist[:iters], state=state, out=out, graph=None)
+
+    def map_opt_init(self, g: GaussianParams) -> torch.Tensor:
+        """Zeroed mapping optimiser state (bytes) for g."""
+        nbytes = int(_ABI.gsr_map_state_size(g.n, int(g.isotropic)))
+        state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        _abi.check(_ABI.gsr_map_opt_init(self._ctx, g.n, int(g.isotropic), _ptr(state), _stream_ptr()), self._ctx)
+        return state
+
+    def map_opt_step(self, g: GaussianParams, grads: dict, state: torch.Tensor, hp: MapAdam = MapAdam()) -> None:
+        """One Adam step over g's arrays in place; grads holds g_means, g_quats,
+        g_log_scales, g_opacity_logits, g_rgb (as returned by the backward)."""
+        self._gauss(g)
+        keys = ("means", "quats", "log_scales", "opacity_logits", "rgb")
+        for k in keys:
+            _check_f32("g_" + k, grads["g_" + k], tuple(getattr(g, k).shape), self.device)
+        rw = _abi.GaussiansRW(g.n, *[_ptr(getattr(g, k)) for k in keys])
+        gg = _abi.GaussGrads(*[_ptr(grads["g_" + k]) for k in keys])
+        hpc = hp.c()
+        _abi.check(_ABI.gsr_map_opt_step(self._ctx, rw, C.byref(gg), int(g.isotropic), C.byref(hpc), _ptr(state),
+                                         _stream_ptr()), self._ctx)
+
+    def densify(self, cam, quat: torch.Tensor, trans: torch.Tensor, rgb: torch.Tensor, depth: torch.Tensor,
+                sil: Optional[torch.Tensor], out: GaussianParams, offset: int, sil_thresh: float = 0.5,
+                n_new: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """New Gaussians from one RGB-D frame written into rows offset.. of
+        `out` (its row count is the capacity).  Returns the device count
+        (int64 [1]) of qualifying pixels, written or not."""
+        P = int(cam.width) * int(cam.height)
+        _check_f32("quat", quat, (4,), self.device)
+        _check_f32("trans", trans, (3,), self.device)
+        _check_f32("rgb", rgb, (3 * P,), self.device)
+        _check_f32("depth", depth, (P,), self.device)
+        if sil is not None:
+            _check_f32("sil", sil, (P,), self.device)
+        self._gauss(out)
+        if n_new is None:
+            n_new = torch.zeros(1, dtype=torch.int64, device=self.device)
+        wb = int(_ABI.gsr_densify_work_size(int(cam.width), int(cam.height)))
+        work = torch.empty(wb, dtype=torch.uint8, device=self.device)
+        camc = _abi.Camera(int(cam.width), int(cam.height), float(cam.fx), float(cam.fy), float(cam.cx),
+                           float(cam.cy))
+        rw = _abi.GaussiansRW(out.n, *[_ptr(t) for t in out.tensors()])
+        _abi.check(_ABI.gsr_densify(self._ctx, camc, _ptr(quat), _ptr(trans), _ptr(rgb), _ptr(depth), _ptr(sil),
+                                    float(sil_thresh), rw, int(out.isotropic), int(offset), int(out.n), _ptr(n_new),
+                                    _ptr(work), wb, _stream_ptr()), self._ctx)
+        self._densify_keep = work
+        return n_new
 
     def selftest(self) -> int:
         d = torch.empty(1, dtype=torch.int32, device=self.device)

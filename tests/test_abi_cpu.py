@@ -114,3 +114,33 @@ def test_create_without_a_device_reports_an_error():
     st = lib.gsr_create(C.byref(h), 0)
     assert st != _abi.GSR_OK and not h.value
     assert lib.gsr_last_error(None)
+
+
+def test_optimiser_state_sizes():
+    lib = _abi.load()
+    assert C.sizeof(_abi.PoseAdam) == 20 and C.sizeof(_abi.MapAdam) == 32 and C.sizeof(_abi.GaussiansRW) == 48
+    # header (256 B) + two moment arrays; every segment padded to 64 floats
+    aniso = lib.gsr_map_state_size(1000, 0)
+    iso = lib.gsr_map_state_size(1000, 1)
+    assert aniso == 256 + 2 * 4 * (3008 + 4032 + 3008 + 1024 + 3008)
+    assert iso == 256 + 2 * 4 * (3008 + 0 + 1024 + 1024 + 3008)
+    assert lib.gsr_map_state_size(0, 0) == 256 and lib.gsr_map_state_size(-1, 0) == 0
+    assert lib.gsr_densify_work_size(0, 10) == 0
+    assert lib.gsr_densify_work_size(640, 480) >= 256 + 8 * 75 + 256
+
+
+def test_optimiser_entry_points_reject_a_null_context():
+    lib = _abi.load()
+    hp = _abi.PoseAdam(1e-3, 1e-3, 0.9, 0.999, 1e-8)
+    assert lib.gsr_pose_opt_init(None, 1, None, None, None, None) == _abi.GSR_EINVAL
+    assert lib.gsr_pose_opt_step(None, 1, None, None, C.byref(hp), None, None, None, None) == _abi.GSR_EINVAL
+    assert lib.gsr_map_opt_init(None, 10, 0, None, None) == _abi.GSR_EINVAL
+    rw = _abi.GaussiansRW(0, None, None, None, None, None)
+    assert lib.gsr_map_opt_step(None, rw, None, 0, None, None, None) == _abi.GSR_EINVAL
+    cam = _abi.Camera(8, 8, 10.0, 10.0, 3.5, 3.5)
+    assert lib.gsr_densify(None, cam, None, None, None, None, None, 0.5, rw, 1, 0, 0, None, None, 0,
+                           None) == _abi.GSR_EINVAL
+    gid = C.c_int32()
+    assert lib.gsr_track_capture(None, None, None, 1, None, None, None, None, _abi.Workspace(None, 0, 0),
+                                 _abi.Images(None, None, None), None, None, None, None, 1, None, None,
+                                 C.byref(gid)) == _abi.GSR_EINVAL

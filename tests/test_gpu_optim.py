@@ -1,0 +1,261 @@
+"""GPU parity of the optimisation steps (decoupled pose step and tracking
+loop, map step, new Gaussians from an RGB-D frame) against the FP64 oracle
+in oracle/optim.py, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import optim
+from paper_2408_05635_amd import scenes
+from gpu_util import dev_params, dev_poses, oracle_targets, to_dev
+
+pytestmark = pytest.mark.gpu
+
+f32 = np.float32
+
+
+@pytest.fixture(scope="module")
+def rast():
+    from paper_2408_05635_amd import raster
+    return raster.Rasterizer(0)
+
+
+def _hp32(hp):
+    """The oracle's hyper-parameters rounded as the ABI's float fields are."""
+    return type(hp)(**{k: float(f32(v)) for k, v in hp.__dict__.items()})
+
+
+# ----------------------------------------------------------------------------
+# pose step
+# ----------------------------------------------------------------------------
+
+def test_pose_step_matches_oracle(rast):
+    from paper_2408_05635_amd.raster import PoseAdam
+    rng = np.random.default_rng(21)
+    V = 5
+    q = (rng.normal(size=(V, 4)) * rng.uniform(0.5, 2.0, size=(V, 1))).astype(f32)
+    t = rng.normal(size=(V, 3)).astype(f32)
+    hp = PoseAdam(lr_rot=3e-3, lr_pos=1e-2)
+    ohp = _hp32(optim.PoseAdam(**hp.__dict__))
+    qd, td = torch.tensor(q, device="cuda"), torch.tensor(t, device="cuda")
+    state = rast.pose_opt_init(qd, td)
+    ost = [optim.PoseState.from_pose(q[v].astype(np.float64), t[v].astype(np.float64)) for v in range(V)]
+    for step in range(4):
+        scale = 10.0 ** rng.uniform(-5, 1, size=(V, 1))
+        gq = (rng.normal(size=(V, 4)) * scale).astype(f32)
+        gc = (rng.normal(size=(V, 3)) * scale).astype(f32)
+        if step == 2:
+            gc[1] = 0.0                          # a view whose centre gradient vanishes
+        rast.pose_opt_step(state, torch.tensor(gq, device="cuda"), torch.tensor(gc, device="cuda"), qd, td, hp)
+        ost = [optim.pose_step(ost[v], gq[v].astype(np.float64), gc[v].astype(np.float64), ohp) for v in range(V)]
+    torch.cuda.synchronize()
+    s = state.cpu().numpy()
+    for v in range(V):
+        np.testing.assert_allclose(s[v, 0:4], ost[v].q, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(s[v, 4:7], ost[v].C, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(s[v, 7:11], ost[v].mq, rtol=1e-12, atol=1e-300)
+        np.testing.assert_allclose(s[v, 11:15], ost[v].vq, rtol=1e-12, atol=1e-300)
+        assert s[v, 21] == 4.0
+        oq, ot = ost[v].pose()
+        # the FP32 pose is the rounding of the FP64 state: equal up to one rounding
+        np.testing.assert_allclose(qd[v].cpu().numpy(), oq, rtol=2 ** -23, atol=0)
+        np.testing.assert_allclose(td[v].cpu().numpy(), ot, rtol=2 ** -22, atol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# tracking loop
+# ----------------------------------------------------------------------------
+
+def _track_setup(w):
+    from paper_2408_05635_amd.raster import RenderOptions
+    g = dev_params(w.gaussians)
+    q, t = dev_poses(w.views)
+    tg = to_dev(oracle_targets(w))
+    return g, q, t, tg, RenderOptions(**w.weights)
+
+
+def test_track_equals_stepwise_calls_and_graph(rast):
+    """gsr_track is exactly the sequence (render_loss_grad, pose_opt_step);
+    its captured graph replays it bit for bit."""
+    from paper_2408_05635_amd.raster import PoseAdam, RenderOptions
+    w = scenes.config1()
+    g, q0, t0, tg, opts = _track_setup(w)
+    hp = PoseAdam(lr_rot=1e-3, lr_pos=1e-3)
+    iters = 6
+    q1, t1 = q0.clone(), t0.clone()
+    r1 = rast.track(g, q1, t1, w.views.cams, tg, opts, hp, iters)
+    # by hand
+    q2, t2 = q0.clone(), t0.clone()
+    st2 = rast.pose_opt_init(q2, t2)
+    o2 = RenderOptions(**{**opts.__dict__, "gauss_grads": False})
+    losses = []
+    for _ in range(iters):
+        out = rast.render_loss_grad(g, q2, t2, w.views.cams, tg, o2, check=False)
+        losses.append(out["loss"].clone())
+        rast.pose_opt_step(st2, out["dq_c"], out["dc"], q2, t2, hp)
+    torch.cuda.synchronize()
+    assert torch.equal(q1, q2) and torch.equal(t1, t2) and torch.equal(r1["state"], st2)
+    assert torch.equal(r1["loss_hist"], torch.stack(losses))
+    # captured (on a side stream: the null stream cannot be captured): one replay = the whole loop
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        q3, t3 = q0.clone(), t0.clone()
+        r3 = rast.track(g, q3, t3, w.views.cams, tg, opts, hp, iters, capture=True)
+        assert torch.equal(q3, q0)                       # capture does not run the loop
+        for rep in range(2):                             # replays continue from the state they find
+            rast.launch_graph(r3["graph"])
+            side.synchronize()
+            if rep == 0:
+                assert torch.equal(q3, q1) and torch.equal(t3, t1)
+                assert torch.equal(r3["loss_hist"], r1["loss_hist"])
+    torch.cuda.current_stream().wait_stream(side)
+    r4 = rast.track(g, q1, t1, w.views.cams, tg, opts, hp, iters, state=r1["state"])
+    torch.cuda.synchronize()
+    assert torch.equal(q3, q1) and torch.equal(t3, t1) and torch.equal(r3["loss_hist"], r4["loss_hist"])
+    rast.destroy_graph(r3["graph"])
+
+
+def test_track_follows_the_oracle_loop(rast):
+    """Five iterations on the tiny tracking scene against the oracle's loop.
+    The two loops see gradients that differ by FP32 rounding (1e-5 relative
+    at most, from the parity bar), and Adam's first step is lr * sign(g), so
+    the poses agree to a small fraction of one step unless a gradient
+    component is within that rounding of zero."""
+    from paper_2408_05635_amd.raster import PoseAdam
+    w = scenes.config1()
+    g, q, t, tg, opts = _track_setup(w)
+    hp = PoseAdam(lr_rot=1e-3, lr_pos=1e-3)
+    iters = 5
+    q0, t0 = q.cpu().numpy().astype(np.float64), t.cpu().numpy().astype(np.float64)
+    r = rast.track(g, q, t, w.views.cams, tg, opts, hp, iters)
+    torch.cuda.synchronize()
+    otg = oracle_targets(w)
+    hist, ol = optim.track(w.gaussians, w.views.cams, q0, t0,
+                           oracle.Targets(otg["rgb"], otg["depth"], otg["sil"]), oracle.Options(**w.weights),
+                           _hp32(optim.PoseAdam(**hp.__dict__)), iters)
+    s = r["state"].cpu().numpy()[0]
+    oq, oc = hist[-1][0].q, hist[-1][0].C
+    dq = np.abs(s[0:4] / np.linalg.norm(s[0:4]) - oq / np.linalg.norm(oq)).max()
+    dc = np.abs(s[4:7] - oc).max()
+    dl = np.abs(r["loss_hist"].cpu().numpy()[:, 0] - ol[:, 0]).max() / ol[0, 0]
+    print(f"after {iters} iterations: |dq| {dq:.2e} |dC| {dc:.2e} (step size {hp.lr_rot:g}), loss rel {dl:.2e}")
+    assert dq < 0.05 * hp.lr_rot and dc < 0.05 * hp.lr_pos
+    assert dl < 1e-4
+
+
+def test_track_reduces_pose_error_tracking_room(rast):
+    """One view of the 200k-Gaussian room from the 2 deg / 2 cm perturbed
+    start: the loop moves toward the true pose."""
+    from paper_2408_05635_amd.raster import PoseAdam, RenderOptions
+    w = scenes.config2(n_views=1)
+    g = dev_params(w.gaussians)
+    q, t = dev_poses(w.views)
+    tg = to_dev(oracle_targets(w))
+
+    def err(qq, ttt):
+        qa, ta = qq.cpu().numpy()[0].astype(np.float64), ttt.cpu().numpy()[0].astype(np.float64)
+        qb, tb = w.target_views.quat[0], w.target_views.trans[0]
+        ang = 2 * np.degrees(np.arccos(min(1.0, abs(np.dot(qa / np.linalg.norm(qa), qb / np.linalg.norm(qb))))))
+        return ang, np.linalg.norm(optim.centre_of(qa, ta) - optim.centre_of(qb, tb))
+    e0 = err(q, t)
+    r = rast.track(g, q, t, w.views.cams, tg, RenderOptions(**w.weights), PoseAdam(lr_rot=1e-3, lr_pos=1e-3), 40)
+    torch.cuda.synchronize()
+    e1 = err(q, t)
+    lh = r["loss_hist"].cpu().numpy()[:, 0]
+    print(f"rotation {e0[0]:.3f} -> {e1[0]:.3f} deg, centre {e0[1] * 100:.2f} -> {e1[1] * 100:.2f} cm, "
+          f"loss {lh[0]:.5f} -> {lh[-1]:.5f}")
+    assert lh[-1] < 0.8 * lh[0] and np.all(np.isfinite(lh))
+    assert e1[0] < 0.5 * e0[0] and e1[1] < e0[1]
+
+
+# ----------------------------------------------------------------------------
+# map step
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("iso", [False, True])
+def test_map_step_matches_oracle(rast, iso):
+    from paper_2408_05635_amd.raster import GaussianParams, MapAdam
+    rng = np.random.default_rng(31 + iso)
+    n = 5003                                   # ragged against the float4 and block granularity
+    shapes = dict(means=(n, 3), quats=(n, 4), log_scales=(n, 1 if iso else 3), opacity_logits=(n,), rgb=(n, 3))
+    p = {k: rng.normal(size=s).astype(f32) for k, s in shapes.items()}
+    hp = MapAdam()
+    ohp = _hp32(optim.MapAdam(**hp.__dict__))
+    g = GaussianParams(**{k: torch.tensor(a, device="cuda") for k, a in p.items()})
+    state = rast.map_opt_init(g)
+    op = {k: a.astype(np.float64) for k, a in p.items()}
+    if iso:
+        op.pop("quats")
+    om = {k: np.zeros_like(a) for k, a in op.items()}
+    ov = {k: np.zeros_like(a) for k, a in op.items()}
+    steps = 3
+    for step in range(1, steps + 1):
+        gr = {k: (rng.normal(size=s) * 10.0 ** rng.uniform(-6, 0, size=s)).astype(f32) for k, s in shapes.items()}
+        gr["means"][:7] = 0.0                  # zero gradients leave their entries in place
+        rast.map_opt_step(g, {"g_" + k: torch.tensor(a, device="cuda") for k, a in gr.items()}, state, hp)
+        op, om, ov = optim.map_step(op, {k: gr[k].astype(np.float64) for k in op}, om, ov, step, ohp)
+    torch.cuda.synchronize()
+    # FP32 Adam: a few roundings of x, plus a relative 1e-6 of each step's size
+    for k in op:
+        got = getattr(g, k).cpu().numpy().astype(np.float64)
+        np.testing.assert_allclose(got, op[k], rtol=1e-6, atol=1e-6 * ohp.lr(k) * steps, err_msg=k)
+    if iso:
+        assert np.array_equal(g.quats.cpu().numpy(), p["quats"])   # not touched
+    assert np.array_equal(g.means.cpu().numpy()[:7], p["means"][:7])
+
+
+# ----------------------------------------------------------------------------
+# new Gaussians
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("W,H,iso", [(128, 96, True), (640, 480, False)])
+def test_densify_matches_oracle(rast, W, H, iso):
+    from paper_2408_05635_amd.raster import GaussianParams
+    rng = np.random.default_rng(41 + W)
+    cam = scenes.Camera(W, H, 525.0 * W / 640, 530.0 * W / 640, (W - 1) / 2, (H - 1) / 2)
+    P = W * H
+    depth = rng.uniform(0.3, 5.0, size=P).astype(f32)
+    depth[rng.random(P) < 0.1] = 0.0
+    sil = rng.random(P).astype(f32)
+    sil[::7] = 0.5                             # exactly at the threshold: not selected
+    rgb = rng.random(3 * P).astype(f32)
+    q = np.array([0.95, -0.1, 0.2, 0.05], f32)
+    t = np.array([0.3, -0.2, 0.1], f32)
+    cap = 20 + P
+    out = GaussianParams(means=torch.full((cap, 3), -7.0, device="cuda"), quats=torch.full((cap, 4), -7.0,
+                         device="cuda"), log_scales=torch.full((cap, 1 if iso else 3), -7.0, device="cuda"),
+                         opacity_logits=torch.full((cap,), -7.0, device="cuda"),
+                         rgb=torch.full((cap, 3), -7.0, device="cuda"))
+    d = lambda a: torch.tensor(a, device="cuda")  # noqa: E731
+    off = 13
+    n_new = rast.densify(cam, d(q), d(t), d(rgb), d(depth), d(sil), out, off, 0.5)
+    torch.cuda.synchronize()
+    pix, og = optim.new_gaussians(cam, q.astype(np.float64), t.astype(np.float64), rgb.reshape(3, P),
+                                  depth, sil, 0.5, isotropic=iso)
+    k = pix.size
+    assert int(n_new.item()) == k
+    sl = slice(off, off + k)
+    np.testing.assert_allclose(out.means[sl].cpu().numpy(), og["means"], rtol=3e-7, atol=1e-7)
+    np.testing.assert_allclose(out.log_scales[sl].cpu().numpy(), og["log_scales"], rtol=2.4e-7, atol=1e-7)
+    np.testing.assert_array_equal(out.rgb[sl].cpu().numpy(), og["rgb"].astype(f32))
+    assert torch.all(out.opacity_logits[sl] == 0)
+    if not iso:
+        np.testing.assert_array_equal(out.quats[sl].cpu().numpy(), og["quats"].astype(f32))
+    # rows outside [off, off + k) untouched
+    assert torch.all(out.means[:off] == -7.0) and torch.all(out.means[off + k:] == -7.0)
+    # a capacity that cuts the list: only rows below it written, the count still full
+    out2 = GaussianParams(**{f: torch.full_like(getattr(out, f), -7.0) for f in ("means", "quats", "log_scales",
+                                                                              "opacity_logits", "rgb")})
+    small = GaussianParams(**{f: getattr(out2, f)[:off + 100] for f in ("means", "quats", "log_scales",
+                                                                        "opacity_logits", "rgb")})
+    n2 = rast.densify(cam, d(q), d(t), d(rgb), d(depth), d(sil), small, off, 0.5)
+    torch.cuda.synchronize()
+    assert int(n2.item()) == k
+    np.testing.assert_allclose(out2.means[off:off + 100].cpu().numpy(), og["means"][:100], rtol=3e-7, atol=1e-7)
+    assert torch.all(out2.means[off + 100:] == -7.0)
+    # initialisation: no silhouette, every pixel with depth
+    n3 = rast.densify(cam, d(q), d(t), d(rgb), d(depth), None, out, 0, 0.5)
+    torch.cuda.synchronize()
+    assert int(n3.item()) == int((depth > 0).sum())
