@@ -19,6 +19,10 @@ Reported (one JSON line):
                 VALU peak, from counted work
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample
   pose_fd       FP32 central-difference check of the pose gradients
+  next_rows     the steps around the path: the 40-iteration tracking loop
+                of one view as one graph replay, the mapping Adam step
+                (HBM roofline), new Gaussians from a 640x480 RGB-D frame,
+                and the batched step with isotropic Gaussians
 """
 from __future__ import annotations
 
@@ -59,6 +63,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=8, help="views in the oracle's timed sample")
+    ap.add_argument("--no-next", action="store_true", help="skip the tracking / mapping / densify / isotropic legs")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many batched steps (for a profiler) and print nothing else")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -206,6 +211,9 @@ def main():
     # pose-gradient check: FP32 central differences on 64 Gaussians seen by view 0
     pose_fd = pose_fd_check(rast, raster, w, dev, opts)
 
+    next_rows = None if args.no_next else next_rows_bench(rast, raster, scenes, w, g, q, t, targets, opts, timed,
+                                                          args)
+
     # CPU baseline: the oracle on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu:
@@ -229,8 +237,105 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "pose_fd": pose_fd,
+        "next_rows": next_rows,
     }
     print(json.dumps(res), flush=True)
+
+
+def next_rows_bench(rast, raster, scenes, w, g, q, t, targets, opts, timed, args):
+    """The rows after the path, each timed with HIP events on the current stream."""
+    import torch
+    dev = q.device
+    res = {}
+    P1 = 640 * 480
+    # tracking: one view, 40 pose-only iterations captured in one graph; a
+    # replay continues from the pose and state it finds
+    cam0 = [w.views.cams[0]]
+    q1, t1 = q[:1].clone(), t[:1].clone()
+    tg1 = {k: v[:(3 * P1 if k == "rgb" else P1)].contiguous() for k, v in targets.items()}
+    qt0 = w.target_views.quat[0].astype(np.float64)
+    ct0 = -_rot(qt0).T @ w.target_views.trans[0].astype(np.float64)
+
+    def pose_err(qq, tt):
+        qa = qq[0].double().cpu().numpy()
+        ta = tt[0].double().cpu().numpy()
+        ang = 2 * np.degrees(np.arccos(min(1.0, abs(float(np.dot(qa / np.linalg.norm(qa), qt0 / np.linalg.norm(qt0)))))))
+        return ang, float(np.linalg.norm(-_rot(qa).T @ ta - ct0))
+
+    e0 = pose_err(q1, t1)
+    hp = raster.PoseAdam(lr_rot=1e-3, lr_pos=1e-3)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        tr = rast.track(g, q1, t1, cam0, tg1, opts, hp, 40, capture=True)
+        rast.launch_graph(tr["graph"])
+        s.synchronize()
+        e1 = pose_err(q1, t1)
+        lh = tr["loss_hist"][:, 0].cpu().numpy()
+        reps = max(3, args.steps // 4)
+        ms_frame = timed(lambda: rast.launch_graph(tr["graph"]), reps, 1)
+        s.synchronize()
+        _, _, ovf = rast.read_counters(rast.shared_workspace())
+        rast.destroy_graph(tr["graph"])
+    torch.cuda.synchronize()
+    res["tracking"] = dict(workload="one 640x480 view of the 200k room, pose-only fwd+loss+bwd + decoupled Adam step, "
+                                    "40 iterations as one graph replay", iterations=40, ms_per_frame=ms_frame,
+                           iterations_per_s=40 * 1000.0 / ms_frame, overflow=bool(ovf),
+                           rotation_err_deg=[e0[0], e1[0]], centre_err_cm=[100 * e0[1], 100 * e1[1]],
+                           loss_first_last=[float(lh[0]), float(lh[-1])])
+    print(f"[bench] tracking {ms_frame:.3f} ms per 40-iteration frame", file=sys.stderr, flush=True)
+
+    # mapping Adam step at the mapping (500k) and large (3M) map sizes
+    res["map_step"] = []
+    for n in (500_000, 3_000_000):
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(61)
+        mk = lambda *sh: torch.randn(*sh, generator=gen, device=dev)  # noqa: E731
+        gm = raster.GaussianParams(mk(n, 3), mk(n, 4), mk(n, 3), mk(n), mk(n, 3))
+        grads = {"g_" + k: mk(*getattr(gm, k).shape) * 1e-3 for k in ("means", "quats", "log_scales",
+                                                                      "opacity_logits", "rgb")}
+        st = rast.map_opt_init(gm)
+        ms = timed(lambda: rast.map_opt_step(gm, grads, st), max(5, args.steps), 2)
+        floats = 14 * n
+        algo = floats * 4 * 7   # x read+write, g read, m and v read+write
+        gbs = algo / (ms * 1e-3) / 1e9
+        res["map_step"].append(dict(n_gaussians=n, ms=ms, algorithmic_bytes=algo, achieved_gbs=gbs,
+                                    roofline=dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                                                  frac=gbs / HBM_PEAK_GBS)))
+        print(f"[bench] map step n={n}: {ms:.3f} ms ({gbs:.0f} GB/s)", file=sys.stderr, flush=True)
+        del gm, grads, st
+
+    # new Gaussians from a 640x480 RGB-D frame (silhouette-guided)
+    cam = w.views.cams[0]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(62)
+    depth = torch.rand(P1, generator=gen, device=dev) * 4.0
+    sil = torch.rand(P1, generator=gen, device=dev)
+    rgb = torch.rand(3 * P1, generator=gen, device=dev)
+    cap = P1
+    outg = raster.GaussianParams(torch.empty(cap, 3, device=dev), torch.empty(cap, 4, device=dev),
+                                 torch.empty(cap, 3, device=dev), torch.empty(cap, device=dev),
+                                 torch.empty(cap, 3, device=dev))
+    n_new = torch.zeros(1, dtype=torch.int64, device=dev)
+    ms_d = timed(lambda: rast.densify(cam, q[0], t[0], rgb, depth, sil, outg, 0, 0.5, n_new=n_new),
+                 max(5, args.steps), 2)
+    res["densify"] = dict(width=640, height=480, ms=ms_d, new_gaussians=int(n_new.item()),
+                          pixels_per_s=P1 * 1000.0 / ms_d)
+    print(f"[bench] densify {ms_d:.3f} ms", file=sys.stderr, flush=True)
+
+    # the batched step with isotropic Gaussians (one log-scale each, no rotation)
+    giso = raster.GaussianParams(g.means, g.quats, g.log_scales.mean(1, keepdim=True).contiguous(),
+                                 g.opacity_logits, g.rgb)
+    V = len(w.views.cams)
+    P = V * P1
+    oiso = rast.alloc_outputs(giso, V, P, opts)
+    rast.render_loss_grad(giso, q, t, w.views.cams, targets, opts, check=True, out=oiso)
+    ms_iso = timed(lambda: rast.render_loss_grad(giso, q, t, w.views.cams, targets, opts, check=False, out=oiso),
+                   args.steps, args.warmup)
+    _, _, ovf = rast.read_counters(rast.shared_workspace())
+    res["isotropic"] = dict(value=V * 1000.0 / ms_iso, unit="views/s", ms_per_step=ms_iso, overflow=bool(ovf))
+    print(f"[bench] isotropic {ms_iso:.3f} ms/step", file=sys.stderr, flush=True)
+    return res
 
 
 def kernel_source_hash() -> str:
