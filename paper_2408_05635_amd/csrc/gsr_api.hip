@@ -98,7 +98,7 @@ constexpr int kRecBwdMaxBlocks = 2048;   // grid cap of the record backward (one
 constexpr size_t kSyncTickets = 256;
 constexpr int kSortPasses = 8;   // 4 passes of the depth sort, at most 4 of the tile sort
 // ids of the binning's scans
-enum SyncId : uint32_t { kIdVisible = 0, kIdOffsets = 1, kIdOwner = 2 };
+enum SyncId : uint32_t { kIdVisible = 0, kIdOffsets = 1 };
 
 struct Layout {
     int64_t vn;           // V * N
@@ -406,39 +406,40 @@ struct OffSink {
     __device__ void operator()(int64_t s, uint32_t pos, uint32_t) const { off[s] = pos; }
 };
 
-// Pair j's owning record is the number of record starts in [1, j]: records
-// own contiguous, non-empty ranges [poff[s], poff[s] + cnt_s[s]) (every
-// visible record touches at least one tile).  k_mark_heads sets owner[poff[s]]
-// = 1 for s >= 1 into a zeroed array, and an inclusive prefix sum turns it
-// into the owner of every pair.  Emission is then one thread per pair, which
-// stays balanced however many tiles a record covers.
-__global__ void k_mark_heads(const int64_t *__restrict__ counters, const uint32_t *__restrict__ poff,
-                             uint32_t *__restrict__ owner) {
-    const int64_t M = counters[kCntVisible];
-    if (counters[kCntPairsUsed] == 0) return;
-    for (int64_t s = 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < M; s += (int64_t)gridDim.x * blockDim.x)
-        owner[poff[s]] = 1u;
-}
-
-struct OwnSrc {
-    const uint32_t *h;
-    __device__ uint32_t operator()(int64_t i) const { return h[i]; }
-};
-struct OwnSink {   // inclusive prefix, written in place (each thread rewrites only what it read)
-    uint32_t *h;
-    __device__ void operator()(int64_t i, uint32_t pre, uint32_t v) const { h[i] = pre + v; }
+// The pair total: the capacity check is made by the scan's last block.
+struct PairTotal {
+    int64_t *counters;
+    int64_t cap;
+    __device__ void operator()(int64_t K) const {
+        counters[kCntPairs] = K;
+        counters[kCntPairsUsed] = K <= cap ? K : 0;
+        counters[kCntOverflow] = K <= cap ? 0 : 1;
+        if (K > cap) counters[kCntOverflowAny] = 1;
+    }
 };
 
-// Pair j: key = global tile id, value = j.
+// Pair j: key = global tile id, value = j.  Records own contiguous ranges
+// [poff[s], poff[s] + cnt_s[s]) in record order, so pair j's record is the
+// last s with poff[s] <= j (binary search; empty ranges are skipped by
+// "last").  One thread per pair stays balanced however many tiles a record
+// covers; owner[j] keeps the record for the sorted pairs.
 __global__ void k_emit(const int64_t *__restrict__ counters, const uint32_t *__restrict__ poff,
                        const uint2 *__restrict__ trect, const uint32_t *__restrict__ gid,
-                       const ViewTable *__restrict__ vt, int64_t n, const uint32_t *__restrict__ owner,
+                       const ViewTable *__restrict__ vt, int64_t n, uint32_t *__restrict__ owner,
                        uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
     const int64_t K = counters[kCntPairsUsed];
     const int64_t M = counters[kCntVisible];
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < K; j += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t s = owner[j];
-        if ((int64_t)s >= M) s = 0;   // never expected; keeps reads in bounds
+        int64_t lo = 0, hi = M;   // poff[0] = 0 <= j < poff[M] (= K)
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)poff[mid] <= j)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const uint32_t s = (uint32_t)lo;
+        owner[j] = s;
         const uint32_t k = (uint32_t)j - poff[s];
         const uint2 tr = trect[s];
         const uint32_t tx0 = tr.x & 0xffffu, nx = (tr.x >> 16) - tx0 + 1u, ty0 = tr.y & 0xffffu;
@@ -465,13 +466,6 @@ __global__ void k_pair_records(const int64_t *__restrict__ counters, const uint3
         prec[e] = owner[sorted_j[e]];
 }
 
-__global__ void k_check_capacity(int64_t *counters, int64_t cap) {
-    const int64_t K = counters[kCntPairs];
-    counters[kCntPairsUsed] = K <= cap ? K : 0;
-    counters[kCntOverflow] = K <= cap ? 0 : 1;
-    if (K > cap) counters[kCntOverflowAny] = 1;
-}
-
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t val) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = val;
@@ -488,14 +482,25 @@ __global__ void k_fill_f64(double *p, int64_t n) {
         p[i] = 0.0;
 }
 
+// [start, end) of every tile in the sorted keys: two binary searches per tile
+// (tiles without pairs get an empty range).
 __global__ void k_ranges(const uint32_t *__restrict__ keys, const int64_t *__restrict__ counters,
                          uint2 *__restrict__ ranges, int64_t n_tiles) {
     const int64_t K = counters[kCntPairsUsed];
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < K; j += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t t = keys[j];
-        if (t >= (uint32_t)n_tiles) continue;   // never expected; keeps writes in bounds
-        if (j == 0 || keys[j - 1] != t) ranges[t].x = (uint32_t)j;
-        if (j == K - 1 || keys[j + 1] != t) ranges[t].y = (uint32_t)(j + 1);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t r[2];
+        for (int k = 0; k < 2; ++k) {   // first index with key >= t + k
+            int64_t lo = 0, hi = K;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if ((int64_t)keys[mid] < t + k)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            r[k] = (uint32_t)lo;
+        }
+        ranges[t] = make_uint2(r[0], r[1]);
     }
 }
 
@@ -520,7 +525,7 @@ struct GradOut {
 // a long range alone.  Both row sums are deterministic.
 constexpr uint32_t kLongRows = 32;
 
-template <bool ISO>
+template <bool ISO, int NV>
 __global__ __launch_bounds__(256) void k_record_bwd(ProjParams pp, const ViewTable *__restrict__ vt,
                                                     const PoseF64 *__restrict__ poses,
                                                     const uint32_t *__restrict__ gid_sorted,
@@ -548,24 +553,26 @@ __global__ __launch_bounds__(256) void k_record_bwd(ProjParams pp, const ViewTab
             j0 = poff[s];
             nrow = cnt_s[s];
         }
-        float g2[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float r2[NV];   // the record's row sum (NV partials; 6 = pose only: 0..4 and depth)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) r2[c] = 0.0f;
         if (nrow <= kLongRows) {   // rows in order; four rows' loads in flight at once
             uint32_t jj = j0;
             const uint32_t end = j0 + nrow;
             for (; jj + 4 <= end; jj += 4) {
-                float rows[40];
-                const float *row = gpairs + 10 * (size_t)jj;
+                float rows[4 * NV];
+                const float *row = gpairs + NV * (size_t)jj;
 #pragma unroll
-                for (int c = 0; c < 40; ++c) rows[c] = row[c];
+                for (int c = 0; c < 4 * NV; ++c) rows[c] = row[c];
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
 #pragma unroll
-                    for (int c = 0; c < 10; ++c) g2[c] += rows[10 * q + c];
+                    for (int c = 0; c < NV; ++c) r2[c] += rows[NV * q + c];
             }
             for (; jj < end; ++jj) {
-                const float *row = gpairs + 10 * (size_t)jj;
+                const float *row = gpairs + NV * (size_t)jj;
 #pragma unroll
-                for (int c = 0; c < 10; ++c) g2[c] += row[c];
+                for (int c = 0; c < NV; ++c) r2[c] += row[c];
             }
         }
         uint64_t longm = ballot(nrow > kLongRows);
@@ -573,17 +580,29 @@ __global__ __launch_bounds__(256) void k_record_bwd(ProjParams pp, const ViewTab
             const int src = __builtin_ctzll(longm);
             longm &= longm - 1;
             const uint32_t a = __shfl(j0, src, 64), cnt = __shfl(nrow, src, 64);
-            float part[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            float part[NV];
+#pragma unroll
+            for (int c = 0; c < NV; ++c) part[c] = 0.0f;
             for (uint32_t jj = a + lane; jj < a + cnt; jj += 64) {
-                const float *row = gpairs + 10 * (size_t)jj;
+                const float *row = gpairs + NV * (size_t)jj;
 #pragma unroll
-                for (int c = 0; c < 10; ++c) part[c] += row[c];
+                for (int c = 0; c < NV; ++c) part[c] += row[c];
             }
 #pragma unroll
-            for (int c = 0; c < 10; ++c) {
+            for (int c = 0; c < NV; ++c) {
                 const float t = wave_sum(part[c]);
-                if ((int)lane == src) g2[c] = t;
+                if ((int)lane == src) r2[c] = t;
             }
+        }
+        float g2[10];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) g2[c] = r2[c];
+        if constexpr (NV == 10) {
+#pragma unroll
+            for (int c = 5; c < 10; ++c) g2[c] = r2[c];
+        } else {
+            g2[5] = g2[6] = g2[7] = g2[8] = 0.0f;
+            g2[9] = r2[5];
         }
         if (!valid) continue;
         const uint32_t gid = gid_sorted[s];
@@ -844,7 +863,8 @@ void enqueue_binning(Call &c, const gsr_views *views) {
                            poses, cnt, zkey);
     }
     // compaction of the visible (view, Gaussian) records, index order kept
-    scan_exclusive(VisSrc{cnt}, VisSink{zkey, dk0, dv0}, nullptr, L.vn, ss, kIdVisible, counters + kCntVisible, st);
+    scan_exclusive(VisSrc{cnt}, VisSink{zkey, dk0, dv0}, nullptr, L.vn, ss, kIdVisible,
+                   TotalTo{counters + kCntVisible}, st);
     // depth order: stable sort on the float32 depth bits (positive floats sort as integers)
     const bool d_in1 =
         radix_sort(dk0, dv0, dk1, dv1, counters + kCntVisible, L.vn, 32, so, 0, st);
@@ -859,27 +879,22 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     uint32_t *pk0 = at<uint32_t>(ws, L.pk0), *pv0 = at<uint32_t>(ws, L.pv0);
     uint32_t *pk1 = at<uint32_t>(ws, L.pk1), *pv1 = at<uint32_t>(ws, L.pv1);
     uint32_t *poff = at<uint32_t>(ws, L.poff), *owner = at<uint32_t>(ws, L.owner);
-    scan_exclusive(CntSrc{cnt_s}, OffSink{poff}, counters + kCntVisible, L.vn, ss, kIdOffsets, counters + kCntPairs,
-                   st);
-    hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(1), 0, st, counters, L.kcap);
-    if (L.vn > 0 && L.kcap > 0) {
-        hipLaunchKernelGGL(k_fill_u32_dev, dim3(grid_for(L.kcap, 256, 8192)), dim3(256), 0, st, owner,
-                           (const int64_t *)(counters + kCntPairsUsed), 0u);
-        hipLaunchKernelGGL(k_mark_heads, dim3(grid_for(L.vn, 256, 8192)), dim3(256), 0, st, counters, poff, owner);
-        scan_exclusive(OwnSrc{owner}, OwnSink{owner}, counters + kCntPairsUsed, L.kcap, ss, kIdOwner,
-                       counters + kCntScratch, st);
+    uint32_t *prec = at<uint32_t>(ws, L.prec);
+    // pair offsets of the records; the last block checks the pair capacity
+    scan_exclusive(CntSrc{cnt_s}, OffSink{poff}, counters + kCntVisible, L.vn, ss, kIdOffsets,
+                   PairTotal{counters, L.kcap}, st);
+    if (L.vn > 0 && L.kcap > 0)
         hipLaunchKernelGGL(k_emit, dim3(grid_for(L.kcap, 256, 16384)), dim3(256), 0, st, counters, poff, trect,
                            gid_sorted, vt, c.pp.n, owner, pk0, pv0);
-    }
-    const bool p_in1 = radix_sort(pk0, pv0, pk1, pv1, counters + kCntPairsUsed, L.kcap, L.tile_bits, so, 4, st);
+    // tile order (stable: depth order within a tile); the last pass maps pairs to records
+    const bool p_in1 = radix_sort(pk0, pv0, pk1, pv1, counters + kCntPairsUsed, L.kcap, L.tile_bits, so, 4, st,
+                                  owner, prec);
     uint2 *ranges = at<uint2>(ws, L.ranges);
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(2 * L.T, 256)), dim3(256), 0, st, (uint32_t *)ranges, 2 * L.T, 0u);
-    if (L.kcap > 0) {
-        hipLaunchKernelGGL(k_ranges, dim3(grid_for(L.kcap, 256, 16384)), dim3(256), 0, st, p_in1 ? pk1 : pk0,
-                           counters, ranges, L.T);
-        hipLaunchKernelGGL(k_pair_records, dim3(grid_for(L.kcap, 256, 16384)), dim3(256), 0, st, counters,
-                           p_in1 ? pv1 : pv0, owner, at<uint32_t>(ws, L.prec));
-    }
+    hipLaunchKernelGGL(k_ranges, dim3(grid_for(L.T, 256, 4096)), dim3(256), 0, st, p_in1 ? pk1 : pk0,
+                       (const int64_t *)counters, ranges, L.T);
+    if (L.kcap > 0 && L.tile_bits == 0)   // one tile: no sort pass, the emission order is the tile order
+        hipLaunchKernelGGL(k_pair_records, dim3(grid_for(L.kcap, 256, 16384)), dim3(256), 0, st, counters, pv0, owner,
+                           prec);
 }
 
 // emission index of every sorted pair (the sort's result buffer is fixed by the key bits)
@@ -919,6 +934,13 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
     int64_t *counters = at<int64_t>(c.ws, L.counters);
     float *gpairs = at<float>(c.ws, L.gpairs);
     li.loss_tile = at<double>(c.ws, L.losst);
+    GradOut go;
+    memset(&go, 0, sizeof(go));
+    if (gg) go.gg = *gg;
+    go.want_gauss = gg && !(opts->flags & GSR_NO_GAUSS_GRADS) &&
+                    (gg->means || gg->quats || gg->log_scales || gg->opacity_logits || gg->rgb);
+    go.want_pose = pg && !(opts->flags & GSR_NO_POSE_GRADS) && (pg->dq_t || pg->dt || pg->dq_c || pg->dc);
+    const bool pose_only = !go.want_gauss;   // 6 partials per entry reach the pose
     BlendOut bo{out.rgb, out.depth, out.sil, at<float>(c.ws, L.tfinal), at<uint32_t>(c.ws, L.nlast),
                 at<uint32_t>(c.ws, L.phash)};
     {
@@ -926,8 +948,11 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
         const unsigned grid = (unsigned)(((L.T + 7) / 8) * 8);
         const unsigned threads = (unsigned)(64 * (opts->tile_w / kBlk) * (opts->tile_h / kBlk));
         if (grid > 0 && L.kcap > 0) {
-            auto kern = fused ? (c.count ? k_blend_bwd<true, true> : k_blend_bwd<true, false>)
-                              : (c.count ? k_blend_bwd<false, true> : k_blend_bwd<false, false>);
+            auto kern =
+                pose_only ? (fused ? (c.count ? k_blend_bwd<true, true, 6> : k_blend_bwd<true, false, 6>)
+                                   : (c.count ? k_blend_bwd<false, true, 6> : k_blend_bwd<false, false, 6>))
+                          : (fused ? (c.count ? k_blend_bwd<true, true, 10> : k_blend_bwd<true, false, 10>)
+                                   : (c.count ? k_blend_bwd<false, true, 10> : k_blend_bwd<false, false, 10>));
             hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, vt, at<float4>(c.ws, L.rec), pair_values(c),
                                pair_j(c), at<uint2>(c.ws, L.ranges), counters, bo, li, gpairs);
         }
@@ -937,17 +962,13 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
             hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(L.T, 256)), dim3(256), 0, st, li.loss_tile, L.T);
         hipLaunchKernelGGL(k_loss_final, dim3(views->n_views), dim3(256), 0, st, vt, li.loss_tile, li.loss);
     }
-    GradOut go;
-    memset(&go, 0, sizeof(go));
-    if (gg) go.gg = *gg;
-    go.want_gauss = gg && !(opts->flags & GSR_NO_GAUSS_GRADS) &&
-                    (gg->means || gg->quats || gg->log_scales || gg->opacity_logits || gg->rgb);
-    go.want_pose = pg && !(opts->flags & GSR_NO_POSE_GRADS) && (pg->dq_t || pg->dt || pg->dq_c || pg->dc);
     StageTimer timer(c.ctx, kStageProjectBwd, st);
     const unsigned rec_blocks = std::min<unsigned>(grid_for(L.vn, 256, 1ll << 30), kRecBwdMaxBlocks);
     double *pose_blocks = at<double>(c.ws, L.poseblk);
     if (c.pp.n > 0 && (go.want_gauss || go.want_pose))
-        hipLaunchKernelGGL(c.pp.iso ? k_record_bwd<true> : k_record_bwd<false>, dim3(rec_blocks), dim3(256), 0, st,
+        hipLaunchKernelGGL(pose_only ? (c.pp.iso ? k_record_bwd<true, 6> : k_record_bwd<false, 6>)
+                                     : (c.pp.iso ? k_record_bwd<true, 10> : k_record_bwd<false, 10>),
+                           dim3(rec_blocks), dim3(256), 0, st,
                            c.pp, vt, at<PoseF64>(c.ws, L.poses),
                            depth_sorted_gid(c), at<uint32_t>(c.ws, L.poff), at<uint32_t>(c.ws, L.cnt_s), gpairs,
                            (const int64_t *)counters, at<float>(c.ws, L.rgrad), pose_blocks, go.want_gauss,
@@ -1611,7 +1632,7 @@ gsr_status gsr_densify(gsr_ctx *ctx, gsr_camera cam, const float *quat, const fl
     SyncState ss{reinterpret_cast<uint32_t *>(w), reinterpret_cast<uint64_t *>(w + kSyncTickets), err};
     NewSink sink{cam, Rt, rgb, depth, P, offset, capacity, out.means, iso ? nullptr : out.quats, out.log_scales,
                  out.opacity_logits, out.rgb, iso};
-    scan_exclusive(NewSrc{depth, sil, sil_thresh}, sink, nullptr, P, ss, 0u, n_new, st);
+    scan_exclusive(NewSrc{depth, sil, sil_thresh}, sink, nullptr, P, ss, 0u, TotalTo{n_new}, st);
     hipLaunchKernelGGL(k_densify_finish, dim3(1), dim3(64), 0, st, (const int64_t *)err, n_new);
     return check_hip(ctx, hipGetLastError(), "gsr_densify launch");
 }

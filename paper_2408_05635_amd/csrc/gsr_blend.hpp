@@ -235,7 +235,10 @@ __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.0f) - (x 
 constexpr int kBwdMaxWaves = 4;
 constexpr int kSeg = 32;   // list entries per segment (LDS: 4 waves x 4 rows x kSeg x 10 floats)
 
-template <bool FUSED, bool COUNT>
+// NV = 10: all partials per entry (dL/d of the conic factors and mean, opacity,
+// colour, depth).  NV = 6 (pose only): the opacity and colour partials do not
+// reach the pose, so only (0..4, depth) are formed, reduced and written.
+template <bool FUSED, bool COUNT, int NV>
 __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__ vt, const float4 *__restrict__ rec,
                                                    const uint32_t *__restrict__ pair_rec,
                                                    const uint32_t *__restrict__ pair_j,
@@ -243,7 +246,8 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                                                    BlendOut st, LossIn L, float *__restrict__ grad_pairs) {
     __shared__ float4 s_a[kBwdMaxWaves][kSeg], s_b[kBwdMaxWaves][kSeg], s_c[kBwdMaxWaves][kSeg];
     __shared__ uint32_t s_pos[kBwdMaxWaves][kSeg];
-    // per wave, per 16-lane row, per entry of the segment: the row's sums of the 10 partials
+    // per wave, per 16-lane row, per entry of the segment: the row's sums of the NV partials
+    // (row stride kSeg * 10 for both NV)
     __shared__ float s_acc[kBwdMaxWaves][4][kSeg * 10];
     __shared__ uint32_t s_wmax[kBwdMaxWaves];
     __shared__ double s_loss[kBwdMaxWaves];
@@ -338,9 +342,9 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
     for (int w = 0; w < nw; ++w) bmax = s_wmax[w] > bmax ? s_wmax[w] : bmax;
     // entries behind every pixel's last contributor get zero rows
     for (uint32_t e = bmax + threadIdx.x; e < rg.y; e += blockDim.x) {
-        float *dst = grad_pairs + 10 * (size_t)pair_j[e];
+        float *dst = grad_pairs + NV * (size_t)pair_j[e];
 #pragma unroll
-        for (int c = 0; c < 10; ++c) dst[c] = 0.0f;
+        for (int c = 0; c < NV; ++c) dst[c] = 0.0f;
     }
 
     float b0 = 0.f, b1 = 0.f, b2 = 0.f, bd = 0.f, bs = 0.f;
@@ -397,17 +401,21 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                 const float dp2 = live * dal * ev.alpha * kLn2f;
                 const float tu = 2.0f * ev.u * dp2, tw = 2.0f * ev.w * dp2;
                 const float wc = contrib ? wgt : 0.0f;
-                float d[10];
+                float d[NV];
                 d[0] = tu * b.x;
                 d[1] = tu * b.y + tw * b.z;
                 d[2] = -tu * ev.dx;
                 d[3] = -tu * ev.dy;
                 d[4] = -tw * ev.dy;
-                d[5] = live * dal * ev.G;
-                d[6] = g[0] * wc;
-                d[7] = g[1] * wc;
-                d[8] = g[2] * wc;
-                d[9] = g[3] * wc;
+                if constexpr (NV == 10) {
+                    d[5] = live * dal * ev.G;
+                    d[6] = g[0] * wc;
+                    d[7] = g[1] * wc;
+                    d[8] = g[2] * wc;
+                    d[9] = g[3] * wc;
+                } else {
+                    d[5] = g[3] * wc;
+                }
                 if (contrib) {
                     b0 = ev.alpha * cc.x + oma * b0;
                     b1 = ev.alpha * cc.y + oma * b1;
@@ -416,35 +424,32 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                     bs = ev.alpha + oma * bs;
                     T = Tk;
                 }
-                // sums within each row of 16 lanes, the ten chains interleaved
+                // sums within each row of 16 lanes, the chains interleaved
 #pragma unroll
-                for (int c = 0; c < 10; ++c) d[c] += dpp_f<0xb1>(d[c]);    // quad_perm [1,0,3,2]
+                for (int c = 0; c < NV; ++c) d[c] += dpp_f<0xb1>(d[c]);    // quad_perm [1,0,3,2]
 #pragma unroll
-                for (int c = 0; c < 10; ++c) d[c] += dpp_f<0x4e>(d[c]);    // quad_perm [2,3,0,1]
+                for (int c = 0; c < NV; ++c) d[c] += dpp_f<0x4e>(d[c]);    // quad_perm [2,3,0,1]
 #pragma unroll
-                for (int c = 0; c < 10; ++c) d[c] += dpp_f<0x114>(d[c]);   // row_shr:4
+                for (int c = 0; c < NV; ++c) d[c] += dpp_f<0x114>(d[c]);   // row_shr:4
 #pragma unroll
-                for (int c = 0; c < 10; ++c) d[c] += dpp_f<0x118>(d[c]);   // row_shr:8
+                for (int c = 0; c < NV; ++c) d[c] += dpp_f<0x118>(d[c]);   // row_shr:8
                 if ((lane & 15u) == 15u) {   // the row's sum is in its last lane
-                    float2 *dst = reinterpret_cast<float2 *>(acc + (row * kSeg + (pos - seg_lo)) * 10);
-                    dst[0] = make_float2(d[0], d[1]);
-                    dst[1] = make_float2(d[2], d[3]);
-                    dst[2] = make_float2(d[4], d[5]);
-                    dst[3] = make_float2(d[6], d[7]);
-                    dst[4] = make_float2(d[8], d[9]);
+                    float2 *dst = reinterpret_cast<float2 *>(acc + row * (kSeg * 10) + (pos - seg_lo) * NV);
+#pragma unroll
+                    for (int c = 0; c < NV / 2; ++c) dst[c] = make_float2(d[2 * c], d[2 * c + 1]);
                 }
             }
         }
         __syncthreads();
         // add the rows of all waves in a fixed order and write each entry's row
         const uint32_t n_e = seg_hi - seg_lo;
-        for (uint32_t idx = threadIdx.x; idx < n_e * 10; idx += blockDim.x) {
-            const uint32_t e = idx / 10, c = idx - e * 10;
+        for (uint32_t idx = threadIdx.x; idx < n_e * NV; idx += blockDim.x) {
+            const uint32_t e = idx / NV, c = idx - e * NV;
             float sum = 0.0f;
             for (int w = 0; w < nw; ++w)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) sum += s_acc[w][r][idx];
-            grad_pairs[10 * (size_t)pair_j[seg_lo + e] + c] = sum;
+            grad_pairs[NV * (size_t)pair_j[seg_lo + e] + c] = sum;
         }
         __syncthreads();
         seg_hi = seg_lo;

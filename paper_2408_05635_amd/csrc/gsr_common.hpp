@@ -43,7 +43,6 @@ enum Counter {
     kCntPairsUsed = 2,   // K if it fits the capacity, else 0
     kCntOverflow = 3,    // 1 if K exceeded the capacity
     kCntOverflowAny = 4, // 1 if K exceeded it in any call of a tracking loop (kept across its iterations)
-    kCntScratch = 5,     // totals of internal scans
     kCntSyncError = 6,   // waits between blocks that gave up (never expected)
     // work counters (GSR_COUNT_WORK): (pixel, entry) evaluations and
     // contributions in the forward and backward blends, and (wave, entry)

@@ -152,11 +152,19 @@ __device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t x, uint32_t &to
     return before + incl - x;
 }
 
+// The total of a scan goes to one int64.
+struct TotalTo {
+    int64_t *p;
+    __device__ void operator()(int64_t t) const {
+        if (p) *p = t;
+    }
+};
+
 // Single-pass exclusive scan: sink(i, exclusive_prefix, value) for every
-// i < n, the total to *total.  The sink may overwrite the source in place.
-template <class Src, class Sink>
+// i < n, then fin(total) once.  The sink may overwrite the source in place.
+template <class Src, class Sink, class Fin>
 __global__ __launch_bounds__(kScanThreads) void k_scan(Src src, Sink sink, const int64_t *n_dev, int64_t n_host,
-                                                       SyncState ss, uint32_t id, int64_t *total) {
+                                                       SyncState ss, uint32_t id, Fin fin) {
     __shared__ uint32_t s_b, s_excl;
     if (threadIdx.x == 0) s_b = take_ticket(ss.tickets, id);
     __syncthreads();
@@ -164,7 +172,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Src src, Sink sink, const
     const int64_t n = dev_count(n_dev, n_host);
     const int64_t nb = (n + kChunk - 1) / kChunk;
     if (b >= nb) {   // block-uniform
-        if (nb == 0 && b == 0 && threadIdx.x == 0 && total) *total = 0;
+        if (nb == 0 && b == 0 && threadIdx.x == 0) fin(0);
         return;
     }
     const int64_t first = b * kChunk + (int64_t)threadIdx.x * kScanItems;
@@ -184,7 +192,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Src src, Sink sink, const
         if (threadIdx.x == 0) {
             if (b > 0) publish(mine, id, kFlagPrefix, excl + agg);
             s_excl = excl;
-            if (b == nb - 1 && total) *total = (int64_t)excl + (int64_t)agg;
+            if (b == nb - 1) fin((int64_t)excl + (int64_t)agg);
         }
     }
     __syncthreads();
@@ -196,13 +204,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Src src, Sink sink, const
     }
 }
 
-template <class Src, class Sink>
+template <class Src, class Sink, class Fin>
 inline void scan_exclusive(Src src, Sink sink, const int64_t *n_dev, int64_t n_cap, const SyncState &ss, uint32_t id,
-                           int64_t *total, hipStream_t st) {
+                           Fin fin, hipStream_t st) {
     int64_t nb = (n_cap + kChunk - 1) / kChunk;
     if (nb < 1) nb = 1;   // one block still publishes a zero total
-    hipLaunchKernelGGL((k_scan<Src, Sink>), dim3((unsigned)nb), dim3(kScanThreads), 0, st, src, sink, n_dev, n_cap,
-                       ss, id, total);
+    hipLaunchKernelGGL((k_scan<Src, Sink, Fin>), dim3((unsigned)nb), dim3(kScanThreads), 0, st, src, sink, n_dev,
+                       n_cap, ss, id, fin);
 }
 
 // ---------------------------------------------------------------------------
@@ -331,7 +339,9 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
                                                                 const uint32_t *__restrict__ vin,
                                                                 uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                                 const int64_t *n_dev, int64_t n_host, int shift,
-                                                                int dbits, SortState so) {
+                                                                int dbits, SortState so,
+                                                                const uint32_t *__restrict__ map_in,
+                                                                uint32_t *__restrict__ map_out) {
     __shared__ uint32_t s_off[256];
     __shared__ uint32_t s_w[kScanThreads / 64][256];
     const int64_t n = dev_count(n_dev, n_host);
@@ -378,6 +388,7 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
             if ((int64_t)pos < n) {   // always true for consistent counts; keeps writes in bounds
                 kout[pos] = key;
                 vout[pos] = val;
+                if (map_out) map_out[pos] = map_in[val];
             }
         }
         __syncthreads();
@@ -385,10 +396,13 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
 }
 
 // Sorts n (device count, <= cap) pairs by key bits [0, bits), using the
-// arrival counters and tags of passes pass0, pass0 + 1, ...  Returns true if the result is in
-// (k1, v1), false if in (k0, v0).
+// arrival counters and tags of passes pass0, pass0 + 1, ...  If map_out is
+// given, the last pass also writes map_out[i] = map_in[value of sorted pair
+// i] (bits must be > 0).  Returns true if the result is in (k1, v1), false
+// if in (k0, v0).
 inline bool radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const int64_t *n_dev, int64_t cap,
-                       int bits, const SortState &so, int pass0, hipStream_t st) {
+                       int bits, const SortState &so, int pass0, hipStream_t st, const uint32_t *map_in = nullptr,
+                       uint32_t *map_out = nullptr) {
     const int64_t nb = (cap + kChunk - 1) / kChunk;
     if (nb == 0 || bits <= 0) return false;
     bool in1 = false;
@@ -398,8 +412,9 @@ inline bool radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, c
         uint32_t *ko = in1 ? k0 : k1, *vo = in1 ? v0 : v1;
         hipLaunchKernelGGL(k_radix_count, dim3((unsigned)nb), dim3(kScanThreads), 0, st, ki, n_dev, cap, shift, dbits,
                            so, p);
+        const bool last = shift + 8 >= bits;
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kScanThreads), 0, st, ki, vi, ko, vo, n_dev, cap,
-                           shift, dbits, so);
+                           shift, dbits, so, last ? map_in : nullptr, last ? map_out : nullptr);
         in1 = !in1;
     }
     return in1;
