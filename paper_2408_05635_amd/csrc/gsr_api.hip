@@ -108,7 +108,7 @@ struct Layout {
     int32_t G;            // total blend blocks
     int tile_bits;        // key bits of the tile sort
     size_t views, poses, counters, cnt, zkey, dk0, dv0, dk1, dv1, inv, rec, trect, cnt_s, poff, pk0, pv0, pk1, pv1,
-        owner, prec, ranges, tfinal, nlast, phash, gpairs, rgrad, losst, poseblk, sgbase, sync;
+        ranges, tfinal, nlast, phash, gpairs, rgrad, losst, poseblk, sgbase, sync;
     int64_t sort_groups;  // groups of sort blocks at the capacity
     // offsets in the sync region (cleared by every call): scan look-back
     // words, sort arrival counters, sort block words, sort group words
@@ -263,8 +263,6 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     L.pv0 = take(4 * kc);
     L.pk1 = take(4 * kc);
     L.pv1 = take(4 * kc);
-    L.owner = take(4 * kc);
-    L.prec = take(4 * kc);
     L.ranges = take(8 * (size_t)L.T);
     L.tfinal = take(4 * (size_t)L.P);
     L.nlast = take(4 * (size_t)L.P);
@@ -418,15 +416,15 @@ struct PairTotal {
     }
 };
 
-// Pair j: key = global tile id, value = j.  Records own contiguous ranges
-// [poff[s], poff[s] + cnt_s[s]) in record order, so pair j's record is the
-// last s with poff[s] <= j (binary search; empty ranges are skipped by
-// "last").  One thread per pair stays balanced however many tiles a record
-// covers; owner[j] keeps the record for the sorted pairs.
+// Pair j: key = global tile id, value = its record.  Records own contiguous
+// ranges [poff[s], poff[s] + cnt_s[s]) in record order, so pair j's record
+// is the last s with poff[s] <= j (binary search; empty ranges are skipped by
+// "last"); j itself is recovered later from (record, tile) by pair_index.
+// One thread per pair stays balanced however many tiles a record covers.
 __global__ void k_emit(const int64_t *__restrict__ counters, const uint32_t *__restrict__ poff,
                        const uint2 *__restrict__ trect, const uint32_t *__restrict__ gid,
-                       const ViewTable *__restrict__ vt, int64_t n, uint32_t *__restrict__ owner,
-                       uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+                       const ViewTable *__restrict__ vt, int64_t n, uint32_t *__restrict__ keys,
+                       uint32_t *__restrict__ vals) {
     const int64_t K = counters[kCntPairsUsed];
     const int64_t M = counters[kCntVisible];
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < K; j += (int64_t)gridDim.x * blockDim.x) {
@@ -439,7 +437,6 @@ __global__ void k_emit(const int64_t *__restrict__ counters, const uint32_t *__r
                 hi = mid;
         }
         const uint32_t s = (uint32_t)lo;
-        owner[j] = s;
         const uint32_t k = (uint32_t)j - poff[s];
         const uint2 tr = trect[s];
         const uint32_t tx0 = tr.x & 0xffffu, nx = (tr.x >> 16) - tx0 + 1u, ty0 = tr.y & 0xffffu;
@@ -448,7 +445,7 @@ __global__ void k_emit(const int64_t *__restrict__ counters, const uint32_t *__r
         const ViewInfo &V = vt->v[v];
         const uint32_t ty = ty0 + k / nx, tx = tx0 + k % nx;
         keys[j] = (uint32_t)V.tile_off + ty * (uint32_t)V.tiles_x + tx;
-        vals[j] = (uint32_t)j;
+        vals[j] = s;
     }
 }
 
@@ -456,14 +453,6 @@ __global__ void k_fill_u32_dev(uint32_t *p, const int64_t *n_dev, uint32_t val) 
     const int64_t n = *n_dev;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = val;
-}
-
-// record index of every sorted pair
-__global__ void k_pair_records(const int64_t *__restrict__ counters, const uint32_t *__restrict__ sorted_j,
-                               const uint32_t *__restrict__ owner, uint32_t *__restrict__ prec) {
-    const int64_t K = counters[kCntPairsUsed];
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < K; e += (int64_t)gridDim.x * blockDim.x)
-        prec[e] = owner[sorted_j[e]];
 }
 
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t val) {
@@ -878,34 +867,26 @@ void enqueue_binning(Call &c, const gsr_views *views) {
                            gid_sorted, rec, trect, cnt_s, inv, c.pp.g.rgb);
     uint32_t *pk0 = at<uint32_t>(ws, L.pk0), *pv0 = at<uint32_t>(ws, L.pv0);
     uint32_t *pk1 = at<uint32_t>(ws, L.pk1), *pv1 = at<uint32_t>(ws, L.pv1);
-    uint32_t *poff = at<uint32_t>(ws, L.poff), *owner = at<uint32_t>(ws, L.owner);
-    uint32_t *prec = at<uint32_t>(ws, L.prec);
+    uint32_t *poff = at<uint32_t>(ws, L.poff);
     // pair offsets of the records; the last block checks the pair capacity
     scan_exclusive(CntSrc{cnt_s}, OffSink{poff}, counters + kCntVisible, L.vn, ss, kIdOffsets,
                    PairTotal{counters, L.kcap}, st);
     if (L.vn > 0 && L.kcap > 0)
         hipLaunchKernelGGL(k_emit, dim3(grid_for(L.kcap, 256, 16384)), dim3(256), 0, st, counters, poff, trect,
-                           gid_sorted, vt, c.pp.n, owner, pk0, pv0);
-    // tile order (stable: depth order within a tile); the last pass maps pairs to records
-    const bool p_in1 = radix_sort(pk0, pv0, pk1, pv1, counters + kCntPairsUsed, L.kcap, L.tile_bits, so, 4, st,
-                                  owner, prec);
+                           gid_sorted, vt, c.pp.n, pk0, pv0);
+    // tile order (stable: depth order within a tile); the values are the pairs' records
+    const bool p_in1 = radix_sort(pk0, pv0, pk1, pv1, counters + kCntPairsUsed, L.kcap, L.tile_bits, so, 4, st);
     uint2 *ranges = at<uint2>(ws, L.ranges);
     hipLaunchKernelGGL(k_ranges, dim3(grid_for(L.T, 256, 4096)), dim3(256), 0, st, p_in1 ? pk1 : pk0,
                        (const int64_t *)counters, ranges, L.T);
-    if (L.kcap > 0 && L.tile_bits == 0)   // one tile: no sort pass, the emission order is the tile order
-        hipLaunchKernelGGL(k_pair_records, dim3(grid_for(L.kcap, 256, 16384)), dim3(256), 0, st, counters, pv0, owner,
-                           prec);
 }
 
-// emission index of every sorted pair (the sort's result buffer is fixed by the key bits)
-const uint32_t *pair_j(const Call &c) {
+// record index of every sorted pair (the sort's result buffer is fixed by the key bits)
+const uint32_t *pair_values(const Call &c) {
     const int passes = (c.L.tile_bits + 7) / 8;
     const bool in1 = (c.L.kcap > 0 && c.L.tile_bits > 0) ? (passes % 2 == 1) : false;
     return at<uint32_t>(c.ws, in1 ? c.L.pv1 : c.L.pv0);
 }
-
-// record index of every sorted pair
-const uint32_t *pair_values(const Call &c) { return at<uint32_t>(c.ws, c.L.prec); }
 
 const uint32_t *depth_sorted_gid(const Call &c) {
     const bool in1 = false;   // 4 passes over 32 bits: the result is back in the first buffer
@@ -954,7 +935,8 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
                           : (fused ? (c.count ? k_blend_bwd<true, true, 10> : k_blend_bwd<true, false, 10>)
                                    : (c.count ? k_blend_bwd<false, true, 10> : k_blend_bwd<false, false, 10>));
             hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, vt, at<float4>(c.ws, L.rec), pair_values(c),
-                               pair_j(c), at<uint2>(c.ws, L.ranges), counters, bo, li, gpairs);
+                               at<uint32_t>(c.ws, L.poff), at<uint2>(c.ws, L.trect), at<uint2>(c.ws, L.ranges),
+                               counters, bo, li, gpairs);
         }
     }
     if (fused) {

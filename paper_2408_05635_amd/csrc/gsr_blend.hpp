@@ -241,7 +241,7 @@ constexpr int kSeg = 32;   // list entries per segment (LDS: 4 waves x 4 rows x 
 template <bool FUSED, bool COUNT, int NV>
 __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__ vt, const float4 *__restrict__ rec,
                                                    const uint32_t *__restrict__ pair_rec,
-                                                   const uint32_t *__restrict__ pair_j,
+                                                   const uint32_t *__restrict__ poff, const uint2 *__restrict__ trect,
                                                    const uint2 *__restrict__ ranges, int64_t *__restrict__ counters,
                                                    BlendOut st, LossIn L, float *__restrict__ grad_pairs) {
     __shared__ float4 s_a[kBwdMaxWaves][kSeg], s_b[kBwdMaxWaves][kSeg], s_c[kBwdMaxWaves][kSeg];
@@ -250,6 +250,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
     // (row stride kSeg * 10 for both NV)
     __shared__ float s_acc[kBwdMaxWaves][4][kSeg * 10];
     __shared__ uint32_t s_wmax[kBwdMaxWaves];
+    __shared__ uint32_t s_j[kSeg];   // gradient-row slot of each entry of the segment
     __shared__ double s_loss[kBwdMaxWaves];
 
     // tile of this workgroup (tiles of all views, view by view)
@@ -340,9 +341,22 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
     }
     uint32_t bmax = rg.x;
     for (int w = 0; w < nw; ++w) bmax = s_wmax[w] > bmax ? s_wmax[w] : bmax;
+    // The gradient row of entry e: records own the rows [poff, poff + tiles)
+    // of their tile rectangles, row-major, so the slot follows from the
+    // record and this tile's place in its rectangle (~0u: not a valid entry).
+    auto row_of = [&](uint32_t e) -> uint32_t {
+        const uint32_t s = pair_rec[e];
+        if (s >= n_rec) return ~0u;   // never expected; keeps writes in bounds
+        const uint2 tr = trect[s];
+        const uint32_t tx0 = tr.x & 0xffffu, nx = (tr.x >> 16) - tx0 + 1u, ty0 = tr.y & 0xffffu;
+        const uint32_t j = poff[s] + ((uint32_t)ty - ty0) * nx + ((uint32_t)tx - tx0);
+        return j < n_pair ? j : ~0u;
+    };
     // entries behind every pixel's last contributor get zero rows
     for (uint32_t e = bmax + threadIdx.x; e < rg.y; e += blockDim.x) {
-        float *dst = grad_pairs + NV * (size_t)pair_j[e];
+        const uint32_t j = row_of(e);
+        if (j == ~0u) continue;
+        float *dst = grad_pairs + NV * (size_t)j;
 #pragma unroll
         for (int c = 0; c < NV; ++c) dst[c] = 0.0f;
     }
@@ -354,6 +368,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
     for (uint32_t seg_hi = bmax; seg_hi > rg.x;) {
         const uint32_t seg_lo = seg_hi - rg.x > (uint32_t)kSeg ? seg_hi - kSeg : rg.x;
         for (int c = lane; c < 4 * kSeg * 10; c += 64) acc[c] = 0.0f;
+        if (threadIdx.x < seg_hi - seg_lo) s_j[threadIdx.x] = row_of(seg_lo + threadIdx.x);   // read after the barrier
         if (wmax > seg_lo) {   // wave-uniform: this wave has pixels with entries in the segment
             const uint32_t hi = wmax < seg_hi ? wmax : seg_hi;
             const uint32_t e = seg_lo + lane;
@@ -449,7 +464,8 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
             for (int w = 0; w < nw; ++w)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) sum += s_acc[w][r][idx];
-            grad_pairs[NV * (size_t)pair_j[seg_lo + e] + c] = sum;
+            const uint32_t j = s_j[e];
+            if (j != ~0u) grad_pairs[NV * (size_t)j + c] = sum;
         }
         __syncthreads();
         seg_hi = seg_lo;

@@ -339,9 +339,7 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
                                                                 const uint32_t *__restrict__ vin,
                                                                 uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                                 const int64_t *n_dev, int64_t n_host, int shift,
-                                                                int dbits, SortState so,
-                                                                const uint32_t *__restrict__ map_in,
-                                                                uint32_t *__restrict__ map_out) {
+                                                                int dbits, SortState so) {
     __shared__ uint32_t s_off[256];
     __shared__ uint32_t s_w[kScanThreads / 64][256];
     const int64_t n = dev_count(n_dev, n_host);
@@ -388,7 +386,6 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
             if ((int64_t)pos < n) {   // always true for consistent counts; keeps writes in bounds
                 kout[pos] = key;
                 vout[pos] = val;
-                if (map_out) map_out[pos] = map_in[val];
             }
         }
         __syncthreads();
@@ -396,13 +393,10 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
 }
 
 // Sorts n (device count, <= cap) pairs by key bits [0, bits), using the
-// arrival counters and tags of passes pass0, pass0 + 1, ...  If map_out is
-// given, the last pass also writes map_out[i] = map_in[value of sorted pair
-// i] (bits must be > 0).  Returns true if the result is in (k1, v1), false
-// if in (k0, v0).
+// arrival counters and tags of passes pass0, pass0 + 1, ...  Returns true
+// if the result is in (k1, v1), false if in (k0, v0).
 inline bool radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const int64_t *n_dev, int64_t cap,
-                       int bits, const SortState &so, int pass0, hipStream_t st, const uint32_t *map_in = nullptr,
-                       uint32_t *map_out = nullptr) {
+                       int bits, const SortState &so, int pass0, hipStream_t st) {
     const int64_t nb = (cap + kChunk - 1) / kChunk;
     if (nb == 0 || bits <= 0) return false;
     bool in1 = false;
@@ -412,9 +406,8 @@ inline bool radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, c
         uint32_t *ko = in1 ? k0 : k1, *vo = in1 ? v0 : v1;
         hipLaunchKernelGGL(k_radix_count, dim3((unsigned)nb), dim3(kScanThreads), 0, st, ki, n_dev, cap, shift, dbits,
                            so, p);
-        const bool last = shift + 8 >= bits;
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kScanThreads), 0, st, ki, vi, ko, vo, n_dev, cap,
-                           shift, dbits, so, last ? map_in : nullptr, last ? map_out : nullptr);
+                           shift, dbits, so);
         in1 = !in1;
     }
     return in1;
