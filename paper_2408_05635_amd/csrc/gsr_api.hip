@@ -93,6 +93,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kRecGrad = 14;   // per-record parameter gradient: mu 3, q 4, log_s 3, logit 1, rgb 3
 constexpr int kRecBwdMaxBlocks = 2048;   // grid cap of the record backward (one pose row per block)
+constexpr int kEmitChunk = 1024;         // pairs per emission block
 // synchronisation region, cleared by every call: scan tickets (256 B), the
 // scans' look-back words, the sort passes' arrival counters and tagged words
 constexpr size_t kSyncTickets = 256;
@@ -108,7 +109,7 @@ struct Layout {
     int32_t G;            // total blend blocks
     int tile_bits;        // key bits of the tile sort
     size_t views, poses, counters, cnt, zkey, dk0, dv0, dk1, dv1, inv, rec, trect, cnt_s, poff, pk0, pv0, pk1, pv1,
-        ranges, tfinal, nlast, phash, gpairs, rgrad, losst, poseblk, sgbase, sync;
+        chunk, ranges, tfinal, nlast, phash, gpairs, rgrad, losst, poseblk, sgbase, sync;
     int64_t sort_groups;  // groups of sort blocks at the capacity
     // offsets in the sync region (cleared by every call): scan look-back
     // words, sort arrival counters, sort block words, sort group words
@@ -263,6 +264,7 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     L.pv0 = take(4 * kc);
     L.pk1 = take(4 * kc);
     L.pv1 = take(4 * kc);
+    L.chunk = take(4 * (size_t)((kc + kEmitChunk - 1) / kEmitChunk + 1));
     L.ranges = take(8 * (size_t)L.T);
     L.tfinal = take(4 * (size_t)L.P);
     L.nlast = take(4 * (size_t)L.P);
@@ -272,11 +274,12 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     L.losst = take(sizeof(double) * (size_t)L.T);
     L.poseblk = take(sizeof(double) * 12 * V * (size_t)std::max<int64_t>(
                                            std::min<int64_t>((L.vn + 255) / 256, kRecBwdMaxBlocks), 1));
-    const int64_t nb = std::max<int64_t>((std::max<int64_t>(L.vn, kcap) + kChunk - 1) / kChunk, 1);
+    const int64_t nb_scan = std::max<int64_t>((std::max<int64_t>(L.vn, kcap) + kChunk - 1) / kChunk, 1);
+    const int64_t nb = std::max<int64_t>(std::max(sort_blocks(L.vn), sort_blocks(kcap)), 1);
     L.sort_groups = (nb + kSortGroup - 1) / kSortGroup;
     L.sgbase = take(4 * 256 * (size_t)L.sort_groups);
     L.sync_status = kSyncTickets;
-    L.sync_done = align_up(L.sync_status + 8 * (size_t)nb);
+    L.sync_done = align_up(L.sync_status + 8 * (size_t)nb_scan);
     L.sync_words = align_up(L.sync_done + 4 * (size_t)kSortPasses * (size_t)(L.sort_groups + 1));
     L.sync_gwords = align_up(L.sync_words + 8 * 256 * (size_t)nb);
     L.sync_bytes = align_up(L.sync_gwords + 8 * 256 * (size_t)L.sort_groups);
@@ -399,9 +402,18 @@ struct CntSrc {
     const uint32_t *cnt;
     __device__ uint32_t operator()(int64_t i) const { return cnt[i]; }
 };
+// Pair offsets of the records; also the first record of every kEmitChunk
+// pairs (the record whose range holds pair m * kEmitChunk).
 struct OffSink {
-    uint32_t *off;
-    __device__ void operator()(int64_t s, uint32_t pos, uint32_t) const { off[s] = pos; }
+    uint32_t *off, *chunk_first;
+    int64_t n_chunks;   // capacity of chunk_first
+    __device__ void operator()(int64_t s, uint32_t pos, uint32_t cnt) const {
+        off[s] = pos;
+        if (cnt == 0) return;
+        for (int64_t m = ((int64_t)pos + kEmitChunk - 1) / kEmitChunk;
+             m * kEmitChunk < (int64_t)pos + cnt && m < n_chunks; ++m)
+            chunk_first[m] = (uint32_t)s;
+    }
 };
 
 // The pair total: the capacity check is made by the scan's last block.
@@ -417,27 +429,40 @@ struct PairTotal {
 };
 
 // Pair j: key = global tile id, value = its record.  Records own contiguous
-// ranges [poff[s], poff[s] + cnt_s[s]) in record order, so pair j's record
-// is the last s with poff[s] <= j (binary search; empty ranges are skipped by
-// "last"); j itself is recovered later from (record, tile) by pair_index.
-// One thread per pair stays balanced however many tiles a record covers.
-__global__ void k_emit(const int64_t *__restrict__ counters, const uint32_t *__restrict__ poff,
-                       const uint2 *__restrict__ trect, const uint32_t *__restrict__ gid,
-                       const ViewTable *__restrict__ vt, int64_t n, uint32_t *__restrict__ keys,
-                       uint32_t *__restrict__ vals) {
+// ranges [poff[s], poff[s] + cnt_s[s]) in record order (every visible record
+// touches at least one tile), so pair j's record is the last s with
+// poff[s] <= j.  A block takes kEmitChunk consecutive pairs: their records
+// lie between the chunk's first record and the next chunk's, at most
+// kEmitChunk + 1 of them; their offsets are staged in LDS and each pair
+// searches there.  j itself is recovered later from (record, tile).
+__global__ __launch_bounds__(256) void k_emit(const int64_t *__restrict__ counters, const uint32_t *__restrict__ poff,
+                                              const uint32_t *__restrict__ chunk_first,
+                                              const uint2 *__restrict__ trect, const uint32_t *__restrict__ gid,
+                                              const ViewTable *__restrict__ vt, int64_t n,
+                                              uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    __shared__ uint32_t s_off[kEmitChunk + 1];
     const int64_t K = counters[kCntPairsUsed];
     const int64_t M = counters[kCntVisible];
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < K; j += (int64_t)gridDim.x * blockDim.x) {
-        int64_t lo = 0, hi = M;   // poff[0] = 0 <= j < poff[M] (= K)
+    const int64_t j0 = (int64_t)blockIdx.x * kEmitChunk;
+    if (j0 >= K) return;   // block-uniform
+    const int64_t s0 = chunk_first[blockIdx.x];
+    const int64_t s1 = j0 + kEmitChunk < K ? (int64_t)chunk_first[blockIdx.x + 1] + 1 : M;   // window end
+    const int nwin = (int)((s1 - s0 < kEmitChunk + 1 ? s1 - s0 : kEmitChunk + 1));
+    for (int k = threadIdx.x; k < nwin; k += blockDim.x) s_off[k] = poff[s0 + k];
+    __syncthreads();
+    for (int q = threadIdx.x; q < kEmitChunk; q += blockDim.x) {
+        const int64_t j = j0 + q;
+        if (j >= K) break;
+        int lo = 0, hi = nwin;   // s_off[0] <= j; find the last entry <= j
         while (hi - lo > 1) {
-            const int64_t mid = (lo + hi) >> 1;
-            if ((int64_t)poff[mid] <= j)
+            const int mid = (lo + hi) >> 1;
+            if ((int64_t)s_off[mid] <= j)
                 lo = mid;
             else
                 hi = mid;
         }
-        const uint32_t s = (uint32_t)lo;
-        const uint32_t k = (uint32_t)j - poff[s];
+        const uint32_t s = (uint32_t)(s0 + lo);
+        const uint32_t k = (uint32_t)j - s_off[lo];
         const uint2 tr = trect[s];
         const uint32_t tx0 = tr.x & 0xffffu, nx = (tr.x >> 16) - tx0 + 1u, ty0 = tr.y & 0xffffu;
         int v = (int)(gid[s] / (uint64_t)n);
@@ -869,11 +894,13 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     uint32_t *pk1 = at<uint32_t>(ws, L.pk1), *pv1 = at<uint32_t>(ws, L.pv1);
     uint32_t *poff = at<uint32_t>(ws, L.poff);
     // pair offsets of the records; the last block checks the pair capacity
-    scan_exclusive(CntSrc{cnt_s}, OffSink{poff}, counters + kCntVisible, L.vn, ss, kIdOffsets,
+    uint32_t *chunk_first = at<uint32_t>(ws, L.chunk);
+    const int64_t n_chunks = (L.kcap + kEmitChunk - 1) / kEmitChunk;
+    scan_exclusive(CntSrc{cnt_s}, OffSink{poff, chunk_first, n_chunks}, counters + kCntVisible, L.vn, ss, kIdOffsets,
                    PairTotal{counters, L.kcap}, st);
     if (L.vn > 0 && L.kcap > 0)
-        hipLaunchKernelGGL(k_emit, dim3(grid_for(L.kcap, 256, 16384)), dim3(256), 0, st, counters, poff, trect,
-                           gid_sorted, vt, c.pp.n, pk0, pv0);
+        hipLaunchKernelGGL(k_emit, dim3((unsigned)n_chunks), dim3(256), 0, st, counters, poff,
+                           (const uint32_t *)chunk_first, trect, gid_sorted, vt, c.pp.n, pk0, pv0);
     // tile order (stable: depth order within a tile); the values are the pairs' records
     const bool p_in1 = radix_sort(pk0, pv0, pk1, pv1, counters + kCntPairsUsed, L.kcap, L.tile_bits, so, 4, st);
     uint2 *ranges = at<uint2>(ws, L.ranges);

@@ -227,6 +227,17 @@ inline void scan_exclusive(Src src, Sink sink, const int64_t *n_dev, int64_t n_c
 
 constexpr int kSortGroup = 64;
 
+// Items per thread of a sort pass: small blocks (1024 items) keep every CU
+// busy and each block's ranking rounds few for the sizes of one frame;
+// larger inputs use 4096-item blocks, whose fewer count words and groups
+// cost less than the longer rounds.
+constexpr int64_t kSmallSortCap = 2ll << 20;
+inline int sort_items(int64_t cap) { return cap <= kSmallSortCap ? 4 : 16; }
+inline int64_t sort_blocks(int64_t cap) {
+    const int64_t chunk = (int64_t)kScanThreads * sort_items(cap);
+    return (cap + chunk - 1) / chunk;
+}
+
 // Per-call state of the sort passes.
 struct SortState {
     uint64_t *words;     // [256 * blocks] tagged digit counts, then offsets within the group (cleared per call)
@@ -259,13 +270,14 @@ __device__ __forceinline__ bool arrive_last(uint32_t *counter, uint32_t of) {
     return s_last != 0u;
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(kScanThreads) void k_radix_count(const uint32_t *__restrict__ kin, const int64_t *n_dev,
                                                               int64_t n_host, int shift, int dbits, SortState so,
                                                               int pass) {
     __shared__ uint32_t s_cnt[256];
     const uint32_t t = threadIdx.x;
     const int64_t n = dev_count(n_dev, n_host);
-    const int64_t nb = (n + kChunk - 1) / kChunk;
+    const int64_t nb = (n + (kScanThreads * ITEMS) - 1) / (kScanThreads * ITEMS);
     const int64_t b = blockIdx.x;
     if (b >= nb) return;   // block-uniform
     const int nd = 1 << dbits;
@@ -273,15 +285,15 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_count(const uint32_t *__
     const uint32_t tag = (uint32_t)pass + 1u;
     s_cnt[t] = 0u;
     __syncthreads();
-    const int64_t base = b * kChunk;
-    uint32_t key[kScanItems];   // all loads in flight at once
+    const int64_t base = b * (kScanThreads * ITEMS);
+    uint32_t key[ITEMS];   // all loads in flight at once
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const int64_t i = base + (int64_t)j * kScanThreads + t;
         key[j] = i < n ? kin[i] : 0u;
     }
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const bool valid = base + (int64_t)j * kScanThreads + t < n;
         const uint32_t d = (key[j] >> shift) & mask;
         const uint64_t peers = match_digit(d, dbits, ballot(valid));
@@ -334,37 +346,44 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_count(const uint32_t *__
     for (int64_t q = 0; q < ng; ++q) so.gbase[(size_t)q * 256 + t] += dbase;
 }
 
-// Stable scatter: items keep their input order within a digit.
+// Stable scatter: items keep their input order within a digit.  The block
+// first ranks its items within their digits (round by round, in input
+// order), then places them in LDS in digit order and writes each digit's
+// run to consecutive global positions, so that the stores are coalesced
+// runs instead of one transaction per item.
+template <int ITEMS>
 __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *__restrict__ kin,
                                                                 const uint32_t *__restrict__ vin,
                                                                 uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                                 const int64_t *n_dev, int64_t n_host, int shift,
                                                                 int dbits, SortState so) {
-    __shared__ uint32_t s_off[256];
+    constexpr int kItems = kScanThreads * ITEMS;
+    __shared__ uint32_t s_goff[256];   // global position of the block's first item of each digit
+    __shared__ uint32_t s_cnt[256];    // running count per digit, then the digit's first slot in s_k
     __shared__ uint32_t s_w[kScanThreads / 64][256];
+    __shared__ uint32_t s_k[kItems], s_v[kItems];
     const int64_t n = dev_count(n_dev, n_host);
     const int64_t b = blockIdx.x;
-    const int64_t base = b * kChunk;
+    const int64_t base = b * kItems;
     if (base >= n) return;   // block-uniform
     const int nd = 1 << dbits;
     const uint32_t mask = (uint32_t)nd - 1u;
     const uint32_t t = threadIdx.x, wave = t >> 6;
-    s_off[t] = (uint32_t)so.words[(size_t)b * 256 + t] + so.gbase[(size_t)(b / kSortGroup) * 256 + t];
-    uint32_t keys[kScanItems], vals[kScanItems];   // all loads in flight at once
+    s_goff[t] = (uint32_t)so.words[(size_t)b * 256 + t] + so.gbase[(size_t)(b / kSortGroup) * 256 + t];
+    s_cnt[t] = 0u;
+    uint32_t keys[ITEMS], vals[ITEMS], lrank[ITEMS];   // all loads in flight at once
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const int64_t i = base + (int64_t)j * kScanThreads + t;
         keys[j] = i < n ? kin[i] : 0u;
         vals[j] = i < n ? vin[i] : 0u;
+        lrank[j] = 0u;
     }
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         if (base + (int64_t)j * kScanThreads >= n) break;   // block-uniform
-        const int64_t i = base + (int64_t)j * kScanThreads + t;
-        const bool valid = i < n;
-        const uint32_t key = keys[j];
-        const uint32_t val = vals[j];
-        const uint32_t d = (key >> shift) & mask;
+        const bool valid = base + (int64_t)j * kScanThreads + t < n;
+        const uint32_t d = (keys[j] >> shift) & mask;
         for (int k = t; k < (kScanThreads / 64) * 256; k += kScanThreads) (&s_w[0][0])[k] = 0u;
         __syncthreads();
         const uint64_t peers = match_digit(d, dbits, ballot(valid));
@@ -372,23 +391,44 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
         if (valid && rank == 0) s_w[wave][d] = (uint32_t)__popcll(peers);
         __syncthreads();
         if ((int)t < nd) {
-            uint32_t run = s_off[t];
+            uint32_t run = s_cnt[t];
             for (int w = 0; w < kScanThreads / 64; ++w) {
                 const uint32_t c = s_w[w][t];
                 s_w[w][t] = run;
                 run += c;
             }
-            s_off[t] = run;
+            s_cnt[t] = run;
         }
         __syncthreads();
-        if (valid) {
-            const uint32_t pos = s_w[wave][d] + rank;
-            if ((int64_t)pos < n) {   // always true for consistent counts; keeps writes in bounds
-                kout[pos] = key;
-                vout[pos] = val;
+        if (valid) lrank[j] = s_w[wave][d] + rank;
+        __syncthreads();   // s_w is cleared by the next round
+    }
+    // digits' first slots in the block's digit-ordered staging
+    uint32_t tot;
+    const uint32_t lbase = block_excl_scan_u32<kScanThreads>(s_cnt[t], tot);
+    s_cnt[t] = lbase;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        if (base + (int64_t)j * kScanThreads + t < n) {
+            const uint32_t d = (keys[j] >> shift) & mask;
+            const uint32_t lp = s_cnt[d] + lrank[j];
+            if (lp < (uint32_t)kItems) {   // always true for consistent counts
+                s_k[lp] = keys[j];
+                s_v[lp] = vals[j];
             }
         }
-        __syncthreads();
+    }
+    __syncthreads();
+    const int nblk = (int)(n - base < kItems ? n - base : kItems);
+    for (int i = t; i < nblk; i += kScanThreads) {
+        const uint32_t key = s_k[i];
+        const uint32_t d = (key >> shift) & mask;
+        const uint32_t pos = s_goff[d] + ((uint32_t)i - s_cnt[d]);
+        if ((int64_t)pos < n) {   // always true for consistent counts; keeps writes in bounds
+            kout[pos] = key;
+            vout[pos] = s_v[i];
+        }
     }
 }
 
@@ -397,17 +437,18 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
 // if the result is in (k1, v1), false if in (k0, v0).
 inline bool radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const int64_t *n_dev, int64_t cap,
                        int bits, const SortState &so, int pass0, hipStream_t st) {
-    const int64_t nb = (cap + kChunk - 1) / kChunk;
+    const int64_t nb = sort_blocks(cap);
     if (nb == 0 || bits <= 0) return false;
+    const bool small = sort_items(cap) == 4;
     bool in1 = false;
     for (int shift = 0, p = pass0; shift < bits; shift += 8, ++p) {
         const int dbits = bits - shift < 8 ? bits - shift : 8;
         uint32_t *ki = in1 ? k1 : k0, *vi = in1 ? v1 : v0;
         uint32_t *ko = in1 ? k0 : k1, *vo = in1 ? v0 : v1;
-        hipLaunchKernelGGL(k_radix_count, dim3((unsigned)nb), dim3(kScanThreads), 0, st, ki, n_dev, cap, shift, dbits,
-                           so, p);
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kScanThreads), 0, st, ki, vi, ko, vo, n_dev, cap,
-                           shift, dbits, so);
+        hipLaunchKernelGGL(small ? k_radix_count<4> : k_radix_count<16>, dim3((unsigned)nb), dim3(kScanThreads), 0,
+                           st, ki, n_dev, cap, shift, dbits, so, p);
+        hipLaunchKernelGGL(small ? k_radix_scatter<4> : k_radix_scatter<16>, dim3((unsigned)nb), dim3(kScanThreads),
+                           0, st, ki, vi, ko, vo, n_dev, cap, shift, dbits, so);
         in1 = !in1;
     }
     return in1;
