@@ -1,0 +1,156 @@
+"""Edge cases of the rasteriser on the GPU against the oracle: no Gaussians,
+nothing visible, one Gaussian covering the whole image, the maximum number
+of views in one call, one-pixel and ragged images, and the pose-only
+(6-partial) backward."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2408_05635_amd import scenes
+from gpu_util import GRAD_TOL, IMG_TOL, RES_MARGIN, dev_params, dev_poses, grad_errors, image_errors, \
+    oracle_targets, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rast():
+    from paper_2408_05635_amd import raster
+    return raster.Rasterizer(0)
+
+
+def _workload(g, cams, quat, trans, tquat=None, ttrans=None, name="edge"):
+    views = scenes.Views(list(cams), np.asarray(quat, np.float32), np.asarray(trans, np.float32))
+    tv = views if tquat is None else scenes.Views(list(cams), np.asarray(tquat, np.float32),
+                                                  np.asarray(ttrans, np.float32))
+    return scenes.Workload(name, g, views, tv, weights=dict(w_rgb=0.5, w_depth=1.0, w_sil=1.0, w_prior=0.0))
+
+
+def _run(rast, w, tile=(16, 16), gauss_grads=True):
+    """GPU and oracle on the same inputs, with the oracle's ambiguous pixels
+    weighted out on both sides."""
+    from paper_2408_05635_amd.raster import RenderOptions
+    tg = oracle_targets(w)
+    otg = oracle.Targets(tg["rgb"], tg["depth"], tg["sil"])
+    r = oracle.run(w.gaussians, w.views, oracle.Options(**w.weights), otg, want_grads=True, mask_ambiguous=True,
+                   res_margin=RES_MARGIN)
+    ok = r.ambiguous == 0
+    g = dev_params(w.gaussians)
+    q, t = dev_poses(w.views)
+    out = rast.render_loss_grad(g, q, t, w.views.cams, to_dev({**tg, "weight": ok.astype(np.float32)}),
+                                RenderOptions(**w.weights, tile=tile, gauss_grads=gauss_grads))
+    torch.cuda.synchronize()
+    return out, r, ok
+
+
+def _check(out, r, ok, w, label, keys=None):
+    ie = image_errors(out, r, w.views.cams, ok)
+    # The loss is a weighted mean of |image - target| terms with per-pixel
+    # weights summing to at most 1 per channel, so an image error of IMG_TOL
+    # relative to the image's largest value moves it by at most
+    # IMG_TOL * (3 w_rgb max|C| + w_depth max|D| + w_sil max|S|).  (Relative to
+    # the loss itself no bound follows: a nearly matched one-pixel view has a
+    # loss close to zero.)
+    wt = w.weights
+    bound = IMG_TOL * (3 * wt["w_rgb"] * np.abs(r.rgb).max() + wt["w_depth"] * np.abs(r.depth).max() +
+                       wt["w_sil"] * np.abs(r.sil).max())
+    la = float(np.abs(out["loss"].cpu().numpy() - r.loss).max())
+    ge = grad_errors(out, r.grads, keys=keys)
+    print(f"{label}: ambiguous={int((~ok).sum())}/{ok.size} loss abs err={la:.2e} (bound {bound:.2e}) "
+          f"images={ie} grads={ge}")
+    assert max(ie.values()) <= IMG_TOL and la <= bound
+    assert max(ge.values()) <= GRAD_TOL, ge
+
+
+def _empty_gaussians():
+    z = lambda *s: np.zeros(s, np.float32)  # noqa: E731
+    return scenes.Gaussians(means=z(0, 3), quats=z(0, 4), log_scales=z(0, 3), opacity_logits=z(0), rgb=z(0, 3))
+
+
+def test_no_gaussians(rast):
+    """N = 0: black images, the loss of the targets alone, zero pose gradients."""
+    base = scenes.tiny_scene(31, n=20)
+    w = _workload(_empty_gaussians(), base.views.cams, base.views.quat, base.views.trans)
+    w.target_gaussians = base.gaussians          # targets from a non-empty scene
+    out, r, ok = _run(rast, w)
+    for k in ("rgb", "depth", "sil"):
+        assert torch.all(out[k] == 0)
+    assert np.allclose(out["loss"].cpu().numpy(), r.loss, rtol=1e-6, atol=0) and r.loss[0] > 0
+    for k in ("dq_t", "dt", "dq_c", "dc"):
+        assert torch.all(out[k] == 0)
+    assert out["g_means"].shape == (0, 3)
+
+
+def test_nothing_visible(rast):
+    """Every Gaussian behind the near plane: no records, no pairs, black images."""
+    base = scenes.tiny_scene(32, n=30)
+    g = base.gaussians
+    g2 = scenes.Gaussians(means=(g.means * np.array([1, 1, -1], np.float32)).astype(np.float32), quats=g.quats,
+                          log_scales=g.log_scales, opacity_logits=g.opacity_logits, rgb=g.rgb)
+    w = _workload(g2, base.views.cams, base.views.quat, base.views.trans)
+    w.target_gaussians = g
+    out, r, ok = _run(rast, w)
+    for k in ("rgb", "depth", "sil"):
+        assert torch.all(out[k] == 0)
+    assert np.allclose(out["loss"].cpu().numpy(), r.loss, rtol=1e-6, atol=0)
+    for k in ("g_means", "g_quats", "g_log_scales", "g_opacity_logits", "g_rgb", "dq_t", "dt", "dq_c", "dc"):
+        assert torch.all(out[k] == 0), k
+    m, kk, o = rast.read_counters(rast.shared_workspace())
+    assert m == 0 and kk == 0 and o == 0
+
+
+def test_one_gaussian_covers_the_image(rast):
+    """A 1 m Gaussian 1.2 m in front of the camera touches every tile and
+    saturates the transmittance; a few small ones in front and behind it."""
+    rng = np.random.default_rng(33)
+    n = 12
+    means = np.concatenate([[[0.05, -0.03, 1.2]], np.stack([rng.uniform(-0.3, 0.3, n - 1),
+                                                             rng.uniform(-0.2, 0.2, n - 1),
+                                                             rng.uniform(0.6, 2.5, n - 1)], 1)]).astype(np.float32)
+    ls = np.concatenate([[[0.0, -0.2, 0.1]], rng.normal(-2.5, 0.3, (n - 1, 3))]).astype(np.float32)
+    g = scenes.Gaussians(means=means, quats=scenes.random_unit_quats(rng, n), log_scales=ls,
+                         opacity_logits=np.concatenate([[3.0], rng.normal(0.5, 1.0, n - 1)]).astype(np.float32),
+                         rgb=rng.uniform(0, 1, (n, 3)).astype(np.float32))
+    base = scenes.tiny_scene(33, n=4, width=48, height=40)
+    w = _workload(g, base.views.cams, base.views.quat, base.views.trans, base.target_views.quat,
+                  base.target_views.trans)
+    for tile in ((16, 16), (8, 8)):
+        out, r, ok = _run(rast, w, tile)
+        _check(out, r, ok, w, f"cover {tile}")
+
+
+def test_maximum_views_in_one_call(rast):
+    """GSR_MAX_VIEWS = 64 small views of one scene, each at its own pose."""
+    from paper_2408_05635_amd import _abi
+    base = scenes.tiny_scene(34, n=60, width=24, height=16)
+    V = _abi.GSR_MAX_VIEWS
+    rng = np.random.default_rng(34)
+    q = np.tile(base.views.quat, (V, 1)) + rng.normal(0, 0.03, (V, 4)).astype(np.float32)
+    t = rng.normal(0, 0.05, (V, 3)).astype(np.float32)
+    w = _workload(base.gaussians, [base.views.cams[0]] * V, q, t, q + rng.normal(0, 0.01, (V, 4)).astype(np.float32),
+                  t + rng.normal(0, 0.005, (V, 3)).astype(np.float32))
+    out, r, ok = _run(rast, w)
+    _check(out, r, ok, w, "64 views")
+
+
+@pytest.mark.parametrize("W,H,tile", [(1, 1, (16, 16)), (33, 17, (16, 8)), (17, 33, (8, 16)), (9, 7, (8, 8))])
+def test_one_pixel_and_ragged_images(rast, W, H, tile):
+    base = scenes.tiny_scene(35 + W, n=30, width=W, height=H, spread=0.2)
+    w = _workload(base.gaussians, base.views.cams, base.views.quat, base.views.trans, base.target_views.quat,
+                  base.target_views.trans)
+    out, r, ok = _run(rast, w, tile)
+    if ok.sum() == 0:
+        pytest.skip("every pixel ambiguous at this seed")
+    _check(out, r, ok, w, f"{W}x{H} tile {tile}")
+
+
+def test_pose_only_backward_matches_oracle(rast):
+    """The 6-partial backward (Gaussian gradients off) gives the oracle's pose gradients."""
+    w = scenes.config1()
+    out, r, ok = _run(rast, w, gauss_grads=False)
+    assert out.get("g_means") is None
+    _check(out, r, ok, w, "pose only", keys=["dq_t", "dt", "dq_c", "dc"])
+    w2 = scenes.config2(n_views=2, n=40000)
+    out, r, ok = _run(rast, w2, gauss_grads=False)
+    _check(out, r, ok, w2, "pose only, 2 room views", keys=["dq_t", "dt", "dq_c", "dc"])
