@@ -342,10 +342,12 @@ __global__ __launch_bounds__(256) void k_project_count(ProjParams pp, const View
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= pp.n) return;
     const GaussIn p = load_gauss<ISO>(pp.g, i);
+    GaussPre pre;   // once for all views
+    prep_gauss<ISO>(p, pre);
     const int V = vt->n_views;
     for (int v = 0; v < V; ++v) {
         Proj r;
-        project<false, ISO>(p, poses[v], vt->v[v], pp.z_near, pp.blur, r);
+        project_pre<false, ISO>(p, pre, poses[v], vt->v[v], pp.z_near, pp.blur, r);
         uint32_t c = 0;
         if (r.visible) {
             uint32_t a, b;
@@ -631,7 +633,7 @@ __global__ __launch_bounds__(256) void k_record_bwd(ProjParams pp, const ViewTab
         for (int k = 0; k < 4; ++k) pg.q[k] = 0.0;
         pg.logit = 0.0;
         double gX[3], GW[9];
-        project_backward<ISO>(p, poses[v], vt->v[v], r, g2, pg, gX, GW);
+        project_backward<ISO, NV == 10>(p, poses[v], vt->v[v], r, g2, pg, gX, GW);
         if (want_gauss) {
             float *o = rgrad + kRecGrad * (size_t)s;
             for (int k = 0; k < 3; ++k) o[k] = (float)pg.mu[k];

@@ -106,13 +106,41 @@ struct Proj {
     int32_t px0, px1, py0, py1;   // clamped pixel rectangle of the binning radius (inclusive)
 };
 
-// Project Gaussian p into view (pose, camera).  Culls: z <= z_near, 255 o <= 1,
-// det(Sigma') <= 0, non-finite values, rectangle outside the image.  With
-// ISO, Sigma = s^2 I, so M = W Sigma W^T = s^2 I (W is a rotation) and no
-// rotation or covariance product is formed.
+// The view-independent part of a projection: opacity, squared scales,
+// rotation and world covariance (the same FP64 operations whichever view).
+struct GaussPre {
+    double o;
+    double s2[3];
+    double Rg[9];
+    double Sig[9];
+};
+
+template <bool ISO>
+__device__ __forceinline__ void prep_gauss(const GaussIn &p, GaussPre &g) {
+    g.o = 1.0 / (1.0 + exp(-p.logit));
+    if constexpr (ISO) {
+        g.s2[0] = g.s2[1] = g.s2[2] = exp(2.0 * p.ls[0]);
+    } else {
+        for (int k = 0; k < 3; ++k) g.s2[k] = exp(2.0 * p.ls[k]);
+        quat_to_rot_f64(p.q[0], p.q[1], p.q[2], p.q[3], g.Rg);
+        for (int i = 0; i < 3; ++i)
+            for (int j = i; j < 3; ++j) {
+                const double v = g.Rg[3 * i] * g.s2[0] * g.Rg[3 * j] + g.Rg[3 * i + 1] * g.s2[1] * g.Rg[3 * j + 1] +
+                                 g.Rg[3 * i + 2] * g.s2[2] * g.Rg[3 * j + 2];
+                g.Sig[3 * i + j] = v;
+                g.Sig[3 * j + i] = v;
+            }
+    }
+}
+
+// Project Gaussian p (view-independent part g) into view (pose, camera).
+// Culls: z <= z_near, 255 o <= 1, det(Sigma') <= 0, non-finite values,
+// rectangle outside the image.  With ISO, Sigma = s^2 I, so
+// M = W Sigma W^T = s^2 I (W is a rotation) and no rotation or covariance
+// product is formed.
 template <bool FULL, bool ISO>
-__device__ __forceinline__ void project(const GaussIn &p, const PoseF64 &pose, const ViewInfo &cam, double z_near,
-                                        double blur, Proj &r) {
+__device__ __forceinline__ void project_pre(const GaussIn &p, const GaussPre &g, const PoseF64 &pose,
+                                            const ViewInfo &cam, double z_near, double blur, Proj &r) {
     r.visible = false;
     const double *W = pose.W;
     for (int k = 0; k < 3; ++k)
@@ -120,21 +148,16 @@ __device__ __forceinline__ void project(const GaussIn &p, const PoseF64 &pose, c
     const double x = r.X[0], y = r.X[1], z = r.X[2];
     r.z32 = (float)z;
     if (!(z > z_near)) return;
-    r.o = 1.0 / (1.0 + exp(-p.logit));
+    r.o = g.o;
     if (!(255.0 * r.o > 1.0)) return;
+    for (int k = 0; k < 3; ++k) r.s2[k] = g.s2[k];
     if constexpr (ISO) {
-        r.s2[0] = r.s2[1] = r.s2[2] = exp(2.0 * p.ls[0]);
         for (int k = 0; k < 9; ++k) r.M[k] = (k % 4 == 0) ? r.s2[0] : 0.0;
     } else {
-        for (int k = 0; k < 3; ++k) r.s2[k] = exp(2.0 * p.ls[k]);
-        quat_to_rot_f64(p.q[0], p.q[1], p.q[2], p.q[3], r.Rg);
-        for (int i = 0; i < 3; ++i)
-            for (int j = i; j < 3; ++j) {
-                const double v = r.Rg[3 * i] * r.s2[0] * r.Rg[3 * j] + r.Rg[3 * i + 1] * r.s2[1] * r.Rg[3 * j + 1] +
-                                 r.Rg[3 * i + 2] * r.s2[2] * r.Rg[3 * j + 2];
-                r.Sig[3 * i + j] = v;
-                r.Sig[3 * j + i] = v;
-            }
+        for (int k = 0; k < 9; ++k) {
+            r.Rg[k] = g.Rg[k];
+            r.Sig[k] = g.Sig[k];
+        }
         // M = W Sigma W^T
         double WS[9];
         for (int i = 0; i < 3; ++i)
@@ -191,6 +214,14 @@ __device__ __forceinline__ void project(const GaussIn &p, const PoseF64 &pose, c
     r.visible = true;
 }
 
+template <bool FULL, bool ISO>
+__device__ __forceinline__ void project(const GaussIn &p, const PoseF64 &pose, const ViewInfo &cam, double z_near,
+                                        double blur, Proj &r) {
+    GaussPre g;
+    prep_gauss<ISO>(p, g);
+    project_pre<FULL, ISO>(p, g, pose, cam, z_near, blur, r);
+}
+
 // Chain rule from the per-record 2D gradient (dmx, dmy, dl11, dl21, dl22, do,
 // dr, dg, db, dz) to the raw parameters of Gaussian p and to the pose
 // partials of this view: gX (dL/dX, which sums to dL/dt) and
@@ -199,7 +230,9 @@ struct ParamGrad {
     double mu[3], q[4], ls[3], logit, rgb[3];
 };
 
-template <bool ISO>
+// GAUSS = false: only the pose partials (gX, GW) are formed, not the
+// Gaussian's own parameter gradients.
+template <bool ISO, bool GAUSS = true>
 __device__ __forceinline__ void project_backward(const GaussIn &p, const PoseF64 &pose, const ViewInfo &cam,
                                                  const Proj &r, const float *g2, ParamGrad &pg, double gX[3],
                                                  double GW[9]) {
@@ -237,7 +270,8 @@ __device__ __forceinline__ void project_backward(const GaussIn &p, const PoseF64
     gX[1] = dJ[5] * (-fy * iz2) + dmy * fy * iz;
     gX[2] = dJ[0] * (-fx * iz2) + dJ[2] * (2.0 * fx * x * iz3) + dJ[4] * (-fy * iz2) + dJ[5] * (2.0 * fy * y * iz3) -
             dmx * fx * x * iz2 - dmy * fy * y * iz2 + dz;
-    for (int k = 0; k < 3; ++k) pg.mu[k] += W[k] * gX[0] + W[3 + k] * gX[1] + W[6 + k] * gX[2];
+    if constexpr (GAUSS)
+        for (int k = 0; k < 3; ++k) pg.mu[k] += W[k] * gX[0] + W[3 + k] * gX[1] + W[6 + k] * gX[2];
     // M = W Sigma W^T: dSigma = W^T dM W; dW = 2 dM W Sigma (+ gX mu^T from X = W mu + t)
     if constexpr (ISO) {
         // Sigma = s^2 I: dW = gX mu^T + 2 s^2 dM W, and dL/dlog s = 2 s^2 tr(W^T dM W) = 2 s^2 tr(dM)
@@ -245,7 +279,7 @@ __device__ __forceinline__ void project_backward(const GaussIn &p, const PoseF64
             for (int j = 0; j < 3; ++j)
                 GW[3 * i + j] = gX[i] * p.mu[j] + 2.0 * r.s2[0] *
                                                       (dM[3 * i] * W[j] + dM[3 * i + 1] * W[3 + j] + dM[3 * i + 2] * W[6 + j]);
-        pg.ls[0] += 2.0 * r.s2[0] * (dM[0] + dM[4] + dM[8]);
+        if constexpr (GAUSS) pg.ls[0] += 2.0 * r.s2[0] * (dM[0] + dM[4] + dM[8]);
         return;
     } else {
     double WSg[9];
@@ -256,6 +290,7 @@ __device__ __forceinline__ void project_backward(const GaussIn &p, const PoseF64
         for (int j = 0; j < 3; ++j)
             GW[3 * i + j] = gX[i] * p.mu[j] +
                             2.0 * (dM[3 * i] * WSg[j] + dM[3 * i + 1] * WSg[3 + j] + dM[3 * i + 2] * WSg[6 + j]);
+    if constexpr (!GAUSS) return;
     double T1[9], dS[9];
     for (int i = 0; i < 3; ++i)   // T1 = W^T dM
         for (int j = 0; j < 3; ++j) T1[3 * i + j] = W[i] * dM[j] + W[3 + i] * dM[3 + j] + W[6 + i] * dM[6 + j];
