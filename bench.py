@@ -20,9 +20,10 @@ Reported (one JSON line):
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample
   pose_fd       FP32 central-difference check of the pose gradients
   next_rows     the steps around the path: the 40-iteration tracking loop
-                of one view as one graph replay, the mapping Adam step
-                (HBM roofline), new Gaussians from a 640x480 RGB-D frame,
-                and the batched step with isotropic Gaussians
+                of one view as one graph replay, the mapping loop (10
+                iterations per graph replay), the mapping Adam step (HBM
+                roofline), new Gaussians from a 640x480 RGB-D frame, and the
+                batched step with isotropic Gaussians
 """
 from __future__ import annotations
 
@@ -284,6 +285,37 @@ def next_rows_bench(rast, raster, scenes, w, g, q, t, targets, opts, timed, args
                            rotation_err_deg=[e0[0], e1[0]], centre_err_cm=[100 * e0[1], 100 * e1[1]],
                            loss_first_last=[float(lh[0]), float(lh[-1])])
     print(f"[bench] tracking {ms_frame:.3f} ms per 40-iteration frame", file=sys.stderr, flush=True)
+
+    # mapping loop: the mapping configuration's perturbed 500k map, 8 keyframes, 10 iterations
+    # (render + loss + Gaussian gradients + Adam step) per graph replay
+    wm = scenes.config3()
+    t32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)  # noqa: E731
+    Gm, Gt = wm.gaussians, wm.truth
+    gm = raster.GaussianParams(t32(Gm.means), t32(Gm.quats), t32(Gm.log_scales), t32(Gm.opacity_logits), t32(Gm.rgb))
+    gt = raster.GaussianParams(t32(Gt.means), t32(Gt.quats), t32(Gt.log_scales), t32(Gt.opacity_logits), t32(Gt.rgb))
+    qm, tm = t32(wm.views.quat), t32(wm.views.trans)
+    om = raster.RenderOptions(**{**wm.weights, "w_prior": 0.0}, tile=opts.tile)
+    trgb, tdep, tsil, _ = rast.forward(gt, qm, tm, wm.views.cams, om)
+    tgm = dict(rgb=trgb.clone(), depth=tdep.clone(), sil=tsil.clone())
+    with torch.cuda.stream(s):
+        mp = rast.map_iterate(gm, qm, tm, wm.views.cams, tgm, om, raster.MapAdam(), 10, capture=True)
+        rast.launch_graph(mp["graph"])
+        s.synchronize()
+        l0 = mp["loss_hist"].sum(1).cpu().numpy()
+        reps = max(3, args.steps // 4)
+        ms_map = timed(lambda: rast.launch_graph(mp["graph"]), reps, 1)
+        s.synchronize()
+        l1 = mp["loss_hist"].sum(1).cpu().numpy()
+        _, _, ovf = rast.read_counters(rast.shared_workspace())
+        rast.destroy_graph(mp["graph"])
+    torch.cuda.synchronize()
+    res["mapping"] = dict(workload=f"mapping room: {Gm.n} Gaussians (perturbed map), {wm.views.n} keyframes at 640x480, "
+                                   "fwd+loss+bwd to all Gaussian parameters + Adam step, 10 iterations per graph replay",
+                          ms_per_iteration=ms_map / 10, iterations_per_s=10 * 1000.0 / ms_map, overflow=bool(ovf),
+                          loss_first_replay=[float(l0[0]), float(l0[-1])],
+                          loss_after=float(l1[-1]), replays=1 + 1 + reps)
+    print(f"[bench] mapping {ms_map / 10:.3f} ms per iteration", file=sys.stderr, flush=True)
+    del gm, gt, tgm
 
     # mapping Adam step at the mapping (500k) and large (3M) map sizes
     res["map_step"] = []

@@ -381,6 +381,27 @@ gsr_status gsr_map_opt_init(gsr_ctx *ctx, int64_t n, int32_t isotropic, void *st
 gsr_status gsr_map_opt_step(gsr_ctx *ctx, gsr_gaussians_rw params, const gsr_gaussian_grads *grads,
                             int32_t isotropic, const gsr_map_adam *hp, void *state, void *stream);
 
+/* The mapping loop: `iters` times render + loss + gradients to every
+ * Gaussian parameter over `views` (a window of keyframes, poses fixed: pose
+ * gradients are not formed), then gsr_map_opt_step on `params` in place, all
+ * enqueued on `stream`.  gg receives each iteration's gradients (scratch;
+ * laid out as params).  loss [V] holds the last iteration's loss; loss_hist
+ * (device, optional) receives every iteration's, [iters, V].  `state` must
+ * have been started by gsr_map_opt_init.  EINVAL with GSR_NO_GAUSS_GRADS.
+ * After the loop, gsr_read_counters reports an overflow if the pair
+ * capacity was exceeded in any iteration. */
+gsr_status gsr_map_iterate(gsr_ctx *ctx, gsr_gaussians_rw params, const gsr_views *views, const gsr_options *opts,
+                           const gsr_targets *targets, gsr_workspace ws, gsr_images out, double *loss,
+                           gsr_gaussian_grads *gg, const gsr_map_adam *hp, void *state, int32_t iters,
+                           double *loss_hist, void *stream);
+
+/* gsr_map_iterate captured into one graph (replayed with gsr_graph_launch;
+ * every replay continues from the parameters and state it finds). */
+gsr_status gsr_map_capture(gsr_ctx *ctx, gsr_gaussians_rw params, const gsr_views *views, const gsr_options *opts,
+                           const gsr_targets *targets, gsr_workspace ws, gsr_images out, double *loss,
+                           gsr_gaussian_grads *gg, const gsr_map_adam *hp, void *state, int32_t iters,
+                           double *loss_hist, void *stream, int32_t *graph_id);
+
 /* New Gaussians from one RGB-D frame (initialisation section: one Gaussian
  * per pixel at the point unprojected with the pixel's depth, with the
  * pixel's colour, opacity 0.5 and a radius of one pixel, depth / focal

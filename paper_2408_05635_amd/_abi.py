@@ -81,7 +81,7 @@ EXPORTS = ["gsr_create", "gsr_destroy", "gsr_last_error", "gsr_workspace_size", 
            "gsr_debug_binning", "gsr_debug_pixel_state", "gsr_selftest", "gsr_autotune", "gsr_set_tile",
            "gsr_graph_capture", "gsr_graph_launch", "gsr_graph_destroy", "gsr_pose_opt_init", "gsr_pose_opt_step",
            "gsr_track", "gsr_track_capture", "gsr_map_state_size", "gsr_map_opt_init", "gsr_map_opt_step",
-           "gsr_densify_work_size", "gsr_densify"]
+           "gsr_densify_work_size", "gsr_densify", "gsr_map_iterate", "gsr_map_capture"]
 
 _lib = None
 
@@ -155,6 +155,12 @@ def load() -> C.CDLL:
     lib.gsr_map_opt_init.restype = st
     lib.gsr_map_opt_step.argtypes = [_vp, GaussiansRW, P(GaussGrads), C.c_int32, P(MapAdam), _vp, _vp]
     lib.gsr_map_opt_step.restype = st
+    map_args = [_vp, GaussiansRW, P(Views), P(Options), P(Targets), Workspace, Images, _vp, P(GaussGrads), P(MapAdam),
+                _vp, C.c_int32, _vp, _vp]
+    lib.gsr_map_iterate.argtypes = map_args
+    lib.gsr_map_iterate.restype = st
+    lib.gsr_map_capture.argtypes = map_args + [P(C.c_int32)]
+    lib.gsr_map_capture.restype = st
     lib.gsr_densify_work_size.argtypes = [C.c_int32, C.c_int32]
     lib.gsr_densify_work_size.restype = C.c_size_t
     lib.gsr_densify.argtypes = [_vp, Camera, _vp, _vp, _vp, _vp, _vp, C.c_float, GaussiansRW, C.c_int32, C.c_int64,

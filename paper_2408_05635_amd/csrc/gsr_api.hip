@@ -1070,6 +1070,87 @@ gsr_status track_impl(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *ca
     }
     return s;
 }
+
+// Moment-array layout of the mapping state: segment k of both arrays starts
+// at moff[k] floats (256-byte aligned); returns the floats of one array.
+int64_t map_layout(int64_t n, bool iso, int64_t moff[kMapSegs], int64_t cnt[kMapSegs]) {
+    const int64_t per[kMapSegs] = {3, 4, iso ? 1 : 3, 1, 3};
+    int64_t off = 0;
+    for (int k = 0; k < kMapSegs; ++k) {
+        cnt[k] = (k == 1 && iso) ? 0 : per[k] * n;
+        moff[k] = off;
+        off += (cnt[k] + (int64_t)kMapAlign - 1) / (int64_t)kMapAlign * (int64_t)kMapAlign;
+    }
+    return off;
+}
+
+// One Adam step of the map (enqueue only).
+gsr_status map_step_impl(gsr_ctx *ctx, const gsr_gaussians_rw &params, const gsr_gaussian_grads *grads, bool iso,
+                         const gsr_map_adam *hp, void *state, hipStream_t st) {
+    if (!grads || !hp || !state) return fail(ctx, GSR_EINVAL, "map_opt_step: NULL argument");
+    if (params.n < 0) return fail(ctx, GSR_EINVAL, "map_opt_step: n must be >= 0");
+    float *xs[kMapSegs] = {params.means, iso ? nullptr : params.quats, params.log_scales, params.opacity_logits,
+                           params.rgb};
+    const float *gs[kMapSegs] = {grads->means, iso ? nullptr : grads->quats, grads->log_scales,
+                                 grads->opacity_logits, grads->rgb};
+    const float lrs[kMapSegs] = {hp->lr_means, hp->lr_quats, hp->lr_log_scales, hp->lr_opacity, hp->lr_rgb};
+    int64_t moff[kMapSegs], cnt[kMapSegs];
+    const int64_t per_array = map_layout(params.n, iso, moff, cnt);
+    MapSegs segs;
+    int64_t most = 0;
+    for (int k = 0; k < kMapSegs; ++k) {
+        if ((xs[k] == nullptr) != (gs[k] == nullptr))
+            return fail(ctx, GSR_EINVAL, "map_opt_step: parameter array %d and its gradient must both be given", k);
+        segs.s[k] = MapSeg{xs[k], gs[k], xs[k] ? cnt[k] : 0, moff[k], lrs[k]};
+        most = std::max(most, segs.s[k].count);
+    }
+    MapHeader *h = reinterpret_cast<MapHeader *>(state);
+    float *m = reinterpret_cast<float *>(static_cast<char *>(state) + kMapHeader);
+    float *v = m + per_array;
+    hipLaunchKernelGGL(k_map_opt_begin, dim3(1), dim3(64), 0, st, h, hp->beta1, hp->beta2);
+    if (most > 0) {
+        const unsigned gx = grid_for((most + 3) / 4, 256, 4096);
+        hipLaunchKernelGGL(k_map_opt_step, dim3(gx, kMapSegs), dim3(256), 0, st, segs, m, v, (const MapHeader *)h,
+                           hp->beta1, hp->beta2, hp->eps);
+    }
+    return check_hip(ctx, hipGetLastError(), "map step launch");
+}
+
+__global__ void k_copy_f64(const double *__restrict__ src, double *__restrict__ dst, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// The mapping loop (enqueue only): iters x (render + loss + Gaussian
+// gradients over the views, Adam step of the map).
+gsr_status map_iterate_impl(gsr_ctx *ctx, const gsr_gaussians_rw &params, const gsr_views *views,
+                            const gsr_options *opts, const gsr_targets *targets, gsr_workspace ws, gsr_images out,
+                            double *loss, gsr_gaussian_grads *gg, const gsr_map_adam *hp, void *state, int32_t iters,
+                            double *loss_hist, void *stream) {
+    if (!ctx) return GSR_EINVAL;
+    if (!views || !opts || !gg || !hp || !state)
+        return fail(ctx, GSR_EINVAL, "map_iterate: NULL argument (views, opts, gg, hp, state)");
+    if (iters < 0) return fail(ctx, GSR_EINVAL, "map_iterate: iters must be >= 0 (got %d)", iters);
+    if (opts->flags & GSR_NO_GAUSS_GRADS)
+        return fail(ctx, GSR_EINVAL, "map_iterate: GSR_NO_GAUSS_GRADS leaves nothing to update");
+    const bool iso = (opts->flags & GSR_ISOTROPIC) != 0;
+    const gsr_gaussians g{params.n, params.means, params.quats, params.log_scales, params.opacity_logits, params.rgb};
+    gsr_options o = *opts;
+    o.flags |= GSR_NO_POSE_GRADS;
+    o = resolve_tile(ctx, g.n, views, &o);
+    gsr_status s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    for (int32_t it = 0; it < iters && s == GSR_OK; ++it) {
+        s = render_loss_grad_impl(ctx, &g, views, &o, targets, ws, out, loss, gg, nullptr, stream, it > 0);
+        if (s != GSR_OK) break;
+        s = map_step_impl(ctx, params, gg, iso, hp, state, st);
+        if (s == GSR_OK && loss_hist)
+            hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(64), 0, st, (const double *)loss,
+                               loss_hist + (size_t)it * views->n_views, views->n_views);
+        if (s == GSR_OK) s = check_hip(ctx, hipGetLastError(), "gsr_map_iterate launch");
+    }
+    return s;
+}
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1537,20 +1618,6 @@ gsr_status gsr_track_capture(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_cam
     return GSR_OK;
 }
 
-namespace {
-// Moment-array layout of the mapping state: segment k of both arrays starts
-// at moff[k] floats (256-byte aligned); returns the floats of one array.
-int64_t map_layout(int64_t n, bool iso, int64_t moff[kMapSegs], int64_t cnt[kMapSegs]) {
-    const int64_t per[kMapSegs] = {3, 4, iso ? 1 : 3, 1, 3};
-    int64_t off = 0;
-    for (int k = 0; k < kMapSegs; ++k) {
-        cnt[k] = (k == 1 && iso) ? 0 : per[k] * n;
-        moff[k] = off;
-        off += (cnt[k] + (int64_t)kMapAlign - 1) / (int64_t)kMapAlign * (int64_t)kMapAlign;
-    }
-    return off;
-}
-}  // namespace
 
 size_t gsr_map_state_size(int64_t n, int32_t isotropic) {
     if (n < 0) return 0;
@@ -1572,37 +1639,61 @@ gsr_status gsr_map_opt_init(gsr_ctx *ctx, int64_t n, int32_t isotropic, void *st
 gsr_status gsr_map_opt_step(gsr_ctx *ctx, gsr_gaussians_rw params, const gsr_gaussian_grads *grads,
                             int32_t isotropic, const gsr_map_adam *hp, void *state, void *stream) {
     if (!ctx) return GSR_EINVAL;
-    if (!grads || !hp || !state) return fail(ctx, GSR_EINVAL, "map_opt_step: NULL argument");
-    if (params.n < 0) return fail(ctx, GSR_EINVAL, "map_opt_step: n must be >= 0");
-    const bool iso = isotropic != 0;
-    float *xs[kMapSegs] = {params.means, iso ? nullptr : params.quats, params.log_scales, params.opacity_logits,
-                           params.rgb};
-    const float *gs[kMapSegs] = {grads->means, iso ? nullptr : grads->quats, grads->log_scales,
-                                 grads->opacity_logits, grads->rgb};
-    const float lrs[kMapSegs] = {hp->lr_means, hp->lr_quats, hp->lr_log_scales, hp->lr_opacity, hp->lr_rgb};
-    int64_t moff[kMapSegs], cnt[kMapSegs];
-    const int64_t per_array = map_layout(params.n, iso, moff, cnt);
-    MapSegs segs;
-    int64_t most = 0;
-    for (int k = 0; k < kMapSegs; ++k) {
-        if ((xs[k] == nullptr) != (gs[k] == nullptr))
-            return fail(ctx, GSR_EINVAL, "map_opt_step: parameter array %d and its gradient must both be given", k);
-        segs.s[k] = MapSeg{xs[k], gs[k], xs[k] ? cnt[k] : 0, moff[k], lrs[k]};
-        most = std::max(most, segs.s[k].count);
-    }
     gsr_status s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     if (s != GSR_OK) return s;
-    hipStream_t st = (hipStream_t)stream;
-    MapHeader *h = reinterpret_cast<MapHeader *>(state);
-    float *m = reinterpret_cast<float *>(static_cast<char *>(state) + kMapHeader);
-    float *v = m + per_array;
-    hipLaunchKernelGGL(k_map_opt_begin, dim3(1), dim3(64), 0, st, h, hp->beta1, hp->beta2);
-    if (most > 0) {
-        const unsigned gx = grid_for((most + 3) / 4, 256, 4096);
-        hipLaunchKernelGGL(k_map_opt_step, dim3(gx, kMapSegs), dim3(256), 0, st, segs, m, v, (const MapHeader *)h,
-                           hp->beta1, hp->beta2, hp->eps);
+    return map_step_impl(ctx, params, grads, isotropic != 0, hp, state, (hipStream_t)stream);
+}
+
+gsr_status gsr_map_iterate(gsr_ctx *ctx, gsr_gaussians_rw params, const gsr_views *views, const gsr_options *opts,
+                           const gsr_targets *targets, gsr_workspace ws, gsr_images out, double *loss,
+                           gsr_gaussian_grads *gg, const gsr_map_adam *hp, void *state, int32_t iters,
+                           double *loss_hist, void *stream) {
+    return map_iterate_impl(ctx, params, views, opts, targets, ws, out, loss, gg, hp, state, iters, loss_hist,
+                            stream);
+}
+
+gsr_status gsr_map_capture(gsr_ctx *ctx, gsr_gaussians_rw params, const gsr_views *views, const gsr_options *opts,
+                           const gsr_targets *targets, gsr_workspace ws, gsr_images out, double *loss,
+                           gsr_gaussian_grads *gg, const gsr_map_adam *hp, void *state, int32_t iters,
+                           double *loss_hist, void *stream, int32_t *graph_id) {
+    if (!ctx) return GSR_EINVAL;
+    if (!graph_id) return fail(ctx, GSR_EINVAL, "graph_id must not be NULL");
+    if (!stream) return fail(ctx, GSR_EINVAL, "graph capture needs a stream other than the null stream");
+    if (!views || !opts) return fail(ctx, GSR_EINVAL, "map_capture: views and opts must not be NULL");
+    {   // validate before the capture starts (one render's worth of checks)
+        const gsr_gaussians g{params.n, params.means, params.quats, params.log_scales, params.opacity_logits,
+                              params.rgb};
+        gsr_options o = *opts;
+        o.flags |= GSR_NO_POSE_GRADS;
+        o = resolve_tile(ctx, g.n, views, &o);
+        Call c;
+        const gsr_status sv = prepare(ctx, &g, views, &o, ws, stream, c);
+        if (sv != GSR_OK) return sv;
     }
-    return check_hip(ctx, hipGetLastError(), "gsr_map_opt_step launch");
+    hipStream_t st = (hipStream_t)stream;
+    gsr_status s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (s != GSR_OK) return s;
+    s = check_hip(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    if (s != GSR_OK) return s;
+    ctx->capturing = true;
+    const gsr_status s_call = map_iterate_impl(ctx, params, views, opts, targets, ws, out, loss, gg, hp, state, iters,
+                                               loss_hist, stream);
+    ctx->capturing = false;
+    hipGraph_t graph = nullptr;
+    s = check_hip(ctx, hipStreamEndCapture(st, &graph), "hipStreamEndCapture");
+    if (s_call != GSR_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s_call;
+    }
+    if (s != GSR_OK) return s;
+    hipGraphExec_t exec = nullptr;
+    s = check_hip(ctx, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    (void)hipGraphDestroy(graph);
+    if (s != GSR_OK) return s;
+    const int32_t id = ctx->next_graph++;
+    ctx->graphs[id] = exec;
+    *graph_id = id;
+    return GSR_OK;
 }
 
 size_t gsr_densify_work_size(int32_t width, int32_t height) {

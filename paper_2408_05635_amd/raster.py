@@ -532,6 +532,53 @@ class Rasterizer:
         _abi.check(_ABI.gsr_map_opt_step(self._ctx, rw, C.byref(gg), int(g.isotropic), C.byref(hpc), _ptr(state),
                                          _stream_ptr()), self._ctx)
 
+    def map_iterate(self, g: GaussianParams, quat: torch.Tensor, trans: torch.Tensor, cams: Sequence,
+                    targets: dict, opts: RenderOptions = RenderOptions(), hp: MapAdam = MapAdam(), iters: int = 10,
+                    state: Optional[torch.Tensor] = None, capture: bool = False, out: Optional[dict] = None):
+        """The mapping loop on the device: `iters` x (render + loss + Gaussian
+        gradients over the views, Adam step of the map); g's arrays are updated
+        in place.  Returns dict(loss_hist [iters, V] float64, state, out, graph).
+        Eagerly, the pair capacity is checked after the loop and the loop re-run
+        from its start if any iteration overflowed it; with capture=True the loop
+        is captured (not run)."""
+        V = len(cams)
+        P = total_pixels(cams)
+        opts = RenderOptions(**{**opts.__dict__, "gauss_grads": True, "pose_grads": False})
+        if out is None:
+            out = self.alloc_outputs(g, V, P, opts)
+        if state is None:
+            state = self.map_opt_init(g)
+        hist = torch.zeros(max(iters, 1), V, dtype=torch.float64, device=self.device)
+        self.render_loss_grad(g, quat, trans, cams, targets, opts, check=True, out=out)   # size the capacity
+
+        def args():
+            a = self._fused_args(g, quat, trans, cams, targets, opts, out)
+            ws = self._shared_ws(g.n, a["views"], a["o"])
+            hpc = hp.c()
+            rw = _abi.GaussiansRW(g.n, *[_ptr(t) for t in g.tensors()])
+            return [self._ctx, rw, C.byref(a["views"]), C.byref(a["o"]), C.byref(a["tg"]), ws, a["imgs"],
+                    _ptr(out["loss"]), C.byref(a["gg"]), C.byref(hpc), _ptr(state), int(iters), _ptr(hist),
+                    _stream_ptr()], (a, hpc, ws, rw)
+
+        if capture:
+            al, keep = args()
+            gid = C.c_int32()
+            _abi.check(_ABI.gsr_map_capture(*al, C.byref(gid)), self._ctx)
+            self._graph_refs = getattr(self, "_graph_refs", {})
+            self._graph_refs[gid.value] = (keep, out, hist, state, self._ws)
+            return dict(loss_hist=hist[:iters], state=state, out=out, graph=gid.value)
+        saved = [t.clone() for t in g.tensors()] + [state.clone()]
+        while True:
+            al, keep = args()
+            _abi.check(_ABI.gsr_map_iterate(*al), self._ctx)
+            _, k, ovf = self.read_counters(keep[2])
+            if not ovf:
+                break
+            self._grow(k)
+            for t, s0 in zip(list(g.tensors()) + [state], saved):
+                t.copy_(s0)
+        return dict(loss_hist=hist[:iters], state=state, out=out, graph=None)
+
     def densify(self, cam, quat: torch.Tensor, trans: torch.Tensor, rgb: torch.Tensor, depth: torch.Tensor,
                 sil: Optional[torch.Tensor], out: GaussianParams, offset: int, sil_thresh: float = 0.5,
                 n_new: Optional[torch.Tensor] = None) -> torch.Tensor:

@@ -144,3 +144,15 @@ def test_optimiser_entry_points_reject_a_null_context():
     assert lib.gsr_track_capture(None, None, None, 1, None, None, None, None, _abi.Workspace(None, 0, 0),
                                  _abi.Images(None, None, None), None, None, None, None, 1, None, None,
                                  C.byref(gid)) == _abi.GSR_EINVAL
+
+
+def test_mapping_loop_rejects_a_null_context():
+    lib = _abi.load()
+    rw = _abi.GaussiansRW(0, None, None, None, None, None)
+    ws = _abi.Workspace(None, 0, 0)
+    imgs = _abi.Images(None, None, None)
+    assert lib.gsr_map_iterate(None, rw, None, None, None, ws, imgs, None, None, None, None, 1, None,
+                               None) == _abi.GSR_EINVAL
+    gid = C.c_int32()
+    assert lib.gsr_map_capture(None, rw, None, None, None, ws, imgs, None, None, None, None, 1, None, None,
+                               C.byref(gid)) == _abi.GSR_EINVAL

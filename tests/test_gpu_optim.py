@@ -259,3 +259,106 @@ def test_densify_matches_oracle(rast, W, H, iso):
     n3 = rast.densify(cam, d(q), d(t), d(rgb), d(depth), None, out, 0, 0.5)
     torch.cuda.synchronize()
     assert int(n3.item()) == int((depth > 0).sum())
+
+
+# ----------------------------------------------------------------------------
+# mapping loop
+# ----------------------------------------------------------------------------
+
+def _map_setup(w):
+    from paper_2408_05635_amd.raster import RenderOptions
+    g = dev_params(w.gaussians)
+    q, t = dev_poses(w.views)
+    tg = to_dev(oracle_targets(w))
+    return g, q, t, tg, RenderOptions(**w.weights)
+
+
+def test_map_iterate_equals_stepwise_calls_and_graph(rast):
+    from paper_2408_05635_amd.raster import GaussianParams, MapAdam, RenderOptions
+    w = scenes.config3(n=30000, n_views=2)
+    g0, q, t, tg, opts = _map_setup(w)
+    hp = MapAdam()
+    iters = 4
+    clone = lambda g: GaussianParams(*[x.clone() for x in g.tensors()])  # noqa: E731
+    g1 = clone(g0)
+    r1 = rast.map_iterate(g1, q, t, w.views.cams, tg, opts, hp, iters)
+    # by hand
+    g2 = clone(g0)
+    st2 = rast.map_opt_init(g2)
+    o2 = RenderOptions(**{**opts.__dict__, "pose_grads": False})
+    losses = []
+    for _ in range(iters):
+        out = rast.render_loss_grad(g2, q, t, w.views.cams, tg, o2, check=False)
+        losses.append(out["loss"].clone())
+        rast.map_opt_step(g2, out, st2, hp)
+    torch.cuda.synchronize()
+    for a, b in zip(g1.tensors(), g2.tensors()):
+        assert torch.equal(a, b)
+    assert torch.equal(r1["state"], st2) and torch.equal(r1["loss_hist"], torch.stack(losses))
+    # captured on a side stream; a replay runs the whole loop
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        g3 = clone(g0)
+        r3 = rast.map_iterate(g3, q, t, w.views.cams, tg, opts, hp, iters, capture=True)
+        assert all(torch.equal(a, b) for a, b in zip(g3.tensors(), g0.tensors()))
+        rast.launch_graph(r3["graph"])
+        side.synchronize()
+        for a, b in zip(g3.tensors(), g1.tensors()):
+            assert torch.equal(a, b)
+        assert torch.equal(r3["loss_hist"], r1["loss_hist"])
+    torch.cuda.current_stream().wait_stream(side)
+    rast.destroy_graph(r3["graph"])
+
+
+def test_map_iterate_follows_the_oracle_loop(rast):
+    """Three mapping iterations on a small scene against the oracle's loop
+    (oracle gradients, oracle Adam).  Adam's step is lr * g / (|g| + eps), a
+    sign-like function, so an entry whose gradient is within FP32 rounding of
+    zero (1e-6 of its group's largest here) may step the other way; the other
+    entries must agree to FP32 rounding of the steps."""
+    from paper_2408_05635_amd.raster import MapAdam
+    w = scenes.tiny_scene(41, n=60, width=40, height=30)
+    g, q, t, tg, opts = _map_setup(w)
+    hp = MapAdam()
+    iters = 3
+    rast.map_iterate(g, q, t, w.views.cams, tg, opts, hp, iters)
+    torch.cuda.synchronize()
+    ohp = _hp32(optim.MapAdam(**hp.__dict__))
+    otg = oracle_targets(w)
+    params = {k: np.asarray(getattr(w.gaussians, k), np.float64) for k in optim.MAP_KEYS}
+    m = {k: np.zeros_like(a) for k, a in params.items()}
+    v = {k: np.zeros_like(a) for k, a in params.items()}
+    stable = {k: np.ones(a.shape, bool) for k, a in params.items()}
+
+    class G:
+        pass
+    for step in range(1, iters + 1):
+        gg = G()
+        for k, a in params.items():
+            setattr(gg, k, a.astype(np.float32))   # the GPU renders the FP32 parameters
+        r = oracle.run(gg, w.views, oracle.Options(**w.weights),
+                       oracle.Targets(otg["rgb"], otg["depth"], otg["sil"]), want_grads=True)
+        grads = {k: r.grads[k].reshape(params[k].shape) for k in params}
+        for k in params:
+            stable[k] &= np.abs(grads[k]) > 1e-6 * np.abs(grads[k]).max()
+        params, m, v = optim.map_step(params, grads, m, v, step, ohp)
+    for k in params:
+        got = getattr(g, k).cpu().numpy().astype(np.float64).reshape(params[k].shape)
+        sel = stable[k]
+        err = np.abs(got - params[k])[sel].max() if sel.any() else 0.0
+        print(f"{k}: {int(sel.sum())}/{sel.size} entries compared, max abs err {err:.2e} (lr {ohp.lr(k):g})")
+        np.testing.assert_allclose(got[sel], params[k][sel], rtol=1e-6, atol=1e-3 * ohp.lr(k) * iters, err_msg=k)
+
+
+def test_map_iterate_reduces_the_loss(rast):
+    """The mapping configuration's perturbed map, two keyframes: the loop
+    lowers the loss against renders of the true scene."""
+    from paper_2408_05635_amd.raster import MapAdam
+    w = scenes.config3(n=100000, n_views=2)
+    g, q, t, tg, opts = _map_setup(w)
+    r = rast.map_iterate(g, q, t, w.views.cams, tg, opts, MapAdam(), 30)
+    torch.cuda.synchronize()
+    lh = r["loss_hist"].cpu().numpy().sum(1)
+    print(f"mapping loss {lh[0]:.5f} -> {lh[-1]:.5f} over 30 iterations")
+    assert np.all(np.isfinite(lh)) and lh[-1] < 0.9 * lh[0]
