@@ -476,19 +476,7 @@ __global__ __launch_bounds__(256) void k_emit(const int64_t *__restrict__ counte
     }
 }
 
-__global__ void k_fill_u32_dev(uint32_t *p, const int64_t *n_dev, uint32_t val) {
-    const int64_t n = *n_dev;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = val;
-}
-
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t val) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = val;
-}
-
-__global__ void k_fill_f32_dev(float *p, const int64_t *n_dev, int64_t mult, float val) {
-    const int64_t n = *n_dev * mult;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = val;
 }

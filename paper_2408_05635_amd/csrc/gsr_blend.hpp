@@ -216,13 +216,15 @@ __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.0f) - (x 
 
 // Backward blend.  One workgroup per binning tile, one wave per 8x8 block of
 // it (tiles are at most 16x16, so at most four waves).  The tile's list is
-// walked in reverse in segments of 64 entries; within a segment every wave
-// culls and processes the entries against its own block, reduces each
-// entry's 10 partial derivatives over its 64 lanes (DPP) and writes the sums
-// to its own LDS slots.  At the end of the segment the waves' slots are added
-// in a fixed order and written, without atomics, to the pair's own row of
-// `grad_pairs` (indexed by the pair's emission index, so that a record's rows
-// are contiguous).  Every pair of the list gets exactly one row per call.
+// walked in reverse, from the last contributor of any pixel of the tile, in
+// segments of kSeg entries; within a segment every wave culls and processes
+// the entries against its own block, sums each entry's partial derivatives
+// over each 16-lane row (DPP) and writes the row sums to its own LDS slots.
+// At the end of the segment the waves' slots are added in a fixed order and
+// written, without atomics, to the pair's own row of `grad_pairs`: record s
+// owns the rows [poff[s], poff[s] + tiles of s), one per tile of its
+// rectangle in row-major order, so that a record's rows are contiguous.
+// Every pair of the list gets exactly one row per call.
 //
 // Partial derivatives per (pixel, entry), for alpha = o exp2(p2),
 // p2 = -(u^2 + w^2), u = l11 dx + l21 dy, w = l22 dy, dx = px - mx:
