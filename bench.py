@@ -285,6 +285,21 @@ def next_rows_bench(rast, raster, scenes, w, g, q, t, targets, opts, timed, args
                            rotation_err_deg=[e0[0], e1[0]], centre_err_cm=[100 * e0[1], 100 * e1[1]],
                            loss_first_last=[float(lh[0]), float(lh[-1])])
     print(f"[bench] tracking {ms_frame:.3f} ms per 40-iteration frame", file=sys.stderr, flush=True)
+    # the same loop for all 8 poses at once (independent per view: a camera rig or pose hypotheses)
+    q8, t8 = q.clone(), t.clone()
+    with torch.cuda.stream(s):
+        tr8 = rast.track(g, q8, t8, w.views.cams, targets, opts, hp, 40, capture=True)
+        rast.launch_graph(tr8["graph"])
+        s.synchronize()
+        ms_frame8 = timed(lambda: rast.launch_graph(tr8["graph"]), max(3, args.steps // 4), 1)
+        s.synchronize()
+        _, _, ovf8 = rast.read_counters(rast.shared_workspace())
+        rast.destroy_graph(tr8["graph"])
+    torch.cuda.synchronize()
+    V8 = len(w.views.cams)
+    res["tracking_batched"] = dict(views=V8, iterations=40, ms_per_frame=ms_frame8,
+                                   view_iterations_per_s=V8 * 40 * 1000.0 / ms_frame8, overflow=bool(ovf8))
+    print(f"[bench] tracking {V8} views: {ms_frame8:.3f} ms per 40-iteration frame", file=sys.stderr, flush=True)
 
     # mapping loop: the mapping configuration's perturbed 500k map, 8 keyframes, 10 iterations
     # (render + loss + Gaussian gradients + Adam step) per graph replay
