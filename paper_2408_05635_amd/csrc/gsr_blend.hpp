@@ -230,12 +230,36 @@ __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.0f) - (x 
 // p2 = -(u^2 + w^2), u = l11 dx + l21 dy, w = l22 dy, dx = px - mx:
 //   dL/dalpha = T_k sum_ch g_ch (f_ch - B_ch)    (B: colour behind, per unit of
 //                                                 the transmittance after k)
+//             = T_k (S_k - W)   with S_k = sum_ch g_ch f_ch (f_sil = 1) and
+//                               W = sum_ch g_ch B_ch, which obeys the same
+//                               recursion as each B_ch: W <- alpha S_k + (1 - alpha) W
 //   dL/df_ch  = g_ch alpha T_k                   (rgb and depth)
 //   dL/do = dL/dalpha G,  dL/dp2 = dL/dalpha alpha ln2   (unless clamped)
 //   dL/dmx = dL/dp2 2u l11,  dL/dmy = dL/dp2 2(u l21 + w l22)
 //   dL/dl11 = -dL/dp2 2u dx, dL/dl21 = -dL/dp2 2u dy, dL/dl22 = -dL/dp2 2w dy
+// Sums of each value over every row of 16 lanes, the NV chains interleaved;
+// the row's sum lands in its last lane.  Contraction is off so that each
+// stage stays one DPP add (fused with the product that made the value, the
+// add would become an FMA, whose addend cannot take the DPP operand).  The
+// empty asm keeps the last stage in front of the caller's store branch: sunk
+// into it, each add would split into a DPP move for all lanes and a masked add.
+template <int NV>
+__device__ __forceinline__ void row_sums16(float (&d)[NV]) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int c = 0; c < NV; ++c) d[c] += dpp_f<0xb1>(d[c]);    // quad_perm [1,0,3,2]
+#pragma unroll
+    for (int c = 0; c < NV; ++c) d[c] += dpp_f<0x4e>(d[c]);    // quad_perm [2,3,0,1]
+#pragma unroll
+    for (int c = 0; c < NV; ++c) d[c] += dpp_f<0x114>(d[c]);   // row_shr:4
+#pragma unroll
+    for (int c = 0; c < NV; ++c) d[c] += dpp_f<0x118>(d[c]);   // row_shr:8
+#pragma unroll
+    for (int c = 0; c < NV; ++c) asm volatile("" : "+v"(d[c]));
+}
+
 constexpr int kBwdMaxWaves = 4;
-constexpr int kSeg = 32;   // list entries per segment (LDS: 4 waves x 4 rows x kSeg x 10 floats)
+constexpr int kSeg = 24;   // list entries per segment (LDS: 4 waves x 4 rows x kSeg x 10 floats)
 
 // NV = 10: all partials per entry (dL/d of the conic factors and mean, opacity,
 // colour, depth).  NV = 6 (pose only): the opacity and colour partials do not
@@ -363,7 +387,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
         for (int c = 0; c < NV; ++c) dst[c] = 0.0f;
     }
 
-    float b0 = 0.f, b1 = 0.f, b2 = 0.f, bd = 0.f, bs = 0.f;
+    float W = 0.f;   // sum over the channels of dL/d(channel) x (channel behind the current entry)
     uint32_t n_eval = 0, n_contrib = 0, n_red = 0;
     float *acc = &s_acc[wave][0][0];
     const uint32_t row = lane >> 4;
@@ -409,15 +433,21 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                     ++n_red;
                 }
                 const float4 cc = s_c[wave][k];
-                const float oma = 1.0f - ev.alpha;
+                // A lane that does not take this entry continues with alpha = 0:
+                // every update below then leaves its state exactly as it was
+                // (fma(0, S, W 1) = W) and every partial is zero, so no branch
+                // and no select is needed for the state.
+                const float ae = contrib ? ev.alpha : 0.0f;
+                const float oma = 1.0f - ae;
                 const float Tk = T * __builtin_amdgcn_rcpf(oma);   // transmittance in front of this entry
-                const float wgt = ev.alpha * Tk;
-                const float dal = Tk * (g[0] * (cc.x - b0) + g[1] * (cc.y - b1) + g[2] * (cc.z - b2) +
-                                        g[3] * (cc.w - bd) + g[4] * (1.0f - bs));
-                const float live = (contrib && !ev.clamped) ? 1.0f : 0.0f;
-                const float dp2 = live * dal * ev.alpha * kLn2f;
-                const float tu = 2.0f * ev.u * dp2, tw = 2.0f * ev.w * dp2;
-                const float wc = contrib ? wgt : 0.0f;
+                const float S = g[0] * cc.x + g[1] * cc.y + g[2] * cc.z + g[3] * cc.w + g[4];
+                const float dal = Tk * (S - W);
+                // unclamped: alpha = o G, so dL/do = dL/dalpha G and
+                // 2 dL/dp2 = dL/dalpha alpha 2 ln2 = dL/do (2 o ln2)
+                const float dop = dal * ((contrib && !ev.clamped) ? ev.G : 0.0f);
+                const float dq2 = dop * (b.w * (2.0f * kLn2f));
+                const float tu = ev.u * dq2, tw = ev.w * dq2;
+                const float wc = ae * Tk;
                 float d[NV];
                 d[0] = tu * b.x;
                 d[1] = tu * b.y + tw * b.z;
@@ -425,7 +455,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                 d[3] = -tu * ev.dy;
                 d[4] = -tw * ev.dy;
                 if constexpr (NV == 10) {
-                    d[5] = live * dal * ev.G;
+                    d[5] = dop;
                     d[6] = g[0] * wc;
                     d[7] = g[1] * wc;
                     d[8] = g[2] * wc;
@@ -433,23 +463,9 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                 } else {
                     d[5] = g[3] * wc;
                 }
-                if (contrib) {
-                    b0 = ev.alpha * cc.x + oma * b0;
-                    b1 = ev.alpha * cc.y + oma * b1;
-                    b2 = ev.alpha * cc.z + oma * b2;
-                    bd = ev.alpha * cc.w + oma * bd;
-                    bs = ev.alpha + oma * bs;
-                    T = Tk;
-                }
-                // sums within each row of 16 lanes, the chains interleaved
-#pragma unroll
-                for (int c = 0; c < NV; ++c) d[c] += dpp_f<0xb1>(d[c]);    // quad_perm [1,0,3,2]
-#pragma unroll
-                for (int c = 0; c < NV; ++c) d[c] += dpp_f<0x4e>(d[c]);    // quad_perm [2,3,0,1]
-#pragma unroll
-                for (int c = 0; c < NV; ++c) d[c] += dpp_f<0x114>(d[c]);   // row_shr:4
-#pragma unroll
-                for (int c = 0; c < NV; ++c) d[c] += dpp_f<0x118>(d[c]);   // row_shr:8
+                W = __builtin_fmaf(ae, S, W * oma);
+                T = contrib ? Tk : T;
+                row_sums16<NV>(d);
                 if ((lane & 15u) == 15u) {   // the row's sum is in its last lane
                     float2 *dst = reinterpret_cast<float2 *>(acc + row * (kSeg * 10) + (pos - seg_lo) * NV);
 #pragma unroll
