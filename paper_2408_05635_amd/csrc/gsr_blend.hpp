@@ -155,29 +155,30 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
         __syncthreads();
         const int n = __popcll(m);
         for (int k = 0; k < n; ++k) {
-            if (!done) {
-                const AlphaEval ev = eval_alpha(s_a[k], s_b[k], fpx, fpy);
-                if (COUNT) ++n_eval;
-                if (ev.alpha >= kAlphaMin) {
-                    const float Tn = T * (1.0f - ev.alpha);
-                    if (Tn < kTMin) {
-                        done = true;
-                        hsh = (hsh ^ 0xffffffffu) * 0x01000193u;
-                    } else {
-                        if (COUNT) ++n_contrib;
-                        hsh = (hsh ^ (2u * s_rec_id[k] + (ev.clamped ? 1u : 0u))) * 0x01000193u;
-                        const float4 cc = s_c[k];
-                        const float wgt = ev.alpha * T;
-                        c0 = __builtin_fmaf(wgt, cc.x, c0);
-                        c1 = __builtin_fmaf(wgt, cc.y, c1);
-                        c2 = __builtin_fmaf(wgt, cc.z, c2);
-                        cd = __builtin_fmaf(wgt, cc.w, cd);
-                        cs += wgt;
-                        T = Tn;
-                        last = s_pos[k] + 1u;
-                    }
-                }
-            }
+            // Every lane evaluates; a lane that is done, or that the entry does
+            // not reach, takes weight 0, which leaves its sums exactly as they
+            // were (fma(0, c, x) = x), so the updates need no branches.
+            const AlphaEval ev = eval_alpha(s_a[k], s_b[k], fpx, fpy);
+            if (COUNT) n_eval += done ? 0u : 1u;
+            const bool hit = !done && ev.alpha >= kAlphaMin;
+            const float Tn = T * (1.0f - ev.alpha);
+            const bool stop = hit && Tn < kTMin;
+            const bool take = hit && !(Tn < kTMin);
+            if (COUNT) n_contrib += take ? 1u : 0u;
+            const float4 cc = s_c[k];
+            uint32_t pos1 = s_pos[k] + 1u, rid2 = 2u * s_rec_id[k] + (ev.clamped ? 1u : 0u);
+            asm volatile("" : "+v"(pos1), "+v"(rid2));   // read for every lane: no branch around the reads
+            const float wgt = take ? ev.alpha * T : 0.0f;
+            c0 = __builtin_fmaf(wgt, cc.x, c0);
+            c1 = __builtin_fmaf(wgt, cc.y, c1);
+            c2 = __builtin_fmaf(wgt, cc.z, c2);
+            cd = __builtin_fmaf(wgt, cc.w, cd);
+            cs += wgt;
+            T = take ? Tn : T;
+            last = take ? pos1 : last;
+            const uint32_t hin = take ? rid2 : 0xffffffffu;
+            hsh = (take || stop) ? (hsh ^ hin) * 0x01000193u : hsh;
+            done = done || stop;
             if ((k & 7) == 7 && ballot(!done) == 0) break;
         }
         __syncthreads();
@@ -218,8 +219,9 @@ __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.0f) - (x 
 // it (tiles are at most 16x16, so at most four waves).  The tile's list is
 // walked in reverse, from the last contributor of any pixel of the tile, in
 // segments of kSeg entries; within a segment every wave culls and processes
-// the entries against its own block, sums each entry's partial derivatives
-// over each 16-lane row (DPP) and writes the row sums to its own LDS slots.
+// the entries against its own block and sums each entry's partial derivatives
+// over its 64 pixels (DPP quad sums, then a batched column sum in LDS) into
+// its own LDS slots.
 // At the end of the segment the waves' slots are added in a fixed order and
 // written, without atomics, to the pair's own row of `grad_pairs`: record s
 // owns the rows [poff[s], poff[s] + tiles of s), one per tile of its
@@ -237,29 +239,26 @@ __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.0f) - (x 
 //   dL/do = dL/dalpha G,  dL/dp2 = dL/dalpha alpha ln2   (unless clamped)
 //   dL/dmx = dL/dp2 2u l11,  dL/dmy = dL/dp2 2(u l21 + w l22)
 //   dL/dl11 = -dL/dp2 2u dx, dL/dl21 = -dL/dp2 2u dy, dL/dl22 = -dL/dp2 2w dy
-// Sums of each value over every row of 16 lanes, the NV chains interleaved;
-// the row's sum lands in its last lane.  Contraction is off so that each
-// stage stays one DPP add (fused with the product that made the value, the
-// add would become an FMA, whose addend cannot take the DPP operand).  The
-// empty asm keeps the last stage in front of the caller's store branch: sunk
-// into it, each add would split into a DPP move for all lanes and a masked add.
+// Sums of each value over every quad of lanes (4 neighbouring pixels of a
+// row), the NV chains interleaved; afterwards every lane of a quad holds the
+// quad's sums.  Contraction is off so that each stage stays one DPP add (fused
+// with the product that made the value, the add would become an FMA, whose
+// addend cannot take the DPP operand).  The empty asm keeps the last stage in
+// front of the caller's store branch: sunk into it, each add would split into
+// a DPP move for all lanes and a masked add.
 template <int NV>
-__device__ __forceinline__ void row_sums16(float (&d)[NV]) {
+__device__ __forceinline__ void quad_sums(float (&d)[NV]) {
 #pragma clang fp contract(off)
 #pragma unroll
     for (int c = 0; c < NV; ++c) d[c] += dpp_f<0xb1>(d[c]);    // quad_perm [1,0,3,2]
 #pragma unroll
     for (int c = 0; c < NV; ++c) d[c] += dpp_f<0x4e>(d[c]);    // quad_perm [2,3,0,1]
 #pragma unroll
-    for (int c = 0; c < NV; ++c) d[c] += dpp_f<0x114>(d[c]);   // row_shr:4
-#pragma unroll
-    for (int c = 0; c < NV; ++c) d[c] += dpp_f<0x118>(d[c]);   // row_shr:8
-#pragma unroll
     for (int c = 0; c < NV; ++c) asm volatile("" : "+v"(d[c]));
 }
 
 constexpr int kBwdMaxWaves = 4;
-constexpr int kSeg = 24;   // list entries per segment (LDS: 4 waves x 4 rows x kSeg x 10 floats)
+constexpr int kSeg = 24;   // list entries per segment
 
 // NV = 10: all partials per entry (dL/d of the conic factors and mean, opacity,
 // colour, depth).  NV = 6 (pose only): the opacity and colour partials do not
@@ -272,9 +271,15 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                                                    BlendOut st, LossIn L, float *__restrict__ grad_pairs) {
     __shared__ float4 s_a[kBwdMaxWaves][kSeg], s_b[kBwdMaxWaves][kSeg], s_c[kBwdMaxWaves][kSeg];
     __shared__ uint32_t s_pos[kBwdMaxWaves][kSeg];
-    // per wave, per 16-lane row, per entry of the segment: the row's sums of the NV partials
-    // (row stride kSeg * 10 for both NV)
-    __shared__ float s_acc[kBwdMaxWaves][4][kSeg * 10];
+    // The NV partials of an entry are summed over the wave in two steps: DPP
+    // sums over each quad of lanes, stored by the quad's first lane into
+    // s_q[wave][batch slot][quad][NV]; once kBatch entries are stored, lane
+    // (k, c) adds the 16 quad sums of value c of entry k, in quad order, into
+    // s_acc[wave][entry of the segment][c].
+    constexpr int kBatch = 64 / NV;
+    __shared__ float s_q[kBwdMaxWaves][kBatch * 16 * NV];
+    __shared__ uint32_t s_bslot[kBwdMaxWaves][kBatch];
+    __shared__ float s_acc[kBwdMaxWaves][kSeg * NV];
     __shared__ uint32_t s_wmax[kBwdMaxWaves];
     __shared__ uint32_t s_j[kSeg];   // gradient-row slot of each entry of the segment
     __shared__ double s_loss[kBwdMaxWaves];
@@ -389,11 +394,27 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
 
     float W = 0.f;   // sum over the channels of dL/d(channel) x (channel behind the current entry)
     uint32_t n_eval = 0, n_contrib = 0, n_red = 0;
-    float *acc = &s_acc[wave][0][0];
-    const uint32_t row = lane >> 4;
+    float *acc = &s_acc[wave][0];
+    float *qs = &s_q[wave][0];
+    const uint32_t fk = lane / NV, fc = lane - fk * NV;   // the batch entry and the value this lane adds up
+    // Adds the quad sums of the batch's nb entries (lanes of one wave; LDS
+    // operations of a wave complete in order, so no barrier beyond the wave's).
+    auto flush = [&](uint32_t nb) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (fk < nb) {
+            const float *src = qs + fk * 16 * NV + fc;
+            float sum = src[0];
+#pragma unroll
+            for (int q = 1; q < 16; ++q) sum += src[q * NV];
+            acc[s_bslot[wave][fk] * NV + fc] = sum;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    };
     for (uint32_t seg_hi = bmax; seg_hi > rg.x;) {
         const uint32_t seg_lo = seg_hi - rg.x > (uint32_t)kSeg ? seg_hi - kSeg : rg.x;
-        for (int c = lane; c < 4 * kSeg * 10; c += 64) acc[c] = 0.0f;
+        for (int c = lane; c < kSeg * NV; c += 64) acc[c] = 0.0f;
         if (threadIdx.x < seg_hi - seg_lo) s_j[threadIdx.x] = row_of(seg_lo + threadIdx.x);   // read after the barrier
         if (wmax > seg_lo) {   // wave-uniform: this wave has pixels with entries in the segment
             const uint32_t hi = wmax < seg_hi ? wmax : seg_hi;
@@ -417,6 +438,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
+            uint32_t nb = 0;   // entries stored in the batch (wave-uniform)
             for (int k = __popcll(m) - 1; k >= 0; --k) {
                 const uint32_t pos = s_pos[wave][k];
                 const bool act = pos < last;
@@ -465,23 +487,27 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                 }
                 W = __builtin_fmaf(ae, S, W * oma);
                 T = contrib ? Tk : T;
-                row_sums16<NV>(d);
-                if ((lane & 15u) == 15u) {   // the row's sum is in its last lane
-                    float2 *dst = reinterpret_cast<float2 *>(acc + row * (kSeg * 10) + (pos - seg_lo) * NV);
+                quad_sums<NV>(d);
+                if ((lane & 3u) == 0u) {
+                    float2 *dst = reinterpret_cast<float2 *>(qs + (nb * 16 + (lane >> 2)) * NV);
 #pragma unroll
                     for (int c = 0; c < NV / 2; ++c) dst[c] = make_float2(d[2 * c], d[2 * c + 1]);
                 }
+                if (lane == 0) s_bslot[wave][nb] = pos - seg_lo;
+                if (++nb == (uint32_t)kBatch) {
+                    flush(nb);
+                    nb = 0;
+                }
             }
+            if (nb != 0) flush(nb);
         }
         __syncthreads();
-        // add the rows of all waves in a fixed order and write each entry's row
+        // add the waves' sums in a fixed order and write each entry's row
         const uint32_t n_e = seg_hi - seg_lo;
         for (uint32_t idx = threadIdx.x; idx < n_e * NV; idx += blockDim.x) {
             const uint32_t e = idx / NV, c = idx - e * NV;
             float sum = 0.0f;
-            for (int w = 0; w < nw; ++w)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) sum += s_acc[w][r][idx];
+            for (int w = 0; w < nw; ++w) sum += s_acc[w][idx];
             const uint32_t j = s_j[e];
             if (j != ~0u) grad_pairs[NV * (size_t)j + c] = sum;
         }
