@@ -418,7 +418,7 @@ def decision_stable_pose_fd(rast, raster, g, q0, t0, cams, tg, opts, h):
     analytic gradient is taken with the same pixel weights.  Returns the
     analytic and FD gradients (q then t) and the number of stable pixels."""
     import torch
-    o = raster.RenderOptions(**{**opts.__dict__, "gauss_grads": False})
+    o = raster.RenderOptions(**{**opts.__dict__, "gauss_grads": False, "pixel_hash": True})
     dev = q0.device
 
     P = tg["depth"].numel()

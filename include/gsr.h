@@ -97,6 +97,8 @@ typedef enum {
 #define GSR_NO_GAUSS_GRADS 0x2u  /* skip gradients to the Gaussians (pose-only tracking) */
 #define GSR_NO_POSE_GRADS  0x4u  /* skip gradients to the poses (mapping) */
 #define GSR_COUNT_WORK     0x8u  /* count blend work (gsr_read_work); costs a little time */
+#define GSR_PIXEL_HASH     0x10u /* the forward also writes the per-pixel decision hash that
+                                    gsr_debug_pixel_state reports (test hook; 0 without it) */
 
 /* stages reported by gsr_read_timing() */
 #define GSR_STAGE_BINNING     0  /* projection, compaction, depth sort, records, pairs, tile sort, ranges */
@@ -283,7 +285,8 @@ gsr_status gsr_debug_binning(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_vie
  * stream): the final transmittance, the list position + 1 of the last
  * contributing entry, and a hash of the pixel's decisions (which records
  * contributed, in order, which had their alpha clamped at 0.99, and whether
- * the transmittance cut-off ended the pixel).  Equal hashes under a small
+ * the transmittance cut-off ended the pixel; written only by a forward with
+ * GSR_PIXEL_HASH, 0 otherwise).  Equal hashes under a small
  * parameter change mean the images moved smoothly there, which is what a
  * finite-difference check of the gradients needs. */
 gsr_status gsr_debug_pixel_state(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views,

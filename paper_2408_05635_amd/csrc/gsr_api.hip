@@ -300,9 +300,13 @@ T *at(const gsr_workspace &ws, size_t off) {
 // Call setup: view table, FP64 poses, zero counters (block 0), and a cleared
 // synchronisation region (all blocks).
 __global__ void k_setup(ViewTable tab, ViewTable *vt, const float *__restrict__ pq, const float *__restrict__ pt,
-                        PoseF64 *poses, int64_t *counters, uint4 *sync, int64_t sync16, bool keep_sticky) {
+                        PoseF64 *poses, int64_t *counters, uint4 *sync, int64_t sync16, uint2 *ranges,
+                        int64_t n_tiles, bool keep_sticky) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < sync16; k += (int64_t)gridDim.x * blockDim.x)
         sync[k] = make_uint4(0u, 0u, 0u, 0u);
+    // every tile's range starts empty; k_ranges sets those of the tiles with pairs
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_tiles; k += (int64_t)gridDim.x * blockDim.x)
+        ranges[k] = make_uint2(0u, 0u);
     if (blockIdx.x != 0) return;
     const int t = threadIdx.x;
     const int words = (int)(sizeof(ViewTable) / 4);
@@ -486,25 +490,18 @@ __global__ void k_fill_f64(double *p, int64_t n) {
         p[i] = 0.0;
 }
 
-// [start, end) of every tile in the sorted keys: two binary searches per tile
-// (tiles without pairs get an empty range).
+// [start, end) of every tile with pairs, from the sorted keys: a pair whose
+// key differs from its predecessor's starts its tile's run, one whose key
+// differs from its successor's ends it.  k_setup gave every tile an empty
+// range beforehand.
 __global__ void k_ranges(const uint32_t *__restrict__ keys, const int64_t *__restrict__ counters,
                          uint2 *__restrict__ ranges, int64_t n_tiles) {
     const int64_t K = counters[kCntPairsUsed];
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t r[2];
-        for (int k = 0; k < 2; ++k) {   // first index with key >= t + k
-            int64_t lo = 0, hi = K;
-            while (lo < hi) {
-                const int64_t mid = (lo + hi) >> 1;
-                if ((int64_t)keys[mid] < t + k)
-                    lo = mid + 1;
-                else
-                    hi = mid;
-            }
-            r[k] = (uint32_t)lo;
-        }
-        ranges[t] = make_uint2(r[0], r[1]);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = keys[i];
+        if ((int64_t)k >= n_tiles) continue;   // never expected; keeps writes in bounds
+        if (i == 0 || keys[i - 1] != k) ranges[k].x = (uint32_t)i;
+        if (i == K - 1 || keys[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
     }
 }
 
@@ -797,7 +794,8 @@ unsigned grid_for(int64_t n, int threads, int64_t max_blocks = 65536) {
 }
 
 struct Call {
-    bool count;
+    bool count = false;
+    bool hash = false;   // the forward writes the per-pixel decision hash
     bool keep_sticky = false;   // inside a tracking loop after its first iteration
     gsr_ctx *ctx;
     ViewTable tab;
@@ -836,6 +834,7 @@ gsr_status prepare(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views,
     c.pp.blur = opts->blur2d;
     c.pp.iso = (opts->flags & GSR_ISOTROPIC) != 0;
     c.count = (opts->flags & GSR_COUNT_WORK) != 0;
+    c.hash = (opts->flags & GSR_PIXEL_HASH) != 0;
     return GSR_OK;
 }
 
@@ -860,7 +859,7 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     const int64_t sync16 = (int64_t)(L.sync_bytes / 16);
     hipLaunchKernelGGL(k_setup, dim3((unsigned)std::min<int64_t>(std::max<int64_t>((sync16 + 255) / 256, 1), 1024)),
                        dim3(256), 0, st, c.tab, vt, views->quat, views->trans, poses, counters,
-                       reinterpret_cast<uint4 *>(sync), sync16, c.keep_sticky);
+                       reinterpret_cast<uint4 *>(sync), sync16, at<uint2>(ws, L.ranges), L.T, c.keep_sticky);
     if (L.vn > 0) {
         hipLaunchKernelGGL(c.pp.iso ? k_project_count<true> : k_project_count<false>,
                            dim3(grid_for(c.pp.n, 256, 1ll << 30)), dim3(256), 0, st, c.pp, vt,
@@ -894,7 +893,7 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     // tile order (stable: depth order within a tile); the values are the pairs' records
     const bool p_in1 = radix_sort(pk0, pv0, pk1, pv1, counters + kCntPairsUsed, L.kcap, L.tile_bits, so, 4, st);
     uint2 *ranges = at<uint2>(ws, L.ranges);
-    hipLaunchKernelGGL(k_ranges, dim3(grid_for(L.T, 256, 4096)), dim3(256), 0, st, p_in1 ? pk1 : pk0,
+    hipLaunchKernelGGL(k_ranges, dim3(grid_for(L.kcap, 256, 4096)), dim3(256), 0, st, p_in1 ? pk1 : pk0,
                        (const int64_t *)counters, ranges, L.T);
 }
 
@@ -917,7 +916,8 @@ void enqueue_blend_fwd(Call &c, gsr_images out) {
                 at<uint32_t>(c.ws, L.phash)};
     const unsigned grid = (unsigned)(((L.G + 7) / 8) * 8);
     if (grid > 0) {
-        auto kern = c.count ? k_blend_fwd<true> : k_blend_fwd<false>;
+        auto kern = c.count ? (c.hash ? k_blend_fwd<true, true> : k_blend_fwd<true, false>)
+                            : (c.hash ? k_blend_fwd<false, true> : k_blend_fwd<false, false>);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, c.st, at<ViewTable>(c.ws, L.views),
                            at<float4>(c.ws, L.rec), pair_values(c), at<uint2>(c.ws, L.ranges),
                            at<int64_t>(c.ws, L.counters), bo);

@@ -108,7 +108,8 @@ struct BlendOut {
     uint32_t *hash;             // per pixel: hash of the contributing records, clamp flags and the stop
 };
 
-template <bool COUNT>
+// HASH: also fold the pixel's decisions into out.hash (a test hook; 0 otherwise).
+template <bool COUNT, bool HASH>
 __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ vt, const float4 *__restrict__ rec,
                                                   const uint32_t *__restrict__ pair_rec,
                                                   const uint2 *__restrict__ ranges, int64_t *__restrict__ counters,
@@ -150,7 +151,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
             s_b[slot] = B;
             s_c[slot] = C;
             s_pos[slot] = e;
-            s_rec_id[slot] = s;
+            if (HASH) s_rec_id[slot] = s;
         }
         __syncthreads();
         const int n = __popcll(m);
@@ -166,8 +167,8 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
             const bool take = hit && !(Tn < kTMin);
             if (COUNT) n_contrib += take ? 1u : 0u;
             const float4 cc = s_c[k];
-            uint32_t pos1 = s_pos[k] + 1u, rid2 = 2u * s_rec_id[k] + (ev.clamped ? 1u : 0u);
-            asm volatile("" : "+v"(pos1), "+v"(rid2));   // read for every lane: no branch around the reads
+            uint32_t pos1 = s_pos[k] + 1u;
+            asm volatile("" : "+v"(pos1));   // read for every lane: no branch around the read
             const float wgt = take ? ev.alpha * T : 0.0f;
             c0 = __builtin_fmaf(wgt, cc.x, c0);
             c1 = __builtin_fmaf(wgt, cc.y, c1);
@@ -176,8 +177,12 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
             cs += wgt;
             T = take ? Tn : T;
             last = take ? pos1 : last;
-            const uint32_t hin = take ? rid2 : 0xffffffffu;
-            hsh = (take || stop) ? (hsh ^ hin) * 0x01000193u : hsh;
+            if (HASH) {
+                uint32_t rid2 = 2u * s_rec_id[k] + (ev.clamped ? 1u : 0u);
+                asm volatile("" : "+v"(rid2));
+                const uint32_t hin = take ? rid2 : 0xffffffffu;
+                hsh = (take || stop) ? (hsh ^ hin) * 0x01000193u : hsh;
+            }
             done = done || stop;
             if ((k & 7) == 7 && ballot(!done) == 0) break;
         }
@@ -200,7 +205,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
         out.sil[V.pix_off + pix] = cs;
         out.t_final[V.pix_off + pix] = T;
         out.n_last[V.pix_off + pix] = last;
-        out.hash[V.pix_off + pix] = hsh;
+        out.hash[V.pix_off + pix] = HASH ? hsh : 0u;
     }
 }
 

@@ -226,6 +226,10 @@ inline void scan_exclusive(Src src, Sink sink, const int64_t *n_dev, int64_t n_c
 // ---------------------------------------------------------------------------
 
 constexpr int kSortGroup = 64;
+// Loads in flight per thread when the last blocks collect counts: each round
+// is a device-coherent round trip, so a group of kSortGroup blocks costs
+// kSortGroup / kRound of them.
+constexpr int kRound = 16;
 
 // Items per thread of a sort pass: small blocks (1024 items) keep every CU
 // busy and each block's ranking rounds few for the sizes of one frame;
@@ -309,13 +313,13 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_count(const uint32_t *__
     if (!arrive_last(done + g, (uint32_t)g_n)) return;
     // last block of group g: exclusive offsets of digit t within the group
     uint32_t run = 0;
-    for (int q0 = 0; q0 < g_n; q0 += 16) {
-        uint64_t w[16];
+    for (int q0 = 0; q0 < g_n; q0 += kRound) {
+        uint64_t w[kRound];
 #pragma unroll
-        for (int k = 0; k < 16; ++k)   // 16 loads in flight
+        for (int k = 0; k < kRound; ++k)   // kRound loads in flight
             w[k] = q0 + k < g_n ? peek(so.words + (size_t)(g0 + q0 + k) * 256 + t) : 0ull;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
+        for (int k = 0; k < kRound; ++k) {
             if (q0 + k < g_n) {
                 uint64_t *p = so.words + (size_t)(g0 + q0 + k) * 256 + t;
                 const uint32_t c = await_word(p, w[k], tag, so.error);
@@ -328,12 +332,12 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_count(const uint32_t *__
     if (!arrive_last(done + so.groups_cap, (uint32_t)ng)) return;
     // last group: global base of every (group, digit)
     uint32_t tot = 0;
-    for (int64_t q0 = 0; q0 < ng; q0 += 16) {
-        uint64_t w[16];
+    for (int64_t q0 = 0; q0 < ng; q0 += kRound) {
+        uint64_t w[kRound];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) w[k] = q0 + k < ng ? peek(so.gwords + (size_t)(q0 + k) * 256 + t) : 0ull;
+        for (int k = 0; k < kRound; ++k) w[k] = q0 + k < ng ? peek(so.gwords + (size_t)(q0 + k) * 256 + t) : 0ull;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
+        for (int k = 0; k < kRound; ++k) {
             if (q0 + k < ng) {
                 const uint32_t c = await_word(so.gwords + (size_t)(q0 + k) * 256 + t, w[k], tag, so.error);
                 so.gbase[(size_t)(q0 + k) * 256 + t] = tot;
@@ -343,14 +347,21 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_count(const uint32_t *__
     }
     uint32_t all;
     const uint32_t dbase = block_excl_scan_u32<kScanThreads>((int)t < nd ? tot : 0u, all);
-    for (int64_t q = 0; q < ng; ++q) so.gbase[(size_t)q * 256 + t] += dbase;
+    for (int64_t q0 = 0; q0 < ng; q0 += kRound) {   // kRound loads in flight, then the stores
+        uint32_t v[kRound];
+#pragma unroll
+        for (int k = 0; k < kRound; ++k) v[k] = q0 + k < ng ? so.gbase[(size_t)(q0 + k) * 256 + t] : 0u;
+#pragma unroll
+        for (int k = 0; k < kRound; ++k)
+            if (q0 + k < ng) so.gbase[(size_t)(q0 + k) * 256 + t] = v[k] + dbase;
+    }
 }
 
 // Stable scatter: items keep their input order within a digit.  The block
-// first ranks its items within their digits (round by round, in input
-// order), then places them in LDS in digit order and writes each digit's
-// run to consecutive global positions, so that the stores are coalesced
-// runs instead of one transaction per item.
+// first ranks its items within their digits (each wave its own contiguous
+// run, in input order), then places them in LDS in digit order and writes
+// each digit's run to consecutive global positions, so that the stores are
+// coalesced runs instead of one transaction per item.
 template <int ITEMS>
 __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *__restrict__ kin,
                                                                 const uint32_t *__restrict__ vin,
@@ -358,9 +369,10 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
                                                                 const int64_t *n_dev, int64_t n_host, int shift,
                                                                 int dbits, SortState so) {
     constexpr int kItems = kScanThreads * ITEMS;
+    constexpr int kWaves = kScanThreads / 64;
     __shared__ uint32_t s_goff[256];   // global position of the block's first item of each digit
-    __shared__ uint32_t s_cnt[256];    // running count per digit, then the digit's first slot in s_k
-    __shared__ uint32_t s_w[kScanThreads / 64][256];
+    __shared__ uint32_t s_cnt[256];    // the block's count of each digit, then the digit's first slot in s_k
+    __shared__ uint32_t s_h[kWaves][256];   // per wave: running count of each digit, then the wave's offset in it
     __shared__ uint32_t s_k[kItems], s_v[kItems];
     const int64_t n = dev_count(n_dev, n_host);
     const int64_t b = blockIdx.x;
@@ -368,41 +380,52 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
     if (base >= n) return;   // block-uniform
     const int nd = 1 << dbits;
     const uint32_t mask = (uint32_t)nd - 1u;
-    const uint32_t t = threadIdx.x, wave = t >> 6;
+    const uint32_t t = threadIdx.x, wave = t >> 6, lane = t & 63u;
     s_goff[t] = (uint32_t)so.words[(size_t)b * 256 + t] + so.gbase[(size_t)(b / kSortGroup) * 256 + t];
-    s_cnt[t] = 0u;
+    for (uint32_t k = lane; k < 256u; k += 64u) s_h[wave][k] = 0u;
+    // Each wave holds a contiguous run of 64 * ITEMS items of the block, so the
+    // block's stable order is (wave, round, lane): every wave ranks its own
+    // items in order without block barriers, and one scan over the waves per
+    // digit joins them.
+    const int64_t wbase = base + (int64_t)wave * (64 * ITEMS);
     uint32_t keys[ITEMS], vals[ITEMS], lrank[ITEMS];   // all loads in flight at once
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        const int64_t i = base + (int64_t)j * kScanThreads + t;
+        const int64_t i = wbase + (int64_t)j * 64 + lane;
         keys[j] = i < n ? kin[i] : 0u;
         vals[j] = i < n ? vin[i] : 0u;
         lrank[j] = 0u;
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        if (base + (int64_t)j * kScanThreads >= n) break;   // block-uniform
-        const bool valid = base + (int64_t)j * kScanThreads + t < n;
+        const bool valid = wbase + (int64_t)j * 64 + lane < n;
+        const uint64_t vmask = ballot(valid);
+        if (vmask == 0) break;   // wave-uniform
         const uint32_t d = (keys[j] >> shift) & mask;
-        for (int k = t; k < (kScanThreads / 64) * 256; k += kScanThreads) (&s_w[0][0])[k] = 0u;
-        __syncthreads();
-        const uint64_t peers = match_digit(d, dbits, ballot(valid));
+        const uint64_t peers = match_digit(d, dbits, vmask);
         const uint32_t rank = rank_below(peers);
-        if (valid && rank == 0) s_w[wave][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if ((int)t < nd) {
-            uint32_t run = s_cnt[t];
-            for (int w = 0; w < kScanThreads / 64; ++w) {
-                const uint32_t c = s_w[w][t];
-                s_w[w][t] = run;
-                run += c;
-            }
-            s_cnt[t] = run;
-        }
-        __syncthreads();
-        if (valid) lrank[j] = s_w[wave][d] + rank;
-        __syncthreads();   // s_w is cleared by the next round
+        // every lane reads the digit's count before its first lane updates it
+        // (the LDS completes one wave's operations in order)
+        const uint32_t before = s_h[wave][d];
+        lrank[j] = before + rank;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rank == 0) s_h[wave][d] = before + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
+    __syncthreads();
+    uint32_t run = 0;
+    if ((int)t < nd) {
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t c = s_h[w][t];
+            s_h[w][t] = run;
+            run += c;
+        }
+    }
+    s_cnt[t] = run;
+    __syncthreads();
     // digits' first slots in the block's digit-ordered staging
     uint32_t tot;
     const uint32_t lbase = block_excl_scan_u32<kScanThreads>(s_cnt[t], tot);
@@ -410,9 +433,9 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        if (base + (int64_t)j * kScanThreads + t < n) {
+        if (wbase + (int64_t)j * 64 + lane < n) {
             const uint32_t d = (keys[j] >> shift) & mask;
-            const uint32_t lp = s_cnt[d] + lrank[j];
+            const uint32_t lp = s_cnt[d] + s_h[wave][d] + lrank[j];
             if (lp < (uint32_t)kItems) {   // always true for consistent counts
                 s_k[lp] = keys[j];
                 s_v[lp] = vals[j];

@@ -37,6 +37,7 @@ class RenderOptions:
     gauss_grads: bool = True
     pose_grads: bool = True
     count_work: bool = False
+    pixel_hash: bool = False   # forwards write the decision hash that pixel_state reports
 
 
 @dataclass
@@ -168,6 +169,8 @@ class Rasterizer:
             flags |= _abi.GSR_NO_POSE_GRADS
         if o.count_work:
             flags |= _abi.GSR_COUNT_WORK
+        if o.pixel_hash:
+            flags |= _abi.GSR_PIXEL_HASH
         return _abi.Options(o.w_rgb, o.w_depth, o.w_sil, o.w_prior, o.z_near, o.blur2d, o.sil_mask_thresh,
                             int(o.tile[0]), int(o.tile[1]), flags)
 

@@ -68,7 +68,7 @@ def test_pose_gradient_fd_config1(rast):
     g = dev_params(w.gaussians)
     q, t = dev_poses(w.views)
     tg = to_dev(oracle_targets(w))
-    opts = RenderOptions(**w.weights, gauss_grads=False)
+    opts = RenderOptions(**w.weights, gauss_grads=False, pixel_hash=True)
 
     def perturb(k, d):
         qq, tt = q.clone(), t.clone()
@@ -92,7 +92,7 @@ def test_gaussian_gradient_fd_tiny(rast):
     g = dev_params(w.gaussians)
     q, t = dev_poses(w.views)
     tg = to_dev(oracle_targets(w))
-    opts = RenderOptions(**w.weights, pose_grads=False)
+    opts = RenderOptions(**w.weights, pose_grads=False, pixel_hash=True)
     # mean x/y/z, one log-scale, one quaternion component, opacity and red of three Gaussians
     coords = []
     for i in (0, 7, 19):
