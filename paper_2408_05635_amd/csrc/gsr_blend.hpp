@@ -54,7 +54,8 @@ __device__ __forceinline__ BlockPos locate_block(const ViewTable *vt) {
 // Can the record reach alpha >= 1/255 anywhere in the 8x8 block?  The
 // quadratic form Q = (l11 dx + l21 dy)^2 + (l22 dy)^2 is minimised over the
 // block's box: zero if the mean is inside, else the least value along the four
-// edges (each edge's minimiser is the clamped 1-D minimiser).  Kept when
+// edges (each edge's minimiser is the clamped 1-D minimiser, located with a
+// hardware reciprocal: its error moves Q only to second order).  Kept when
 // Q_min <= log2(255 o) with a relative margin of 2^-8, far above FP32 rounding.
 __device__ __forceinline__ bool block_may_contribute(const float4 A, const float4 B, float bx0, float by0) {
     const float o = B.w;
@@ -71,10 +72,11 @@ __device__ __forceinline__ bool block_may_contribute(const float4 A, const float
         return u * u + w * w;
     };
     auto clampf = [](float x, float lo, float hi) { return fminf(fmaxf(x, lo), hi); };
-    float q = Q(dx0, clampf(-qb * dx0 / qc, dy0, dy1));
-    q = fminf(q, Q(dx1, clampf(-qb * dx1 / qc, dy0, dy1)));
-    q = fminf(q, Q(clampf(-qb * dy0 / qa, dx0, dx1), dy0));
-    q = fminf(q, Q(clampf(-qb * dy1 / qa, dx0, dx1), dy1));
+    const float rqc = __builtin_amdgcn_rcpf(qc), rqa = __builtin_amdgcn_rcpf(qa);
+    float q = Q(dx0, clampf(-qb * dx0 * rqc, dy0, dy1));
+    q = fminf(q, Q(dx1, clampf(-qb * dx1 * rqc, dy0, dy1)));
+    q = fminf(q, Q(clampf(-qb * dy0 * rqa, dx0, dx1), dy0));
+    q = fminf(q, Q(clampf(-qb * dy1 * rqa, dx0, dx1), dy1));
     return q <= qcut * (1.0f + 0x1p-8f) + 0x1p-10f;
 }
 
@@ -447,14 +449,16 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
             for (int k = __popcll(m) - 1; k >= 0; --k) {
                 const uint32_t pos = s_pos[wave][k];
                 const bool act = pos < last;
-                if (ballot(act) == 0) continue;   // wave-uniform
+                const uint64_t m_act = ballot(act);
+                if (m_act == 0) continue;   // wave-uniform
                 const float4 a = s_a[wave][k], b = s_b[wave][k];
                 // every lane evaluates (the wave pays for it either way); the
                 // decisions and the state updates are selects, not branches
                 const AlphaEval ev = eval_alpha(a, b, fpx, fpy);
-                const bool contrib = act && ev.alpha >= kAlphaMin;
+                const bool reach = ev.alpha >= kAlphaMin;
+                const bool contrib = act && reach;
                 if (COUNT) n_eval += act ? 1u : 0u;
-                if (ballot(contrib) == 0) continue;   // wave-uniform: nothing to add for this entry
+                if ((ballot(reach) & m_act) == 0) continue;   // wave-uniform: nothing to add for this entry
                 if (COUNT) {
                     n_contrib += contrib ? 1u : 0u;
                     ++n_red;
@@ -494,7 +498,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                 T = contrib ? Tk : T;
                 quad_sums<NV>(d);
                 if ((lane & 3u) == 0u) {
-                    float2 *dst = reinterpret_cast<float2 *>(qs + (nb * 16 + (lane >> 2)) * NV);
+                    float2 *dst = reinterpret_cast<float2 *>(&s_q[wave][(nb * 16 + (lane >> 2)) * NV]);
 #pragma unroll
                     for (int c = 0; c < NV / 2; ++c) dst[c] = make_float2(d[2 * c], d[2 * c + 1]);
                 }
