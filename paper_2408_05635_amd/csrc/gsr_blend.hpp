@@ -157,16 +157,16 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
         }
         __syncthreads();
         const int n = __popcll(m);
-        for (int k = 0; k < n; ++k) {
-            // Every lane evaluates; a lane that is done, or that the entry does
-            // not reach, takes weight 0, which leaves its sums exactly as they
-            // were (fma(0, c, x) = x), so the updates need no branches.
+        // Every lane evaluates; a lane that is done, or that the entry does
+        // not reach, takes weight 0, which leaves its sums exactly as they
+        // were (fma(0, c, x) = x), so the updates need no branches.
+        auto entry = [&](int k) {
             const AlphaEval ev = eval_alpha(s_a[k], s_b[k], fpx, fpy);
             if (COUNT) n_eval += done ? 0u : 1u;
             const bool hit = !done && ev.alpha >= kAlphaMin;
             const float Tn = T * (1.0f - ev.alpha);
             const bool stop = hit && Tn < kTMin;
-            const bool take = hit && !(Tn < kTMin);
+            const bool take = hit != stop;   // hit and not stopped
             if (COUNT) n_contrib += take ? 1u : 0u;
             const float4 cc = s_c[k];
             uint32_t pos1 = s_pos[k] + 1u;
@@ -186,7 +186,14 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
                 hsh = (take || stop) ? (hsh ^ hin) * 0x01000193u : hsh;
             }
             done = done || stop;
-            if ((k & 7) == 7 && ballot(!done) == 0) break;
+        };
+        // groups of 8 entries (LDS addresses as immediate offsets), then the
+        // wave checks whether any of its pixels is still open
+        for (int k0 = 0; k0 < n; k0 += 8) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (k0 + j < n) entry(k0 + j);
+            if (ballot(!done) == 0) break;
         }
         __syncthreads();
     }
