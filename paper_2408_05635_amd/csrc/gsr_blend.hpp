@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
     // s_q[wave][batch slot][quad][NV]; once kBatch entries are stored, lane
     // (k, c) adds the 16 quad sums of value c of entry k, in quad order, into
     // s_acc[wave][entry of the segment][c].
-    constexpr int kBatch = 64 / NV;
+    constexpr int kBatch = 40 / NV;   // entries per batch: 4 (NV = 10) or 6 (NV = 6), LDS sized for occupancy
     __shared__ float s_q[kBwdMaxWaves][kBatch * 16 * NV];
     __shared__ uint32_t s_bslot[kBwdMaxWaves][kBatch];
     __shared__ float s_acc[kBwdMaxWaves][kSeg * NV];
@@ -453,11 +453,11 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             uint32_t nb = 0;   // entries stored in the batch (wave-uniform)
-            for (int k = __popcll(m) - 1; k >= 0; --k) {
+            auto entry = [&](int k) {
                 const uint32_t pos = s_pos[wave][k];
                 const bool act = pos < last;
                 const uint64_t m_act = ballot(act);
-                if (m_act == 0) continue;   // wave-uniform
+                if (m_act == 0) return;   // wave-uniform
                 const float4 a = s_a[wave][k], b = s_b[wave][k];
                 // every lane evaluates (the wave pays for it either way); the
                 // decisions and the state updates are selects, not branches
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                 const bool reach = ev.alpha >= kAlphaMin;
                 const bool contrib = act && reach;
                 if (COUNT) n_eval += act ? 1u : 0u;
-                if ((ballot(reach) & m_act) == 0) continue;   // wave-uniform: nothing to add for this entry
+                if ((ballot(reach) & m_act) == 0) return;   // wave-uniform: nothing to add for this entry
                 if (COUNT) {
                     n_contrib += contrib ? 1u : 0u;
                     ++n_red;
@@ -514,6 +514,12 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                     flush(nb);
                     nb = 0;
                 }
+            };
+            // entries in reverse, in groups of 4 (LDS addresses as immediate offsets)
+            for (int k0 = __popcll(m) - 1; k0 >= 0; k0 -= 4) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (k0 - j >= 0) entry(k0 - j);
             }
             if (nb != 0) flush(nb);
         }
