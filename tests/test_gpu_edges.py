@@ -154,3 +154,26 @@ def test_pose_only_backward_matches_oracle(rast):
     w2 = scenes.config2(n_views=2, n=40000)
     out, r, ok = _run(rast, w2, gauss_grads=False)
     _check(out, r, ok, w2, "pose only, 2 room views", keys=["dq_t", "dt", "dq_c", "dc"])
+
+
+def test_pixel_hash_only_on_request(rast):
+    """The decision hash is written only with GSR_PIXEL_HASH; the images do not
+    depend on the flag, and the hash is the same on a repeated call."""
+    from paper_2408_05635_amd.raster import RenderOptions
+    base = scenes.tiny_scene(37, n=40)
+    g = dev_params(base.gaussians)
+    q, t = dev_poses(base.views)
+    cams = base.views.cams
+    runs = []
+    for flag in (False, True, True):
+        o = RenderOptions(pixel_hash=flag)
+        rgb, depth, sil, ws = rast.forward(g, q, t, cams, o)
+        st = rast.pixel_state(g, q, t, cams, o, ws=ws[1])
+        runs.append((rgb.clone(), depth.clone(), sil.clone(), st["hash"].clone(), st["n_last"].clone()))
+    torch.cuda.synchronize()
+    off, on, again = runs
+    assert torch.all(off[3] == 0)
+    assert bool((on[3] != 0).any())
+    assert torch.equal(on[3], again[3])
+    for k in (0, 1, 2, 4):   # images and last contributors do not depend on the flag
+        assert torch.equal(off[k], on[k]), k
