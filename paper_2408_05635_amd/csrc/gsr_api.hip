@@ -94,10 +94,9 @@ constexpr size_t kAlign = 256;
 constexpr int kRecGrad = 14;   // per-record parameter gradient: mu 3, q 4, log_s 3, logit 1, rgb 3
 constexpr int kRecBwdMaxBlocks = 2048;   // grid cap of the record backward (one pose row per block)
 constexpr int kEmitChunk = 1024;         // pairs per emission block
-// synchronisation region, cleared by every call: scan tickets (256 B), the
-// scans' look-back words, the sort passes' arrival counters and tagged words
+// synchronisation region, cleared by every call: scan tickets (256 B) and the
+// scans' look-back words
 constexpr size_t kSyncTickets = 256;
-constexpr int kSortPasses = 8;   // 4 passes of the depth sort, at most 4 of the tile sort
 // ids of the binning's scans
 enum SyncId : uint32_t { kIdVisible = 0, kIdOffsets = 1 };
 
@@ -109,11 +108,10 @@ struct Layout {
     int32_t G;            // total blend blocks
     int tile_bits;        // key bits of the tile sort
     size_t views, poses, counters, cnt, zkey, dk0, dv0, dk1, dv1, inv, rec, trect, cnt_s, poff, pk0, pv0, pk1, pv1,
-        chunk, ranges, tfinal, nlast, phash, gpairs, rgrad, losst, poseblk, sgbase, sync;
-    int64_t sort_groups;  // groups of sort blocks at the capacity
-    // offsets in the sync region (cleared by every call): scan look-back
-    // words, sort arrival counters, sort block words, sort group words
-    size_t sync_status, sync_done, sync_words, sync_gwords, sync_bytes;
+        chunk, ranges, tfinal, nlast, phash, gpairs, rgrad, losst, poseblk, scounts, stotals, sync;
+    int64_t sort_nb;      // sort blocks of the larger sort (row length of scounts)
+    // offsets in the sync region (cleared by every call): scan look-back words
+    size_t sync_status, sync_bytes;
     size_t total;
 };
 
@@ -275,14 +273,11 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     L.poseblk = take(sizeof(double) * 12 * V * (size_t)std::max<int64_t>(
                                            std::min<int64_t>((L.vn + 255) / 256, kRecBwdMaxBlocks), 1));
     const int64_t nb_scan = std::max<int64_t>((std::max<int64_t>(L.vn, kcap) + kChunk - 1) / kChunk, 1);
-    const int64_t nb = std::max<int64_t>(std::max(sort_blocks(L.vn), sort_blocks(kcap)), 1);
-    L.sort_groups = (nb + kSortGroup - 1) / kSortGroup;
-    L.sgbase = take(4 * 256 * (size_t)L.sort_groups);
+    L.sort_nb = std::max<int64_t>(std::max(sort_blocks(L.vn), sort_blocks(kcap)), 1);
+    L.scounts = take(4 * 256 * (size_t)L.sort_nb);
+    L.stotals = take(4 * 256);
     L.sync_status = kSyncTickets;
-    L.sync_done = align_up(L.sync_status + 8 * (size_t)nb_scan);
-    L.sync_words = align_up(L.sync_done + 4 * (size_t)kSortPasses * (size_t)(L.sort_groups + 1));
-    L.sync_gwords = align_up(L.sync_words + 8 * 256 * (size_t)nb);
-    L.sync_bytes = align_up(L.sync_gwords + 8 * 256 * (size_t)L.sort_groups);
+    L.sync_bytes = align_up(L.sync_status + 8 * (size_t)nb_scan);
     L.sync = take(L.sync_bytes);
     L.total = off;
     return L;
@@ -853,9 +848,7 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     char *sync = at<char>(ws, L.sync);
     SyncState ss{reinterpret_cast<uint32_t *>(sync), reinterpret_cast<uint64_t *>(sync + L.sync_status),
                  counters + kCntSyncError};
-    SortState so{reinterpret_cast<uint64_t *>(sync + L.sync_words), reinterpret_cast<uint64_t *>(sync + L.sync_gwords),
-                 at<uint32_t>(ws, L.sgbase), reinterpret_cast<uint32_t *>(sync + L.sync_done), L.sort_groups,
-                 counters + kCntSyncError};
+    SortState so{at<uint32_t>(ws, L.scounts), at<uint32_t>(ws, L.stotals)};
     const int64_t sync16 = (int64_t)(L.sync_bytes / 16);
     hipLaunchKernelGGL(k_setup, dim3((unsigned)std::min<int64_t>(std::max<int64_t>((sync16 + 255) / 256, 1), 1024)),
                        dim3(256), 0, st, c.tab, vt, views->quat, views->trans, poses, counters,
@@ -870,7 +863,7 @@ void enqueue_binning(Call &c, const gsr_views *views) {
                    TotalTo{counters + kCntVisible}, st);
     // depth order: stable sort on the float32 depth bits (positive floats sort as integers)
     const bool d_in1 =
-        radix_sort(dk0, dv0, dk1, dv1, counters + kCntVisible, L.vn, 32, so, 0, st);
+        radix_sort(dk0, dv0, dk1, dv1, counters + kCntVisible, L.vn, 32, so, st);
     const uint32_t *gid_sorted = d_in1 ? dv1 : dv0;
     float4 *rec = at<float4>(ws, L.rec);
     uint2 *trect = at<uint2>(ws, L.trect);
@@ -891,7 +884,7 @@ void enqueue_binning(Call &c, const gsr_views *views) {
         hipLaunchKernelGGL(k_emit, dim3((unsigned)n_chunks), dim3(256), 0, st, counters, poff,
                            (const uint32_t *)chunk_first, trect, gid_sorted, vt, c.pp.n, pk0, pv0);
     // tile order (stable: depth order within a tile); the values are the pairs' records
-    const bool p_in1 = radix_sort(pk0, pv0, pk1, pv1, counters + kCntPairsUsed, L.kcap, L.tile_bits, so, 4, st);
+    const bool p_in1 = radix_sort(pk0, pv0, pk1, pv1, counters + kCntPairsUsed, L.kcap, L.tile_bits, so, st);
     uint2 *ranges = at<uint2>(ws, L.ranges);
     hipLaunchKernelGGL(k_ranges, dim3(grid_for(L.kcap, 256, 4096)), dim3(256), 0, st, p_in1 ? pk1 : pk0,
                        (const int64_t *)counters, ranges, L.T);

@@ -216,25 +216,17 @@ inline void scan_exclusive(Src src, Sink sink, const int64_t *n_dev, int64_t n_c
 // ---------------------------------------------------------------------------
 // stable LSD radix sort of (uint32 key, uint32 value) pairs, <= 8 bits a pass
 //
-// Two launches a pass.  k_radix_count publishes every block's digit counts
-// as tagged words; the last block of each group of kSortGroup blocks to
-// arrive (found with an atomic counter) collects its group's counts, stores
-// exclusive offsets within the group and publishes the group totals; the
-// last group to arrive turns the group totals into global bases.  Blocks
-// that arrive last only wait for words whose writers have already issued
-// them.  k_radix_scatter then places every block's items stably.
+// Three launches a pass, none of which waits for another block:
+// k_radix_count stores every block's digit counts (plain stores, laid out
+// digit-major); k_digit_scan, one block per digit, turns a digit's counts
+// into exclusive offsets over the blocks and its total; k_radix_scatter adds
+// the digit bases (an exclusive scan of the 256 totals, done by every block)
+// and places its items stably.  The kernel boundaries order the passes, so
+// nothing needs clearing between calls.
 // ---------------------------------------------------------------------------
 
-constexpr int kSortGroup = 64;
-// Loads in flight per thread when the last blocks collect counts: each round
-// is a device-coherent round trip, so a group of kSortGroup blocks costs
-// kSortGroup / kRound of them.
-constexpr int kRound = 16;
-
-// Items per thread of a sort pass: small blocks (1024 items) keep every CU
-// busy and each block's ranking rounds few for the sizes of one frame;
-// larger inputs use 4096-item blocks, whose fewer count words and groups
-// cost less than the longer rounds.
+// Items per thread of a sort pass: 1024-item blocks up to 2M items, 4096
+// above (fewer blocks, so fewer count rows to scan).
 constexpr int64_t kSmallSortCap = 2ll << 20;
 inline int sort_items(int64_t cap) { return cap <= kSmallSortCap ? 4 : 16; }
 inline int64_t sort_blocks(int64_t cap) {
@@ -242,14 +234,10 @@ inline int64_t sort_blocks(int64_t cap) {
     return (cap + chunk - 1) / chunk;
 }
 
-// Per-call state of the sort passes.
+// Per-call state of the sort passes (no clearing needed).
 struct SortState {
-    uint64_t *words;     // [256 * blocks] tagged digit counts, then offsets within the group (cleared per call)
-    uint64_t *gwords;    // [256 * groups] tagged group totals (cleared per call)
-    uint32_t *gbase;     // [256 * groups] global base of each (group, digit)
-    uint32_t *done;      // [passes][groups + 1] arrival counters (cleared per call)
-    int64_t groups_cap;  // groups of the capacity
-    int64_t *error;      // raised when a wait gives up
+    uint32_t *counts;   // [256][blocks of the largest sort] digit counts, then exclusive offsets over the blocks
+    uint32_t *totals;   // [256] digit totals of the current pass
 };
 
 // Lanes of the wave holding the same digit as this lane (among `valid` lanes).
@@ -263,30 +251,17 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, int dbits, uint64_t 
     return peers;
 }
 
-// Whether this block is the last of `of` blocks to arrive at the counter
-// (every thread's earlier stores are issued before the block arrives).
-__device__ __forceinline__ bool arrive_last(uint32_t *counter, uint32_t of) {
-    __shared__ uint32_t s_last;
-    __syncthreads();
-    if (threadIdx.x == 0)
-        s_last = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == of - 1u;
-    __syncthreads();
-    return s_last != 0u;
-}
-
 template <int ITEMS>
 __global__ __launch_bounds__(kScanThreads) void k_radix_count(const uint32_t *__restrict__ kin, const int64_t *n_dev,
                                                               int64_t n_host, int shift, int dbits, SortState so,
-                                                              int pass) {
+                                                              int64_t nb_cap) {
     __shared__ uint32_t s_cnt[256];
     const uint32_t t = threadIdx.x;
     const int64_t n = dev_count(n_dev, n_host);
     const int64_t nb = (n + (kScanThreads * ITEMS) - 1) / (kScanThreads * ITEMS);
     const int64_t b = blockIdx.x;
-    if (b >= nb) return;   // block-uniform
-    const int nd = 1 << dbits;
-    const uint32_t mask = (uint32_t)nd - 1u;
-    const uint32_t tag = (uint32_t)pass + 1u;
+    if (b >= nb || b >= nb_cap) return;   // block-uniform
+    const uint32_t mask = (1u << dbits) - 1u;
     s_cnt[t] = 0u;
     __syncthreads();
     const int64_t base = b * (kScanThreads * ITEMS);
@@ -304,57 +279,36 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_count(const uint32_t *__
         if (valid && rank_below(peers) == 0) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
     }
     __syncthreads();
-    store_word(so.words + (size_t)b * 256 + t, tag, s_cnt[t]);
-    const int64_t ng = (nb + kSortGroup - 1) / kSortGroup;
-    const int64_t g = b / kSortGroup;
-    const int64_t g0 = g * kSortGroup;
-    const int g_n = (int)((g0 + kSortGroup < nb ? g0 + kSortGroup : nb) - g0);
-    uint32_t *done = so.done + (size_t)pass * (so.groups_cap + 1);
-    if (!arrive_last(done + g, (uint32_t)g_n)) return;
-    // last block of group g: exclusive offsets of digit t within the group
-    uint32_t run = 0;
-    for (int q0 = 0; q0 < g_n; q0 += kRound) {
-        uint64_t w[kRound];
-#pragma unroll
-        for (int k = 0; k < kRound; ++k)   // kRound loads in flight
-            w[k] = q0 + k < g_n ? peek(so.words + (size_t)(g0 + q0 + k) * 256 + t) : 0ull;
-#pragma unroll
-        for (int k = 0; k < kRound; ++k) {
-            if (q0 + k < g_n) {
-                uint64_t *p = so.words + (size_t)(g0 + q0 + k) * 256 + t;
-                const uint32_t c = await_word(p, w[k], tag, so.error);
-                store_word(p, 0u, run);
-                run += c;
-            }
-        }
+    so.counts[(size_t)t * nb_cap + b] = s_cnt[t];
+}
+
+// One block per digit: exclusive offsets of the digit over the blocks (in
+// block order) and the digit's total.
+template <int ITEMS>
+__global__ __launch_bounds__(kScanThreads) void k_digit_scan(const int64_t *n_dev, int64_t n_host, int dbits,
+                                                             SortState so, int64_t nb_cap) {
+    const int d = blockIdx.x;
+    const int64_t n = dev_count(n_dev, n_host);
+    int64_t nb = (n + (kScanThreads * ITEMS) - 1) / (kScanThreads * ITEMS);
+    nb = nb < nb_cap ? nb : nb_cap;
+    if (d >= (1 << dbits)) {   // block-uniform
+        if (threadIdx.x == 0) so.totals[d] = 0u;
+        return;
     }
-    store_word(so.gwords + (size_t)g * 256 + t, tag, run);
-    if (!arrive_last(done + so.groups_cap, (uint32_t)ng)) return;
-    // last group: global base of every (group, digit)
-    uint32_t tot = 0;
-    for (int64_t q0 = 0; q0 < ng; q0 += kRound) {
-        uint64_t w[kRound];
-#pragma unroll
-        for (int k = 0; k < kRound; ++k) w[k] = q0 + k < ng ? peek(so.gwords + (size_t)(q0 + k) * 256 + t) : 0ull;
-#pragma unroll
-        for (int k = 0; k < kRound; ++k) {
-            if (q0 + k < ng) {
-                const uint32_t c = await_word(so.gwords + (size_t)(q0 + k) * 256 + t, w[k], tag, so.error);
-                so.gbase[(size_t)(q0 + k) * 256 + t] = tot;
-                tot += c;
-            }
-        }
-    }
+    uint32_t *row = so.counts + (size_t)d * nb_cap;
+    const int64_t per = (nb + kScanThreads - 1) / kScanThreads;   // consecutive blocks per thread
+    const int64_t q0 = (int64_t)threadIdx.x * per;
+    const int64_t q1 = q0 + per < nb ? q0 + per : nb;
+    uint32_t s = 0;
+    for (int64_t q = q0; q < q1; ++q) s += row[q];
     uint32_t all;
-    const uint32_t dbase = block_excl_scan_u32<kScanThreads>((int)t < nd ? tot : 0u, all);
-    for (int64_t q0 = 0; q0 < ng; q0 += kRound) {   // kRound loads in flight, then the stores
-        uint32_t v[kRound];
-#pragma unroll
-        for (int k = 0; k < kRound; ++k) v[k] = q0 + k < ng ? so.gbase[(size_t)(q0 + k) * 256 + t] : 0u;
-#pragma unroll
-        for (int k = 0; k < kRound; ++k)
-            if (q0 + k < ng) so.gbase[(size_t)(q0 + k) * 256 + t] = v[k] + dbase;
+    uint32_t run = block_excl_scan_u32<kScanThreads>(s, all);
+    for (int64_t q = q0; q < q1; ++q) {
+        const uint32_t c = row[q];
+        row[q] = run;
+        run += c;
     }
+    if (threadIdx.x == 0) so.totals[d] = all;
 }
 
 // Stable scatter: items keep their input order within a digit.  The block
@@ -367,7 +321,7 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
                                                                 const uint32_t *__restrict__ vin,
                                                                 uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                                 const int64_t *n_dev, int64_t n_host, int shift,
-                                                                int dbits, SortState so) {
+                                                                int dbits, SortState so, int64_t nb_cap) {
     constexpr int kItems = kScanThreads * ITEMS;
     constexpr int kWaves = kScanThreads / 64;
     __shared__ uint32_t s_goff[256];   // global position of the block's first item of each digit
@@ -381,7 +335,12 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
     const int nd = 1 << dbits;
     const uint32_t mask = (uint32_t)nd - 1u;
     const uint32_t t = threadIdx.x, wave = t >> 6, lane = t & 63u;
-    s_goff[t] = (uint32_t)so.words[(size_t)b * 256 + t] + so.gbase[(size_t)(b / kSortGroup) * 256 + t];
+    {   // global position of the block's first item of each digit: the digit's
+        // base (totals of the smaller digits) plus the counts of earlier blocks
+        uint32_t all;
+        const uint32_t dbase = block_excl_scan_u32<kScanThreads>((int)t < nd ? so.totals[t] : 0u, all);
+        s_goff[t] = ((int)t < nd ? so.counts[(size_t)t * nb_cap + b] : 0u) + dbase;
+    }
     for (uint32_t k = lane; k < 256u; k += 64u) s_h[wave][k] = 0u;
     // Each wave holds a contiguous run of 64 * ITEMS items of the block, so the
     // block's stable order is (wave, round, lane): every wave ranks its own
@@ -455,23 +414,24 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
     }
 }
 
-// Sorts n (device count, <= cap) pairs by key bits [0, bits), using the
-// arrival counters and tags of passes pass0, pass0 + 1, ...  Returns true
+// Sorts n (device count, <= cap) pairs by key bits [0, bits).  Returns true
 // if the result is in (k1, v1), false if in (k0, v0).
 inline bool radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const int64_t *n_dev, int64_t cap,
-                       int bits, const SortState &so, int pass0, hipStream_t st) {
+                       int bits, const SortState &so, hipStream_t st) {
     const int64_t nb = sort_blocks(cap);
     if (nb == 0 || bits <= 0) return false;
     const bool small = sort_items(cap) == 4;
     bool in1 = false;
-    for (int shift = 0, p = pass0; shift < bits; shift += 8, ++p) {
+    for (int shift = 0; shift < bits; shift += 8) {
         const int dbits = bits - shift < 8 ? bits - shift : 8;
         uint32_t *ki = in1 ? k1 : k0, *vi = in1 ? v1 : v0;
         uint32_t *ko = in1 ? k0 : k1, *vo = in1 ? v0 : v1;
         hipLaunchKernelGGL(small ? k_radix_count<4> : k_radix_count<16>, dim3((unsigned)nb), dim3(kScanThreads), 0,
-                           st, ki, n_dev, cap, shift, dbits, so, p);
+                           st, ki, n_dev, cap, shift, dbits, so, nb);
+        hipLaunchKernelGGL(small ? k_digit_scan<4> : k_digit_scan<16>, dim3(256), dim3(kScanThreads), 0, st, n_dev,
+                           cap, dbits, so, nb);
         hipLaunchKernelGGL(small ? k_radix_scatter<4> : k_radix_scatter<16>, dim3((unsigned)nb), dim3(kScanThreads),
-                           0, st, ki, vi, ko, vo, n_dev, cap, shift, dbits, so);
+                           0, st, ki, vi, ko, vo, n_dev, cap, shift, dbits, so, nb);
         in1 = !in1;
     }
     return in1;
