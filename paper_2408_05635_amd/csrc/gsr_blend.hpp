@@ -232,10 +232,12 @@ __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.0f) - (x 
 // Backward blend.  One workgroup per binning tile, one wave per 8x8 block of
 // it (tiles are at most 16x16, so at most four waves).  The tile's list is
 // walked in reverse, from the last contributor of any pixel of the tile, in
-// segments of kSeg entries; within a segment every wave culls and processes
-// the entries against its own block and sums each entry's partial derivatives
-// over its 64 pixels (DPP quad sums, then a batched column sum in LDS) into
-// its own LDS slots.
+// segments of kSeg entries; within a segment every wave culls the entries
+// against its own block (one lane per entry), then takes the survivors one
+// by one, reading each one's record at a wave-uniform address (scalar loads,
+// no LDS staging), and sums each entry's partial derivatives over its 64
+// pixels (DPP quad sums, then a batched column sum in LDS) into its own LDS
+// slots.
 // At the end of the segment the waves' slots are added in a fixed order and
 // written, without atomics, to the pair's own row of `grad_pairs`: record s
 // owns the rows [poff[s], poff[s] + tiles of s), one per tile of its
@@ -283,8 +285,6 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                                                    const uint32_t *__restrict__ poff, const uint2 *__restrict__ trect,
                                                    const uint2 *__restrict__ ranges, int64_t *__restrict__ counters,
                                                    BlendOut st, LossIn L, float *__restrict__ grad_pairs) {
-    __shared__ float4 s_a[kBwdMaxWaves][kSeg], s_b[kBwdMaxWaves][kSeg], s_c[kBwdMaxWaves][kSeg];
-    __shared__ uint32_t s_pos[kBwdMaxWaves][kSeg];
     // The NV partials of an entry are summed over the wave in two steps: DPP
     // sums over each quad of lanes, stored by the quad's first lane into
     // s_q[wave][batch slot][quad][NV]; once kBatch entries are stored, lane
@@ -434,31 +434,22 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
             const uint32_t hi = wmax < seg_hi ? wmax : seg_hi;
             const uint32_t e = seg_lo + lane;
             bool keep = false;
-            float4 A, B, C;
+            uint32_t s = 0;
             if (lane < (uint32_t)kSeg && e < hi && pair_rec[e] < n_rec) {
-                const uint32_t s = pair_rec[e];
-                A = rec[3 * (size_t)s];
-                B = rec[3 * (size_t)s + 1];
-                C = rec[3 * (size_t)s + 2];
-                keep = block_may_contribute(A, B, (float)bx0, (float)by0);
+                s = pair_rec[e];
+                keep = block_may_contribute(rec[3 * (size_t)s], rec[3 * (size_t)s + 1], (float)bx0, (float)by0);
             }
-            const uint64_t m = ballot(keep);
-            if (keep) {
-                const uint32_t slot = rank_below(m);
-                s_a[wave][slot] = A;
-                s_b[wave][slot] = B;
-                s_c[wave][slot] = C;
-                s_pos[wave][slot] = e;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+            // survivors in reverse list order: the lanes of the set bits of m, highest first;
+            // an entry's record is read at a wave-uniform address (scalar loads)
+            uint64_t mm = ballot(keep);
             uint32_t nb = 0;   // entries stored in the batch (wave-uniform)
-            auto entry = [&](int k) {
-                const uint32_t pos = s_pos[wave][k];
+            auto entry = [&](int src) {
+                const uint32_t pos = seg_lo + (uint32_t)src;
+                const uint32_t rs = __builtin_amdgcn_readlane(s, src);
                 const bool act = pos < last;
                 const uint64_t m_act = ballot(act);
                 if (m_act == 0) return;   // wave-uniform
-                const float4 a = s_a[wave][k], b = s_b[wave][k];
+                const float4 a = rec[3 * (size_t)rs], b = rec[3 * (size_t)rs + 1];
                 // every lane evaluates (the wave pays for it either way); the
                 // decisions and the state updates are selects, not branches
                 const AlphaEval ev = eval_alpha(a, b, fpx, fpy);
@@ -470,7 +461,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                     n_contrib += contrib ? 1u : 0u;
                     ++n_red;
                 }
-                const float4 cc = s_c[wave][k];
+                const float4 cc = rec[3 * (size_t)rs + 2];
                 // A lane that does not take this entry continues with alpha = 0:
                 // every update below then leaves its state exactly as it was
                 // (fma(0, S, W 1) = W) and every partial is zero, so no branch
@@ -515,11 +506,10 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                     nb = 0;
                 }
             };
-            // entries in reverse, in groups of 4 (LDS addresses as immediate offsets)
-            for (int k0 = __popcll(m) - 1; k0 >= 0; k0 -= 4) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (k0 - j >= 0) entry(k0 - j);
+            while (mm != 0) {   // wave-uniform
+                const int src = 63 - __builtin_clzll(mm);
+                mm &= ~(1ull << src);
+                entry(src);
             }
             if (nb != 0) flush(nb);
         }
