@@ -274,7 +274,7 @@ __device__ __forceinline__ void quad_sums(float (&d)[NV]) {
 }
 
 constexpr int kBwdMaxWaves = 4;
-constexpr int kSeg = 32;   // list entries per segment
+constexpr int kSeg = 48;   // list entries per segment
 
 // NV = 10: all partials per entry (dL/d of the conic factors and mean, opacity,
 // colour, depth).  NV = 6 (pose only): the opacity and colour partials do not
