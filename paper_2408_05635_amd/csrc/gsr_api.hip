@@ -693,8 +693,10 @@ __global__ __launch_bounds__(256) void k_pose_final(const float *__restrict__ pq
     const int v = blockIdx.x, t = threadIdx.x;
     double acc[12];
     for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+#pragma unroll 4   // loads in flight together; the additions keep their order
     for (int b = t; b < nblocks; b += 256) {
         const double *row = pose_blocks + ((size_t)b * V + v) * 12;
+#pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] += row[k];
     }
     for (int k = 0; k < 12; ++k) s_red[k][t] = acc[k];

@@ -543,6 +543,7 @@ __global__ __launch_bounds__(256) void k_loss_final(const ViewTable *__restrict_
     const ViewInfo &V = vt->v[blockIdx.x];
     const int n = V.tiles_x * V.tiles_y;
     double t = 0.0;
+#pragma unroll 8   // loads in flight together; the additions keep their order
     for (int k = threadIdx.x; k < n; k += 256) t += loss_tile[V.tile_off + k];
     s[threadIdx.x] = t;
     __syncthreads();
