@@ -110,6 +110,7 @@ struct Proj {
 // rotation and world covariance (the same FP64 operations whichever view).
 struct GaussPre {
     double o;
+    double qmax;   // 2 ln(255 o): the alpha >= 1/255 level of the exponent (used when 255 o > 1)
     double s2[3];
     double Rg[9];
     double Sig[9];
@@ -118,6 +119,7 @@ struct GaussPre {
 template <bool ISO>
 __device__ __forceinline__ void prep_gauss(const GaussIn &p, GaussPre &g) {
     g.o = 1.0 / (1.0 + exp(-p.logit));
+    g.qmax = 2.0 * log(255.0 * g.o);
     if constexpr (ISO) {
         g.s2[0] = g.s2[1] = g.s2[2] = exp(2.0 * p.ls[0]);
     } else {
@@ -193,7 +195,7 @@ __device__ __forceinline__ void project_pre(const GaussIn &p, const GaussPre &g,
     // Binning radius: a circle holding the whole alpha >= 1/255 ellipse
     // (d^T Sigma'^-1 d <= 2 ln(255 o)), widened by 2^-10 relatively and
     // absolutely so that FP32 rounding never clips a contributing pixel.
-    const double qmax = 2.0 * log(255.0 * r.o);
+    const double qmax = g.qmax;
     const double mid = 0.5 * (r.a + r.c);
     const double lmax = mid + sqrt(fmax(mid * mid - r.det, 0.0));
     r.radius = (float)((1.0 + 0x1p-10) * sqrt(qmax * lmax) + 0x1p-10);
