@@ -439,7 +439,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                 s = pair_rec[e];
                 keep = block_may_contribute(rec[3 * (size_t)s], rec[3 * (size_t)s + 1], (float)bx0, (float)by0);
             }
-            // survivors in reverse list order: the lanes of the set bits of m, highest first;
+            // survivors in reverse list order: the lanes of the set bits of mm, highest first;
             // an entry's record is read at a wave-uniform address (scalar loads)
             uint64_t mm = ballot(keep);
             uint32_t nb = 0;   // entries stored in the batch (wave-uniform)
