@@ -590,16 +590,6 @@ __global__ __launch_bounds__(256) void k_record_bwd(ProjParams pp, const ViewTab
                 if ((int)lane == src) r2[c] = t;
             }
         }
-        float g2[10];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) g2[c] = r2[c];
-        if constexpr (NV == 10) {
-#pragma unroll
-            for (int c = 5; c < 10; ++c) g2[c] = r2[c];
-        } else {
-            g2[5] = g2[6] = g2[7] = g2[8] = 0.0f;
-            g2[9] = r2[5];
-        }
         if (!valid) continue;
         const uint32_t gid = gid_sorted[s];
         const int v = (int)(gid / (uint64_t)pp.n);
@@ -608,6 +598,21 @@ __global__ __launch_bounds__(256) void k_record_bwd(ProjParams pp, const ViewTab
         const GaussIn p = load_gauss<ISO>(pp.g, i);
         Proj r;
         project<true, ISO>(p, poses[v], vt->v[v], pp.z_near, pp.blur, r);
+        // the rows carry the conic-factor and mean partials without their
+        // per-record factors k = 2 o ln2 and (l11, l21, l22)
+        const double k2 = 2.0 * kLn2 * r.o;
+        float g2[10];
+        g2[0] = (float)(k2 * r.l11 * (double)r2[0]);
+        g2[1] = (float)(k2 * (r.l21 * (double)r2[0] + r.l22 * (double)r2[1]));
+#pragma unroll
+        for (int c = 2; c < 5; ++c) g2[c] = (float)(k2 * (double)r2[c]);
+        if constexpr (NV == 10) {
+#pragma unroll
+            for (int c = 5; c < 10; ++c) g2[c] = r2[c];
+        } else {
+            g2[5] = g2[6] = g2[7] = g2[8] = 0.0f;
+            g2[9] = r2[5];
+        }
         ParamGrad pg;
         for (int k = 0; k < 3; ++k) pg.mu[k] = pg.ls[k] = pg.rgb[k] = 0.0;
         for (int k = 0; k < 4; ++k) pg.q[k] = 0.0;

@@ -255,6 +255,12 @@ __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.0f) - (x 
 //   dL/do = dL/dalpha G,  dL/dp2 = dL/dalpha alpha ln2   (unless clamped)
 //   dL/dmx = dL/dp2 2u l11,  dL/dmy = dL/dp2 2(u l21 + w l22)
 //   dL/dl11 = -dL/dp2 2u dx, dL/dl21 = -dL/dp2 2u dy, dL/dl22 = -dL/dp2 2w dy
+// With 2 dL/dp2 = k dL/do, k = 2 o ln2, and (k, l11, l21, l22) fixed per entry,
+// a pair's row holds R = (sum u dL/do, sum w dL/do, -sum u dx dL/do,
+// -sum u dy dL/do, -sum w dy dL/do, sum dL/do, sum dL/df_ch) over the tile's
+// pixels, and the record's backward applies the factors to the summed rows:
+// dL/dmx = k l11 R0, dL/dmy = k (l21 R0 + l22 R1), dL/dl.. = k R2..R4.
+// Pose-only rows (NV = 6) hold R0..R4 and the depth partial.
 // Sums of each value over every quad of lanes (4 neighbouring pixels of a
 // row), the NV chains interleaved; afterwards every lane of a quad holds the
 // quad's sums.  Contraction is off so that each stage stays one DPP add (fused
@@ -472,29 +478,40 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                 const float S = g[0] * cc.x + g[1] * cc.y + g[2] * cc.z + g[3] * cc.w + g[4];
                 const float dal = Tk * (S - W);
                 // unclamped: alpha = o G, so dL/do = dL/dalpha G and
-                // 2 dL/dp2 = dL/dalpha alpha 2 ln2 = dL/do (2 o ln2)
+                // 2 dL/dp2 = dL/dalpha alpha 2 ln2 = dL/do (2 o ln2); the
+                // entry's constant factors (2 o ln2, l11, l21, l22) are applied
+                // to the row sums, once per record
                 const float dop = dal * ((contrib && !ev.clamped) ? ev.G : 0.0f);
-                const float dq2 = dop * (b.w * (2.0f * kLn2f));
-                const float tu = ev.u * dq2, tw = ev.w * dq2;
+                const float tu = ev.u * dop, tw = ev.w * dop;
                 const float wc = ae * Tk;
-                float d[NV];
-                d[0] = tu * b.x;
-                d[1] = tu * b.y + tw * b.z;
-                d[2] = -tu * ev.dx;
-                d[3] = -tu * ev.dy;
-                d[4] = -tw * ev.dy;
+                // quad sums of (u, w, -u dx) dL/do, dL/do and the colour
+                // partials; the four lanes of a quad share their row, hence dy,
+                // so -u dy dL/do and -w dy dL/do follow from the sums
+                constexpr int NQ = NV - 2;
+                float q[NQ];
+                q[0] = tu;
+                q[1] = tw;
+                q[2] = -tu * ev.dx;
                 if constexpr (NV == 10) {
-                    d[5] = dop;
-                    d[6] = g[0] * wc;
-                    d[7] = g[1] * wc;
-                    d[8] = g[2] * wc;
-                    d[9] = g[3] * wc;
+                    q[3] = dop;
+                    q[4] = g[0] * wc;
+                    q[5] = g[1] * wc;
+                    q[6] = g[2] * wc;
+                    q[7] = g[3] * wc;
                 } else {
-                    d[5] = g[3] * wc;
+                    q[3] = g[3] * wc;
                 }
                 W = __builtin_fmaf(ae, S, W * oma);
                 T = contrib ? Tk : T;
-                quad_sums<NV>(d);
+                quad_sums<NQ>(q);
+                float d[NV];
+                d[0] = q[0];
+                d[1] = q[1];
+                d[2] = q[2];
+                d[3] = -ev.dy * q[0];
+                d[4] = -ev.dy * q[1];
+#pragma unroll
+                for (int c = 5; c < NV; ++c) d[c] = q[c - 2];
                 if ((lane & 3u) == 0u) {
                     float2 *dst = reinterpret_cast<float2 *>(&s_q[wave][(nb * 16 + (lane >> 2)) * NV]);
 #pragma unroll
