@@ -510,7 +510,7 @@ struct GradOut {
 // parameters (written per record, 14 floats) and to the view's pose partials
 // (G_W and g_t, 12 values), which are summed per view in FP64: in LDS over
 // the block, then written as one row per block (no global atomics) for
-// k_pose_final to add in a fixed order.
+// the pose finalisation to add in a fixed order.
 //
 // Load balance: records are depth-sorted, so the nearest ones, which can
 // cover every tile of the image, are neighbours.  Lane l of wave slot w takes
@@ -642,13 +642,13 @@ __global__ __launch_bounds__(256) void k_record_bwd(ProjParams pp, const ViewTab
 // Per Gaussian: its gradient is the sum of its records' contributions over
 // the views, in view order (deterministic).  The loads of four views are in
 // flight together.
-__global__ __launch_bounds__(256) void k_gauss_sum(ProjParams pp, const ViewTable *__restrict__ vt,
-                                                   const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ inv,
-                                                   const float *__restrict__ rgrad, GradOut go,
-                                                   const int64_t *__restrict__ counters) {
+__device__ __forceinline__ void gauss_sum_block(const ProjParams &pp, const ViewTable *__restrict__ vt,
+                                                const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ inv,
+                                                const float *__restrict__ rgrad, const GradOut &go,
+                                                const int64_t *__restrict__ counters, int64_t blk) {
     const int V = vt->n_views;
     const uint32_t n_rec = (uint32_t)counters[kCntVisible];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = blk * blockDim.x + threadIdx.x;
     if (i >= pp.n) return;
     float acc[kRecGrad];
     for (int k = 0; k < kRecGrad; ++k) acc[k] = 0.0f;
@@ -691,11 +691,11 @@ __global__ __launch_bounds__(256) void k_gauss_sum(ProjParams pp, const ViewTabl
 // Per view (one block each): the pose partials (G_W, g_t) summed over the
 // record blocks' rows in a fixed order (deterministic), then
 // (G_W, g_t) -> dL/dq | t, dL/dt, dL/dq | C, dL/dC with C = -W^T t.
-__global__ __launch_bounds__(256) void k_pose_final(const float *__restrict__ pq, const float *__restrict__ pt,
-                                                    const PoseF64 *poses, const double *__restrict__ pose_blocks,
-                                                    int nblocks, int V, gsr_pose_grads pg) {
+__device__ __forceinline__ void pose_final_view(const float *__restrict__ pq, const float *__restrict__ pt,
+                                                const PoseF64 *poses, const double *__restrict__ pose_blocks,
+                                                int nblocks, int V, const gsr_pose_grads &pg, int v) {
     __shared__ double s_red[12][256];
-    const int v = blockIdx.x, t = threadIdx.x;
+    const int t = threadIdx.x;
     double acc[12];
     for (int k = 0; k < 12; ++k) acc[k] = 0.0;
 #pragma unroll 4   // loads in flight together; the additions keep their order
@@ -736,6 +736,42 @@ __global__ __launch_bounds__(256) void k_pose_final(const float *__restrict__ pq
     rot_grad_to_quat_f64(q, G2, gq);
     if (pg.dq_c)
         for (int k = 0; k < 4; ++k) pg.dq_c[4 * v + k] = (float)gq[k];
+}
+
+// The last step of a backward, one launch: blocks [0, n_pose) finish the
+// views' pose gradients, the next n_loss blocks the views' losses, the rest
+// sum the Gaussians' gradients.  The three are independent (each reads what
+// earlier kernels wrote), so their latencies overlap.
+struct FinalArgs {
+    int n_pose, n_loss;
+    const float *pq, *pt;   // pose inputs
+    const PoseF64 *poses;
+    const double *pose_blocks;
+    int pose_rows, V;
+    gsr_pose_grads pg;
+    const ViewTable *vt;   // loss
+    const double *loss_tile;
+    double *loss;
+    ProjParams pp;   // Gaussian sums
+    const uint32_t *cnt, *inv;
+    const float *rgrad;
+    GradOut go;
+    const int64_t *counters;
+};
+
+__global__ __launch_bounds__(256) void k_finalize(FinalArgs a) {
+    int b = (int)blockIdx.x;
+    if (b < a.n_pose) {
+        pose_final_view(a.pq, a.pt, a.poses, a.pose_blocks, a.pose_rows, a.V, a.pg, b);
+        return;
+    }
+    b -= a.n_pose;
+    if (b < a.n_loss) {
+        loss_final_view(a.vt, a.loss_tile, a.loss, b);
+        return;
+    }
+    b -= a.n_loss;
+    gauss_sum_block(a.pp, a.vt, a.cnt, a.inv, a.rgrad, a.go, a.counters, b);
 }
 
 // Binning test hook: record fields in depth order.
@@ -956,11 +992,8 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
                                counters, bo, li, gpairs);
         }
     }
-    if (fused) {
-        if (L.kcap == 0)   // no blend ran: every tile's partial is zero
-            hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(L.T, 256)), dim3(256), 0, st, li.loss_tile, L.T);
-        hipLaunchKernelGGL(k_loss_final, dim3(views->n_views), dim3(256), 0, st, vt, li.loss_tile, li.loss);
-    }
+    if (fused && L.kcap == 0)   // no blend ran: every tile's partial is zero
+        hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(L.T, 256)), dim3(256), 0, st, li.loss_tile, L.T);
     StageTimer timer(c.ctx, kStageProjectBwd, st);
     const unsigned rec_blocks = std::min<unsigned>(grid_for(L.vn, 256, 1ll << 30), kRecBwdMaxBlocks);
     double *pose_blocks = at<double>(c.ws, L.poseblk);
@@ -972,17 +1005,32 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
                            depth_sorted_gid(c), at<uint32_t>(c.ws, L.poff), at<uint32_t>(c.ws, L.cnt_s), gpairs,
                            (const int64_t *)counters, at<float>(c.ws, L.rgrad), pose_blocks, go.want_gauss,
                            go.want_pose);
-    if (c.pp.n > 0 && go.want_gauss)
-        hipLaunchKernelGGL(k_gauss_sum, dim3(grid_for(c.pp.n, 256, 1ll << 30)), dim3(256), 0, st, c.pp, vt,
-                           at<uint32_t>(c.ws, L.cnt), at<uint32_t>(c.ws, L.inv), at<float>(c.ws, L.rgrad), go,
-                           (const int64_t *)counters);
-    if (go.want_pose) {
-        if (c.pp.n == 0)   // no record blocks ran: their rows are zero
-            hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((int64_t)rec_blocks * 12 * views->n_views, 256)), dim3(256),
-                               0, st, pose_blocks, (int64_t)rec_blocks * 12 * views->n_views);
-        hipLaunchKernelGGL(k_pose_final, dim3(views->n_views), dim3(256), 0, st, views->quat, views->trans,
-                           at<PoseF64>(c.ws, L.poses), pose_blocks, (int)rec_blocks, views->n_views, *pg);
-    }
+    if (go.want_pose && c.pp.n == 0)   // no record blocks ran: their rows are zero
+        hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((int64_t)rec_blocks * 12 * views->n_views, 256)), dim3(256), 0,
+                           st, pose_blocks, (int64_t)rec_blocks * 12 * views->n_views);
+    FinalArgs fa;
+    memset(&fa, 0, sizeof(fa));
+    fa.n_pose = go.want_pose ? views->n_views : 0;
+    fa.n_loss = fused ? views->n_views : 0;
+    const int64_t n_gauss_blocks = (c.pp.n > 0 && go.want_gauss) ? grid_for(c.pp.n, 256, 1ll << 30) : 0;
+    fa.pq = views->quat;
+    fa.pt = views->trans;
+    fa.poses = at<PoseF64>(c.ws, L.poses);
+    fa.pose_blocks = pose_blocks;
+    fa.pose_rows = (int)rec_blocks;
+    fa.V = views->n_views;
+    if (pg) fa.pg = *pg;
+    fa.vt = vt;
+    fa.loss_tile = li.loss_tile;
+    fa.loss = li.loss;
+    fa.pp = c.pp;
+    fa.cnt = at<uint32_t>(c.ws, L.cnt);
+    fa.inv = at<uint32_t>(c.ws, L.inv);
+    fa.rgrad = at<float>(c.ws, L.rgrad);
+    fa.go = go;
+    fa.counters = counters;
+    const int64_t n_final = fa.n_pose + fa.n_loss + n_gauss_blocks;
+    if (n_final > 0) hipLaunchKernelGGL(k_finalize, dim3((unsigned)n_final), dim3(256), 0, st, fa);
     // with the Gaussian gradients off, or for N = 0, the outputs are still defined (zero)
     if (gg && !go.want_gauss && c.pp.n > 0) {
         float *ptrs[5] = {gg->means, gg->quats, gg->log_scales, gg->opacity_logits, gg->rgb};

@@ -157,6 +157,9 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
         }
         __syncthreads();
         const int n = __popcll(m);
+        // staging slot of this lane's last contributor within the chunk (-1:
+        // none yet); turned into the list position once the chunk is done
+        int lastk = -1;
         // Every lane evaluates; a lane that is done, or that the entry does
         // not reach, takes weight 0, which leaves its sums exactly as they
         // were (fma(0, c, x) = x), so the updates need no branches.
@@ -169,8 +172,6 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
             const bool take = hit != stop;   // hit and not stopped
             if (COUNT) n_contrib += take ? 1u : 0u;
             const float4 cc = s_c[k];
-            uint32_t pos1 = s_pos[k] + 1u;
-            asm volatile("" : "+v"(pos1));   // read for every lane: no branch around the read
             const float wgt = take ? ev.alpha * T : 0.0f;
             c0 = __builtin_fmaf(wgt, cc.x, c0);
             c1 = __builtin_fmaf(wgt, cc.y, c1);
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
             cd = __builtin_fmaf(wgt, cc.w, cd);
             cs += wgt;
             T = take ? Tn : T;
-            last = take ? pos1 : last;
+            lastk = take ? k : lastk;
             if (HASH) {
                 uint32_t rid2 = 2u * s_rec_id[k] + (ev.clamped ? 1u : 0u);
                 asm volatile("" : "+v"(rid2));
@@ -195,6 +196,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
                 if (k0 + j < n) entry(k0 + j);
             if (ballot(!done) == 0) break;
         }
+        if (lastk >= 0) last = s_pos[lastk] + 1u;
         __syncthreads();
     }
     if (COUNT) {
@@ -223,7 +225,7 @@ struct LossIn {
     const float *t_rgb, *t_depth, *t_sil, *t_prior, *t_weight;
     float w_rgb, w_depth, w_sil, w_prior, sil_thresh;
     const float *g_rgb, *g_depth, *g_sil;   // upstream dL/dimage (split backward)
-    double *loss;                           // [V] per-view loss (fused; written by k_loss_final)
+    double *loss;                           // [V] per-view loss (fused; written by loss_final_view)
     double *loss_tile;                      // [tiles] per-tile loss partials (fused, workspace)
 };
 
@@ -475,7 +477,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                 const float ae = contrib ? ev.alpha : 0.0f;
                 const float oma = 1.0f - ae;
                 const float Tk = T * __builtin_amdgcn_rcpf(oma);   // transmittance in front of this entry
-                const float S = g[0] * cc.x + g[1] * cc.y + g[2] * cc.z + g[3] * cc.w + g[4];
+                const float S = __builtin_fmaf(g[0], cc.x, __builtin_fmaf(g[1], cc.y, __builtin_fmaf(g[2], cc.z, __builtin_fmaf(g[3], cc.w, g[4]))));
                 const float dal = Tk * (S - W);
                 // unclamped: alpha = o G, so dL/do = dL/dalpha G and
                 // 2 dL/dp2 = dL/dalpha alpha 2 ln2 = dL/do (2 o ln2); the
@@ -553,11 +555,12 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
     }
 }
 
-// Per-view loss: the view's tile partials added in a fixed tree order.
-__global__ __launch_bounds__(256) void k_loss_final(const ViewTable *__restrict__ vt,
-                                                    const double *__restrict__ loss_tile, double *__restrict__ loss) {
+// Per-view loss: the view's tile partials added in a fixed tree order (one
+// 256-thread block per view).
+__device__ __forceinline__ void loss_final_view(const ViewTable *__restrict__ vt, const double *__restrict__ loss_tile,
+                                                double *__restrict__ loss, int view) {
     __shared__ double s[256];
-    const ViewInfo &V = vt->v[blockIdx.x];
+    const ViewInfo &V = vt->v[view];
     const int n = V.tiles_x * V.tiles_y;
     double t = 0.0;
 #pragma unroll 8   // loads in flight together; the additions keep their order
@@ -568,7 +571,7 @@ __global__ __launch_bounds__(256) void k_loss_final(const ViewTable *__restrict_
         if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) loss[blockIdx.x] = s[0];
+    if (threadIdx.x == 0) loss[view] = s[0];
 }
 
 }  // namespace gsr
