@@ -292,31 +292,6 @@ T *at(const gsr_workspace &ws, size_t off) {
 // kernels
 // ---------------------------------------------------------------------------
 
-// Call setup: view table, FP64 poses, zero counters (block 0), and a cleared
-// synchronisation region (all blocks).
-__global__ void k_setup(ViewTable tab, ViewTable *vt, const float *__restrict__ pq, const float *__restrict__ pt,
-                        PoseF64 *poses, int64_t *counters, uint4 *sync, int64_t sync16, uint2 *ranges,
-                        int64_t n_tiles, bool keep_sticky) {
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < sync16; k += (int64_t)gridDim.x * blockDim.x)
-        sync[k] = make_uint4(0u, 0u, 0u, 0u);
-    // every tile's range starts empty; k_ranges sets those of the tiles with pairs
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_tiles; k += (int64_t)gridDim.x * blockDim.x)
-        ranges[k] = make_uint2(0u, 0u);
-    if (blockIdx.x != 0) return;
-    const int t = threadIdx.x;
-    const int words = (int)(sizeof(ViewTable) / 4);
-    const int32_t *src = reinterpret_cast<const int32_t *>(&tab);
-    int32_t *dst = reinterpret_cast<int32_t *>(vt);
-    for (int k = t; k < words; k += blockDim.x) dst[k] = src[k];
-    if (t < kNumCounters && !(keep_sticky && t == kCntOverflowAny)) counters[t] = 0;
-    if (t < tab.n_views) {
-        PoseF64 p;
-        quat_to_rot_f64(pq[4 * t], pq[4 * t + 1], pq[4 * t + 2], pq[4 * t + 3], p.W);
-        for (int k = 0; k < 3; ++k) p.t[k] = (double)pt[3 * t + k];
-        poses[t] = p;
-    }
-}
-
 struct ProjParams {
     gsr_gaussians g;
     int64_t n;
@@ -333,24 +308,52 @@ __device__ __forceinline__ uint32_t tiles_of(const Proj &r, const ViewTable *vt,
     return (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
 }
 
-// per Gaussian i, per view v: tiles touched (0 = not visible) and depth key
+// The call's first kernel.  Set-up: the view table and the FP64 poses are
+// written for the later kernels, the counters zeroed (block 0), the
+// synchronisation region and every tile's range cleared (all blocks); each
+// block also forms the poses in LDS for itself.  Then per Gaussian i, per view
+// v: tiles touched (0 = not visible) and the depth key.
 template <bool ISO>
-__global__ __launch_bounds__(256) void k_project_count(ProjParams pp, const ViewTable *__restrict__ vt,
-                                                       const PoseF64 *__restrict__ poses, uint32_t *__restrict__ cnt,
-                                                       uint32_t *__restrict__ zkey) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_setup_project(ViewTable tab, ViewTable *vt, const float *__restrict__ pq,
+                                                       const float *__restrict__ pt, PoseF64 *poses,
+                                                       int64_t *counters, uint4 *sync, int64_t sync16, uint2 *ranges,
+                                                       int64_t n_tiles, bool keep_sticky, ProjParams pp,
+                                                       uint32_t *__restrict__ cnt, uint32_t *__restrict__ zkey) {
+    __shared__ PoseF64 s_pose[GSR_MAX_VIEWS];
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = gtid; k < sync16; k += gstride) sync[k] = make_uint4(0u, 0u, 0u, 0u);
+    // every tile's range starts empty; k_ranges sets those of the tiles with pairs
+    for (int64_t k = gtid; k < n_tiles; k += gstride) ranges[k] = make_uint2(0u, 0u);
+    const int t = threadIdx.x;
+    if (blockIdx.x == 0) {
+        const int words = (int)(sizeof(ViewTable) / 4);
+        const int32_t *src = reinterpret_cast<const int32_t *>(&tab);
+        int32_t *dst = reinterpret_cast<int32_t *>(vt);
+        for (int k = t; k < words; k += blockDim.x) dst[k] = src[k];
+        if (t < kNumCounters && !(keep_sticky && t == kCntOverflowAny)) counters[t] = 0;
+    }
+    const int V = tab.n_views;
+    if (t < V) {
+        PoseF64 p;
+        quat_to_rot_f64(pq[4 * t], pq[4 * t + 1], pq[4 * t + 2], pq[4 * t + 3], p.W);
+        for (int k = 0; k < 3; ++k) p.t[k] = (double)pt[3 * t + k];
+        s_pose[t] = p;
+        if (blockIdx.x == 0) poses[t] = p;
+    }
+    __syncthreads();
+    const int64_t i = gtid;
     if (i >= pp.n) return;
     const GaussIn p = load_gauss<ISO>(pp.g, i);
     GaussPre pre;   // once for all views
     prep_gauss<ISO>(p, pre);
-    const int V = vt->n_views;
     for (int v = 0; v < V; ++v) {
         Proj r;
-        project_pre<false, ISO>(p, pre, poses[v], vt->v[v], pp.z_near, pp.blur, r);
+        project_pre<false, ISO>(p, pre, s_pose[v], tab.v[v], pp.z_near, pp.blur, r);
         uint32_t c = 0;
         if (r.visible) {
             uint32_t a, b;
-            c = tiles_of(r, vt, vt->v[v], a, b);
+            c = tiles_of(r, &tab, tab.v[v], a, b);
         }
         cnt[(int64_t)v * pp.n + i] = c;
         zkey[(int64_t)v * pp.n + i] = __float_as_uint(r.z32);
@@ -487,7 +490,7 @@ __global__ void k_fill_f64(double *p, int64_t n) {
 
 // [start, end) of every tile with pairs, from the sorted keys: a pair whose
 // key differs from its predecessor's starts its tile's run, one whose key
-// differs from its successor's ends it.  k_setup gave every tile an empty
+// differs from its successor's ends it.  the set-up gave every tile an empty
 // range beforehand.
 __global__ void k_ranges(const uint32_t *__restrict__ keys, const int64_t *__restrict__ counters,
                          uint2 *__restrict__ ranges, int64_t n_tiles) {
@@ -893,13 +896,14 @@ void enqueue_binning(Call &c, const gsr_views *views) {
                  counters + kCntSyncError};
     SortState so{at<uint32_t>(ws, L.scounts), at<uint32_t>(ws, L.stotals)};
     const int64_t sync16 = (int64_t)(L.sync_bytes / 16);
-    hipLaunchKernelGGL(k_setup, dim3((unsigned)std::min<int64_t>(std::max<int64_t>((sync16 + 255) / 256, 1), 1024)),
-                       dim3(256), 0, st, c.tab, vt, views->quat, views->trans, poses, counters,
-                       reinterpret_cast<uint4 *>(sync), sync16, at<uint2>(ws, L.ranges), L.T, c.keep_sticky);
-    if (L.vn > 0) {
-        hipLaunchKernelGGL(c.pp.iso ? k_project_count<true> : k_project_count<false>,
-                           dim3(grid_for(c.pp.n, 256, 1ll << 30)), dim3(256), 0, st, c.pp, vt,
-                           poses, cnt, zkey);
+    {
+        // one thread per Gaussian (none for an empty call: the set-up still runs)
+        const unsigned grid = L.vn > 0 ? grid_for(c.pp.n, 256, 1ll << 30) : 1u;
+        ProjParams pp = c.pp;
+        if (L.vn == 0) pp.n = 0;
+        hipLaunchKernelGGL(c.pp.iso ? k_setup_project<true> : k_setup_project<false>, dim3(grid), dim3(256), 0, st,
+                           c.tab, vt, views->quat, views->trans, poses, counters, reinterpret_cast<uint4 *>(sync),
+                           sync16, at<uint2>(ws, L.ranges), L.T, c.keep_sticky, pp, cnt, zkey);
     }
     // compaction of the visible (view, Gaussian) records, index order kept
     scan_exclusive(VisSrc{cnt}, VisSink{zkey, dk0, dv0}, nullptr, L.vn, ss, kIdVisible,
