@@ -98,7 +98,7 @@ constexpr int kEmitChunk = 1024;         // pairs per emission block
 // scans' look-back words
 constexpr size_t kSyncTickets = 256;
 // ids of the binning's scans
-enum SyncId : uint32_t { kIdVisible = 0, kIdOffsets = 1 };
+enum SyncId : uint32_t { kIdOffsets = 1 };
 
 struct Layout {
     int64_t vn;           // V * N
@@ -359,21 +359,6 @@ __global__ __launch_bounds__(256) void k_setup_project(ViewTable tab, ViewTable 
         zkey[(int64_t)v * pp.n + i] = __float_as_uint(r.z32);
     }
 }
-
-struct VisSrc {
-    const uint32_t *cnt;
-    __device__ uint32_t operator()(int64_t i) const { return cnt[i] != 0u ? 1u : 0u; }
-};
-struct VisSink {
-    const uint32_t *zkey;
-    uint32_t *keys, *vals;
-    __device__ void operator()(int64_t i, uint32_t pos, uint32_t v) const {
-        if (v) {
-            keys[pos] = zkey[i];
-            vals[pos] = (uint32_t)i;
-        }
-    }
-};
 
 // per visible record s (depth order): full projection -> record, tile rect
 template <bool ISO>
@@ -905,13 +890,11 @@ void enqueue_binning(Call &c, const gsr_views *views) {
                            c.tab, vt, views->quat, views->trans, poses, counters, reinterpret_cast<uint4 *>(sync),
                            sync16, at<uint2>(ws, L.ranges), L.T, c.keep_sticky, pp, cnt, zkey);
     }
-    // compaction of the visible (view, Gaussian) records, index order kept
-    scan_exclusive(VisSrc{cnt}, VisSink{zkey, dk0, dv0}, nullptr, L.vn, ss, kIdVisible,
-                   TotalTo{counters + kCntVisible}, st);
-    // depth order: stable sort on the float32 depth bits (positive floats sort as integers)
-    const bool d_in1 =
-        radix_sort(dk0, dv0, dk1, dv1, counters + kCntVisible, L.vn, 32, so, st);
-    const uint32_t *gid_sorted = d_in1 ? dv1 : dv0;
+    // the visible (view, Gaussian) records in depth order: stable sort on the
+    // float32 depth bits (positive floats sort as integers), whose first pass
+    // also compacts them (index order kept) and counts them
+    radix_sort_visible(cnt, zkey, L.vn, dk0, dv0, dk1, dv1, counters + kCntVisible, so, st);
+    const uint32_t *gid_sorted = dv0;
     float4 *rec = at<float4>(ws, L.rec);
     uint2 *trect = at<uint2>(ws, L.trect);
     uint32_t *cnt_s = at<uint32_t>(ws, L.cnt_s), *inv = at<uint32_t>(ws, L.inv);
@@ -945,8 +928,7 @@ const uint32_t *pair_values(const Call &c) {
 }
 
 const uint32_t *depth_sorted_gid(const Call &c) {
-    const bool in1 = false;   // 4 passes over 32 bits: the result is back in the first buffer
-    return at<uint32_t>(c.ws, in1 ? c.L.dv1 : c.L.dv0);
+    return at<uint32_t>(c.ws, c.L.dv0);   // where the depth sort leaves its result
 }
 
 void enqueue_blend_fwd(Call &c, gsr_images out) {

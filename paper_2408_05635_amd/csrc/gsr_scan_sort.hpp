@@ -240,6 +240,29 @@ struct SortState {
     uint32_t *totals;   // [256] digit totals of the current pass
 };
 
+// Inputs of a sort pass.  PairIn: items [0, n) of (key, value) arrays.
+// VisIn (the first pass of the depth sort): item i of [0, n) takes part only
+// if cnt[i] != 0 (a visible record), with key zkey[i] and value i, so the pass
+// also compacts the visible records, in index order within a digit.
+struct PairIn {
+    const uint32_t *k, *v;
+    __device__ __forceinline__ bool load(int64_t i, int64_t n, uint32_t &key, uint32_t &val) const {
+        if (i >= n) return false;
+        key = k[i];
+        val = v[i];
+        return true;
+    }
+};
+struct VisIn {
+    const uint32_t *cnt, *zkey;
+    __device__ __forceinline__ bool load(int64_t i, int64_t n, uint32_t &key, uint32_t &val) const {
+        if (i >= n || cnt[i] == 0u) return false;
+        key = zkey[i];
+        val = (uint32_t)i;
+        return true;
+    }
+};
+
 // Lanes of the wave holding the same digit as this lane (among `valid` lanes).
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, int dbits, uint64_t valid) {
     uint64_t peers = valid;
@@ -251,10 +274,9 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, int dbits, uint64_t 
     return peers;
 }
 
-template <int ITEMS>
-__global__ __launch_bounds__(kScanThreads) void k_radix_count(const uint32_t *__restrict__ kin, const int64_t *n_dev,
-                                                              int64_t n_host, int shift, int dbits, SortState so,
-                                                              int64_t nb_cap) {
+template <int ITEMS, class In>
+__global__ __launch_bounds__(kScanThreads) void k_radix_count(In in, const int64_t *n_dev, int64_t n_host, int shift,
+                                                              int dbits, SortState so, int64_t nb_cap) {
     __shared__ uint32_t s_cnt[256];
     const uint32_t t = threadIdx.x;
     const int64_t n = dev_count(n_dev, n_host);
@@ -266,14 +288,16 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_count(const uint32_t *__
     __syncthreads();
     const int64_t base = b * (kScanThreads * ITEMS);
     uint32_t key[ITEMS];   // all loads in flight at once
+    bool ok[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        const int64_t i = base + (int64_t)j * kScanThreads + t;
-        key[j] = i < n ? kin[i] : 0u;
+        uint32_t val;
+        key[j] = 0u;
+        ok[j] = in.load(base + (int64_t)j * kScanThreads + t, n, key[j], val);
     }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        const bool valid = base + (int64_t)j * kScanThreads + t < n;
+        const bool valid = ok[j];
         const uint32_t d = (key[j] >> shift) & mask;
         const uint64_t peers = match_digit(d, dbits, ballot(valid));
         if (valid && rank_below(peers) == 0) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
@@ -283,10 +307,11 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_count(const uint32_t *__
 }
 
 // One block per digit: exclusive offsets of the digit over the blocks (in
-// block order) and the digit's total.
+// block order) and the digit's total; with total_out (zero beforehand), the
+// sum of the totals, i.e. the number of items that took part.
 template <int ITEMS>
 __global__ __launch_bounds__(kScanThreads) void k_digit_scan(const int64_t *n_dev, int64_t n_host, int dbits,
-                                                             SortState so, int64_t nb_cap) {
+                                                             SortState so, int64_t nb_cap, int64_t *total_out) {
     const int d = blockIdx.x;
     const int64_t n = dev_count(n_dev, n_host);
     int64_t nb = (n + (kScanThreads * ITEMS) - 1) / (kScanThreads * ITEMS);
@@ -308,7 +333,10 @@ __global__ __launch_bounds__(kScanThreads) void k_digit_scan(const int64_t *n_de
         row[q] = run;
         run += c;
     }
-    if (threadIdx.x == 0) so.totals[d] = all;
+    if (threadIdx.x == 0) {
+        so.totals[d] = all;
+        if (total_out) atomicAdd((unsigned long long *)total_out, (unsigned long long)all);   // integer: any order
+    }
 }
 
 // Stable scatter: items keep their input order within a digit.  The block
@@ -316,12 +344,11 @@ __global__ __launch_bounds__(kScanThreads) void k_digit_scan(const int64_t *n_de
 // run, in input order), then places them in LDS in digit order and writes
 // each digit's run to consecutive global positions, so that the stores are
 // coalesced runs instead of one transaction per item.
-template <int ITEMS>
-__global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *__restrict__ kin,
-                                                                const uint32_t *__restrict__ vin,
-                                                                uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
-                                                                const int64_t *n_dev, int64_t n_host, int shift,
-                                                                int dbits, SortState so, int64_t nb_cap) {
+template <int ITEMS, class In>
+__global__ __launch_bounds__(kScanThreads) void k_radix_scatter(In in, uint32_t *__restrict__ kout,
+                                                                uint32_t *__restrict__ vout, const int64_t *n_dev,
+                                                                int64_t n_host, int shift, int dbits, SortState so,
+                                                                int64_t nb_cap) {
     constexpr int kItems = kScanThreads * ITEMS;
     constexpr int kWaves = kScanThreads / 64;
     __shared__ uint32_t s_goff[256];   // global position of the block's first item of each digit
@@ -348,20 +375,19 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
     // digit joins them.
     const int64_t wbase = base + (int64_t)wave * (64 * ITEMS);
     uint32_t keys[ITEMS], vals[ITEMS], lrank[ITEMS];   // all loads in flight at once
+    bool ok[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        const int64_t i = wbase + (int64_t)j * 64 + lane;
-        keys[j] = i < n ? kin[i] : 0u;
-        vals[j] = i < n ? vin[i] : 0u;
-        lrank[j] = 0u;
+        keys[j] = vals[j] = lrank[j] = 0u;
+        ok[j] = in.load(wbase + (int64_t)j * 64 + lane, n, keys[j], vals[j]);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        const bool valid = wbase + (int64_t)j * 64 + lane < n;
+        const bool valid = ok[j];
         const uint64_t vmask = ballot(valid);
-        if (vmask == 0) break;   // wave-uniform
+        if (vmask == 0) continue;   // wave-uniform
         const uint32_t d = (keys[j] >> shift) & mask;
         const uint64_t peers = match_digit(d, dbits, vmask);
         const uint32_t rank = rank_below(peers);
@@ -392,7 +418,7 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        if (wbase + (int64_t)j * 64 + lane < n) {
+        if (ok[j]) {
             const uint32_t d = (keys[j] >> shift) & mask;
             const uint32_t lp = s_cnt[d] + s_h[wave][d] + lrank[j];
             if (lp < (uint32_t)kItems) {   // always true for consistent counts
@@ -402,7 +428,7 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
         }
     }
     __syncthreads();
-    const int nblk = (int)(n - base < kItems ? n - base : kItems);
+    const int nblk = (int)(tot < (uint32_t)kItems ? tot : (uint32_t)kItems);   // the block's items that take part
     for (int i = t; i < nblk; i += kScanThreads) {
         const uint32_t key = s_k[i];
         const uint32_t d = (key >> shift) & mask;
@@ -414,27 +440,47 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(const uint32_t *
     }
 }
 
+// One pass: items of `in` -> (ko, vo) by key bits [shift, shift + dbits).
+template <class In>
+inline void radix_pass(In in, uint32_t *ko, uint32_t *vo, const int64_t *n_dev, int64_t n_host, int64_t cap,
+                       int shift, int dbits, const SortState &so, int64_t *total_out, hipStream_t st) {
+    const int64_t nb = sort_blocks(cap);
+    const bool small = sort_items(cap) == 4;
+    hipLaunchKernelGGL((small ? k_radix_count<4, In> : k_radix_count<16, In>), dim3((unsigned)nb), dim3(kScanThreads), 0,
+                       st, in, n_dev, n_host, shift, dbits, so, nb);
+    hipLaunchKernelGGL(small ? k_digit_scan<4> : k_digit_scan<16>, dim3(256), dim3(kScanThreads), 0, st, n_dev, n_host,
+                       dbits, so, nb, total_out);
+    hipLaunchKernelGGL((small ? k_radix_scatter<4, In> : k_radix_scatter<16, In>), dim3((unsigned)nb),
+                       dim3(kScanThreads), 0, st, in, ko, vo, n_dev, n_host, shift, dbits, so, nb);
+}
+
 // Sorts n (device count, <= cap) pairs by key bits [0, bits).  Returns true
 // if the result is in (k1, v1), false if in (k0, v0).
 inline bool radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const int64_t *n_dev, int64_t cap,
                        int bits, const SortState &so, hipStream_t st) {
-    const int64_t nb = sort_blocks(cap);
-    if (nb == 0 || bits <= 0) return false;
-    const bool small = sort_items(cap) == 4;
+    if (sort_blocks(cap) == 0 || bits <= 0) return false;
     bool in1 = false;
     for (int shift = 0; shift < bits; shift += 8) {
         const int dbits = bits - shift < 8 ? bits - shift : 8;
-        uint32_t *ki = in1 ? k1 : k0, *vi = in1 ? v1 : v0;
-        uint32_t *ko = in1 ? k0 : k1, *vo = in1 ? v0 : v1;
-        hipLaunchKernelGGL(small ? k_radix_count<4> : k_radix_count<16>, dim3((unsigned)nb), dim3(kScanThreads), 0,
-                           st, ki, n_dev, cap, shift, dbits, so, nb);
-        hipLaunchKernelGGL(small ? k_digit_scan<4> : k_digit_scan<16>, dim3(256), dim3(kScanThreads), 0, st, n_dev,
-                           cap, dbits, so, nb);
-        hipLaunchKernelGGL(small ? k_radix_scatter<4> : k_radix_scatter<16>, dim3((unsigned)nb), dim3(kScanThreads),
-                           0, st, ki, vi, ko, vo, n_dev, cap, shift, dbits, so, nb);
+        radix_pass(PairIn{in1 ? k1 : k0, in1 ? v1 : v0}, in1 ? k0 : k1, in1 ? v0 : v1, n_dev, cap, cap, shift, dbits,
+                   so, nullptr, st);
         in1 = !in1;
     }
     return in1;
+}
+
+// The depth sort: the visible records among the n (view, Gaussian) items
+// (cnt[i] != 0), compacted and stably sorted by the 32-bit depth key; the
+// first pass reads the projection's arrays and writes the number of visible
+// records to *n_out (zero beforehand), which bounds the later passes.  Four
+// passes, (k1, v1), (k0, v0), (k1, v1), (k0, v0): the result is in (k0, v0).
+inline void radix_sort_visible(const uint32_t *cnt, const uint32_t *zkey, int64_t n, uint32_t *k0, uint32_t *v0,
+                               uint32_t *k1, uint32_t *v1, int64_t *n_out, const SortState &so, hipStream_t st) {
+    if (sort_blocks(n) == 0) return;
+    radix_pass(VisIn{cnt, zkey}, k1, v1, nullptr, n, n, 0, 8, so, n_out, st);
+    radix_pass(PairIn{k1, v1}, k0, v0, n_out, n, n, 8, 8, so, nullptr, st);
+    radix_pass(PairIn{k0, v0}, k1, v1, n_out, n, n, 16, 8, so, nullptr, st);
+    radix_pass(PairIn{k1, v1}, k0, v0, n_out, n, n, 24, 8, so, nullptr, st);
 }
 
 }  // namespace gsr
