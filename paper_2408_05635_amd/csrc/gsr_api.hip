@@ -679,9 +679,19 @@ __device__ __forceinline__ void gauss_sum_block(const ProjParams &pp, const View
 // Per view (one block each): the pose partials (G_W, g_t) summed over the
 // record blocks' rows in a fixed order (deterministic), then
 // (G_W, g_t) -> dL/dq | t, dL/dt, dL/dq | C, dL/dC with C = -W^T t.
+// A tracking loop's pose step, applied where the pose gradients are formed
+// (st == nullptr: none).
+struct PoseOpt {
+    gsr_pose_adam hp;
+    PoseOptState *st;
+    float *quat, *trans;   // the poses the next iteration renders
+    double *hist;          // per-iteration losses (may be null)
+};
+
 __device__ __forceinline__ void pose_final_view(const float *__restrict__ pq, const float *__restrict__ pt,
                                                 const PoseF64 *poses, const double *__restrict__ pose_blocks,
-                                                int nblocks, int V, const gsr_pose_grads &pg, int v) {
+                                                int nblocks, int V, const gsr_pose_grads &pg, const PoseOpt &po,
+                                                int v) {
     __shared__ double s_red[12][256];
     const int t = threadIdx.x;
     double acc[12];
@@ -724,6 +734,12 @@ __device__ __forceinline__ void pose_final_view(const float *__restrict__ pq, co
     rot_grad_to_quat_f64(q, G2, gq);
     if (pg.dq_c)
         for (int k = 0; k < 4; ++k) pg.dq_c[4 * v + k] = (float)gq[k];
+    if (po.st) {   // the step takes the gradients as written (FP32); pq and pt were read above
+        double sq[4], sc[3];
+        for (int k = 0; k < 4; ++k) sq[k] = (double)(float)gq[k];
+        for (int k = 0; k < 3; ++k) sc[k] = (double)(float)gc[k];
+        pose_adam_apply(v, sq, sc, po.hp, po.st, po.quat, po.trans);
+    }
 }
 
 // The last step of a backward, one launch: blocks [0, n_pose) finish the
@@ -737,6 +753,7 @@ struct FinalArgs {
     const double *pose_blocks;
     int pose_rows, V;
     gsr_pose_grads pg;
+    PoseOpt po;
     const ViewTable *vt;   // loss
     const double *loss_tile;
     double *loss;
@@ -750,12 +767,12 @@ struct FinalArgs {
 __global__ __launch_bounds__(256) void k_finalize(FinalArgs a) {
     int b = (int)blockIdx.x;
     if (b < a.n_pose) {
-        pose_final_view(a.pq, a.pt, a.poses, a.pose_blocks, a.pose_rows, a.V, a.pg, b);
+        pose_final_view(a.pq, a.pt, a.poses, a.pose_blocks, a.pose_rows, a.V, a.pg, a.po, b);
         return;
     }
     b -= a.n_pose;
     if (b < a.n_loss) {
-        loss_final_view(a.vt, a.loss_tile, a.loss, b);
+        loss_final_view(a.vt, a.loss_tile, a.loss, a.po.hist, b);
         return;
     }
     b -= a.n_loss;
@@ -947,7 +964,7 @@ void enqueue_blend_fwd(Call &c, gsr_images out) {
 }
 
 void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, gsr_images out, LossIn li,
-                      bool fused, gsr_gaussian_grads *gg, gsr_pose_grads *pg) {
+                      bool fused, gsr_gaussian_grads *gg, gsr_pose_grads *pg, const PoseOpt *po = nullptr) {
     const Layout &L = c.L;
     hipStream_t st = c.st;
     ViewTable *vt = at<ViewTable>(c.ws, L.views);
@@ -1006,6 +1023,7 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
     fa.pose_rows = (int)rec_blocks;
     fa.V = views->n_views;
     if (pg) fa.pg = *pg;
+    if (po) fa.po = *po;
     fa.vt = vt;
     fa.loss_tile = li.loss_tile;
     fa.loss = li.loss;
@@ -1035,7 +1053,7 @@ gsr_status finish(Call &c, const char *what) {
 gsr_status render_loss_grad_impl(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views,
                                  const gsr_options *opts, const gsr_targets *targets, gsr_workspace ws,
                                  gsr_images out, double *loss, gsr_gaussian_grads *gg, gsr_pose_grads *pg,
-                                 void *stream, bool keep_sticky = false) {
+                                 void *stream, bool keep_sticky = false, const PoseOpt *po = nullptr) {
     Call c;
     gsr_status s = prepare(ctx, g, views, opts, ws, stream, c);
     if (s != GSR_OK) return s;
@@ -1060,7 +1078,7 @@ gsr_status render_loss_grad_impl(gsr_ctx *ctx, const gsr_gaussians *g, const gsr
     li.w_prior = opts->w_prior;
     li.sil_thresh = opts->sil_mask_thresh;
     li.loss = loss;
-    enqueue_backward(c, views, opts, out, li, true, gg, pg);
+    enqueue_backward(c, views, opts, out, li, true, gg, pg, po);
     return finish(c, "gsr_render_loss_grad launch");
 }
 
@@ -1081,14 +1099,12 @@ gsr_status track_impl(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *ca
     o.flags |= GSR_NO_GAUSS_GRADS;
     o = resolve_tile(ctx, g->n, &views, &o);
     gsr_status s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
-    hipStream_t st = (hipStream_t)stream;
     for (int32_t it = 0; it < iters && s == GSR_OK; ++it) {
-        s = render_loss_grad_impl(ctx, g, &views, &o, targets, ws, out, loss, nullptr, pg, stream, it > 0);
-        if (s != GSR_OK) break;
-        hipLaunchKernelGGL(k_pose_opt_step, dim3(1), dim3(64), 0, st, V, (const float *)pg->dq_c,
-                           (const float *)pg->dc, *hp, reinterpret_cast<PoseOptState *>(state), quat, trans,
-                           (const double *)loss, loss_hist ? loss_hist + (size_t)it * V : nullptr);
-        s = check_hip(ctx, hipGetLastError(), "gsr_track launch");
+        // the pose step runs in the backward's last launch, where the pose
+        // gradients are formed
+        const PoseOpt po{*hp, reinterpret_cast<PoseOptState *>(state), quat, trans,
+                         loss_hist ? loss_hist + (size_t)it * V : nullptr};
+        s = render_loss_grad_impl(ctx, g, &views, &o, targets, ws, out, loss, nullptr, pg, stream, it > 0, &po);
     }
     return s;
 }

@@ -556,9 +556,9 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
 }
 
 // Per-view loss: the view's tile partials added in a fixed tree order (one
-// 256-thread block per view).
+// 256-thread block per view); also copied to hist if that is set.
 __device__ __forceinline__ void loss_final_view(const ViewTable *__restrict__ vt, const double *__restrict__ loss_tile,
-                                                double *__restrict__ loss, int view) {
+                                                double *__restrict__ loss, double *__restrict__ hist, int view) {
     __shared__ double s[256];
     const ViewInfo &V = vt->v[view];
     const int n = V.tiles_x * V.tiles_y;
@@ -571,7 +571,10 @@ __device__ __forceinline__ void loss_final_view(const ViewTable *__restrict__ vt
         if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) loss[view] = s[0];
+    if (threadIdx.x == 0) {
+        loss[view] = s[0];
+        if (hist) hist[view] = s[0];   // a tracking loop's per-iteration record
+    }
 }
 
 }  // namespace gsr

@@ -53,27 +53,36 @@ __global__ void k_pose_opt_init(int V, const float *__restrict__ quat, const flo
     st[v] = s;
 }
 
-// One decoupled Adam step per view; writes the pose the next render reads
-// (FP32) and, if hist is set, copies the view's loss into it.
-__global__ void k_pose_opt_step(int V, const float *__restrict__ dq_c, const float *__restrict__ dc,
-                                gsr_pose_adam hp, PoseOptState *__restrict__ st, float *__restrict__ quat,
-                                float *__restrict__ trans, const double *__restrict__ loss, double *__restrict__ hist) {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= V) return;
+// One decoupled Adam step of view v from its gradients (dL/dq | C, dL/dC);
+// writes the pose the next render reads (FP32).
+__device__ __forceinline__ void pose_adam_apply(int v, const double dq_c[4], const double dc[3], const gsr_pose_adam &hp,
+                                                PoseOptState *__restrict__ st, float *__restrict__ quat,
+                                                float *__restrict__ trans) {
     PoseOptState s = st[v];
     s.step += 1.0;
     const double b1 = hp.beta1, b2 = hp.beta2, eps = hp.eps;
     const double c1 = 1.0 - pow(b1, s.step), c2 = 1.0 - pow(b2, s.step);
-    for (int k = 0; k < 4; ++k)
-        adam_update(s.q[k], (double)dq_c[4 * v + k], s.mq[k], s.vq[k], (double)hp.lr_rot, b1, b2, eps, c1, c2);
-    for (int k = 0; k < 3; ++k)
-        adam_update(s.C[k], (double)dc[3 * v + k], s.mc[k], s.vc[k], (double)hp.lr_pos, b1, b2, eps, c1, c2);
+    for (int k = 0; k < 4; ++k) adam_update(s.q[k], dq_c[k], s.mq[k], s.vq[k], (double)hp.lr_rot, b1, b2, eps, c1, c2);
+    for (int k = 0; k < 3; ++k) adam_update(s.C[k], dc[k], s.mc[k], s.vc[k], (double)hp.lr_pos, b1, b2, eps, c1, c2);
     st[v] = s;
     double R[9];
     quat_to_rot_f64(s.q[0], s.q[1], s.q[2], s.q[3], R);
     for (int k = 0; k < 4; ++k) quat[4 * v + k] = (float)s.q[k];
     for (int k = 0; k < 3; ++k)   // t = -R C
         trans[3 * v + k] = (float)(-(R[3 * k] * s.C[0] + R[3 * k + 1] * s.C[1] + R[3 * k + 2] * s.C[2]));
+}
+
+// One decoupled Adam step per view from the gradient arrays; if hist is set,
+// also copies the view's loss into it.
+__global__ void k_pose_opt_step(int V, const float *__restrict__ dq_c, const float *__restrict__ dc,
+                                gsr_pose_adam hp, PoseOptState *__restrict__ st, float *__restrict__ quat,
+                                float *__restrict__ trans, const double *__restrict__ loss, double *__restrict__ hist) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    double gq[4], gc[3];
+    for (int k = 0; k < 4; ++k) gq[k] = (double)dq_c[4 * v + k];
+    for (int k = 0; k < 3; ++k) gc[k] = (double)dc[3 * v + k];
+    pose_adam_apply(v, gq, gc, hp, st, quat, trans);
     if (hist) hist[v] = loss[v];
 }
 
