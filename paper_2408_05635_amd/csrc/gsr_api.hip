@@ -108,7 +108,7 @@ struct Layout {
     int32_t G;            // total blend blocks
     int tile_bits;        // key bits of the tile sort
     size_t views, poses, counters, cnt, zkey, dk0, dv0, dk1, dv1, inv, rec, trect, cnt_s, poff, pk0, pv0, pk1, pv1,
-        chunk, ranges, tfinal, nlast, phash, gpairs, rgrad, losst, poseblk, scounts, stotals, sync;
+        chunk, ranges, torder, tfinal, nlast, phash, gpairs, rgrad, losst, poseblk, scounts, stotals, sync;
     int64_t sort_nb;      // sort blocks of the larger sort (row length of scounts)
     // offsets in the sync region (cleared by every call): scan look-back words
     size_t sync_status, sync_bytes;
@@ -264,6 +264,7 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     L.pv1 = take(4 * kc);
     L.chunk = take(4 * (size_t)((kc + kEmitChunk - 1) / kEmitChunk + 1));
     L.ranges = take(8 * (size_t)L.T);
+    L.torder = take(4 * (size_t)L.T);
     L.tfinal = take(4 * (size_t)L.P);
     L.nlast = take(4 * (size_t)L.P);
     L.phash = take(4 * (size_t)L.P);
@@ -485,6 +486,37 @@ __global__ void k_ranges(const uint32_t *__restrict__ keys, const int64_t *__res
         if ((int64_t)k >= n_tiles) continue;   // never expected; keeps writes in bounds
         if (i == 0 || keys[i - 1] != k) ranges[k].x = (uint32_t)i;
         if (i == K - 1 || keys[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
+    }
+}
+
+// Heaviest tiles first: a permutation of the tiles by decreasing list length
+// (buckets of 16 entries, the longest first, any order within a bucket), so
+// that the blend launches start the long lists early instead of ending on
+// them.  Only the order of the work changes, never a result.
+constexpr int kOrderThreads = 1024;
+constexpr uint32_t kOrderBuckets = 256;
+
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint2 *__restrict__ ranges, int64_t n_tiles,
+                                                              uint32_t *__restrict__ order) {
+    __shared__ uint32_t s_h[kOrderBuckets];
+    const int t = threadIdx.x;
+    if (t < (int)kOrderBuckets) s_h[t] = 0u;
+    __syncthreads();
+    auto bucket = [&](int64_t i) {
+        const uint2 r = ranges[i];
+        const uint32_t len = r.y > r.x ? r.y - r.x : 0u;
+        const uint32_t b = len >> 4;
+        return (kOrderBuckets - 1u) - (b < kOrderBuckets - 1u ? b : kOrderBuckets - 1u);
+    };
+    for (int64_t i = t; i < n_tiles; i += kOrderThreads) atomicAdd(&s_h[bucket(i)], 1u);
+    __syncthreads();
+    uint32_t all;
+    const uint32_t first = block_excl_scan_u32<kOrderThreads>(t < (int)kOrderBuckets ? s_h[t] : 0u, all);
+    if (t < (int)kOrderBuckets) s_h[t] = first;
+    __syncthreads();
+    for (int64_t i = t; i < n_tiles; i += kOrderThreads) {
+        const uint32_t pos = atomicAdd(&s_h[bucket(i)], 1u);
+        if ((int64_t)pos < n_tiles) order[pos] = (uint32_t)i;   // always true; keeps writes in bounds
     }
 }
 
@@ -935,6 +967,9 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     uint2 *ranges = at<uint2>(ws, L.ranges);
     hipLaunchKernelGGL(k_ranges, dim3(grid_for(L.kcap, 256, 4096)), dim3(256), 0, st, p_in1 ? pk1 : pk0,
                        (const int64_t *)counters, ranges, L.T);
+    if (L.T > 0)
+        hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, st, (const uint2 *)ranges, L.T,
+                           at<uint32_t>(ws, L.torder));
 }
 
 // record index of every sorted pair (the sort's result buffer is fixed by the key bits)
@@ -953,13 +988,15 @@ void enqueue_blend_fwd(Call &c, gsr_images out) {
     const Layout &L = c.L;
     BlendOut bo{out.rgb, out.depth, out.sil, at<float>(c.ws, L.tfinal), at<uint32_t>(c.ws, L.nlast),
                 at<uint32_t>(c.ws, L.phash)};
-    const unsigned grid = (unsigned)(((L.G + 7) / 8) * 8);
+    // the tiles' blocks, tile ranks dealt to the XCDs in turn (see locate_block)
+    const int64_t nsub = (int64_t)(c.tab.tile_w / kBlk) * (c.tab.tile_h / kBlk);
+    const unsigned grid = (unsigned)(8 * nsub * ((L.T + 7) / 8));
     if (grid > 0) {
         auto kern = c.count ? (c.hash ? k_blend_fwd<true, true> : k_blend_fwd<true, false>)
                             : (c.hash ? k_blend_fwd<false, true> : k_blend_fwd<false, false>);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, c.st, at<ViewTable>(c.ws, L.views),
                            at<float4>(c.ws, L.rec), pair_values(c), at<uint2>(c.ws, L.ranges),
-                           at<int64_t>(c.ws, L.counters), bo);
+                           at<uint32_t>(c.ws, L.torder), at<int64_t>(c.ws, L.counters), bo);
     }
 }
 
@@ -992,7 +1029,7 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
                                    : (c.count ? k_blend_bwd<false, true, 10> : k_blend_bwd<false, false, 10>));
             hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, vt, at<float4>(c.ws, L.rec), pair_values(c),
                                at<uint32_t>(c.ws, L.poff), at<uint2>(c.ws, L.trect), at<uint2>(c.ws, L.ranges),
-                               counters, bo, li, gpairs);
+                               at<uint32_t>(c.ws, L.torder), counters, bo, li, gpairs);
         }
     }
     if (fused && L.kcap == 0)   // no blend ran: every tile's partial is zero

@@ -27,22 +27,28 @@ struct BlockPos {
     bool valid;
 };
 
-// Logical block id from the hardware id: consecutive logical blocks (the
-// sub-blocks of one binning tile, then neighbouring tiles) are placed on the
-// same XCD, whose L2 then holds the tile's records for all of them.
-__device__ __forceinline__ BlockPos locate_block(const ViewTable *vt) {
+// The block of workgroup i: tiles go heaviest first (torder, a permutation of
+// the tiles), tile rank r to XCD r mod 8 (the hardware deals workgroups to the
+// XCDs in turn), and the sub-blocks of a tile run one after the other on the
+// same XCD, whose L2 then holds the tile's records for all of them:
+// i = 8 (nsub floor(r / 8) + sub) + r mod 8.
+__device__ __forceinline__ BlockPos locate_block(const ViewTable *vt, const uint32_t *__restrict__ torder) {
     BlockPos bp;
-    const int32_t G = vt->total_blocks;
-    const int32_t per = (G + 7) >> 3;
-    const int32_t bid = (int32_t)(blockIdx.x & 7u) * per + (int32_t)(blockIdx.x >> 3);
-    bp.valid = bid < G;
+    const int sx = vt->tile_w / kBlk, sy = vt->tile_h / kBlk, nsub = sx * sy;
+    const int32_t T = vt->total_tiles;
+    const uint32_t i = blockIdx.x, k = i >> 3;
+    const int32_t r = (int32_t)(8u * (k / (uint32_t)nsub) + (i & 7u));
+    const int sub = (int)(k % (uint32_t)nsub);
+    bp.valid = r < T;
     if (!bp.valid) return bp;
-    bp.v = view_of_block(vt, bid);
-    const ViewInfo &V = vt->v[bp.v];
-    const int sx = vt->tile_w / kBlk, sy = vt->tile_h / kBlk;
-    const int local = bid - V.blk_off;
-    const int tile = local / (sx * sy);
-    const int sub = local - tile * (sx * sy);
+    const int32_t tg = (int32_t)torder[r];
+    bp.valid = tg < T;   // always true for a permutation; keeps reads in bounds
+    if (!bp.valid) return bp;
+    int v = 0;
+    while (v + 1 < vt->n_views && vt->v[v + 1].tile_off <= tg) ++v;
+    bp.v = v;
+    const ViewInfo &V = vt->v[v];
+    const int tile = tg - V.tile_off;
     const int ty = tile / V.tiles_x, tx = tile - ty * V.tiles_x;
     bp.tile = tile;
     bp.bx0 = tx * vt->tile_w + (sub % sx) * kBlk;
@@ -114,11 +120,12 @@ struct BlendOut {
 template <bool COUNT, bool HASH>
 __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ vt, const float4 *__restrict__ rec,
                                                   const uint32_t *__restrict__ pair_rec,
-                                                  const uint2 *__restrict__ ranges, int64_t *__restrict__ counters,
+                                                  const uint2 *__restrict__ ranges,
+                                                  const uint32_t *__restrict__ torder, int64_t *__restrict__ counters,
                                                   BlendOut out) {
     __shared__ float4 s_a[64], s_b[64], s_c[64];
     __shared__ uint32_t s_pos[64], s_rec_id[64];
-    const BlockPos bp = locate_block(vt);
+    const BlockPos bp = locate_block(vt, torder);
     if (!bp.valid) return;
     const ViewInfo &V = vt->v[bp.v];
     const uint32_t lane = threadIdx.x;
@@ -291,7 +298,8 @@ template <bool FUSED, bool COUNT, int NV>
 __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__ vt, const float4 *__restrict__ rec,
                                                    const uint32_t *__restrict__ pair_rec,
                                                    const uint32_t *__restrict__ poff, const uint2 *__restrict__ trect,
-                                                   const uint2 *__restrict__ ranges, int64_t *__restrict__ counters,
+                                                   const uint2 *__restrict__ ranges,
+                                                   const uint32_t *__restrict__ torder, int64_t *__restrict__ counters,
                                                    BlendOut st, LossIn L, float *__restrict__ grad_pairs) {
     // The NV partials of an entry are summed over the wave in two steps: DPP
     // sums over each quad of lanes, stored by the quad's first lane into
@@ -306,11 +314,13 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
     __shared__ uint32_t s_j[kSeg];   // gradient-row slot of each entry of the segment
     __shared__ double s_loss[kBwdMaxWaves];
 
-    // tile of this workgroup (tiles of all views, view by view)
+    // tile of this workgroup: the i-th of the order, heaviest first (the
+    // hardware deals workgroups to the XCDs in turn, so the long lists spread
+    // over all of them)
     const int32_t T_all = vt->total_tiles;
-    const int32_t per = (T_all + 7) >> 3;
-    const int32_t tid_g = (int32_t)(blockIdx.x & 7u) * per + (int32_t)(blockIdx.x >> 3);   // XCD-aware
-    if (tid_g >= T_all) return;
+    if ((int32_t)blockIdx.x >= T_all) return;
+    const int32_t tid_g = (int32_t)torder[blockIdx.x];
+    if (tid_g >= T_all) return;   // always false for a permutation; keeps reads in bounds
     int v = 0;
     while (v + 1 < vt->n_views && vt->v[v + 1].tile_off <= tid_g) ++v;
     const ViewInfo &V = vt->v[v];

@@ -110,13 +110,4 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
 
 __device__ __forceinline__ float ld_nc(const float *p) { return __builtin_nontemporal_load(p); }
 
-// Find the view that owns global index `x` given prefix offsets (linear scan
-// over a small table in device memory; the table is wave-uniform).
-__device__ __forceinline__ int view_of_block(const ViewTable *vt, int32_t blk) {
-    int v = 0;
-    const int n = vt->n_views;
-    while (v + 1 < n && vt->v[v + 1].blk_off <= blk) ++v;
-    return v;
-}
-
 }  // namespace gsr
