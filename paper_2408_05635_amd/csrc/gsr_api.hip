@@ -92,6 +92,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kRecGrad = 14;   // per-record parameter gradient: mu 3, q 4, log_s 3, logit 1, rgb 3
+constexpr size_t kCpBudgetBytes = 96u << 20;   // checkpoints of split lists (the longest lists get them first)
+constexpr int64_t kSplitMaxTiles = 2048;       // about the backward workgroups resident at once
 constexpr int kRecBwdMaxBlocks = 2048;   // grid cap of the record backward (one pose row per block)
 constexpr int kEmitChunk = 1024;         // pairs per emission block
 // synchronisation region, cleared by every call: scan tickets (256 B) and the
@@ -108,7 +110,10 @@ struct Layout {
     int32_t G;            // total blend blocks
     int tile_bits;        // key bits of the tile sort
     size_t views, poses, counters, cnt, zkey, dk0, dv0, dk1, dv1, inv, rec, trect, cnt_s, poff, pk0, pv0, pk1, pv1,
-        chunk, ranges, torder, tfinal, nlast, phash, gpairs, rgrad, losst, poseblk, scounts, stotals, sync;
+        chunk, ranges, torder, cpoff, work, nwork, cp, tfinal, nlast, phash, gpairs, rgrad, losst, poseblk, scounts,
+        stotals, sync;
+    int64_t cp_slots;     // checkpoint slots of split lists (each: the tile's pixels x 6 floats)
+    int64_t work_cap;     // backward work items at most: one per tile plus one per slot
     int64_t sort_nb;      // sort blocks of the larger sort (row length of scounts)
     // offsets in the sync region (cleared by every call): scan look-back words
     size_t sync_status, sync_bytes;
@@ -265,6 +270,19 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     L.chunk = take(4 * (size_t)((kc + kEmitChunk - 1) / kEmitChunk + 1));
     L.ranges = take(8 * (size_t)L.T);
     L.torder = take(4 * (size_t)L.T);
+    L.cpoff = take(4 * (size_t)L.T);
+    {   // a split list needs chunks_of(len) - 1 slots; at most kcap / kChunkEntries in all, within a budget
+        const size_t slot_bytes = (size_t)(vt.tile_w / kBlk) * (vt.tile_h / kBlk) * kCpValues * 64 * 4;
+        // only when the tiles leave resident workgroups idle: with more, the
+        // heaviest-first order already balances the backward
+        L.cp_slots = L.T <= kSplitMaxTiles
+                         ? std::min<int64_t>(kcap / kChunkEntries + 1, (int64_t)(kCpBudgetBytes / slot_bytes))
+                         : 0;
+        L.work_cap = L.T + L.cp_slots;
+        L.work = take(4 * (size_t)L.work_cap);
+        L.nwork = take(8);
+        L.cp = take(slot_bytes * (size_t)L.cp_slots);
+    }
     L.tfinal = take(4 * (size_t)L.P);
     L.nlast = take(4 * (size_t)L.P);
     L.phash = take(4 * (size_t)L.P);
@@ -489,34 +507,101 @@ __global__ void k_ranges(const uint32_t *__restrict__ keys, const int64_t *__res
     }
 }
 
-// Heaviest tiles first: a permutation of the tiles by decreasing list length
-// (buckets of 16 entries, the longest first, any order within a bucket), so
-// that the blend launches start the long lists early instead of ending on
-// them.  Only the order of the work changes, never a result.
+// Heaviest work first.  (1) torder: a permutation of the tiles by decreasing
+// list length (256 buckets of 16 entries, the longest first, any order within
+// a bucket), the order in which the forward takes its tiles.  (2) In that
+// order, each list longer than kSplitMin gets chunks_of(len) - 1 checkpoint
+// slots (cpoff: its first slot, or kNoSplit) while they fit in slots_cap.
+// (3) work: the backward's items (tile | chunk << 24), again longest first,
+// and their number.  Only the order and the split of the work change, never a
+// result; one block does it all.
 constexpr int kOrderThreads = 1024;
 constexpr uint32_t kOrderBuckets = 256;
 
-__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint2 *__restrict__ ranges, int64_t n_tiles,
-                                                              uint32_t *__restrict__ order) {
+__global__ __launch_bounds__(kOrderThreads) void k_work_order(const uint2 *__restrict__ ranges, int64_t n_tiles,
+                                                              int64_t slots_cap, uint32_t *__restrict__ torder,
+                                                              uint32_t *__restrict__ cpoff, uint32_t *__restrict__ work,
+                                                              int64_t *__restrict__ n_work) {
     __shared__ uint32_t s_h[kOrderBuckets];
+    __shared__ int64_t s_run;
     const int t = threadIdx.x;
-    if (t < (int)kOrderBuckets) s_h[t] = 0u;
-    __syncthreads();
-    auto bucket = [&](int64_t i) {
+    auto len_of = [&](int64_t i) {
         const uint2 r = ranges[i];
-        const uint32_t len = r.y > r.x ? r.y - r.x : 0u;
+        return r.y > r.x ? r.y - r.x : 0u;
+    };
+    auto bucket_of = [](uint32_t len) {
         const uint32_t b = len >> 4;
         return (kOrderBuckets - 1u) - (b < kOrderBuckets - 1u ? b : kOrderBuckets - 1u);
     };
-    for (int64_t i = t; i < n_tiles; i += kOrderThreads) atomicAdd(&s_h[bucket(i)], 1u);
+    // turns the bucket counts into first positions; returns the total
+    auto bucket_starts = [&]() {
+        uint32_t all;
+        const uint32_t first = block_excl_scan_u32<kOrderThreads>(t < (int)kOrderBuckets ? s_h[t] : 0u, all);
+        if (t < (int)kOrderBuckets) s_h[t] = first;
+        __syncthreads();
+        return all;
+    };
+    // (1) tiles by decreasing length
+    if (t < (int)kOrderBuckets) s_h[t] = 0u;
     __syncthreads();
-    uint32_t all;
-    const uint32_t first = block_excl_scan_u32<kOrderThreads>(t < (int)kOrderBuckets ? s_h[t] : 0u, all);
-    if (t < (int)kOrderBuckets) s_h[t] = first;
+    for (int64_t i = t; i < n_tiles; i += kOrderThreads) atomicAdd(&s_h[bucket_of(len_of(i))], 1u);
+    __syncthreads();
+    bucket_starts();
+    for (int64_t i = t; i < n_tiles; i += kOrderThreads) {
+        const uint32_t pos = atomicAdd(&s_h[bucket_of(len_of(i))], 1u);
+        if ((int64_t)pos < n_tiles) {   // always true; keeps writes in bounds
+            torder[pos] = (uint32_t)i;
+            if (slots_cap == 0) work[pos] = (uint32_t)i;   // no splits: the items are the tiles, in that order
+        }
+        if (slots_cap == 0) cpoff[i] = kNoSplit;
+    }
+    if (slots_cap == 0) {
+        if (t == 0) *n_work = n_tiles;
+        return;
+    }
+    __syncthreads();
+    // (2) checkpoint slots in that order
+    if (t == 0) s_run = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < n_tiles; base += kOrderThreads) {
+        const int64_t r = base + t;
+        uint32_t need = 0, tile = 0;
+        if (r < n_tiles) {
+            tile = torder[r];
+            const uint32_t len = len_of(tile), nch = chunks_of(len);
+            need = (len > kSplitMin && nch <= kMaxChunks) ? nch - 1u : 0u;
+        }
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan_u32<kOrderThreads>(need, tot);
+        const int64_t p = s_run + (int64_t)ex;
+        if (r < n_tiles) cpoff[tile] = (need > 0u && p + (int64_t)need <= slots_cap) ? (uint32_t)p : kNoSplit;
+        __syncthreads();
+        if (t == 0) s_run += tot;
+        __syncthreads();
+    }
+    // (3) the backward's items, longest first
+    auto item_len = [&](uint32_t len, bool split, uint32_t m) {
+        return split ? (len - m * kChunkEntries < kChunkEntries ? len - m * kChunkEntries : kChunkEntries) : len;
+    };
+    if (t < (int)kOrderBuckets) s_h[t] = 0u;
     __syncthreads();
     for (int64_t i = t; i < n_tiles; i += kOrderThreads) {
-        const uint32_t pos = atomicAdd(&s_h[bucket(i)], 1u);
-        if ((int64_t)pos < n_tiles) order[pos] = (uint32_t)i;   // always true; keeps writes in bounds
+        const uint32_t len = len_of(i);
+        const bool split = cpoff[i] != kNoSplit;
+        const uint32_t nch = split ? chunks_of(len) : 1u;
+        for (uint32_t m = 0; m < nch; ++m) atomicAdd(&s_h[bucket_of(item_len(len, split, m))], 1u);
+    }
+    __syncthreads();
+    const uint32_t total = bucket_starts();
+    if (t == 0) *n_work = total;
+    for (int64_t i = t; i < n_tiles; i += kOrderThreads) {
+        const uint32_t len = len_of(i);
+        const bool split = cpoff[i] != kNoSplit;
+        const uint32_t nch = split ? chunks_of(len) : 1u;
+        for (uint32_t m = 0; m < nch; ++m) {
+            const uint32_t pos = atomicAdd(&s_h[bucket_of(item_len(len, split, m))], 1u);
+            if (pos < total) work[pos] = (uint32_t)i | (m << 24);   // always true; keeps writes in bounds
+        }
     }
 }
 
@@ -897,6 +982,8 @@ gsr_status prepare(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views,
     if (ws.pair_capacity < 0 || ws.pair_capacity >= (int64_t)0xffffffffLL)
         return fail(ctx, GSR_EINVAL, "pair_capacity must be in [0, 2^32)");
     build_table(views, opts, c.tab);
+    if (c.tab.total_tiles >= (1 << 24))   // a backward work item holds the tile in 24 bits
+        return fail(ctx, GSR_EUNSUPPORTED, "more than 2^24 - 1 tiles in one call (got %d)", c.tab.total_tiles);
     c.L = make_layout(g->n, c.tab, ws.pair_capacity);
     if (ws.bytes < c.L.total)
         return fail(ctx, GSR_ENOMEM, "workspace has %zu bytes, this call needs %zu", ws.bytes, c.L.total);
@@ -968,8 +1055,9 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     hipLaunchKernelGGL(k_ranges, dim3(grid_for(L.kcap, 256, 4096)), dim3(256), 0, st, p_in1 ? pk1 : pk0,
                        (const int64_t *)counters, ranges, L.T);
     if (L.T > 0)
-        hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, st, (const uint2 *)ranges, L.T,
-                           at<uint32_t>(ws, L.torder));
+        hipLaunchKernelGGL(k_work_order, dim3(1), dim3(kOrderThreads), 0, st, (const uint2 *)ranges, L.T, L.cp_slots,
+                           at<uint32_t>(ws, L.torder), at<uint32_t>(ws, L.cpoff), at<uint32_t>(ws, L.work),
+                           at<int64_t>(ws, L.nwork));
 }
 
 // record index of every sorted pair (the sort's result buffer is fixed by the key bits)
@@ -996,7 +1084,8 @@ void enqueue_blend_fwd(Call &c, gsr_images out) {
                             : (c.hash ? k_blend_fwd<false, true> : k_blend_fwd<false, false>);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, c.st, at<ViewTable>(c.ws, L.views),
                            at<float4>(c.ws, L.rec), pair_values(c), at<uint2>(c.ws, L.ranges),
-                           at<uint32_t>(c.ws, L.torder), at<int64_t>(c.ws, L.counters), bo);
+                           at<uint32_t>(c.ws, L.torder), at<uint32_t>(c.ws, L.cpoff), at<float>(c.ws, L.cp),
+                           at<int64_t>(c.ws, L.counters), bo);
     }
 }
 
@@ -1019,9 +1108,9 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
                 at<uint32_t>(c.ws, L.phash)};
     {
         StageTimer timer(c.ctx, kStageBlendBwd, st);
-        const unsigned grid = (unsigned)(((L.T + 7) / 8) * 8);
+        const unsigned grid = (unsigned)(((L.work_cap + 7) / 8) * 8);   // the items past n_work leave at once
         const unsigned threads = (unsigned)(64 * (opts->tile_w / kBlk) * (opts->tile_h / kBlk));
-        if (grid > 0 && L.kcap > 0) {
+        if (grid > 0 && L.kcap > 0 && L.T > 0) {
             auto kern =
                 pose_only ? (fused ? (c.count ? k_blend_bwd<true, true, 6> : k_blend_bwd<true, false, 6>)
                                    : (c.count ? k_blend_bwd<false, true, 6> : k_blend_bwd<false, false, 6>))
@@ -1029,7 +1118,8 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
                                    : (c.count ? k_blend_bwd<false, true, 10> : k_blend_bwd<false, false, 10>));
             hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, vt, at<float4>(c.ws, L.rec), pair_values(c),
                                at<uint32_t>(c.ws, L.poff), at<uint2>(c.ws, L.trect), at<uint2>(c.ws, L.ranges),
-                               at<uint32_t>(c.ws, L.torder), counters, bo, li, gpairs);
+                               at<uint32_t>(c.ws, L.work), at<int64_t>(c.ws, L.nwork), at<uint32_t>(c.ws, L.cpoff),
+                               at<float>(c.ws, L.cp), counters, bo, li, gpairs);
         }
     }
     if (fused && L.kcap == 0)   // no blend ran: every tile's partial is zero

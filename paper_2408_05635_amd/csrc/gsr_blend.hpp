@@ -23,9 +23,32 @@ namespace gsr {
 struct BlockPos {
     int v;            // view
     int tile;         // tile index within the view
+    int tg;           // tile index over all views
+    int sub;          // the block's place in its tile (row-major 8x8 blocks)
     int bx0, by0;     // top-left pixel of the 8x8 block
     bool valid;
 };
+
+// List chunks of the backward.  The reverse walk of a long list is the
+// serial path of a whole backward launch, so a tile whose list is longer than
+// kSplitMin entries may be walked by several workgroups, one per chunk of
+// kChunkEntries entries.  The forward leaves, at every chunk boundary b and
+// for every pixel of such a tile, the transmittance in front of entry b and
+// the five channel sums over the entries before b; a chunk starts its walk
+// from there (T = T_b, and the colour behind = final image - sums, per unit
+// of T_b), which is the state the full walk would reach at b.
+constexpr uint32_t kChunkEntries = 256;   // a multiple of 64: the forward's staging rounds meet every boundary
+constexpr uint32_t kSplitMin = 384;
+constexpr uint32_t kMaxChunks = 256;      // chunk index in the top 8 bits of a work item
+constexpr uint32_t kNoSplit = 0xffffffffu;
+constexpr int kCpValues = 6;              // T, r, g, b, depth, silhouette
+
+__device__ __forceinline__ uint32_t chunks_of(uint32_t len) { return (len + kChunkEntries - 1) / kChunkEntries; }
+
+// checkpoint value q of lane `lane` of block `sub` in slot `slot`
+__device__ __forceinline__ size_t cp_index(uint32_t slot, int nsub, int sub, int q, uint32_t lane) {
+    return (((size_t)slot * (size_t)nsub + (size_t)sub) * kCpValues + (size_t)q) * 64 + lane;
+}
 
 // The block of workgroup i: tiles go heaviest first (torder, a permutation of
 // the tiles), tile rank r to XCD r mod 8 (the hardware deals workgroups to the
@@ -51,6 +74,8 @@ __device__ __forceinline__ BlockPos locate_block(const ViewTable *vt, const uint
     const int tile = tg - V.tile_off;
     const int ty = tile / V.tiles_x, tx = tile - ty * V.tiles_x;
     bp.tile = tile;
+    bp.tg = tg;
+    bp.sub = sub;
     bp.bx0 = tx * vt->tile_w + (sub % sx) * kBlk;
     bp.by0 = ty * vt->tile_h + (sub / sx) * kBlk;
     bp.valid = bp.bx0 < V.W && bp.by0 < V.H;
@@ -121,8 +146,9 @@ template <bool COUNT, bool HASH>
 __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ vt, const float4 *__restrict__ rec,
                                                   const uint32_t *__restrict__ pair_rec,
                                                   const uint2 *__restrict__ ranges,
-                                                  const uint32_t *__restrict__ torder, int64_t *__restrict__ counters,
-                                                  BlendOut out) {
+                                                  const uint32_t *__restrict__ torder,
+                                                  const uint32_t *__restrict__ cpoff, float *__restrict__ cp,
+                                                  int64_t *__restrict__ counters, BlendOut out) {
     __shared__ float4 s_a[64], s_b[64], s_c[64];
     __shared__ uint32_t s_pos[64], s_rec_id[64];
     const BlockPos bp = locate_block(vt, torder);
@@ -140,8 +166,24 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, cd = 0.0f, cs = 0.0f;
     uint32_t last = 0, n_eval = 0, n_contrib = 0, hsh = 0x811c9dc5u;
     bool done = !inside;
+    // chunk boundaries of a split list: the state in front of entry rg.x + j C
+    const uint32_t cpo = cpoff[bp.tg];
+    const uint32_t n_ch = rg.y > rg.x ? chunks_of(rg.y - rg.x) : 1u;
+    const uint32_t n_cp = (cpo != kNoSplit && n_ch <= kMaxChunks) ? n_ch - 1u : 0u;
+    const int nsub = (vt->tile_w / kBlk) * (vt->tile_h / kBlk);
+    uint32_t next_cp = 1;
+    auto write_cp = [&](uint32_t j) {
+        float *d = cp + cp_index(cpo + (j - 1u), nsub, bp.sub, 0, lane);
+        d[0] = T;
+        d[64] = c0;
+        d[128] = c1;
+        d[192] = c2;
+        d[256] = cd;
+        d[320] = cs;
+    };
     for (uint32_t c = rg.x; c < rg.y; c += 64) {
         if (ballot(!done) == 0) break;
+        if (next_cp <= n_cp && c == rg.x + next_cp * kChunkEntries) write_cp(next_cp++);   // wave-uniform
         const uint32_t e = c + lane;
         bool keep = false;
         float4 A, B, C;
@@ -206,6 +248,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
         if (lastk >= 0) last = s_pos[lastk] + 1u;
         __syncthreads();
     }
+    for (; next_cp <= n_cp; ++next_cp) write_cp(next_cp);   // boundaries past the end: the final state
     if (COUNT) {
         const uint32_t e = wave_sum_u32(n_eval), c = wave_sum_u32(n_contrib);
         if (lane == 0) {
@@ -299,8 +342,10 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                                                    const uint32_t *__restrict__ pair_rec,
                                                    const uint32_t *__restrict__ poff, const uint2 *__restrict__ trect,
                                                    const uint2 *__restrict__ ranges,
-                                                   const uint32_t *__restrict__ torder, int64_t *__restrict__ counters,
-                                                   BlendOut st, LossIn L, float *__restrict__ grad_pairs) {
+                                                   const uint32_t *__restrict__ work, const int64_t *__restrict__ n_work,
+                                                   const uint32_t *__restrict__ cpoff, const float *__restrict__ cp,
+                                                   int64_t *__restrict__ counters, BlendOut st, LossIn L,
+                                                   float *__restrict__ grad_pairs) {
     // The NV partials of an entry are summed over the wave in two steps: DPP
     // sums over each quad of lanes, stored by the quad's first lane into
     // s_q[wave][batch slot][quad][NV]; once kBatch entries are stored, lane
@@ -314,13 +359,15 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
     __shared__ uint32_t s_j[kSeg];   // gradient-row slot of each entry of the segment
     __shared__ double s_loss[kBwdMaxWaves];
 
-    // tile of this workgroup: the i-th of the order, heaviest first (the
-    // hardware deals workgroups to the XCDs in turn, so the long lists spread
-    // over all of them)
+    // work item of this workgroup: the i-th (tile, chunk) of the order, longest
+    // first (the hardware deals workgroups to the XCDs in turn, so the long
+    // ones spread over all of them)
     const int32_t T_all = vt->total_tiles;
-    if ((int32_t)blockIdx.x >= T_all) return;
-    const int32_t tid_g = (int32_t)torder[blockIdx.x];
-    if (tid_g >= T_all) return;   // always false for a permutation; keeps reads in bounds
+    if ((int64_t)blockIdx.x >= *n_work) return;
+    const uint32_t item = work[blockIdx.x];
+    const int32_t tid_g = (int32_t)(item & 0xffffffu);
+    const uint32_t chunk = item >> 24;
+    if (tid_g >= T_all) return;   // never expected; keeps reads in bounds
     int v = 0;
     while (v + 1 < vt->n_views && vt->v[v + 1].tile_off <= tid_g) ++v;
     const ViewInfo &V = vt->v[v];
@@ -394,16 +441,43 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
     const uint32_t n_rec = (uint32_t)counters[kCntVisible];
     const uint32_t n_pair = (uint32_t)counters[kCntPairsUsed];
     if (rg.y > n_pair || rg.x > rg.y) rg = make_uint2(0u, 0u);   // never expected; keeps reads in bounds
+    // this workgroup's entries [lo, hi): the whole list, or one chunk of a split one
+    const uint32_t cpo = cpoff[tid_g];
+    const uint32_t n_ch = rg.y > rg.x ? chunks_of(rg.y - rg.x) : 1u;
+    const bool split = cpo != kNoSplit && n_ch <= kMaxChunks;
+    uint32_t lo = rg.x, hi = rg.y;
+    if (split) {
+        lo = rg.x + chunk * kChunkEntries < rg.y ? rg.x + chunk * kChunkEntries : rg.y;
+        hi = lo + kChunkEntries < rg.y ? lo + kChunkEntries : rg.y;
+    } else if (chunk != 0u) {
+        lo = hi = rg.y;   // never expected: only split lists have chunks past the first
+    }
+    // a chunk before the last starts from the forward's state at hi (W: the
+    // colour behind, weighted by dL/d(channel), per unit of T)
+    float W = 0.f;
+    if (split && hi < rg.y && inside) {
+        const int nsub = (vt->tile_w / kBlk) * (vt->tile_h / kBlk);
+        const float *c = cp + cp_index(cpo + chunk, nsub, (int)wave, 0, lane);
+        const float Tb = c[0];
+        const float b0 = st.rgb[3 * V.pix_off + pix] - c[64];
+        const float b1 = st.rgb[3 * V.pix_off + P + pix] - c[128];
+        const float b2 = st.rgb[3 * V.pix_off + 2 * P + pix] - c[192];
+        const float bd = st.depth[gp] - c[256];
+        const float bs = st.sil[gp] - c[320];
+        W = (g[0] * b0 + g[1] * b1 + g[2] * b2 + g[3] * bd + g[4] * bs) / Tb;
+        T = Tb;
+    }
     const uint32_t wmax = wave_max_u32(last);
     if (lane == 0) s_wmax[wave] = wmax;
     __syncthreads();
-    if (FUSED && threadIdx.x == 0) {   // the tile's loss: its waves in a fixed order
+    if (FUSED && threadIdx.x == 0 && chunk == 0u) {   // the tile's loss: its waves in a fixed order
         double t = 0.0;
         for (int w = 0; w < nw; ++w) t += s_loss[w];
         L.loss_tile[tid_g] = t;
     }
     uint32_t bmax = rg.x;
     for (int w = 0; w < nw; ++w) bmax = s_wmax[w] > bmax ? s_wmax[w] : bmax;
+    const uint32_t top = bmax < lo ? lo : (bmax > hi ? hi : bmax);   // the walk starts here
     // The gradient row of entry e: records own the rows [poff, poff + tiles)
     // of their tile rectangles, row-major, so the slot follows from the
     // record and this tile's place in its rectangle (~0u: not a valid entry).
@@ -416,7 +490,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
         return j < n_pair ? j : ~0u;
     };
     // entries behind every pixel's last contributor get zero rows
-    for (uint32_t e = bmax + threadIdx.x; e < rg.y; e += blockDim.x) {
+    for (uint32_t e = top + threadIdx.x; e < hi; e += blockDim.x) {
         const uint32_t j = row_of(e);
         if (j == ~0u) continue;
         float *dst = grad_pairs + NV * (size_t)j;
@@ -424,7 +498,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
         for (int c = 0; c < NV; ++c) dst[c] = 0.0f;
     }
 
-    float W = 0.f;   // sum over the channels of dL/d(channel) x (channel behind the current entry)
+    // W: sum over the channels of dL/d(channel) x (channel behind the current entry)
     uint32_t n_eval = 0, n_contrib = 0, n_red = 0;
     float *acc = &s_acc[wave][0];
     float *qs = &s_q[wave][0];
@@ -444,16 +518,16 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     };
-    for (uint32_t seg_hi = bmax; seg_hi > rg.x;) {
-        const uint32_t seg_lo = seg_hi - rg.x > (uint32_t)kSeg ? seg_hi - kSeg : rg.x;
+    for (uint32_t seg_hi = top; seg_hi > lo;) {
+        const uint32_t seg_lo = seg_hi - lo > (uint32_t)kSeg ? seg_hi - kSeg : lo;
         for (int c = lane; c < kSeg * NV; c += 64) acc[c] = 0.0f;
         if (threadIdx.x < seg_hi - seg_lo) s_j[threadIdx.x] = row_of(seg_lo + threadIdx.x);   // read after the barrier
         if (wmax > seg_lo) {   // wave-uniform: this wave has pixels with entries in the segment
-            const uint32_t hi = wmax < seg_hi ? wmax : seg_hi;
+            const uint32_t w_hi = wmax < seg_hi ? wmax : seg_hi;   // this wave's last entry + 1 in the segment
             const uint32_t e = seg_lo + lane;
             bool keep = false;
             uint32_t s = 0;
-            if (lane < (uint32_t)kSeg && e < hi && pair_rec[e] < n_rec) {
+            if (lane < (uint32_t)kSeg && e < w_hi && pair_rec[e] < n_rec) {
                 s = pair_rec[e];
                 keep = block_may_contribute(rec[3 * (size_t)s], rec[3 * (size_t)s + 1], (float)bx0, (float)by0);
             }
