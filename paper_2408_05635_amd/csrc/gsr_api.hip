@@ -276,7 +276,8 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
         // only when the tiles leave resident workgroups idle: with more, the
         // heaviest-first order already balances the backward
         L.cp_slots = L.T <= kSplitMaxTiles
-                         ? std::min<int64_t>(kcap / kChunkEntries + 1, (int64_t)(kCpBudgetBytes / slot_bytes))
+                         ? std::min<int64_t>(std::min<int64_t>(kcap / kChunkEntries + 1, L.T),
+                                             (int64_t)(kCpBudgetBytes / slot_bytes))
                          : 0;
         L.work_cap = L.T + L.cp_slots;
         L.work = take(4 * (size_t)L.work_cap);

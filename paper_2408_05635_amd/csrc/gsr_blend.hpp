@@ -37,8 +37,8 @@ struct BlockPos {
 // the five channel sums over the entries before b; a chunk starts its walk
 // from there (T = T_b, and the colour behind = final image - sums, per unit
 // of T_b), which is the state the full walk would reach at b.
-constexpr uint32_t kChunkEntries = 256;   // a multiple of 64: the forward's staging rounds meet every boundary
-constexpr uint32_t kSplitMin = 384;
+constexpr uint32_t kChunkEntries = 128;   // a multiple of 64: the forward's staging rounds meet every boundary
+constexpr uint32_t kSplitMin = 192;
 constexpr uint32_t kMaxChunks = 256;      // chunk index in the top 8 bits of a work item
 constexpr uint32_t kNoSplit = 0xffffffffu;
 constexpr int kCpValues = 6;              // T, r, g, b, depth, silhouette
