@@ -254,7 +254,9 @@ gsr_status gsr_read_counters(gsr_ctx *ctx, gsr_workspace ws, void *stream, int64
  * `stream`): work[0] (pixel, entry) alpha evaluations in the forward blend,
  * work[1] contributions (alpha >= 1/255, before termination) in the forward,
  * work[2], work[3] the same in the backward blend, work[4] (wave, entry)
- * gradient reductions in the backward.  Host array of 5. */
+ * gradient reductions in the backward, work[5] the backward's work items (one
+ * per tile, plus one per extra chunk of a list split across workgroups; set
+ * by every call).  Host array of 6. */
 gsr_status gsr_read_work(gsr_ctx *ctx, gsr_workspace ws, void *stream, int64_t *work);
 
 /* Per-stage timing with HIP events: while enabled, every call brackets each

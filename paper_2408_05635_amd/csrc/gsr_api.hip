@@ -522,7 +522,8 @@ constexpr uint32_t kOrderBuckets = 256;
 __global__ __launch_bounds__(kOrderThreads) void k_work_order(const uint2 *__restrict__ ranges, int64_t n_tiles,
                                                               int64_t slots_cap, uint32_t *__restrict__ torder,
                                                               uint32_t *__restrict__ cpoff, uint32_t *__restrict__ work,
-                                                              int64_t *__restrict__ n_work) {
+                                                              int64_t *__restrict__ n_work,
+                                                              int64_t *__restrict__ counters) {
     __shared__ uint32_t s_h[kOrderBuckets];
     __shared__ int64_t s_run;
     const int t = threadIdx.x;
@@ -557,7 +558,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_work_order(const uint2 *__res
         if (slots_cap == 0) cpoff[i] = kNoSplit;
     }
     if (slots_cap == 0) {
-        if (t == 0) *n_work = n_tiles;
+        if (t == 0) *n_work = counters[kCntWorkItems] = n_tiles;
         return;
     }
     __syncthreads();
@@ -594,7 +595,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_work_order(const uint2 *__res
     }
     __syncthreads();
     const uint32_t total = bucket_starts();
-    if (t == 0) *n_work = total;
+    if (t == 0) *n_work = counters[kCntWorkItems] = total;
     for (int64_t i = t; i < n_tiles; i += kOrderThreads) {
         const uint32_t len = len_of(i);
         const bool split = cpoff[i] != kNoSplit;
@@ -1058,7 +1059,7 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     if (L.T > 0)
         hipLaunchKernelGGL(k_work_order, dim3(1), dim3(kOrderThreads), 0, st, (const uint2 *)ranges, L.T, L.cp_slots,
                            at<uint32_t>(ws, L.torder), at<uint32_t>(ws, L.cpoff), at<uint32_t>(ws, L.work),
-                           at<int64_t>(ws, L.nwork));
+                           at<int64_t>(ws, L.nwork), counters);
 }
 
 // record index of every sorted pair (the sort's result buffer is fixed by the key bits)
@@ -1603,6 +1604,7 @@ gsr_status gsr_read_work(gsr_ctx *ctx, gsr_workspace ws, void *stream, int64_t *
     s = check_hip(ctx, hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
     if (s != GSR_OK) return s;
     for (int k = 0; k < 5; ++k) work[k] = h[kCntEvalFwd + k];
+    work[5] = h[kCntWorkItems];
     return GSR_OK;
 }
 

@@ -52,6 +52,7 @@ enum Counter {
     kCntEvalBwd = 10,
     kCntContribBwd = 11,
     kCntReduceBwd = 12,
+    kCntWorkItems = 13,  // the backward's work items (tiles, or chunks of split lists)
     kNumCounters = 16
 };
 

@@ -203,9 +203,10 @@ class Rasterizer:
         """Work counters of the last GSR_COUNT_WORK call (synchronises)."""
         if ws is None:
             ws = _abi.Workspace(self._ws.data_ptr(), self._ws.numel(), self.pair_capacity)
-        arr = (C.c_int64 * 5)()
+        arr = (C.c_int64 * 6)()
         _abi.check(_ABI.gsr_read_work(self._ctx, ws, _stream_ptr(), arr), self._ctx)
-        return dict(eval_fwd=arr[0], contrib_fwd=arr[1], eval_bwd=arr[2], contrib_bwd=arr[3], reduce_bwd=arr[4])
+        return dict(eval_fwd=arr[0], contrib_fwd=arr[1], eval_bwd=arr[2], contrib_bwd=arr[3], reduce_bwd=arr[4],
+                    work_items=arr[5])
 
     def set_timing(self, on: bool) -> None:
         _abi.check(_ABI.gsr_set_timing(self._ctx, int(bool(on))), self._ctx)

@@ -177,3 +177,35 @@ def test_pixel_hash_only_on_request(rast):
     assert torch.equal(on[3], again[3])
     for k in (0, 1, 2, 4):   # images and last contributors do not depend on the flag
         assert torch.equal(off[k], on[k]), k
+
+
+def test_long_lists_walked_in_chunks_only_when_tiles_are_few(rast):
+    """One 640x480 view of the room has 1 200 tiles, fewer than the backward
+    keeps resident, so its lists over 192 entries are walked in 128-entry
+    chunks by separate workgroups (more work items than tiles); with two views
+    (2 400 tiles) the items are the tiles.  The oracle checks the chunked path
+    on this view in test_config2_full_view_parity; here the view's pose
+    gradients from the chunked call match those of the two-view call, whose
+    backward walks every list whole."""
+    from paper_2408_05635_amd.raster import RenderOptions
+    w = scenes.config2(n_views=2)
+    g = dev_params(w.gaussians)
+    q, t = dev_poses(w.views)
+    cams = w.views.cams
+    tg = to_dev(oracle_targets(w))
+    P = cams[0].width * cams[0].height
+    o = RenderOptions(tile=(16, 16), count_work=True, **w.weights)
+    tiles1 = ((cams[0].width + 15) // 16) * ((cams[0].height + 15) // 16)
+    one = rast.render_loss_grad(g, q[:1], t[:1], cams[:1], {k: v[:(3 * P if k == "rgb" else P)] for k, v in tg.items()},
+                                o)
+    items1 = rast.read_work()["work_items"]
+    two = rast.render_loss_grad(g, q, t, cams, tg, o)
+    items2 = rast.read_work()["work_items"]
+    torch.cuda.synchronize()
+    assert items1 > tiles1, (items1, tiles1)
+    assert items2 == 2 * tiles1, (items2, 2 * tiles1)
+    for key in ("dq_t", "dt", "dq_c", "dc"):
+        a = one[key][0].double().cpu()
+        b = two[key][0].double().cpu()
+        err = float((a - b).abs().max() / max(float(b.abs().max()), 1e-30))
+        assert err <= GRAD_TOL, (key, err)
