@@ -113,17 +113,23 @@ __device__ __forceinline__ bool block_may_contribute(const float4 A, const float
 
 // alpha of one record at one pixel; identical instruction sequence in the
 // forward and the backward kernels (explicit fma, no contraction), so both
-// take the same decisions.
+// take the same decisions.  The record enters through its offset from the
+// 8x8 block's origin, d0 = (bx0 - mx, by0 - my), formed once per (block,
+// entry) by block_offset; the pixel adds its place (jx, jy) in the block.
 struct AlphaEval {
     float dx, dy, u, w, G, alpha;
     bool clamped;
 };
 
-__device__ __forceinline__ AlphaEval eval_alpha(const float4 A, const float4 B, float px, float py) {
+__device__ __forceinline__ float2 block_offset(const float4 A, float bx0, float by0) {
+    return make_float2(__fsub_rn(__fsub_rn(bx0, A.x), A.z), __fsub_rn(__fsub_rn(by0, A.y), A.w));
+}
+
+__device__ __forceinline__ AlphaEval eval_alpha(const float2 d0, const float4 B, float jx, float jy) {
 #pragma clang fp contract(off)
     AlphaEval e;
-    e.dx = __fsub_rn(__fsub_rn(px, A.x), A.z);
-    e.dy = __fsub_rn(__fsub_rn(py, A.y), A.w);
+    e.dx = __fadd_rn(d0.x, jx);
+    e.dy = __fadd_rn(d0.y, jy);
     e.u = __builtin_fmaf(B.y, e.dy, __fmul_rn(B.x, e.dx));
     e.w = __fmul_rn(B.z, e.dy);
     const float p2 = -__builtin_fmaf(e.u, e.u, __fmul_rn(e.w, e.w));
@@ -149,7 +155,9 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
                                                   const uint32_t *__restrict__ torder,
                                                   const uint32_t *__restrict__ cpoff, float *__restrict__ cp,
                                                   int64_t *__restrict__ counters, BlendOut out) {
-    __shared__ float4 s_a[64], s_b[64], s_c[64];
+    // staged entries: offset from the block origin (x, y; float4-strided like
+    // the others, so that one base address serves all three), B and C
+    __shared__ float4 s_d[64], s_b[64], s_c[64];
     __shared__ uint32_t s_pos[64], s_rec_id[64];
     const BlockPos bp = locate_block(vt, torder);
     if (!bp.valid) return;
@@ -157,7 +165,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
     const uint32_t lane = threadIdx.x;
     const int px = bp.bx0 + (int)(lane & 7u), py = bp.by0 + (int)(lane >> 3);
     const bool inside = px < V.W && py < V.H;
-    const float fpx = (float)px, fpy = (float)py;
+    const float fjx = (float)(lane & 7u), fjy = (float)(lane >> 3);   // the pixel's place in its block
     uint2 rg = ranges[V.tile_off + bp.tile];
     const uint32_t n_rec = (uint32_t)counters[kCntVisible];
     const uint32_t n_pair = (uint32_t)counters[kCntPairsUsed];
@@ -198,7 +206,8 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
         const uint64_t m = ballot(keep);
         if (keep) {
             const uint32_t slot = rank_below(m);
-            s_a[slot] = A;
+            const float2 d0 = block_offset(A, (float)bp.bx0, (float)bp.by0);
+            s_d[slot] = make_float4(d0.x, d0.y, 0.0f, 0.0f);
             s_b[slot] = B;
             s_c[slot] = C;
             s_pos[slot] = e;
@@ -213,7 +222,8 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
         // not reach, takes weight 0, which leaves its sums exactly as they
         // were (fma(0, c, x) = x), so the updates need no branches.
         auto entry = [&](int k) {
-            const AlphaEval ev = eval_alpha(s_a[k], s_b[k], fpx, fpy);
+            const float4 d4 = s_d[k];
+            const AlphaEval ev = eval_alpha(make_float2(d4.x, d4.y), s_b[k], fjx, fjy);
             if (COUNT) n_eval += done ? 0u : 1u;
             const bool hit = !done && ev.alpha >= kAlphaMin;
             const float Tn = T * (1.0f - ev.alpha);
@@ -240,9 +250,13 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
         // groups of 8 entries (LDS addresses as immediate offsets), then the
         // wave checks whether any of its pixels is still open
         for (int k0 = 0; k0 < n; k0 += 8) {
+            // the group's first slot held in a vector register, so the
+            // entries' staging reads take one base and immediate offsets
+            int vk = k0;
+            asm volatile("" : "+v"(vk));
 #pragma unroll
             for (int j = 0; j < 8; ++j)
-                if (k0 + j < n) entry(k0 + j);
+                if (k0 + j < n) entry(vk + j);
             if (ballot(!done) == 0) break;
         }
         if (lastk >= 0) last = s_pos[lastk] + 1u;
@@ -357,6 +371,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
     __shared__ float s_acc[kBwdMaxWaves][kSeg * NV];
     __shared__ uint32_t s_wmax[kBwdMaxWaves];
     __shared__ uint32_t s_j[kSeg];   // gradient-row slot of each entry of the segment
+    __shared__ float2 s_d[kBwdMaxWaves][kSeg];   // per wave: the segment's entries' offsets from the block origin
     __shared__ double s_loss[kBwdMaxWaves];
 
     // work item of this workgroup: the i-th (tile, chunk) of the order, longest
@@ -380,7 +395,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
     const int by0 = ty * vt->tile_h + (int)(wave / sx) * kBlk;
     const int px = bx0 + (int)(lane & 7u), py = by0 + (int)(lane >> 3);
     const bool inside = px < V.W && py < V.H;
-    const float fpx = (float)px, fpy = (float)py;
+    const float fjx = (float)(lane & 7u), fjy = (float)(lane >> 3);   // the pixel's place in its block
     const int64_t P = (int64_t)V.W * V.H;
     const int64_t pix = (int64_t)py * V.W + px;
     const int64_t gp = V.pix_off + pix;
@@ -529,8 +544,12 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
             uint32_t s = 0;
             if (lane < (uint32_t)kSeg && e < w_hi && pair_rec[e] < n_rec) {
                 s = pair_rec[e];
-                keep = block_may_contribute(rec[3 * (size_t)s], rec[3 * (size_t)s + 1], (float)bx0, (float)by0);
+                const float4 A = rec[3 * (size_t)s];
+                keep = block_may_contribute(A, rec[3 * (size_t)s + 1], (float)bx0, (float)by0);
+                s_d[wave][lane] = block_offset(A, (float)bx0, (float)by0);
             }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // the offsets before the entries read them
+            __builtin_amdgcn_wave_barrier();
             // survivors in reverse list order: the lanes of the set bits of mm, highest first;
             // an entry's record is read at a wave-uniform address (scalar loads)
             uint64_t mm = ballot(keep);
@@ -541,10 +560,10 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
                 const bool act = pos < last;
                 const uint64_t m_act = ballot(act);
                 if (m_act == 0) return;   // wave-uniform
-                const float4 a = rec[3 * (size_t)rs], b = rec[3 * (size_t)rs + 1];
+                const float4 b = rec[3 * (size_t)rs + 1];
                 // every lane evaluates (the wave pays for it either way); the
                 // decisions and the state updates are selects, not branches
-                const AlphaEval ev = eval_alpha(a, b, fpx, fpy);
+                const AlphaEval ev = eval_alpha(s_d[wave][src], b, fjx, fjy);
                 const bool reach = ev.alpha >= kAlphaMin;
                 const bool contrib = act && reach;
                 if (COUNT) n_eval += act ? 1u : 0u;
