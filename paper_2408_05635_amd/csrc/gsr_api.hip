@@ -94,7 +94,7 @@ constexpr size_t kAlign = 256;
 constexpr int kRecGrad = 14;   // per-record parameter gradient: mu 3, q 4, log_s 3, logit 1, rgb 3
 constexpr size_t kCpBudgetBytes = 96u << 20;   // checkpoints of split lists (the longest lists get them first)
 constexpr int64_t kSplitMaxTiles = 2048;       // about the backward workgroups resident at once
-constexpr int kRecBwdMaxBlocks = 2048;   // grid cap of the record backward (one pose row per block)
+constexpr int kRecBwdMaxBlocks = 1024;   // grid cap of the record backward (one pose row per block)
 constexpr int kEmitChunk = 1024;         // pairs per emission block
 // synchronisation region, cleared by every call: scan tickets (256 B) and the
 // scans' look-back words
