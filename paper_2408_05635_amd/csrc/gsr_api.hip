@@ -4,18 +4,20 @@
 // scan and radix sort in gsr_scan_sort.hpp.
 //
 // Launch sequence of one call (all views at once, no host synchronisation):
-//   setup         view table and FP64 pose matrices into the workspace
-//   project_count per Gaussian, per view: visibility, depth key, tiles touched
-//   compact       scan of visibility -> (depth key, view*N+i) of visible records
-//   depth sort    stable radix sort on the float32 depth bits
+//   setup+project view table, FP64 poses, cleared counters; per Gaussian, per
+//                 view: visibility, depth key, tiles touched
+//   depth sort    stable radix sort of the visible records on the float32
+//                 depth bits; its first pass also compacts them
 //   gather        per visible record in depth order: full projection -> record
-//   emit          scan of tiles touched -> (global tile id, record) pairs
+//   offsets       scan of tiles touched; emit -> (global tile id, record) pairs
 //   tile sort     stable radix sort on the tile id: per-tile lists in depth order
 //   ranges        [start, end) of every tile's list
+//   work order    tiles heaviest first; with few tiles, long lists in chunks
 //   blend_fwd     compositing (eqs. 2-4)
-//   blend_bwd     loss + reverse compositing -> per-record 2D gradients
-//   project_bwd   chain rule to the raw parameters; pose partials per view
-//   pose_final    (q, t) and decoupled (q | C fixed, C) pose gradients
+//   blend_bwd     loss + reverse compositing -> per-pair 2D gradient rows
+//   record_bwd    chain rule to the raw parameters; pose partials per block
+//   finalize      per view (q, t) and decoupled (q | C fixed, C) pose gradients
+//                 and the loss; per Gaussian the sum over views
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -1,7 +1,8 @@
 // Front-to-back alpha compositing of RGB (eq. 2), depth (eq. 3) and
 // silhouette (eq. 4), and its reverse-order backward.
 //
-// Work decomposition: one wave64 workgroup per 8x8 pixel block, one pixel per
+// Work decomposition: one wave64 workgroup per 8x8 pixel block in the
+// forward, one wave per 8x8 block of a tile in the backward, one pixel per
 // lane.  A block reads the depth-sorted list of the binning tile it lies in,
 // 64 entries at a time: each lane fetches one record and tests exactly whether
 // the record's alpha >= 1/255 ellipse can reach the 8x8 block (with a safety
@@ -11,7 +12,7 @@
 // state untouched; it only removes work.
 //
 // Record layout (3 x float4 per visible (view, Gaussian), depth-sorted):
-//   A = (mx_hi, my_hi, mx_lo, my_lo)   mean, split so that px - mx is exact
+//   A = (mx_hi, my_hi, mx_lo, my_lo)   mean as an FP32 pair (mx = hi + lo)
 //   B = (l11, l21, l22, o)             scaled conic factor and opacity
 //   C = (r, g, b, z)                   colour and camera depth
 #pragma once
@@ -295,15 +296,15 @@ struct LossIn {
 
 __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.0f) - (x < 0.0f)); }
 
-// Backward blend.  One workgroup per binning tile, one wave per 8x8 block of
-// it (tiles are at most 16x16, so at most four waves).  The tile's list is
-// walked in reverse, from the last contributor of any pixel of the tile, in
-// segments of kSeg entries; within a segment every wave culls the entries
-// against its own block (one lane per entry), then takes the survivors one
-// by one, reading each one's record at a wave-uniform address (scalar loads,
-// no LDS staging), and sums each entry's partial derivatives over its 64
-// pixels (DPP quad sums, then a batched column sum in LDS) into its own LDS
-// slots.
+// Backward blend.  One workgroup per work item, a binning tile or one chunk
+// of a split list, one wave per 8x8 block of the tile (tiles are at most
+// 16x16, so at most four waves).  The item's entries are walked in reverse,
+// from the last contributor of any pixel of the tile, in segments of kSeg
+// entries; within a segment every wave culls the entries against its own
+// block (one lane per entry), then takes the survivors one by one, reading
+// each one's record at a wave-uniform address (scalar loads, no LDS staging),
+// and sums each entry's partial derivatives over its 64 pixels (DPP quad
+// sums, then a batched column sum in LDS) into its own LDS slots.
 // At the end of the segment the waves' slots are added in a fixed order and
 // written, without atomics, to the pair's own row of `grad_pairs`: record s
 // owns the rows [poff[s], poff[s] + tiles of s), one per tile of its
