@@ -243,7 +243,7 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     for (int v = 0; v < V; ++v) L.P += (int64_t)vt.v[v].W * vt.v[v].H;
     L.T = vt.total_tiles;
     L.G = vt.total_blocks;
-    L.tile_bits = bits_for(L.T);
+    L.tile_bits = std::max(bits_for(L.T), 1);   // at least one pass: its scatter records the tile ranges
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -345,8 +345,9 @@ __global__ __launch_bounds__(256) void k_setup_project(ViewTable tab, ViewTable 
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = gtid; k < sync16; k += gstride) sync[k] = make_uint4(0u, 0u, 0u, 0u);
-    // every tile's range starts empty; k_ranges sets those of the tiles with pairs
-    for (int64_t k = gtid; k < n_tiles; k += gstride) ranges[k] = make_uint2(0u, 0u);
+    // every tile's range starts empty, (0xffffffff, 0); the tile sort's last
+    // pass narrows those of the tiles with pairs
+    for (int64_t k = gtid; k < n_tiles; k += gstride) ranges[k] = make_uint2(0xffffffffu, 0u);
     const int t = threadIdx.x;
     if (blockIdx.x == 0) {
         const int words = (int)(sizeof(ViewTable) / 4);
@@ -493,21 +494,6 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t val) {
 __global__ void k_fill_f64(double *p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0.0;
-}
-
-// [start, end) of every tile with pairs, from the sorted keys: a pair whose
-// key differs from its predecessor's starts its tile's run, one whose key
-// differs from its successor's ends it.  the set-up gave every tile an empty
-// range beforehand.
-__global__ void k_ranges(const uint32_t *__restrict__ keys, const int64_t *__restrict__ counters,
-                         uint2 *__restrict__ ranges, int64_t n_tiles) {
-    const int64_t K = counters[kCntPairsUsed];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t k = keys[i];
-        if ((int64_t)k >= n_tiles) continue;   // never expected; keeps writes in bounds
-        if (i == 0 || keys[i - 1] != k) ranges[k].x = (uint32_t)i;
-        if (i == K - 1 || keys[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
-    }
 }
 
 // Heaviest work first.  (1) torder: a permutation of the tiles by decreasing
@@ -932,6 +918,15 @@ __global__ void k_debug_copy_u32(const uint32_t *src, const int64_t *counters, i
         dst[i] = src[i];
 }
 
+// Tile ranges as [start, end), an empty one as (0, 0) (in the workspace it is
+// (0xffffffff, 0), see the set-up).
+__global__ void k_debug_ranges(const uint2 *__restrict__ src, int64_t n, uint2 *__restrict__ dst) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint2 r = src[i];
+        dst[i] = r.x < r.y ? r : make_uint2(0u, 0u);
+    }
+}
+
 // Wave-primitive self test: 0 failures expected.
 __global__ void k_selftest(int *fail) {
     const uint32_t lane = threadIdx.x;
@@ -1053,11 +1048,10 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     if (L.vn > 0 && L.kcap > 0)
         hipLaunchKernelGGL(k_emit, dim3((unsigned)n_chunks), dim3(256), 0, st, counters, poff,
                            (const uint32_t *)chunk_first, trect, gid_sorted, vt, c.pp.n, pk0, pv0);
-    // tile order (stable: depth order within a tile); the values are the pairs' records
-    const bool p_in1 = radix_sort(pk0, pv0, pk1, pv1, counters + kCntPairsUsed, L.kcap, L.tile_bits, so, st);
+    // tile order (stable: depth order within a tile); the values are the
+    // pairs' records; the last pass also sets every tile's [start, end)
     uint2 *ranges = at<uint2>(ws, L.ranges);
-    hipLaunchKernelGGL(k_ranges, dim3(grid_for(L.kcap, 256, 4096)), dim3(256), 0, st, p_in1 ? pk1 : pk0,
-                       (const int64_t *)counters, ranges, L.T);
+    radix_sort(pk0, pv0, pk1, pv1, counters + kCntPairsUsed, L.kcap, L.tile_bits, so, st, ranges, L.T);
     if (L.T > 0)
         hipLaunchKernelGGL(k_work_order, dim3(1), dim3(kOrderThreads), 0, st, (const uint2 *)ranges, L.T, L.cp_slots,
                            at<uint32_t>(ws, L.torder), at<uint32_t>(ws, L.cpoff), at<uint32_t>(ws, L.work),
@@ -1660,8 +1654,8 @@ gsr_status gsr_debug_binning(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_vie
                        dim3(256), 0, c.st, counters,
                        depth_sorted_gid(c), at<float4>(ws, L.rec), at<uint2>(ws, L.trect), max_rec, rec_gid, rec_xy,
                        rec_radius, rec_z, c.pp, at<ViewTable>(ws, L.views), at<PoseF64>(ws, L.poses));
-    hipLaunchKernelGGL(k_debug_copy_u32, dim3(grid_for(2 * L.T, 256, 4096)), dim3(256), 0, c.st,
-                       at<uint32_t>(ws, L.ranges), counters, -1, 2 * max_tiles, ranges, 2 * L.T);
+    hipLaunchKernelGGL(k_debug_ranges, dim3(grid_for(L.T, 256, 4096)), dim3(256), 0, c.st, at<uint2>(ws, L.ranges),
+                       std::min<int64_t>(L.T, max_tiles), reinterpret_cast<uint2 *>(ranges));
     hipLaunchKernelGGL(k_debug_copy_u32, dim3(grid_for(L.kcap, 256, 4096)), dim3(256), 0, c.st, pair_values(c),
                        counters, (int)kCntPairsUsed, max_pairs, pair_rec, (int64_t)0);
     return finish(c, "gsr_debug_binning launch");

@@ -344,11 +344,18 @@ __global__ __launch_bounds__(kScanThreads) void k_digit_scan(const int64_t *n_de
 // run, in input order), then places them in LDS in digit order and writes
 // each digit's run to consecutive global positions, so that the stores are
 // coalesced runs instead of one transaction per item.
+// ranges (the last pass only, else null): every key's [first, last + 1)
+// position in the output, for keys < n_keys.  Within a block's run of one
+// digit the items are in final order, so a key's first and last positions are
+// where its LDS neighbours differ, or at the ends of a run, where the adjacent
+// block may hold the same key: atomicMin / atomicMax over the candidates
+// (ranges start as (0xffffffff, 0)) give the exact bounds in any order.
 template <int ITEMS, class In>
 __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(In in, uint32_t *__restrict__ kout,
                                                                 uint32_t *__restrict__ vout, const int64_t *n_dev,
                                                                 int64_t n_host, int shift, int dbits, SortState so,
-                                                                int64_t nb_cap) {
+                                                                int64_t nb_cap, uint2 *__restrict__ ranges,
+                                                                int64_t n_keys) {
     constexpr int kItems = kScanThreads * ITEMS;
     constexpr int kWaves = kScanThreads / 64;
     __shared__ uint32_t s_goff[256];   // global position of the block's first item of each digit
@@ -436,6 +443,11 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(In in, uint32_t 
         if ((int64_t)pos < n) {   // always true for consistent counts; keeps writes in bounds
             kout[pos] = key;
             vout[pos] = s_v[i];
+            if (ranges && (int64_t)key < n_keys) {   // block-uniform choice
+                const uint32_t run0 = s_cnt[d], run1 = d + 1u < 256u ? s_cnt[d + 1] : tot;
+                if ((uint32_t)i == run0 || s_k[i - 1] != key) atomicMin(&ranges[key].x, pos);
+                if ((uint32_t)i + 1u == run1 || s_k[i + 1] != key) atomicMax(&ranges[key].y, pos + 1u);
+            }
         }
     }
 }
@@ -443,7 +455,8 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scatter(In in, uint32_t 
 // One pass: items of `in` -> (ko, vo) by key bits [shift, shift + dbits).
 template <class In>
 inline void radix_pass(In in, uint32_t *ko, uint32_t *vo, const int64_t *n_dev, int64_t n_host, int64_t cap,
-                       int shift, int dbits, const SortState &so, int64_t *total_out, hipStream_t st) {
+                       int shift, int dbits, const SortState &so, int64_t *total_out, hipStream_t st,
+                       uint2 *ranges = nullptr, int64_t n_keys = 0) {
     const int64_t nb = sort_blocks(cap);
     const bool small = sort_items(cap) == 4;
     hipLaunchKernelGGL((small ? k_radix_count<4, In> : k_radix_count<16, In>), dim3((unsigned)nb), dim3(kScanThreads), 0,
@@ -451,19 +464,21 @@ inline void radix_pass(In in, uint32_t *ko, uint32_t *vo, const int64_t *n_dev, 
     hipLaunchKernelGGL(small ? k_digit_scan<4> : k_digit_scan<16>, dim3(256), dim3(kScanThreads), 0, st, n_dev, n_host,
                        dbits, so, nb, total_out);
     hipLaunchKernelGGL((small ? k_radix_scatter<4, In> : k_radix_scatter<16, In>), dim3((unsigned)nb),
-                       dim3(kScanThreads), 0, st, in, ko, vo, n_dev, n_host, shift, dbits, so, nb);
+                       dim3(kScanThreads), 0, st, in, ko, vo, n_dev, n_host, shift, dbits, so, nb, ranges, n_keys);
 }
 
 // Sorts n (device count, <= cap) pairs by key bits [0, bits).  Returns true
-// if the result is in (k1, v1), false if in (k0, v0).
+// if the result is in (k1, v1), false if in (k0, v0).  With ranges, the last
+// pass also records every key's [start, end) (see k_radix_scatter).
 inline bool radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const int64_t *n_dev, int64_t cap,
-                       int bits, const SortState &so, hipStream_t st) {
+                       int bits, const SortState &so, hipStream_t st, uint2 *ranges = nullptr, int64_t n_keys = 0) {
     if (sort_blocks(cap) == 0 || bits <= 0) return false;
     bool in1 = false;
     for (int shift = 0; shift < bits; shift += 8) {
         const int dbits = bits - shift < 8 ? bits - shift : 8;
+        const bool last = shift + 8 >= bits;
         radix_pass(PairIn{in1 ? k1 : k0, in1 ? v1 : v0}, in1 ? k0 : k1, in1 ? v0 : v1, n_dev, cap, cap, shift, dbits,
-                   so, nullptr, st);
+                   so, nullptr, st, last ? ranges : nullptr, n_keys);
         in1 = !in1;
     }
     return in1;
