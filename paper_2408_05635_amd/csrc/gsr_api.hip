@@ -10,8 +10,8 @@
 //                 depth bits; its first pass also compacts them
 //   gather        per visible record in depth order: full projection -> record
 //   offsets       scan of tiles touched; emit -> (global tile id, record) pairs
-//   tile sort     stable radix sort on the tile id: per-tile lists in depth order
-//   ranges        [start, end) of every tile's list
+//   tile sort     stable radix sort on the tile id: per-tile lists in depth
+//                 order; its last pass also records every tile's [start, end)
 //   work order    tiles heaviest first; with few tiles, long lists in chunks
 //   blend_fwd     compositing (eqs. 2-4)
 //   blend_bwd     loss + reverse compositing -> per-pair 2D gradient rows
