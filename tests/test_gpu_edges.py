@@ -196,9 +196,15 @@ def test_long_lists_walked_in_chunks_only_when_tiles_are_few(rast):
     P = cams[0].width * cams[0].height
     o = RenderOptions(tile=(16, 16), count_work=True, **w.weights)
     tiles1 = ((cams[0].width + 15) // 16) * ((cams[0].height + 15) // 16)
-    one = rast.render_loss_grad(g, q[:1], t[:1], cams[:1], {k: v[:(3 * P if k == "rgb" else P)] for k, v in tg.items()},
-                                o)
+    tg1 = {k: v[:(3 * P if k == "rgb" else P)] for k, v in tg.items()}
+    one = rast.render_loss_grad(g, q[:1], t[:1], cams[:1], tg1, o)
     items1 = rast.read_work()["work_items"]
+    one = {k: (v.clone() if isinstance(v, torch.Tensor) else v) for k, v in one.items()}
+    again = rast.render_loss_grad(g, q[:1], t[:1], cams[:1], tg1, o)   # the chunks add up in a fixed order
+    torch.cuda.synchronize()
+    for key, val in one.items():
+        if isinstance(val, torch.Tensor):
+            assert torch.equal(val, again[key]), key
     two = rast.render_loss_grad(g, q, t, cams, tg, o)
     items2 = rast.read_work()["work_items"]
     torch.cuda.synchronize()
