@@ -76,6 +76,15 @@ typedef struct {
     double *g_q_t, *g_t, *g_q_c, *g_c;     /* [V,4],[V,3],[V,4],[V,3] */
     uint64_t *decision_hash;               /* [V] */
     double *grad2d;                        /* optional [V,N,10] */
+    /* the two kinds of ambiguity, per pixel (NULL = not wanted):
+     *   decision_amb: an alpha, clamp or transmittance decision within the
+     *     margin of its threshold, so the image itself may differ between
+     *     precisions;
+     *   residual_amb: the sign of a weighted L1 residual, or the tracking
+     *     mask [S > thresh], within its margin: the image is well defined
+     *     there, only the loss derivative's sign may differ.
+     * `ambiguous` is their union. */
+    uint8_t *decision_amb, *residual_amb;
 } or_out;
 
 /* per (view, Gaussian) projection */
@@ -300,6 +309,8 @@ int oracle_run(const or_in *in, or_out *out) {
                     if (out->t_final) out->t_final[off + p] = 1.0;
                     if (out->n_contrib) out->n_contrib[off + p] = 0;
                     if (out->ambiguous) out->ambiguous[off + p] = 0;
+                    if (out->decision_amb) out->decision_amb[off + p] = 0;
+                    if (out->residual_amb) out->residual_amb[off + p] = 0;
                 }
                 if (out->loss) out->loss[v] = 0.0;
                 if (out->decision_hash) out->decision_hash[v] = 0;
@@ -378,7 +389,8 @@ int oracle_run(const or_in *in, or_out *out) {
                     const int64_t gp = off + pix;
                     double acc[5] = {0, 0, 0, 0, 0};  /* r, g, b, depth, silhouette */
                     double T = 1.0;
-                    int amb = 0;
+                    int amb = 0;     /* decisions of the compositing */
+                    int amb_r = 0;   /* residual signs and the tracking mask */
                     int64_t nh = 0;
                     if (in->pixel_mask && !in->pixel_mask[gp]) {
                         if (out->rgb) { out->rgb[3 * off + pix] = 0; out->rgb[3 * off + P + pix] = 0; out->rgb[3 * off + 2 * P + pix] = 0; }
@@ -387,6 +399,8 @@ int oracle_run(const or_in *in, or_out *out) {
                         if (out->t_final) out->t_final[gp] = 1.0;
                         if (out->n_contrib) out->n_contrib[gp] = 0;
                         if (out->ambiguous) out->ambiguous[gp] = 0;
+                        if (out->decision_amb) out->decision_amb[gp] = 0;
+                        if (out->residual_amb) out->residual_amb[gp] = 0;
                         continue;
                     }
                     const double m = in->margin;
@@ -429,8 +443,10 @@ int oracle_run(const or_in *in, or_out *out) {
                     if (out->sil) out->sil[gp] = acc[4];
                     if (out->t_final) out->t_final[gp] = T;
                     if (out->n_contrib) out->n_contrib[gp] = (int32_t)nh;
+                    if (out->decision_amb) out->decision_amb[gp] = (uint8_t)amb;
                     if (!in->t_rgb) {
                         if (out->ambiguous) out->ambiguous[gp] = (uint8_t)amb;
+                        if (out->residual_amb) out->residual_amb[gp] = 0;
                         continue;
                     }
 
@@ -457,15 +473,16 @@ int oracle_run(const or_in *in, or_out *out) {
                     for (int ch = 0; ch < 5; ++ch)
                         if (wch[ch] != 0.0 && (acc[ch] != 0.0 || tv[ch] != 0.0) &&
                             fabs(res[ch]) <= in->res_margin * (fabs(acc[ch]) + fabs(tv[ch])))
-                            amb = 1;
+                            amb_r = 1;
                     if (trk * dpr * in->w_prior != 0.0 && (acc[3] != 0.0 || tpr != 0.0) &&
                         fabs(rpr) <= in->res_margin * (fabs(acc[3]) + fabs(tpr)))
-                        amb = 1;
+                        amb_r = 1;
                     if (in->sil_mask_thresh >= 0.0 &&
                         fabs(acc[4] - in->sil_mask_thresh) <= m * fmax(fabs(acc[4]), in->sil_mask_thresh))
-                        amb = 1;
-                    if (out->ambiguous) out->ambiguous[gp] = (uint8_t)amb;
-                    if (in->mask_ambiguous && amb) wgt = 0.0;
+                        amb_r = 1;
+                    if (out->ambiguous) out->ambiguous[gp] = (uint8_t)(amb | amb_r);
+                    if (out->residual_amb) out->residual_amb[gp] = (uint8_t)amb_r;
+                    if (in->mask_ambiguous && (amb | amb_r)) wgt = 0.0;
                     if (wgt == 0.0) continue;
                     const double lp = wgt * inv_P *
                         (trk * dm * (in->w_rgb * (fabs(res[0]) + fabs(res[1]) + fabs(res[2])) + in->w_depth * fabs(res[3])) +

@@ -70,6 +70,7 @@ class _Out(C.Structure):
         ("g_means", _dp), ("g_quats", _dp), ("g_log_scales", _dp), ("g_opacity", _dp), ("g_rgb", _dp),
         ("g_q_t", _dp), ("g_t", _dp), ("g_q_c", _dp), ("g_c", _dp),
         ("decision_hash", _u64p), ("grad2d", _dp),
+        ("decision_amb", _u8p), ("residual_amb", _u8p),
     ]
 
 
@@ -125,11 +126,17 @@ class Result:
     sil: np.ndarray
     t_final: np.ndarray
     n_contrib: np.ndarray
-    ambiguous: np.ndarray
+    ambiguous: np.ndarray           # union of the two flags below
     loss: np.ndarray
     decision_hash: np.ndarray
     grads: Optional[dict] = None
     grad2d: Optional[np.ndarray] = None
+    # a compositing decision (alpha vs 1/255 or 0.99, transmittance vs 1e-4)
+    # within `margin` of its threshold: the image itself may differ
+    decision_ambiguous: Optional[np.ndarray] = None
+    # a weighted L1 residual's sign or the tracking mask within its margin:
+    # the image is well defined, only the sign of the loss derivative is not
+    residual_ambiguous: Optional[np.ndarray] = None
 
 
 def _make_in(g, views, opts: Options, keep: list):
@@ -168,10 +175,13 @@ def run(g, views, opts: Options = Options(), targets: Optional[Targets] = None, 
     """Render every view; with targets also the loss; with want_grads the gradients.
 
     A pixel is flagged ambiguous when a decision on its path lies within a
-    relative margin of its threshold: alpha vs 1/255 and vs 0.99 and the next
-    transmittance vs 1e-4 (`margin`), or the sign of a weighted loss residual
-    and the tracking mask (`res_margin`, default `margin`).  FP32 and FP64
-    may decide such pixels differently; mask_ambiguous gives them weight 0."""
+    relative margin of its threshold.  Two kinds are reported apart:
+    decision_ambiguous (alpha vs 1/255 and vs 0.99, the next transmittance vs
+    1e-4; `margin`), where the image itself may differ between FP32 and FP64,
+    and residual_ambiguous (the sign of a weighted loss residual, the tracking
+    mask; `res_margin`, default `margin`), where only the sign of the loss
+    derivative may.  `ambiguous` is their union; mask_ambiguous gives those
+    pixels loss weight 0."""
     keep = []
     s, n, iso = _make_in(g, views, opts, keep)
     V = len(views.cams)
@@ -198,8 +208,11 @@ def run(g, views, opts: Options = Options(), targets: Optional[Targets] = None, 
     o = _Out()
     res = Result(rgb=np.zeros(3 * P), depth=np.zeros(P), sil=np.zeros(P), t_final=np.zeros(P),
                  n_contrib=np.zeros(P, np.int32), ambiguous=np.zeros(P, np.uint8), loss=np.zeros(V),
-                 decision_hash=np.zeros(V, np.uint64))
+                 decision_hash=np.zeros(V, np.uint64), decision_ambiguous=np.zeros(P, np.uint8),
+                 residual_ambiguous=np.zeros(P, np.uint8))
     o.rgb, o.depth, o.sil, o.t_final = _p(res.rgb), _p(res.depth), _p(res.sil), _p(res.t_final)
+    o.decision_amb = _p(res.decision_ambiguous, _u8p)
+    o.residual_amb = _p(res.residual_ambiguous, _u8p)
     o.n_contrib = _p(res.n_contrib, _ip)
     o.ambiguous = _p(res.ambiguous, _u8p)
     o.loss = _p(res.loss)

@@ -5,6 +5,8 @@ evaluates a strided sample of the pixels of some of the views (prime stride,
 so the sample does not alias with tiles or rows).  Both sides use the same
 per-pixel weights: 1 on sampled, non-ambiguous pixels of the checked views,
 0 elsewhere, so losses and gradients are the same function on both sides.
+Images are compared on every sampled pixel without an ambiguous compositing
+decision.  Each comparison states its pixel count and fails below its floor.
 """
 import numpy as np
 import pytest
@@ -12,7 +14,8 @@ import torch
 
 import oracle
 from paper_2408_05635_amd import scenes
-from gpu_util import GRAD_TOL, IMG_TOL, RES_MARGIN, dev_params, dev_poses, grad_errors, to_dev
+from gpu_util import (GRAD_ELEM_TOL, GRAD_TOL, IMG_TOL, RES_MARGIN, dev_params, dev_poses, grad_errors,
+                      require_coverage, to_dev)
 
 pytestmark = pytest.mark.gpu
 STRIDE = 97
@@ -24,9 +27,7 @@ def rast():
     return raster.Rasterizer(0)
 
 
-def _sampled_parity(rast, w, check_views, label, prior_sigma=None):
-    from paper_2408_05635_amd.raster import RenderOptions
-    cams = w.views.cams
+def _sampled_targets(w, check_views, prior_sigma=None):
     offs = w.views.pixel_offsets()
     P = int(offs[-1])
     sample = np.zeros(P, np.uint8)
@@ -38,35 +39,49 @@ def _sampled_parity(rast, w, check_views, label, prior_sigma=None):
     tg = dict(rgb=f32(tr.rgb), depth=f32(tr.depth), sil=f32(tr.sil))
     if prior_sigma is not None:
         tg["prior"] = f32(tr.depth * (1.0 + w.prior_noise[:P].astype(np.float64)))
+    return sample, tg
+
+
+def _sampled_parity(rast, w, check_views, label, sample, tg, img_floor=0.9, grad_floor=0.9, **over):
+    from paper_2408_05635_amd.raster import RenderOptions
+    cams = w.views.cams
+    offs = w.views.pixel_offsets()
+    weights = {**w.weights, **over}
     otg = oracle.Targets(tg["rgb"], tg["depth"], tg["sil"], prior=tg.get("prior"), weight=sample.astype(np.float64))
-    r = oracle.run(w.gaussians, w.views, oracle.Options(**w.weights), otg, want_grads=True, pixel_mask=sample,
+    r = oracle.run(w.gaussians, w.views, oracle.Options(**weights), otg, want_grads=True, pixel_mask=sample,
                    mask_ambiguous=True, res_margin=RES_MARGIN)
-    ok = (sample == 1) & (r.ambiguous == 0)
-    wgt = ok.astype(np.float32)
+    sampled = sample == 1
+    ok_img = sampled & (r.decision_ambiguous == 0)
+    ok = sampled & (r.ambiguous == 0)
+    n_img = require_coverage(ok_img[sampled], img_floor, f"{label} images")
+    n_grad = require_coverage(ok[sampled], grad_floor, f"{label} loss and gradients")
     g = dev_params(w.gaussians)
     q, t = dev_poses(w.views)
-    out = rast.render_loss_grad(g, q, t, cams, to_dev({**tg, "weight": wgt}), RenderOptions(**w.weights))
+    out = rast.render_loss_grad(g, q, t, cams, to_dev({**tg, "weight": ok.astype(np.float32)}),
+                                RenderOptions(**weights))
     torch.cuda.synchronize()
-    # images on the checked pixels, per channel, relative to the channel's max there
+    # images on the compared pixels, per channel, relative to the channel's max there
     errs = {}
     rgb = out["rgb"].double().cpu().numpy()
     for name, gimg, oimg in (("depth", out["depth"].double().cpu().numpy(), r.depth),
                              ("sil", out["sil"].double().cpu().numpy(), r.sil)):
-        errs[name] = float(np.abs(gimg - oimg)[ok].max() / max(np.abs(oimg[ok]).max(), 1e-30))
+        errs[name] = float(np.abs(gimg - oimg)[ok_img].max() / max(np.abs(oimg[ok_img]).max(), 1e-30))
     for c in range(3):
         idx = np.concatenate([3 * offs[v] + c * (offs[v + 1] - offs[v]) + np.arange(offs[v + 1] - offs[v])
                               for v in range(len(cams))])
-        okc = ok
-        errs["rgb"[c]] = float(np.abs(rgb[idx] - r.rgb[idx])[okc].max() / max(np.abs(r.rgb[idx][okc]).max(), 1e-30))
-    ge = grad_errors(out, r.grads)
+        errs["rgb"[c]] = float(np.abs(rgb[idx] - r.rgb[idx])[ok_img].max() /
+                               max(np.abs(r.rgb[idx][ok_img]).max(), 1e-30))
+    elem = {}
+    ge = grad_errors(out, r.grads, elem=elem)
     loss_g = out["loss"].cpu().numpy()
     sel = np.array(check_views)
     le = float(np.abs(loss_g[sel] - r.loss[sel]).max() / max(np.abs(r.loss[sel]).max(), 1e-30))
-    print(f"{label}: checked {int(ok.sum())} pixels ({int((sample == 1).sum() - ok.sum())} ambiguous) "
-          f"images={errs} loss={le:.2e} grads={ge}")
+    print(f"{label}: images on {n_img}, gradients on {n_grad} of {int(sampled.sum())} sampled pixels; "
+          f"images={errs} loss={le:.2e} grads={ge} elementwise(>1e-3 max)={elem}")
     assert max(errs.values()) <= IMG_TOL
     assert le <= IMG_TOL
     assert max(ge.values()) <= GRAD_TOL, ge
+    assert max(elem.values()) <= GRAD_ELEM_TOL, elem
 
 
 @pytest.mark.timeout(600)
@@ -77,12 +92,21 @@ def test_config4_uneven_32_views_sampled(rast):
     by_res = {}
     for v, c in enumerate(w.views.cams):
         by_res.setdefault((c.width, c.height), v)
-    _sampled_parity(rast, w, sorted(by_res.values()), "config4")
+    views = sorted(by_res.values())
+    sample, tg = _sampled_targets(w, views)
+    _sampled_parity(rast, w, views, "config4", sample, tg, grad_floor=0.75)
 
 
 @pytest.mark.timeout(600)
 def test_config5_large_anisotropic_sampled(rast):
     """3M anisotropic Gaussians, 16 views at 1200x680 with a depth prior, one
-    call; the oracle checks two views."""
+    call; the oracle checks two views.  Their pixels end saturated (on
+    average 228 contributions, the last ones tiny, so that T_final sits just
+    above 1e-4), which leaves the silhouette residual's sign undecided in
+    FP32 on most pixels: with the full loss, the gradients are compared on
+    the rest; a second comparison without the silhouette term covers nearly
+    every sampled pixel."""
     w = scenes.config5()
-    _sampled_parity(rast, w, [0, 9], "config5", prior_sigma=0.02)
+    sample, tg = _sampled_targets(w, [0, 9], prior_sigma=0.02)
+    _sampled_parity(rast, w, [0, 9], "config5", sample, tg, grad_floor=0.25)
+    _sampled_parity(rast, w, [0, 9], "config5 w_sil=0", sample, tg, grad_floor=0.95, w_sil=0.0)

@@ -1,10 +1,12 @@
 """Parity of the HIP rasteriser (through the C ABI) with the FP64 oracle.
 
 Bar: images within 1e-5 relative (max abs error / max |oracle| per channel,
-over pixels whose decisions are not within the ambiguity margin), gradients
-within 1e-4 relative per parameter group (||.||_inf), binning and sorting
-bit-exact.  Pixels the oracle flags as ambiguous get loss weight 0 on both
-sides; their count is printed with every comparison.
+over the pixels without a compositing decision within the ambiguity margin),
+gradients within 1e-4 relative per parameter group (||.||_inf), binning and
+sorting bit-exact.  Pixels the oracle flags as ambiguous (a compositing
+decision, or the sign of a weighted residual, near its threshold) get loss
+weight 0 on both sides.  Every comparison prints how many pixels it covered
+and fails below its floor.
 """
 import numpy as np
 import pytest
@@ -12,8 +14,8 @@ import torch
 
 import oracle
 from paper_2408_05635_amd import scenes
-from gpu_util import (GRAD_TOL, IMG_TOL, RES_MARGIN, dev_params, dev_poses, grad_errors, image_errors,
-                      oracle_targets, to_dev)
+from gpu_util import (GRAD_ELEM_TOL, GRAD_TOL, IMG_TOL, RES_MARGIN, dev_params, dev_poses, grad_errors,
+                      image_errors, oracle_targets, require_coverage, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -53,9 +55,9 @@ def test_forward_tiny_scenes(rast, seed, iso):
     w = scenes.tiny_scene(seed, n=48, width=36, height=28, isotropic=iso, opacity=(1.5, 1.5))
     out, _ = _forward(rast, w)
     r = oracle.run(w.gaussians, w.views, _oracle_opts(w))
-    ok = r.ambiguous == 0
-    err = image_errors(out, r, w.views.cams, ok)
-    print(f"tiny seed={seed} iso={iso} ambiguous={int((~ok).sum())} err={err}")
+    ok = r.decision_ambiguous == 0
+    err = image_errors(out, r, w.views.cams, ok, 0.9, f"tiny seed={seed} iso={iso}")
+    print(f"tiny seed={seed} iso={iso} err={err}")
     assert max(err.values()) <= IMG_TOL
 
 
@@ -63,9 +65,9 @@ def test_forward_config1(rast):
     w = scenes.config1()
     out, _ = _forward(rast, w)
     r = oracle.run(w.gaussians, w.views, _oracle_opts(w))
-    ok = r.ambiguous == 0
-    err = image_errors(out, r, w.views.cams, ok)
-    print(f"config1 ambiguous={int((~ok).sum())} err={err}")
+    ok = r.decision_ambiguous == 0
+    err = image_errors(out, r, w.views.cams, ok, 0.9, "config1 forward")
+    print(f"config1 err={err}")
     assert max(err.values()) <= IMG_TOL
 
 
@@ -150,24 +152,36 @@ def _fused(rast, w, tile=(16, 16), targets=None, weight=None, **kw):
     return out
 
 
-def _oracle_fused(w, tg):
+def _oracle_fused(w, tg, weights=None):
     otg = oracle.Targets(tg["rgb"], tg["depth"], tg["sil"], prior=tg.get("prior"))
-    return oracle.run(w.gaussians, w.views, _oracle_opts(w), otg, want_grads=True, mask_ambiguous=True,
+    opts = oracle.Options(**(w.weights if weights is None else weights))
+    return oracle.run(w.gaussians, w.views, opts, otg, want_grads=True, mask_ambiguous=True,
                       res_margin=RES_MARGIN)
 
 
-def _fused_parity(rast, w, tg, label, tile=(16, 16)):
-    r = _oracle_fused(w, tg)
+def _fused_parity(rast, w, tg, label, tile=(16, 16), img_floor=0.9, grad_floor=0.9, **kw):
+    """Fused render + loss + backward against the oracle.  Images are compared
+    on every pixel without an ambiguous compositing decision (img_floor of
+    them at least); the loss and gradients use weight 0 on every ambiguous
+    pixel on both sides (grad_floor of the pixels keep weight 1).  kw: option
+    overrides on both sides (loss weights, sil_mask_thresh)."""
+    weights = {**w.weights, **{k: v for k, v in kw.items() if k in ("w_rgb", "w_depth", "w_sil", "w_prior",
+                                                                     "sil_mask_thresh")}}
+    r = _oracle_fused(w, tg, weights)
+    ok_img = r.decision_ambiguous == 0
     ok = r.ambiguous == 0
-    out = _fused(rast, w, tile, tg, weight=ok.astype(np.float32))
-    ie = image_errors(out, r, w.views.cams, ok)
-    ge = grad_errors(out, r.grads)
-    loss_g = out["loss"].cpu().numpy()
+    require_coverage(ok, grad_floor, f"{label} (loss and gradients)")
+    out = _fused(rast, w, tile, tg, weight=ok.astype(np.float32), **kw)
+    ie = image_errors(out, r, w.views.cams, ok_img, img_floor, f"{label} (images)")
+    elem = {}
+    ge = grad_errors(out, r.grads, elem=elem)
+    loss_g = out["loss"].cpu().numpy()[:w.views.n]
     le = float(np.abs(loss_g - r.loss).max() / max(np.abs(r.loss).max(), 1e-30))
-    print(f"{label}: ambiguous={int((~ok).sum())}/{ok.size} loss rel err={le:.2e} images={ie} grads={ge}")
+    print(f"{label}: loss rel err={le:.2e} images={ie} grads={ge} elementwise(>1e-3 max)={elem}")
     assert max(ie.values()) <= IMG_TOL
     assert le <= IMG_TOL
     assert max(ge.values()) <= GRAD_TOL, ge
+    assert max(elem.values()) <= GRAD_ELEM_TOL, elem
     return out, r
 
 
@@ -182,36 +196,64 @@ def test_fused_tiny(rast, seed, iso):
     _fused_parity(rast, w, oracle_targets(w), f"tiny{seed}")
 
 
-def test_split_backward_matches_oracle(rast):
+@pytest.mark.parametrize("which", ["all", "pose_only", "gauss_only"])
+def test_split_backward_matches_oracle(rast, which):
     """render() + upstream image gradients (the loss derivative computed in
-    numpy from the oracle's images) gives the oracle's parameter gradients."""
+    numpy from the oracle's images) gives the oracle's gradients.  With only
+    the pose tensors requiring grad the library runs its pose-only backward
+    (6 partials per entry); with only the Gaussians, no pose gradients."""
     from paper_2408_05635_amd import raster
     w = scenes.config1()
     tg = oracle_targets(w)
     r = _oracle_fused(w, tg)
-    ok = (r.ambiguous == 0).astype(np.float64)
+    ok = r.ambiguous == 0
+    require_coverage(ok, 0.9, f"split backward ({which})")
+    okf = ok.astype(np.float64)
     cam = w.views.cams[0]
     P = cam.width * cam.height
     wts = w.weights
     dm = (tg["depth"] > 0).astype(np.float64)
     sgn = np.sign
-    g_rgb = (ok * dm * wts["w_rgb"] / P)[None, :] * sgn(r.rgb.reshape(3, P) - tg["rgb"].reshape(3, P))
-    g_depth = ok * dm * wts["w_depth"] / P * sgn(r.depth - tg["depth"])
-    g_sil = ok * wts["w_sil"] / P * sgn(r.sil - tg["sil"])
+    g_rgb = (okf * dm * wts["w_rgb"] / P)[None, :] * sgn(r.rgb.reshape(3, P) - tg["rgb"].reshape(3, P))
+    g_depth = okf * dm * wts["w_depth"] / P * sgn(r.depth - tg["depth"])
+    g_sil = okf * wts["w_sil"] / P * sgn(r.sil - tg["sil"])
     gp = dev_params(w.gaussians)
-    for t in gp.tensors():
-        t.requires_grad_(True)
     q, t = dev_poses(w.views)
-    q.requires_grad_(True)
-    t.requires_grad_(True)
+    if which in ("all", "gauss_only"):
+        for tt in gp.tensors():
+            tt.requires_grad_(True)
+    if which in ("all", "pose_only"):
+        q.requires_grad_(True)
+        t.requires_grad_(True)
     img, depth, sil = raster.render(rast, gp, q, t, w.views.cams, _opts(w))
     up = [torch.from_numpy(a.reshape(-1).astype(np.float32)).cuda() for a in (g_rgb, g_depth, g_sil)]
     torch.autograd.backward([img, depth, sil], up)
     got = dict(g_means=gp.means.grad, g_quats=gp.quats.grad, g_log_scales=gp.log_scales.grad,
                g_opacity_logits=gp.opacity_logits.grad, g_rgb=gp.rgb.grad, dq_t=q.grad, dt=t.grad)
-    ge = grad_errors(got, r.grads, keys=["means", "quats", "log_scales", "opacity_logits", "rgb", "dq_t", "dt"])
-    print("split backward grads", ge)
+    keys = {"all": ["means", "quats", "log_scales", "opacity_logits", "rgb", "dq_t", "dt"],
+            "pose_only": ["dq_t", "dt"],
+            "gauss_only": ["means", "quats", "log_scales", "opacity_logits", "rgb"]}[which]
+    for k, gk in (("means", "g_means"), ("dq_t", "dq_t"), ("dt", "dt")):
+        if k in keys:
+            assert got[gk] is not None, gk
+        else:
+            assert got[gk] is None, gk
+    ge = grad_errors(got, r.grads, keys=keys)
+    print(f"split backward ({which}) grads", ge)
+    assert sorted(ge) == sorted(keys)
     assert max(ge.values()) <= GRAD_TOL, ge
+
+
+def test_tracking_mask_config1(rast):
+    """The tracking mask of the loss, [S > 0.99] on the photometric, depth and
+    prior terms (the silhouette of eq. 4 selecting the well-observed pixels)."""
+    w = scenes.config1()
+    _fused_parity(rast, w, oracle_targets(w), "config1 tracking mask 0.99", sil_mask_thresh=0.99)
+
+
+def test_tracking_mask_config2_view(rast):
+    w = scenes.config2(n_views=1)
+    _fused_parity(rast, w, oracle_targets(w), "config2 tracking mask 0.99", sil_mask_thresh=0.99)
 
 
 def test_tile_size_invariance(rast):
@@ -291,11 +333,19 @@ def test_config2_full_view_parity(rast):
     _fused_parity(rast, w, oracle_targets(w), "config2")
 
 
-def test_config3_two_keyframes_with_depth_prior(rast):
-    w = scenes.config3(n=500_000, n_views=2)
-    P = w.views.cams[0].width * w.views.cams[0].height
-    tg = oracle_targets(w, prior_noise=w.prior_noise[:2 * P])
-    _fused_parity(rast, w, tg, "config3[2 views]")
+@pytest.mark.timeout(300)
+def test_config3_eight_keyframes_with_depth_prior(rast):
+    """The mapping configuration as the bench's mapping leg runs it: 500k
+    Gaussians, all 8 keyframes at 640x480 in one call, depth prior on, every
+    pixel checked.  Saturated silhouettes (S and S* both within 1e-5 of
+    1 - 1e-4) make the silhouette residual's sign ambiguous on about a sixth
+    of the pixels, so the full loss keeps a lower floor; without the
+    silhouette term nearly every pixel is compared."""
+    w = scenes.config3(n=500_000, n_views=8)
+    P = sum(c.width * c.height for c in w.views.cams)
+    tg = oracle_targets(w, prior_noise=w.prior_noise[:P])
+    _fused_parity(rast, w, tg, "config3[8 views]", grad_floor=0.75)
+    _fused_parity(rast, w, tg, "config3[8 views] w_sil=0", w_sil=0.0, grad_floor=0.98)
 
 
 def test_autotune_and_tuned_calls(rast):

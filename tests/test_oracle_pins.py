@@ -514,3 +514,87 @@ def test_pixel_mask_skips_unselected_views_exactly(oracle_lib):
         np.testing.assert_allclose(r2.grads[k], r1.grads[k], rtol=1e-12, atol=1e-15 * np.abs(r1.grads[k]).max())
     assert np.all(r2.grads["dq_t"][1] == 0) and np.all(r2.grads["dt"][1] == 0)
     np.testing.assert_allclose(r2.grads["dq_t"][0], r1.grads["dq_t"][0], rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# the parity policy's two flags: compositing decisions and residual signs
+# --------------------------------------------------------------------------
+def _unique_pixel(vals, lo, hi):
+    """A pixel whose value lies in (lo, hi) and is not within 1e-4 relative of
+    any other pixel's value."""
+    for p in np.argsort(vals)[::-1]:
+        x = vals[p]
+        if lo < x < hi and int((np.abs(vals - x) <= 1e-4 * x).sum()) == 1:
+            return int(p)
+    raise AssertionError("no isolated pixel value")
+
+
+def test_residual_sign_flag_inside_and_outside_its_margin(oracle_lib):
+    """A weighted L1 residual within res_margin (relative to |image| +
+    |target|) of zero flags its pixel residual-ambiguous, and only that pixel
+    and only that kind; a residual just outside the margin flags nothing.
+    Checked for each colour channel, the depth, the silhouette, the depth
+    prior, and the tracking mask's threshold.  Targets are far from the
+    render everywhere else."""
+    w = scenes.tiny_scene(10, n=40)
+    cam = w.views.cams[0]
+    P = cam.width * cam.height
+    r = oracle.run(w.gaussians, w.views, OPTS)
+    p = _unique_pixel(r.sil, 0.2, 0.95)
+    assert r.depth[p] > 0 and min(r.rgb[p], r.rgb[P + p], r.rgb[2 * P + p]) > 0
+    m = 4e-6
+    # t = x (1 - d): flagged iff x d <= m x (2 - d), i.e. d <= 2m / (1 + m)
+    d_edge = 2 * m / (1 + m)
+    opts = oracle.Options(w_prior=1.0)
+
+    def far():
+        return oracle.Targets(r.rgb + 0.25, r.depth + 0.5, r.sil + 0.25, prior=r.depth + 0.5)
+
+    base = oracle.run(w.gaussians, w.views, opts, far(), res_margin=m)
+    assert base.residual_ambiguous.sum() == 0
+    cases = [("rgb", p, r.rgb[p]), ("rgb", P + p, r.rgb[P + p]), ("rgb", 2 * P + p, r.rgb[2 * P + p]),
+             ("depth", p, r.depth[p]), ("sil", p, r.sil[p]), ("prior", p, r.depth[p])]
+    for name, idx, x in cases:
+        for frac, expect in ((0.9, 1), (1.1, 0)):
+            t = far()
+            getattr(t, name)[idx] = x * (1.0 - frac * d_edge)
+            out = oracle.run(w.gaussians, w.views, opts, t, res_margin=m)
+            assert out.residual_ambiguous[p] == expect, (name, frac)
+            assert out.residual_ambiguous.sum() == expect, (name, frac)
+            assert np.array_equal(out.decision_ambiguous, base.decision_ambiguous)
+            assert np.array_equal(out.ambiguous, out.decision_ambiguous | out.residual_ambiguous)
+    # the tracking mask [S > tau]: flagged within `margin` of tau (relative)
+    S = r.sil[p]
+    for rel, expect in ((0.5e-5, 1), (2e-5, 0)):
+        out = oracle.run(w.gaussians, w.views, oracle.Options(w_prior=1.0, sil_mask_thresh=S * (1 + rel)), far(),
+                         res_margin=m, margin=1e-5)
+        assert out.residual_ambiguous[p] == expect and out.residual_ambiguous.sum() == expect, rel
+
+
+def test_decision_flag_does_not_depend_on_targets(oracle_lib):
+    """The compositing decisions are those of the render alone: the same with
+    or without targets, and for any targets."""
+    w = scenes.config1()
+    a = oracle.run(w.gaussians, w.views, OPTS)
+    tr = oracle.run(w.truth, w.target_views)
+    b = oracle.run(w.gaussians, w.views, OPTS, oracle.Targets(tr.rgb, tr.depth, tr.sil), res_margin=4e-6)
+    assert np.array_equal(a.decision_ambiguous, b.decision_ambiguous)
+    assert a.residual_ambiguous.sum() == 0 and b.residual_ambiguous.sum() > 0
+
+
+@pytest.mark.parametrize("which", ["config1", "config2_view"])
+def test_flagged_share_is_bounded(oracle_lib, which):
+    """How many pixels each flag removes from a parity comparison, bounded
+    per workload: decisions near a threshold are rare; residual signs near
+    zero come almost only from saturated silhouettes (S and S* both close to
+    1 - 1e-4), so without the silhouette term they are rare too."""
+    w = scenes.config1() if which == "config1" else scenes.config2(n_views=1)
+    tr = oracle.run(w.truth, w.target_views)
+    tg = oracle.Targets(tr.rgb, tr.depth, tr.sil)
+    full = oracle.run(w.gaussians, w.views, oracle.Options(**w.weights), tg, res_margin=4e-6)
+    nosil = oracle.run(w.gaussians, w.views, oracle.Options(**{**w.weights, "w_sil": 0.0}), tg, res_margin=4e-6)
+    res_bound = 0.005 if which == "config1" else 0.08
+    print(which, full.decision_ambiguous.mean(), full.residual_ambiguous.mean(), nosil.residual_ambiguous.mean())
+    assert full.decision_ambiguous.mean() <= 0.001
+    assert full.residual_ambiguous.mean() <= res_bound
+    assert nosil.residual_ambiguous.mean() <= 0.005
