@@ -57,17 +57,25 @@
  *     final transmittance and last contributor) from gsr_forward() to
  *     gsr_backward(); it must not be reused in between.
  *   - All work is enqueued on `stream` (a hipStream_t; NULL = the null
- *     stream) and is stream-ordered; no call synchronises the host except
- *     gsr_read_counters().  Inputs must stay valid until the work completes.
+ *     stream) and is stream-ordered.  Only these wait on the host:
+ *     gsr_plan(), gsr_check_overflow(), gsr_read_counters(), gsr_read_work(),
+ *     gsr_read_timing(), gsr_autotune() and calls made with GSR_SYNC.
+ *     Inputs must stay valid until the work completes.
  *   - A gsr_ctx is not thread-safe: use one per host thread.
  *
  * Errors: every call returns a gsr_status.  Arguments are validated on the
  * host before any work is enqueued; on error nothing is enqueued and
  * gsr_last_error() describes the problem.  GSR_EHIP wraps a failing HIP call.
- * If the (Gaussian, tile) pairs of a call exceed the workspace's pair
- * capacity, the call still returns GSR_OK (it cannot know without a host
- * synchronisation), outputs are undefined, and gsr_read_counters() reports
- * the overflow together with the number of pairs that was needed.
+ * Pair capacity: the (Gaussian, tile) pairs of a call must fit the
+ * workspace's pair capacity.  Their number is known only on the device, so
+ *   - gsr_plan() runs the binning, waits, and returns the number needed
+ *     (GSR_ECAPACITY if the workspace it was given cannot hold them);
+ *   - with GSR_SYNC a render call waits after its binning and returns
+ *     GSR_ECAPACITY, writing no output, if the pairs do not fit;
+ *   - without GSR_SYNC (and always inside a graph) the call returns GSR_OK,
+ *     its outputs are undefined on an overflow, and a device flag records
+ *     it: gsr_check_overflow() (or gsr_read_counters()) reads it afterwards,
+ *     and the caller re-plans with a larger workspace.
  */
 #ifndef GSR_H
 #define GSR_H
@@ -85,7 +93,7 @@ typedef enum {
     GSR_OK = 0,
     GSR_EINVAL = -1,       /* invalid argument (nothing was enqueued) */
     GSR_ENOMEM = -2,       /* workspace too small for this call */
-    GSR_ECAPACITY = -3,    /* reserved: pair capacity exceeded (see gsr_read_counters) */
+    GSR_ECAPACITY = -3,    /* pair capacity exceeded (gsr_plan, GSR_SYNC, gsr_check_overflow) */
     GSR_EHIP = -4,         /* a HIP runtime call failed; gsr_last_error() has its text */
     GSR_EUNSUPPORTED = -5  /* e.g. more than GSR_MAX_VIEWS views in one call */
 } gsr_status;
@@ -99,6 +107,14 @@ typedef enum {
 #define GSR_COUNT_WORK     0x8u  /* count blend work (gsr_read_work); costs a little time */
 #define GSR_PIXEL_HASH     0x10u /* the forward also writes the per-pixel decision hash that
                                     gsr_debug_pixel_state reports (test hook; 0 without it) */
+#define GSR_POSE_CENTRE    0x20u /* views->trans holds each camera's centre C in world
+                                    coordinates instead of t: X_c = R(q) (X_w - C).  The
+                                    decoupled gradients dq_c, dc are then the gradients of the
+                                    pose inputs (Pose Estimation: rotation and translation
+                                    updated apart).  Not accepted by the tracking loop. */
+#define GSR_SYNC           0x40u /* the call waits for its binning and returns GSR_ECAPACITY
+                                    (no output written) if the pairs exceed the workspace's
+                                    capacity; not allowed inside a graph capture */
 
 /* stages reported by gsr_read_timing() */
 #define GSR_STAGE_BINNING     0  /* projection, compaction, depth sort, records, pairs, tile sort, ranges */
@@ -123,7 +139,8 @@ typedef struct {
 } gsr_gaussians;
 
 /* Views: n_views cameras (host array) and world-to-camera poses (device):
- * quat [V,4] (w,x,y,z, any norm) and trans [V,3], X_c = R(q) X_w + t. */
+ * quat [V,4] (w,x,y,z, any norm) and trans [V,3], X_c = R(q) X_w + t (with
+ * GSR_POSE_CENTRE, trans is the camera centre C and X_c = R(q) (X_w - C)). */
 typedef struct {
     int32_t n_views;
     const gsr_camera *cams;
@@ -204,8 +221,10 @@ gsr_status gsr_backward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *v
                         const float *g_sil, gsr_gaussian_grads *gg, gsr_pose_grads *pg, void *stream);
 
 /* Forward, loss and backward in one call (the tracking/mapping step):
- * renders into `out`, writes the per-view loss to loss[V] (device, float64,
- * overwritten) and the gradients. */
+ * renders into `out`, writes the loss to loss[V + 1] (device, float64,
+ * overwritten): the per-view losses loss[0..V-1], then their sum in view
+ * order, loss[V] (the total the combined objective minimises), and the
+ * gradients of that total. */
 gsr_status gsr_render_loss_grad(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views,
                                 const gsr_options *opts, const gsr_targets *targets, gsr_workspace ws,
                                 gsr_images out, double *loss, gsr_gaussian_grads *gg, gsr_pose_grads *pg,
@@ -246,9 +265,26 @@ gsr_status gsr_graph_destroy(gsr_ctx *ctx, int32_t graph_id);
 
 /* Synchronises `stream` and reads the counters of the last call on ws:
  * visible (view, Gaussian) records, (Gaussian, tile) pairs needed, and
- * whether the pair capacity overflowed (then outputs are undefined). */
+ * whether the pair capacity overflowed (then outputs are undefined).  Any
+ * of the three pointers may be NULL. */
 gsr_status gsr_read_counters(gsr_ctx *ctx, gsr_workspace ws, void *stream, int64_t *n_visible, int64_t *n_pairs,
                              int32_t *overflow);
+
+/* The capacity check of the asynchronous paths (graph launches, calls
+ * without GSR_SYNC): synchronises `stream`, sets *overflowed (host) to 1 if
+ * the last call on ws -- or any iteration of the last tracking or mapping
+ * loop on it -- needed more pairs than the workspace holds, and then
+ * returns GSR_ECAPACITY (re-plan with gsr_plan and a larger workspace);
+ * GSR_OK and 0 otherwise. */
+gsr_status gsr_check_overflow(gsr_ctx *ctx, gsr_workspace ws, void *stream, int32_t *overflowed);
+
+/* Plans a call: runs its projection and binning on `stream` (same g, views
+ * and opts as the call; ws may have any pair capacity, 0 included), waits,
+ * and writes the number of (Gaussian, tile) pairs the call needs to
+ * *pairs_needed (host).  Returns GSR_ECAPACITY (with *pairs_needed set) if
+ * ws cannot hold them.  Not allowed inside a graph capture. */
+gsr_status gsr_plan(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views, const gsr_options *opts,
+                    gsr_workspace ws, int64_t *pairs_needed, void *stream);
 
 /* Work counters of the last call on ws made with GSR_COUNT_WORK (synchronises
  * `stream`): work[0] (pixel, entry) alpha evaluations in the forward blend,
@@ -341,7 +377,7 @@ gsr_status gsr_pose_opt_step(gsr_ctx *ctx, int32_t n_views, const float *dq_c, c
  * as there), then gsr_pose_opt_step, all enqueued on `stream`.  quat/trans
  * (device) hold the start pose and receive the optimised one; `state` must
  * have been started by gsr_pose_opt_init.  pg must provide dq_c and dc
- * (scratch for every iteration; dq_t and dt are optional).  loss [V] holds
+ * (scratch for every iteration; dq_t and dt are optional).  loss [V + 1] holds
  * the last iteration's loss; loss_hist (device, optional) receives every
  * iteration's, [iters, V].  After the loop, gsr_read_counters reports an
  * overflow if the pair capacity was exceeded in any iteration. */
@@ -390,7 +426,8 @@ gsr_status gsr_map_opt_step(gsr_ctx *ctx, gsr_gaussians_rw params, const gsr_gau
  * Gaussian parameter over `views` (a window of keyframes, poses fixed: pose
  * gradients are not formed), then gsr_map_opt_step on `params` in place, all
  * enqueued on `stream`.  gg receives each iteration's gradients (scratch;
- * laid out as params).  loss [V] holds the last iteration's loss; loss_hist
+ * laid out as params).  loss [V + 1] holds the last iteration's loss (per view,
+ * then the total); loss_hist
  * (device, optional) receives every iteration's, [iters, V].  `state` must
  * have been started by gsr_map_opt_init.  EINVAL with GSR_NO_GAUSS_GRADS.
  * After the loop, gsr_read_counters reports an overflow if the pair

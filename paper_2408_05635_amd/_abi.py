@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(_HERE, "libgsr.so")
 GSR_OK, GSR_EINVAL, GSR_ENOMEM, GSR_ECAPACITY, GSR_EHIP, GSR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 GSR_MAX_VIEWS = 64
 GSR_ISOTROPIC, GSR_NO_GAUSS_GRADS, GSR_NO_POSE_GRADS, GSR_COUNT_WORK, GSR_PIXEL_HASH = 0x1, 0x2, 0x4, 0x8, 0x10
+GSR_POSE_CENTRE, GSR_SYNC = 0x20, 0x40
 STAGES = ("binning", "blend_fwd", "blend_bwd", "project_bwd")
 
 _fp = C.POINTER(C.c_float)
@@ -81,7 +82,8 @@ EXPORTS = ["gsr_create", "gsr_destroy", "gsr_last_error", "gsr_workspace_size", 
            "gsr_debug_binning", "gsr_debug_pixel_state", "gsr_selftest", "gsr_autotune", "gsr_set_tile",
            "gsr_graph_capture", "gsr_graph_launch", "gsr_graph_destroy", "gsr_pose_opt_init", "gsr_pose_opt_step",
            "gsr_track", "gsr_track_capture", "gsr_map_state_size", "gsr_map_opt_init", "gsr_map_opt_step",
-           "gsr_densify_work_size", "gsr_densify", "gsr_map_iterate", "gsr_map_capture"]
+           "gsr_densify_work_size", "gsr_densify", "gsr_map_iterate", "gsr_map_capture", "gsr_plan",
+           "gsr_check_overflow"]
 
 _lib = None
 
@@ -114,6 +116,10 @@ def load() -> C.CDLL:
     lib.gsr_render_loss_grad.restype = st
     lib.gsr_read_counters.argtypes = [_vp, Workspace, _vp, P(C.c_int64), P(C.c_int64), P(C.c_int32)]
     lib.gsr_read_counters.restype = st
+    lib.gsr_check_overflow.argtypes = [_vp, Workspace, _vp, P(C.c_int32)]
+    lib.gsr_check_overflow.restype = st
+    lib.gsr_plan.argtypes = [_vp, P(Gaussians), P(Views), P(Options), Workspace, P(C.c_int64), _vp]
+    lib.gsr_plan.restype = st
     lib.gsr_read_work.argtypes = [_vp, Workspace, _vp, P(C.c_int64)]
     lib.gsr_read_work.restype = st
     lib.gsr_set_timing.argtypes = [_vp, C.c_int32]

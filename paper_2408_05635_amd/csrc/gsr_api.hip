@@ -209,6 +209,7 @@ void build_table(const gsr_views *views, const gsr_options *opts, ViewTable &vt)
     vt.n_views = views->n_views;
     vt.tile_w = opts->tile_w;
     vt.tile_h = opts->tile_h;
+    vt.pose_centre = (opts->flags & GSR_POSE_CENTRE) ? 1 : 0;
     int64_t pix = 0;
     int32_t tiles = 0, blocks = 0;
     const int spt = (opts->tile_w / kBlk) * (opts->tile_h / kBlk);
@@ -360,7 +361,12 @@ __global__ __launch_bounds__(256) void k_setup_project(ViewTable tab, ViewTable 
     if (t < V) {
         PoseF64 p;
         quat_to_rot_f64(pq[4 * t], pq[4 * t + 1], pq[4 * t + 2], pq[4 * t + 3], p.W);
-        for (int k = 0; k < 3; ++k) p.t[k] = (double)pt[3 * t + k];
+        if (tab.pose_centre) {   // X_c = W (X - C) = W X + t with t = -W C
+            const double C[3] = {(double)pt[3 * t], (double)pt[3 * t + 1], (double)pt[3 * t + 2]};
+            for (int k = 0; k < 3; ++k) p.t[k] = -(p.W[3 * k] * C[0] + p.W[3 * k + 1] * C[1] + p.W[3 * k + 2] * C[2]);
+        } else {
+            for (int k = 0; k < 3; ++k) p.t[k] = (double)pt[3 * t + k];
+        }
         s_pose[t] = p;
         if (blockIdx.x == 0) poses[t] = p;
     }
@@ -796,9 +802,9 @@ struct PoseOpt {
 };
 
 __device__ __forceinline__ void pose_final_view(const float *__restrict__ pq, const float *__restrict__ pt,
-                                                const PoseF64 *poses, const double *__restrict__ pose_blocks,
-                                                int nblocks, int V, const gsr_pose_grads &pg, const PoseOpt &po,
-                                                int v) {
+                                                bool centre, const PoseF64 *poses,
+                                                const double *__restrict__ pose_blocks, int nblocks, int V,
+                                                const gsr_pose_grads &pg, const PoseOpt &po, int v) {
     __shared__ double s_red[12][256];
     const int t = threadIdx.x;
     double acc[12];
@@ -828,9 +834,10 @@ __device__ __forceinline__ void pose_final_view(const float *__restrict__ pq, co
         for (int k = 0; k < 4; ++k) pg.dq_t[4 * v + k] = (float)gq[k];
     if (pg.dt)
         for (int k = 0; k < 3; ++k) pg.dt[3 * v + k] = (float)gt[k];
-    double C[3], gc[3];
+    double C[3], gc[3];   // C = -W^T t (or given, with GSR_POSE_CENTRE); dL/dC = -W^T dL/dt
     for (int k = 0; k < 3; ++k) {
-        C[k] = -(W[k] * pt[3 * v] + W[3 + k] * pt[3 * v + 1] + W[6 + k] * pt[3 * v + 2]);
+        C[k] = centre ? (double)pt[3 * v + k]
+                      : -(W[k] * pt[3 * v] + W[3 + k] * pt[3 * v + 1] + W[6 + k] * pt[3 * v + 2]);
         gc[k] = -(W[k] * gt[0] + W[3 + k] * gt[1] + W[6 + k] * gt[2]);
     }
     if (pg.dc)
@@ -856,6 +863,7 @@ __device__ __forceinline__ void pose_final_view(const float *__restrict__ pq, co
 struct FinalArgs {
     int n_pose, n_loss;
     const float *pq, *pt;   // pose inputs
+    int centre;             // pt holds the camera centre (GSR_POSE_CENTRE)
     const PoseF64 *poses;
     const double *pose_blocks;
     int pose_rows, V;
@@ -869,17 +877,18 @@ struct FinalArgs {
     const float *rgrad;
     GradOut go;
     const int64_t *counters;
+    int64_t *loss_ticket;   // cleared by the call's set-up
 };
 
 __global__ __launch_bounds__(256) void k_finalize(FinalArgs a) {
     int b = (int)blockIdx.x;
     if (b < a.n_pose) {
-        pose_final_view(a.pq, a.pt, a.poses, a.pose_blocks, a.pose_rows, a.V, a.pg, a.po, b);
+        pose_final_view(a.pq, a.pt, a.centre != 0, a.poses, a.pose_blocks, a.pose_rows, a.V, a.pg, a.po, b);
         return;
     }
     b -= a.n_pose;
     if (b < a.n_loss) {
-        loss_final_view(a.vt, a.loss_tile, a.loss, a.po.hist, b);
+        loss_final_view(a.vt, a.loss_tile, a.loss, a.po.hist, a.loss_ticket, b);
         return;
     }
     b -= a.n_loss;
@@ -952,6 +961,28 @@ unsigned grid_for(int64_t n, int threads, int64_t max_blocks = 65536) {
     return (unsigned)b;
 }
 
+// Calls that wait on the host (GSR_SYNC, gsr_plan) cannot be part of a graph.
+gsr_status reject_capture(gsr_ctx *ctx, void *stream, const char *what) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (ctx->capturing ||
+        (hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone))
+        return fail(ctx, GSR_EINVAL, "%s waits on the host and cannot be captured into a graph", what);
+    return GSR_OK;
+}
+
+// Copies the counters of the last call on the workspace to the host (waits
+// for the stream); GSR_EHIP if a wait between blocks gave up.
+gsr_status read_counters_sync(gsr_ctx *ctx, const gsr_workspace &ws, hipStream_t st, int64_t h[kNumCounters]) {
+    gsr_status s = check_hip(ctx, hipMemcpyAsync(h, ws.ptr, sizeof(int64_t) * kNumCounters, hipMemcpyDeviceToHost, st),
+                             "hipMemcpyAsync(counters)");
+    if (s == GSR_OK) s = check_hip(ctx, hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (s != GSR_OK) return s;
+    if (h[kCntSyncError] != 0)
+        return fail(ctx, GSR_EHIP, "%lld waits between blocks of the binning gave up; outputs are undefined",
+                    (long long)h[kCntSyncError]);
+    return GSR_OK;
+}
+
 struct Call {
     bool count = false;
     bool hash = false;   // the forward writes the per-pixel decision hash
@@ -970,6 +1001,10 @@ gsr_status prepare(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views,
     if (!g) return fail(ctx, GSR_EINVAL, "gaussians must not be NULL");
     gsr_status s = validate_views(ctx, views, opts);
     if (s != GSR_OK) return s;
+    if (opts->flags & GSR_SYNC) {
+        s = reject_capture(ctx, stream, "GSR_SYNC");
+        if (s != GSR_OK) return s;
+    }
     if (g->n < 0) return fail(ctx, GSR_EINVAL, "n must be >= 0 (got %lld)", (long long)g->n);
     if ((int64_t)views->n_views * g->n >= (int64_t)0xffffffffLL)
         return fail(ctx, GSR_EUNSUPPORTED, "views x Gaussians must be < 2^32");
@@ -1143,6 +1178,7 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
     const int64_t n_gauss_blocks = (c.pp.n > 0 && go.want_gauss) ? grid_for(c.pp.n, 256, 1ll << 30) : 0;
     fa.pq = views->quat;
     fa.pt = views->trans;
+    fa.centre = c.tab.pose_centre;
     fa.poses = at<PoseF64>(c.ws, L.poses);
     fa.pose_blocks = pose_blocks;
     fa.pose_rows = (int)rec_blocks;
@@ -1158,6 +1194,7 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
     fa.rgrad = at<float>(c.ws, L.rgrad);
     fa.go = go;
     fa.counters = counters;
+    fa.loss_ticket = counters + kCntLossTicket;
     const int64_t n_final = fa.n_pose + fa.n_loss + n_gauss_blocks;
     if (n_final > 0) hipLaunchKernelGGL(k_finalize, dim3((unsigned)n_final), dim3(256), 0, st, fa);
     // with the Gaussian gradients off, or for N = 0, the outputs are still defined (zero)
@@ -1175,6 +1212,21 @@ gsr_status finish(Call &c, const char *what) {
     return check_hip(c.ctx, hipGetLastError(), what);
 }
 
+// GSR_SYNC: waits for the binning just enqueued and fails with GSR_ECAPACITY,
+// enqueueing nothing more, if its pairs exceed the workspace's capacity.
+gsr_status sync_capacity(Call &c) {
+    gsr_status s = check_hip(c.ctx, hipGetLastError(), "binning launch");
+    if (s != GSR_OK) return s;
+    int64_t h[kNumCounters];
+    s = read_counters_sync(c.ctx, c.ws, c.st, h);
+    if (s != GSR_OK) return s;
+    if (h[kCntOverflow] != 0)
+        return fail(c.ctx, GSR_ECAPACITY,
+                    "%lld (Gaussian, tile) pairs needed, the workspace holds %lld; no output was written",
+                    (long long)h[kCntPairs], (long long)c.L.kcap);
+    return GSR_OK;
+}
+
 gsr_status render_loss_grad_impl(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views,
                                  const gsr_options *opts, const gsr_targets *targets, gsr_workspace ws,
                                  gsr_images out, double *loss, gsr_gaussian_grads *gg, gsr_pose_grads *pg,
@@ -1189,6 +1241,10 @@ gsr_status render_loss_grad_impl(gsr_ctx *ctx, const gsr_gaussians *g, const gsr
     s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     if (s != GSR_OK) return s;
     enqueue_binning(c, views);
+    if (opts->flags & GSR_SYNC) {
+        s = sync_capacity(c);
+        if (s != GSR_OK) return s;
+    }
     enqueue_blend_fwd(c, out);
     LossIn li;
     memset(&li, 0, sizeof(li));
@@ -1219,6 +1275,8 @@ gsr_status track_impl(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *ca
         return fail(ctx, GSR_EINVAL, "track: NULL argument (g, cams, opts, hp, state, quat, trans, pg->dq_c, pg->dc)");
     if (iters < 0) return fail(ctx, GSR_EINVAL, "track: iters must be >= 0 (got %d)", iters);
     if (V < 1 || V > GSR_MAX_VIEWS) return fail(ctx, GSR_EINVAL, "track: n_views must be in [1, %d]", GSR_MAX_VIEWS);
+    if (opts->flags & GSR_POSE_CENTRE)
+        return fail(ctx, GSR_EUNSUPPORTED, "track: the loop updates (q, t) poses; GSR_POSE_CENTRE is not accepted");
     const gsr_views views{V, cams, quat, trans};
     gsr_options o = *opts;
     o.flags |= GSR_NO_GAUSS_GRADS;
@@ -1401,6 +1459,10 @@ gsr_status gsr_forward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *vi
         if (s != GSR_OK) return s;
     }
     enqueue_binning(c, views);
+    if (opts->flags & GSR_SYNC) {
+        s = sync_capacity(c);
+        if (s != GSR_OK) return s;
+    }
     enqueue_blend_fwd(c, out);
     return finish(c, "gsr_forward launch");
 }
@@ -1515,6 +1577,8 @@ gsr_status gsr_graph_capture(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_vie
     if (!ctx) return GSR_EINVAL;
     if (!graph_id) return fail(ctx, GSR_EINVAL, "graph_id must not be NULL");
     if (!stream) return fail(ctx, GSR_EINVAL, "graph capture needs a stream other than the null stream");
+    if (opts && (opts->flags & GSR_SYNC))
+        return fail(ctx, GSR_EINVAL, "GSR_SYNC waits on the host and cannot be captured into a graph");
     gsr_options o_res;
     if (opts && views && g) {
         o_res = resolve_tile(ctx, g->n, views, opts);
@@ -1573,17 +1637,52 @@ gsr_status gsr_read_counters(gsr_ctx *ctx, gsr_workspace ws, void *stream, int64
     int64_t h[kNumCounters];
     gsr_status s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     if (s != GSR_OK) return s;
-    s = check_hip(ctx, hipMemcpyAsync(h, ws.ptr, sizeof(h), hipMemcpyDeviceToHost, (hipStream_t)stream),
-                  "hipMemcpyAsync(counters)");
-    if (s != GSR_OK) return s;
-    s = check_hip(ctx, hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+    s = read_counters_sync(ctx, ws, (hipStream_t)stream, h);
     if (s != GSR_OK) return s;
     if (n_visible) *n_visible = h[kCntVisible];
     if (n_pairs) *n_pairs = h[kCntPairs];
     if (overflow) *overflow = (int32_t)(h[kCntOverflow] | h[kCntOverflowAny]);
-    if (h[kCntSyncError] != 0)
-        return fail(ctx, GSR_EHIP, "%lld waits between blocks of the binning gave up; outputs are undefined",
-                    (long long)h[kCntSyncError]);
+    return GSR_OK;
+}
+
+gsr_status gsr_check_overflow(gsr_ctx *ctx, gsr_workspace ws, void *stream, int32_t *overflowed) {
+    if (!ctx) return GSR_EINVAL;
+    if (!overflowed) return fail(ctx, GSR_EINVAL, "overflowed must not be NULL");
+    int64_t k = 0;
+    const gsr_status s = gsr_read_counters(ctx, ws, stream, nullptr, &k, overflowed);
+    if (s != GSR_OK) return s;
+    if (*overflowed)
+        return fail(ctx, GSR_ECAPACITY, "the pair capacity overflowed (%lld pairs needed by the last call)",
+                    (long long)k);
+    return GSR_OK;
+}
+
+gsr_status gsr_plan(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views, const gsr_options *opts,
+                    gsr_workspace ws, int64_t *pairs_needed, void *stream) {
+    if (!ctx) return GSR_EINVAL;
+    if (!pairs_needed) return fail(ctx, GSR_EINVAL, "pairs_needed must not be NULL");
+    gsr_status s = reject_capture(ctx, stream, "gsr_plan");
+    if (s != GSR_OK) return s;
+    gsr_options o_res;
+    if (opts && views && g) {
+        o_res = resolve_tile(ctx, g->n, views, opts);
+        opts = &o_res;
+    }
+    Call c;
+    s = prepare(ctx, g, views, opts, ws, stream, c);
+    if (s != GSR_OK) return s;
+    s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (s != GSR_OK) return s;
+    enqueue_binning(c, views);
+    s = check_hip(ctx, hipGetLastError(), "gsr_plan launch");
+    if (s != GSR_OK) return s;
+    int64_t h[kNumCounters];
+    s = read_counters_sync(ctx, ws, c.st, h);
+    if (s != GSR_OK) return s;
+    *pairs_needed = h[kCntPairs];
+    if (h[kCntOverflow] != 0)
+        return fail(ctx, GSR_ECAPACITY, "%lld (Gaussian, tile) pairs needed, the workspace holds %lld",
+                    (long long)h[kCntPairs], (long long)ws.pair_capacity);
     return GSR_OK;
 }
 
@@ -1747,6 +1846,8 @@ gsr_status gsr_track_capture(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_cam
     // validate before the capture starts (one render's worth of checks)
     if (!g || !cams || !opts || n_views < 1 || n_views > GSR_MAX_VIEWS)
         return fail(ctx, GSR_EINVAL, "track_capture: bad arguments");
+    if (opts->flags & GSR_SYNC)
+        return fail(ctx, GSR_EINVAL, "GSR_SYNC waits on the host and cannot be captured into a graph");
     {
         const gsr_views views{n_views, cams, quat, trans};
         gsr_options o = *opts;
@@ -1824,6 +1925,8 @@ gsr_status gsr_map_capture(gsr_ctx *ctx, gsr_gaussians_rw params, const gsr_view
     if (!graph_id) return fail(ctx, GSR_EINVAL, "graph_id must not be NULL");
     if (!stream) return fail(ctx, GSR_EINVAL, "graph capture needs a stream other than the null stream");
     if (!views || !opts) return fail(ctx, GSR_EINVAL, "map_capture: views and opts must not be NULL");
+    if (opts->flags & GSR_SYNC)
+        return fail(ctx, GSR_EINVAL, "GSR_SYNC waits on the host and cannot be captured into a graph");
     {   // validate before the capture starts (one render's worth of checks)
         const gsr_gaussians g{params.n, params.means, params.quats, params.log_scales, params.opacity_logits,
                               params.rgb};

@@ -660,9 +660,13 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
 }
 
 // Per-view loss: the view's tile partials added in a fixed tree order (one
-// 256-thread block per view); also copied to hist if that is set.
+// 256-thread block per view); also copied to hist if that is set.  The block
+// that finishes last (a ticket taken with acquire-release ordering at device
+// scope, so it sees every other block's view loss) adds the V view losses in
+// view order into loss[V], the total.
 __device__ __forceinline__ void loss_final_view(const ViewTable *__restrict__ vt, const double *__restrict__ loss_tile,
-                                                double *__restrict__ loss, double *__restrict__ hist, int view) {
+                                                double *__restrict__ loss, double *__restrict__ hist,
+                                                int64_t *__restrict__ ticket, int view) {
     __shared__ double s[256];
     const ViewInfo &V = vt->v[view];
     const int n = V.tiles_x * V.tiles_y;
@@ -678,6 +682,14 @@ __device__ __forceinline__ void loss_final_view(const ViewTable *__restrict__ vt
     if (threadIdx.x == 0) {
         loss[view] = s[0];
         if (hist) hist[view] = s[0];   // a tracking loop's per-iteration record
+        const int nv = vt->n_views;
+        const int64_t k = __hip_atomic_fetch_add(ticket, (int64_t)1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (k == (int64_t)nv - 1) {
+            double tot = 0.0;
+            for (int v = 0; v < nv; ++v) tot += v == view ? s[0] : __hip_atomic_load(&loss[v], __ATOMIC_RELAXED,
+                                                                                      __HIP_MEMORY_SCOPE_AGENT);
+            loss[nv] = tot;
+        }
     }
 }
 

@@ -32,7 +32,8 @@ struct ViewTable {
     int32_t tile_w, tile_h;
     int32_t total_tiles;
     int32_t total_blocks;
-    int32_t pad[3];
+    int32_t pose_centre;   // GSR_POSE_CENTRE: the pose translation input is the camera centre C
+    int32_t pad[2];
     ViewInfo v[GSR_MAX_VIEWS];
 };
 
@@ -44,6 +45,7 @@ enum Counter {
     kCntOverflow = 3,    // 1 if K exceeded the capacity
     kCntOverflowAny = 4, // 1 if K exceeded it in any call of a tracking loop (kept across its iterations)
     kCntSyncError = 6,   // waits between blocks that gave up (never expected)
+    kCntLossTicket = 7,  // per-view loss blocks that have finished (the last one forms the total)
     // work counters (GSR_COUNT_WORK): (pixel, entry) evaluations and
     // contributions in the forward and backward blends, and (wave, entry)
     // gradient reductions in the backward

@@ -38,6 +38,11 @@ class RenderOptions:
     pose_grads: bool = True
     count_work: bool = False
     pixel_hash: bool = False   # forwards write the decision hash that pixel_state reports
+    # the pose translation tensor holds the camera centre C (X_c = R(q)(X - C)); the
+    # autograd functions then return dL/dq at fixed C and dL/dC (decoupled update)
+    pose_centre: bool = False
+    # the library waits after its binning and raises GsrError(GSR_ECAPACITY) on overflow
+    sync: bool = False
 
 
 @dataclass
@@ -103,6 +108,18 @@ def _check_f32(name: str, t: torch.Tensor, shape, device):
         raise ValueError(f"{name} must be contiguous")
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _loss_ptr(out: dict):
+    """Device pointer of the loss buffer of `out`: the library writes V + 1
+    float64 values there (per view, then the total)."""
+    loss = out["loss"]
+    V = int(loss.numel())
+    if loss.dtype != torch.float64 or not loss.is_cuda:
+        raise TypeError("loss must be a float64 device tensor")
+    if loss.untyped_storage().nbytes() < (loss.storage_offset() + V + 1) * 8:
+        raise ValueError("the loss buffer needs V + 1 entries (per view, then the total): use alloc_outputs")
+    return _ptr(loss)
 
 
 def _stream_ptr():
@@ -171,6 +188,10 @@ class Rasterizer:
             flags |= _abi.GSR_COUNT_WORK
         if o.pixel_hash:
             flags |= _abi.GSR_PIXEL_HASH
+        if o.pose_centre:
+            flags |= _abi.GSR_POSE_CENTRE
+        if o.sync:
+            flags |= _abi.GSR_SYNC
         return _abi.Options(o.w_rgb, o.w_depth, o.w_sil, o.w_prior, o.z_near, o.blur2d, o.sil_mask_thresh,
                             int(o.tile[0]), int(o.tile[1]), flags)
 
@@ -191,6 +212,31 @@ class Rasterizer:
             self._ws = None
             self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         return _abi.Workspace(self._ws.data_ptr(), self._ws.numel(), self.pair_capacity)
+
+    def plan(self, g: GaussianParams, quat, trans, cams, opts: RenderOptions = RenderOptions()) -> int:
+        """(Gaussian, tile) pairs the call with these inputs needs (runs the
+        binning and synchronises); grows the pair capacity to hold them."""
+        views, keep = self._views(cams, quat, trans)
+        gs = self._gauss(g)
+        o = self._opts(opts, g.isotropic)
+        ws = self._shared_ws(g.n, views, o)
+        k = C.c_int64()
+        st = _ABI.gsr_plan(self._ctx, C.byref(gs), C.byref(views), C.byref(o), ws, C.byref(k), _stream_ptr())
+        if st == _abi.GSR_ECAPACITY:
+            self._grow(int(k.value))
+        else:
+            _abi.check(st, self._ctx)
+        return int(k.value)
+
+    def check_overflow(self, ws: Optional[_abi.Workspace] = None) -> bool:
+        """True if the last call (or loop iteration) on ws overflowed its pair
+        capacity (synchronises)."""
+        ws = self.shared_workspace() if ws is None else ws
+        o = C.c_int32()
+        st = _ABI.gsr_check_overflow(self._ctx, ws, _stream_ptr(), C.byref(o))
+        if st != _abi.GSR_ECAPACITY:
+            _abi.check(st, self._ctx)
+        return bool(o.value)
 
     def read_counters(self, ws: _abi.Workspace) -> Tuple[int, int, int]:
         m, k, o = C.c_int64(), C.c_int64(), C.c_int32()
@@ -262,7 +308,7 @@ class Rasterizer:
         best = (C.c_int32 * 2)()
         ms = C.c_double()
         _abi.check(_ABI.gsr_autotune(self._ctx, C.byref(a["gs"]), C.byref(a["views"]), C.byref(a["o"]),
-                                     C.byref(a["tg"]), ws, a["imgs"], _ptr(out["loss"]), C.byref(a["gg"]),
+                                     C.byref(a["tg"]), ws, a["imgs"], _loss_ptr(out), C.byref(a["gg"]),
                                      C.byref(a["pg"]), int(reps), best, C.byref(ms), _stream_ptr()), self._ctx)
         return (int(best[0]), int(best[1])), float(ms.value)
 
@@ -290,7 +336,7 @@ class Rasterizer:
         ws = self._shared_ws(g.n, a["views"], a["o"])
         gid = C.c_int32()
         _abi.check(_ABI.gsr_graph_capture(self._ctx, C.byref(a["gs"]), C.byref(a["views"]), C.byref(a["o"]),
-                                          C.byref(a["tg"]), ws, a["imgs"], _ptr(out["loss"]), C.byref(a["gg"]),
+                                          C.byref(a["tg"]), ws, a["imgs"], _loss_ptr(out), C.byref(a["gg"]),
                                           C.byref(a["pg"]), _stream_ptr(), C.byref(gid)), self._ctx)
         self._graph_refs = getattr(self, "_graph_refs", {})
         self._graph_refs[gid.value] = (a, out, self._ws)
@@ -331,7 +377,7 @@ class Rasterizer:
                                                                 "g_opacity_logits", "g_rgb")])
             pg = _abi.PoseGrads(*[_ptr(out.get(k)) for k in ("dq_t", "dt", "dq_c", "dc")])
             st = _ABI.gsr_render_loss_grad(self._ctx, C.byref(gs), C.byref(views), C.byref(o), C.byref(tg), ws,
-                                           imgs, _ptr(out["loss"]), C.byref(gg), C.byref(pg), _stream_ptr())
+                                           imgs, _loss_ptr(out), C.byref(gg), C.byref(pg), _stream_ptr())
             _abi.check(st, self._ctx)
             if not check:
                 break
@@ -342,9 +388,13 @@ class Rasterizer:
         return out
 
     def alloc_outputs(self, g: GaussianParams, V: int, P: int, opts: RenderOptions) -> dict:
+        """Output tensors of a fused call.  The library writes V + 1 losses (per
+        view, then their total): `loss` is the per-view view [V] of that
+        buffer and `loss_total` its last entry."""
         dev = self.device
         e = lambda *s: torch.empty(*s, dtype=torch.float32, device=dev)  # noqa: E731
-        out = dict(rgb=e(3 * P), depth=e(P), sil=e(P), loss=torch.empty(V, dtype=torch.float64, device=dev))
+        lbuf = torch.empty(V + 1, dtype=torch.float64, device=dev)
+        out = dict(rgb=e(3 * P), depth=e(P), sil=e(P), loss=lbuf[:V], loss_total=lbuf[V])
         n = g.n
         if opts.gauss_grads:
             out.update(g_means=e(n, 3), g_quats=e(n, 4), g_log_scales=e(*g.log_scales.shape),
@@ -473,7 +523,7 @@ class Rasterizer:
         ws = self._shared_ws(g.n, a["views"], self._opts(opts, g.isotropic, gauss_grads=False))
         hpc = hp.c()
         args = [self._ctx, C.byref(a["gs"]), a["views"].cams, len(cams), _ptr(quat), _ptr(trans), C.byref(a["o"]),
-                C.byref(a["tg"]), ws, a["imgs"], _ptr(out["loss"]), C.byref(a["pg"]), C.byref(hpc), _ptr(state),
+                C.byref(a["tg"]), ws, a["imgs"], _loss_ptr(out), C.byref(a["pg"]), C.byref(hpc), _ptr(state),
                 int(iters), _ptr(hist), _stream_ptr()]
         return args, (a, hpc, ws)
 
@@ -561,7 +611,7 @@ class Rasterizer:
             hpc = hp.c()
             rw = _abi.GaussiansRW(g.n, *[_ptr(t) for t in g.tensors()])
             return [self._ctx, rw, C.byref(a["views"]), C.byref(a["o"]), C.byref(a["tg"]), ws, a["imgs"],
-                    _ptr(out["loss"]), C.byref(a["gg"]), C.byref(hpc), _ptr(state), int(iters), _ptr(hist),
+                    _loss_ptr(out), C.byref(a["gg"]), C.byref(hpc), _ptr(state), int(iters), _ptr(hist),
                     _stream_ptr()], (a, hpc, ws, rw)
 
         if capture:
@@ -619,15 +669,24 @@ class Rasterizer:
 # ---------------------------------------------------------------------------
 # autograd
 # ---------------------------------------------------------------------------
+def _pose_grads(pr: dict, opts: RenderOptions):
+    """The gradients of the pose tensors as passed: (dL/dq at fixed t, dL/dt),
+    or with opts.pose_centre, where the translation tensor is the camera centre,
+    (dL/dq at fixed C, dL/dC)."""
+    if opts.pose_centre:
+        return pr.get("dq_c"), pr.get("dc")
+    return pr.get("dq_t"), pr.get("dt")
+
+
 class _RenderFn(torch.autograd.Function):
     """Images as a differentiable function of the Gaussians and the poses.
     The workspace holding the forward state travels in ctx."""
 
     @staticmethod
-    def forward(ctx, means, quats, log_scales, opacity_logits, rgb, pose_q, pose_t, rast, cams, opts):
+    def forward(ctx, means, quats, log_scales, opacity_logits, rgb, pose_q, pose_t, rast, cams, opts, check):
         g = GaussianParams(means.detach(), quats.detach(), log_scales.detach(), opacity_logits.detach(),
                            rgb.detach())
-        img, depth, sil, ws_pair = rast.forward(g, pose_q.detach(), pose_t.detach(), cams, opts)
+        img, depth, sil, ws_pair = rast.forward(g, pose_q.detach(), pose_t.detach(), cams, opts, check=check)
         ctx.rast, ctx.cams, ctx.opts, ctx.ws_pair = rast, cams, opts, ws_pair
         ctx.save_for_backward(means, quats, log_scales, opacity_logits, rgb, pose_q, pose_t, img, depth, sil)
         return img, depth, sil
@@ -642,45 +701,52 @@ class _RenderFn(torch.autograd.Function):
         gr, pr = ctx.rast.backward(g, pose_q, pose_t, ctx.cams, ctx.opts, ctx.ws_pair, (img, depth, sil),
                                    cont(g_img), cont(g_depth), cont(g_sil), gauss_grads=need_g, pose_grads=need_p)
         ctx.ws_pair = None
-        gq = pr.get("dq_t")
-        gt = pr.get("dt")
+        gq, gt = _pose_grads(pr, ctx.opts)
         return (gr.get("means"), gr.get("quats"), gr.get("log_scales"), gr.get("opacity_logits"), gr.get("rgb"),
-                gq, gt, None, None, None)
+                gq, gt, None, None, None, None)
 
 
 def render(rast: Rasterizer, g: GaussianParams, pose_q: torch.Tensor, pose_t: torch.Tensor, cams: Sequence,
-           opts: RenderOptions = RenderOptions()):
-    """(rgb [3*sumP], depth [sumP], sil [sumP]) with autograd to every input tensor."""
+           opts: RenderOptions = RenderOptions(), check: bool = True):
+    """(rgb [3*sumP], depth [sumP], sil [sumP]) with autograd to every input
+    tensor.  With opts.pose_centre, pose_t is the camera centre C and its
+    gradient dL/dC (the pose_q gradient is then taken at fixed C).  check=False
+    skips the host synchronisation that verifies the pair capacity (for
+    timing loops and graph capture; verify with rast.check_overflow())."""
     return _RenderFn.apply(g.means, g.quats, g.log_scales, g.opacity_logits, g.rgb, pose_q, pose_t, rast,
-                           list(cams), opts)
+                           list(cams), opts, check)
 
 
 class _RenderLossFn(torch.autograd.Function):
-    """The fused paper loss: forward computes the loss and, in the same
-    kernels, all its gradients; backward scales them by the upstream scalar."""
+    """The fused loss: the library computes the loss (per view and their FP64
+    total) and, in the same kernels, all its gradients; backward scales them
+    by the upstream scalar."""
 
     @staticmethod
-    def forward(ctx, means, quats, log_scales, opacity_logits, rgb, pose_q, pose_t, rast, cams, targets, opts):
+    def forward(ctx, means, quats, log_scales, opacity_logits, rgb, pose_q, pose_t, rast, cams, targets, opts, check):
         g = GaussianParams(means.detach(), quats.detach(), log_scales.detach(), opacity_logits.detach(),
                            rgb.detach())
         o = RenderOptions(**{**opts.__dict__})
         o.gauss_grads = any(ctx.needs_input_grad[:5])
         o.pose_grads = any(ctx.needs_input_grad[5:7])
-        out = rast.render_loss_grad(g, pose_q.detach(), pose_t.detach(), cams, targets, o)
-        ctx.out = out
-        ctx.mark_non_differentiable
-        return out["loss"].sum().to(torch.float32)
+        out = rast.render_loss_grad(g, pose_q.detach(), pose_t.detach(), cams, targets, o, check=check)
+        ctx.out, ctx.opts = out, o
+        return out["loss_total"]
 
     @staticmethod
     def backward(ctx, gl):
         out = ctx.out
-        s = lambda k: None if out.get(k) is None else out[k] * gl  # noqa: E731
-        return (s("g_means"), s("g_quats"), s("g_log_scales"), s("g_opacity_logits"), s("g_rgb"), s("dq_t"),
-                s("dt"), None, None, None, None)
+        s = lambda t: None if t is None else t * gl.to(t.dtype)  # noqa: E731
+        gq, gt = _pose_grads(out, ctx.opts)
+        return (s(out.get("g_means")), s(out.get("g_quats")), s(out.get("g_log_scales")),
+                s(out.get("g_opacity_logits")), s(out.get("g_rgb")), s(gq), s(gt), None, None, None, None, None)
 
 
 def render_loss(rast: Rasterizer, g: GaussianParams, pose_q, pose_t, cams, targets: dict,
-                opts: RenderOptions = RenderOptions()):
-    """Scalar loss (sum over views) of the paper's combined objective, differentiable."""
+                opts: RenderOptions = RenderOptions(), check: bool = True):
+    """The combined objective (sum over the views of the per-view losses, as
+    the library's FP64 total: a float64 scalar), differentiable.  With
+    opts.pose_centre, pose_t is the camera centre C (see render()).
+    check=False skips the host synchronisation of the pair-capacity check."""
     return _RenderLossFn.apply(g.means, g.quats, g.log_scales, g.opacity_logits, g.rgb, pose_q, pose_t, rast,
-                               list(cams), targets, opts)
+                               list(cams), targets, opts, check)

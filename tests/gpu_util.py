@@ -75,7 +75,7 @@ def to_dev(d, device="cuda"):
 
 
 def _np(a):
-    return a.double().cpu().numpy() if hasattr(a, "double") else np.asarray(a, np.float64)
+    return a.detach().double().cpu().numpy() if hasattr(a, "double") else np.asarray(a, np.float64)
 
 
 def _channel_planes(rgb: np.ndarray, cams) -> list:

@@ -156,3 +156,21 @@ def test_mapping_loop_rejects_a_null_context():
     gid = C.c_int32()
     assert lib.gsr_map_capture(None, rw, None, None, None, ws, imgs, None, None, None, None, 1, None, None,
                                C.byref(gid)) == _abi.GSR_EINVAL
+
+
+def test_flag_values_match_the_header():
+    src = open(os.path.join(ROOT, "include", "gsr.h")).read()
+    flags = dict((k, int(v, 16)) for k, v in re.findall(r"#define (GSR_[A-Z_]+)\s+(0x[0-9a-f]+)u", src))
+    assert flags == {"GSR_ISOTROPIC": _abi.GSR_ISOTROPIC, "GSR_NO_GAUSS_GRADS": _abi.GSR_NO_GAUSS_GRADS,
+                     "GSR_NO_POSE_GRADS": _abi.GSR_NO_POSE_GRADS, "GSR_COUNT_WORK": _abi.GSR_COUNT_WORK,
+                     "GSR_PIXEL_HASH": _abi.GSR_PIXEL_HASH, "GSR_POSE_CENTRE": _abi.GSR_POSE_CENTRE,
+                     "GSR_SYNC": _abi.GSR_SYNC}
+    assert len(set(flags.values())) == len(flags)
+
+
+def test_capacity_calls_reject_a_null_context():
+    lib = _abi.load()
+    o = C.c_int32()
+    k = C.c_int64()
+    assert lib.gsr_check_overflow(None, _abi.Workspace(None, 0, 0), None, C.byref(o)) == _abi.GSR_EINVAL
+    assert lib.gsr_plan(None, None, None, None, _abi.Workspace(None, 0, 0), C.byref(k), None) == _abi.GSR_EINVAL

@@ -1,0 +1,218 @@
+"""The boundary's contract on the GPU: synchronous capacity errors
+(gsr_plan, GSR_SYNC, gsr_check_overflow), the FP64 loss total written by the
+library, camera-centre poses, and the autograd functions' decoupled pose
+gradients, against the oracle."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2408_05635_amd import scenes
+from gpu_util import (GRAD_TOL, IMG_TOL, RES_MARGIN, dev_params, dev_poses, grad_errors, image_errors,
+                      oracle_targets, require_coverage, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rast():
+    from paper_2408_05635_amd import raster
+    return raster.Rasterizer(0)
+
+
+def _opts(w, **kw):
+    from paper_2408_05635_amd.raster import RenderOptions
+    return RenderOptions(**{**w.weights, **kw})
+
+
+def test_plan_returns_the_pairs_a_call_needs(rast):
+    from paper_2408_05635_amd import _abi, raster
+    w = scenes.config2(n_views=2, n=30000)
+    g = dev_params(w.gaussians)
+    q, t = dev_poses(w.views)
+    small = raster.Rasterizer(0, pair_capacity=0)
+    k = small.plan(g, q, t, w.views.cams, _opts(w))
+    assert k > 0 and small.pair_capacity >= k   # the plan grew the capacity
+    # the same count as a checked call reports
+    rast.render_loss_grad(g, q, t, w.views.cams, to_dev(oracle_targets(w)), _opts(w))
+    _, k2, ovf = rast.last_counters
+    assert k2 == k and not ovf
+    # a workspace that holds them: GSR_OK
+    assert small.plan(g, q, t, w.views.cams, _opts(w)) == k
+    # directly through the ABI with too small a workspace: GSR_ECAPACITY and the count
+    views, keep = small._views(w.views.cams, q, t)
+    o = small._opts(_opts(w), False)
+    buf, ws = small.new_workspace(g.n, views, o, 10)
+    kk = C.c_int64(-1)
+    st = _abi.load().gsr_plan(small._ctx, C.byref(small._gauss(g)), C.byref(views), C.byref(o), ws, C.byref(kk),
+                              None)
+    assert st == _abi.GSR_ECAPACITY and kk.value == k
+
+
+def test_sync_flag_returns_ecapacity_and_writes_nothing(rast):
+    from paper_2408_05635_amd import _abi, raster
+    w = scenes.config1()
+    g = dev_params(w.gaussians)
+    q, t = dev_poses(w.views)
+    tg = to_dev(oracle_targets(w))
+    small = raster.Rasterizer(0, pair_capacity=100)
+    P = w.views.cams[0].width * w.views.cams[0].height
+    out = small.alloc_outputs(g, 1, P, _opts(w))
+    for v in out.values():
+        v.fill_(-7.0)
+    with pytest.raises(_abi.GsrError) as ei:
+        small.render_loss_grad(g, q, t, w.views.cams, tg, _opts(w, sync=True), check=False, out=out)
+    assert ei.value.status == _abi.GSR_ECAPACITY
+    assert "pairs needed" in str(ei.value)
+    torch.cuda.synchronize()
+    for k, v in out.items():
+        assert torch.all(v == -7.0), k   # no output was written
+    # the forward alone too
+    with pytest.raises(_abi.GsrError) as ei:
+        small.forward(g, q, t, w.views.cams, _opts(w, sync=True), check=False)
+    assert ei.value.status == _abi.GSR_ECAPACITY
+    # with enough capacity the synchronous call is the plain call, bit for bit
+    a = rast.render_loss_grad(g, q, t, w.views.cams, tg, _opts(w, sync=True), check=False)
+    a = {k: v.clone() for k, v in a.items()}
+    b = rast.render_loss_grad(g, q, t, w.views.cams, tg, _opts(w), check=True)
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_check_overflow_after_an_asynchronous_call(rast):
+    from paper_2408_05635_amd import raster
+    w = scenes.config1()
+    g = dev_params(w.gaussians)
+    q, t = dev_poses(w.views)
+    tg = to_dev(oracle_targets(w))
+    small = raster.Rasterizer(0, pair_capacity=100)
+    small.render_loss_grad(g, q, t, w.views.cams, tg, _opts(w), check=False)
+    assert small.check_overflow() is True
+    rast.render_loss_grad(g, q, t, w.views.cams, tg, _opts(w), check=False)
+    assert rast.check_overflow() is False
+
+
+def test_sync_flag_is_refused_in_graph_capture(rast):
+    from paper_2408_05635_amd import _abi
+    w = scenes.config1()
+    g = dev_params(w.gaussians)
+    q, t = dev_poses(w.views)
+    tg = to_dev(oracle_targets(w))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with pytest.raises(_abi.GsrError) as ei:
+            rast.capture_graph(g, q, t, w.views.cams, tg, _opts(w, sync=True))
+        assert ei.value.status == _abi.GSR_EINVAL and "GSR_SYNC" in str(ei.value)
+    torch.cuda.synchronize()
+
+
+def test_loss_total_is_the_view_sum_in_view_order(rast):
+    w = scenes.config2(n_views=3, n=30000)
+    g = dev_params(w.gaussians)
+    q, t = dev_poses(w.views)
+    out = rast.render_loss_grad(g, q, t, w.views.cams, to_dev(oracle_targets(w)), _opts(w))
+    per = out["loss"].cpu().numpy()
+    tot = 0.0
+    for x in per:
+        tot += float(x)
+    assert out["loss"].numel() == 3 and out["loss_total"].dim() == 0
+    assert float(out["loss_total"].item()) == tot and tot > 0
+
+
+def _centre_workload():
+    """config1 with each pose given as (q, C), C = -R(q)^T t rounded to
+    float32; the oracle renders the same (q, t = -R(q) C) in FP64."""
+    w = scenes.config1()
+    q32 = np.asarray(w.views.quat, np.float32)
+    t64 = np.asarray(w.views.trans, np.float64)
+    R = oracle.quat_to_rot(q32[0].astype(np.float64))
+    C32 = (-(R.T @ t64[0])).astype(np.float32)[None, :]
+    t_or = -(R @ C32[0].astype(np.float64))[None, :]
+    wo = scenes.Workload(w.name, w.gaussians, scenes.Views(w.views.cams, q32, t_or), w.target_views,
+                         weights=w.weights)
+    return w, wo, q32, C32
+
+
+def test_camera_centre_autograd_matches_the_oracle(rast):
+    """render_loss with the camera-centre pose form: the gradients of the pose
+    tensors are the decoupled ones (dL/dq at fixed C, dL/dC), and the loss is
+    the library's FP64 total."""
+    from paper_2408_05635_amd import raster
+    w, wo, q32, C32 = _centre_workload()
+    tg = oracle_targets(w)
+    r = oracle.run(wo.gaussians, wo.views, oracle.Options(**w.weights), oracle.Targets(tg["rgb"], tg["depth"], tg["sil"]),
+                   want_grads=True, mask_ambiguous=True, res_margin=RES_MARGIN)
+    ok = r.ambiguous == 0
+    require_coverage(ok, 0.9, "camera-centre autograd")
+    gp = dev_params(w.gaussians)
+    for tt in gp.tensors():
+        tt.requires_grad_(True)
+    q = torch.from_numpy(q32).cuda().requires_grad_(True)
+    c = torch.from_numpy(C32).cuda().requires_grad_(True)
+    tgd = to_dev({**tg, "weight": ok.astype(np.float32)})
+    loss = raster.render_loss(rast, gp, q, c, w.views.cams, tgd, _opts(w, pose_centre=True))
+    assert loss.dtype == torch.float64 and loss.dim() == 0
+    le = abs(loss.item() - float(r.loss.sum())) / abs(float(r.loss.sum()))
+    loss.backward()
+    got = dict(g_means=gp.means.grad, g_quats=gp.quats.grad, g_log_scales=gp.log_scales.grad,
+               g_opacity_logits=gp.opacity_logits.grad, g_rgb=gp.rgb.grad, dq_c=q.grad, dc=c.grad)
+    ge = grad_errors(got, r.grads, keys=["means", "quats", "log_scales", "opacity_logits", "rgb", "dq_c", "dc"])
+    print(f"camera-centre render_loss: loss rel err {le:.2e}, grads {ge}")
+    assert le <= IMG_TOL
+    assert max(ge.values()) <= GRAD_TOL, ge
+    # (q, t) poses through the same function give the coupled gradients
+    ro = oracle.run(w.gaussians, w.views, oracle.Options(**w.weights), oracle.Targets(tg["rgb"], tg["depth"], tg["sil"]),
+                    want_grads=True, mask_ambiguous=True, res_margin=RES_MARGIN)
+    ok2 = ro.ambiguous == 0
+    require_coverage(ok2, 0.9, "(q, t) autograd")
+    qa = torch.from_numpy(q32).cuda().requires_grad_(True)
+    ta = torch.from_numpy(np.asarray(w.views.trans, np.float32)).cuda().requires_grad_(True)
+    loss2 = raster.render_loss(rast, dev_params(w.gaussians), qa, ta, w.views.cams,
+                               to_dev({**tg, "weight": ok2.astype(np.float32)}), _opts(w))
+    loss2.backward()
+    ge2 = grad_errors(dict(dq_t=qa.grad, dt=ta.grad), ro.grads, keys=["dq_t", "dt"])
+    print("(q, t) render_loss pose grads", ge2)
+    assert max(ge2.values()) <= GRAD_TOL, ge2
+
+
+def test_camera_centre_render_and_split_backward(rast):
+    """render() with (q, C) poses: the same images as the oracle at
+    t = -R C, and the decoupled pose gradients from the split backward."""
+    from paper_2408_05635_amd import raster
+    w, wo, q32, C32 = _centre_workload()
+    tg = oracle_targets(w)
+    r = oracle.run(wo.gaussians, wo.views, oracle.Options(**w.weights), oracle.Targets(tg["rgb"], tg["depth"], tg["sil"]),
+                   want_grads=True, mask_ambiguous=True, res_margin=RES_MARGIN)
+    ok = r.ambiguous == 0
+    q = torch.from_numpy(q32).cuda().requires_grad_(True)
+    c = torch.from_numpy(C32).cuda().requires_grad_(True)
+    img, depth, sil = raster.render(rast, dev_params(w.gaussians), q, c, w.views.cams, _opts(w, pose_centre=True),
+                                    check=False)
+    assert rast.check_overflow() is False
+    ie = image_errors(dict(rgb=img, depth=depth, sil=sil), r, w.views.cams, r.decision_ambiguous == 0, 0.9,
+                      "camera-centre render")
+    assert max(ie.values()) <= IMG_TOL, ie
+    cam = w.views.cams[0]
+    P = cam.width * cam.height
+    okf = ok.astype(np.float64)
+    dm = (tg["depth"] > 0).astype(np.float64)
+    g_rgb = (okf * dm * w.weights["w_rgb"] / P)[None, :] * np.sign(r.rgb.reshape(3, P) - tg["rgb"].reshape(3, P))
+    g_depth = okf * dm * w.weights["w_depth"] / P * np.sign(r.depth - tg["depth"])
+    g_sil = okf * w.weights["w_sil"] / P * np.sign(r.sil - tg["sil"])
+    up = [torch.from_numpy(a.reshape(-1).astype(np.float32)).cuda() for a in (g_rgb, g_depth, g_sil)]
+    torch.autograd.backward([img, depth, sil], up)
+    ge = grad_errors(dict(dq_c=q.grad, dc=c.grad), r.grads, keys=["dq_c", "dc"])
+    print("camera-centre split backward", ge)
+    assert max(ge.values()) <= GRAD_TOL, ge
+
+
+def test_tracking_loop_refuses_camera_centre_poses(rast):
+    from paper_2408_05635_amd import _abi
+    w = scenes.config1()
+    g = dev_params(w.gaussians)
+    q, t = dev_poses(w.views)
+    with pytest.raises(_abi.GsrError) as ei:
+        rast.track(g, q, t, w.views.cams, to_dev(oracle_targets(w)), _opts(w, pose_centre=True), iters=2)
+    assert ei.value.status == _abi.GSR_EUNSUPPORTED
