@@ -230,6 +230,28 @@ gsr_status gsr_render_loss_grad(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_
                                 gsr_images out, double *loss, gsr_gaussian_grads *gg, gsr_pose_grads *pg,
                                 void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): gsr_render_loss_grad()
+ * with no workspace argument.  The library uses a static scratch of 128 MiB
+ * per device instead, a device array held by the loaded module until the
+ * process ends; the call allocates nothing (no device memory, no events).
+ * The pair capacity is the largest whose layout fits the scratch.  Other
+ * arguments and outputs as in gsr_render_loss_grad().  `used` (host, may be
+ * NULL) receives the workspace the call used (the scratch's device address,
+ * its size and that capacity), to pass to gsr_check_overflow() or
+ * gsr_read_counters() afterwards: an overflow leaves the outputs undefined
+ * as on the asynchronous path.  The scratch is shared by every call on the
+ * device and keeps the last call's contents (each call clears what it
+ * needs), so calls that overlap on one device, on different streams or host
+ * threads, race.  Returns GSR_ENOMEM if the call needs more than the scratch
+ * before any pair (too many views x Gaussians or pixels: use a workspace),
+ * GSR_EINVAL with GSR_SYNC, GSR_EUNSUPPORTED if the device has no scratch
+ * (ordinal 64 or above). */
+gsr_status gsr_render_loss_grad_noalloc(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views,
+                                        const gsr_options *opts, const gsr_targets *targets, gsr_images out,
+                                        double *loss, gsr_gaussian_grads *gg, gsr_pose_grads *pg, void *stream,
+                                        gsr_workspace *used);
+
 /* Tile autotuner.  Runs the fused call of gsr_render_loss_grad() (same
  * arguments; opts' tile is ignored) with every supported tile size (16x16,
  * 16x8, 8x16, 8x8) that fits ws, checks each once against the pair capacity

@@ -83,7 +83,7 @@ EXPORTS = ["gsr_create", "gsr_destroy", "gsr_last_error", "gsr_workspace_size", 
            "gsr_graph_capture", "gsr_graph_launch", "gsr_graph_destroy", "gsr_pose_opt_init", "gsr_pose_opt_step",
            "gsr_track", "gsr_track_capture", "gsr_map_state_size", "gsr_map_opt_init", "gsr_map_opt_step",
            "gsr_densify_work_size", "gsr_densify", "gsr_map_iterate", "gsr_map_capture", "gsr_plan",
-           "gsr_check_overflow"]
+           "gsr_check_overflow", "gsr_render_loss_grad_noalloc"]
 
 _lib = None
 
@@ -114,6 +114,9 @@ def load() -> C.CDLL:
     lib.gsr_render_loss_grad.argtypes = [_vp, P(Gaussians), P(Views), P(Options), P(Targets), Workspace, Images,
                                          _vp, P(GaussGrads), P(PoseGrads), _vp]
     lib.gsr_render_loss_grad.restype = st
+    lib.gsr_render_loss_grad_noalloc.argtypes = [_vp, P(Gaussians), P(Views), P(Options), P(Targets), Images, _vp,
+                                                 P(GaussGrads), P(PoseGrads), _vp, P(Workspace)]
+    lib.gsr_render_loss_grad_noalloc.restype = st
     lib.gsr_read_counters.argtypes = [_vp, Workspace, _vp, P(C.c_int64), P(C.c_int64), P(C.c_int32)]
     lib.gsr_read_counters.restype = st
     lib.gsr_check_overflow.argtypes = [_vp, Workspace, _vp, P(C.c_int32)]

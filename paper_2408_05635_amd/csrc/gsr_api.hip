@@ -26,6 +26,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -44,8 +45,10 @@ struct gsr_ctx {
     int device;
     int num_cus;
     std::string err;
+    void *scratch = nullptr;                           // this device's static scratch (device address)
     bool timing = false;
     bool capturing = false;                            // no event timing inside a graph capture
+    bool no_alloc = false;                             // a call that must not create events either
     std::map<std::string, std::pair<int, int>> tuned;  // autotuned tile per input shape
     std::map<int32_t, hipGraphExec_t> graphs;          // captured call sequences
     int32_t next_graph = 1;
@@ -74,7 +77,7 @@ struct StageTimer {
     hipStream_t st;
     hipEvent_t a = nullptr, b = nullptr;
     StageTimer(gsr_ctx *c, int s, hipStream_t stream) : ctx(c), stage(s), st(stream) {
-        if (ctx->timing && !ctx->capturing && ctx->recs.size() < 65536) {
+        if (ctx->timing && !ctx->capturing && !ctx->no_alloc && ctx->recs.size() < 65536) {
             a = ctx->take_event();
             b = ctx->take_event();
             if (a && b) (void)hipEventRecord(a, st);
@@ -89,6 +92,17 @@ struct StageTimer {
 };
 
 static std::string g_create_err;
+
+// The workspace of gsr_render_loss_grad_noalloc, for callers that cannot
+// allocate: one array per device, held by the loaded module until the
+// process ends.  Its name is not a device address in host code; the device
+// address of each device's copy is looked up once (gsr_create, with that
+// device current) and kept in g_scratch_ptr.
+constexpr size_t kStaticScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxScratchDevices] = {};
 
 namespace {
 
@@ -1401,9 +1415,27 @@ gsr_status gsr_create(gsr_ctx **out, int device) {
         g_create_err = std::string("hipGetDeviceProperties: ") + hipGetErrorString(e);
         return GSR_EHIP;
     }
+    void *sp = nullptr;
+    if (device < kMaxScratchDevices) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            int prev = 0;
+            e = hipGetDevice(&prev);
+            if (e == hipSuccess) e = hipSetDevice(device);
+            if (e == hipSuccess) e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+            if (e == hipSuccess) e = hipSetDevice(prev);
+            if (e != hipSuccess) {
+                g_create_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+                return GSR_EHIP;
+            }
+            g_scratch_ptr[device] = sp;
+        }
+        sp = g_scratch_ptr[device];
+    }
     gsr_ctx *c = new gsr_ctx;
     c->device = device;
     c->num_cus = prop.multiProcessorCount;
+    c->scratch = sp;
     *out = c;
     return GSR_OK;
 }
@@ -1499,6 +1531,49 @@ gsr_status gsr_render_loss_grad(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_
         opts = &o_res;
     }
     return render_loss_grad_impl(ctx, g, views, opts, targets, ws, out, loss, gg, pg, stream);
+}
+
+// The fused call with the device's static scratch as its workspace: the pair
+// capacity is the largest whose layout fits the scratch.  No allocation of
+// any kind (no device memory, no events); GSR_SYNC is refused because the
+// host wait it adds would copy through the runtime's staging memory.
+gsr_status gsr_render_loss_grad_noalloc(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *views,
+                                        const gsr_options *opts, const gsr_targets *targets, gsr_images out,
+                                        double *loss, gsr_gaussian_grads *gg, gsr_pose_grads *pg, void *stream,
+                                        gsr_workspace *used) {
+    if (!ctx) return GSR_EINVAL;
+    if (!ctx->scratch) return fail(ctx, GSR_EUNSUPPORTED, "no static scratch on device %d", ctx->device);
+    if (!g || !views || !opts) return fail(ctx, GSR_EINVAL, "g, views and opts must not be NULL");
+    if (opts->flags & GSR_SYNC) return fail(ctx, GSR_EINVAL, "the static-scratch call does not accept GSR_SYNC");
+    const gsr_options o = resolve_tile(ctx, g->n, views, opts);
+    gsr_status s = validate_views(ctx, views, &o);
+    if (s != GSR_OK) return s;
+    if (g->n < 0) return fail(ctx, GSR_EINVAL, "n must be >= 0 (got %lld)", (long long)g->n);
+    if ((int64_t)views->n_views * g->n >= (int64_t)0xffffffffLL)
+        return fail(ctx, GSR_EUNSUPPORTED, "views x Gaussians must be < 2^32");
+    ViewTable tab;
+    build_table(views, &o, tab);
+    const size_t base = make_layout(g->n, tab, 0).total;
+    if (base > kStaticScratchBytes)
+        return fail(ctx, GSR_ENOMEM,
+                    "this call needs %zu bytes before any pair, the static scratch holds %zu (%zu MiB): use "
+                    "gsr_render_loss_grad with a workspace",
+                    base, kStaticScratchBytes, kStaticScratchBytes >> 20);
+    // the largest pair capacity whose layout fits (the layout grows with it)
+    int64_t lo = 0, hi = (int64_t)0xfffffffeLL;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (make_layout(g->n, tab, mid).total <= kStaticScratchBytes)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const gsr_workspace ws{ctx->scratch, kStaticScratchBytes, lo};
+    if (used) *used = ws;
+    ctx->no_alloc = true;
+    s = render_loss_grad_impl(ctx, g, views, &o, targets, ws, out, loss, gg, pg, stream);
+    ctx->no_alloc = false;
+    return s;
 }
 
 // Tile autotuner: every candidate is run once (checked against the pair

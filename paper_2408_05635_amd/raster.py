@@ -387,6 +387,20 @@ class Rasterizer:
             self._grow(k)
         return out
 
+    def render_loss_grad_noalloc(self, g: GaussianParams, quat: torch.Tensor, trans: torch.Tensor, cams: Sequence,
+                                 targets: dict, out: dict, opts: RenderOptions = RenderOptions()) -> _abi.Workspace:
+        """gsr_render_loss_grad_noalloc: the fused call on the device's static
+        scratch (the library allocates nothing; `out` comes from
+        alloc_outputs).  Returns the workspace the call used, for
+        check_overflow() and read_counters()."""
+        a = self._fused_args(g, quat, trans, cams, targets, opts, out)
+        used = _abi.Workspace()
+        _abi.check(_ABI.gsr_render_loss_grad_noalloc(self._ctx, C.byref(a["gs"]), C.byref(a["views"]),
+                                                     C.byref(a["o"]), C.byref(a["tg"]), a["imgs"], _loss_ptr(out),
+                                                     C.byref(a["gg"]), C.byref(a["pg"]), _stream_ptr(),
+                                                     C.byref(used)), self._ctx)
+        return used
+
     def alloc_outputs(self, g: GaussianParams, V: int, P: int, opts: RenderOptions) -> dict:
         """Output tensors of a fused call.  The library writes V + 1 losses (per
         view, then their total): `loss` is the per-view view [V] of that
