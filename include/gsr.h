@@ -115,6 +115,14 @@ typedef enum {
 #define GSR_SYNC           0x40u /* the call waits for its binning and returns GSR_ECAPACITY
                                     (no output written) if the pairs exceed the workspace's
                                     capacity; not allowed inside a graph capture */
+#define GSR_DETERMINISTIC  0x80u /* gradients bit-reproducible run to run: each (tile, list
+                                    entry) writes its partials to a row of its own and every
+                                    Gaussian sums its rows in a fixed order.  Without it the
+                                    backward sums each entry over a tile's pixels (wave and
+                                    workgroup reductions) and adds the sums to the Gaussian's
+                                    row with global float atomics, whose order varies (results
+                                    differ in the last bits).  A gsr_backward() must use the
+                                    flag of the gsr_forward() it follows. */
 
 /* stages reported by gsr_read_timing() */
 #define GSR_STAGE_BINNING     0  /* projection, compaction, depth sort, records, pairs, tile sort, ranges */

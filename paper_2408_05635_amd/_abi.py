@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(_HERE, "libgsr.so")
 GSR_OK, GSR_EINVAL, GSR_ENOMEM, GSR_ECAPACITY, GSR_EHIP, GSR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 GSR_MAX_VIEWS = 64
 GSR_ISOTROPIC, GSR_NO_GAUSS_GRADS, GSR_NO_POSE_GRADS, GSR_COUNT_WORK, GSR_PIXEL_HASH = 0x1, 0x2, 0x4, 0x8, 0x10
-GSR_POSE_CENTRE, GSR_SYNC = 0x20, 0x40
+GSR_POSE_CENTRE, GSR_SYNC, GSR_DETERMINISTIC = 0x20, 0x40, 0x80
 STAGES = ("binning", "blend_fwd", "blend_bwd", "project_bwd")
 
 _fp = C.POINTER(C.c_float)

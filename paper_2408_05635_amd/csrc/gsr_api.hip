@@ -126,7 +126,7 @@ struct Layout {
     int32_t G;            // total blend blocks
     int tile_bits;        // key bits of the tile sort
     size_t views, poses, counters, cnt, zkey, dk0, dv0, dk1, dv1, inv, rec, trect, cnt_s, poff, pk0, pv0, pk1, pv1,
-        chunk, ranges, torder, cpoff, work, nwork, cp, tfinal, nlast, phash, gpairs, rgrad, losst, poseblk, scounts,
+        chunk, ranges, torder, cpoff, work, nwork, cp, tfinal, nlast, phash, gpairs, rrows, rgrad, losst, poseblk, scounts,
         stotals, sync;
     int64_t cp_slots;     // checkpoint slots of split lists (each: the tile's pixels x 6 floats)
     int64_t work_cap;     // backward work items at most: one per tile plus one per slot
@@ -224,6 +224,7 @@ void build_table(const gsr_views *views, const gsr_options *opts, ViewTable &vt)
     vt.tile_w = opts->tile_w;
     vt.tile_h = opts->tile_h;
     vt.pose_centre = (opts->flags & GSR_POSE_CENTRE) ? 1 : 0;
+    vt.deterministic = (opts->flags & GSR_DETERMINISTIC) ? 1 : 0;
     int64_t pix = 0;
     int32_t tiles = 0, blocks = 0;
     const int spt = (opts->tile_w / kBlk) * (opts->tile_h / kBlk);
@@ -304,7 +305,10 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     L.tfinal = take(4 * (size_t)L.P);
     L.nlast = take(4 * (size_t)L.P);
     L.phash = take(4 * (size_t)L.P);
-    L.gpairs = take(40 * kc);
+    // the backward's 2D gradient rows: one per (tile, entry) pair with
+    // GSR_DETERMINISTIC, else one per record (kRowStride floats each)
+    L.gpairs = take(vt.deterministic ? 4 * kRowStride * kc : 0);
+    L.rrows = take(vt.deterministic ? 0 : 4 * kRowStride * vn);
     L.rgrad = take(4 * kRecGrad * vn);
     L.losst = take(sizeof(double) * (size_t)L.T);
     L.poseblk = take(sizeof(double) * 12 * V * (size_t)std::max<int64_t>(
@@ -409,7 +413,8 @@ __global__ __launch_bounds__(256) void k_gather(ProjParams pp, const ViewTable *
                                                 const PoseF64 *__restrict__ poses, const int64_t *__restrict__ counters,
                                                 const uint32_t *__restrict__ sorted_gid, float4 *__restrict__ rec,
                                                 uint2 *__restrict__ trect, uint32_t *__restrict__ cnt_s,
-                                                uint32_t *__restrict__ inv, const float *__restrict__ rgb) {
+                                                uint32_t *__restrict__ inv, const float *__restrict__ rgb,
+                                                float *__restrict__ rrows) {
     const int64_t M = counters[kCntVisible];
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < M; s += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t gid = sorted_gid[s];
@@ -427,6 +432,11 @@ __global__ __launch_bounds__(256) void k_gather(ProjParams pp, const ViewTable *
         trect[s] = make_uint2(a, b);
         cnt_s[s] = c;
         inv[gid] = (uint32_t)s;
+        if (rrows) {   // the backward's atomics add into this record's row
+            float2 *z = reinterpret_cast<float2 *>(rrows + kRowStride * (size_t)s);
+#pragma unroll
+            for (int k = 0; k < kRowStride / 2; ++k) z[k] = make_float2(0.0f, 0.0f);
+        }
     }
 }
 
@@ -636,13 +646,16 @@ struct GradOut {
 // a long range alone.  Both row sums are deterministic.
 constexpr uint32_t kLongRows = 32;
 
-template <bool ISO, int NV>
+// ATOMIC: the record's 2D gradient is its own row of gpairs (kRowStride
+// floats, summed there by the blend's atomics), which is read and cleared
+// again, so that a second backward on the same forward state starts from zero.
+template <bool ISO, int NV, bool ATOMIC>
 __global__ __launch_bounds__(256) void k_record_bwd(ProjParams pp, const ViewTable *__restrict__ vt,
                                                     const PoseF64 *__restrict__ poses,
                                                     const uint32_t *__restrict__ gid_sorted,
                                                     const uint32_t *__restrict__ poff,
                                                     const uint32_t *__restrict__ cnt_s,
-                                                    const float *__restrict__ gpairs, const int64_t *__restrict__ counters,
+                                                    float *__restrict__ gpairs, const int64_t *__restrict__ counters,
                                                     float *__restrict__ rgrad, double *__restrict__ pose_blocks,
                                                     bool want_gauss, bool want_pose) {
     __shared__ double s_pose[GSR_MAX_VIEWS * 12];
@@ -667,7 +680,15 @@ __global__ __launch_bounds__(256) void k_record_bwd(ProjParams pp, const ViewTab
         float r2[NV];   // the record's row sum (NV partials; 6 = pose only: 0..4 and depth)
 #pragma unroll
         for (int c = 0; c < NV; ++c) r2[c] = 0.0f;
-        if (nrow <= kLongRows) {   // rows in order; four rows' loads in flight at once
+        if constexpr (ATOMIC) {
+            if (valid && have_pairs) {
+                float *row = gpairs + kRowStride * (size_t)s;
+#pragma unroll
+                for (int c = 0; c < NV; ++c) r2[c] = row[c];
+#pragma unroll
+                for (int c = 0; c < NV; ++c) row[c] = 0.0f;
+            }
+        } else if (nrow <= kLongRows) {   // rows in order; four rows' loads in flight at once
             uint32_t jj = j0;
             const uint32_t end = j0 + nrow;
             for (; jj + 4 <= end; jj += 4) {
@@ -686,7 +707,7 @@ __global__ __launch_bounds__(256) void k_record_bwd(ProjParams pp, const ViewTab
                 for (int c = 0; c < NV; ++c) r2[c] += row[c];
             }
         }
-        uint64_t longm = ballot(nrow > kLongRows);
+        uint64_t longm = ATOMIC ? 0ull : ballot(nrow > kLongRows);
         while (longm) {   // wave-uniform loop over this wave's long records
             const int src = __builtin_ctzll(longm);
             longm &= longm - 1;
@@ -1085,7 +1106,8 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     if (L.vn > 0)
         hipLaunchKernelGGL(c.pp.iso ? k_gather<true> : k_gather<false>, dim3(grid_for(L.vn, 256, 8192)), dim3(256),
                            0, st, c.pp, vt, poses, counters,
-                           gid_sorted, rec, trect, cnt_s, inv, c.pp.g.rgb);
+                           gid_sorted, rec, trect, cnt_s, inv, c.pp.g.rgb,
+                           c.tab.deterministic ? nullptr : at<float>(ws, L.rrows));
     uint32_t *pk0 = at<uint32_t>(ws, L.pk0), *pv0 = at<uint32_t>(ws, L.pv0);
     uint32_t *pk1 = at<uint32_t>(ws, L.pk1), *pv1 = at<uint32_t>(ws, L.pv1);
     uint32_t *poff = at<uint32_t>(ws, L.poff);
@@ -1136,13 +1158,26 @@ void enqueue_blend_fwd(Call &c, gsr_images out) {
     }
 }
 
+// The backward blend's instantiation for a call.
+template <int NV, bool ATOMIC>
+auto blend_bwd_kernel(bool fused, bool count) {
+    return fused ? (count ? k_blend_bwd<true, true, NV, ATOMIC> : k_blend_bwd<true, false, NV, ATOMIC>)
+                 : (count ? k_blend_bwd<false, true, NV, ATOMIC> : k_blend_bwd<false, false, NV, ATOMIC>);
+}
+template <int NV, bool ATOMIC>
+auto record_bwd_kernel(bool iso) {
+    return iso ? k_record_bwd<true, NV, ATOMIC> : k_record_bwd<false, NV, ATOMIC>;
+}
+
 void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, gsr_images out, LossIn li,
                       bool fused, gsr_gaussian_grads *gg, gsr_pose_grads *pg, const PoseOpt *po = nullptr) {
     const Layout &L = c.L;
     hipStream_t st = c.st;
     ViewTable *vt = at<ViewTable>(c.ws, L.views);
     int64_t *counters = at<int64_t>(c.ws, L.counters);
-    float *gpairs = at<float>(c.ws, L.gpairs);
+    // 2D gradient rows: per (tile, entry) pair (GSR_DETERMINISTIC) or per record (atomics)
+    const bool atomic = !c.tab.deterministic;
+    float *gpairs = atomic ? at<float>(c.ws, L.rrows) : at<float>(c.ws, L.gpairs);
     li.loss_tile = at<double>(c.ws, L.losst);
     GradOut go;
     memset(&go, 0, sizeof(go));
@@ -1158,11 +1193,10 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
         const unsigned grid = (unsigned)(((L.work_cap + 7) / 8) * 8);   // the items past n_work leave at once
         const unsigned threads = (unsigned)(64 * (opts->tile_w / kBlk) * (opts->tile_h / kBlk));
         if (grid > 0 && L.kcap > 0 && L.T > 0) {
-            auto kern =
-                pose_only ? (fused ? (c.count ? k_blend_bwd<true, true, 6> : k_blend_bwd<true, false, 6>)
-                                   : (c.count ? k_blend_bwd<false, true, 6> : k_blend_bwd<false, false, 6>))
-                          : (fused ? (c.count ? k_blend_bwd<true, true, 10> : k_blend_bwd<true, false, 10>)
-                                   : (c.count ? k_blend_bwd<false, true, 10> : k_blend_bwd<false, false, 10>));
+            auto kern = pose_only ? (atomic ? blend_bwd_kernel<6, true>(fused, c.count)
+                                            : blend_bwd_kernel<6, false>(fused, c.count))
+                                  : (atomic ? blend_bwd_kernel<10, true>(fused, c.count)
+                                            : blend_bwd_kernel<10, false>(fused, c.count));
             hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, vt, at<float4>(c.ws, L.rec), pair_values(c),
                                at<uint32_t>(c.ws, L.poff), at<uint2>(c.ws, L.trect), at<uint2>(c.ws, L.ranges),
                                at<uint32_t>(c.ws, L.work), at<int64_t>(c.ws, L.nwork), at<uint32_t>(c.ws, L.cpoff),
@@ -1174,9 +1208,12 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
     StageTimer timer(c.ctx, kStageProjectBwd, st);
     const unsigned rec_blocks = std::min<unsigned>(grid_for(L.vn, 256, 1ll << 30), kRecBwdMaxBlocks);
     double *pose_blocks = at<double>(c.ws, L.poseblk);
-    if (c.pp.n > 0 && (go.want_gauss || go.want_pose))
-        hipLaunchKernelGGL(pose_only ? (c.pp.iso ? k_record_bwd<true, 6> : k_record_bwd<false, 6>)
-                                     : (c.pp.iso ? k_record_bwd<true, 10> : k_record_bwd<false, 10>),
+    // with atomics the record rows are also cleared here, so this runs whenever the blend did
+    if (c.pp.n > 0 && (go.want_gauss || go.want_pose || (atomic && L.kcap > 0 && L.T > 0)))
+        hipLaunchKernelGGL(pose_only ? (atomic ? record_bwd_kernel<6, true>(c.pp.iso)
+                                               : record_bwd_kernel<6, false>(c.pp.iso))
+                                     : (atomic ? record_bwd_kernel<10, true>(c.pp.iso)
+                                               : record_bwd_kernel<10, false>(c.pp.iso)),
                            dim3(rec_blocks), dim3(256), 0, st,
                            c.pp, vt, at<PoseF64>(c.ws, L.poses),
                            depth_sorted_gid(c), at<uint32_t>(c.ws, L.poff), at<uint32_t>(c.ws, L.cnt_s), gpairs,

@@ -348,11 +348,16 @@ __device__ __forceinline__ void quad_sums(float (&d)[NV]) {
 
 constexpr int kBwdMaxWaves = 4;
 constexpr int kSeg = 48;   // list entries per segment
+constexpr int kRowStride = 10;   // floats per record row of the atomic backward (NV of them used)
 
 // NV = 10: all partials per entry (dL/d of the conic factors and mean, opacity,
 // colour, depth).  NV = 6 (pose only): the opacity and colour partials do not
 // reach the pose, so only (0..4, depth) are formed, reduced and written.
-template <bool FUSED, bool COUNT, int NV>
+// ATOMIC: instead of a row per (tile, entry), each entry's sum over the tile
+// is added with global float atomics (skipping exact zeros) to its record's
+// row, grad_pairs[kRowStride * record], zeroed by the gather; entries no pixel
+// reaches cost nothing.  The sums then arrive in a varying order.
+template <bool FUSED, bool COUNT, int NV, bool ATOMIC>
 __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__ vt, const float4 *__restrict__ rec,
                                                    const uint32_t *__restrict__ pair_rec,
                                                    const uint32_t *__restrict__ poff, const uint2 *__restrict__ trect,
@@ -500,13 +505,14 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
     auto row_of = [&](uint32_t e) -> uint32_t {
         const uint32_t s = pair_rec[e];
         if (s >= n_rec) return ~0u;   // never expected; keeps writes in bounds
+        if constexpr (ATOMIC) return s;   // the record's own row
         const uint2 tr = trect[s];
         const uint32_t tx0 = tr.x & 0xffffu, nx = (tr.x >> 16) - tx0 + 1u, ty0 = tr.y & 0xffffu;
         const uint32_t j = poff[s] + ((uint32_t)ty - ty0) * nx + ((uint32_t)tx - tx0);
         return j < n_pair ? j : ~0u;
     };
     // entries behind every pixel's last contributor get zero rows
-    for (uint32_t e = top + threadIdx.x; e < hi; e += blockDim.x) {
+    for (uint32_t e = top + threadIdx.x; !ATOMIC && e < hi; e += blockDim.x) {
         const uint32_t j = row_of(e);
         if (j == ~0u) continue;
         float *dst = grad_pairs + NV * (size_t)j;
@@ -644,7 +650,11 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
             float sum = 0.0f;
             for (int w = 0; w < nw; ++w) sum += s_acc[w][idx];
             const uint32_t j = s_j[e];
-            if (j != ~0u) grad_pairs[NV * (size_t)j + c] = sum;
+            if constexpr (ATOMIC) {
+                if (j != ~0u && sum != 0.0f) atomicAdd(&grad_pairs[kRowStride * (size_t)j + c], sum);
+            } else {
+                if (j != ~0u) grad_pairs[NV * (size_t)j + c] = sum;
+            }
         }
         __syncthreads();
         seg_hi = seg_lo;

@@ -33,7 +33,8 @@ struct ViewTable {
     int32_t total_tiles;
     int32_t total_blocks;
     int32_t pose_centre;   // GSR_POSE_CENTRE: the pose translation input is the camera centre C
-    int32_t pad[2];
+    int32_t deterministic; // GSR_DETERMINISTIC: per-pair gradient rows summed in a fixed order
+    int32_t pad;
     ViewInfo v[GSR_MAX_VIEWS];
 };
 

@@ -43,6 +43,8 @@ class RenderOptions:
     pose_centre: bool = False
     # the library waits after its binning and raises GsrError(GSR_ECAPACITY) on overflow
     sync: bool = False
+    # gradients bit-reproducible run to run (fixed-order sums instead of float atomics)
+    deterministic: bool = False
 
 
 @dataclass
@@ -192,6 +194,8 @@ class Rasterizer:
             flags |= _abi.GSR_POSE_CENTRE
         if o.sync:
             flags |= _abi.GSR_SYNC
+        if o.deterministic:
+            flags |= _abi.GSR_DETERMINISTIC
         return _abi.Options(o.w_rgb, o.w_depth, o.w_sil, o.w_prior, o.z_near, o.blur2d, o.sil_mask_thresh,
                             int(o.tile[0]), int(o.tile[1]), flags)
 

@@ -164,7 +164,7 @@ def test_flag_values_match_the_header():
     assert flags == {"GSR_ISOTROPIC": _abi.GSR_ISOTROPIC, "GSR_NO_GAUSS_GRADS": _abi.GSR_NO_GAUSS_GRADS,
                      "GSR_NO_POSE_GRADS": _abi.GSR_NO_POSE_GRADS, "GSR_COUNT_WORK": _abi.GSR_COUNT_WORK,
                      "GSR_PIXEL_HASH": _abi.GSR_PIXEL_HASH, "GSR_POSE_CENTRE": _abi.GSR_POSE_CENTRE,
-                     "GSR_SYNC": _abi.GSR_SYNC}
+                     "GSR_SYNC": _abi.GSR_SYNC, "GSR_DETERMINISTIC": _abi.GSR_DETERMINISTIC}
     assert len(set(flags.values())) == len(flags)
 
 

@@ -196,7 +196,7 @@ def test_long_lists_walked_in_chunks_only_when_tiles_are_few(rast):
     cams = w.views.cams
     tg = to_dev(oracle_targets(w))
     P = cams[0].width * cams[0].height
-    o = RenderOptions(tile=(16, 16), count_work=True, **w.weights)
+    o = RenderOptions(tile=(16, 16), count_work=True, deterministic=True, **w.weights)
     tiles1 = ((cams[0].width + 15) // 16) * ((cams[0].height + 15) // 16)
     tg1 = {k: v[:(3 * P if k == "rgb" else P)] for k, v in tg.items()}
     one = rast.render_loss_grad(g, q[:1], t[:1], cams[:1], tg1, o)
