@@ -160,7 +160,7 @@ typedef struct {
     float z_near;                          /* near-plane cull (camera-frame z, metres) */
     float blur2d;                          /* added to the 2D covariance diagonal (px^2), >= 0 */
     float sil_mask_thresh;                 /* < 0: off; else photometric/depth terms need S > thresh */
-    int32_t tile_w, tile_h;                /* binning tile in pixels: each 8 or 16; 0 and 0 = the tile
+    int32_t tile_w, tile_h;                /* binning tile in pixels: each 8, 16 or 32; 0 and 0 = the tile
                                               gsr_autotune() chose for this input shape, else 16x16 */
     uint32_t flags;                        /* GSR_* flags */
 } gsr_options;
@@ -261,8 +261,8 @@ gsr_status gsr_render_loss_grad_noalloc(gsr_ctx *ctx, const gsr_gaussians *g, co
                                         gsr_workspace *used);
 
 /* Tile autotuner.  Runs the fused call of gsr_render_loss_grad() (same
- * arguments; opts' tile is ignored) with every supported tile size (16x16,
- * 16x8, 8x16, 8x8) that fits ws, checks each once against the pair capacity
+ * arguments; opts' tile is ignored) with each candidate tile size (16x16,
+ * 16x8, 8x16, 8x8, 32x32, 32x16, 16x32) that fits ws, checks each once against the pair capacity
  * (a synchronisation), times `reps` calls of each with HIP events, and keeps
  * the fastest for this input shape (the views' resolutions, N rounded up to a
  * power of two, the flags); later calls with tile 0x0 use it.  Writes the

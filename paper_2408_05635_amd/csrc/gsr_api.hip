@@ -112,6 +112,7 @@ constexpr size_t kCpBudgetBytes = 96u << 20;   // checkpoints of split lists (th
 constexpr int64_t kSplitMaxTiles = 2048;       // about the backward workgroups resident at once
 constexpr int kRecBwdMaxBlocks = 1024;   // grid cap of the record backward (one pose row per block)
 constexpr int kEmitChunk = 1024;         // pairs per emission block
+constexpr int kTuneCandidates = 7;       // tile shapes the autotuner tries
 // synchronisation region, cleared by every call: scan tickets (256 B) and the
 // scans' look-back words
 constexpr size_t kSyncTickets = 256;
@@ -191,6 +192,8 @@ gsr_options resolve_tile(const gsr_ctx *ctx, int64_t n, const gsr_views *views, 
     return o;
 }
 
+bool tile_side_ok(int s) { return s == 8 || s == 16 || s == 32; }
+
 gsr_status validate_views(gsr_ctx *ctx, const gsr_views *views, const gsr_options *opts) {
     if (!views || !opts) return fail(ctx, GSR_EINVAL, "views and opts must not be NULL");
     if (views->n_views < 1) return fail(ctx, GSR_EINVAL, "n_views must be >= 1 (got %d)", views->n_views);
@@ -206,8 +209,8 @@ gsr_status validate_views(gsr_ctx *ctx, const gsr_views *views, const gsr_option
             return fail(ctx, GSR_EINVAL, "view %d: focal lengths must be finite and > 0", v);
     }
     const int tw = opts->tile_w, th = opts->tile_h;
-    if ((tw != 8 && tw != 16) || (th != 8 && th != 16))
-        return fail(ctx, GSR_EINVAL, "tile size %dx%d: each side must be 8 or 16", tw, th);
+    if (!tile_side_ok(tw) || !tile_side_ok(th))
+        return fail(ctx, GSR_EINVAL, "tile size %dx%d: each side must be 8, 16 or 32", tw, th);
     if (!(opts->blur2d >= 0.f) || !std::isfinite(opts->blur2d))
         return fail(ctx, GSR_EINVAL, "blur2d must be finite and >= 0");
     if (!(opts->z_near >= 0.f) || !std::isfinite(opts->z_near))
@@ -1159,10 +1162,15 @@ void enqueue_blend_fwd(Call &c, gsr_images out) {
 }
 
 // The backward blend's instantiation for a call.
+template <int NV, bool ATOMIC, int WAVES>
+auto blend_bwd_kernel_w(bool fused, bool count) {
+    return fused ? (count ? k_blend_bwd<true, true, NV, ATOMIC, WAVES> : k_blend_bwd<true, false, NV, ATOMIC, WAVES>)
+                 : (count ? k_blend_bwd<false, true, NV, ATOMIC, WAVES> : k_blend_bwd<false, false, NV, ATOMIC, WAVES>);
+}
 template <int NV, bool ATOMIC>
-auto blend_bwd_kernel(bool fused, bool count) {
-    return fused ? (count ? k_blend_bwd<true, true, NV, ATOMIC> : k_blend_bwd<true, false, NV, ATOMIC>)
-                 : (count ? k_blend_bwd<false, true, NV, ATOMIC> : k_blend_bwd<false, false, NV, ATOMIC>);
+auto blend_bwd_kernel(bool fused, bool count, int waves) {
+    return waves <= kBwdWavesSmall ? blend_bwd_kernel_w<NV, ATOMIC, kBwdWavesSmall>(fused, count)
+                                   : blend_bwd_kernel_w<NV, ATOMIC, kBwdWavesLarge>(fused, count);
 }
 template <int NV, bool ATOMIC>
 auto record_bwd_kernel(bool iso) {
@@ -1193,10 +1201,11 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
         const unsigned grid = (unsigned)(((L.work_cap + 7) / 8) * 8);   // the items past n_work leave at once
         const unsigned threads = (unsigned)(64 * (opts->tile_w / kBlk) * (opts->tile_h / kBlk));
         if (grid > 0 && L.kcap > 0 && L.T > 0) {
-            auto kern = pose_only ? (atomic ? blend_bwd_kernel<6, true>(fused, c.count)
-                                            : blend_bwd_kernel<6, false>(fused, c.count))
-                                  : (atomic ? blend_bwd_kernel<10, true>(fused, c.count)
-                                            : blend_bwd_kernel<10, false>(fused, c.count));
+            const int waves = (int)(threads / 64);
+            auto kern = pose_only ? (atomic ? blend_bwd_kernel<6, true>(fused, c.count, waves)
+                                            : blend_bwd_kernel<6, false>(fused, c.count, waves))
+                                  : (atomic ? blend_bwd_kernel<10, true>(fused, c.count, waves)
+                                            : blend_bwd_kernel<10, false>(fused, c.count, waves));
             hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, vt, at<float4>(c.ws, L.rec), pair_values(c),
                                at<uint32_t>(c.ws, L.poff), at<uint2>(c.ws, L.trect), at<uint2>(c.ws, L.ranges),
                                at<uint32_t>(c.ws, L.work), at<int64_t>(c.ws, L.nwork), at<uint32_t>(c.ws, L.cpoff),
@@ -1623,7 +1632,7 @@ gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *v
     if (!ctx) return GSR_EINVAL;
     if (!g || !views || !opts || !best_tile || !ms_per_call) return fail(ctx, GSR_EINVAL, "autotune: NULL argument");
     if (reps < 1) return fail(ctx, GSR_EINVAL, "autotune: reps must be >= 1");
-    static const int cand[4][2] = {{16, 16}, {16, 8}, {8, 16}, {8, 8}};
+    static const int cand[kTuneCandidates][2] = {{16, 16}, {16, 8}, {8, 16}, {8, 8}, {32, 32}, {32, 16}, {16, 32}};
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t a = nullptr, b = nullptr;
     gsr_status s = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
@@ -1631,7 +1640,7 @@ gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_views *v
     if (s == GSR_OK) s = check_hip(ctx, hipEventCreate(&b), "hipEventCreate");
     double best = -1.0;
     int bw = 0, bh = 0;
-    for (int k = 0; k < 4 && s == GSR_OK; ++k) {
+    for (int k = 0; k < kTuneCandidates && s == GSR_OK; ++k) {
         gsr_options o = *opts;
         o.tile_w = cand[k][0];
         o.tile_h = cand[k][1];
@@ -1675,8 +1684,8 @@ gsr_status gsr_set_tile(gsr_ctx *ctx, int64_t n, const gsr_views *views, uint32_
     if (!ctx) return GSR_EINVAL;
     if (!views || !views->cams || views->n_views < 1 || views->n_views > GSR_MAX_VIEWS)
         return fail(ctx, GSR_EINVAL, "set_tile: invalid views");
-    if ((tile_w != 8 && tile_w != 16) || (tile_h != 8 && tile_h != 16))
-        return fail(ctx, GSR_EINVAL, "set_tile: each side must be 8 or 16");
+    if (!tile_side_ok(tile_w) || !tile_side_ok(tile_h))
+        return fail(ctx, GSR_EINVAL, "set_tile: each side must be 8, 16 or 32");
     ctx->tuned[shape_key(n, views, flags)] = {tile_w, tile_h};
     return GSR_OK;
 }

@@ -298,7 +298,7 @@ __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.0f) - (x 
 
 // Backward blend.  One workgroup per work item, a binning tile or one chunk
 // of a split list, one wave per 8x8 block of the tile (tiles are at most
-// 16x16, so at most four waves).  The item's entries are walked in reverse,
+// 32x32, so at most sixteen waves).  The item's entries are walked in reverse,
 // from the last contributor of any pixel of the tile, in segments of kSeg
 // entries; within a segment every wave culls the entries against its own
 // block (one lane per entry), then takes the survivors one by one, reading
@@ -346,7 +346,11 @@ __device__ __forceinline__ void quad_sums(float (&d)[NV]) {
     for (int c = 0; c < NV; ++c) asm volatile("" : "+v"(d[c]));
 }
 
-constexpr int kBwdMaxWaves = 4;
+// Waves of a backward workgroup, one per 8x8 block of the tile: tiles up to
+// 16x16 (or 32x8) take the 4-wave build, larger ones (32x16, 32x32) the
+// 16-wave build, whose LDS arrays are sized for 16 waves.
+constexpr int kBwdWavesSmall = 4;
+constexpr int kBwdWavesLarge = 16;
 constexpr int kSeg = 48;   // list entries per segment
 constexpr int kRowStride = 10;   // floats per record row of the atomic backward (NV of them used)
 
@@ -357,8 +361,8 @@ constexpr int kRowStride = 10;   // floats per record row of the atomic backward
 // is added with global float atomics (skipping exact zeros) to its record's
 // row, grad_pairs[kRowStride * record], zeroed by the gather; entries no pixel
 // reaches cost nothing.  The sums then arrive in a varying order.
-template <bool FUSED, bool COUNT, int NV, bool ATOMIC>
-__global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__ vt, const float4 *__restrict__ rec,
+template <bool FUSED, bool COUNT, int NV, bool ATOMIC, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__restrict__ vt, const float4 *__restrict__ rec,
                                                    const uint32_t *__restrict__ pair_rec,
                                                    const uint32_t *__restrict__ poff, const uint2 *__restrict__ trect,
                                                    const uint2 *__restrict__ ranges,
@@ -372,13 +376,13 @@ __global__ __launch_bounds__(256) void k_blend_bwd(const ViewTable *__restrict__
     // (k, c) adds the 16 quad sums of value c of entry k, in quad order, into
     // s_acc[wave][entry of the segment][c].
     constexpr int kBatch = 40 / NV;   // entries per batch: 4 (NV = 10) or 6 (NV = 6), LDS sized for occupancy
-    __shared__ float s_q[kBwdMaxWaves][kBatch * 16 * NV];
-    __shared__ uint32_t s_bslot[kBwdMaxWaves][kBatch];
-    __shared__ float s_acc[kBwdMaxWaves][kSeg * NV];
-    __shared__ uint32_t s_wmax[kBwdMaxWaves];
+    __shared__ float s_q[WAVES][kBatch * 16 * NV];
+    __shared__ uint32_t s_bslot[WAVES][kBatch];
+    __shared__ float s_acc[WAVES][kSeg * NV];
+    __shared__ uint32_t s_wmax[WAVES];
     __shared__ uint32_t s_j[kSeg];   // gradient-row slot of each entry of the segment
-    __shared__ float2 s_d[kBwdMaxWaves][kSeg];   // per wave: the segment's entries' offsets from the block origin
-    __shared__ double s_loss[kBwdMaxWaves];
+    __shared__ float2 s_d[WAVES][kSeg];   // per wave: the segment's entries' offsets from the block origin
+    __shared__ double s_loss[WAVES];
 
     // work item of this workgroup: the i-th (tile, chunk) of the order, longest
     // first (the hardware deals workgroups to the XCDs in turn, so the long

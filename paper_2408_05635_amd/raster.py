@@ -22,6 +22,9 @@ from . import _abi
 
 _ABI = _abi.load()
 
+# the tile shapes gsr_autotune tries (the order of the sizing calls does not matter)
+TUNE_TILES = ((8, 8), (8, 16), (16, 8), (16, 16), (32, 16), (16, 32), (32, 32))
+
 
 @dataclass
 class RenderOptions:
@@ -303,7 +306,7 @@ class Rasterizer:
         P = total_pixels(cams)
         if out is None:
             out = self.alloc_outputs(g, V, P, opts)
-        for tile in ((8, 8), (8, 16), (16, 8), (16, 16)):
+        for tile in TUNE_TILES:
             self.render_loss_grad(g, quat, trans, cams, targets, RenderOptions(**{**opts.__dict__, "tile": tile}),
                                   check=True, out=out)
         a = self._fused_args(g, quat, trans, cams, targets, opts, out)

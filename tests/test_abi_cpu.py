@@ -63,7 +63,7 @@ def test_workspace_size_grows_with_inputs():
     assert st == _abi.GSR_OK and d > 0
 
 
-@pytest.mark.parametrize("tile", [(4, 16), (16, 12), (32, 16), (0, 8)])
+@pytest.mark.parametrize("tile", [(4, 16), (16, 12), (64, 16), (0, 8), (32, 24)])
 def test_rejects_bad_tiles(tile):
     v, keep = _views(1)
     st, _, msg = _size(1000, v, _opts(*tile), 1000)

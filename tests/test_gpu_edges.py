@@ -117,7 +117,7 @@ def test_one_gaussian_covers_the_image(rast):
     base = scenes.tiny_scene(33, n=4, width=48, height=40)
     w = _workload(g, base.views.cams, base.views.quat, base.views.trans, base.target_views.quat,
                   base.target_views.trans)
-    for tile in ((16, 16), (8, 8)):
+    for tile in ((16, 16), (8, 8), (32, 32)):
         out, r, ok = _run(rast, w, tile)
         _check(out, r, ok, w, f"cover {tile}")
 
@@ -136,7 +136,8 @@ def test_maximum_views_in_one_call(rast):
     _check(out, r, ok, w, "64 views")
 
 
-@pytest.mark.parametrize("W,H,tile", [(1, 1, (16, 16)), (33, 17, (16, 8)), (17, 33, (8, 16)), (9, 7, (8, 8))])
+@pytest.mark.parametrize("W,H,tile", [(1, 1, (16, 16)), (33, 17, (16, 8)), (17, 33, (8, 16)), (9, 7, (8, 8)),
+                                      (45, 37, (32, 32)), (70, 21, (32, 16)), (1, 1, (32, 32))])
 def test_one_pixel_and_ragged_images(rast, W, H, tile):
     base = scenes.tiny_scene(35 + W, n=30, width=W, height=H, spread=0.2)
     w = _workload(base.gaussians, base.views.cams, base.views.quat, base.views.trans, base.target_views.quat,

@@ -124,7 +124,7 @@ def _check_binning(rast, w, tile):
     return mism
 
 
-@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (8, 16)])
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (8, 16), (32, 32), (32, 16), (16, 32)])
 def test_binning_bit_exact_config1(rast, tile):
     assert _check_binning(rast, scenes.config1(), tile) == 0
 
@@ -263,7 +263,7 @@ def test_tile_size_invariance(rast):
     w = scenes.config1()
     tg = oracle_targets(w)
     base = _fused(rast, w, (16, 16), tg)
-    for tile in [(8, 8), (16, 8), (8, 16)]:
+    for tile in [(8, 8), (16, 8), (8, 16), (32, 32), (32, 16), (16, 32)]:
         out = _fused(rast, w, tile, tg)
         for k in ("rgb", "depth", "sil"):
             assert torch.equal(out[k], base[k]), (tile, k)
@@ -344,6 +344,15 @@ def test_config2_full_view_parity(rast, det):
     _fused_parity(rast, w, oracle_targets(w), f"config2 deterministic={det}", deterministic=det)
 
 
+@pytest.mark.parametrize("tile", [(32, 32), (32, 16)])
+def test_config2_view_parity_large_tiles(rast, tile):
+    """The 16-wave backward (tiles with a 32-pixel side) on one 640x480 view,
+    whose 300 (or 600) tiles are few enough that long lists are walked in
+    chunks."""
+    w = scenes.config2(n_views=1)
+    _fused_parity(rast, w, oracle_targets(w), f"config2 tile {tile}", tile=tile)
+
+
 @pytest.mark.timeout(300)
 def test_config3_eight_keyframes_with_depth_prior(rast):
     """The mapping configuration as the bench's mapping leg runs it: 500k
@@ -371,7 +380,7 @@ def test_autotune_and_tuned_calls(rast):
     opts = _opts(w, deterministic=True)
     tile, ms = r2.autotune(g, q, t, w.views.cams, tg, opts, reps=3)
     print("autotuned tile", tile, f"{ms:.3f} ms per call")
-    assert tile in [(16, 16), (16, 8), (8, 16), (8, 8)] and ms > 0
+    assert tile in [(16, 16), (16, 8), (8, 16), (8, 8), (32, 32), (32, 16), (16, 32)] and ms > 0
     auto = r2.render_loss_grad(g, q, t, w.views.cams, tg, _opts(w, (0, 0), deterministic=True))
     auto = {k: v.clone() for k, v in auto.items()}
     expl = r2.render_loss_grad(g, q, t, w.views.cams, tg, _opts(w, tile, deterministic=True))
