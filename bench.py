@@ -84,8 +84,11 @@ def parse():
     ap.add_argument("--no-fd", action="store_true", help="skip the pose finite-difference check")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many batched steps (for a profiler) and print nothing else")
-    ap.add_argument("--profile-workload", default="tracking", choices=["tracking", "uneven", "large"],
-                    help="with --profile-steps: the tracking step, the 32-view uneven batch or the 3M scene")
+    ap.add_argument("--profile-workload", default="tracking", choices=["tracking", "frame", "uneven", "large"],
+                    help="with --profile-steps: the 8-view tracking-room step, one 640x480 view's 40-iteration "
+                         "tracking loop (run profile-steps times, eagerly), the 32-view uneven batch or the 3M scene")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="with --profile-steps: the fixed-order backward (GSR_DETERMINISTIC)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="with --profile-steps: also copy 256 MiB device to device, the reference for the "
                          "HBM byte counters")
@@ -155,7 +158,7 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    if args.profile_steps and args.profile_workload != "tracking":
+    if args.profile_steps and args.profile_workload in ("uneven", "large"):
         profile_uneven(args, raster, scenes, dev)
         return
     w = scenes.config2(n_views=args.views, n=args.n)
@@ -179,7 +182,11 @@ def main():
     else:
         tile = tuple(int(x) for x in args.tile.split("x"))
     tw, th = tile
-    opts = raster.RenderOptions(tile=(tw, th), **w.weights)
+    opts = raster.RenderOptions(tile=(tw, th), deterministic=bool(args.profile_steps and args.deterministic),
+                                **w.weights)
+    if args.profile_steps and args.profile_workload == "frame":
+        profile_frame(args, rast, raster, w, g, q, t, targets, opts)
+        return
     out = rast.render_loss_grad(g, q, t, cams, targets, opts, check=True)   # sizes the pair capacity
     torch.cuda.synchronize()
     M, K, ovf = rast.last_counters
@@ -436,6 +443,21 @@ def uneven_bench(rast, raster, scenes, dev, args):
                                  "large multi-room: 3M anisotropic Gaussians, 16 views at 1200x680, depth prior, "
                                  "fwd+loss+bwd, one graph replay", max(3, reps // 2), 1)
     return res
+
+
+def profile_frame(args, rast, raster, w, g, q, t, targets, opts):
+    """--profile-steps for the tracking frame: one 640x480 view, 40 pose-only
+    iterations with the decoupled step, eagerly (every launch visible to a
+    kernel trace), profile-steps times from the same start pose."""
+    import torch
+    P1 = 640 * 480
+    tg1 = {k: v[:(3 * P1 if k == "rgb" else P1)].contiguous() for k, v in targets.items()}
+    hp = raster.PoseAdam(lr_rot=1e-3, lr_pos=1e-3)
+    for _ in range(args.profile_steps):
+        q1, t1 = q[:1].clone(), t[:1].clone()
+        rast.track(g, q1, t1, [w.views.cams[0]], tg1, opts, hp, 40)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_steps": args.profile_steps, "workload": "frame", "iterations": 40}), flush=True)
 
 
 def profile_uneven(args, raster, scenes, dev):

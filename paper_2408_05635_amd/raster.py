@@ -13,6 +13,8 @@ Conventions (the C ABI's, include/gsr.h): Gaussian parameters are raw
 from __future__ import annotations
 
 import ctypes as C
+import json
+import os
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence, Tuple
 
@@ -131,6 +133,17 @@ def _stream_ptr():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+@dataclass
+class _SizeOnly:
+    """A camera of which only the resolution matters (tuning-cache shapes)."""
+    width: int
+    height: int
+    fx: float = 1.0
+    fy: float = 1.0
+    cx: float = 0.0
+    cy: float = 0.0
+
+
 def total_pixels(cams: Sequence) -> int:
     return int(sum(c.width * c.height for c in cams))
 
@@ -152,6 +165,7 @@ class Rasterizer:
         self.pair_capacity = int(pair_capacity)
         self._ws: Optional[torch.Tensor] = None
         self.last_counters = (0, 0, 0)
+        self.tuning: List[dict] = []   # tile choices of autotune()/set_tile(), for save_tuning()
 
     def __del__(self):
         try:
@@ -317,10 +331,40 @@ class Rasterizer:
         _abi.check(_ABI.gsr_autotune(self._ctx, C.byref(a["gs"]), C.byref(a["views"]), C.byref(a["o"]),
                                      C.byref(a["tg"]), ws, a["imgs"], _loss_ptr(out), C.byref(a["gg"]),
                                      C.byref(a["pg"]), int(reps), best, C.byref(ms), _stream_ptr()), self._ctx)
-        return (int(best[0]), int(best[1])), float(ms.value)
+        tile = (int(best[0]), int(best[1]))
+        self._remember(g.n, cams, tile, g.isotropic, opts.gauss_grads, opts.pose_grads, float(ms.value))
+        return tile, float(ms.value)
+
+    def _remember(self, n, cams, tile, isotropic, gauss_grads, pose_grads, ms=None):
+        e = dict(n=int(n), sizes=[[int(c.width), int(c.height)] for c in cams], tile=list(tile),
+                 isotropic=bool(isotropic), gauss_grads=bool(gauss_grads), pose_grads=bool(pose_grads))
+        self.tuning = [x for x in self.tuning if {**x, "tile": None, "ms": None} != {**e, "tile": None, "ms": None}]
+        if ms is not None:
+            e["ms"] = ms
+        self.tuning.append(e)
+
+    def save_tuning(self, path: str) -> None:
+        """Writes the tile choices made in this process (autotune, set_tile)
+        as JSON, for load_tuning() in a later one."""
+        tmp = path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump({"tiles": self.tuning}, fh, indent=1)
+        os.replace(tmp, path)
+
+    def load_tuning(self, path: str) -> int:
+        """Applies the tile choices of a save_tuning() file through gsr_set_tile
+        (calls with tile (0, 0) then use them); returns how many it applied."""
+        with open(path) as fh:
+            entries = json.load(fh)["tiles"]
+        for e in entries:
+            cams = [_SizeOnly(w, h) for w, h in e["sizes"]]
+            self.set_tile(e["n"], cams, tuple(e["tile"]), e["isotropic"], e["gauss_grads"], e["pose_grads"])
+        return len(entries)
 
     def set_tile(self, n: int, cams, tile: Tuple[int, int], isotropic=False, gauss_grads=True, pose_grads=True):
-        """Record a tile choice for a shape (e.g. loaded from a tuning cache)."""
+        """Record a tile choice for a shape (e.g. loaded from a tuning cache):
+        the Gaussian count's power-of-two class, the views' resolutions and
+        the gradient and isotropy flags form the shape."""
         V = len(cams)
         arr = (_abi.Camera * V)(*[_abi.Camera(int(c.width), int(c.height), float(c.fx), float(c.fy), float(c.cx),
                                               float(c.cy)) for c in cams])
@@ -328,6 +372,7 @@ class Rasterizer:
         flags = (_abi.GSR_ISOTROPIC if isotropic else 0) | (0 if gauss_grads else _abi.GSR_NO_GAUSS_GRADS) | \
             (0 if pose_grads else _abi.GSR_NO_POSE_GRADS)
         _abi.check(_ABI.gsr_set_tile(self._ctx, n, C.byref(views), flags, int(tile[0]), int(tile[1])), self._ctx)
+        self._remember(n, cams, tile, isotropic, gauss_grads, pose_grads)
 
     def capture_graph(self, g: GaussianParams, quat, trans, cams, targets: dict,
                       opts: RenderOptions = RenderOptions(), out: Optional[dict] = None):

@@ -72,6 +72,10 @@ def test_forward_config1(rast):
 
 
 def _check_binning(rast, w, tile):
+    """Records: the visible set of each view equals the oracle's, in (float32
+    depth bits, index) order.  Lists: every tile's list equals the one rebuilt
+    from the GPU's own float32 records (rectangle rule in float32), ordered by
+    (float32 depth bits, index).  Returns the number of mismatching tiles."""
     g = dev_params(w.gaussians)
     q, t = dev_poses(w.views)
     o = _opts(w, tile)
@@ -114,6 +118,7 @@ def _check_binning(rast, w, tile):
         for ty in range(tyn):
             for tx in range(txn):
                 hit = sel[(tx0 <= tx) & (tx <= tx1) & (ty0 <= ty) & (ty <= ty1)]
+                hit = hit[np.lexsort((hit, zb[hit]))]   # (depth bits, index)
                 s, e = ranges[toff + ty * txn + tx]
                 got = pairs[s:e] if e > s else np.zeros(0, np.int64)
                 if not np.array_equal(got, hit):
@@ -132,6 +137,31 @@ def test_binning_bit_exact_config1(rast, tile):
 def test_binning_bit_exact_multiview(rast):
     w = scenes.config2(n_views=3, n=20000)
     assert _check_binning(rast, w, (16, 16)) == 0
+
+
+@pytest.mark.parametrize("capacity", [200_000, 3_000_000])
+def test_binning_bit_exact_long_lists(capacity):
+    """Lists of about 14 000 entries with exact depth ties (groups of seven
+    Gaussians at one float32 depth), broken by index, at two pair capacities
+    (sort blocks of 1024 items up to 2M pairs of capacity, of 4096 above)."""
+    from paper_2408_05635_amd import raster
+    rng = np.random.default_rng(77)
+    n = 14000
+    z = np.repeat(rng.uniform(1.0, 3.0, n // 7), 7).astype(np.float32)   # 7 Gaussians per depth
+    xy = rng.normal(0.0, 0.04, (n, 2)).astype(np.float32) * z[:, None]
+    g = scenes.Gaussians(means=np.concatenate([xy, z[:, None]], 1).astype(np.float32),
+                         quats=scenes.random_unit_quats(rng, n),
+                         log_scales=rng.normal(-3.0, 0.2, (n, 3)).astype(np.float32),
+                         opacity_logits=rng.normal(0.0, 1.0, n).astype(np.float32),
+                         rgb=rng.uniform(0, 1, (n, 3)).astype(np.float32))
+    cam = scenes.Camera(256, 256, 200.0, 200.0, 127.5, 127.5)
+    views = scenes.Views([cam], np.array([[1, 0, 0, 0]], np.float32), np.zeros((1, 3), np.float32))
+    w = scenes.Workload("long lists", g, views, views, weights=dict(w_rgb=0.5, w_depth=1.0, w_sil=1.0, w_prior=0.0))
+    r = raster.Rasterizer(0, pair_capacity=capacity)
+    mism = _check_binning(r, w, (16, 16))
+    b = r.last_counters
+    print(f"long lists: capacity {capacity}, pairs {b[1]}, mismatching tiles {mism}")
+    assert mism == 0
 
 
 def test_binning_bit_exact_many_blocks(rast):
@@ -386,6 +416,34 @@ def test_autotune_and_tuned_calls(rast):
     expl = r2.render_loss_grad(g, q, t, w.views.cams, tg, _opts(w, tile, deterministic=True))
     for k in ("rgb", "depth", "sil", "loss", "g_means", "dq_t"):
         assert torch.equal(auto[k], expl[k]), k
+
+
+def test_tuning_cache_round_trip(tmp_path):
+    """Tile choices saved by one rasteriser and loaded by a fresh one: its
+    calls with tile (0, 0) then use the saved tile for that shape (the
+    workspace layout shows which tile a call resolves to) and give the same
+    images and loss as the explicit tile."""
+    from paper_2408_05635_amd import raster
+    w = scenes.config2(n_views=2, n=30000)
+    tg = to_dev(oracle_targets(w))
+    g = dev_params(w.gaussians)
+    q, t = dev_poses(w.views)
+    a = raster.Rasterizer(0)
+    tile, _ = a.autotune(g, q, t, w.views.cams, tg, _opts(w), reps=2)
+    a.set_tile(10_000, w.views.cams[:1], (8, 16))   # a second shape
+    path = str(tmp_path / "tiles.json")
+    a.save_tuning(path)
+    b = raster.Rasterizer(0)
+    assert b.load_tuning(path) == 2
+    views, keep = b._views(w.views.cams, q, t)
+    auto = b.workspace_bytes(g.n, views, b._opts(_opts(w, (0, 0)), False), 1 << 20)
+    expl = b.workspace_bytes(g.n, views, b._opts(_opts(w, tile), False), 1 << 20)
+    assert auto == expl
+    oa = b.render_loss_grad(g, q, t, w.views.cams, tg, _opts(w, (0, 0)))
+    oa = {k: v.clone() for k, v in oa.items()}
+    ob = b.render_loss_grad(g, q, t, w.views.cams, tg, _opts(w, tile))
+    for k in ("rgb", "depth", "sil", "loss"):
+        assert torch.equal(oa[k], ob[k]), k
 
 
 def test_native_graph_replay_matches_eager(rast):
