@@ -376,7 +376,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
     // (k, c) adds the 16 quad sums of value c of entry k, in quad order, into
     // s_acc[wave][entry of the segment][c].
     constexpr int kBatch = 40 / NV;   // entries per batch: 4 (NV = 10) or 6 (NV = 6), LDS sized for occupancy
-    __shared__ float s_q[WAVES][kBatch * 16 * NV];
+    // batch slots kQStride floats apart: 16 quads x NV values, padded by 8
+    // floats so that the column sums of a batch's entries (lanes (k, c) reading
+    // slot k, value c) fall in different LDS banks, where a stride of 160
+    // (a multiple of the bank count) put the four slots' value c in one bank
+    constexpr int kQStride = 16 * NV + 8;
+    __shared__ float s_q[WAVES][kBatch * kQStride];
     __shared__ uint32_t s_bslot[WAVES][kBatch];
     __shared__ float s_acc[WAVES][kSeg * NV];
     __shared__ uint32_t s_wmax[WAVES];
@@ -535,7 +540,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         if (fk < nb) {
-            const float *src = qs + fk * 16 * NV + fc;
+            const float *src = qs + fk * kQStride + fc;
             float sum = src[0];
 #pragma unroll
             for (int q = 1; q < 16; ++q) sum += src[q * NV];
@@ -629,7 +634,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
 #pragma unroll
                 for (int c = 5; c < NV; ++c) d[c] = q[c - 2];
                 if ((lane & 3u) == 0u) {
-                    float2 *dst = reinterpret_cast<float2 *>(&s_q[wave][(nb * 16 + (lane >> 2)) * NV]);
+                    float2 *dst = reinterpret_cast<float2 *>(&s_q[wave][nb * kQStride + (lane >> 2) * NV]);
 #pragma unroll
                     for (int c = 0; c < NV / 2; ++c) dst[c] = make_float2(d[2 * c], d[2 * c + 1]);
                 }
