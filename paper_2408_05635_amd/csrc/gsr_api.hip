@@ -111,13 +111,15 @@ constexpr int kRecGrad = 14;   // per-record parameter gradient: mu 3, q 4, log_
 constexpr size_t kCpBudgetBytes = 96u << 20;   // checkpoints of split lists (the longest lists get them first)
 constexpr int64_t kSplitMaxTiles = 2048;       // about the backward workgroups resident at once
 constexpr int kRecBwdMaxBlocks = 1024;   // grid cap of the record backward (one pose row per block)
-constexpr int kEmitChunk = 1024;         // pairs per emission block
+constexpr int kEmitChunk = 4096;         // pairs per emission block
 constexpr int kTuneCandidates = 7;       // tile shapes the autotuner tries
-// synchronisation region, cleared by every call: scan tickets (256 B) and the
-// scans' look-back words
+// synchronisation region, cleared by every call: block tickets (256 B), the
+// single-pass scans' look-back words, the one-launch sort passes' look-back
+// words and their digit histograms
 constexpr size_t kSyncTickets = 256;
-// ids of the binning's scans
-enum SyncId : uint32_t { kIdOffsets = 1 };
+// ids of the binning's scans and sort passes (tickets and look-back tags)
+enum SyncId : uint32_t { kIdOffsets = 1, kIdCompact = 2, kIdSweepDepth = 8, kIdSweepTile = 12 };
+constexpr int kDepthPasses = 4, kMaxTilePasses = 3;
 
 struct Layout {
     int64_t vn;           // V * N
@@ -131,9 +133,11 @@ struct Layout {
         stotals, sync;
     int64_t cp_slots;     // checkpoint slots of split lists (each: the tile's pixels x 6 floats)
     int64_t work_cap;     // backward work items at most: one per tile plus one per slot
-    int64_t sort_nb;      // sort blocks of the larger sort (row length of scounts)
-    // offsets in the sync region (cleared by every call): scan look-back words
-    size_t sync_status, sync_bytes;
+    int64_t sort_nb;      // blocks of the larger three-launch sort (row length of scounts)
+    bool depth_sweep, tile_sweep;   // sorts done with one launch per pass
+    // offsets in the sync region (cleared by every call): scan look-back words,
+    // sort-pass look-back words, digit histograms (depth passes, then tile passes)
+    size_t sync_status, sync_sweep, sync_hist, sync_bytes;
     size_t total;
 };
 
@@ -316,12 +320,18 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     L.losst = take(sizeof(double) * (size_t)L.T);
     L.poseblk = take(sizeof(double) * 12 * V * (size_t)std::max<int64_t>(
                                            std::min<int64_t>((L.vn + 255) / 256, kRecBwdMaxBlocks), 1));
-    const int64_t nb_scan = std::max<int64_t>((std::max<int64_t>(L.vn, kcap) + kChunk - 1) / kChunk, 1);
-    L.sort_nb = std::max<int64_t>(std::max(sort_blocks(L.vn), sort_blocks(kcap)), 1);
+    // blocks of the record scan (256 records each) bound those of the compaction
+    const int64_t nb_scan = std::max<int64_t>((L.vn + 255) / 256, 1);
+    L.depth_sweep = sweep_fits(L.vn);
+    L.tile_sweep = sweep_fits(kcap);
+    L.sort_nb = std::max<int64_t>(std::max(L.depth_sweep ? 0 : sort_blocks(L.vn), L.tile_sweep ? 0 : sort_blocks(kcap)), 1);
     L.scounts = take(4 * 256 * (size_t)L.sort_nb);
     L.stotals = take(4 * 256);
+    const int64_t nb_sweep = std::max(L.depth_sweep ? sweep_blocks(L.vn) : 0, L.tile_sweep ? sweep_blocks(kcap) : 0);
     L.sync_status = kSyncTickets;
-    L.sync_bytes = align_up(L.sync_status + 8 * (size_t)nb_scan);
+    L.sync_sweep = align_up(L.sync_status + 8 * (size_t)nb_scan);
+    L.sync_hist = align_up(L.sync_sweep + 4 * 256 * (size_t)nb_sweep);
+    L.sync_bytes = align_up(L.sync_hist + 4 * 256 * (size_t)(kDepthPasses + kMaxTilePasses));
     L.sync = take(L.sync_bytes);
     L.total = off;
     return L;
@@ -410,43 +420,6 @@ __global__ __launch_bounds__(256) void k_setup_project(ViewTable tab, ViewTable 
     }
 }
 
-// per visible record s (depth order): full projection -> record, tile rect
-template <bool ISO>
-__global__ __launch_bounds__(256) void k_gather(ProjParams pp, const ViewTable *__restrict__ vt,
-                                                const PoseF64 *__restrict__ poses, const int64_t *__restrict__ counters,
-                                                const uint32_t *__restrict__ sorted_gid, float4 *__restrict__ rec,
-                                                uint2 *__restrict__ trect, uint32_t *__restrict__ cnt_s,
-                                                uint32_t *__restrict__ inv, const float *__restrict__ rgb,
-                                                float *__restrict__ rrows) {
-    const int64_t M = counters[kCntVisible];
-    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < M; s += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t gid = sorted_gid[s];
-        const int v = (int)(gid / (uint64_t)pp.n);
-        if (v >= vt->n_views) continue;   // never expected; keeps reads in bounds
-        const int64_t i = (int64_t)gid - (int64_t)v * pp.n;
-        const GaussIn p = load_gauss<ISO>(pp.g, i);
-        Proj r;
-        project<true, ISO>(p, poses[v], vt->v[v], pp.z_near, pp.blur, r);
-        uint32_t a = 0, b = 0;
-        const uint32_t c = tiles_of(r, vt, vt->v[v], a, b);
-        rec[3 * s] = make_float4(r.mxh, r.myh, r.mxl, r.myl);
-        rec[3 * s + 1] = make_float4((float)r.l11, (float)r.l21, (float)r.l22, (float)r.o);
-        rec[3 * s + 2] = make_float4(rgb[3 * i], rgb[3 * i + 1], rgb[3 * i + 2], r.z32);
-        trect[s] = make_uint2(a, b);
-        cnt_s[s] = c;
-        inv[gid] = (uint32_t)s;
-        if (rrows) {   // the backward's atomics add into this record's row
-            float2 *z = reinterpret_cast<float2 *>(rrows + kRowStride * (size_t)s);
-#pragma unroll
-            for (int k = 0; k < kRowStride / 2; ++k) z[k] = make_float2(0.0f, 0.0f);
-        }
-    }
-}
-
-struct CntSrc {
-    const uint32_t *cnt;
-    __device__ uint32_t operator()(int64_t i) const { return cnt[i]; }
-};
 // Pair offsets of the records; also the first record of every kEmitChunk
 // pairs (the record whose range holds pair m * kEmitChunk).
 struct OffSink {
@@ -473,6 +446,105 @@ struct PairTotal {
     }
 };
 
+// Per visible record s (depth order): full projection -> record, tile rect;
+// with SCAN, also its pair offset, the exclusive scan of the records' tile counts, found
+// in the same launch by decoupled look-back over blocks (blocks take tickets
+// and block b holds records [256 b, 256 b + 256)).  The block of the last
+// record forms the pair total and checks it against the capacity.
+// One record: written at s, its tile count returned (every thread of the
+// record kernels below calls it for s < M).
+template <bool ISO>
+__device__ __forceinline__ uint32_t gather_record(const ProjParams &pp, const ViewTable *__restrict__ vt,
+                                                  const PoseF64 *__restrict__ poses,
+                                                  const uint32_t *__restrict__ sorted_gid, float4 *__restrict__ rec,
+                                                  uint2 *__restrict__ trect, uint32_t *__restrict__ cnt_s,
+                                                  uint32_t *__restrict__ inv, const float *__restrict__ rgb,
+                                                  float *__restrict__ rrows, int64_t s) {
+    const uint32_t gid = sorted_gid[s];
+    int v = (int)(gid / (uint32_t)pp.n);
+    if (v >= vt->n_views) v = 0;   // never expected; keeps reads in bounds
+    const int64_t i = (int64_t)gid - (int64_t)v * pp.n;
+    const GaussIn p = load_gauss<ISO>(pp.g, i);
+    Proj r;
+    project<true, ISO>(p, poses[v], vt->v[v], pp.z_near, pp.blur, r);
+    uint32_t a = 0, b = 0;
+    const uint32_t c = tiles_of(r, vt, vt->v[v], a, b);
+    rec[3 * s] = make_float4(r.mxh, r.myh, r.mxl, r.myl);
+    rec[3 * s + 1] = make_float4((float)r.l11, (float)r.l21, (float)r.l22, (float)r.o);
+    rec[3 * s + 2] = make_float4(rgb[3 * i], rgb[3 * i + 1], rgb[3 * i + 2], r.z32);
+    trect[s] = make_uint2(a, b);
+    cnt_s[s] = c;
+    inv[gid] = (uint32_t)s;
+    if (rrows) {   // the backward's atomics add into this record's row
+        float2 *z = reinterpret_cast<float2 *>(rrows + kRowStride * (size_t)s);
+#pragma unroll
+        for (int k = 0; k < kRowStride / 2; ++k) z[k] = make_float2(0.0f, 0.0f);
+    }
+    return c;
+}
+
+template <bool ISO>
+__global__ __launch_bounds__(256) void k_gather(ProjParams pp, const ViewTable *__restrict__ vt,
+                                                const PoseF64 *__restrict__ poses, const int64_t *__restrict__ counters,
+                                                const uint32_t *__restrict__ sorted_gid, float4 *__restrict__ rec,
+                                                uint2 *__restrict__ trect, uint32_t *__restrict__ cnt_s,
+                                                uint32_t *__restrict__ inv, const float *__restrict__ rgb,
+                                                float *__restrict__ rrows) {
+    const int64_t M = counters[kCntVisible];
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < M; s += (int64_t)gridDim.x * blockDim.x)
+        gather_record<ISO>(pp, vt, poses, sorted_gid, rec, trect, cnt_s, inv, rgb, rrows, s);
+}
+
+// The same, fused with the pair offsets: the exclusive scan of the records'
+// tile counts, found in the same launch by decoupled look-back over blocks
+// (blocks take tickets and block b holds records [256 b, 256 b + 256)); the
+// block of the last record forms the pair total and checks it against the
+// capacity.  Used where launches dominate (few records).
+template <bool ISO>
+__global__ __launch_bounds__(256) void k_gather_scan(ProjParams pp, const ViewTable *__restrict__ vt,
+                                                     const PoseF64 *__restrict__ poses, int64_t *__restrict__ counters,
+                                                     const uint32_t *__restrict__ sorted_gid, float4 *__restrict__ rec,
+                                                     uint2 *__restrict__ trect, uint32_t *__restrict__ cnt_s,
+                                                     uint32_t *__restrict__ inv, const float *__restrict__ rgb,
+                                                     float *__restrict__ rrows, SyncState ss, uint32_t id,
+                                                     OffSink sink, PairTotal fin) {
+    __shared__ uint32_t s_b, s_excl;
+    const uint32_t t = threadIdx.x;
+    const int64_t M = counters[kCntVisible];
+    const int64_t nb = (M + 255) / 256;
+    // the grid is sized for V x N: the blocks past the records leave without a
+    // ticket, so the tickets of the others are exactly [0, nb)
+    if ((int64_t)blockIdx.x >= nb) {   // block-uniform
+        if (nb == 0 && blockIdx.x == 0 && t == 0) fin(0);
+        return;
+    }
+    if (t == 0) s_b = take_ticket(ss.tickets, id);
+    __syncthreads();
+    const int64_t b = s_b;
+    const int64_t s = b * 256 + t;
+    const uint32_t c =
+        s < M ? gather_record<ISO>(pp, vt, poses, sorted_gid, rec, trect, cnt_s, inv, rgb, rrows, s) : 0u;
+    uint32_t agg;
+    const uint32_t run = block_excl_scan_u32<256>(c, agg);
+    uint64_t *mine = ss.status + b;
+    if (t == 0) publish(mine, id, b == 0 ? kFlagPrefix : kFlagAgg, agg);
+    if (t < 64) {   // wave 0 looks back
+        const uint32_t excl = b == 0 ? 0u : look_back_wave(ss.status, b, id, ss.error);
+        if (t == 0) {
+            if (b > 0) publish(mine, id, kFlagPrefix, excl + agg);
+            s_excl = excl;
+            if (b == nb - 1) fin((int64_t)excl + (int64_t)agg);
+        }
+    }
+    __syncthreads();
+    if (s < M) sink(s, s_excl + run, c);
+}
+
+struct CntSrc {
+    const uint32_t *cnt;
+    __device__ uint32_t operator()(int64_t i) const { return cnt[i]; }
+};
+
 // Pair j: key = global tile id, value = its record.  Records own contiguous
 // ranges [poff[s], poff[s] + cnt_s[s]) in record order (every visible record
 // touches at least one tile), so pair j's record is the last s with
@@ -480,24 +552,31 @@ struct PairTotal {
 // lie between the chunk's first record and the next chunk's, at most
 // kEmitChunk + 1 of them; their offsets are staged in LDS and each pair
 // searches there.  j itself is recovered later from (record, tile).
-__global__ __launch_bounds__(256) void k_emit(const int64_t *__restrict__ counters, const uint32_t *__restrict__ poff,
+// With hist (the one-launch tile sort), the histograms of the key bits
+// [0, key_bits) in 8-bit digits are also added into hist[pass][256] (zero
+// beforehand).
+constexpr int kEmitThreads = 1024;
+__global__ __launch_bounds__(kEmitThreads) void k_emit(const int64_t *__restrict__ counters, const uint32_t *__restrict__ poff,
                                               const uint32_t *__restrict__ chunk_first,
                                               const uint2 *__restrict__ trect, const uint32_t *__restrict__ gid,
                                               const ViewTable *__restrict__ vt, int64_t n,
-                                              uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+                                              uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                              uint32_t *__restrict__ hist, int key_bits) {
     __shared__ uint32_t s_off[kEmitChunk + 1];
+    __shared__ uint32_t s_hist[3 * 256];
     const int64_t K = counters[kCntPairsUsed];
     const int64_t M = counters[kCntVisible];
     const int64_t j0 = (int64_t)blockIdx.x * kEmitChunk;
     if (j0 >= K) return;   // block-uniform
+    const int passes = hist ? (key_bits + 7) / 8 : 0;
+    for (int k = threadIdx.x; k < passes * 256; k += blockDim.x) s_hist[k] = 0u;
     const int64_t s0 = chunk_first[blockIdx.x];
     const int64_t s1 = j0 + kEmitChunk < K ? (int64_t)chunk_first[blockIdx.x + 1] + 1 : M;   // window end
     const int nwin = (int)((s1 - s0 < kEmitChunk + 1 ? s1 - s0 : kEmitChunk + 1));
     for (int k = threadIdx.x; k < nwin; k += blockDim.x) s_off[k] = poff[s0 + k];
     __syncthreads();
-    for (int q = threadIdx.x; q < kEmitChunk; q += blockDim.x) {
-        const int64_t j = j0 + q;
-        if (j >= K) break;
+    // pair j -> (tile key, record)
+    auto pair_of = [&](int64_t j, uint32_t &rec_s) {
         int lo = 0, hi = nwin;   // s_off[0] <= j; find the last entry <= j
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -506,16 +585,31 @@ __global__ __launch_bounds__(256) void k_emit(const int64_t *__restrict__ counte
             else
                 hi = mid;
         }
-        const uint32_t s = (uint32_t)(s0 + lo);
+        rec_s = (uint32_t)(s0 + lo);
         const uint32_t k = (uint32_t)j - s_off[lo];
-        const uint2 tr = trect[s];
+        const uint2 tr = trect[rec_s];
         const uint32_t tx0 = tr.x & 0xffffu, nx = (tr.x >> 16) - tx0 + 1u, ty0 = tr.y & 0xffffu;
-        int v = (int)(gid[s] / (uint64_t)n);
+        int v = (int)(gid[rec_s] / (uint32_t)n);
         if (v >= vt->n_views) v = 0;
         const ViewInfo &V = vt->v[v];
         const uint32_t ty = ty0 + k / nx, tx = tx0 + k % nx;
-        keys[j] = (uint32_t)V.tile_off + ty * (uint32_t)V.tiles_x + tx;
-        vals[j] = s;
+        return (uint32_t)V.tile_off + ty * (uint32_t)V.tiles_x + tx;
+    };
+    for (int q0 = 0; q0 < kEmitChunk; q0 += blockDim.x) {
+        const int64_t j = j0 + q0 + (int)threadIdx.x;
+        const bool live = j < K;
+        uint32_t key = 0;
+        if (live) {
+            uint32_t rs;
+            key = pair_of(j, rs);
+            keys[j] = key;
+            vals[j] = rs;
+        }
+        if (passes) add_digit_hist(key, live, key_bits, s_hist);
+    }
+    if (passes) {
+        __syncthreads();
+        flush_digit_hist(s_hist, passes, hist);
     }
 }
 
@@ -1098,34 +1192,75 @@ void enqueue_binning(Call &c, const gsr_views *views) {
                            c.tab, vt, views->quat, views->trans, poses, counters, reinterpret_cast<uint4 *>(sync),
                            sync16, at<uint2>(ws, L.ranges), L.T, c.keep_sticky, pp, cnt, zkey);
     }
+    SweepState sw{reinterpret_cast<uint32_t *>(sync + L.sync_sweep), reinterpret_cast<uint32_t *>(sync),
+                  counters + kCntSyncError};
+    uint32_t *dhist = reinterpret_cast<uint32_t *>(sync + L.sync_hist), *thist = dhist + 256 * kDepthPasses;
     // the visible (view, Gaussian) records in depth order: stable sort on the
-    // float32 depth bits (positive floats sort as integers), whose first pass
-    // also compacts them (index order kept) and counts them
-    radix_sort_visible(cnt, zkey, L.vn, dk0, dv0, dk1, dv1, counters + kCntVisible, so, st);
+    // float32 depth bits (positive floats sort as integers), which also
+    // compacts them (index order kept) and counts them
+    if (L.vn > 0) {
+        if (L.depth_sweep) {
+            hipLaunchKernelGGL(k_compact_hist, dim3((unsigned)((L.vn + kCompactChunk - 1) / kCompactChunk)),
+                               dim3(kCompactThreads), 0, st, (const uint32_t *)cnt, (const uint32_t *)zkey, L.vn, dk0,
+                               dv0, ss, (uint32_t)kIdCompact, dhist, counters + kCntVisible);
+            for (int p = 0; p < kDepthPasses; ++p) {   // (k0, v0) -> (k1, v1) -> ... -> (k0, v0)
+                const bool from0 = p % 2 == 0;
+                hipLaunchKernelGGL(k_sweep<PairIn>, dim3((unsigned)sweep_blocks(L.vn)), dim3(kSweepThreads), 0, st,
+                                   PairIn{from0 ? dk0 : dk1, from0 ? dv0 : dv1}, from0 ? dk1 : dk0, from0 ? dv1 : dv0,
+                                   (const int64_t *)(counters + kCntVisible), L.vn, 8 * p, 8,
+                                   (const uint32_t *)(dhist + 256 * p), sw, (uint32_t)(kIdSweepDepth + p),
+                                   (uint2 *)nullptr, (int64_t)0);
+            }
+        } else {
+            radix_sort_visible(cnt, zkey, L.vn, dk0, dv0, dk1, dv1, counters + kCntVisible, so, st);
+        }
+    }
     const uint32_t *gid_sorted = dv0;
     float4 *rec = at<float4>(ws, L.rec);
     uint2 *trect = at<uint2>(ws, L.trect);
     uint32_t *cnt_s = at<uint32_t>(ws, L.cnt_s), *inv = at<uint32_t>(ws, L.inv);
-    if (L.vn > 0)
-        hipLaunchKernelGGL(c.pp.iso ? k_gather<true> : k_gather<false>, dim3(grid_for(L.vn, 256, 8192)), dim3(256),
-                           0, st, c.pp, vt, poses, counters,
-                           gid_sorted, rec, trect, cnt_s, inv, c.pp.g.rgb,
-                           c.tab.deterministic ? nullptr : at<float>(ws, L.rrows));
     uint32_t *pk0 = at<uint32_t>(ws, L.pk0), *pv0 = at<uint32_t>(ws, L.pv0);
     uint32_t *pk1 = at<uint32_t>(ws, L.pk1), *pv1 = at<uint32_t>(ws, L.pv1);
     uint32_t *poff = at<uint32_t>(ws, L.poff);
-    // pair offsets of the records; the last block checks the pair capacity
     uint32_t *chunk_first = at<uint32_t>(ws, L.chunk);
     const int64_t n_chunks = (L.kcap + kEmitChunk - 1) / kEmitChunk;
-    scan_exclusive(CntSrc{cnt_s}, OffSink{poff, chunk_first, n_chunks}, counters + kCntVisible, L.vn, ss, kIdOffsets,
-                   PairTotal{counters, L.kcap}, st);
+    // records and their pair offsets; the last block checks the pair capacity
+    float *rrows = c.tab.deterministic ? nullptr : at<float>(ws, L.rrows);
+    if (L.depth_sweep) {   // few records: one launch
+        if (L.vn > 0)
+            hipLaunchKernelGGL(c.pp.iso ? k_gather_scan<true> : k_gather_scan<false>,
+                               dim3((unsigned)((L.vn + 255) / 256)), dim3(256), 0, st, c.pp, vt, poses, counters,
+                               gid_sorted, rec, trect, cnt_s, inv, c.pp.g.rgb, rrows, ss, (uint32_t)kIdOffsets,
+                               OffSink{poff, chunk_first, n_chunks}, PairTotal{counters, L.kcap});
+    } else {
+        if (L.vn > 0)
+            hipLaunchKernelGGL(c.pp.iso ? k_gather<true> : k_gather<false>, dim3(grid_for(L.vn, 256, 8192)),
+                               dim3(256), 0, st, c.pp, vt, poses, counters, gid_sorted, rec, trect, cnt_s, inv,
+                               c.pp.g.rgb, rrows);
+        scan_exclusive(CntSrc{cnt_s}, OffSink{poff, chunk_first, n_chunks}, counters + kCntVisible, L.vn, ss,
+                       kIdOffsets, PairTotal{counters, L.kcap}, st);
+    }
     if (L.vn > 0 && L.kcap > 0)
-        hipLaunchKernelGGL(k_emit, dim3((unsigned)n_chunks), dim3(256), 0, st, counters, poff,
-                           (const uint32_t *)chunk_first, trect, gid_sorted, vt, c.pp.n, pk0, pv0);
+        hipLaunchKernelGGL(k_emit, dim3((unsigned)n_chunks), dim3(kEmitThreads), 0, st, counters, poff,
+                           (const uint32_t *)chunk_first, trect, gid_sorted, vt, c.pp.n, pk0, pv0,
+                           L.tile_sweep ? thist : nullptr, L.tile_bits);
     // tile order (stable: depth order within a tile); the values are the
     // pairs' records; the last pass also sets every tile's [start, end)
     uint2 *ranges = at<uint2>(ws, L.ranges);
-    radix_sort(pk0, pv0, pk1, pv1, counters + kCntPairsUsed, L.kcap, L.tile_bits, so, st, ranges, L.T);
+    if (L.tile_sweep) {
+        const int passes = (L.tile_bits + 7) / 8;
+        for (int p = 0; L.kcap > 0 && p < passes; ++p) {   // (k0, v0) -> (k1, v1) -> ...
+            const bool from0 = p % 2 == 0, last = p == passes - 1;
+            const int dbits = std::min(8, L.tile_bits - 8 * p);
+            hipLaunchKernelGGL(k_sweep<PairIn>, dim3((unsigned)sweep_blocks(L.kcap)), dim3(kSweepThreads), 0, st,
+                               PairIn{from0 ? pk0 : pk1, from0 ? pv0 : pv1}, from0 ? pk1 : pk0, from0 ? pv1 : pv0,
+                               (const int64_t *)(counters + kCntPairsUsed), L.kcap, 8 * p, dbits,
+                               (const uint32_t *)(thist + 256 * p), sw, (uint32_t)(kIdSweepTile + p),
+                               last ? ranges : (uint2 *)nullptr, (int64_t)L.T);
+        }
+    } else {
+        radix_sort(pk0, pv0, pk1, pv1, counters + kCntPairsUsed, L.kcap, L.tile_bits, so, st, ranges, L.T);
+    }
     if (L.T > 0)
         hipLaunchKernelGGL(k_work_order, dim3(1), dim3(kOrderThreads), 0, st, (const uint2 *)ranges, L.T, L.cp_slots,
                            at<uint32_t>(ws, L.torder), at<uint32_t>(ws, L.cpoff), at<uint32_t>(ws, L.work),

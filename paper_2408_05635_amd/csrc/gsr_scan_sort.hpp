@@ -498,4 +498,297 @@ inline void radix_sort_visible(const uint32_t *cnt, const uint32_t *zkey, int64_
     radix_pass(PairIn{k1, v1}, k0, v0, n_out, n, n, 24, 8, so, nullptr, st);
 }
 
+// ---------------------------------------------------------------------------
+// One launch per pass (the "onesweep" scheme of Adinets and Merrill, 2022)
+//
+// The digit totals of every pass are known before the first one: the keys are
+// the same multiset in every pass, so one histogram of all their digits,
+// taken where the keys are produced, serves them all.  A pass is then a single
+// kernel: each block takes a ticket, ranks its chunk of 4096 items, publishes
+// its count of every digit, and finds the counts of the blocks before it by a
+// decoupled look-back per digit (thread d walks digit d's words back, 32
+// blocks per poll, until it meets an inclusive prefix), so no block ever waits
+// for a block that started after it.  Look-back words are 32 bits: a 5-bit tag
+// (pass id << 1 | inclusive) over a 27-bit count; they are cleared with the
+// rest of the synchronisation region at the start of every call, and every
+// pass of a call has its own id.  Sorts of more than kSweepMaxBlocks chunks
+// take the three-launch passes above instead: with hundreds of blocks polling
+// at once the look-back chains resolve more slowly than the two extra
+// launches cost, and this scheme pays off where launches dominate (small
+// sorts, such as one view's records and pairs in a tracking iteration).
+// ---------------------------------------------------------------------------
+constexpr int kSweepThreads = 1024;
+constexpr int kSweepItems = 4;
+constexpr int kSweepChunk = kSweepThreads * kSweepItems;   // 4096 items per block
+constexpr int kSweepWaves = kSweepThreads / 64;
+constexpr int kSweepLook = 32;                             // predecessors per thread and poll
+constexpr int64_t kSweepMaxBlocks = 256;   // 1M items
+constexpr uint32_t kSweepValBits = 27;
+constexpr uint32_t kSweepValMask = (1u << kSweepValBits) - 1u;
+
+inline int64_t sweep_blocks(int64_t cap) { return (cap + kSweepChunk - 1) / kSweepChunk; }
+inline bool sweep_fits(int64_t cap) { return sweep_blocks(cap) <= kSweepMaxBlocks; }
+
+struct SweepState {
+    uint32_t *status;    // [blocks][256] look-back words
+    uint32_t *tickets;   // block tickets, indexed by pass id
+    int64_t *error;      // raised when a wait gives up
+};
+
+__device__ __forceinline__ uint32_t sweep_word(uint32_t pass_id, bool inclusive, uint32_t v) {
+    return (((pass_id << 1) | (inclusive ? 1u : 0u)) << kSweepValBits) | (v & kSweepValMask);
+}
+
+__device__ __forceinline__ void sweep_store(uint32_t *p, uint32_t w) {
+    __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t sweep_load(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Count of digit d in the blocks before block b (b > 0), from their words in
+// `status` (row q = block q).  Bounded wait: raises *error and returns what it
+// has summed if a predecessor never publishes.
+__device__ __forceinline__ uint32_t sweep_look_back(const uint32_t *status, int64_t b, uint32_t d, uint32_t pass_id,
+                                                    int64_t *error) {
+    const uint32_t tag_agg = pass_id << 1, tag_pre = (pass_id << 1) | 1u;
+    uint32_t excl = 0, spins = 0;
+    int64_t p = b - 1;   // next predecessor to read
+    while (p >= 0) {
+        uint32_t w[kSweepLook];
+#pragma unroll
+        for (int k = 0; k < kSweepLook; ++k)
+            w[k] = p - k >= 0 ? sweep_load(status + (size_t)(p - k) * 256 + d) : (tag_pre << kSweepValBits);
+        int k = 0;
+        bool done = false;
+#pragma unroll
+        for (int j = 0; j < kSweepLook; ++j) {   // in order of decreasing block
+            if (done || k != j) continue;
+            const uint32_t tag = w[j] >> kSweepValBits;
+            if (tag == tag_pre) {
+                excl += w[j] & kSweepValMask;
+                done = true;
+            } else if (tag == tag_agg) {
+                excl += w[j] & kSweepValMask;
+                ++k;
+            }
+        }
+        if (done) break;
+        p -= k;
+        if (k == 0) {
+            if (++spins > kSpinLimit) {   // never expected: report it and stop waiting
+                atomicAdd((unsigned long long *)error, 1ull);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    return excl;
+}
+
+// One pass: items of `in` -> (kout, vout) stably by key bits [shift, shift +
+// dbits); totals[d] = number of items with digit d.  ranges as in
+// k_radix_scatter (last pass of the tile sort only).
+template <class In>
+__global__ __launch_bounds__(kSweepThreads) void k_sweep(In in, uint32_t *__restrict__ kout,
+                                                         uint32_t *__restrict__ vout, const int64_t *n_dev,
+                                                         int64_t n_host, int shift, int dbits,
+                                                         const uint32_t *__restrict__ totals, SweepState sw,
+                                                         uint32_t pass_id, uint2 *__restrict__ ranges,
+                                                         int64_t n_keys) {
+    __shared__ uint32_t s_b;
+    __shared__ uint32_t s_goff[256];   // digit base, then the global position of the block's first item of the digit
+    __shared__ uint32_t s_cnt[256];    // the block's count of each digit, then the digit's first slot in s_k
+    __shared__ uint32_t s_h[kSweepWaves][256];
+    __shared__ uint32_t s_k[kSweepChunk], s_v[kSweepChunk];
+    const uint32_t t = threadIdx.x, wave = t >> 6, lane = t & 63u;
+    const int64_t n = dev_count(n_dev, n_host);
+    const int64_t nb = (n + kSweepChunk - 1) / kSweepChunk;
+    // grids are sized for the capacity: the blocks past the device count leave
+    // without a ticket, so the tickets of the others are exactly [0, nb)
+    if ((int64_t)blockIdx.x >= nb) return;   // block-uniform
+    if (t == 0) s_b = take_ticket(sw.tickets, pass_id);
+    for (uint32_t k = lane; k < 256u; k += 64u) s_h[wave][k] = 0u;
+    const int nd = 1 << dbits;
+    const uint32_t mask = (uint32_t)nd - 1u;
+    {   // digit bases: exclusive scan of the totals
+        uint32_t all;
+        const uint32_t dbase = block_excl_scan_u32<kSweepThreads>((int)t < nd ? totals[t] : 0u, all);
+        if (t < 256u) s_goff[t] = dbase;
+    }
+    __syncthreads();   // s_b, s_h and s_goff are set
+    const int64_t b = s_b;
+    const int64_t wbase = b * kSweepChunk + (int64_t)wave * (64 * kSweepItems);
+    uint32_t keys[kSweepItems], vals[kSweepItems], lrank[kSweepItems];
+    bool ok[kSweepItems];
+#pragma unroll
+    for (int j = 0; j < kSweepItems; ++j) {
+        keys[j] = vals[j] = lrank[j] = 0u;
+        ok[j] = in.load(wbase + (int64_t)j * 64 + lane, n, keys[j], vals[j]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int j = 0; j < kSweepItems; ++j) {   // per-wave stable ranks, as in k_radix_scatter
+        const bool valid = ok[j];
+        const uint64_t vmask = ballot(valid);
+        if (vmask == 0) continue;   // wave-uniform
+        const uint32_t d = (keys[j] >> shift) & mask;
+        const uint64_t peers = match_digit(d, dbits, vmask);
+        const uint32_t rank = rank_below(peers);
+        const uint32_t before = s_h[wave][d];
+        lrank[j] = before + rank;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rank == 0) s_h[wave][d] = before + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    if ((int)t < nd) {
+        uint32_t run = 0;
+        for (int w = 0; w < kSweepWaves; ++w) {
+            const uint32_t c = s_h[w][t];
+            s_h[w][t] = run;
+            run += c;
+        }
+        s_cnt[t] = run;
+        uint32_t *mine = sw.status + (size_t)b * 256 + t;
+        if (b == 0) {
+            sweep_store(mine, sweep_word(pass_id, true, run));
+        } else {
+            sweep_store(mine, sweep_word(pass_id, false, run));
+            const uint32_t excl = sweep_look_back(sw.status, b, t, pass_id, sw.error);
+            sweep_store(mine, sweep_word(pass_id, true, excl + run));
+            s_goff[t] += excl;
+        }
+    } else if (t < 256u) {
+        s_cnt[t] = 0u;
+    }
+    __syncthreads();
+    uint32_t tot;
+    const uint32_t lbase = block_excl_scan_u32<kSweepThreads>(t < 256u ? s_cnt[t] : 0u, tot);
+    if (t < 256u) s_cnt[t] = lbase;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSweepItems; ++j) {
+        if (ok[j]) {
+            const uint32_t d = (keys[j] >> shift) & mask;
+            const uint32_t lp = s_cnt[d] + s_h[wave][d] + lrank[j];
+            if (lp < (uint32_t)kSweepChunk) {   // always true for consistent counts
+                s_k[lp] = keys[j];
+                s_v[lp] = vals[j];
+            }
+        }
+    }
+    __syncthreads();
+    const int nblk = (int)(tot < (uint32_t)kSweepChunk ? tot : (uint32_t)kSweepChunk);
+    for (int i = t; i < nblk; i += kSweepThreads) {
+        const uint32_t key = s_k[i];
+        const uint32_t d = (key >> shift) & mask;
+        const uint32_t pos = s_goff[d] + ((uint32_t)i - s_cnt[d]);
+        if ((int64_t)pos < n) {   // always true for consistent counts; keeps writes in bounds
+            kout[pos] = key;
+            vout[pos] = s_v[i];
+            if (ranges && (int64_t)key < n_keys) {   // block-uniform choice
+                const uint32_t run0 = s_cnt[d], run1 = d + 1u < 256u ? s_cnt[d + 1] : tot;
+                if ((uint32_t)i == run0 || s_k[i - 1] != key) atomicMin(&ranges[key].x, pos);
+                if ((uint32_t)i + 1u == run1 || s_k[i + 1] != key) atomicMax(&ranges[key].y, pos + 1u);
+            }
+        }
+    }
+}
+
+// Adds a valid key's 8-bit digits of bits [0, bits) into hist[pass][256] in
+// LDS.  Plain LDS atomics: lanes that share a digit are serialised by the
+// LDS, which costs less than finding them with ballots.
+__device__ __forceinline__ void add_digit_hist(uint32_t key, bool valid, int bits, uint32_t *s_hist) {
+    if (!valid) return;
+    for (int shift = 0, p = 0; shift < bits; shift += 8, ++p)
+        atomicAdd(&s_hist[p * 256 + ((key >> shift) & 255u)], 1u);
+}
+
+// Adds a block's LDS histogram (passes x 256) into the global one (zero
+// before the call's first block), skipping empty bins.
+__device__ __forceinline__ void flush_digit_hist(const uint32_t *s_hist, int passes, uint32_t *hist) {
+    for (int k = threadIdx.x; k < passes * 256; k += blockDim.x) {
+        const uint32_t c = s_hist[k];
+        if (c) atomicAdd(&hist[k], c);
+    }
+}
+
+// First step of the depth sort in the one-launch scheme: the visible items
+// (cnt[i] != 0) among the n (view, Gaussian) items, compacted in index order
+// into (kout = depth key, vout = index) by a single-pass scan (decoupled
+// look-back over blocks of kCompactChunk items), the histograms of the four
+// byte digits of their keys (added into hist[4][256], zero beforehand), and
+// their number (written to *n_out by the last block).
+constexpr int kCompactThreads = 1024;
+constexpr int kCompactItems = 4;
+constexpr int kCompactChunk = kCompactThreads * kCompactItems;
+
+__global__ __launch_bounds__(kCompactThreads) void k_compact_hist(const uint32_t *__restrict__ cnt,
+                                                                  const uint32_t *__restrict__ zkey, int64_t n,
+                                                                  uint32_t *__restrict__ kout,
+                                                                  uint32_t *__restrict__ vout, SyncState ss,
+                                                                  uint32_t id, uint32_t *__restrict__ hist,
+                                                                  int64_t *__restrict__ n_out) {
+    __shared__ uint32_t s_b, s_excl;
+    __shared__ uint32_t s_hist[4 * 256];
+    const uint32_t t = threadIdx.x;
+    const int64_t nb = (n + kCompactChunk - 1) / kCompactChunk;
+    if ((int64_t)blockIdx.x >= nb) return;   // block-uniform
+    if (t == 0) s_b = take_ticket(ss.tickets, id);
+    s_hist[t] = 0u;
+    __syncthreads();
+    const int64_t b = s_b;
+    const int64_t first = b * kCompactChunk + (int64_t)t * kCompactItems;
+    uint32_t c[kCompactItems], k[kCompactItems];
+    if (first + kCompactItems <= n) {   // 16-byte aligned runs of 4
+        const uint4 *c4 = reinterpret_cast<const uint4 *>(cnt + first);
+        const uint4 *k4 = reinterpret_cast<const uint4 *>(zkey + first);
+#pragma unroll
+        for (int q = 0; q < kCompactItems / 4; ++q) {
+            const uint4 a = c4[q], z = k4[q];
+            c[4 * q] = a.x, c[4 * q + 1] = a.y, c[4 * q + 2] = a.z, c[4 * q + 3] = a.w;
+            k[4 * q] = z.x, k[4 * q + 1] = z.y, k[4 * q + 2] = z.z, k[4 * q + 3] = z.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kCompactItems; ++j) {
+            const bool in = first + j < n;
+            c[j] = in ? cnt[first + j] : 0u;
+            k[j] = in ? zkey[first + j] : 0u;
+        }
+    }
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kCompactItems; ++j) s += c[j] != 0u ? 1u : 0u;
+#pragma unroll
+    for (int j = 0; j < kCompactItems; ++j) add_digit_hist(k[j], c[j] != 0u, 32, s_hist);
+    uint32_t agg;
+    uint32_t run = block_excl_scan_u32<kCompactThreads>(s, agg);
+    uint64_t *mine = ss.status + b;
+    if (t == 0) publish(mine, id, b == 0 ? kFlagPrefix : kFlagAgg, agg);
+    if (t < 64) {   // wave 0 looks back
+        const uint32_t excl = b == 0 ? 0u : look_back_wave(ss.status, b, id, ss.error);
+        if (t == 0) {
+            if (b > 0) publish(mine, id, kFlagPrefix, excl + agg);
+            s_excl = excl;
+            if (b == nb - 1) *n_out = (int64_t)excl + (int64_t)agg;
+        }
+    }
+    __syncthreads();   // also orders the LDS histogram's atomics before the flush
+    run += s_excl;
+#pragma unroll
+    for (int j = 0; j < kCompactItems; ++j) {
+        if (c[j] != 0u) {
+            kout[run] = k[j];
+            vout[run] = (uint32_t)(first + j);
+            ++run;
+        }
+    }
+    flush_digit_hist(s_hist, 4, hist);
+}
+
 }  // namespace gsr
