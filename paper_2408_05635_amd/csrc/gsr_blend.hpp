@@ -591,8 +591,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
                 const float4 cc = rec[3 * (size_t)rs + 2];
                 // A lane that does not take this entry continues with alpha = 0:
                 // every update below then leaves its state exactly as it was
-                // (fma(0, S, W 1) = W) and every partial is zero, so no branch
-                // and no select is needed for the state.
+                // (fma(0, S, W 1) = W, T rcp(1) = T) and every partial is zero,
+                // so no branch and no select is needed for the state.
                 const float ae = contrib ? ev.alpha : 0.0f;
                 const float oma = 1.0f - ae;
                 const float Tk = T * __builtin_amdgcn_rcpf(oma);   // transmittance in front of this entry
@@ -623,7 +623,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
                     q[3] = g[3] * wc;
                 }
                 W = __builtin_fmaf(ae, S, W * oma);
-                T = contrib ? Tk : T;
+                T = Tk;
                 quad_sums<NQ>(q);
                 float d[NV];
                 d[0] = q[0];
