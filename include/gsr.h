@@ -127,7 +127,7 @@ typedef enum {
 /* stages reported by gsr_read_timing() */
 #define GSR_STAGE_BINNING     0  /* projection, compaction, depth sort, records, pairs, tile sort, ranges */
 #define GSR_STAGE_BLEND_FWD   1  /* front-to-back compositing (eqs. 2-4) */
-#define GSR_STAGE_BLEND_BWD   2  /* loss + reverse compositing -> per-pair 2D gradients (one kernel) */
+#define GSR_STAGE_BLEND_BWD   2  /* loss + reverse compositing -> 2D gradients per record (one kernel) */
 #define GSR_STAGE_PROJECT_BWD 3  /* chain rule to the parameters, pose gradients */
 #define GSR_NUM_STAGES        4
 
