@@ -651,7 +651,8 @@ def measured_traffic(kernel: str, tile):
             list(t.get("tile", [16, 16])) != list(tile):
         return None, "stale: " + TRAFFIC_PROFILE
     return t["read_bytes"] + t["write_bytes"], "stored: " + TRAFFIC_PROFILE + \
-        " (rocprofv3 FETCH_SIZE and WRITE_SIZE of the same command, copy-calibrated)"
+        " (rocprofv3 FETCH_SIZE and WRITE_SIZE passes over this 8-view step at this tile with the current kernel" \
+        " sources, scaled by a device copy's counts; " + t.get("profile", "") + ")"
 
 
 def decision_stable_pose_fd(rast, raster, g, q0, t0, cams, tg, opts, h):
