@@ -11,12 +11,12 @@
 // of a call has its own id, so a word left by an earlier scan never passes
 // for a current one.  A waiting loop gives up after kSpinLimit polls and
 // raises an error counter: every wave terminates, whatever happens.  The
-// radix sort needs no waiting (see below).
+// three-launch radix sort passes need no waiting; the one-launch passes for
+// small sorts wait the same bounded way (see below).
 //
 // Element counts may live in device memory: grids are sized for a host-side
-// capacity and blocks whose ticket lies past the device count exit at once,
-// so a whole call can be enqueued (or captured in a graph) without a host
-// synchronisation.
+// capacity and blocks past the device count exit at once, so a whole call can
+// be enqueued (or captured in a graph) without a host synchronisation.
 #pragma once
 
 #include "gsr_common.hpp"
