@@ -111,6 +111,7 @@ constexpr int kRecGrad = 14;   // per-record parameter gradient: mu 3, q 4, log_
 constexpr size_t kCpBudgetBytes = 96u << 20;   // checkpoints of split lists (the longest lists get them first)
 constexpr int64_t kSplitMaxTiles = 2048;       // about the backward workgroups resident at once
 constexpr int kRecBwdMaxBlocks = 1024;   // grid cap of the record backward (one pose row per block)
+constexpr int64_t kRecBwdItemsPerBlock = 1024;   // (view, Gaussian) items per record-backward block below the cap
 constexpr int kEmitChunk = 4096;         // pairs per emission block
 constexpr int kTuneCandidates = 7;       // tile shapes the autotuner tries
 // synchronisation region, cleared by every call: block tickets (256 B), the
@@ -319,7 +320,7 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     L.rgrad = take(4 * kRecGrad * vn);
     L.losst = take(sizeof(double) * (size_t)L.T);
     L.poseblk = take(sizeof(double) * 12 * V * (size_t)std::max<int64_t>(
-                                           std::min<int64_t>((L.vn + 255) / 256, kRecBwdMaxBlocks), 1));
+                                           std::min<int64_t>((L.vn + kRecBwdItemsPerBlock - 1) / kRecBwdItemsPerBlock, kRecBwdMaxBlocks), 1));
     // blocks of the record scan (256 records each) bound those of the compaction
     const int64_t nb_scan = std::max<int64_t>((L.vn + 255) / 256, 1);
     L.depth_sweep = sweep_fits(L.vn);
@@ -1350,7 +1351,7 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
     if (fused && L.kcap == 0)   // no blend ran: every tile's partial is zero
         hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(L.T, 256)), dim3(256), 0, st, li.loss_tile, L.T);
     StageTimer timer(c.ctx, kStageProjectBwd, st);
-    const unsigned rec_blocks = std::min<unsigned>(grid_for(L.vn, 256, 1ll << 30), kRecBwdMaxBlocks);
+    const unsigned rec_blocks = std::min<unsigned>(grid_for(L.vn, kRecBwdItemsPerBlock, 1ll << 30), kRecBwdMaxBlocks);
     double *pose_blocks = at<double>(c.ws, L.poseblk);
     // with atomics the record rows are also cleared here, so this runs whenever the blend did
     if (c.pp.n > 0 && (go.want_gauss || go.want_pose || (atomic && L.kcap > 0 && L.T > 0)))
