@@ -382,7 +382,6 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
     // (a multiple of the bank count) put the four slots' value c in one bank
     constexpr int kQStride = 16 * NV + 8;
     __shared__ float s_q[WAVES][kBatch * kQStride];
-    __shared__ uint32_t s_bslot[WAVES][kBatch];
     __shared__ float s_acc[WAVES][kSeg * NV];
     __shared__ uint32_t s_wmax[WAVES];
     __shared__ uint32_t s_j[kSeg];   // gradient-row slot of each entry of the segment
@@ -536,7 +535,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
     const uint32_t fk = lane / NV, fc = lane - fk * NV;   // the batch entry and the value this lane adds up
     // Adds the quad sums of the batch's nb entries (lanes of one wave; LDS
     // operations of a wave complete in order, so no barrier beyond the wave's).
-    auto flush = [&](uint32_t nb) {
+    // bpack: the batch entries' places in the segment, 6 bits each (a
+    // wave-uniform value, held in scalar registers).
+    static_assert(6 * kBatch <= 64, "batch places fit one 64-bit word");
+    auto flush = [&](uint32_t nb, uint64_t bpack) {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         if (fk < nb) {
@@ -544,7 +546,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
             float sum = src[0];
 #pragma unroll
             for (int q = 1; q < 16; ++q) sum += src[q * NV];
-            acc[s_bslot[wave][fk] * NV + fc] = sum;
+            const uint32_t slot = (uint32_t)(bpack >> (6u * fk)) & 63u;
+            acc[slot * NV + fc] = sum;
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -570,6 +573,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
             // an entry's record is read at a wave-uniform address (scalar loads)
             uint64_t mm = ballot(keep);
             uint32_t nb = 0;   // entries stored in the batch (wave-uniform)
+            uint64_t bpack = 0;   // their places in the segment (wave-uniform)
             auto entry = [&](int src) {
                 const uint32_t pos = seg_lo + (uint32_t)src;
                 const uint32_t rs = __builtin_amdgcn_readlane(s, src);
@@ -638,10 +642,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
 #pragma unroll
                     for (int c = 0; c < NV / 2; ++c) dst[c] = make_float2(d[2 * c], d[2 * c + 1]);
                 }
-                if (lane == 0) s_bslot[wave][nb] = pos - seg_lo;
+                bpack |= (uint64_t)(pos - seg_lo) << (6u * nb);
                 if (++nb == (uint32_t)kBatch) {
-                    flush(nb);
+                    flush(nb, bpack);
                     nb = 0;
+                    bpack = 0;
                 }
             };
             while (mm != 0) {   // wave-uniform
@@ -649,7 +654,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
                 mm &= ~(1ull << src);
                 entry(src);
             }
-            if (nb != 0) flush(nb);
+            if (nb != 0) flush(nb, bpack);
         }
         __syncthreads();
         // add the waves' sums in a fixed order and write each entry's row
