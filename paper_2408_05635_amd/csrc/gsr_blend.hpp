@@ -595,13 +595,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
                 const float4 cc = rec[3 * (size_t)rs + 2];
                 // A lane that does not take this entry continues with alpha = 0:
                 // every update below then leaves its state exactly as it was
-                // (fma(0, S, W 1) = W, T rcp(1) = T) and every partial is zero,
-                // so no branch and no select is needed for the state.
+                // (fma(0, S - W, W) = W, T rcp(1) = T) and every partial is
+                // zero, so no branch and no select is needed for the state.
                 const float ae = contrib ? ev.alpha : 0.0f;
                 const float oma = 1.0f - ae;
                 const float Tk = T * __builtin_amdgcn_rcpf(oma);   // transmittance in front of this entry
                 const float S = __builtin_fmaf(g[0], cc.x, __builtin_fmaf(g[1], cc.y, __builtin_fmaf(g[2], cc.z, __builtin_fmaf(g[3], cc.w, g[4]))));
-                const float dal = Tk * (S - W);
+                const float sw = S - W;
+                const float dal = Tk * sw;
                 // unclamped: alpha = o G, so dL/do = dL/dalpha G and
                 // 2 dL/dp2 = dL/dalpha alpha 2 ln2 = dL/do (2 o ln2); the
                 // entry's constant factors (2 o ln2, l11, l21, l22) are applied
@@ -626,7 +627,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
                 } else {
                     q[3] = g[3] * wc;
                 }
-                W = __builtin_fmaf(ae, S, W * oma);
+                W = __builtin_fmaf(ae, sw, W);   // alpha S + (1 - alpha) W
                 T = Tk;
                 quad_sums<NQ>(q);
                 float d[NV];
