@@ -17,6 +17,8 @@
 //   C = (r, g, b, z)                   colour and camera depth
 #pragma once
 
+#include <type_traits>
+
 #include "gsr_common.hpp"
 
 namespace gsr {
@@ -530,15 +532,15 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
 
     // W: sum over the channels of dL/d(channel) x (channel behind the current entry)
     uint32_t n_eval = 0, n_contrib = 0, n_red = 0;
-    float *acc = &s_acc[wave][0];
     float *qs = &s_q[wave][0];
     const uint32_t fk = lane / NV, fc = lane - fk * NV;   // the batch entry and the value this lane adds up
     // Adds the quad sums of the batch's nb entries (lanes of one wave; LDS
     // operations of a wave complete in order, so no barrier beyond the wave's).
     // bpack: the batch entries' places in the segment, 6 bits each (a
     // wave-uniform value, held in scalar registers).
+    using Pack = std::conditional_t<6 * kBatch <= 32, uint32_t, uint64_t>;
     static_assert(6 * kBatch <= 64, "batch places fit one 64-bit word");
-    auto flush = [&](uint32_t nb, uint64_t bpack) {
+    auto flush = [&](uint32_t nb, Pack bpack) {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         if (fk < nb) {
@@ -547,14 +549,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
 #pragma unroll
             for (int q = 1; q < 16; ++q) sum += src[q * NV];
             const uint32_t slot = (uint32_t)(bpack >> (6u * fk)) & 63u;
-            acc[slot * NV + fc] = sum;
+            s_acc[wave][slot * NV + fc] = sum;   // 32-bit LDS index
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     };
     for (uint32_t seg_hi = top; seg_hi > lo;) {
         const uint32_t seg_lo = seg_hi - lo > (uint32_t)kSeg ? seg_hi - kSeg : lo;
-        for (int c = lane; c < kSeg * NV; c += 64) acc[c] = 0.0f;
+        for (int c = lane; c < kSeg * NV; c += 64) s_acc[wave][c] = 0.0f;
         if (threadIdx.x < seg_hi - seg_lo) s_j[threadIdx.x] = row_of(seg_lo + threadIdx.x);   // read after the barrier
         if (wmax > seg_lo) {   // wave-uniform: this wave has pixels with entries in the segment
             const uint32_t w_hi = wmax < seg_hi ? wmax : seg_hi;   // this wave's last entry + 1 in the segment
@@ -573,7 +575,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
             // an entry's record is read at a wave-uniform address (scalar loads)
             uint64_t mm = ballot(keep);
             uint32_t nb = 0;   // entries stored in the batch (wave-uniform)
-            uint64_t bpack = 0;   // their places in the segment (wave-uniform)
+            Pack bpack = 0;   // their places in the segment (wave-uniform)
             auto entry = [&](int src) {
                 const uint32_t pos = seg_lo + (uint32_t)src;
                 const uint32_t rs = __builtin_amdgcn_readlane(s, src);
@@ -643,7 +645,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
 #pragma unroll
                     for (int c = 0; c < NV / 2; ++c) dst[c] = make_float2(d[2 * c], d[2 * c + 1]);
                 }
-                bpack |= (uint64_t)(pos - seg_lo) << (6u * nb);
+                bpack |= (Pack)(pos - seg_lo) << (6u * nb);
                 if (++nb == (uint32_t)kBatch) {
                     flush(nb, bpack);
                     nb = 0;
