@@ -130,7 +130,7 @@ struct Layout {
     int32_t G;            // total blend blocks
     int tile_bits;        // key bits of the tile sort
     size_t views, poses, counters, cnt, zkey, dk0, dv0, dk1, dv1, inv, rec, trect, cnt_s, poff, pk0, pv0, pk1, pv1,
-        chunk, ranges, torder, cpoff, work, nwork, cp, tfinal, nlast, phash, gpairs, rrows, rgrad, losst, poseblk, scounts,
+        chunk, ranges, torder, cpoff, work, nwork, cp, tfinal, nlast, phash, cmask, gpairs, rrows, rgrad, losst, poseblk, scounts,
         stotals, sync;
     int64_t cp_slots;     // checkpoint slots of split lists (each: the tile's pixels x 6 floats)
     int64_t work_cap;     // backward work items at most: one per tile plus one per slot
@@ -313,6 +313,8 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     L.tfinal = take(4 * (size_t)L.P);
     L.nlast = take(4 * (size_t)L.P);
     L.phash = take(4 * (size_t)L.P);
+    // the forward's culling ballots for the backward: K / 64 + T + 2 words per block of a tile
+    L.cmask = take(8 * (size_t)((vt.tile_w / kBlk) * (vt.tile_h / kBlk)) * ((size_t)(kc / 64) + (size_t)L.T + 2));
     // the backward's 2D gradient rows: one per (tile, entry) pair with
     // GSR_DETERMINISTIC, else one per record (kRowStride floats each)
     L.gpairs = take(vt.deterministic ? 4 * kRowStride * kc : 0);
@@ -1283,7 +1285,7 @@ void enqueue_blend_fwd(Call &c, gsr_images out) {
     StageTimer timer(c.ctx, kStageBlendFwd, c.st);
     const Layout &L = c.L;
     BlendOut bo{out.rgb, out.depth, out.sil, at<float>(c.ws, L.tfinal), at<uint32_t>(c.ws, L.nlast),
-                at<uint32_t>(c.ws, L.phash)};
+                at<uint32_t>(c.ws, L.phash), at<uint64_t>(c.ws, L.cmask)};
     // the tiles' blocks, tile ranks dealt to the XCDs in turn (see locate_block)
     const int64_t nsub = (int64_t)(c.tab.tile_w / kBlk) * (c.tab.tile_h / kBlk);
     const unsigned grid = (unsigned)(8 * nsub * ((L.T + 7) / 8));
@@ -1331,7 +1333,7 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
     go.want_pose = pg && !(opts->flags & GSR_NO_POSE_GRADS) && (pg->dq_t || pg->dt || pg->dq_c || pg->dc);
     const bool pose_only = !go.want_gauss;   // 6 partials per entry reach the pose
     BlendOut bo{out.rgb, out.depth, out.sil, at<float>(c.ws, L.tfinal), at<uint32_t>(c.ws, L.nlast),
-                at<uint32_t>(c.ws, L.phash)};
+                at<uint32_t>(c.ws, L.phash), at<uint64_t>(c.ws, L.cmask)};
     {
         StageTimer timer(c.ctx, kStageBlendBwd, st);
         const unsigned grid = (unsigned)(((L.work_cap + 7) / 8) * 8);   // the items past n_work leave at once

@@ -148,7 +148,19 @@ struct BlendOut {
     float *t_final;             // per pixel
     uint32_t *n_last;           // per pixel: list position + 1 of the last contributor (0: none)
     uint32_t *hash;             // per pixel: hash of the contributing records, clamp flags and the stop
+    uint64_t *cmask;            // the forward's culling decisions, for the backward (cmask_index)
 };
+
+// The forward's culling ballot of list entries [start + 64 c, start + 64 c +
+// 64) of tile tg (list range [start, end)) for 8x8 block `sub` of the tile:
+// word (start / 64 + tg + c) nsub + sub.  The words of successive tiles do not
+// overlap (a tile's ceil((end - start) / 64) words end by end / 64 + tg + 1),
+// so the array needs K / 64 + T + 2 words per block of a tile.  The backward
+// takes these bits instead of repeating block_may_contribute: the same test
+// for the same block, so the same decisions.
+__device__ __forceinline__ size_t cmask_index(uint32_t start, int32_t tg, uint32_t rel, int nsub, int sub) {
+    return ((size_t)(start >> 6) + (size_t)tg + (size_t)(rel >> 6)) * (size_t)nsub + (size_t)sub;
+}
 
 // HASH: also fold the pixel's decisions into out.hash (a test hook; 0 otherwise).
 template <bool COUNT, bool HASH>
@@ -207,6 +219,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
             keep = block_may_contribute(A, B, (float)bp.bx0, (float)bp.by0);
         }
         const uint64_t m = ballot(keep);
+        if (lane == 0) out.cmask[cmask_index(rg.x, bp.tg, c - rg.x, nsub, bp.sub)] = m;
         if (keep) {
             const uint32_t slot = rank_below(m);
             const float2 d0 = block_offset(A, (float)bp.bx0, (float)bp.by0);
@@ -302,8 +315,9 @@ __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.0f) - (x 
 // of a split list, one wave per 8x8 block of the tile (tiles are at most
 // 32x32, so at most sixteen waves).  The item's entries are walked in reverse,
 // from the last contributor of any pixel of the tile, in segments of kSeg
-// entries; within a segment every wave culls the entries against its own
-// block (one lane per entry), then takes the survivors one by one, reading
+// entries; within a segment every wave reads the forward's culling decisions
+// for its own block (one lane per entry, one bit each), then takes the
+// survivors one by one, reading
 // each one's record at a wave-uniform address (scalar loads, no LDS staging),
 // and sums each entry's partial derivatives over its 64 pixels (DPP quad
 // sums, then a batched column sum in LDS) into its own LDS slots.
@@ -564,10 +578,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
             bool keep = false;
             uint32_t s = 0;
             if (lane < (uint32_t)kSeg && e < w_hi && pair_rec[e] < n_rec) {
-                s = pair_rec[e];
-                const float4 A = rec[3 * (size_t)s];
-                keep = block_may_contribute(A, rec[3 * (size_t)s + 1], (float)bx0, (float)by0);
-                s_d[wave][lane] = block_offset(A, (float)bx0, (float)by0);
+                // the forward's decision for this entry and block
+                const uint32_t rel = e - rg.x;
+                keep = (st.cmask[cmask_index(rg.x, tid_g, rel, nw, (int)wave)] >> (rel & 63u)) & 1ull;
+                if (keep) {
+                    s = pair_rec[e];
+                    s_d[wave][lane] = block_offset(rec[3 * (size_t)s], (float)bx0, (float)by0);
+                }
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // the offsets before the entries read them
             __builtin_amdgcn_wave_barrier();
