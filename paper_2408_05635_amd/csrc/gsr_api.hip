@@ -121,6 +121,10 @@ constexpr size_t kSyncTickets = 256;
 // ids of the binning's scans and sort passes (tickets and look-back tags)
 enum SyncId : uint32_t { kIdOffsets = 1, kIdCompact = 2, kIdSweepDepth = 8, kIdSweepTile = 12 };
 constexpr int kDepthPasses = 4, kMaxTilePasses = 3;
+// tile-local binning: at most this many tiles, and a pair capacity of at most
+// this many pairs per tile
+constexpr int64_t kTileLocalMaxTiles = 16384;   // a block's tile counts fit LDS (64 KB)
+constexpr int64_t kTileLocalMaxAvg = 4096;
 
 struct Layout {
     int64_t vn;           // V * N
@@ -136,9 +140,15 @@ struct Layout {
     int64_t work_cap;     // backward work items at most: one per tile plus one per slot
     int64_t sort_nb;      // blocks of the larger three-launch sort (row length of scounts)
     bool depth_sweep, tile_sweep;   // sorts done with one launch per pass
+    // tile-local binning (short lists): records in index order, pairs placed
+    // per tile and each list sorted on its own; else the two global sorts
+    bool tile_local;
+    int64_t tv_max;       // tiles of the largest view (row length of the per-block tile counts)
+    size_t tcnt, ttot, tstart;
     // offsets in the sync region (cleared by every call): scan look-back words,
-    // sort-pass look-back words, digit histograms (depth passes, then tile passes)
-    size_t sync_status, sync_sweep, sync_hist, sync_bytes;
+    // sort-pass look-back words, digit histograms (depth passes, then tile
+    // passes), the views' first pairs (tile-local binning; 1 + pair, 0 = none)
+    size_t sync_status, sync_sweep, sync_hist, sync_vstart, sync_bytes;
     size_t total;
 };
 
@@ -268,6 +278,11 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     L.T = vt.total_tiles;
     L.G = vt.total_blocks;
     L.tile_bits = std::max(bits_for(L.T), 1);   // at least one pass: its scatter records the tile ranges
+    // lists short enough on average for the per-tile sort, and few enough
+    // tiles for a block's counts in LDS
+    L.tile_local = L.T <= kTileLocalMaxTiles && kcap <= kTileLocalMaxAvg * L.T;
+    L.tv_max = 1;
+    for (int v = 0; v < V; ++v) L.tv_max = std::max<int64_t>(L.tv_max, (int64_t)vt.v[v].tiles_x * vt.v[v].tiles_y);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -295,6 +310,10 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     L.pv1 = take(4 * kc);
     L.chunk = take(4 * (size_t)((kc + kEmitChunk - 1) / kEmitChunk + 1));
     L.ranges = take(8 * (size_t)L.T);
+    // one row per (emission block, view it touches): row b + v (see k_emit_count)
+    L.tcnt = take(L.tile_local ? 4 * (size_t)((kc + kEmitChunk - 1) / kEmitChunk + V) * (size_t)L.tv_max : 0);
+    L.ttot = take(L.tile_local ? 4 * (size_t)L.T : 0);
+    L.tstart = take(L.tile_local ? 4 * (size_t)L.T : 0);
     L.torder = take(4 * (size_t)L.T);
     L.cpoff = take(4 * (size_t)L.T);
     {   // a split list needs chunks_of(len) - 1 slots; at most kcap / kChunkEntries in all, within a budget
@@ -334,7 +353,8 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     L.sync_status = kSyncTickets;
     L.sync_sweep = align_up(L.sync_status + 8 * (size_t)nb_scan);
     L.sync_hist = align_up(L.sync_sweep + 4 * 256 * (size_t)nb_sweep);
-    L.sync_bytes = align_up(L.sync_hist + 4 * 256 * (size_t)(kDepthPasses + kMaxTilePasses));
+    L.sync_vstart = align_up(L.sync_hist + 4 * 256 * (size_t)(kDepthPasses + kMaxTilePasses));
+    L.sync_bytes = align_up(L.sync_vstart + 4 * (size_t)(V + 1));
     L.sync = take(L.sync_bytes);
     L.total = off;
     return L;
@@ -428,8 +448,17 @@ __global__ __launch_bounds__(256) void k_setup_project(ViewTable tab, ViewTable 
 struct OffSink {
     uint32_t *off, *chunk_first;
     int64_t n_chunks;   // capacity of chunk_first
+    // tile-local binning (records in view order): 1 + the first pair of every
+    // view up to the record's, past the previous record's view
+    uint32_t *vstart1 = nullptr;
+    const uint32_t *gid = nullptr;
+    int64_t n = 1;
     __device__ void operator()(int64_t s, uint32_t pos, uint32_t cnt) const {
         off[s] = pos;
+        if (vstart1) {
+            const int64_t v = gid[s] / n, vp = s > 0 ? (int64_t)(gid[s - 1] / n) : -1;
+            for (int64_t u = vp + 1; u <= v && u < GSR_MAX_VIEWS; ++u) vstart1[u] = pos + 1u;
+        }
         if (cnt == 0) return;
         for (int64_t m = ((int64_t)pos + kEmitChunk - 1) / kEmitChunk;
              m * kEmitChunk < (int64_t)pos + cnt && m < n_chunks; ++m)
@@ -449,13 +478,10 @@ struct PairTotal {
     }
 };
 
-// Per visible record s (depth order): full projection -> record, tile rect;
-// with SCAN, also its pair offset, the exclusive scan of the records' tile counts, found
-// in the same launch by decoupled look-back over blocks (blocks take tickets
-// and block b holds records [256 b, 256 b + 256)).  The block of the last
-// record forms the pair total and checks it against the capacity.
-// One record: written at s, its tile count returned (every thread of the
-// record kernels below calls it for s < M).
+// Per visible record s (in depth order, or in (view, index) order with
+// tile-local binning): full projection -> record, tile rect.  One record:
+// written at s, its tile count returned (every thread of the record kernels
+// below calls it for s < M).
 template <bool ISO>
 __device__ __forceinline__ uint32_t gather_record(const ProjParams &pp, const ViewTable *__restrict__ vt,
                                                   const PoseF64 *__restrict__ poses,
@@ -551,14 +577,55 @@ struct CntSrc {
 // Pair j: key = global tile id, value = its record.  Records own contiguous
 // ranges [poff[s], poff[s] + cnt_s[s]) in record order (every visible record
 // touches at least one tile), so pair j's record is the last s with
-// poff[s] <= j.  A block takes kEmitChunk consecutive pairs: their records
-// lie between the chunk's first record and the next chunk's, at most
-// kEmitChunk + 1 of them; their offsets are staged in LDS and each pair
-// searches there.  j itself is recovered later from (record, tile).
-// With hist (the one-launch tile sort), the histograms of the key bits
-// [0, key_bits) in 8-bit digits are also added into hist[pass][256] (zero
-// beforehand).
+// poff[s] <= j.  Chunk m holds pairs [m C, m C + C) (C = kEmitChunk): their
+// records lie between the chunk's first record and the next chunk's, at most
+// C + 1 of them; a block stages their offsets in LDS and each pair searches
+// there.  j itself is recovered later from (record, tile).
 constexpr int kEmitThreads = 1024;
+
+struct EmitWindow {
+    int64_t s0;   // first record of the chunk
+    int nwin;     // records staged
+};
+
+// Stages chunk m's record offsets in s_off (the whole block calls it; the
+// caller synchronises before the searches).
+__device__ __forceinline__ EmitWindow emit_stage(int64_t m, int64_t K, int64_t M, const uint32_t *__restrict__ poff,
+                                                 const uint32_t *__restrict__ chunk_first, uint32_t *s_off) {
+    EmitWindow w;
+    w.s0 = chunk_first[m];
+    const int64_t s1 = (m + 1) * kEmitChunk < K ? (int64_t)chunk_first[m + 1] + 1 : M;   // window end
+    w.nwin = (int)(s1 - w.s0 < kEmitChunk + 1 ? s1 - w.s0 : kEmitChunk + 1);
+    for (int k = threadIdx.x; k < w.nwin; k += blockDim.x) s_off[k] = poff[w.s0 + k];
+    return w;
+}
+
+// Pair j of the staged chunk -> its tile key, and its record in rec_s.
+__device__ __forceinline__ uint32_t emit_pair(int64_t j, const EmitWindow &w, const uint32_t *s_off,
+                                              const uint2 *__restrict__ trect, const uint32_t *__restrict__ gid,
+                                              const ViewTable *__restrict__ vt, int64_t n, uint32_t &rec_s) {
+    int lo = 0, hi = w.nwin;   // s_off[0] <= j; find the last entry <= j
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)s_off[mid] <= j)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    rec_s = (uint32_t)(w.s0 + lo);
+    const uint32_t k = (uint32_t)j - s_off[lo];
+    const uint2 tr = trect[rec_s];
+    const uint32_t tx0 = tr.x & 0xffffu, nx = (tr.x >> 16) - tx0 + 1u, ty0 = tr.y & 0xffffu;
+    int v = (int)(gid[rec_s] / (uint32_t)n);
+    if (v >= vt->n_views) v = 0;
+    const ViewInfo &V = vt->v[v];
+    const uint32_t ty = ty0 + k / nx, tx = tx0 + k % nx;
+    return (uint32_t)V.tile_off + ty * (uint32_t)V.tiles_x + tx;
+}
+
+// One block per chunk: keys[j] = tile, vals[j] = record.  With hist (the
+// one-launch tile sort), the histograms of the key bits [0, key_bits) in
+// 8-bit digits are also added into hist[pass][256] (zero beforehand).
 __global__ __launch_bounds__(kEmitThreads) void k_emit(const int64_t *__restrict__ counters, const uint32_t *__restrict__ poff,
                                               const uint32_t *__restrict__ chunk_first,
                                               const uint2 *__restrict__ trect, const uint32_t *__restrict__ gid,
@@ -573,38 +640,15 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(const int64_t *__restrict
     if (j0 >= K) return;   // block-uniform
     const int passes = hist ? (key_bits + 7) / 8 : 0;
     for (int k = threadIdx.x; k < passes * 256; k += blockDim.x) s_hist[k] = 0u;
-    const int64_t s0 = chunk_first[blockIdx.x];
-    const int64_t s1 = j0 + kEmitChunk < K ? (int64_t)chunk_first[blockIdx.x + 1] + 1 : M;   // window end
-    const int nwin = (int)((s1 - s0 < kEmitChunk + 1 ? s1 - s0 : kEmitChunk + 1));
-    for (int k = threadIdx.x; k < nwin; k += blockDim.x) s_off[k] = poff[s0 + k];
+    const EmitWindow w = emit_stage(blockIdx.x, K, M, poff, chunk_first, s_off);
     __syncthreads();
-    // pair j -> (tile key, record)
-    auto pair_of = [&](int64_t j, uint32_t &rec_s) {
-        int lo = 0, hi = nwin;   // s_off[0] <= j; find the last entry <= j
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if ((int64_t)s_off[mid] <= j)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        rec_s = (uint32_t)(s0 + lo);
-        const uint32_t k = (uint32_t)j - s_off[lo];
-        const uint2 tr = trect[rec_s];
-        const uint32_t tx0 = tr.x & 0xffffu, nx = (tr.x >> 16) - tx0 + 1u, ty0 = tr.y & 0xffffu;
-        int v = (int)(gid[rec_s] / (uint32_t)n);
-        if (v >= vt->n_views) v = 0;
-        const ViewInfo &V = vt->v[v];
-        const uint32_t ty = ty0 + k / nx, tx = tx0 + k % nx;
-        return (uint32_t)V.tile_off + ty * (uint32_t)V.tiles_x + tx;
-    };
     for (int q0 = 0; q0 < kEmitChunk; q0 += blockDim.x) {
         const int64_t j = j0 + q0 + (int)threadIdx.x;
         const bool live = j < K;
         uint32_t key = 0;
         if (live) {
             uint32_t rs;
-            key = pair_of(j, rs);
+            key = emit_pair(j, w, s_off, trect, gid, vt, n, rs);
             keys[j] = key;
             vals[j] = rs;
         }
@@ -613,6 +657,155 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(const int64_t *__restrict
     if (passes) {
         __syncthreads();
         flush_digit_hist(s_hist, passes, hist);
+    }
+}
+
+// Tile-local binning, the emission in two passes over the same pairs, one
+// block per chunk.  Records are in view order, so the pairs of block b belong
+// to a run of views [v0, v1] (usually one); k_emit_count counts them per tile
+// in LDS and stores, for each of those views v, the row counts[b + v][0, T_v)
+// (b + v grows with (b, v) over the rows written, so rows never collide).
+// k_tile_offsets turns every tile's column, over the blocks holding pairs of
+// its view, into exclusive offsets (and the tile's total); k_tile_ranges turns
+// the totals into list starts; k_emit_place gives each pair the next free
+// place of its tile within its block's share, cursor = start + offset in LDS.
+// No global atomics: a tile's pairs come from every part of its view's records.
+struct ViewSpan {
+    int v0, v1;
+};
+
+// the views of the first and last pair of the staged chunk (thread 0 finds
+// them; the caller synchronises before s_span is read)
+__device__ __forceinline__ void chunk_views(int64_t m, int64_t K, const EmitWindow &w, const uint32_t *s_off,
+                                            const uint2 *__restrict__ trect, const uint32_t *__restrict__ gid,
+                                            const ViewTable *__restrict__ vt, int64_t n, ViewSpan *s_span) {
+    if (threadIdx.x != 0) return;
+    const int64_t j0 = m * kEmitChunk, j1 = (j0 + kEmitChunk < K ? j0 + kEmitChunk : K) - 1;
+    uint32_t r0, r1;
+    (void)emit_pair(j0, w, s_off, trect, gid, vt, n, r0);
+    (void)emit_pair(j1, w, s_off, trect, gid, vt, n, r1);
+    int v0 = (int)(gid[r0] / (uint64_t)n), v1 = (int)(gid[r1] / (uint64_t)n);
+    const int nv = vt->n_views;
+    v0 = v0 < nv ? v0 : nv - 1;   // never expected; keeps rows in bounds
+    v1 = v1 < nv ? (v1 > v0 ? v1 : v0) : nv - 1;
+    s_span->v0 = v0;
+    s_span->v1 = v1;
+}
+
+__global__ __launch_bounds__(kEmitThreads) void k_emit_count(const int64_t *__restrict__ counters,
+                                                             const uint32_t *__restrict__ poff,
+                                                             const uint32_t *__restrict__ chunk_first,
+                                                             const uint2 *__restrict__ trect,
+                                                             const uint32_t *__restrict__ gid,
+                                                             const ViewTable *__restrict__ vt, int64_t n,
+                                                             int64_t n_tiles, int64_t row_len,
+                                                             uint32_t *__restrict__ counts) {
+    __shared__ uint32_t s_off[kEmitChunk + 1];
+    __shared__ uint32_t s_h[kTileLocalMaxTiles];
+    __shared__ ViewSpan s_span;
+    const int64_t K = counters[kCntPairsUsed], M = counters[kCntVisible];
+    const int64_t m = blockIdx.x, j0 = m * kEmitChunk;
+    if (j0 >= K) return;   // block-uniform: rows past the pairs are never read
+    for (int64_t k = threadIdx.x; k < n_tiles; k += blockDim.x) s_h[k] = 0u;
+    const EmitWindow w = emit_stage(m, K, M, poff, chunk_first, s_off);
+    __syncthreads();
+    chunk_views(m, K, w, s_off, trect, gid, vt, n, &s_span);
+    for (int q0 = 0; q0 < kEmitChunk; q0 += blockDim.x) {
+        const int64_t j = j0 + q0 + (int)threadIdx.x;
+        if (j < K) {
+            uint32_t rs;
+            const uint32_t key = emit_pair(j, w, s_off, trect, gid, vt, n, rs);
+            if ((int64_t)key < n_tiles) atomicAdd(&s_h[key], 1u);   // always true; keeps accesses in bounds
+        }
+    }
+    __syncthreads();
+    for (int v = s_span.v0; v <= s_span.v1; ++v) {
+        const ViewInfo &V = vt->v[v];
+        const int tv = V.tiles_x * V.tiles_y;
+        uint32_t *row = counts + (size_t)(m + v) * (size_t)row_len;
+        for (int k = threadIdx.x; k < tv; k += blockDim.x) row[k] = s_h[V.tile_off + k];
+    }
+}
+
+// One thread per tile: the exclusive offsets of its column over the blocks
+// that hold pairs of its view (those whose chunks meet the view's pair range
+// [start(v), start(v + 1)), from vstart1), and its total.
+__global__ __launch_bounds__(256) void k_tile_offsets(const ViewTable *__restrict__ vt,
+                                                      const int64_t *__restrict__ counters,
+                                                      const uint32_t *__restrict__ vstart1, int64_t n_tiles,
+                                                      int64_t row_len, uint32_t *__restrict__ counts,
+                                                      uint32_t *__restrict__ ttot) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_tiles) return;
+    const int64_t K = counters[kCntPairsUsed];
+    const int nv = vt->n_views;
+    int v = 0;
+    while (v + 1 < nv && vt->v[v + 1].tile_off <= t) ++v;
+    const int64_t x = t - vt->v[v].tile_off;
+    const int64_t ps = vstart1[v] ? (int64_t)vstart1[v] - 1 : K;
+    const int64_t pe = v + 1 < nv && vstart1[v + 1] ? (int64_t)vstart1[v + 1] - 1 : K;
+    uint32_t run = 0;
+    if (pe > ps && pe <= K) {
+        const int64_t b0 = ps / kEmitChunk, b1 = (pe - 1) / kEmitChunk;
+        uint32_t *col = counts + (size_t)(b0 + v) * (size_t)row_len + (size_t)x;
+        const int64_t nb = b1 - b0 + 1;
+        int64_t b = 0;
+        for (; b + 8 <= nb; b += 8) {   // eight loads in flight
+            uint32_t c[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) c[q] = col[(size_t)(b + q) * (size_t)row_len];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                col[(size_t)(b + q) * (size_t)row_len] = run;
+                run += c[q];
+            }
+        }
+        for (; b < nb; ++b) {
+            const uint32_t c = col[(size_t)b * (size_t)row_len];
+            col[(size_t)b * (size_t)row_len] = run;
+            run += c;
+        }
+    }
+    ttot[t] = run;
+}
+
+__global__ __launch_bounds__(kEmitThreads) void k_emit_place(const int64_t *__restrict__ counters,
+                                                             const uint32_t *__restrict__ poff,
+                                                             const uint32_t *__restrict__ chunk_first,
+                                                             const uint2 *__restrict__ trect,
+                                                             const uint32_t *__restrict__ gid,
+                                                             const ViewTable *__restrict__ vt, int64_t n,
+                                                             int64_t n_tiles, int64_t row_len,
+                                                             const uint32_t *__restrict__ offsets,
+                                                             const uint32_t *__restrict__ tstart,
+                                                             uint32_t *__restrict__ vals) {
+    __shared__ uint32_t s_off[kEmitChunk + 1];
+    __shared__ uint32_t s_cur[kTileLocalMaxTiles];
+    __shared__ ViewSpan s_span;
+    const int64_t K = counters[kCntPairsUsed], M = counters[kCntVisible];
+    const int64_t m = blockIdx.x, j0 = m * kEmitChunk;
+    if (j0 >= K) return;   // block-uniform
+    const EmitWindow w = emit_stage(m, K, M, poff, chunk_first, s_off);
+    __syncthreads();
+    chunk_views(m, K, w, s_off, trect, gid, vt, n, &s_span);
+    __syncthreads();
+    for (int v = s_span.v0; v <= s_span.v1; ++v) {
+        const ViewInfo &V = vt->v[v];
+        const int tv = V.tiles_x * V.tiles_y;
+        const uint32_t *row = offsets + (size_t)(m + v) * (size_t)row_len;
+        for (int k = threadIdx.x; k < tv; k += blockDim.x) s_cur[V.tile_off + k] = tstart[V.tile_off + k] + row[k];
+    }
+    __syncthreads();
+    for (int q0 = 0; q0 < kEmitChunk; q0 += blockDim.x) {
+        const int64_t j = j0 + q0 + (int)threadIdx.x;
+        if (j < K) {
+            uint32_t rs;
+            const uint32_t key = emit_pair(j, w, s_off, trect, gid, vt, n, rs);
+            if ((int64_t)key < n_tiles) {   // always true; keeps accesses in bounds
+                const uint32_t slot = atomicAdd(&s_cur[key], 1u);
+                if ((int64_t)slot < K) vals[slot] = rs;   // always true; keeps writes in bounds
+            }
+        }
     }
 }
 
@@ -637,11 +830,10 @@ __global__ void k_fill_f64(double *p, int64_t n) {
 constexpr int kOrderThreads = 1024;
 constexpr uint32_t kOrderBuckets = 256;
 
-__global__ __launch_bounds__(kOrderThreads) void k_work_order(const uint2 *__restrict__ ranges, int64_t n_tiles,
-                                                              int64_t slots_cap, uint32_t *__restrict__ torder,
-                                                              uint32_t *__restrict__ cpoff, uint32_t *__restrict__ work,
-                                                              int64_t *__restrict__ n_work,
-                                                              int64_t *__restrict__ counters) {
+__device__ __forceinline__ void work_order_block(const uint2 *__restrict__ ranges, int64_t n_tiles, int64_t slots_cap,
+                                                 uint32_t *__restrict__ torder, uint32_t *__restrict__ cpoff,
+                                                 uint32_t *__restrict__ work, int64_t *__restrict__ n_work,
+                                                 int64_t *__restrict__ counters) {
     __shared__ uint32_t s_h[kOrderBuckets];
     __shared__ int64_t s_run;
     const int t = threadIdx.x;
@@ -723,6 +915,58 @@ __global__ __launch_bounds__(kOrderThreads) void k_work_order(const uint2 *__res
             if (pos < total) work[pos] = (uint32_t)i | (m << 24);   // always true; keeps writes in bounds
         }
     }
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_work_order(const uint2 *__restrict__ ranges, int64_t n_tiles,
+                                                              int64_t slots_cap, uint32_t *__restrict__ torder,
+                                                              uint32_t *__restrict__ cpoff, uint32_t *__restrict__ work,
+                                                              int64_t *__restrict__ n_work,
+                                                              int64_t *__restrict__ counters) {
+    work_order_block(ranges, n_tiles, slots_cap, torder, cpoff, work, n_work, counters);
+}
+
+// Tile-local binning: every tile's list [start, end) from the tiles' pair
+// totals (an exclusive scan in tile order), the starts for the placement, the
+// number of lists that the per-tile sort gives a whole workgroup, then the
+// work order.  One block.
+constexpr int kRangeItems = 4;   // tiles per thread and round
+
+__global__ __launch_bounds__(kOrderThreads) void k_tile_ranges(const uint32_t *__restrict__ ttot, int64_t n_tiles,
+                                                               uint2 *__restrict__ ranges, uint32_t *__restrict__ tstart,
+                                                               int64_t slots_cap, uint32_t *__restrict__ torder,
+                                                               uint32_t *__restrict__ cpoff, uint32_t *__restrict__ work,
+                                                               int64_t *__restrict__ n_work,
+                                                               int64_t *__restrict__ counters) {
+    __shared__ uint32_t s_big;
+    const int t = threadIdx.x;
+    if (t == 0) s_big = 0u;
+    uint32_t run = 0, big = 0;   // run: the totals before this round (the same in every thread)
+    for (int64_t base = 0; base < n_tiles; base += (int64_t)kOrderThreads * kRangeItems) {
+        const int64_t d0 = base + (int64_t)t * kRangeItems;
+        uint32_t x[kRangeItems], sum = 0;
+#pragma unroll
+        for (int q = 0; q < kRangeItems; ++q) {
+            x[q] = d0 + q < n_tiles ? ttot[d0 + q] : 0u;
+            sum += x[q];
+        }
+        uint32_t tot;
+        uint32_t start = run + block_excl_scan_u32<kOrderThreads>(sum, tot);   // its barriers order s_big's clear
+        run += tot;
+#pragma unroll
+        for (int q = 0; q < kRangeItems; ++q) {
+            if (d0 + q < n_tiles) {
+                ranges[d0 + q] = make_uint2(start, start + x[q]);
+                tstart[d0 + q] = start;
+                big += x[q] >= kTileSortWaveCap ? 1u : 0u;
+            }
+            start += x[q];
+        }
+    }
+    if (big) atomicAdd(&s_big, big);
+    __threadfence_block();
+    __syncthreads();   // the ranges before the work order reads them
+    if (t == 0) counters[kCntSortBig] = s_big;
+    work_order_block(ranges, n_tiles, slots_cap, torder, cpoff, work, n_work, counters);
 }
 
 struct GradOut {
@@ -1198,10 +1442,15 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     SweepState sw{reinterpret_cast<uint32_t *>(sync + L.sync_sweep), reinterpret_cast<uint32_t *>(sync),
                   counters + kCntSyncError};
     uint32_t *dhist = reinterpret_cast<uint32_t *>(sync + L.sync_hist), *thist = dhist + 256 * kDepthPasses;
-    // the visible (view, Gaussian) records in depth order: stable sort on the
-    // float32 depth bits (positive floats sort as integers), which also
-    // compacts them (index order kept) and counts them
-    if (L.vn > 0) {
+    // Tile-local binning: the visible (view, Gaussian) items compacted in
+    // index order (their depth keys beside them, in dk0), counted.  Else the
+    // visible records in depth order: stable sort on the float32 depth bits
+    // (positive floats sort as integers), which also compacts and counts them.
+    if (L.vn > 0 && L.tile_local) {
+        hipLaunchKernelGGL(k_compact_hist, dim3((unsigned)((L.vn + kCompactChunk - 1) / kCompactChunk)),
+                           dim3(kCompactThreads), 0, st, (const uint32_t *)cnt, (const uint32_t *)zkey, L.vn, dk0, dv0,
+                           ss, (uint32_t)kIdCompact, (uint32_t *)nullptr, counters + kCntVisible);
+    } else if (L.vn > 0) {
         if (L.depth_sweep) {
             hipLaunchKernelGGL(k_compact_hist, dim3((unsigned)((L.vn + kCompactChunk - 1) / kCompactChunk)),
                                dim3(kCompactThreads), 0, st, (const uint32_t *)cnt, (const uint32_t *)zkey, L.vn, dk0,
@@ -1229,19 +1478,57 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     const int64_t n_chunks = (L.kcap + kEmitChunk - 1) / kEmitChunk;
     // records and their pair offsets; the last block checks the pair capacity
     float *rrows = c.tab.deterministic ? nullptr : at<float>(ws, L.rrows);
+    OffSink osink{poff, chunk_first, n_chunks};
+    if (L.tile_local) {
+        osink.vstart1 = reinterpret_cast<uint32_t *>(sync + L.sync_vstart);
+        osink.gid = gid_sorted;
+        osink.n = std::max<int64_t>(c.pp.n, 1);
+    }
     if (L.depth_sweep) {   // few records: one launch
         if (L.vn > 0)
             hipLaunchKernelGGL(c.pp.iso ? k_gather_scan<true> : k_gather_scan<false>,
                                dim3((unsigned)((L.vn + 255) / 256)), dim3(256), 0, st, c.pp, vt, poses, counters,
                                gid_sorted, rec, trect, cnt_s, inv, c.pp.g.rgb, rrows, ss, (uint32_t)kIdOffsets,
-                               OffSink{poff, chunk_first, n_chunks}, PairTotal{counters, L.kcap});
+                               osink, PairTotal{counters, L.kcap});
     } else {
         if (L.vn > 0)
             hipLaunchKernelGGL(c.pp.iso ? k_gather<true> : k_gather<false>, dim3(grid_for(L.vn, 256, 8192)),
                                dim3(256), 0, st, c.pp, vt, poses, counters, gid_sorted, rec, trect, cnt_s, inv,
                                c.pp.g.rgb, rrows);
-        scan_exclusive(CntSrc{cnt_s}, OffSink{poff, chunk_first, n_chunks}, counters + kCntVisible, L.vn, ss,
-                       kIdOffsets, PairTotal{counters, L.kcap}, st);
+        scan_exclusive(CntSrc{cnt_s}, osink, counters + kCntVisible, L.vn, ss, kIdOffsets,
+                       PairTotal{counters, L.kcap}, st);
+    }
+    uint2 *ranges = at<uint2>(ws, L.ranges);
+    if (L.tile_local) {
+        // per-block tile counts, every tile's offsets over the blocks and its
+        // total, the list ranges (and the work order), the pairs placed in
+        // their lists, each list sorted
+        uint32_t *torder = at<uint32_t>(ws, L.torder), *tcnt = at<uint32_t>(ws, L.tcnt);
+        uint32_t *ttot = at<uint32_t>(ws, L.ttot), *tstart = at<uint32_t>(ws, L.tstart);
+        const bool pairs = L.vn > 0 && L.kcap > 0;
+        const uint32_t *vstart1 = reinterpret_cast<const uint32_t *>(sync + L.sync_vstart);
+        if (pairs) {
+            hipLaunchKernelGGL(k_emit_count, dim3((unsigned)n_chunks), dim3(kEmitThreads), 0, st,
+                               (const int64_t *)counters, (const uint32_t *)poff, (const uint32_t *)chunk_first,
+                               (const uint2 *)trect, gid_sorted, (const ViewTable *)vt, c.pp.n, L.T, L.tv_max, tcnt);
+        }
+        if (L.T > 0) {
+            hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)((L.T + 255) / 256)), dim3(256), 0, st,
+                               (const ViewTable *)vt, (const int64_t *)counters, vstart1, L.T, L.tv_max, tcnt, ttot);
+            hipLaunchKernelGGL(k_tile_ranges, dim3(1), dim3(kOrderThreads), 0, st, (const uint32_t *)ttot, L.T,
+                               ranges, tstart, L.cp_slots, torder, at<uint32_t>(ws, L.cpoff), at<uint32_t>(ws, L.work),
+                               at<int64_t>(ws, L.nwork), counters);
+        }
+        if (pairs) {
+            hipLaunchKernelGGL(k_emit_place, dim3((unsigned)n_chunks), dim3(kEmitThreads), 0, st,
+                               (const int64_t *)counters, (const uint32_t *)poff, (const uint32_t *)chunk_first,
+                               (const uint2 *)trect, gid_sorted, (const ViewTable *)vt, c.pp.n, L.T, L.tv_max,
+                               (const uint32_t *)tcnt, (const uint32_t *)tstart, pv0);
+            hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)L.T), dim3(kTileSortThreads), 0, st, (const uint2 *)ranges,
+                               (const uint32_t *)torder, L.T, (const int64_t *)counters, (const uint32_t *)dk0,
+                               (const uint32_t *)pv0, pv1, pk0, pk1);
+        }
+        return;
     }
     if (L.vn > 0 && L.kcap > 0)
         hipLaunchKernelGGL(k_emit, dim3((unsigned)n_chunks), dim3(kEmitThreads), 0, st, counters, poff,
@@ -1249,7 +1536,6 @@ void enqueue_binning(Call &c, const gsr_views *views) {
                            L.tile_sweep ? thist : nullptr, L.tile_bits);
     // tile order (stable: depth order within a tile); the values are the
     // pairs' records; the last pass also sets every tile's [start, end)
-    uint2 *ranges = at<uint2>(ws, L.ranges);
     if (L.tile_sweep) {
         const int passes = (L.tile_bits + 7) / 8;
         for (int p = 0; L.kcap > 0 && p < passes; ++p) {   // (k0, v0) -> (k1, v1) -> ...
@@ -1272,13 +1558,16 @@ void enqueue_binning(Call &c, const gsr_views *views) {
 
 // record index of every sorted pair (the sort's result buffer is fixed by the key bits)
 const uint32_t *pair_values(const Call &c) {
+    if (c.L.tile_local) return at<uint32_t>(c.ws, c.L.pv1);   // where the per-tile sort writes
     const int passes = (c.L.tile_bits + 7) / 8;
     const bool in1 = (c.L.kcap > 0 && c.L.tile_bits > 0) ? (passes % 2 == 1) : false;
     return at<uint32_t>(c.ws, in1 ? c.L.pv1 : c.L.pv0);
 }
 
+// each record's view * N + index (records in depth order, or in that index
+// order with tile-local binning)
 const uint32_t *depth_sorted_gid(const Call &c) {
-    return at<uint32_t>(c.ws, c.L.dv0);   // where the depth sort leaves its result
+    return at<uint32_t>(c.ws, c.L.dv0);   // where the depth sort or the compaction leaves it
 }
 
 void enqueue_blend_fwd(Call &c, gsr_images out) {

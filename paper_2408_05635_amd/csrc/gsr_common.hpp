@@ -56,6 +56,7 @@ enum Counter {
     kCntContribBwd = 11,
     kCntReduceBwd = 12,
     kCntWorkItems = 13,  // the backward's work items (tiles, or chunks of split lists)
+    kCntSortBig = 14,    // tile-local binning: lists that the per-tile sort gives a whole workgroup
     kNumCounters = 16
 };
 

@@ -717,12 +717,12 @@ __device__ __forceinline__ void flush_digit_hist(const uint32_t *s_hist, int pas
     }
 }
 
-// First step of the depth sort in the one-launch scheme: the visible items
-// (cnt[i] != 0) among the n (view, Gaussian) items, compacted in index order
-// into (kout = depth key, vout = index) by a single-pass scan (decoupled
-// look-back over blocks of kCompactChunk items), the histograms of the four
-// byte digits of their keys (added into hist[4][256], zero beforehand), and
-// their number (written to *n_out by the last block).
+// The visible items (cnt[i] != 0) among the n (view, Gaussian) items,
+// compacted in index order into (kout = depth key, vout = index) by a
+// single-pass scan (decoupled look-back over blocks of kCompactChunk items),
+// and their number (written to *n_out by the last block).  With hist (the
+// first step of the one-launch depth sort), also the histograms of the four
+// byte digits of their keys (added into hist[4][256], zero beforehand).
 constexpr int kCompactThreads = 1024;
 constexpr int kCompactItems = 4;
 constexpr int kCompactChunk = kCompactThreads * kCompactItems;
@@ -764,8 +764,10 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact_hist(const uint32_t
     uint32_t s = 0;
 #pragma unroll
     for (int j = 0; j < kCompactItems; ++j) s += c[j] != 0u ? 1u : 0u;
+    if (hist) {
 #pragma unroll
-    for (int j = 0; j < kCompactItems; ++j) add_digit_hist(k[j], c[j] != 0u, 32, s_hist);
+        for (int j = 0; j < kCompactItems; ++j) add_digit_hist(k[j], c[j] != 0u, 32, s_hist);
+    }
     uint32_t agg;
     uint32_t run = block_excl_scan_u32<kCompactThreads>(s, agg);
     uint64_t *mine = ss.status + b;
@@ -788,7 +790,256 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact_hist(const uint32_t
             ++run;
         }
     }
-    flush_digit_hist(s_hist, 4, hist);
+    if (hist) flush_digit_hist(s_hist, 4, hist);
+}
+
+// ---------------------------------------------------------------------------
+// per-tile sort (tile-local binning)
+//
+// The emission places every (tile, record) pair in its tile's range in no
+// particular order; k_tile_sort then orders each list by the 64-bit key
+// (float32 depth bits, record), the order that a stable sort by depth followed
+// by a stable sort by tile gives.  Keys are distinct (records are).
+//
+// Lists of up to kTileSortCap keys are merge-sorted in LDS: each thread sorts
+// 8 keys in registers (Batcher's odd-even merge network, 19 comparators), then
+// rounds merge pairs of sorted runs of L keys into runs of 2L, each thread
+// producing 8 consecutive outputs: a binary search along its diagonal of the
+// merge (the "merge path" of Odeh et al., 2012) finds how many of them precede
+// it in the first run, and a sequential merge of 8 steps follows.  Lists under
+// 512 keys take one wave each; longer ones a workgroup.  A list longer than
+// kTileSortCap sorts its kTileSortCap-blocks that way and merges them with
+// Batcher's bitonic network in global memory (rare: the tile-local binning is
+// chosen for short lists).
+// ---------------------------------------------------------------------------
+constexpr int kTileSortThreads = 256;
+constexpr uint32_t kTileSortCap = 8 * kTileSortThreads;   // 2048 keys (16 KB of LDS)
+constexpr uint32_t kTileSortWaveCap = 8 * 64;              // lists below this take one wave
+constexpr uint64_t kKeyInf = ~0ull;                        // above every key
+
+__device__ __forceinline__ void cmp_swap(uint64_t &a, uint64_t &b) {
+    const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+    a = lo;
+    b = hi;
+}
+
+__device__ __forceinline__ void sort8(uint64_t (&k)[8]) {
+    cmp_swap(k[0], k[1]), cmp_swap(k[2], k[3]), cmp_swap(k[4], k[5]), cmp_swap(k[6], k[7]);
+    cmp_swap(k[0], k[2]), cmp_swap(k[1], k[3]), cmp_swap(k[4], k[6]), cmp_swap(k[5], k[7]);
+    cmp_swap(k[1], k[2]), cmp_swap(k[5], k[6]);
+    cmp_swap(k[0], k[4]), cmp_swap(k[1], k[5]), cmp_swap(k[2], k[6]), cmp_swap(k[3], k[7]);
+    cmp_swap(k[2], k[4]), cmp_swap(k[3], k[5]);
+    cmp_swap(k[1], k[2]), cmp_swap(k[3], k[4]), cmp_swap(k[5], k[6]);
+}
+
+// Sorts n keys (n <= 8 nt, all nt threads calling with their t; thread t
+// holds keys 8t .. 8t + 7 in k, kKeyInf past n) using s[0, n) in LDS, and
+// writes their low words (the records) in order to dst[0, n).  sync() orders
+// the LDS accesses of the nt threads.
+template <class Sync>
+__device__ __forceinline__ void lds_merge_sort(uint64_t *s, uint32_t n, uint32_t t, uint64_t (&k)[8], uint32_t *dst,
+                                               Sync sync) {
+    const uint32_t d0 = 8 * t;
+    sort8(k);
+    if (n <= 8) {   // uniform: one thread holds all
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (d0 + q < n) dst[d0 + q] = (uint32_t)k[q];
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if (d0 + q < n) s[d0 + q] = k[q];
+    sync();
+    for (uint32_t L = 8; L < n; L <<= 1) {
+        uint64_t o[8];
+        uint32_t cnt = 0;
+        if (d0 < n) {
+            const uint32_t base = d0 & ~(2 * L - 1u), d = d0 - base;
+            const uint32_t na = n - base < L ? n - base : L;
+            const uint32_t nb = n - base > L ? (n - base - L < L ? n - base - L : L) : 0u;
+            const uint64_t *A = s + base, *B = A + L;
+            uint32_t lo = d > nb ? d - nb : 0u, hi = d < na ? d : na;
+            while (lo < hi) {   // outputs [0, d) hold A[0, lo) and B[0, d - lo)
+                const uint32_t mid = (lo + hi) >> 1;
+                if (A[mid] < B[d - 1u - mid])
+                    lo = mid + 1u;
+                else
+                    hi = mid;
+            }
+            uint32_t i = lo, j = d - lo;
+            uint64_t ai = i < na ? A[i] : kKeyInf, bj = j < nb ? B[j] : kKeyInf;
+            cnt = na + nb - d < 8u ? na + nb - d : 8u;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const bool take = ai < bj;
+                o[q] = take ? ai : bj;
+                if ((uint32_t)q + 1u < cnt) {
+                    if (take) {
+                        ++i;
+                        ai = i < na ? A[i] : kKeyInf;
+                    } else {
+                        ++j;
+                        bj = j < nb ? B[j] : kKeyInf;
+                    }
+                }
+            }
+        }
+        if (2 * L >= n) {   // the last round writes the records (uniform)
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if ((uint32_t)q < cnt) dst[d0 + q] = (uint32_t)o[q];
+            return;
+        }
+        sync();
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if ((uint32_t)q < cnt) s[d0 + q] = o[q];
+        sync();
+    }
+}
+
+// Positions (i, l), i < l, of comparator c of a bitonic step with distance j
+// (written with ascending comparators only: the first step of the merge of
+// two sorted k/2-blocks, j = k / 2, flip, compares i with its mirror image in
+// the k-block; the later steps i with i + j).  Over a power of two P >= n,
+// positions >= n behave as +inf: no comparator moves a key into them, so the
+// comparators that reach past n are skipped.
+__device__ __forceinline__ void bitonic_pair(uint32_t c, uint32_t j, bool flip, uint32_t &i, uint32_t &l) {
+    const uint32_t off = c & (j - 1u);
+    i = ((c - off) << 1) + off;
+    l = flip ? i + ((j - off) << 1) - 1u : i + j;
+}
+
+__device__ __forceinline__ uint32_t pow2_at_least(uint32_t n) {
+    uint32_t p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// Sorts every tile's list: in = the emission's lists, out = the sorted ones,
+// both over the pair range [ranges[t].x, ranges[t].y); zrec = the records'
+// depth keys; torder = the tiles by decreasing list length, of which the first
+// counters[kCntSortBig] have kTileSortWaveCap keys or more.  Workgroup b <
+// nbig takes tile torder[b]; the others take four short lists each, one per
+// wave.  hi / lo: scratch over the pair range for the keys of the lists
+// longer than kTileSortCap.
+__global__ __launch_bounds__(kTileSortThreads) void k_tile_sort(const uint2 *__restrict__ ranges,
+                                                                const uint32_t *__restrict__ torder, int64_t n_tiles,
+                                                                const int64_t *__restrict__ counters,
+                                                                const uint32_t *__restrict__ zrec,
+                                                                const uint32_t *__restrict__ in,
+                                                                uint32_t *__restrict__ out, uint32_t *__restrict__ hi,
+                                                                uint32_t *__restrict__ lo) {
+    __shared__ uint64_t s[kTileSortCap];
+    const uint32_t t = threadIdx.x, wave = t >> 6, lane = t & 63u;
+    const int64_t nbig = counters[kCntSortBig];
+    const bool big = (int64_t)blockIdx.x < nbig;
+    const int64_t slot = big ? (int64_t)blockIdx.x : nbig + 4 * ((int64_t)blockIdx.x - nbig) + wave;
+    if (slot >= n_tiles) return;   // wave-uniform (a whole workgroup when big)
+    const uint32_t tile = torder[slot];
+    if ((int64_t)tile >= n_tiles) return;   // never expected: torder is a permutation
+    const uint2 r = ranges[tile];
+    const int64_t K = counters[kCntPairsUsed];
+    if (!(r.x < r.y) || (int64_t)r.y > K) return;   // empty (or never expected: out of range)
+    const uint32_t n = r.y - r.x;
+    const uint32_t *src = in + r.x;
+    uint32_t *dst = out + r.x;
+    const uint32_t n_rec = (uint32_t)counters[kCntVisible];
+    auto key_of = [&](uint32_t rec) {   // rec < n_rec always; the select keeps reads in bounds
+        return ((uint64_t)zrec[rec < n_rec ? rec : 0u] << 32) | (uint64_t)rec;
+    };
+    // thread u's keys 8u .. 8u + 7 of list[0, m), all loads in flight together
+    auto load8 = [&](const uint32_t *list, uint32_t m, uint32_t u, uint64_t (&k)[8]) {
+        uint32_t rec[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) rec[q] = 8 * u + q < m ? list[8 * u + q] : 0u;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) k[q] = 8 * u + q < m ? key_of(rec[q]) : kKeyInf;
+    };
+    auto block_sync = [] { __syncthreads(); };
+    if (!big) {   // one wave, its own kTileSortWaveCap keys of LDS
+        if (n > kTileSortWaveCap) {   // never expected (nbig counts every such list); noted, not sorted
+            if (lane == 0) atomicAdd((unsigned long long *)&counters[kCntSyncError], 1ull);
+            return;
+        }
+        uint64_t *w = s + wave * kTileSortWaveCap;
+        auto wave_sync = [] {   // LDS operations of a wave complete in order
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        };
+        uint64_t k[8];
+        load8(src, n, lane, k);
+        lds_merge_sort(w, n, lane, k, dst, wave_sync);
+        return;
+    }
+    constexpr uint32_t NT = kTileSortThreads, C = kTileSortCap;
+    if (n <= C) {
+        uint64_t k[8];
+        load8(src, n, t, k);
+        lds_merge_sort(s, n, t, k, dst, block_sync);
+        return;
+    }
+    // a long list: its C-blocks merge-sorted into (hi, lo), then Batcher's
+    // merges of 2C-blocks and wider, the steps of distance >= C in global
+    // memory and the rest within each C-block in LDS
+    uint32_t *kh = hi + r.x, *kl = lo + r.x;
+    const uint32_t P = pow2_at_least(n), nblk = (n + C - 1) / C;
+    for (uint32_t b = 0; b < nblk; ++b) {
+        const uint32_t base = b * C, nb = n - base < C ? n - base : C;
+        uint64_t k[8];
+        load8(src + base, nb, t, k);
+        __syncthreads();   // the previous block's use of s
+        lds_merge_sort(s, nb, t, k, kl + base, block_sync);   // records in order into lo
+        __syncthreads();
+        for (uint32_t c = t; c < nb; c += NT) kh[base + c] = zrec[kl[base + c] < n_rec ? kl[base + c] : 0u];
+        __syncthreads();
+    }
+    for (uint32_t k = 2 * C; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j >= C; j >>= 1) {
+            const bool flip = j == (k >> 1);
+            for (uint32_t c = t; c < (P >> 1); c += NT) {
+                uint32_t i, l;
+                bitonic_pair(c, j, flip, i, l);
+                if (l < n) {
+                    const uint64_t a = ((uint64_t)kh[i] << 32) | kl[i], b = ((uint64_t)kh[l] << 32) | kl[l];
+                    if (b < a) {
+                        kh[i] = (uint32_t)(b >> 32), kl[i] = (uint32_t)b;
+                        kh[l] = (uint32_t)(a >> 32), kl[l] = (uint32_t)a;
+                    }
+                }
+            }
+            __syncthreads();   // the workgroup's global stores before its next loads
+        }
+        for (uint32_t b = 0; b < nblk; ++b) {
+            const uint32_t base = b * C, nb = n - base < C ? n - base : C, half = pow2_at_least(nb) >> 1;
+            for (uint32_t c = t; c < nb; c += NT) s[c] = ((uint64_t)kh[base + c] << 32) | kl[base + c];
+            __syncthreads();
+            for (uint32_t j = C >> 1; j >= 1; j >>= 1) {   // the half-cleaners of this merge within the block
+                for (uint32_t c = t; c < half; c += NT) {
+                    uint32_t i, l;
+                    bitonic_pair(c, j, false, i, l);
+                    if (l < nb) {
+                        const uint64_t a = s[i], b2 = s[l];
+                        if (b2 < a) {
+                            s[i] = b2;
+                            s[l] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            for (uint32_t c = t; c < nb; c += NT) {
+                if (k == P) {
+                    dst[base + c] = (uint32_t)s[c];
+                } else {
+                    kh[base + c] = (uint32_t)(s[c] >> 32);
+                    kl[base + c] = (uint32_t)s[c];
+                }
+            }
+            __syncthreads();
+        }
+    }
 }
 
 }  // namespace gsr

@@ -92,9 +92,12 @@ def _check_binning(rast, w, tile):
         pr = oracle.project_view(w.gaussians, w.views, v, _oracle_opts(w))
         mine = np.sort(gid[gid // n == v] % n)
         assert np.array_equal(mine, np.nonzero(pr.visible)[0]), f"view {v}: visible sets differ"
-    # records are in (float32 depth bits, view*N+i) order
+    # records are in (float32 depth bits, view*N+i) order (the two global
+    # sorts) or in view*N+i order (tile-local binning)
     zb = z.view(np.uint32).astype(np.int64)
-    assert np.all((zb[1:] > zb[:-1]) | ((zb[1:] == zb[:-1]) & (gid[1:] > gid[:-1])))
+    by_depth = np.all((zb[1:] > zb[:-1]) | ((zb[1:] == zb[:-1]) & (gid[1:] > gid[:-1])))
+    by_index = np.all(gid[1:] > gid[:-1])
+    assert by_depth or by_index
     # rebuild every tile's list from the records' own float32 rectangles
     tw, th = tile
     f32 = np.float32
@@ -129,9 +132,14 @@ def _check_binning(rast, w, tile):
     return mism
 
 
+@pytest.mark.parametrize("capacity", [None, 20_000])
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (8, 16), (32, 32), (32, 16), (16, 32)])
-def test_binning_bit_exact_config1(rast, tile):
-    assert _check_binning(rast, scenes.config1(), tile) == 0
+def test_binning_bit_exact_config1(rast, tile, capacity):
+    """At the default pair capacity (over 4096 pairs per tile) the two global
+    sorts bin; at 20 000 (under 2 000 per tile) the tile-local binning."""
+    from paper_2408_05635_amd import raster
+    r = rast if capacity is None else raster.Rasterizer(0, pair_capacity=capacity)
+    assert _check_binning(r, scenes.config1(), tile) == 0
 
 
 def test_binning_bit_exact_multiview(rast):
@@ -164,11 +172,17 @@ def test_binning_bit_exact_long_lists(capacity):
     assert mism == 0
 
 
-def test_binning_bit_exact_many_blocks(rast):
-    """Hundreds of scan and sort blocks per pass, so that the blocks' look-back
-    chains are long and blocks overtake each other."""
+@pytest.mark.parametrize("per_tile", [0, 5000])
+def test_binning_bit_exact_many_blocks(per_tile):
+    """Hundreds of scan blocks, so that the blocks' look-back chains are long
+    and blocks overtake each other: tile-local binning at the default pair
+    capacity, and (5000 pairs of capacity per tile) the two global sorts with
+    hundreds of sort blocks per pass."""
+    from paper_2408_05635_amd import raster
     w = scenes.config2(n_views=4, n=120000)
-    assert _check_binning(rast, w, (16, 16)) == 0
+    tiles = sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in w.views.cams)
+    r = raster.Rasterizer(0, pair_capacity=per_tile * tiles) if per_tile else raster.Rasterizer(0)
+    assert _check_binning(r, w, (16, 16)) == 0
 
 
 def _fused(rast, w, tile=(16, 16), targets=None, weight=None, **kw):
