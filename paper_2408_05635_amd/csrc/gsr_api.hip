@@ -125,6 +125,7 @@ constexpr int kDepthPasses = 4, kMaxTilePasses = 3;
 // this many pairs per tile
 constexpr int64_t kTileLocalMaxTiles = 16384;   // a block's tile counts fit LDS (64 KB)
 constexpr int64_t kTileLocalMaxAvg = 4096;
+constexpr int64_t kTileSortGrid = 2048;          // workgroups of the per-tile sort (8 per CU), looping over the lists
 
 struct Layout {
     int64_t vn;           // V * N
@@ -147,7 +148,7 @@ struct Layout {
     size_t tcnt, ttot, tstart;
     // offsets in the sync region (cleared by every call): scan look-back words,
     // sort-pass look-back words, digit histograms (depth passes, then tile
-    // passes), the views' first pairs (tile-local binning; 1 + pair, 0 = none)
+    // passes), every view's first record (tile-local binning)
     size_t sync_status, sync_sweep, sync_hist, sync_vstart, sync_bytes;
     size_t total;
 };
@@ -448,17 +449,8 @@ __global__ __launch_bounds__(256) void k_setup_project(ViewTable tab, ViewTable 
 struct OffSink {
     uint32_t *off, *chunk_first;
     int64_t n_chunks;   // capacity of chunk_first
-    // tile-local binning (records in view order): 1 + the first pair of every
-    // view up to the record's, past the previous record's view
-    uint32_t *vstart1 = nullptr;
-    const uint32_t *gid = nullptr;
-    int64_t n = 1;
     __device__ void operator()(int64_t s, uint32_t pos, uint32_t cnt) const {
         off[s] = pos;
-        if (vstart1) {
-            const int64_t v = gid[s] / n, vp = s > 0 ? (int64_t)(gid[s - 1] / n) : -1;
-            for (int64_t u = vp + 1; u <= v && u < GSR_MAX_VIEWS; ++u) vstart1[u] = pos + 1u;
-        }
         if (cnt == 0) return;
         for (int64_t m = ((int64_t)pos + kEmitChunk - 1) / kEmitChunk;
              m * kEmitChunk < (int64_t)pos + cnt && m < n_chunks; ++m)
@@ -623,6 +615,53 @@ __device__ __forceinline__ uint32_t emit_pair(int64_t j, const EmitWindow &w, co
     return (uint32_t)V.tile_off + ty * (uint32_t)V.tiles_x + tx;
 }
 
+// f(j, tile key, record) for the consecutive pairs j in [ja, jb) of the
+// staged chunk: one search for the first pair, then the record's tiles in
+// row-major order, moving to the next record after its last tile.
+template <class F>
+__device__ __forceinline__ void emit_run(int64_t ja, int64_t jb, const EmitWindow &w, const uint32_t *s_off,
+                                         const uint2 *__restrict__ trect, const uint32_t *__restrict__ gid,
+                                         const ViewTable *__restrict__ vt, int64_t n, F f) {
+    if (ja >= jb) return;
+    int lo = 0, hi = w.nwin;   // s_off[0] <= ja; find the last entry <= ja
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)s_off[mid] <= ja)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    uint32_t rec = (uint32_t)(w.s0 + lo), k = (uint32_t)ja - s_off[lo];
+    uint32_t tx0, tx1, tx, ty, np, base, tiles_x;
+    auto load_rec = [&]() {
+        const uint2 tr = trect[rec];
+        tx0 = tr.x & 0xffffu;
+        tx1 = tr.x >> 16;
+        const uint32_t ty0 = tr.y & 0xffffu, nx = tx1 - tx0 + 1u;
+        np = nx * ((tr.y >> 16) - ty0 + 1u);
+        int v = (int)(gid[rec] / (uint32_t)n);
+        if (v >= vt->n_views) v = 0;
+        base = (uint32_t)vt->v[v].tile_off;
+        tiles_x = (uint32_t)vt->v[v].tiles_x;
+        ty = ty0 + k / nx;
+        tx = tx0 + k % nx;
+    };
+    load_rec();
+    for (int64_t j = ja; j < jb; ++j) {
+        f(j, base + ty * tiles_x + tx, rec);
+        if (j + 1 < jb) {
+            if (++k == np) {   // the record's last pair: the next record starts at its first tile
+                ++rec;
+                k = 0;
+                load_rec();
+            } else if (++tx > tx1) {
+                tx = tx0;
+                ++ty;
+            }
+        }
+    }
+}
+
 // One block per chunk: keys[j] = tile, vals[j] = record.  With hist (the
 // one-launch tile sort), the histograms of the key bits [0, key_bits) in
 // 8-bit digits are also added into hist[pass][256] (zero beforehand).
@@ -710,13 +749,13 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_count(const int64_t *__re
     const EmitWindow w = emit_stage(m, K, M, poff, chunk_first, s_off);
     __syncthreads();
     chunk_views(m, K, w, s_off, trect, gid, vt, n, &s_span);
-    for (int q0 = 0; q0 < kEmitChunk; q0 += blockDim.x) {
-        const int64_t j = j0 + q0 + (int)threadIdx.x;
-        if (j < K) {
-            uint32_t rs;
-            const uint32_t key = emit_pair(j, w, s_off, trect, gid, vt, n, rs);
-            if ((int64_t)key < n_tiles) atomicAdd(&s_h[key], 1u);   // always true; keeps accesses in bounds
-        }
+    {   // each thread kEmitChunk / kEmitThreads consecutive pairs
+        constexpr int kRun = kEmitChunk / kEmitThreads;
+        const int64_t ja = j0 + (int64_t)threadIdx.x * kRun, je = j0 + kEmitChunk < K ? j0 + kEmitChunk : K;
+        emit_run(ja, ja + kRun < je ? ja + kRun : je, w, s_off, trect, gid, vt, n,
+                 [&](int64_t, uint32_t key, uint32_t) {
+                     if ((int64_t)key < n_tiles) atomicAdd(&s_h[key], 1u);   // always true; keeps accesses in bounds
+                 });
     }
     __syncthreads();
     for (int v = s_span.v0; v <= s_span.v1; ++v) {
@@ -729,21 +768,23 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_count(const int64_t *__re
 
 // One thread per tile: the exclusive offsets of its column over the blocks
 // that hold pairs of its view (those whose chunks meet the view's pair range
-// [start(v), start(v + 1)), from vstart1), and its total.
+// [start(v), start(v + 1)): start(v) is the first pair of the view's first
+// record vrec[v], K past the last record), and its total.
 __global__ __launch_bounds__(256) void k_tile_offsets(const ViewTable *__restrict__ vt,
                                                       const int64_t *__restrict__ counters,
-                                                      const uint32_t *__restrict__ vstart1, int64_t n_tiles,
+                                                      const uint32_t *__restrict__ vrec,
+                                                      const uint32_t *__restrict__ poff, int64_t n_tiles,
                                                       int64_t row_len, uint32_t *__restrict__ counts,
                                                       uint32_t *__restrict__ ttot) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= n_tiles) return;
-    const int64_t K = counters[kCntPairsUsed];
+    const int64_t K = counters[kCntPairsUsed], M = counters[kCntVisible];
     const int nv = vt->n_views;
     int v = 0;
     while (v + 1 < nv && vt->v[v + 1].tile_off <= t) ++v;
     const int64_t x = t - vt->v[v].tile_off;
-    const int64_t ps = vstart1[v] ? (int64_t)vstart1[v] - 1 : K;
-    const int64_t pe = v + 1 < nv && vstart1[v + 1] ? (int64_t)vstart1[v + 1] - 1 : K;
+    const int64_t ps = (int64_t)vrec[v] < M ? (int64_t)poff[vrec[v]] : K;
+    const int64_t pe = v + 1 < nv && (int64_t)vrec[v + 1] < M ? (int64_t)poff[vrec[v + 1]] : K;
     uint32_t run = 0;
     if (pe > ps && pe <= K) {
         const int64_t b0 = ps / kEmitChunk, b1 = (pe - 1) / kEmitChunk;
@@ -796,16 +837,16 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_place(const int64_t *__re
         for (int k = threadIdx.x; k < tv; k += blockDim.x) s_cur[V.tile_off + k] = tstart[V.tile_off + k] + row[k];
     }
     __syncthreads();
-    for (int q0 = 0; q0 < kEmitChunk; q0 += blockDim.x) {
-        const int64_t j = j0 + q0 + (int)threadIdx.x;
-        if (j < K) {
-            uint32_t rs;
-            const uint32_t key = emit_pair(j, w, s_off, trect, gid, vt, n, rs);
-            if ((int64_t)key < n_tiles) {   // always true; keeps accesses in bounds
-                const uint32_t slot = atomicAdd(&s_cur[key], 1u);
-                if ((int64_t)slot < K) vals[slot] = rs;   // always true; keeps writes in bounds
-            }
-        }
+    {
+        constexpr int kRun = kEmitChunk / kEmitThreads;
+        const int64_t ja = j0 + (int64_t)threadIdx.x * kRun, je = j0 + kEmitChunk < K ? j0 + kEmitChunk : K;
+        emit_run(ja, ja + kRun < je ? ja + kRun : je, w, s_off, trect, gid, vt, n,
+                 [&](int64_t, uint32_t key, uint32_t rs) {
+                     if ((int64_t)key < n_tiles) {   // always true; keeps accesses in bounds
+                         const uint32_t slot = atomicAdd(&s_cur[key], 1u);
+                         if ((int64_t)slot < K) vals[slot] = rs;   // always true; keeps writes in bounds
+                     }
+                 });
     }
 }
 
@@ -830,17 +871,15 @@ __global__ void k_fill_f64(double *p, int64_t n) {
 constexpr int kOrderThreads = 1024;
 constexpr uint32_t kOrderBuckets = 256;
 
-__device__ __forceinline__ void work_order_block(const uint2 *__restrict__ ranges, int64_t n_tiles, int64_t slots_cap,
+// len_of(i): the list length of tile i.
+template <class Len>
+__device__ __forceinline__ void work_order_block(Len len_of, int64_t n_tiles, int64_t slots_cap,
                                                  uint32_t *__restrict__ torder, uint32_t *__restrict__ cpoff,
                                                  uint32_t *__restrict__ work, int64_t *__restrict__ n_work,
                                                  int64_t *__restrict__ counters) {
     __shared__ uint32_t s_h[kOrderBuckets];
     __shared__ int64_t s_run;
     const int t = threadIdx.x;
-    auto len_of = [&](int64_t i) {
-        const uint2 r = ranges[i];
-        return r.y > r.x ? r.y - r.x : 0u;
-    };
     auto bucket_of = [](uint32_t len) {
         const uint32_t b = len >> 4;
         return (kOrderBuckets - 1u) - (b < kOrderBuckets - 1u ? b : kOrderBuckets - 1u);
@@ -922,7 +961,12 @@ __global__ __launch_bounds__(kOrderThreads) void k_work_order(const uint2 *__res
                                                               uint32_t *__restrict__ cpoff, uint32_t *__restrict__ work,
                                                               int64_t *__restrict__ n_work,
                                                               int64_t *__restrict__ counters) {
-    work_order_block(ranges, n_tiles, slots_cap, torder, cpoff, work, n_work, counters);
+    work_order_block(
+        [&](int64_t i) {
+            const uint2 r = ranges[i];
+            return r.y > r.x ? r.y - r.x : 0u;
+        },
+        n_tiles, slots_cap, torder, cpoff, work, n_work, counters);
 }
 
 // Tile-local binning: every tile's list [start, end) from the tiles' pair
@@ -938,6 +982,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_ranges(const uint32_t *_
                                                                int64_t *__restrict__ n_work,
                                                                int64_t *__restrict__ counters) {
     __shared__ uint32_t s_big;
+    __shared__ uint32_t s_len[kTileLocalMaxTiles];   // the list lengths, for the work order
     const int t = threadIdx.x;
     if (t == 0) s_big = 0u;
     uint32_t run = 0, big = 0;   // run: the totals before this round (the same in every thread)
@@ -957,16 +1002,16 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_ranges(const uint32_t *_
             if (d0 + q < n_tiles) {
                 ranges[d0 + q] = make_uint2(start, start + x[q]);
                 tstart[d0 + q] = start;
+                s_len[d0 + q] = x[q];
                 big += x[q] >= kTileSortWaveCap ? 1u : 0u;
             }
             start += x[q];
         }
     }
     if (big) atomicAdd(&s_big, big);
-    __threadfence_block();
-    __syncthreads();   // the ranges before the work order reads them
+    __syncthreads();   // the lengths before the work order reads them
     if (t == 0) counters[kCntSortBig] = s_big;
-    work_order_block(ranges, n_tiles, slots_cap, torder, cpoff, work, n_work, counters);
+    work_order_block([&](int64_t i) { return s_len[i]; }, n_tiles, slots_cap, torder, cpoff, work, n_work, counters);
 }
 
 struct GradOut {
@@ -1449,12 +1494,14 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     if (L.vn > 0 && L.tile_local) {
         hipLaunchKernelGGL(k_compact_hist, dim3((unsigned)((L.vn + kCompactChunk - 1) / kCompactChunk)),
                            dim3(kCompactThreads), 0, st, (const uint32_t *)cnt, (const uint32_t *)zkey, L.vn, dk0, dv0,
-                           ss, (uint32_t)kIdCompact, (uint32_t *)nullptr, counters + kCntVisible);
+                           ss, (uint32_t)kIdCompact, (uint32_t *)nullptr, counters + kCntVisible,
+                           reinterpret_cast<uint32_t *>(sync + L.sync_vstart), c.pp.n);
     } else if (L.vn > 0) {
         if (L.depth_sweep) {
             hipLaunchKernelGGL(k_compact_hist, dim3((unsigned)((L.vn + kCompactChunk - 1) / kCompactChunk)),
                                dim3(kCompactThreads), 0, st, (const uint32_t *)cnt, (const uint32_t *)zkey, L.vn, dk0,
-                               dv0, ss, (uint32_t)kIdCompact, dhist, counters + kCntVisible);
+                               dv0, ss, (uint32_t)kIdCompact, dhist, counters + kCntVisible, (uint32_t *)nullptr,
+                               (int64_t)1);
             for (int p = 0; p < kDepthPasses; ++p) {   // (k0, v0) -> (k1, v1) -> ... -> (k0, v0)
                 const bool from0 = p % 2 == 0;
                 hipLaunchKernelGGL(k_sweep<PairIn>, dim3((unsigned)sweep_blocks(L.vn)), dim3(kSweepThreads), 0, st,
@@ -1479,11 +1526,6 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     // records and their pair offsets; the last block checks the pair capacity
     float *rrows = c.tab.deterministic ? nullptr : at<float>(ws, L.rrows);
     OffSink osink{poff, chunk_first, n_chunks};
-    if (L.tile_local) {
-        osink.vstart1 = reinterpret_cast<uint32_t *>(sync + L.sync_vstart);
-        osink.gid = gid_sorted;
-        osink.n = std::max<int64_t>(c.pp.n, 1);
-    }
     if (L.depth_sweep) {   // few records: one launch
         if (L.vn > 0)
             hipLaunchKernelGGL(c.pp.iso ? k_gather_scan<true> : k_gather_scan<false>,
@@ -1506,7 +1548,7 @@ void enqueue_binning(Call &c, const gsr_views *views) {
         uint32_t *torder = at<uint32_t>(ws, L.torder), *tcnt = at<uint32_t>(ws, L.tcnt);
         uint32_t *ttot = at<uint32_t>(ws, L.ttot), *tstart = at<uint32_t>(ws, L.tstart);
         const bool pairs = L.vn > 0 && L.kcap > 0;
-        const uint32_t *vstart1 = reinterpret_cast<const uint32_t *>(sync + L.sync_vstart);
+        const uint32_t *vrec = reinterpret_cast<const uint32_t *>(sync + L.sync_vstart);
         if (pairs) {
             hipLaunchKernelGGL(k_emit_count, dim3((unsigned)n_chunks), dim3(kEmitThreads), 0, st,
                                (const int64_t *)counters, (const uint32_t *)poff, (const uint32_t *)chunk_first,
@@ -1514,7 +1556,8 @@ void enqueue_binning(Call &c, const gsr_views *views) {
         }
         if (L.T > 0) {
             hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)((L.T + 255) / 256)), dim3(256), 0, st,
-                               (const ViewTable *)vt, (const int64_t *)counters, vstart1, L.T, L.tv_max, tcnt, ttot);
+                               (const ViewTable *)vt, (const int64_t *)counters, vrec, (const uint32_t *)poff, L.T,
+                               L.tv_max, tcnt, ttot);
             hipLaunchKernelGGL(k_tile_ranges, dim3(1), dim3(kOrderThreads), 0, st, (const uint32_t *)ttot, L.T,
                                ranges, tstart, L.cp_slots, torder, at<uint32_t>(ws, L.cpoff), at<uint32_t>(ws, L.work),
                                at<int64_t>(ws, L.nwork), counters);
@@ -1524,9 +1567,9 @@ void enqueue_binning(Call &c, const gsr_views *views) {
                                (const int64_t *)counters, (const uint32_t *)poff, (const uint32_t *)chunk_first,
                                (const uint2 *)trect, gid_sorted, (const ViewTable *)vt, c.pp.n, L.T, L.tv_max,
                                (const uint32_t *)tcnt, (const uint32_t *)tstart, pv0);
-            hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)L.T), dim3(kTileSortThreads), 0, st, (const uint2 *)ranges,
-                               (const uint32_t *)torder, L.T, (const int64_t *)counters, (const uint32_t *)dk0,
-                               (const uint32_t *)pv0, pv1, pk0, pk1);
+            hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)std::min<int64_t>(L.T, kTileSortGrid)),
+                               dim3(kTileSortThreads), 0, st, (const uint2 *)ranges, (const uint32_t *)torder, L.T,
+                               counters, (const uint32_t *)dk0, (const uint32_t *)pv0, pv1, pk0, pk1);
         }
         return;
     }

@@ -722,7 +722,10 @@ __device__ __forceinline__ void flush_digit_hist(const uint32_t *s_hist, int pas
 // single-pass scan (decoupled look-back over blocks of kCompactChunk items),
 // and their number (written to *n_out by the last block).  With hist (the
 // first step of the one-launch depth sort), also the histograms of the four
-// byte digits of their keys (added into hist[4][256], zero beforehand).
+// byte digits of their keys (added into hist[4][256], zero beforehand).  With
+// first (items in groups of `group`, here the views' N Gaussians), also the
+// output place of every group's first visible item: the number of visible
+// items before the group.
 constexpr int kCompactThreads = 1024;
 constexpr int kCompactItems = 4;
 constexpr int kCompactChunk = kCompactThreads * kCompactItems;
@@ -732,7 +735,8 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact_hist(const uint32_t
                                                                   uint32_t *__restrict__ kout,
                                                                   uint32_t *__restrict__ vout, SyncState ss,
                                                                   uint32_t id, uint32_t *__restrict__ hist,
-                                                                  int64_t *__restrict__ n_out) {
+                                                                  int64_t *__restrict__ n_out,
+                                                                  uint32_t *__restrict__ first_of, int64_t group) {
     __shared__ uint32_t s_b, s_excl;
     __shared__ uint32_t s_hist[4 * 256];
     const uint32_t t = threadIdx.x;
@@ -782,8 +786,15 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact_hist(const uint32_t
     }
     __syncthreads();   // also orders the LDS histogram's atomics before the flush
     run += s_excl;
+    // the first group start at or after this thread's first item
+    int64_t gs = -1;
+    if (first_of && first < n) gs = (first + group - 1) / group * group;
 #pragma unroll
     for (int j = 0; j < kCompactItems; ++j) {
+        if (gs == first + j && gs < n) {   // a group starts at item first + j
+            first_of[gs / group] = run;
+            gs += group;
+        }
         if (c[j] != 0u) {
             kout[run] = k[j];
             vout[run] = (uint32_t)(first + j);
@@ -872,16 +883,18 @@ __device__ __forceinline__ void lds_merge_sort(uint64_t *s, uint32_t n, uint32_t
             cnt = na + nb - d < 8u ? na + nb - d : 8u;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
+                // branch-free: the side taken advances and its next key is read
+                // at an address in bounds (the run's first key when past it)
                 const bool take = ai < bj;
                 o[q] = take ? ai : bj;
-                if ((uint32_t)q + 1u < cnt) {
-                    if (take) {
-                        ++i;
-                        ai = i < na ? A[i] : kKeyInf;
-                    } else {
-                        ++j;
-                        bj = j < nb ? B[j] : kKeyInf;
-                    }
+                if (q < 7) {
+                    i += take ? 1u : 0u;
+                    j += take ? 0u : 1u;
+                    const bool in = take ? i < na : j < nb;
+                    const uint64_t nxt = (in && !take ? B : A)[in ? (take ? i : j) : 0u];   // A[0] exists
+                    const uint64_t v = in ? nxt : kKeyInf;
+                    ai = take ? v : ai;
+                    bj = take ? bj : v;
                 }
             }
         }
@@ -920,32 +933,22 @@ __device__ __forceinline__ uint32_t pow2_at_least(uint32_t n) {
 // Sorts every tile's list: in = the emission's lists, out = the sorted ones,
 // both over the pair range [ranges[t].x, ranges[t].y); zrec = the records'
 // depth keys; torder = the tiles by decreasing list length, of which the first
-// counters[kCntSortBig] have kTileSortWaveCap keys or more.  Workgroup b <
-// nbig takes tile torder[b]; the others take four short lists each, one per
-// wave.  hi / lo: scratch over the pair range for the keys of the lists
-// longer than kTileSortCap.
-__global__ __launch_bounds__(kTileSortThreads) void k_tile_sort(const uint2 *__restrict__ ranges,
-                                                                const uint32_t *__restrict__ torder, int64_t n_tiles,
-                                                                const int64_t *__restrict__ counters,
-                                                                const uint32_t *__restrict__ zrec,
-                                                                const uint32_t *__restrict__ in,
-                                                                uint32_t *__restrict__ out, uint32_t *__restrict__ hi,
-                                                                uint32_t *__restrict__ lo) {
-    __shared__ uint64_t s[kTileSortCap];
+// nbig = counters[kCntSortBig] have kTileSortWaveCap keys or more.  Work item
+// w < nbig is tile torder[w] for a whole workgroup; the later items are four
+// short lists each, one per wave; workgroups loop over the items.  hi / lo:
+// scratch over the pair range for the keys of the lists longer than
+// kTileSortCap.
+__device__ __forceinline__ void sort_tile_list(uint64_t *s, bool big, uint32_t tile, const uint2 *__restrict__ ranges,
+                                               int64_t K, uint32_t n_rec, const uint32_t *__restrict__ zrec,
+                                               const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                               uint32_t *__restrict__ hi, uint32_t *__restrict__ lo,
+                                               int64_t *__restrict__ error) {
     const uint32_t t = threadIdx.x, wave = t >> 6, lane = t & 63u;
-    const int64_t nbig = counters[kCntSortBig];
-    const bool big = (int64_t)blockIdx.x < nbig;
-    const int64_t slot = big ? (int64_t)blockIdx.x : nbig + 4 * ((int64_t)blockIdx.x - nbig) + wave;
-    if (slot >= n_tiles) return;   // wave-uniform (a whole workgroup when big)
-    const uint32_t tile = torder[slot];
-    if ((int64_t)tile >= n_tiles) return;   // never expected: torder is a permutation
     const uint2 r = ranges[tile];
-    const int64_t K = counters[kCntPairsUsed];
-    if (!(r.x < r.y) || (int64_t)r.y > K) return;   // empty (or never expected: out of range)
+    if (!(r.x < r.y) || (int64_t)r.y > K) return;   // empty (or never expected: out of range); uniform
     const uint32_t n = r.y - r.x;
     const uint32_t *src = in + r.x;
     uint32_t *dst = out + r.x;
-    const uint32_t n_rec = (uint32_t)counters[kCntVisible];
     auto key_of = [&](uint32_t rec) {   // rec < n_rec always; the select keeps reads in bounds
         return ((uint64_t)zrec[rec < n_rec ? rec : 0u] << 32) | (uint64_t)rec;
     };
@@ -960,7 +963,7 @@ __global__ __launch_bounds__(kTileSortThreads) void k_tile_sort(const uint2 *__r
     auto block_sync = [] { __syncthreads(); };
     if (!big) {   // one wave, its own kTileSortWaveCap keys of LDS
         if (n > kTileSortWaveCap) {   // never expected (nbig counts every such list); noted, not sorted
-            if (lane == 0) atomicAdd((unsigned long long *)&counters[kCntSyncError], 1ull);
+            if (lane == 0) atomicAdd((unsigned long long *)error, 1ull);
             return;
         }
         uint64_t *w = s + wave * kTileSortWaveCap;
@@ -1039,6 +1042,31 @@ __global__ __launch_bounds__(kTileSortThreads) void k_tile_sort(const uint2 *__r
             }
             __syncthreads();
         }
+    }
+}
+
+__global__ __launch_bounds__(kTileSortThreads) void k_tile_sort(const uint2 *__restrict__ ranges,
+                                                                const uint32_t *__restrict__ torder, int64_t n_tiles,
+                                                                int64_t *__restrict__ counters,
+                                                                const uint32_t *__restrict__ zrec,
+                                                                const uint32_t *__restrict__ in,
+                                                                uint32_t *__restrict__ out, uint32_t *__restrict__ hi,
+                                                                uint32_t *__restrict__ lo) {
+    __shared__ uint64_t s[kTileSortCap];
+    const uint32_t wave = threadIdx.x >> 6;
+    const int64_t nbig = counters[kCntSortBig];
+    const int64_t K = counters[kCntPairsUsed];
+    const uint32_t n_rec = (uint32_t)counters[kCntVisible];
+    const int64_t items = nbig + (n_tiles - nbig + 3) / 4;
+    for (int64_t w = blockIdx.x; w < items; w += gridDim.x) {   // uniform over the workgroup
+        const bool big = w < nbig;
+        const int64_t slot = big ? w : nbig + 4 * (w - nbig) + wave;
+        if (slot < n_tiles) {   // wave-uniform; always true for a big item
+            const uint32_t tile = torder[slot];
+            if ((int64_t)tile < n_tiles)   // always true: torder is a permutation
+                sort_tile_list(s, big, tile, ranges, K, n_rec, zrec, in, out, hi, lo, counters + kCntSyncError);
+        }
+        __syncthreads();   // every wave done with s before the next item
     }
 }
 
