@@ -19,6 +19,8 @@
 // be enqueued (or captured in a graph) without a host synchronisation.
 #pragma once
 
+#include <type_traits>
+
 #include "gsr_common.hpp"
 
 namespace gsr {
@@ -813,12 +815,13 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact_hist(const uint32_t
 // by a stable sort by tile gives.  Keys are distinct (records are).
 //
 // Lists of up to kTileSortCap keys are merge-sorted in LDS: each thread sorts
-// 8 keys in registers (Batcher's odd-even merge network, 19 comparators), then
+// E = 1, 2, 4 or 8 keys in registers (Batcher's odd-even merge networks), then
 // rounds merge pairs of sorted runs of L keys into runs of 2L, each thread
-// producing 8 consecutive outputs: a binary search along its diagonal of the
+// producing E consecutive outputs: a binary search along its diagonal of the
 // merge (the "merge path" of Odeh et al., 2012) finds how many of them precede
-// it in the first run, and a sequential merge of 8 steps follows.  Lists under
-// 512 keys take one wave each; longer ones a workgroup.  A list longer than
+// it in the first run, and a sequential merge of E steps follows.  Lists under
+// 512 keys take one wave each (E chosen so that most lanes hold keys); longer
+// ones a workgroup.  A list longer than
 // kTileSortCap sorts its kTileSortCap-blocks that way and merges them with
 // Batcher's bitonic network in global memory (rare: the tile-local binning is
 // chosen for short lists).
@@ -834,36 +837,46 @@ __device__ __forceinline__ void cmp_swap(uint64_t &a, uint64_t &b) {
     b = hi;
 }
 
-__device__ __forceinline__ void sort8(uint64_t (&k)[8]) {
-    cmp_swap(k[0], k[1]), cmp_swap(k[2], k[3]), cmp_swap(k[4], k[5]), cmp_swap(k[6], k[7]);
-    cmp_swap(k[0], k[2]), cmp_swap(k[1], k[3]), cmp_swap(k[4], k[6]), cmp_swap(k[5], k[7]);
-    cmp_swap(k[1], k[2]), cmp_swap(k[5], k[6]);
-    cmp_swap(k[0], k[4]), cmp_swap(k[1], k[5]), cmp_swap(k[2], k[6]), cmp_swap(k[3], k[7]);
-    cmp_swap(k[2], k[4]), cmp_swap(k[3], k[5]);
-    cmp_swap(k[1], k[2]), cmp_swap(k[3], k[4]), cmp_swap(k[5], k[6]);
+template <int E>
+__device__ __forceinline__ void sort_regs(uint64_t (&k)[E]) {   // Batcher's networks for 1, 2, 4, 8 keys
+    if constexpr (E == 2) {
+        cmp_swap(k[0], k[1]);
+    } else if constexpr (E == 4) {
+        cmp_swap(k[0], k[1]), cmp_swap(k[2], k[3]);
+        cmp_swap(k[0], k[2]), cmp_swap(k[1], k[3]);
+        cmp_swap(k[1], k[2]);
+    } else if constexpr (E == 8) {
+        cmp_swap(k[0], k[1]), cmp_swap(k[2], k[3]), cmp_swap(k[4], k[5]), cmp_swap(k[6], k[7]);
+        cmp_swap(k[0], k[2]), cmp_swap(k[1], k[3]), cmp_swap(k[4], k[6]), cmp_swap(k[5], k[7]);
+        cmp_swap(k[1], k[2]), cmp_swap(k[5], k[6]);
+        cmp_swap(k[0], k[4]), cmp_swap(k[1], k[5]), cmp_swap(k[2], k[6]), cmp_swap(k[3], k[7]);
+        cmp_swap(k[2], k[4]), cmp_swap(k[3], k[5]);
+        cmp_swap(k[1], k[2]), cmp_swap(k[3], k[4]), cmp_swap(k[5], k[6]);
+    }
 }
 
-// Sorts n keys (n <= 8 nt, all nt threads calling with their t; thread t
-// holds keys 8t .. 8t + 7 in k, kKeyInf past n) using s[0, n) in LDS, and
-// writes their low words (the records) in order to dst[0, n).  sync() orders
-// the LDS accesses of the nt threads.
-template <class Sync>
-__device__ __forceinline__ void lds_merge_sort(uint64_t *s, uint32_t n, uint32_t t, uint64_t (&k)[8], uint32_t *dst,
+// Sorts n keys (n <= E nt, all nt threads calling with their t; thread t
+// holds keys E t .. E t + E - 1 in k, kKeyInf past n) using s[0, n) in LDS,
+// and writes their low words (the records) in order to dst[0, n).  sync()
+// orders the LDS accesses of the nt threads.  E (keys per thread) is 1, 2, 4
+// or 8: the smallest that keeps the threads busy.
+template <int E, class Sync>
+__device__ __forceinline__ void lds_merge_sort(uint64_t *s, uint32_t n, uint32_t t, uint64_t (&k)[E], uint32_t *dst,
                                                Sync sync) {
-    const uint32_t d0 = 8 * t;
-    sort8(k);
-    if (n <= 8) {   // uniform: one thread holds all
+    const uint32_t d0 = E * t;
+    sort_regs<E>(k);
+    if (n <= (uint32_t)E) {   // uniform: one thread holds all
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < E; ++q)
             if (d0 + q < n) dst[d0 + q] = (uint32_t)k[q];
         return;
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
+    for (int q = 0; q < E; ++q)
         if (d0 + q < n) s[d0 + q] = k[q];
     sync();
-    for (uint32_t L = 8; L < n; L <<= 1) {
-        uint64_t o[8];
+    for (uint32_t L = E; L < n; L <<= 1) {
+        uint64_t o[E];
         uint32_t cnt = 0;
         if (d0 < n) {
             const uint32_t base = d0 & ~(2 * L - 1u), d = d0 - base;
@@ -880,14 +893,14 @@ __device__ __forceinline__ void lds_merge_sort(uint64_t *s, uint32_t n, uint32_t
             }
             uint32_t i = lo, j = d - lo;
             uint64_t ai = i < na ? A[i] : kKeyInf, bj = j < nb ? B[j] : kKeyInf;
-            cnt = na + nb - d < 8u ? na + nb - d : 8u;
+            cnt = na + nb - d < (uint32_t)E ? na + nb - d : (uint32_t)E;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < E; ++q) {
                 // branch-free: the side taken advances and its next key is read
                 // at an address in bounds (the run's first key when past it)
                 const bool take = ai < bj;
                 o[q] = take ? ai : bj;
-                if (q < 7) {
+                if (q < E - 1) {
                     i += take ? 1u : 0u;
                     j += take ? 0u : 1u;
                     const bool in = take ? i < na : j < nb;
@@ -900,13 +913,13 @@ __device__ __forceinline__ void lds_merge_sort(uint64_t *s, uint32_t n, uint32_t
         }
         if (2 * L >= n) {   // the last round writes the records (uniform)
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
+            for (int q = 0; q < E; ++q)
                 if ((uint32_t)q < cnt) dst[d0 + q] = (uint32_t)o[q];
             return;
         }
         sync();
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < E; ++q)
             if ((uint32_t)q < cnt) s[d0 + q] = o[q];
         sync();
     }
@@ -952,15 +965,20 @@ __device__ __forceinline__ void sort_tile_list(uint64_t *s, bool big, uint32_t t
     auto key_of = [&](uint32_t rec) {   // rec < n_rec always; the select keeps reads in bounds
         return ((uint64_t)zrec[rec < n_rec ? rec : 0u] << 32) | (uint64_t)rec;
     };
-    // thread u's keys 8u .. 8u + 7 of list[0, m), all loads in flight together
-    auto load8 = [&](const uint32_t *list, uint32_t m, uint32_t u, uint64_t (&k)[8]) {
-        uint32_t rec[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) rec[q] = 8 * u + q < m ? list[8 * u + q] : 0u;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) k[q] = 8 * u + q < m ? key_of(rec[q]) : kKeyInf;
-    };
     auto block_sync = [] { __syncthreads(); };
+    // thread u's E keys from list[0, m) (all loads in flight together), then
+    // the sort of m keys over s
+    auto sort_with = [&](auto e, uint64_t *sm, const uint32_t *list, uint32_t m, uint32_t u, uint32_t *to,
+                         auto sync) {
+        constexpr int E = decltype(e)::value;
+        uint32_t rec[E];
+        uint64_t k[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) rec[q] = E * u + q < m ? list[E * u + q] : 0u;
+#pragma unroll
+        for (int q = 0; q < E; ++q) k[q] = E * u + q < m ? key_of(rec[q]) : kKeyInf;
+        lds_merge_sort<E>(sm, m, u, k, to, sync);
+    };
     if (!big) {   // one wave, its own kTileSortWaveCap keys of LDS
         if (n > kTileSortWaveCap) {   // never expected (nbig counts every such list); noted, not sorted
             if (lane == 0) atomicAdd((unsigned long long *)error, 1ull);
@@ -971,16 +989,22 @@ __device__ __forceinline__ void sort_tile_list(uint64_t *s, bool big, uint32_t t
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         };
-        uint64_t k[8];
-        load8(src, n, lane, k);
-        lds_merge_sort(w, n, lane, k, dst, wave_sync);
+        if (n <= 64)
+            sort_with(std::integral_constant<int, 1>{}, w, src, n, lane, dst, wave_sync);
+        else if (n <= 128)
+            sort_with(std::integral_constant<int, 2>{}, w, src, n, lane, dst, wave_sync);
+        else if (n <= 256)
+            sort_with(std::integral_constant<int, 4>{}, w, src, n, lane, dst, wave_sync);
+        else
+            sort_with(std::integral_constant<int, 8>{}, w, src, n, lane, dst, wave_sync);
         return;
     }
     constexpr uint32_t NT = kTileSortThreads, C = kTileSortCap;
     if (n <= C) {
-        uint64_t k[8];
-        load8(src, n, t, k);
-        lds_merge_sort(s, n, t, k, dst, block_sync);
+        if (n <= 4 * NT)
+            sort_with(std::integral_constant<int, 4>{}, s, src, n, t, dst, block_sync);
+        else
+            sort_with(std::integral_constant<int, 8>{}, s, src, n, t, dst, block_sync);
         return;
     }
     // a long list: its C-blocks merge-sorted into (hi, lo), then Batcher's
@@ -990,10 +1014,8 @@ __device__ __forceinline__ void sort_tile_list(uint64_t *s, bool big, uint32_t t
     const uint32_t P = pow2_at_least(n), nblk = (n + C - 1) / C;
     for (uint32_t b = 0; b < nblk; ++b) {
         const uint32_t base = b * C, nb = n - base < C ? n - base : C;
-        uint64_t k[8];
-        load8(src + base, nb, t, k);
         __syncthreads();   // the previous block's use of s
-        lds_merge_sort(s, nb, t, k, kl + base, block_sync);   // records in order into lo
+        sort_with(std::integral_constant<int, 8>{}, s, src + base, nb, t, kl + base, block_sync);   // records into lo
         __syncthreads();
         for (uint32_t c = t; c < nb; c += NT) kh[base + c] = zrec[kl[base + c] < n_rec ? kl[base + c] : 0u];
         __syncthreads();
