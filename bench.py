@@ -507,10 +507,14 @@ def next_rows_bench(rast, raster, scenes, w, g, q, t, targets, opts, args):
     e0 = pose_err(q1, t1)
     hp = raster.PoseAdam(lr_rot=1e-3, lr_pos=1e-3)
     rt = raster.Rasterizer(0)   # its own workspace, sized for one view, as a tracking front end holds it
+    # the tile autotuned for this shape: one view, pose gradients only
+    tile1, _ = rt.autotune(g, q1, t1, cam0, tg1, raster.RenderOptions(**{**opts.__dict__, "gauss_grads": False}),
+                           reps=3)
+    opts1 = raster.RenderOptions(**{**opts.__dict__, "tile": tile1})
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
-        tr = rt.track(g, q1, t1, cam0, tg1, opts, hp, 40, capture=True)
+        tr = rt.track(g, q1, t1, cam0, tg1, opts1, hp, 40, capture=True)
         rt.launch_graph(tr["graph"])
         s.synchronize()
         e1 = pose_err(q1, t1)
@@ -522,8 +526,8 @@ def next_rows_bench(rast, raster, scenes, w, g, q, t, targets, opts, args):
         rt.destroy_graph(tr["graph"])
     torch.cuda.synchronize()
     res["tracking"] = dict(workload="one 640x480 view of the 200k room, pose-only fwd+loss+bwd + decoupled Adam step, "
-                                    "40 iterations as one graph replay, own context (pair capacity for one view)",
-                           pair_capacity=rt.pair_capacity, iterations=40, ms_per_frame=ms_frame,
+                                    "40 iterations as one graph replay, own context (pair capacity and autotuned tile for one view)",
+                           tile=list(tile1), pair_capacity=rt.pair_capacity, iterations=40, ms_per_frame=ms_frame,
                            iterations_per_s=40 * 1000.0 / ms_frame, overflow=bool(ovf),
                            rotation_err_deg=[e0[0], e1[0]], centre_err_cm=[100 * e0[1], 100 * e1[1]],
                            loss_first_last=[float(lh[0]), float(lh[-1])])
