@@ -1,7 +1,10 @@
 """Edge cases of the rasteriser on the GPU against the oracle: no Gaussians,
 nothing visible, one Gaussian covering the whole image, the maximum number
 of views in one call, one-pixel and ragged images, and the pose-only
-(6-partial) backward."""
+(6-partial) backward.  Every case runs with both binnings: at the default
+pair capacity these small images have over 4 096 pairs of capacity per tile
+and take the two global sorts; at a capacity of 2 048 (grown by the library
+where a case needs more) they take the tile-local binning."""
 import numpy as np
 import pytest
 import torch
@@ -14,10 +17,10 @@ from gpu_util import GRAD_TOL, IMG_TOL, RES_MARGIN, dev_params, dev_poses, grad_
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def rast():
+@pytest.fixture(scope="module", params=["global_sorts", "tile_local"])
+def rast(request):
     from paper_2408_05635_amd import raster
-    return raster.Rasterizer(0)
+    return raster.Rasterizer(0) if request.param == "global_sorts" else raster.Rasterizer(0, pair_capacity=2048)
 
 
 def _workload(g, cams, quat, trans, tquat=None, ttrans=None, name="edge"):
