@@ -791,12 +791,12 @@ __global__ __launch_bounds__(256) void k_tile_offsets(const ViewTable *__restric
         uint32_t *col = counts + (size_t)(b0 + v) * (size_t)row_len + (size_t)x;
         const int64_t nb = b1 - b0 + 1;
         int64_t b = 0;
-        for (; b + 8 <= nb; b += 8) {   // eight loads in flight
-            uint32_t c[8];
+        for (; b + 16 <= nb; b += 16) {   // sixteen loads in flight
+            uint32_t c[16];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) c[q] = col[(size_t)(b + q) * (size_t)row_len];
+            for (int q = 0; q < 16; ++q) c[q] = col[(size_t)(b + q) * (size_t)row_len];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < 16; ++q) {
                 col[(size_t)(b + q) * (size_t)row_len] = run;
                 run += c[q];
             }

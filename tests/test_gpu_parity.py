@@ -147,6 +147,19 @@ def test_binning_bit_exact_multiview(rast):
     assert _check_binning(rast, w, (16, 16)) == 0
 
 
+@pytest.mark.parametrize("empty", [0, 1, 2])
+def test_binning_bit_exact_view_without_records(rast, empty):
+    """Tile-local binning (3 600 tiles, 1M pairs of capacity) with one view
+    whose camera is moved 1 km back, so that it sees nothing: its tiles get
+    empty lists, and the views before and after it keep theirs (each view's
+    lists come from the count rows of the blocks holding its pairs)."""
+    w = scenes.config2(n_views=3, n=20000)
+    t = w.views.trans.copy()
+    t[empty, 2] -= 1000.0
+    w.views = scenes.Views(w.views.cams, w.views.quat, t)
+    assert _check_binning(rast, w, (16, 16)) == 0
+
+
 @pytest.mark.parametrize("capacity", [200_000, 3_000_000])
 def test_binning_bit_exact_long_lists(capacity):
     """Lists of about 14 000 entries with exact depth ties (groups of seven
