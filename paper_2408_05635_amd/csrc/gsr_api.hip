@@ -350,7 +350,10 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     L.sort_nb = std::max<int64_t>(std::max(L.depth_sweep ? 0 : sort_blocks(L.vn), L.tile_sweep ? 0 : sort_blocks(kcap)), 1);
     L.scounts = take(4 * 256 * (size_t)L.sort_nb);
     L.stotals = take(4 * 256);
-    const int64_t nb_sweep = std::max(L.depth_sweep ? sweep_blocks(L.vn) : 0, L.tile_sweep ? sweep_blocks(kcap) : 0);
+    // the one-launch sort passes' look-back words (none with tile-local binning, which has no global sort)
+    const int64_t nb_sweep = L.tile_local ? 0
+                                          : std::max(L.depth_sweep ? sweep_blocks(L.vn) : 0,
+                                                     L.tile_sweep ? sweep_blocks(kcap) : 0);
     L.sync_status = kSyncTickets;
     L.sync_sweep = align_up(L.sync_status + 8 * (size_t)nb_scan);
     L.sync_hist = align_up(L.sync_sweep + 4 * 256 * (size_t)nb_sweep);
