@@ -386,7 +386,8 @@ typedef struct gsr_pose_adam {
     float beta1, beta2, eps;
 } gsr_pose_adam;
 
-/* Doubles of optimiser state per view: q 4, C 3, m_q 4, v_q 4, m_C 3, v_C 3, step 1, pad 2. */
+/* Doubles of optimiser state per view: q 4, C 3, m_q 4, v_q 4, m_C 3, v_C 3,
+ * step 1, beta1^step 1, beta2^step 1 (the bias corrections' powers). */
 #define GSR_POSE_STATE_DOUBLES 24
 
 /* Starts the state of n_views poses (device quat [V,4], trans [V,3]) in

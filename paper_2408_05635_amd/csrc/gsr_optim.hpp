@@ -21,9 +21,11 @@ namespace gsr {
 // pose
 // ---------------------------------------------------------------------------
 
-// Per-view optimiser state (FP64): q 4, C 3, m_q 4, v_q 4, m_C 3, v_C 3, step, pad.
+// Per-view optimiser state (FP64): q 4, C 3, m_q 4, v_q 4, m_C 3, v_C 3, step,
+// and beta1^step, beta2^step (the bias corrections' powers, kept as running
+// products).
 struct PoseOptState {
-    double q[4], C[3], mq[4], vq[4], mc[3], vc[3], step, pad[2];
+    double q[4], C[3], mq[4], vq[4], mc[3], vc[3], step, b1p, b2p;
 };
 static_assert(sizeof(PoseOptState) == GSR_POSE_STATE_DOUBLES * sizeof(double), "pose state layout");
 
@@ -49,7 +51,7 @@ __global__ void k_pose_opt_init(int V, const float *__restrict__ quat, const flo
     for (int k = 0; k < 4; ++k) s.mq[k] = s.vq[k] = 0.0;
     for (int k = 0; k < 3; ++k) s.mc[k] = s.vc[k] = 0.0;
     s.step = 0.0;
-    s.pad[0] = s.pad[1] = 0.0;
+    s.b1p = s.b2p = 1.0;
     st[v] = s;
 }
 
@@ -61,7 +63,9 @@ __device__ __forceinline__ void pose_adam_apply(int v, const double dq_c[4], con
     PoseOptState s = st[v];
     s.step += 1.0;
     const double b1 = hp.beta1, b2 = hp.beta2, eps = hp.eps;
-    const double c1 = 1.0 - pow(b1, s.step), c2 = 1.0 - pow(b2, s.step);
+    s.b1p *= b1;
+    s.b2p *= b2;
+    const double c1 = 1.0 - s.b1p, c2 = 1.0 - s.b2p;
     for (int k = 0; k < 4; ++k) adam_update(s.q[k], dq_c[k], s.mq[k], s.vq[k], (double)hp.lr_rot, b1, b2, eps, c1, c2);
     for (int k = 0; k < 3; ++k) adam_update(s.C[k], dc[k], s.mc[k], s.vc[k], (double)hp.lr_pos, b1, b2, eps, c1, c2);
     st[v] = s;
