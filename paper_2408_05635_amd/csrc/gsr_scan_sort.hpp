@@ -821,10 +821,9 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact_hist(const uint32_t
 // merge (the "merge path" of Odeh et al., 2012) finds how many of them precede
 // it in the first run, and a sequential merge of E steps follows.  Lists under
 // 512 keys take one wave each (E chosen so that most lanes hold keys); longer
-// ones a workgroup.  A list longer than
-// kTileSortCap sorts its kTileSortCap-blocks that way and merges them with
-// Batcher's bitonic network in global memory (rare: the tile-local binning is
-// chosen for short lists).
+// ones a workgroup.  A list longer than kTileSortCap sorts its
+// kTileSortCap-blocks that way and merges them with Batcher's bitonic network
+// in global memory (rare: the tile-local binning is chosen for short lists).
 // ---------------------------------------------------------------------------
 constexpr int kTileSortThreads = 256;
 constexpr uint32_t kTileSortCap = 8 * kTileSortThreads;   // 2048 keys (16 KB of LDS)
@@ -943,14 +942,11 @@ __device__ __forceinline__ uint32_t pow2_at_least(uint32_t n) {
     return p;
 }
 
-// Sorts every tile's list: in = the emission's lists, out = the sorted ones,
-// both over the pair range [ranges[t].x, ranges[t].y); zrec = the records'
-// depth keys; torder = the tiles by decreasing list length, of which the first
-// nbig = counters[kCntSortBig] have kTileSortWaveCap keys or more.  Work item
-// w < nbig is tile torder[w] for a whole workgroup; the later items are four
-// short lists each, one per wave; workgroups loop over the items.  hi / lo:
-// scratch over the pair range for the keys of the lists longer than
-// kTileSortCap.
+// Sorts one tile's list: in = the emission's list, out = the sorted one, both
+// over the pair range [ranges[tile].x, ranges[tile].y); zrec = the records'
+// depth keys.  big: the whole workgroup calls (a list of kTileSortWaveCap keys
+// or more), else one wave with its own kTileSortWaveCap keys of s.  hi / lo:
+// scratch over the pair range for the keys of a list longer than kTileSortCap.
 __device__ __forceinline__ void sort_tile_list(uint64_t *s, bool big, uint32_t tile, const uint2 *__restrict__ ranges,
                                                int64_t K, uint32_t n_rec, const uint32_t *__restrict__ zrec,
                                                const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
@@ -1067,6 +1063,11 @@ __device__ __forceinline__ void sort_tile_list(uint64_t *s, bool big, uint32_t t
     }
 }
 
+// Every tile's list sorted.  torder = the tiles by decreasing list length, of
+// which the first nbig = counters[kCntSortBig] have kTileSortWaveCap keys or
+// more: work item w < nbig is tile torder[w] for a whole workgroup, the later
+// items are four short lists each, one per wave; the workgroups loop over the
+// items (grid-stride), so none is launched only to find no work.
 __global__ __launch_bounds__(kTileSortThreads) void k_tile_sort(const uint2 *__restrict__ ranges,
                                                                 const uint32_t *__restrict__ torder, int64_t n_tiles,
                                                                 int64_t *__restrict__ counters,
