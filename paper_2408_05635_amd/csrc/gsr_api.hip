@@ -773,6 +773,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_count(const int64_t *__re
 // that hold pairs of its view (those whose chunks meet the view's pair range
 // [start(v), start(v + 1)): start(v) is the first pair of the view's first
 // record vrec[v], K past the last record), and its total.
+constexpr int kOffsetsBatch = 32;   // rows of a column read together
+
 __global__ __launch_bounds__(256) void k_tile_offsets(const ViewTable *__restrict__ vt,
                                                       const int64_t *__restrict__ counters,
                                                       const uint32_t *__restrict__ vrec,
@@ -793,21 +795,15 @@ __global__ __launch_bounds__(256) void k_tile_offsets(const ViewTable *__restric
         const int64_t b0 = ps / kEmitChunk, b1 = (pe - 1) / kEmitChunk;
         uint32_t *col = counts + (size_t)(b0 + v) * (size_t)row_len + (size_t)x;
         const int64_t nb = b1 - b0 + 1;
-        int64_t b = 0;
-        for (; b + 16 <= nb; b += 16) {   // sixteen loads in flight
-            uint32_t c[16];
+        for (int64_t b = 0; b < nb; b += kOffsetsBatch) {   // the batch's loads in flight together
+            uint32_t c[kOffsetsBatch];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) c[q] = col[(size_t)(b + q) * (size_t)row_len];
+            for (int q = 0; q < kOffsetsBatch; ++q) c[q] = b + q < nb ? col[(size_t)(b + q) * (size_t)row_len] : 0u;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                col[(size_t)(b + q) * (size_t)row_len] = run;
+            for (int q = 0; q < kOffsetsBatch; ++q) {
+                if (b + q < nb) col[(size_t)(b + q) * (size_t)row_len] = run;
                 run += c[q];
             }
-        }
-        for (; b < nb; ++b) {
-            const uint32_t c = col[(size_t)b * (size_t)row_len];
-            col[(size_t)b * (size_t)row_len] = run;
-            run += c;
         }
     }
     ttot[t] = run;
@@ -882,7 +878,12 @@ __device__ __forceinline__ void work_order_block(Len len_of, int64_t n_tiles, in
                                                  int64_t *__restrict__ counters) {
     __shared__ uint32_t s_h[kOrderBuckets];
     __shared__ int64_t s_run;
+    // with chunk splits (at most kSplitMaxTiles tiles) the tile order and the
+    // checkpoint slots are also kept here, so the later phases read no global
+    // memory that this block wrote
+    __shared__ uint32_t s_to[kSplitMaxTiles], s_cp[kSplitMaxTiles];
     const int t = threadIdx.x;
+    const bool split_mode = slots_cap > 0 && n_tiles <= kSplitMaxTiles;   // the layout gives slots only then
     auto bucket_of = [](uint32_t len) {
         const uint32_t b = len >> 4;
         return (kOrderBuckets - 1u) - (b < kOrderBuckets - 1u ? b : kOrderBuckets - 1u);
@@ -905,11 +906,14 @@ __device__ __forceinline__ void work_order_block(Len len_of, int64_t n_tiles, in
         const uint32_t pos = atomicAdd(&s_h[bucket_of(len_of(i))], 1u);
         if ((int64_t)pos < n_tiles) {   // always true; keeps writes in bounds
             torder[pos] = (uint32_t)i;
-            if (slots_cap == 0) work[pos] = (uint32_t)i;   // no splits: the items are the tiles, in that order
+            if (split_mode)
+                s_to[pos] = (uint32_t)i;
+            else
+                work[pos] = (uint32_t)i;   // no splits: the items are the tiles, in that order
         }
-        if (slots_cap == 0) cpoff[i] = kNoSplit;
+        if (!split_mode) cpoff[i] = kNoSplit;
     }
-    if (slots_cap == 0) {
+    if (!split_mode) {
         if (t == 0) *n_work = counters[kCntWorkItems] = n_tiles;
         return;
     }
@@ -921,14 +925,18 @@ __device__ __forceinline__ void work_order_block(Len len_of, int64_t n_tiles, in
         const int64_t r = base + t;
         uint32_t need = 0, tile = 0;
         if (r < n_tiles) {
-            tile = torder[r];
+            tile = s_to[r];
             const uint32_t len = len_of(tile), nch = chunks_of(len);
             need = (len > kSplitMin && nch <= kMaxChunks) ? nch - 1u : 0u;
         }
         uint32_t tot;
         const uint32_t ex = block_excl_scan_u32<kOrderThreads>(need, tot);
         const int64_t p = s_run + (int64_t)ex;
-        if (r < n_tiles) cpoff[tile] = (need > 0u && p + (int64_t)need <= slots_cap) ? (uint32_t)p : kNoSplit;
+        if (r < n_tiles) {
+            const uint32_t slot = (need > 0u && p + (int64_t)need <= slots_cap) ? (uint32_t)p : kNoSplit;
+            cpoff[tile] = slot;
+            s_cp[tile] = slot;
+        }
         __syncthreads();
         if (t == 0) s_run += tot;
         __syncthreads();
@@ -941,7 +949,7 @@ __device__ __forceinline__ void work_order_block(Len len_of, int64_t n_tiles, in
     __syncthreads();
     for (int64_t i = t; i < n_tiles; i += kOrderThreads) {
         const uint32_t len = len_of(i);
-        const bool split = cpoff[i] != kNoSplit;
+        const bool split = s_cp[i] != kNoSplit;
         const uint32_t nch = split ? chunks_of(len) : 1u;
         for (uint32_t m = 0; m < nch; ++m) atomicAdd(&s_h[bucket_of(item_len(len, split, m))], 1u);
     }
@@ -950,7 +958,7 @@ __device__ __forceinline__ void work_order_block(Len len_of, int64_t n_tiles, in
     if (t == 0) *n_work = counters[kCntWorkItems] = total;
     for (int64_t i = t; i < n_tiles; i += kOrderThreads) {
         const uint32_t len = len_of(i);
-        const bool split = cpoff[i] != kNoSplit;
+        const bool split = s_cp[i] != kNoSplit;
         const uint32_t nch = split ? chunks_of(len) : 1u;
         for (uint32_t m = 0; m < nch; ++m) {
             const uint32_t pos = atomicAdd(&s_h[bucket_of(item_len(len, split, m))], 1u);
@@ -1232,8 +1240,19 @@ __device__ __forceinline__ void pose_final_view(const float *__restrict__ pq, co
                                                 bool centre, const PoseF64 *poses,
                                                 const double *__restrict__ pose_blocks, int nblocks, int V,
                                                 const gsr_pose_grads &pg, const PoseOpt &po, int v) {
-    __shared__ double s_red[12][256];
+    __shared__ double s_red[12][4];
     const int t = threadIdx.x;
+    // what the lead thread needs after the reduction (the pose inputs, the
+    // rotation and the optimiser state), requested first so that these loads
+    // overlap the rows' loads and the reduction
+    double q[4] = {0.0, 0.0, 0.0, 0.0}, tin[3] = {0.0, 0.0, 0.0}, W[9] = {};
+    PoseOptState s0 = {};
+    if (t == 0) {
+        for (int k = 0; k < 4; ++k) q[k] = pq[4 * v + k];
+        for (int k = 0; k < 3; ++k) tin[k] = pt[3 * v + k];
+        for (int k = 0; k < 9; ++k) W[k] = poses[v].W[k];
+        if (po.st) s0 = po.st[v];
+    }
     double acc[12];
     for (int k = 0; k < 12; ++k) acc[k] = 0.0;
 #pragma unroll 4   // loads in flight together; the additions keep their order
@@ -1242,19 +1261,16 @@ __device__ __forceinline__ void pose_final_view(const float *__restrict__ pq, co
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] += row[k];
     }
-    for (int k = 0; k < 12; ++k) s_red[k][t] = acc[k];
+    // the block's rows summed in a fixed order: each wave's butterfly, then the four waves in order
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = wave_sum_f64(acc[k]);
+    if ((t & 63) == 0)
+        for (int k = 0; k < 12; ++k) s_red[k][t >> 6] = acc[k];
     __syncthreads();
-    for (int h = 128; h >= 1; h >>= 1) {
-        if (t < h)
-            for (int k = 0; k < 12; ++k) s_red[k][t] += s_red[k][t + h];
-        __syncthreads();
-    }
     if (t != 0) return;
     double GW[12];
-    for (int k = 0; k < 12; ++k) GW[k] = s_red[k][0];
+    for (int k = 0; k < 12; ++k) GW[k] = ((s_red[k][0] + s_red[k][1]) + s_red[k][2]) + s_red[k][3];
     const double *gt = GW + 9;
-    const double q[4] = {pq[4 * v], pq[4 * v + 1], pq[4 * v + 2], pq[4 * v + 3]};
-    const double *W = poses[v].W;
     double gq[4];
     rot_grad_to_quat_f64(q, GW, gq);
     if (pg.dq_t)
@@ -1263,8 +1279,7 @@ __device__ __forceinline__ void pose_final_view(const float *__restrict__ pq, co
         for (int k = 0; k < 3; ++k) pg.dt[3 * v + k] = (float)gt[k];
     double C[3], gc[3];   // C = -W^T t (or given, with GSR_POSE_CENTRE); dL/dC = -W^T dL/dt
     for (int k = 0; k < 3; ++k) {
-        C[k] = centre ? (double)pt[3 * v + k]
-                      : -(W[k] * pt[3 * v] + W[3 + k] * pt[3 * v + 1] + W[6 + k] * pt[3 * v + 2]);
+        C[k] = centre ? tin[k] : -(W[k] * tin[0] + W[3 + k] * tin[1] + W[6 + k] * tin[2]);
         gc[k] = -(W[k] * gt[0] + W[3 + k] * gt[1] + W[6 + k] * gt[2]);
     }
     if (pg.dc)
@@ -1279,7 +1294,7 @@ __device__ __forceinline__ void pose_final_view(const float *__restrict__ pq, co
         double sq[4], sc[3];
         for (int k = 0; k < 4; ++k) sq[k] = (double)(float)gq[k];
         for (int k = 0; k < 3; ++k) sc[k] = (double)(float)gc[k];
-        pose_adam_apply(v, sq, sc, po.hp, po.st, po.quat, po.trans);
+        pose_adam_apply(v, sq, sc, po.hp, s0, po.st, po.quat, po.trans);
     }
 }
 

@@ -204,20 +204,30 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
         d[256] = cd;
         d[320] = cs;
     };
+    // The list is read one round ahead of its use, so that a round's loads
+    // wait behind the compositing of the round before: the list entries of
+    // round c + 128 and the records of round c + 64 are requested during round
+    // c (a sentinel >= n_rec past the list's end).
+    auto list_entry = [&](uint32_t c) { return c + lane < rg.y ? pair_rec[c + lane] : 0xffffffffu; };
+    float4 A, B, C;
+    auto load_rec = [&](uint32_t s, float4 &a, float4 &b, float4 &cc) {
+        if (s < n_rec) {
+            a = rec[3 * (size_t)s];
+            b = rec[3 * (size_t)s + 1];
+            cc = rec[3 * (size_t)s + 2];
+        }
+    };
+    uint32_t s = list_entry(rg.x);
+    load_rec(s, A, B, C);
+    uint32_t s_next = list_entry(rg.x + 64u);
     for (uint32_t c = rg.x; c < rg.y; c += 64) {
         if (ballot(!done) == 0) break;
         if (next_cp <= n_cp && c == rg.x + next_cp * kChunkEntries) write_cp(next_cp++);   // wave-uniform
         const uint32_t e = c + lane;
-        bool keep = false;
-        float4 A, B, C;
-        uint32_t s = 0;
-        if (e < rg.y && pair_rec[e] < n_rec) {
-            s = pair_rec[e];
-            A = rec[3 * (size_t)s];
-            B = rec[3 * (size_t)s + 1];
-            C = rec[3 * (size_t)s + 2];
-            keep = block_may_contribute(A, B, (float)bp.bx0, (float)bp.by0);
-        }
+        float4 A2, B2, C2;
+        load_rec(s_next, A2, B2, C2);
+        const uint32_t s_after = list_entry(c + 128u);
+        const bool keep = s < n_rec && block_may_contribute(A, B, (float)bp.bx0, (float)bp.by0);
         const uint64_t m = ballot(keep);
         if (lane == 0) out.cmask[cmask_index(rg.x, bp.tg, c - rg.x, nsub, bp.sub)] = m;
         if (keep) {
@@ -277,6 +287,11 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
         }
         if (lastk >= 0) last = s_pos[lastk] + 1u;
         __syncthreads();
+        s = s_next;
+        s_next = s_after;
+        A = A2;
+        B = B2;
+        C = C2;
     }
     for (; next_cp <= n_cp; ++next_cp) write_cp(next_cp);   // boundaries past the end: the final state
     if (COUNT) {
@@ -703,7 +718,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
     }
 }
 
-// Per-view loss: the view's tile partials added in a fixed tree order (one
+// Per-view loss: the view's tile partials added in a fixed order (one
 // 256-thread block per view); also copied to hist if that is set.  The block
 // that finishes last (a ticket taken with acquire-release ordering at device
 // scope, so it sees every other block's view loss) adds the V view losses in
@@ -711,27 +726,29 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
 __device__ __forceinline__ void loss_final_view(const ViewTable *__restrict__ vt, const double *__restrict__ loss_tile,
                                                 double *__restrict__ loss, double *__restrict__ hist,
                                                 int64_t *__restrict__ ticket, int view) {
-    __shared__ double s[256];
+    __shared__ double s[4];
     const ViewInfo &V = vt->v[view];
     const int n = V.tiles_x * V.tiles_y;
     double t = 0.0;
 #pragma unroll 8   // loads in flight together; the additions keep their order
     for (int k = threadIdx.x; k < n; k += 256) t += loss_tile[V.tile_off + k];
-    s[threadIdx.x] = t;
+    t = wave_sum_f64(t);   // each wave's butterfly, then the four waves in order
+    if ((threadIdx.x & 63u) == 0u) s[threadIdx.x >> 6] = t;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
-        loss[view] = s[0];
-        if (hist) hist[view] = s[0];   // a tracking loop's per-iteration record
+        const double lv = ((s[0] + s[1]) + s[2]) + s[3];
+        loss[view] = lv;
+        if (hist) hist[view] = lv;   // a tracking loop's per-iteration record
         const int nv = vt->n_views;
+        if (nv == 1) {   // the only view: its loss is the total, no other block to wait for
+            loss[1] = lv;
+            return;
+        }
         const int64_t k = __hip_atomic_fetch_add(ticket, (int64_t)1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (k == (int64_t)nv - 1) {
             double tot = 0.0;
-            for (int v = 0; v < nv; ++v) tot += v == view ? s[0] : __hip_atomic_load(&loss[v], __ATOMIC_RELAXED,
-                                                                                      __HIP_MEMORY_SCOPE_AGENT);
+            for (int v = 0; v < nv; ++v) tot += v == view ? lv : __hip_atomic_load(&loss[v], __ATOMIC_RELAXED,
+                                                                                    __HIP_MEMORY_SCOPE_AGENT);
             loss[nv] = tot;
         }
     }

@@ -57,10 +57,10 @@ __global__ void k_pose_opt_init(int V, const float *__restrict__ quat, const flo
 
 // One decoupled Adam step of view v from its gradients (dL/dq | C, dL/dC);
 // writes the pose the next render reads (FP32).
+// s: the view's state as read from st[v] (the caller may read it early).
 __device__ __forceinline__ void pose_adam_apply(int v, const double dq_c[4], const double dc[3], const gsr_pose_adam &hp,
-                                                PoseOptState *__restrict__ st, float *__restrict__ quat,
-                                                float *__restrict__ trans) {
-    PoseOptState s = st[v];
+                                                PoseOptState s, PoseOptState *__restrict__ st,
+                                                float *__restrict__ quat, float *__restrict__ trans) {
     s.step += 1.0;
     const double b1 = hp.beta1, b2 = hp.beta2, eps = hp.eps;
     s.b1p *= b1;
@@ -86,7 +86,7 @@ __global__ void k_pose_opt_step(int V, const float *__restrict__ dq_c, const flo
     double gq[4], gc[3];
     for (int k = 0; k < 4; ++k) gq[k] = (double)dq_c[4 * v + k];
     for (int k = 0; k < 3; ++k) gc[k] = (double)dc[3 * v + k];
-    pose_adam_apply(v, gq, gc, hp, st, quat, trans);
+    pose_adam_apply(v, gq, gc, hp, st[v], st, quat, trans);
     if (hist) hist[v] = loss[v];
 }
 
