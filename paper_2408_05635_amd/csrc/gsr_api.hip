@@ -877,7 +877,6 @@ __device__ __forceinline__ void work_order_block(Len len_of, int64_t n_tiles, in
                                                  uint32_t *__restrict__ work, int64_t *__restrict__ n_work,
                                                  int64_t *__restrict__ counters) {
     __shared__ uint32_t s_h[kOrderBuckets];
-    __shared__ int64_t s_run;
     // with chunk splits (at most kSplitMaxTiles tiles) the tile order and the
     // checkpoint slots are also kept here, so the later phases read no global
     // memory that this block wrote
@@ -918,50 +917,75 @@ __device__ __forceinline__ void work_order_block(Len len_of, int64_t n_tiles, in
         return;
     }
     __syncthreads();
-    // (2) checkpoint slots in that order
-    if (t == 0) s_run = 0;
-    __syncthreads();
-    for (int64_t base = 0; base < n_tiles; base += kOrderThreads) {
-        const int64_t r = base + t;
-        uint32_t need = 0, tile = 0;
-        if (r < n_tiles) {
-            tile = s_to[r];
-            const uint32_t len = len_of(tile), nch = chunks_of(len);
-            need = (len > kSplitMin && nch <= kMaxChunks) ? nch - 1u : 0u;
+    // (2) checkpoint slots in that order: two consecutive places per thread, one block scan
+    static_assert(kSplitMaxTiles <= 2 * kOrderThreads, "the split tiles take one scan");
+    {
+        uint32_t need[2] = {0u, 0u}, tile[2] = {0u, 0u};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t r = 2 * (int64_t)t + h;
+            if (r < n_tiles) {
+                tile[h] = s_to[r];
+                const uint32_t len = len_of(tile[h]), nch = chunks_of(len);
+                need[h] = (len > kSplitMin && nch <= kMaxChunks) ? nch - 1u : 0u;
+            }
         }
         uint32_t tot;
-        const uint32_t ex = block_excl_scan_u32<kOrderThreads>(need, tot);
-        const int64_t p = s_run + (int64_t)ex;
-        if (r < n_tiles) {
-            const uint32_t slot = (need > 0u && p + (int64_t)need <= slots_cap) ? (uint32_t)p : kNoSplit;
-            cpoff[tile] = slot;
-            s_cp[tile] = slot;
+        int64_t p = block_excl_scan_u32<kOrderThreads>(need[0] + need[1], tot);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (2 * (int64_t)t + h < n_tiles) {
+                const uint32_t slot = (need[h] > 0u && p + (int64_t)need[h] <= slots_cap) ? (uint32_t)p : kNoSplit;
+                cpoff[tile[h]] = slot;
+                s_cp[tile[h]] = slot;
+            }
+            p += need[h];
         }
-        __syncthreads();
-        if (t == 0) s_run += tot;
-        __syncthreads();
     }
-    // (3) the backward's items, longest first
+    // (3) the backward's items, longest first.  The chunks of a split list
+    // before its last are all full (kChunkEntries entries, one bucket), so
+    // they take their places by wave prefix sums and one LDS add per wave;
+    // each tile's last (or only) item takes its own.
     auto item_len = [&](uint32_t len, bool split, uint32_t m) {
         return split ? (len - m * kChunkEntries < kChunkEntries ? len - m * kChunkEntries : kChunkEntries) : len;
     };
+    const uint32_t full_bucket = bucket_of(kChunkEntries);
+    const uint32_t lane = (uint32_t)t & 63u;
     if (t < (int)kOrderBuckets) s_h[t] = 0u;
     __syncthreads();
+    // a tile's items: split ? chunks_of(len) : 1, the last at m = n_items - 1
+    auto tile_items = [&](int64_t i, uint32_t &len) -> uint32_t {
+        len = len_of(i);
+        return s_cp[i] != kNoSplit ? chunks_of(len) : 1u;
+    };
+    uint32_t n_full = 0;
     for (int64_t i = t; i < n_tiles; i += kOrderThreads) {
-        const uint32_t len = len_of(i);
-        const bool split = s_cp[i] != kNoSplit;
-        const uint32_t nch = split ? chunks_of(len) : 1u;
-        for (uint32_t m = 0; m < nch; ++m) atomicAdd(&s_h[bucket_of(item_len(len, split, m))], 1u);
+        uint32_t len;
+        const uint32_t ni = tile_items(i, len);
+        n_full += ni - 1u;
+        atomicAdd(&s_h[bucket_of(item_len(len, s_cp[i] != kNoSplit, ni - 1u))], 1u);
     }
+    n_full = wave_sum_u32(n_full);
+    if (lane == 0u && n_full) atomicAdd(&s_h[full_bucket], n_full);
     __syncthreads();
     const uint32_t total = bucket_starts();
     if (t == 0) *n_work = counters[kCntWorkItems] = total;
-    for (int64_t i = t; i < n_tiles; i += kOrderThreads) {
-        const uint32_t len = len_of(i);
-        const bool split = s_cp[i] != kNoSplit;
-        const uint32_t nch = split ? chunks_of(len) : 1u;
-        for (uint32_t m = 0; m < nch; ++m) {
-            const uint32_t pos = atomicAdd(&s_h[bucket_of(item_len(len, split, m))], 1u);
+    for (int64_t base = 0; base < n_tiles; base += kOrderThreads) {   // whole rounds: the wave sums need every lane
+        const int64_t i = base + t;
+        uint32_t len = 0, ni = 0;
+        if (i < n_tiles) ni = tile_items(i, len);
+        const uint32_t nf = ni > 0u ? ni - 1u : 0u;
+        const uint32_t incl = wave_incl_scan_u32(nf);
+        uint32_t wbase = 0;
+        if (lane == 63u && incl) wbase = atomicAdd(&s_h[full_bucket], incl);
+        wbase = __builtin_amdgcn_readlane(wbase, 63);
+        for (uint32_t m = 0; m < nf; ++m) {
+            const uint32_t pos = wbase + incl - nf + m;
+            if (pos < total) work[pos] = (uint32_t)i | (m << 24);   // always true; keeps writes in bounds
+        }
+        if (ni > 0u) {
+            const uint32_t m = ni - 1u;
+            const uint32_t pos = atomicAdd(&s_h[bucket_of(item_len(len, s_cp[i] != kNoSplit, m))], 1u);
             if (pos < total) work[pos] = (uint32_t)i | (m << 24);   // always true; keeps writes in bounds
         }
     }
@@ -983,8 +1007,12 @@ __global__ __launch_bounds__(kOrderThreads) void k_work_order(const uint2 *__res
 // Tile-local binning: every tile's list [start, end) from the tiles' pair
 // totals (an exclusive scan in tile order), the starts for the placement, the
 // number of lists that the per-tile sort gives a whole workgroup, then the
-// work order.  One block.
-constexpr int kRangeItems = 4;   // tiles per thread and round
+// work order.  One block.  The totals are read and the results written
+// coalesced (tile r 1024 + thread in round r, all loads in flight), through
+// LDS, where each thread scans 16 consecutive tiles; the starts stay there,
+// one pad word after every 16 so that those 16 fall in different banks.
+constexpr int kRangePer = (int)(kTileLocalMaxTiles / kOrderThreads);   // tiles per thread
+__device__ __forceinline__ int32_t range_slot(int64_t i) { return (int32_t)(i + (i >> 4)); }
 
 __global__ __launch_bounds__(kOrderThreads) void k_tile_ranges(const uint32_t *__restrict__ ttot, int64_t n_tiles,
                                                                uint2 *__restrict__ ranges, uint32_t *__restrict__ tstart,
@@ -993,36 +1021,53 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_ranges(const uint32_t *_
                                                                int64_t *__restrict__ n_work,
                                                                int64_t *__restrict__ counters) {
     __shared__ uint32_t s_big;
-    __shared__ uint32_t s_len[kTileLocalMaxTiles];   // the list lengths, for the work order
+    // tile i's start at range_slot(i) (tiles past n_tiles have none, so their
+    // starts are the total), the total at range_slot(kTileLocalMaxTiles)
+    __shared__ uint32_t s_st[kTileLocalMaxTiles + kTileLocalMaxTiles / 16 + 1];
     const int t = threadIdx.x;
     if (t == 0) s_big = 0u;
-    uint32_t run = 0, big = 0;   // run: the totals before this round (the same in every thread)
-    for (int64_t base = 0; base < n_tiles; base += (int64_t)kOrderThreads * kRangeItems) {
-        const int64_t d0 = base + (int64_t)t * kRangeItems;
-        uint32_t x[kRangeItems], sum = 0;
+    uint32_t x[kRangePer];
 #pragma unroll
-        for (int q = 0; q < kRangeItems; ++q) {
-            x[q] = d0 + q < n_tiles ? ttot[d0 + q] : 0u;
-            sum += x[q];
-        }
-        uint32_t tot;
-        uint32_t start = run + block_excl_scan_u32<kOrderThreads>(sum, tot);   // its barriers order s_big's clear
-        run += tot;
+    for (int r = 0; r < kRangePer; ++r) {
+        const int64_t i = (int64_t)r * kOrderThreads + t;
+        x[r] = i < n_tiles ? ttot[i] : 0u;
+    }
 #pragma unroll
-        for (int q = 0; q < kRangeItems; ++q) {
-            if (d0 + q < n_tiles) {
-                ranges[d0 + q] = make_uint2(start, start + x[q]);
-                tstart[d0 + q] = start;
-                s_len[d0 + q] = x[q];
-                big += x[q] >= kTileSortWaveCap ? 1u : 0u;
-            }
-            start += x[q];
+    for (int r = 0; r < kRangePer; ++r) s_st[range_slot((int64_t)r * kOrderThreads + t)] = x[r];
+    __syncthreads();
+    const int64_t d0 = (int64_t)t * kRangePer;
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < kRangePer; ++q) {
+        x[q] = s_st[range_slot(d0 + q)];
+        sum += x[q];
+    }
+    uint32_t tot;
+    uint32_t start = block_excl_scan_u32<kOrderThreads>(sum, tot);   // its barriers order s_big's clear
+#pragma unroll
+    for (int q = 0; q < kRangePer; ++q) {   // a thread rewrites only its own tiles' slots
+        s_st[range_slot(d0 + q)] = start;
+        start += x[q];
+    }
+    if (t == 0) s_st[range_slot(kTileLocalMaxTiles)] = tot;
+    __syncthreads();
+    auto len_of = [&](int64_t i) { return s_st[range_slot(i + 1)] - s_st[range_slot(i)]; };
+    uint32_t big = 0;
+#pragma unroll
+    for (int r = 0; r < kRangePer; ++r) {
+        const int64_t i = (int64_t)r * kOrderThreads + t;
+        if (i < n_tiles) {
+            const uint32_t st = s_st[range_slot(i)], en = s_st[range_slot(i + 1)];
+            ranges[i] = make_uint2(st, en);
+            tstart[i] = st;
+            big += en - st >= kTileSortWaveCap ? 1u : 0u;
         }
     }
-    if (big) atomicAdd(&s_big, big);
-    __syncthreads();   // the lengths before the work order reads them
+    big = wave_sum_u32(big);
+    if ((t & 63) == 0 && big) atomicAdd(&s_big, big);
+    __syncthreads();
     if (t == 0) counters[kCntSortBig] = s_big;
-    work_order_block([&](int64_t i) { return s_len[i]; }, n_tiles, slots_cap, torder, cpoff, work, n_work, counters);
+    work_order_block(len_of, n_tiles, slots_cap, torder, cpoff, work, n_work, counters);
 }
 
 struct GradOut {
