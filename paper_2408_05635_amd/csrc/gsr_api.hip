@@ -145,7 +145,7 @@ struct Layout {
     // per tile and each list sorted on its own; else the two global sorts
     bool tile_local;
     int64_t tv_max;       // tiles of the largest view (row length of the per-block tile counts)
-    size_t tcnt, ttot, tstart;
+    size_t tcnt, ttot, tstart, espan;
     // offsets in the sync region (cleared by every call): scan look-back words,
     // sort-pass look-back words, digit histograms (depth passes, then tile
     // passes), every view's first record (tile-local binning)
@@ -314,6 +314,7 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     // one row per (emission block, view it touches): row b + v (see k_emit_count)
     L.tcnt = take(L.tile_local ? 4 * (size_t)((kc + kEmitChunk - 1) / kEmitChunk + V) * (size_t)L.tv_max : 0);
     L.ttot = take(L.tile_local ? 4 * (size_t)L.T : 0);
+    L.espan = take(L.tile_local ? 8 * (size_t)((kc + kEmitChunk - 1) / kEmitChunk) : 0);   // views of each block
     L.tstart = take(L.tile_local ? 4 * (size_t)L.T : 0);
     L.torder = take(4 * (size_t)L.T);
     L.cpoff = take(4 * (size_t)L.T);
@@ -706,7 +707,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(const int64_t *__restrict
 // block per chunk.  Records are in view order, so the pairs of block b belong
 // to a run of views [v0, v1] (usually one); k_emit_count counts them per tile
 // in LDS and stores, for each of those views v, the row counts[b + v][0, T_v)
-// (b + v grows with (b, v) over the rows written, so rows never collide).
+// (b + v grows with (b, v) over the rows written, so rows never collide), and
+// the block's [v0, v1] for the placing pass.
 // k_tile_offsets turns every tile's column, over the blocks holding pairs of
 // its view, into exclusive offsets (and the tile's total); k_tile_ranges turns
 // the totals into list starts; k_emit_place gives each pair the next free
@@ -741,7 +743,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_count(const int64_t *__re
                                                              const uint32_t *__restrict__ gid,
                                                              const ViewTable *__restrict__ vt, int64_t n,
                                                              int64_t n_tiles, int64_t row_len,
-                                                             uint32_t *__restrict__ counts) {
+                                                             uint32_t *__restrict__ counts,
+                                                             uint2 *__restrict__ espan) {
     __shared__ uint32_t s_off[kEmitChunk + 1];
     __shared__ uint32_t s_h[kTileLocalMaxTiles];
     __shared__ ViewSpan s_span;
@@ -761,6 +764,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_count(const int64_t *__re
                  });
     }
     __syncthreads();
+    if (threadIdx.x == 0) espan[m] = make_uint2((uint32_t)s_span.v0, (uint32_t)s_span.v1);   // for the placing pass
     for (int v = s_span.v0; v <= s_span.v1; ++v) {
         const ViewInfo &V = vt->v[v];
         const int tv = V.tiles_x * V.tiles_y;
@@ -818,24 +822,27 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_place(const int64_t *__re
                                                              int64_t n_tiles, int64_t row_len,
                                                              const uint32_t *__restrict__ offsets,
                                                              const uint32_t *__restrict__ tstart,
+                                                             const uint2 *__restrict__ espan,
                                                              uint32_t *__restrict__ vals) {
     __shared__ uint32_t s_off[kEmitChunk + 1];
     __shared__ uint32_t s_cur[kTileLocalMaxTiles];
-    __shared__ ViewSpan s_span;
     const int64_t K = counters[kCntPairsUsed], M = counters[kCntVisible];
     const int64_t m = blockIdx.x, j0 = m * kEmitChunk;
     if (j0 >= K) return;   // block-uniform
+    // the block's views, as the counting pass found them: the cursors' rows
+    // are read while the chunk's record offsets are staged
+    const uint2 sp = espan[m];
+    const int nv = vt->n_views;
+    const int v0 = (int)sp.x < nv ? (int)sp.x : nv - 1;   // never expected; keeps rows in bounds
+    const int v1 = (int)sp.y < nv ? (int)sp.y : nv - 1;
     const EmitWindow w = emit_stage(m, K, M, poff, chunk_first, s_off);
-    __syncthreads();
-    chunk_views(m, K, w, s_off, trect, gid, vt, n, &s_span);
-    __syncthreads();
-    for (int v = s_span.v0; v <= s_span.v1; ++v) {
+    for (int v = v0; v <= v1; ++v) {
         const ViewInfo &V = vt->v[v];
         const int tv = V.tiles_x * V.tiles_y;
         const uint32_t *row = offsets + (size_t)(m + v) * (size_t)row_len;
         for (int k = threadIdx.x; k < tv; k += blockDim.x) s_cur[V.tile_off + k] = tstart[V.tile_off + k] + row[k];
     }
-    __syncthreads();
+    __syncthreads();   // the offsets and the cursors
     {
         constexpr int kRun = kEmitChunk / kEmitThreads;
         const int64_t ja = j0 + (int64_t)threadIdx.x * kRun, je = j0 + kEmitChunk < K ? j0 + kEmitChunk : K;
@@ -1615,7 +1622,8 @@ void enqueue_binning(Call &c, const gsr_views *views) {
         if (pairs) {
             hipLaunchKernelGGL(k_emit_count, dim3((unsigned)n_chunks), dim3(kEmitThreads), 0, st,
                                (const int64_t *)counters, (const uint32_t *)poff, (const uint32_t *)chunk_first,
-                               (const uint2 *)trect, gid_sorted, (const ViewTable *)vt, c.pp.n, L.T, L.tv_max, tcnt);
+                               (const uint2 *)trect, gid_sorted, (const ViewTable *)vt, c.pp.n, L.T, L.tv_max, tcnt,
+                               at<uint2>(ws, L.espan));
         }
         if (L.T > 0) {
             hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)((L.T + 255) / 256)), dim3(256), 0, st,
@@ -1629,7 +1637,8 @@ void enqueue_binning(Call &c, const gsr_views *views) {
             hipLaunchKernelGGL(k_emit_place, dim3((unsigned)n_chunks), dim3(kEmitThreads), 0, st,
                                (const int64_t *)counters, (const uint32_t *)poff, (const uint32_t *)chunk_first,
                                (const uint2 *)trect, gid_sorted, (const ViewTable *)vt, c.pp.n, L.T, L.tv_max,
-                               (const uint32_t *)tcnt, (const uint32_t *)tstart, pv0);
+                               (const uint32_t *)tcnt, (const uint32_t *)tstart, (const uint2 *)at<uint2>(ws, L.espan),
+                               pv0);
             hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)std::min<int64_t>(L.T, kTileSortGrid)),
                                dim3(kTileSortThreads), 0, st, (const uint2 *)ranges, (const uint32_t *)torder, L.T,
                                counters, (const uint32_t *)dk0, (const uint32_t *)pv0, pv1, pk0, pk1);
