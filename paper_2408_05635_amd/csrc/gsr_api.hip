@@ -145,7 +145,7 @@ struct Layout {
     // per tile and each list sorted on its own; else the two global sorts
     bool tile_local;
     int64_t tv_max;       // tiles of the largest view (row length of the per-block tile counts)
-    size_t tcnt, ttot, tstart, espan;
+    size_t tcnt, ttot, tstart, espan, pkv;
     // offsets in the sync region (cleared by every call): scan look-back words,
     // sort-pass look-back words, digit histograms (depth passes, then tile
     // passes), every view's first record (tile-local binning)
@@ -315,6 +315,7 @@ Layout make_layout(int64_t n, const ViewTable &vt, int64_t kcap) {
     L.tcnt = take(L.tile_local ? 4 * (size_t)((kc + kEmitChunk - 1) / kEmitChunk + V) * (size_t)L.tv_max : 0);
     L.ttot = take(L.tile_local ? 4 * (size_t)L.T : 0);
     L.espan = take(L.tile_local ? 8 * (size_t)((kc + kEmitChunk - 1) / kEmitChunk) : 0);   // views of each block
+    L.pkv = take(L.tile_local ? 8 * kc : 0);   // each placed pair's (depth key, record)
     L.tstart = take(L.tile_local ? 4 * (size_t)L.T : 0);
     L.torder = take(4 * (size_t)L.T);
     L.cpoff = take(4 * (size_t)L.T);
@@ -619,13 +620,15 @@ __device__ __forceinline__ uint32_t emit_pair(int64_t j, const EmitWindow &w, co
     return (uint32_t)V.tile_off + ty * (uint32_t)V.tiles_x + tx;
 }
 
-// f(j, tile key, record) for the consecutive pairs j in [ja, jb) of the
+// f(j, tile key, record, z) for the consecutive pairs j in [ja, jb) of the
 // staged chunk: one search for the first pair, then the record's tiles in
-// row-major order, moving to the next record after its last tile.
+// row-major order, moving to the next record after its last tile.  With
+// zrec, z = zrec[record] (read with the record's rectangle), else 0.
 template <class F>
 __device__ __forceinline__ void emit_run(int64_t ja, int64_t jb, const EmitWindow &w, const uint32_t *s_off,
                                          const uint2 *__restrict__ trect, const uint32_t *__restrict__ gid,
-                                         const ViewTable *__restrict__ vt, int64_t n, F f) {
+                                         const ViewTable *__restrict__ vt, int64_t n, F f,
+                                         const uint32_t *__restrict__ zrec = nullptr) {
     if (ja >= jb) return;
     int lo = 0, hi = w.nwin;   // s_off[0] <= ja; find the last entry <= ja
     while (hi - lo > 1) {
@@ -636,9 +639,10 @@ __device__ __forceinline__ void emit_run(int64_t ja, int64_t jb, const EmitWindo
             hi = mid;
     }
     uint32_t rec = (uint32_t)(w.s0 + lo), k = (uint32_t)ja - s_off[lo];
-    uint32_t tx0, tx1, tx, ty, np, base, tiles_x;
+    uint32_t tx0, tx1, tx, ty, np, base, tiles_x, z = 0;
     auto load_rec = [&]() {
         const uint2 tr = trect[rec];
+        if (zrec) z = zrec[rec];
         tx0 = tr.x & 0xffffu;
         tx1 = tr.x >> 16;
         const uint32_t ty0 = tr.y & 0xffffu, nx = tx1 - tx0 + 1u;
@@ -652,7 +656,7 @@ __device__ __forceinline__ void emit_run(int64_t ja, int64_t jb, const EmitWindo
     };
     load_rec();
     for (int64_t j = ja; j < jb; ++j) {
-        f(j, base + ty * tiles_x + tx, rec);
+        f(j, base + ty * tiles_x + tx, rec, z);
         if (j + 1 < jb) {
             if (++k == np) {   // the record's last pair: the next record starts at its first tile
                 ++rec;
@@ -759,7 +763,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_count(const int64_t *__re
         constexpr int kRun = kEmitChunk / kEmitThreads;
         const int64_t ja = j0 + (int64_t)threadIdx.x * kRun, je = j0 + kEmitChunk < K ? j0 + kEmitChunk : K;
         emit_run(ja, ja + kRun < je ? ja + kRun : je, w, s_off, trect, gid, vt, n,
-                 [&](int64_t, uint32_t key, uint32_t) {
+                 [&](int64_t, uint32_t key, uint32_t, uint32_t) {
                      if ((int64_t)key < n_tiles) atomicAdd(&s_h[key], 1u);   // always true; keeps accesses in bounds
                  });
     }
@@ -823,7 +827,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_place(const int64_t *__re
                                                              const uint32_t *__restrict__ offsets,
                                                              const uint32_t *__restrict__ tstart,
                                                              const uint2 *__restrict__ espan,
-                                                             uint32_t *__restrict__ vals) {
+                                                             const uint32_t *__restrict__ zrec,
+                                                             uint2 *__restrict__ kv) {
     __shared__ uint32_t s_off[kEmitChunk + 1];
     __shared__ uint32_t s_cur[kTileLocalMaxTiles];
     const int64_t K = counters[kCntPairsUsed], M = counters[kCntVisible];
@@ -847,12 +852,13 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_place(const int64_t *__re
         constexpr int kRun = kEmitChunk / kEmitThreads;
         const int64_t ja = j0 + (int64_t)threadIdx.x * kRun, je = j0 + kEmitChunk < K ? j0 + kEmitChunk : K;
         emit_run(ja, ja + kRun < je ? ja + kRun : je, w, s_off, trect, gid, vt, n,
-                 [&](int64_t, uint32_t key, uint32_t rs) {
+                 [&](int64_t, uint32_t key, uint32_t rs, uint32_t z) {
                      if ((int64_t)key < n_tiles) {   // always true; keeps accesses in bounds
                          const uint32_t slot = atomicAdd(&s_cur[key], 1u);
-                         if ((int64_t)slot < K) vals[slot] = rs;   // always true; keeps writes in bounds
+                         if ((int64_t)slot < K) kv[slot] = make_uint2(z, rs);   // always true; keeps writes in bounds
                      }
-                 });
+                 },
+                 zrec);
     }
 }
 
@@ -1638,10 +1644,10 @@ void enqueue_binning(Call &c, const gsr_views *views) {
                                (const int64_t *)counters, (const uint32_t *)poff, (const uint32_t *)chunk_first,
                                (const uint2 *)trect, gid_sorted, (const ViewTable *)vt, c.pp.n, L.T, L.tv_max,
                                (const uint32_t *)tcnt, (const uint32_t *)tstart, (const uint2 *)at<uint2>(ws, L.espan),
-                               pv0);
+                               (const uint32_t *)dk0, at<uint2>(ws, L.pkv));
             hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)std::min<int64_t>(L.T, kTileSortGrid)),
-                               dim3(kTileSortThreads), 0, st, (const uint2 *)ranges, (const uint32_t *)torder, L.T,
-                               counters, (const uint32_t *)dk0, (const uint32_t *)pv0, pv1, pk0, pk1);
+                               dim3(kTileSortThreads), 0, st, (const uint2 *)ranges, (const uint32_t *)torder, L.T, counters,
+                               (const uint32_t *)dk0, (const uint2 *)at<uint2>(ws, L.pkv), pv1, pk0, pk1);
         }
         return;
     }

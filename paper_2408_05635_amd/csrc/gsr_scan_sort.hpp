@@ -947,32 +947,27 @@ __device__ __forceinline__ uint32_t pow2_at_least(uint32_t n) {
 // depth keys.  big: the whole workgroup calls (a list of kTileSortWaveCap keys
 // or more), else one wave with its own kTileSortWaveCap keys of s.  hi / lo:
 // scratch over the pair range for the keys of a list longer than kTileSortCap.
-__device__ __forceinline__ void sort_tile_list(uint64_t *s, bool big, uint32_t tile, const uint2 *__restrict__ ranges,
-                                               int64_t K, uint32_t n_rec, const uint32_t *__restrict__ zrec,
-                                               const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
-                                               uint32_t *__restrict__ hi, uint32_t *__restrict__ lo,
-                                               int64_t *__restrict__ error) {
+// The list [r.x, r.y) of placed (depth key, record) pairs kv[].
+__device__ __forceinline__ void sort_tile_list(uint64_t *s, bool big, uint2 r, int64_t K, uint32_t n_rec,
+                                               const uint32_t *__restrict__ zrec, const uint2 *__restrict__ kv,
+                                               uint32_t *__restrict__ out, uint32_t *__restrict__ hi,
+                                               uint32_t *__restrict__ lo, int64_t *__restrict__ error) {
     const uint32_t t = threadIdx.x, wave = t >> 6, lane = t & 63u;
-    const uint2 r = ranges[tile];
     if (!(r.x < r.y) || (int64_t)r.y > K) return;   // empty (or never expected: out of range); uniform
     const uint32_t n = r.y - r.x;
-    const uint32_t *src = in + r.x;
+    const uint2 *src = kv + r.x;
     uint32_t *dst = out + r.x;
-    auto key_of = [&](uint32_t rec) {   // rec < n_rec always; the select keeps reads in bounds
-        return ((uint64_t)zrec[rec < n_rec ? rec : 0u] << 32) | (uint64_t)rec;
-    };
     auto block_sync = [] { __syncthreads(); };
-    // thread u's E keys from list[0, m) (all loads in flight together), then
-    // the sort of m keys over s
-    auto sort_with = [&](auto e, uint64_t *sm, const uint32_t *list, uint32_t m, uint32_t u, uint32_t *to,
-                         auto sync) {
+    // thread u's E keys (depth key, record) from list[0, m) (all loads in
+    // flight together), then the sort of m keys over s
+    auto sort_with = [&](auto e, uint64_t *sm, const uint2 *list, uint32_t m, uint32_t u, uint32_t *to, auto sync) {
         constexpr int E = decltype(e)::value;
-        uint32_t rec[E];
+        uint2 p[E];
         uint64_t k[E];
 #pragma unroll
-        for (int q = 0; q < E; ++q) rec[q] = E * u + q < m ? list[E * u + q] : 0u;
+        for (int q = 0; q < E; ++q) p[q] = E * u + q < m ? list[E * u + q] : make_uint2(0u, 0u);
 #pragma unroll
-        for (int q = 0; q < E; ++q) k[q] = E * u + q < m ? key_of(rec[q]) : kKeyInf;
+        for (int q = 0; q < E; ++q) k[q] = E * u + q < m ? ((uint64_t)p[q].x << 32) | (uint64_t)p[q].y : kKeyInf;
         lds_merge_sort<E>(sm, m, u, k, to, sync);
     };
     if (!big) {   // one wave, its own kTileSortWaveCap keys of LDS
@@ -1067,12 +1062,14 @@ __device__ __forceinline__ void sort_tile_list(uint64_t *s, bool big, uint32_t t
 // which the first nbig = counters[kCntSortBig] have kTileSortWaveCap keys or
 // more: work item w < nbig is tile torder[w] for a whole workgroup, the later
 // items are four short lists each, one per wave; the workgroups loop over the
-// items (grid-stride), so none is launched only to find no work.
+// items (grid-stride), so none is launched only to find no work.  kv: the
+// placed (depth key, record) pairs (zrec: the records' keys, for the long
+// lists' merges).
 __global__ __launch_bounds__(kTileSortThreads) void k_tile_sort(const uint2 *__restrict__ ranges,
                                                                 const uint32_t *__restrict__ torder, int64_t n_tiles,
                                                                 int64_t *__restrict__ counters,
                                                                 const uint32_t *__restrict__ zrec,
-                                                                const uint32_t *__restrict__ in,
+                                                                const uint2 *__restrict__ kv,
                                                                 uint32_t *__restrict__ out, uint32_t *__restrict__ hi,
                                                                 uint32_t *__restrict__ lo) {
     __shared__ uint64_t s[kTileSortCap];
@@ -1087,7 +1084,7 @@ __global__ __launch_bounds__(kTileSortThreads) void k_tile_sort(const uint2 *__r
         if (slot < n_tiles) {   // wave-uniform; always true for a big item
             const uint32_t tile = torder[slot];
             if ((int64_t)tile < n_tiles)   // always true: torder is a permutation
-                sort_tile_list(s, big, tile, ranges, K, n_rec, zrec, in, out, hi, lo, counters + kCntSyncError);
+                sort_tile_list(s, big, ranges[tile], K, n_rec, zrec, kv, out, hi, lo, counters + kCntSyncError);
         }
         __syncthreads();   // every wave done with s before the next item
     }
