@@ -162,12 +162,15 @@ struct TotalTo {
     }
 };
 
+__device__ __forceinline__ uint32_t scan_slot(uint32_t k) { return k + (k >> 4); }
+
 // Single-pass exclusive scan: sink(i, exclusive_prefix, value) for every
 // i < n, then fin(total) once.  The sink may overwrite the source in place.
 template <class Src, class Sink, class Fin>
 __global__ __launch_bounds__(kScanThreads) void k_scan(Src src, Sink sink, const int64_t *n_dev, int64_t n_host,
                                                        SyncState ss, uint32_t id, Fin fin) {
     __shared__ uint32_t s_b, s_excl;
+    __shared__ uint32_t s_val[kChunk + kChunk / 16], s_pre[kChunk + kChunk / 16];
     if (threadIdx.x == 0) s_b = take_ticket(ss.tickets, id);
     __syncthreads();
     const int64_t b = s_b;
@@ -177,16 +180,32 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Src src, Sink sink, const
         if (nb == 0 && b == 0 && threadIdx.x == 0) fin(0);
         return;
     }
-    const int64_t first = b * kChunk + (int64_t)threadIdx.x * kScanItems;
+    // The block's items are read and written coalesced (item j kScanThreads +
+    // thread in round j) through LDS, where each thread scans kScanItems
+    // consecutive items (one pad word after every 16, so that a thread's
+    // items fall in different banks).
+    const int64_t base = b * kChunk;
+    const uint32_t t = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = base + j * kScanThreads + (int64_t)t;
+        s_val[scan_slot(j * kScanThreads + t)] = i < n ? src(i) : 0u;
+    }
+    __syncthreads();
     uint32_t v[kScanItems];
     uint32_t s = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
-        v[j] = (first + j < n) ? src(first + j) : 0u;
+        v[j] = s_val[scan_slot(t * kScanItems + j)];
         s += v[j];
     }
     uint32_t agg;
     uint32_t run = block_excl_scan_u32<kScanThreads>(s, agg);
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {   // each item's prefix within the block
+        s_pre[scan_slot(t * kScanItems + j)] = run;
+        run += v[j];
+    }
     uint64_t *mine = ss.status + b;
     if (threadIdx.x == 0) publish(mine, id, b == 0 ? kFlagPrefix : kFlagAgg, agg);
     if (threadIdx.x < 64) {   // wave 0 looks back
@@ -198,11 +217,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Src src, Sink sink, const
         }
     }
     __syncthreads();
-    run += s_excl;
+    const uint32_t excl = s_excl;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
-        if (first + j < n) sink(first + j, run, v[j]);
-        run += v[j];
+        const int64_t i = base + j * kScanThreads + (int64_t)t;
+        const uint32_t k = scan_slot(j * kScanThreads + t);
+        if (i < n) sink(i, excl + s_pre[k], s_val[k]);
     }
 }
 
