@@ -139,7 +139,7 @@ __device__ __forceinline__ AlphaEval eval_alpha(const float2 d0, const float4 B,
     e.G = __builtin_amdgcn_exp2f(p2);
     const float og = __fmul_rn(B.w, e.G);
     e.clamped = og > kAlphaMax;
-    e.alpha = e.clamped ? kAlphaMax : og;
+    e.alpha = fminf(og, kAlphaMax);   // og for og <= kAlphaMax (a min, one instruction where clamped is unused)
     return e;
 }
 
