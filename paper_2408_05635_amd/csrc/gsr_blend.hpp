@@ -252,7 +252,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(const ViewTable *__restrict__ 
             const AlphaEval ev = eval_alpha(make_float2(d4.x, d4.y), s_b[k], fjx, fjy);
             if (COUNT) n_eval += done ? 0u : 1u;
             const bool hit = !done && ev.alpha >= kAlphaMin;
-            const float Tn = T * (1.0f - ev.alpha);
+            const float Tn = __builtin_fmaf(-ev.alpha, T, T);   // T (1 - alpha), rounded once
             const bool stop = hit && Tn < kTMin;
             const bool take = hit != stop;   // hit and not stopped
             if (COUNT) n_contrib += take ? 1u : 0u;
