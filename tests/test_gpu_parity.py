@@ -185,6 +185,17 @@ def test_binning_bit_exact_long_lists(capacity):
     assert mism == 0
 
 
+@pytest.mark.parametrize("width", [1024, 1040])
+def test_binning_bit_exact_most_tiles(rast, width):
+    """8 views at width x 512 with 16x16 tiles: 16 384 tiles at 1024 (the most
+    that tile-local binning takes, so the range kernel's last thread holds the
+    last tiles and the last list ends at the total) and 16 640 at 1040 (one
+    past: the two global sorts)."""
+    w = scenes.config2(n_views=8, n=60000)
+    w.views = scenes.Views([scenes._room_cam(width, 512)] * 8, w.views.quat, w.views.trans)
+    assert _check_binning(rast, w, (16, 16)) == 0
+
+
 @pytest.mark.parametrize("per_tile", [0, 5000])
 def test_binning_bit_exact_many_blocks(per_tile):
     """Hundreds of scan blocks, so that the blocks' look-back chains are long
