@@ -137,7 +137,8 @@ __device__ __forceinline__ void prep_gauss(const GaussIn &p, GaussPre &g) {
 
 // Project Gaussian p (view-independent part g) into view (pose, camera).
 // Culls: z <= z_near, 255 o <= 1, det(Sigma') <= 0, non-finite values,
-// rectangle outside the image.  With ISO, Sigma = s^2 I, so
+// rectangle outside the image.  FULL: the record's conic factor is formed
+// (else only the culling decisions, the rectangle and the depth).  With ISO, Sigma = s^2 I, so
 // M = W Sigma W^T = s^2 I (W is a rotation) and no rotation or covariance
 // product is formed.
 template <bool FULL, bool ISO>
@@ -188,10 +189,18 @@ __device__ __forceinline__ void project_pre(const GaussIn &p, const GaussPre &g,
     if (!(r.det > 0.0) || !isfinite(r.det)) return;
     r.mx = fx * x * iz + cam.cx;
     r.my = fy * y * iz + cam.cy;
-    r.l11 = kLScale * sqrt(r.c / r.det);
-    r.l21 = -kLScale * r.b / sqrt(r.c * r.det);
-    r.l22 = kLScale / sqrt(r.c);
-    if (!isfinite(r.mx) || !isfinite(r.my) || !isfinite(r.l11) || !isfinite(r.l21)) return;
+    if (!isfinite(r.mx) || !isfinite(r.my)) return;
+    // The conic's scaled Cholesky factor.  Without FULL (culling only) just
+    // whether l11 and l21 are finite, which they are for c and det in
+    // [1e-100, 1e200] and |b| <= 1e200 (c / det <= 1e300; c det >= 1e-200, or
+    // it overflows and l21 = -0): only outside those bounds are they formed.
+    const bool surely_finite = r.c >= 1e-100 && r.c <= 1e200 && r.det >= 1e-100 && fabs(r.b) <= 1e200;
+    if (FULL || !surely_finite) {
+        r.l11 = kLScale * sqrt(r.c / r.det);
+        r.l21 = -kLScale * r.b / sqrt(r.c * r.det);
+        r.l22 = kLScale / sqrt(r.c);
+        if (!isfinite(r.l11) || !isfinite(r.l21)) return;
+    }
     // Binning radius: a circle holding the whole alpha >= 1/255 ellipse
     // (d^T Sigma'^-1 d <= 2 ln(255 o)), widened by 2^-10 relatively and
     // absolutely so that FP32 rounding never clips a contributing pixel.
