@@ -1096,12 +1096,15 @@ struct GradOut {
 // the pose finalisation to add in a fixed order.
 //
 // Load balance: records are depth-sorted, so the nearest ones, which can
-// cover every tile of the image, are neighbours.  Lane l of wave slot w takes
-// record l * W + w (W = number of wave slots needed), which spreads
-// neighbours over different waves; the grid's waves walk the slots with a
-// stride.  A record with more than kLongRows rows is summed by the whole wave
-// (rows lane, lane + 64, ...; then a fixed-order reduction), so no lane walks
-// a long range alone.  Both row sums are deterministic.
+// cover every tile of the image, are neighbours.  With a row per pair, lane l
+// of wave slot w takes record l * W + w (W = number of wave slots needed),
+// which spreads neighbours over different waves; the grid's waves walk the
+// slots with a stride.  A record with more than kLongRows rows is summed by
+// the whole wave (rows lane, lane + 64, ...; then a fixed-order reduction),
+// so no lane walks a long range alone.  Both row sums are deterministic.
+// With one row per record (ATOMIC) every record costs the same, and wave slot
+// w takes records 64 w + l: coalesced reads, and the wave's records mostly of
+// one view, whose pose partials it then sums before adding them.
 constexpr uint32_t kLongRows = 32;
 
 // ATOMIC: the record's 2D gradient is its own row of gpairs (kRowStride
@@ -1128,7 +1131,7 @@ __global__ __launch_bounds__(256) void k_record_bwd(ProjParams pp, const ViewTab
     const uint32_t lane = threadIdx.x & 63u;
     const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
     for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < W; w += wstride) {   // wave-uniform
-        const int64_t s = (int64_t)lane * W + w;
+        const int64_t s = ATOMIC ? 64 * w + (int64_t)lane : (int64_t)lane * W + w;
         const bool valid = s < M;
         uint32_t j0 = 0, nrow = 0;
         if (valid && have_pairs) {
@@ -1184,46 +1187,71 @@ __global__ __launch_bounds__(256) void k_record_bwd(ProjParams pp, const ViewTab
                 if ((int)lane == src) r2[c] = t;
             }
         }
-        if (!valid) continue;
-        const uint32_t gid = gid_sorted[s];
-        const int v = (int)(gid / (uint64_t)pp.n);
-        if (v >= V) continue;   // never expected; keeps reads in bounds
-        const int64_t i = (int64_t)gid - (int64_t)v * pp.n;
-        const GaussIn p = load_gauss<ISO>(pp.g, i);
-        Proj r;
-        project<true, ISO>(p, poses[v], vt->v[v], pp.z_near, pp.blur, r);
-        // the rows carry the conic-factor and mean partials without their
-        // per-record factors k = 2 o ln2 and (l11, l21, l22)
-        const double k2 = 2.0 * kLn2 * r.o;
-        float g2[10];
-        g2[0] = (float)(k2 * r.l11 * (double)r2[0]);
-        g2[1] = (float)(k2 * (r.l21 * (double)r2[0] + r.l22 * (double)r2[1]));
-#pragma unroll
-        for (int c = 2; c < 5; ++c) g2[c] = (float)(k2 * (double)r2[c]);
-        if constexpr (NV == 10) {
-#pragma unroll
-            for (int c = 5; c < 10; ++c) g2[c] = r2[c];
-        } else {
-            g2[5] = g2[6] = g2[7] = g2[8] = 0.0f;
-            g2[9] = r2[5];
+        // every lane goes on to the pose sums below (lanes without a record
+        // with zero partials)
+        double gX[3] = {0.0, 0.0, 0.0}, GW[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int v = -1;
+        if (valid) {
+            const uint32_t gid = gid_sorted[s];
+            v = (int)(gid / (uint64_t)pp.n);
+            if (v >= V) v = -1;   // never expected; keeps reads in bounds
         }
-        ParamGrad pg;
-        for (int k = 0; k < 3; ++k) pg.mu[k] = pg.ls[k] = pg.rgb[k] = 0.0;
-        for (int k = 0; k < 4; ++k) pg.q[k] = 0.0;
-        pg.logit = 0.0;
-        double gX[3], GW[9];
-        project_backward<ISO, NV == 10>(p, poses[v], vt->v[v], r, g2, pg, gX, GW);
-        if (want_gauss) {
-            float *o = rgrad + kRecGrad * (size_t)s;
-            for (int k = 0; k < 3; ++k) o[k] = (float)pg.mu[k];
-            for (int k = 0; k < 4; ++k) o[3 + k] = (float)pg.q[k];
-            for (int k = 0; k < 3; ++k) o[7 + k] = (float)pg.ls[k];
-            o[10] = (float)pg.logit;
-            for (int k = 0; k < 3; ++k) o[11 + k] = (float)pg.rgb[k];
+        if (v >= 0) {
+            const int64_t i = (int64_t)gid_sorted[s] - (int64_t)v * pp.n;
+            const GaussIn p = load_gauss<ISO>(pp.g, i);
+            Proj r;
+            project<true, ISO>(p, poses[v], vt->v[v], pp.z_near, pp.blur, r);
+            // the rows carry the conic-factor and mean partials without their
+            // per-record factors k = 2 o ln2 and (l11, l21, l22)
+            const double k2 = 2.0 * kLn2 * r.o;
+            float g2[10];
+            g2[0] = (float)(k2 * r.l11 * (double)r2[0]);
+            g2[1] = (float)(k2 * (r.l21 * (double)r2[0] + r.l22 * (double)r2[1]));
+#pragma unroll
+            for (int c = 2; c < 5; ++c) g2[c] = (float)(k2 * (double)r2[c]);
+            if constexpr (NV == 10) {
+#pragma unroll
+                for (int c = 5; c < 10; ++c) g2[c] = r2[c];
+            } else {
+                g2[5] = g2[6] = g2[7] = g2[8] = 0.0f;
+                g2[9] = r2[5];
+            }
+            ParamGrad pg;
+            for (int k = 0; k < 3; ++k) pg.mu[k] = pg.ls[k] = pg.rgb[k] = 0.0;
+            for (int k = 0; k < 4; ++k) pg.q[k] = 0.0;
+            pg.logit = 0.0;
+            project_backward<ISO, NV == 10>(p, poses[v], vt->v[v], r, g2, pg, gX, GW);
+            if (want_gauss) {
+                float *o = rgrad + kRecGrad * (size_t)s;
+                for (int k = 0; k < 3; ++k) o[k] = (float)pg.mu[k];
+                for (int k = 0; k < 4; ++k) o[3 + k] = (float)pg.q[k];
+                for (int k = 0; k < 3; ++k) o[7 + k] = (float)pg.ls[k];
+                o[10] = (float)pg.logit;
+                for (int k = 0; k < 3; ++k) o[11 + k] = (float)pg.rgb[k];
+            }
         }
         if (want_pose) {
-            for (int k = 0; k < 9; ++k) atomicAdd(&s_pose[v * 12 + k], GW[k]);
-            for (int k = 0; k < 3; ++k) atomicAdd(&s_pose[v * 12 + 9 + k], gX[k]);
+            // A wave whose records all belong to one view (always so for a
+            // single view) sums its partials first, by butterflies, and adds
+            // them once: the LDS adds of 64 lanes to the same 12 words would
+            // be serialised.  Otherwise each lane adds its own.
+            const uint64_t has = ballot(v >= 0);
+            if (has != 0) {   // wave-uniform
+                const int vf = __builtin_amdgcn_readlane(v, __builtin_ctzll(has));
+                if (ballot(v >= 0 && v != vf) == 0) {
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) GW[k] = wave_sum_f64(GW[k]);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) gX[k] = wave_sum_f64(gX[k]);
+                    if (lane == 0) {
+                        for (int k = 0; k < 9; ++k) atomicAdd(&s_pose[vf * 12 + k], GW[k]);
+                        for (int k = 0; k < 3; ++k) atomicAdd(&s_pose[vf * 12 + 9 + k], gX[k]);
+                    }
+                } else if (v >= 0) {
+                    for (int k = 0; k < 9; ++k) atomicAdd(&s_pose[v * 12 + k], GW[k]);
+                    for (int k = 0; k < 3; ++k) atomicAdd(&s_pose[v * 12 + 9 + k], gX[k]);
+                }
+            }
         }
     }
     if (want_pose) {
