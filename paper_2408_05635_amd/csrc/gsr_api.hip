@@ -510,15 +510,17 @@ __device__ __forceinline__ uint32_t gather_record(const ProjParams &pp, const Vi
 }
 
 template <bool ISO>
-__global__ __launch_bounds__(256) void k_gather(ProjParams pp, const ViewTable *__restrict__ vt,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_gather(ProjParams pp, const ViewTable *__restrict__ vt,
                                                 const PoseF64 *__restrict__ poses, const int64_t *__restrict__ counters,
                                                 const uint32_t *__restrict__ sorted_gid, float4 *__restrict__ rec,
                                                 uint2 *__restrict__ trect, uint32_t *__restrict__ cnt_s,
                                                 uint32_t *__restrict__ inv, const float *__restrict__ rgb,
                                                 float *__restrict__ rrows) {
+    // one record per thread (the grid covers every (view, Gaussian) item): no
+    // loop, so that the registers fit more waves
     const int64_t M = counters[kCntVisible];
-    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < M; s += (int64_t)gridDim.x * blockDim.x)
-        gather_record<ISO>(pp, vt, poses, sorted_gid, rec, trect, cnt_s, inv, rgb, rrows, s);
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < M) gather_record<ISO>(pp, vt, poses, sorted_gid, rec, trect, cnt_s, inv, rgb, rrows, s);
 }
 
 // The same, fused with the pair offsets: the exclusive scan of the records'
@@ -1638,7 +1640,7 @@ void enqueue_binning(Call &c, const gsr_views *views) {
                                osink, PairTotal{counters, L.kcap});
     } else {
         if (L.vn > 0)
-            hipLaunchKernelGGL(c.pp.iso ? k_gather<true> : k_gather<false>, dim3(grid_for(L.vn, 256, 8192)),
+            hipLaunchKernelGGL(c.pp.iso ? k_gather<true> : k_gather<false>, dim3(grid_for(L.vn, 256, 1ll << 24)),
                                dim3(256), 0, st, c.pp, vt, poses, counters, gid_sorted, rec, trect, cnt_s, inv,
                                c.pp.g.rgb, rrows);
         scan_exclusive(CntSrc{cnt_s}, osink, counters + kCntVisible, L.vn, ss, kIdOffsets,
