@@ -1328,19 +1328,25 @@ __device__ __forceinline__ void pose_final_view(const float *__restrict__ pq, co
                                                 bool centre, const PoseF64 *poses,
                                                 const double *__restrict__ pose_blocks, int nblocks, int V,
                                                 const gsr_pose_grads &pg, const PoseOpt &po, int v) {
+    // What the lead thread needs after the reduction (the pose inputs, the
+    // rotation and the optimiser state), one value per thread, requested
+    // first so that these loads overlap the rows' loads, and put in LDS
+    // after them (a value per thread keeps the registers of the kernel's other
+    // block roles free).
+    constexpr int kPreQ = 0, kPreT = 4, kPreW = 7, kPreS = 16;
+    constexpr int kPre = kPreS + GSR_POSE_STATE_DOUBLES;
     __shared__ double s_red[12][4];
+    __shared__ double s_pre[kPre];
     const int t = threadIdx.x;
-    // what the lead thread needs after the reduction (the pose inputs, the
-    // rotation and the optimiser state), requested first so that these loads
-    // overlap the rows' loads and the reduction
-    double q[4] = {0.0, 0.0, 0.0, 0.0}, tin[3] = {0.0, 0.0, 0.0}, W[9] = {};
-    PoseOptState s0 = {};
-    if (t == 0) {
-        for (int k = 0; k < 4; ++k) q[k] = pq[4 * v + k];
-        for (int k = 0; k < 3; ++k) tin[k] = pt[3 * v + k];
-        for (int k = 0; k < 9; ++k) W[k] = poses[v].W[k];
-        if (po.st) s0 = po.st[v];
-    }
+    double pre = 0.0;
+    if (t < kPreT)
+        pre = pq[4 * v + t];
+    else if (t < kPreW)
+        pre = pt[3 * v + (t - kPreT)];
+    else if (t < kPreS)
+        pre = poses[v].W[t - kPreW];
+    else if (t < kPre && po.st)
+        pre = reinterpret_cast<const double *>(po.st + v)[t - kPreS];
     double acc[12];
     for (int k = 0; k < 12; ++k) acc[k] = 0.0;
 #pragma unroll 4   // loads in flight together; the additions keep their order
@@ -1349,6 +1355,7 @@ __device__ __forceinline__ void pose_final_view(const float *__restrict__ pq, co
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] += row[k];
     }
+    if (t < kPre) s_pre[t] = pre;
     // the block's rows summed in a fixed order: each wave's butterfly, then the four waves in order
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = wave_sum_f64(acc[k]);
@@ -1356,6 +1363,7 @@ __device__ __forceinline__ void pose_final_view(const float *__restrict__ pq, co
         for (int k = 0; k < 12; ++k) s_red[k][t >> 6] = acc[k];
     __syncthreads();
     if (t != 0) return;
+    const double *q = s_pre + kPreQ, *tin = s_pre + kPreT, *W = s_pre + kPreW;
     double GW[12];
     for (int k = 0; k < 12; ++k) GW[k] = ((s_red[k][0] + s_red[k][1]) + s_red[k][2]) + s_red[k][3];
     const double *gt = GW + 9;
@@ -1382,6 +1390,9 @@ __device__ __forceinline__ void pose_final_view(const float *__restrict__ pq, co
         double sq[4], sc[3];
         for (int k = 0; k < 4; ++k) sq[k] = (double)(float)gq[k];
         for (int k = 0; k < 3; ++k) sc[k] = (double)(float)gc[k];
+        PoseOptState s0;
+        double *sd = reinterpret_cast<double *>(&s0);
+        for (int k = 0; k < GSR_POSE_STATE_DOUBLES; ++k) sd[k] = s_pre[kPreS + k];
         pose_adam_apply(v, sq, sc, po.hp, s0, po.st, po.quat, po.trans);
     }
 }
@@ -1410,7 +1421,7 @@ struct FinalArgs {
     int64_t *loss_ticket;   // cleared by the call's set-up
 };
 
-__global__ __launch_bounds__(256) void k_finalize(FinalArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 5))) void k_finalize(FinalArgs a) {
     int b = (int)blockIdx.x;
     if (b < a.n_pose) {
         pose_final_view(a.pq, a.pt, a.centre != 0, a.poses, a.pose_blocks, a.pose_rows, a.V, a.pg, a.po, b);

@@ -29,8 +29,11 @@ struct PoseOptState {
 };
 static_assert(sizeof(PoseOptState) == GSR_POSE_STATE_DOUBLES * sizeof(double), "pose state layout");
 
+// (contraction off: the fused tracking step and the separate step kernel
+// then round alike wherever the compiler inlines them)
 __device__ __forceinline__ double adam_update(double &x, double g, double &m, double &v, double lr, double b1, double b2,
                                               double eps, double c1, double c2) {
+#pragma clang fp contract(off)
     m = b1 * m + (1.0 - b1) * g;
     v = b2 * v + (1.0 - b2) * g * g;
     const double m_hat = m / c1, v_hat = v / c2;
@@ -61,6 +64,7 @@ __global__ void k_pose_opt_init(int V, const float *__restrict__ quat, const flo
 __device__ __forceinline__ void pose_adam_apply(int v, const double dq_c[4], const double dc[3], const gsr_pose_adam &hp,
                                                 PoseOptState s, PoseOptState *__restrict__ st,
                                                 float *__restrict__ quat, float *__restrict__ trans) {
+#pragma clang fp contract(off)
     s.step += 1.0;
     const double b1 = hp.beta1, b2 = hp.beta2, eps = hp.eps;
     s.b1p *= b1;
