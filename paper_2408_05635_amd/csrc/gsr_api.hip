@@ -885,19 +885,24 @@ __global__ void k_fill_f64(double *p, int64_t n) {
 constexpr int kOrderThreads = 1024;
 constexpr uint32_t kOrderBuckets = 256;
 
-// len_of(i): the list length of tile i.
+// len_of(i): the list length of tile i.  s_ord: null, or an LDS array of
+// n_tiles words, through which, without splits, the tile order and the work
+// items are written coalesced rather than scattered (with splits the tiles
+// are few and the order stays in s_to).
 template <class Len>
 __device__ __forceinline__ void work_order_block(Len len_of, int64_t n_tiles, int64_t slots_cap,
                                                  uint32_t *__restrict__ torder, uint32_t *__restrict__ cpoff,
                                                  uint32_t *__restrict__ work, int64_t *__restrict__ n_work,
-                                                 int64_t *__restrict__ counters) {
+                                                 int64_t *__restrict__ counters, uint32_t *s_ord = nullptr) {
     __shared__ uint32_t s_h[kOrderBuckets];
     // with chunk splits (at most kSplitMaxTiles tiles) the tile order and the
     // checkpoint slots are also kept here, so the later phases read no global
     // memory that this block wrote
-    __shared__ uint32_t s_to[kSplitMaxTiles], s_cp[kSplitMaxTiles];
+    __shared__ uint32_t s_to_own[kSplitMaxTiles], s_cp[kSplitMaxTiles];
+    uint32_t *s_to = s_to_own;
     const int t = threadIdx.x;
     const bool split_mode = slots_cap > 0 && n_tiles <= kSplitMaxTiles;   // the layout gives slots only then
+    if (split_mode) s_ord = nullptr;
     auto bucket_of = [](uint32_t len) {
         const uint32_t b = len >> 4;
         return (kOrderBuckets - 1u) - (b < kOrderBuckets - 1u ? b : kOrderBuckets - 1u);
@@ -919,13 +924,21 @@ __device__ __forceinline__ void work_order_block(Len len_of, int64_t n_tiles, in
     for (int64_t i = t; i < n_tiles; i += kOrderThreads) {
         const uint32_t pos = atomicAdd(&s_h[bucket_of(len_of(i))], 1u);
         if ((int64_t)pos < n_tiles) {   // always true; keeps writes in bounds
-            torder[pos] = (uint32_t)i;
-            if (split_mode)
-                s_to[pos] = (uint32_t)i;
-            else
-                work[pos] = (uint32_t)i;   // no splits: the items are the tiles, in that order
+            if (s_ord) {
+                s_ord[pos] = (uint32_t)i;
+            } else {
+                torder[pos] = (uint32_t)i;
+                if (split_mode)
+                    s_to[pos] = (uint32_t)i;
+                else
+                    work[pos] = (uint32_t)i;   // no splits: the items are the tiles, in that order
+            }
         }
         if (!split_mode) cpoff[i] = kNoSplit;
+    }
+    if (s_ord) {   // the order copied out in rank order; no splits: the items are the tiles, in that order
+        __syncthreads();
+        for (int64_t r = t; r < n_tiles; r += kOrderThreads) torder[r] = work[r] = s_ord[r];
     }
     if (!split_mode) {
         if (t == 0) *n_work = counters[kCntWorkItems] = n_tiles;
@@ -1082,7 +1095,8 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_ranges(const uint32_t *_
     if ((t & 63) == 0 && big) atomicAdd(&s_big, big);
     __syncthreads();
     if (t == 0) counters[kCntSortBig] = s_big;
-    work_order_block(len_of, n_tiles, slots_cap, torder, cpoff, work, n_work, counters);
+    __shared__ uint32_t s_ord[kTileLocalMaxTiles];
+    work_order_block(len_of, n_tiles, slots_cap, torder, cpoff, work, n_work, counters, s_ord);
 }
 
 struct GradOut {
