@@ -583,21 +583,40 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     };
+    // A segment's list entries and the forward's culling words for them are
+    // read one segment ahead (the lane's entry seg_lo + lane, ~0u where the
+    // wave has none), so that only the kept entries' records are read when a
+    // segment starts.
+    auto seg_lo_of = [&](uint32_t hi_) { return hi_ - lo > (uint32_t)kSeg ? hi_ - kSeg : lo; };
+    uint32_t pf_s = ~0u;
+    uint64_t pf_cm = 0;
+    auto prefetch = [&](uint32_t slo, uint32_t shi) {
+        const uint32_t whi = wmax < shi ? wmax : shi;   // this wave's last entry + 1 in the segment
+        const uint32_t e = slo + lane;
+        pf_s = ~0u;
+        pf_cm = 0;
+        if (wmax > slo && lane < (uint32_t)kSeg && e < whi) {
+            pf_s = pair_rec[e];
+            pf_cm = st.cmask[cmask_index(rg.x, tid_g, e - rg.x, nw, (int)wave)];
+        }
+    };
+    if (top > lo) prefetch(seg_lo_of(top), top);
     for (uint32_t seg_hi = top; seg_hi > lo;) {
-        const uint32_t seg_lo = seg_hi - lo > (uint32_t)kSeg ? seg_hi - kSeg : lo;
+        const uint32_t seg_lo = seg_lo_of(seg_hi);
+        const uint32_t s_cur = pf_s;
+        const uint64_t cm_cur = pf_cm;
+        if (seg_lo > lo) prefetch(seg_lo_of(seg_lo), seg_lo);
         for (int c = lane; c < kSeg * NV; c += 64) s_acc[wave][c] = 0.0f;
         if (threadIdx.x < seg_hi - seg_lo) s_j[threadIdx.x] = row_of(seg_lo + threadIdx.x);   // read after the barrier
         if (wmax > seg_lo) {   // wave-uniform: this wave has pixels with entries in the segment
-            const uint32_t w_hi = wmax < seg_hi ? wmax : seg_hi;   // this wave's last entry + 1 in the segment
             const uint32_t e = seg_lo + lane;
             bool keep = false;
             uint32_t s = 0;
-            if (lane < (uint32_t)kSeg && e < w_hi && pair_rec[e] < n_rec) {
+            if (s_cur < n_rec) {   // an entry of this wave in the segment
                 // the forward's decision for this entry and block
-                const uint32_t rel = e - rg.x;
-                keep = (st.cmask[cmask_index(rg.x, tid_g, rel, nw, (int)wave)] >> (rel & 63u)) & 1ull;
+                keep = (cm_cur >> ((e - rg.x) & 63u)) & 1ull;
                 if (keep) {
-                    s = pair_rec[e];
+                    s = s_cur;
                     s_d[wave][lane] = block_offset(rec[3 * (size_t)s], (float)bx0, (float)by0);
                 }
             }
