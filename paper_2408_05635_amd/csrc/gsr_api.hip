@@ -1622,14 +1622,17 @@ void enqueue_binning(Call &c, const gsr_views *views) {
     // index order (their depth keys beside them, in dk0), counted.  Else the
     // visible records in depth order: stable sort on the float32 depth bits
     // (positive floats sort as integers), which also compacts and counts them.
+    const bool wide = L.vn >= kCompactWideMin;
+    const int64_t compact_chunk = (int64_t)kCompactThreads * (wide ? 8 : 4);
+    auto compact = wide ? k_compact_hist<8> : k_compact_hist<4>;
     if (L.vn > 0 && L.tile_local) {
-        hipLaunchKernelGGL(k_compact_hist, dim3((unsigned)((L.vn + kCompactChunk - 1) / kCompactChunk)),
+        hipLaunchKernelGGL(compact, dim3((unsigned)((L.vn + compact_chunk - 1) / compact_chunk)),
                            dim3(kCompactThreads), 0, st, (const uint32_t *)cnt, (const uint32_t *)zkey, L.vn, dk0, dv0,
                            ss, (uint32_t)kIdCompact, (uint32_t *)nullptr, counters + kCntVisible,
                            reinterpret_cast<uint32_t *>(sync + L.sync_vstart), c.pp.n);
     } else if (L.vn > 0) {
         if (L.depth_sweep) {
-            hipLaunchKernelGGL(k_compact_hist, dim3((unsigned)((L.vn + kCompactChunk - 1) / kCompactChunk)),
+            hipLaunchKernelGGL(compact, dim3((unsigned)((L.vn + compact_chunk - 1) / compact_chunk)),
                                dim3(kCompactThreads), 0, st, (const uint32_t *)cnt, (const uint32_t *)zkey, L.vn, dk0,
                                dv0, ss, (uint32_t)kIdCompact, dhist, counters + kCntVisible, (uint32_t *)nullptr,
                                (int64_t)1);

@@ -741,7 +741,9 @@ __device__ __forceinline__ void flush_digit_hist(const uint32_t *s_hist, int pas
 
 // The visible items (cnt[i] != 0) among the n (view, Gaussian) items,
 // compacted in index order into (kout = depth key, vout = index) by a
-// single-pass scan (decoupled look-back over blocks of kCompactChunk items),
+// single-pass scan (decoupled look-back over blocks of kCompactThreads x ITEMS
+// items: 4 per thread, or 8 for a million items or more, where half as many
+// blocks make a shorter look-back),
 // and their number (written to *n_out by the last block).  With hist (the
 // first step of the one-launch depth sort), also the histograms of the four
 // byte digits of their keys (added into hist[4][256], zero beforehand).  With
@@ -749,9 +751,9 @@ __device__ __forceinline__ void flush_digit_hist(const uint32_t *s_hist, int pas
 // output place of every group's first visible item: the number of visible
 // items before the group.
 constexpr int kCompactThreads = 1024;
-constexpr int kCompactItems = 4;
-constexpr int kCompactChunk = kCompactThreads * kCompactItems;
+constexpr int64_t kCompactWideMin = 1 << 20;   // items from which a thread takes 8
 
+template <int ITEMS>
 __global__ __launch_bounds__(kCompactThreads) void k_compact_hist(const uint32_t *__restrict__ cnt,
                                                                   const uint32_t *__restrict__ zkey, int64_t n,
                                                                   uint32_t *__restrict__ kout,
@@ -762,26 +764,26 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact_hist(const uint32_t
     __shared__ uint32_t s_b, s_excl;
     __shared__ uint32_t s_hist[4 * 256];
     const uint32_t t = threadIdx.x;
-    const int64_t nb = (n + kCompactChunk - 1) / kCompactChunk;
+    const int64_t nb = (n + (kCompactThreads * ITEMS) - 1) / (kCompactThreads * ITEMS);
     if ((int64_t)blockIdx.x >= nb) return;   // block-uniform
     if (t == 0) s_b = take_ticket(ss.tickets, id);
     s_hist[t] = 0u;
     __syncthreads();
     const int64_t b = s_b;
-    const int64_t first = b * kCompactChunk + (int64_t)t * kCompactItems;
-    uint32_t c[kCompactItems], k[kCompactItems];
-    if (first + kCompactItems <= n) {   // 16-byte aligned runs of 4
+    const int64_t first = b * (kCompactThreads * ITEMS) + (int64_t)t * ITEMS;
+    uint32_t c[ITEMS], k[ITEMS];
+    if (first + ITEMS <= n) {   // 16-byte aligned runs of 4
         const uint4 *c4 = reinterpret_cast<const uint4 *>(cnt + first);
         const uint4 *k4 = reinterpret_cast<const uint4 *>(zkey + first);
 #pragma unroll
-        for (int q = 0; q < kCompactItems / 4; ++q) {
+        for (int q = 0; q < ITEMS / 4; ++q) {
             const uint4 a = c4[q], z = k4[q];
             c[4 * q] = a.x, c[4 * q + 1] = a.y, c[4 * q + 2] = a.z, c[4 * q + 3] = a.w;
             k[4 * q] = z.x, k[4 * q + 1] = z.y, k[4 * q + 2] = z.z, k[4 * q + 3] = z.w;
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < kCompactItems; ++j) {
+        for (int j = 0; j < ITEMS; ++j) {
             const bool in = first + j < n;
             c[j] = in ? cnt[first + j] : 0u;
             k[j] = in ? zkey[first + j] : 0u;
@@ -789,10 +791,10 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact_hist(const uint32_t
     }
     uint32_t s = 0;
 #pragma unroll
-    for (int j = 0; j < kCompactItems; ++j) s += c[j] != 0u ? 1u : 0u;
+    for (int j = 0; j < ITEMS; ++j) s += c[j] != 0u ? 1u : 0u;
     if (hist) {
 #pragma unroll
-        for (int j = 0; j < kCompactItems; ++j) add_digit_hist(k[j], c[j] != 0u, 32, s_hist);
+        for (int j = 0; j < ITEMS; ++j) add_digit_hist(k[j], c[j] != 0u, 32, s_hist);
     }
     uint32_t agg;
     uint32_t run = block_excl_scan_u32<kCompactThreads>(s, agg);
@@ -812,7 +814,7 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact_hist(const uint32_t
     int64_t gs = -1;
     if (first_of && first < n) gs = (first + group - 1) / group * group;
 #pragma unroll
-    for (int j = 0; j < kCompactItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         if (gs == first + j && gs < n) {   // a group starts at item first + j
             first_of[gs / group] = run;
             gs += group;
