@@ -779,11 +779,16 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_count(const int64_t *__re
     }
 }
 
-// One thread per tile: the exclusive offsets of its column over the blocks
-// that hold pairs of its view (those whose chunks meet the view's pair range
-// [start(v), start(v + 1)): start(v) is the first pair of the view's first
-// record vrec[v], K past the last record), and its total.
+// Four threads per tile (adjacent lanes), each taking a quarter of its column
+// over the blocks that hold pairs of its view (those whose chunks meet the
+// view's pair range [start(v), start(v + 1)): start(v) is the first pair of the
+// view's first record vrec[v], K past the last record): each sums its rows,
+// the four sums are scanned by lane shuffles, and each writes its rows'
+// exclusive offsets from its share of that scan; the first writes the tile's
+// total.  A quarter of up to kOffsetsBatch rows stays in registers between
+// the two steps, a longer one is read again.
 constexpr int kOffsetsBatch = 32;   // rows of a column read together
+constexpr int kOffsetsParts = 4;
 
 __global__ __launch_bounds__(256) void k_tile_offsets(const ViewTable *__restrict__ vt,
                                                       const int64_t *__restrict__ counters,
@@ -791,32 +796,72 @@ __global__ __launch_bounds__(256) void k_tile_offsets(const ViewTable *__restric
                                                       const uint32_t *__restrict__ poff, int64_t n_tiles,
                                                       int64_t row_len, uint32_t *__restrict__ counts,
                                                       uint32_t *__restrict__ ttot) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= n_tiles) return;
-    const int64_t K = counters[kCntPairsUsed], M = counters[kCntVisible];
-    const int nv = vt->n_views;
-    int v = 0;
-    while (v + 1 < nv && vt->v[v + 1].tile_off <= t) ++v;
-    const int64_t x = t - vt->v[v].tile_off;
-    const int64_t ps = (int64_t)vrec[v] < M ? (int64_t)poff[vrec[v]] : K;
-    const int64_t pe = v + 1 < nv && (int64_t)vrec[v + 1] < M ? (int64_t)poff[vrec[v + 1]] : K;
-    uint32_t run = 0;
-    if (pe > ps && pe <= K) {
-        const int64_t b0 = ps / kEmitChunk, b1 = (pe - 1) / kEmitChunk;
-        uint32_t *col = counts + (size_t)(b0 + v) * (size_t)row_len + (size_t)x;
-        const int64_t nb = b1 - b0 + 1;
-        for (int64_t b = 0; b < nb; b += kOffsetsBatch) {   // the batch's loads in flight together
-            uint32_t c[kOffsetsBatch];
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t t = g / kOffsetsParts;
+    const int part = (int)(g % kOffsetsParts);
+    // every lane goes on to the shuffles; lanes past the tiles take no rows
+    int64_t r0 = 0, r1 = 0;
+    uint32_t *col = counts;
+    if (t < n_tiles) {
+        const int64_t K = counters[kCntPairsUsed], M = counters[kCntVisible];
+        const int nv = vt->n_views;
+        int v = 0;
+        while (v + 1 < nv && vt->v[v + 1].tile_off <= t) ++v;
+        const int64_t x = t - vt->v[v].tile_off;
+        const int64_t ps = (int64_t)vrec[v] < M ? (int64_t)poff[vrec[v]] : K;
+        const int64_t pe = v + 1 < nv && (int64_t)vrec[v + 1] < M ? (int64_t)poff[vrec[v + 1]] : K;
+        if (pe > ps && pe <= K) {
+            const int64_t b0 = ps / kEmitChunk, b1 = (pe - 1) / kEmitChunk;
+            col = counts + (size_t)(b0 + v) * (size_t)row_len + (size_t)x;
+            const int64_t nb = b1 - b0 + 1, per = (nb + kOffsetsParts - 1) / kOffsetsParts;
+            r0 = per * part < nb ? per * part : nb;
+            r1 = r0 + per < nb ? r0 + per : nb;
+        }
+    }
+    auto at_row = [&](int64_t r) -> uint32_t & { return col[(size_t)r * (size_t)row_len]; };
+    const bool one = r1 - r0 <= kOffsetsBatch;
+    uint32_t c[kOffsetsBatch];
+    uint32_t sum = 0;
+    if (one) {
 #pragma unroll
-            for (int q = 0; q < kOffsetsBatch; ++q) c[q] = b + q < nb ? col[(size_t)(b + q) * (size_t)row_len] : 0u;
+        for (int q = 0; q < kOffsetsBatch; ++q) {
+            c[q] = r0 + q < r1 ? at_row(r0 + q) : 0u;
+            sum += c[q];
+        }
+    } else {
+        for (int64_t b = r0; b < r1; b += kOffsetsBatch) {   // the batch's loads in flight together
+#pragma unroll
+            for (int q = 0; q < kOffsetsBatch; ++q) sum += b + q < r1 ? at_row(b + q) : 0u;
+        }
+    }
+    // the tile's four sums: inclusive scan over its lanes, then the total from the last
+    uint32_t incl = sum;
+#pragma unroll
+    for (int d = 1; d < kOffsetsParts; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d, kOffsetsParts);
+        if (part >= d) incl += y;
+    }
+    const uint32_t total = __shfl(incl, kOffsetsParts - 1, kOffsetsParts);
+    uint32_t run = incl - sum;
+    if (one) {
+#pragma unroll
+        for (int q = 0; q < kOffsetsBatch; ++q) {
+            if (r0 + q < r1) at_row(r0 + q) = run;
+            run += c[q];
+        }
+    } else {
+        for (int64_t b = r0; b < r1; b += kOffsetsBatch) {
+            uint32_t cb[kOffsetsBatch];
+#pragma unroll
+            for (int q = 0; q < kOffsetsBatch; ++q) cb[q] = b + q < r1 ? at_row(b + q) : 0u;
 #pragma unroll
             for (int q = 0; q < kOffsetsBatch; ++q) {
-                if (b + q < nb) col[(size_t)(b + q) * (size_t)row_len] = run;
-                run += c[q];
+                if (b + q < r1) at_row(b + q) = run;
+                run += cb[q];
             }
         }
     }
-    ttot[t] = run;
+    if (t < n_tiles && part == 0) ttot[t] = total;
 }
 
 __global__ __launch_bounds__(kEmitThreads) void k_emit_place(const int64_t *__restrict__ counters,
@@ -1690,7 +1735,7 @@ void enqueue_binning(Call &c, const gsr_views *views) {
                                at<uint2>(ws, L.espan));
         }
         if (L.T > 0) {
-            hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)((L.T + 255) / 256)), dim3(256), 0, st,
+            hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)((L.T * kOffsetsParts + 255) / 256)), dim3(256), 0, st,
                                (const ViewTable *)vt, (const int64_t *)counters, vrec, (const uint32_t *)poff, L.T,
                                L.tv_max, tcnt, ttot);
             hipLaunchKernelGGL(k_tile_ranges, dim3(1), dim3(kOrderThreads), 0, st, (const uint32_t *)ttot, L.T,
