@@ -1323,24 +1323,29 @@ __global__ __launch_bounds__(256) void k_record_bwd(ProjParams pp, const ViewTab
 }
 
 // Per Gaussian: its gradient is the sum of its records' contributions over
-// the views, in view order (deterministic).  The loads of four views are in
-// flight together.
+// the views, in a fixed order (deterministic): each half of the views in
+// view order, then the two halves.  The loads of four views are in flight
+// together.
 __device__ __forceinline__ void gauss_sum_block(const ProjParams &pp, const ViewTable *__restrict__ vt,
                                                 const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ inv,
                                                 const float *__restrict__ rgrad, const GradOut &go,
                                                 const int64_t *__restrict__ counters, int64_t blk) {
     const int V = vt->n_views;
     const uint32_t n_rec = (uint32_t)counters[kCntVisible];
-    const int64_t i = blk * blockDim.x + threadIdx.x;
-    if (i >= pp.n) return;
+    // two adjacent lanes per Gaussian, one per half of the views (each in
+    // view order), their sums added by a lane exchange (a fixed order)
+    const int64_t g = blk * blockDim.x + threadIdx.x;
+    const int64_t i = g >> 1;
+    const int half = (int)(g & 1);
+    const int vh = (V + 1) / 2, va = half ? vh : 0, vb = half ? V : vh;
     float acc[kRecGrad];
     for (int k = 0; k < kRecGrad; ++k) acc[k] = 0.0f;
-    for (int v0 = 0; v0 < V; v0 += 4) {
+    for (int v0 = va; i < pp.n && v0 < vb; v0 += 4) {
         uint32_t sv[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int64_t gi = (int64_t)(v0 + k) * pp.n + i;
-            const bool in = v0 + k < V;
+            const bool in = v0 + k < vb;
             const uint32_t c = in ? cnt[gi] : 0u;
             const uint32_t t = in ? inv[gi] : 0u;
             sv[k] = (c != 0u && t < n_rec) ? t : 0xffffffffu;
@@ -1356,6 +1361,12 @@ __device__ __forceinline__ void gauss_sum_block(const ProjParams &pp, const View
             for (int c = 0; c < kRecGrad; ++c) acc[c] += vis ? row[c] : 0.0f;
         }
     }
+#pragma unroll
+    for (int k = 0; k < kRecGrad; ++k) {   // every lane takes part; the two halves added as (first + second)
+        const float other = __shfl_xor(acc[k], 1, 64);
+        acc[k] = half ? other + acc[k] : acc[k] + other;
+    }
+    if (i >= pp.n || half) return;
     if (go.gg.means)
         for (int k = 0; k < 3; ++k) go.gg.means[3 * i + k] = acc[k];
     if (go.gg.quats)
@@ -1886,7 +1897,7 @@ void enqueue_backward(Call &c, const gsr_views *views, const gsr_options *opts, 
     memset(&fa, 0, sizeof(fa));
     fa.n_pose = go.want_pose ? views->n_views : 0;
     fa.n_loss = fused ? views->n_views : 0;
-    const int64_t n_gauss_blocks = (c.pp.n > 0 && go.want_gauss) ? grid_for(c.pp.n, 256, 1ll << 30) : 0;
+    const int64_t n_gauss_blocks = (c.pp.n > 0 && go.want_gauss) ? grid_for(2 * c.pp.n, 256, 1ll << 30) : 0;   // two lanes per Gaussian
     fa.pq = views->quat;
     fa.pt = views->trans;
     fa.centre = c.tab.pose_centre;
