@@ -382,7 +382,11 @@ __device__ __forceinline__ void quad_sums(float (&d)[NV]) {
 // 16-wave build, whose LDS arrays are sized for 16 waves.
 constexpr int kBwdWavesSmall = 4;
 constexpr int kBwdWavesLarge = 16;
-constexpr int kSeg = 48;   // list entries per segment
+// List entries per segment: 48 with all gradients (NV = 10), whose LDS then
+// leaves room for 8 workgroups per CU; 64 with pose gradients only, whose
+// smaller slots keep that occupancy at the longer segment.
+template <int NV>
+constexpr int seg_entries() { return NV == 10 ? 48 : 64; }
 constexpr int kRowStride = 10;   // floats per record row of the atomic backward (NV of them used)
 
 // NV = 10: all partials per entry (dL/d of the conic factors and mean, opacity,
@@ -413,6 +417,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(const ViewTable *__res
     // (a multiple of the bank count) put the four slots' value c in one bank
     constexpr int kQStride = 16 * NV + 8;
     __shared__ float s_q[WAVES][kBatch * kQStride];
+    constexpr int kSeg = seg_entries<NV>();
     __shared__ float s_acc[WAVES][kSeg * NV];
     __shared__ uint32_t s_wmax[WAVES];
     __shared__ uint32_t s_j[kSeg];   // gradient-row slot of each entry of the segment
