@@ -146,6 +146,38 @@ def test_track_follows_the_oracle_loop(rast):
     assert dl < 1e-4
 
 
+@pytest.mark.timeout(300)
+def test_track_follows_the_oracle_loop_tracking_room(rast):
+    """A whole frame of the full-size tracking loop (40 iterations on one
+    640x480 view of the 200k-Gaussian room, the default atomic backward with
+    only the pose gradients and split lists, as timed) against the oracle's
+    loop.  The gradients sum over 300k pixels, so FP32 rounding and the pixels
+    whose decisions straddle a threshold move them far less than a step's
+    worth."""
+    from paper_2408_05635_amd.raster import PoseAdam, RenderOptions
+    w = scenes.config2(n_views=1)
+    g = dev_params(w.gaussians)
+    q, t = dev_poses(w.views)
+    otg = oracle_targets(w)
+    tg = to_dev(otg)
+    hp = PoseAdam(lr_rot=1e-3, lr_pos=1e-3)
+    iters = 40
+    q0, t0 = q.cpu().numpy().astype(np.float64), t.cpu().numpy().astype(np.float64)
+    r = rast.track(g, q, t, w.views.cams, tg, RenderOptions(**w.weights), hp, iters)
+    torch.cuda.synchronize()
+    hist, ol = optim.track(w.gaussians, w.views.cams, q0, t0,
+                           oracle.Targets(otg["rgb"], otg["depth"], otg["sil"]), oracle.Options(**w.weights),
+                           _hp32(optim.PoseAdam(**hp.__dict__)), iters)
+    s = r["state"].cpu().numpy()[0]
+    oq, oc = hist[-1][0].q, hist[-1][0].C
+    dq = np.abs(s[0:4] / np.linalg.norm(s[0:4]) - oq / np.linalg.norm(oq)).max()
+    dc = np.abs(s[4:7] - oc).max()
+    dl = np.abs(r["loss_hist"].cpu().numpy()[:, 0] - ol[:, 0]).max() / ol[0, 0]
+    print(f"after {iters} iterations: |dq| {dq:.2e} |dC| {dc:.2e} (step size {hp.lr_rot:g}), loss rel {dl:.2e}")
+    assert dq < 0.05 * hp.lr_rot and dc < 0.05 * hp.lr_pos
+    assert dl < 1e-4
+
+
 def test_track_reduces_pose_error_tracking_room(rast):
     """One view of the 200k-Gaussian room from the 2 deg / 2 cm perturbed
     start: the loop moves toward the true pose."""
