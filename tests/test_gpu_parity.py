@@ -412,6 +412,19 @@ def test_config2_full_view_parity(rast, det):
     _fused_parity(rast, w, oracle_targets(w), f"config2 deterministic={det}", deterministic=det)
 
 
+def test_config2_isotropic_full_view_parity(rast):
+    """One 640x480 view of the 200k-Gaussian room with isotropic Gaussians
+    (each one log-scale, the mean of its three; no rotation), the variant
+    that the isotropic throughput figure runs: forward + fused loss + backward."""
+    w = scenes.config2(n_views=1)
+    g = w.gaussians
+    giso = scenes.Gaussians(g.means, g.quats, g.log_scales.mean(axis=1, keepdims=True).astype(np.float32),
+                            g.opacity_logits, g.rgb)
+    assert giso.isotropic
+    wiso = scenes.Workload(w.name + "_iso", giso, w.views, w.target_views, weights=w.weights)
+    _fused_parity(rast, wiso, oracle_targets(wiso), "config2 isotropic")
+
+
 @pytest.mark.parametrize("tile", [(32, 32), (32, 16)])
 def test_config2_view_parity_large_tiles(rast, tile):
     """The 16-wave backward (tiles with a 32-pixel side) on one 640x480 view,
