@@ -121,10 +121,10 @@ def test_loss_total_is_the_view_sum_in_view_order(rast):
     assert float(out["loss_total"].item()) == tot and tot > 0
 
 
-def _centre_workload():
-    """config1 with each pose given as (q, C), C = -R(q)^T t rounded to
-    float32; the oracle renders the same (q, t = -R(q) C) in FP64."""
-    w = scenes.config1()
+def _centre_workload(w=None):
+    """config1 (or w, one view) with each pose given as (q, C), C = -R(q)^T t
+    rounded to float32; the oracle renders the same (q, t = -R(q) C) in FP64."""
+    w = scenes.config1() if w is None else w
     q32 = np.asarray(w.views.quat, np.float32)
     t64 = np.asarray(w.views.trans, np.float64)
     R = oracle.quat_to_rot(q32[0].astype(np.float64))
@@ -135,12 +135,14 @@ def _centre_workload():
     return w, wo, q32, C32
 
 
-def test_camera_centre_autograd_matches_the_oracle(rast):
+@pytest.mark.parametrize("scene", ["config1", "config2_view"])
+def test_camera_centre_autograd_matches_the_oracle(rast, scene):
     """render_loss with the camera-centre pose form: the gradients of the pose
     tensors are the decoupled ones (dL/dq at fixed C, dL/dC), and the loss is
-    the library's FP64 total."""
+    the library's FP64 total.  On config1, and on one full 640x480 view of the
+    200k-Gaussian room (the autograd path's throughput workload, one view)."""
     from paper_2408_05635_amd import raster
-    w, wo, q32, C32 = _centre_workload()
+    w, wo, q32, C32 = _centre_workload(scenes.config2(n_views=1) if scene == "config2_view" else None)
     tg = oracle_targets(w)
     r = oracle.run(wo.gaussians, wo.views, oracle.Options(**w.weights), oracle.Targets(tg["rgb"], tg["depth"], tg["sil"]),
                    want_grads=True, mask_ambiguous=True, res_margin=RES_MARGIN)
